@@ -1,0 +1,213 @@
+/*
+ * pgrid.h - C ABI of the MI355X (gfx950) power-grid transient relaxation library.
+ *
+ * The library advances the backward-Euler transient of an on-chip power mesh
+ * (Sec. II-A eqs. 1-3 for RC grids, Sec. III eqs. 9-10 for series R-L vias and
+ * pads).  Every time step solves the symmetric positive definite nodal system
+ * (Lemma 1)
+ *     M v(t+h) = (C/h) v(t) + G0 Vdd - i(t+h) + [inductor history terms],
+ *     M = C/h + G + G0 + [inductor companion conductances],
+ * by topology-based relaxation sweeps (eqs. 15-17, Algorithm 1 with the SOR
+ * blend of eq. 17), without assembling M.  The nodes are swept in red-black
+ * order (colour = parity of x + y + layer); by Theorem 1 any sweep order of a
+ * Gauss-Seidel/SOR iteration on an SPD matrix converges to the same solution.
+ *
+ * Conventions for every entry point:
+ *  - Units are SI (S, F, H, s, A, V) and every value crossing the ABI is a
+ *    double, whatever precision the sweeps use internally.
+ *  - Host arrays are owned by the caller; the library copies what it keeps.
+ *    Device pointers (the *_dev entry points) are also owned by the caller and
+ *    must stay valid until the work queued on the context's stream completes.
+ *  - Mesh node id = (layer * ny + y) * nx + x.  A grid may carry n_scen
+ *    independent current scenarios that share its coefficients.
+ *  - No exception crosses the ABI.  A negative return value is an error;
+ *    pg_last_error() gives a message.  A context is used by one host thread
+ *    at a time.
+ *  - On PG_ERR_NO_CONVERGENCE the state holds the last iterate and the
+ *    statistics are filled in.
+ */
+#ifndef PGRID_H
+#define PGRID_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define PG_ABI_VERSION 1
+
+typedef struct pg_ctx pg_ctx;
+
+typedef enum pg_status {
+  PG_OK = 0,
+  PG_ERR_INVALID_ARG = -1,      /* bad pointer, size, NaN/negative value, option out of range */
+  PG_ERR_TOPOLOGY = -2,         /* violates the topological assumptions 1-3 of Sec. III-B */
+  PG_ERR_NOT_SPD = -3,          /* a connected component has neither a pad nor a capacitor, so M is singular */
+  PG_ERR_NO_CONVERGENCE = -4,   /* a step reached max_sweeps with the residual above tol */
+  PG_ERR_DEVICE = -5,           /* HIP runtime error or no usable gfx950 device */
+  PG_ERR_OOM = -6,              /* device allocation failed */
+  PG_ERR_STATE = -7,            /* call out of order (e.g. stepping before any grid was uploaded) */
+  PG_ERR_UNSUPPORTED = -8       /* valid input this build does not handle */
+} pg_status;
+
+typedef enum pg_precision {
+  PG_PREC_FP64 = 0,             /* sweeps, residual and state in FP64 */
+  PG_PREC_FP32_REFINE = 1       /* FP32 correction sweeps, FP64 residual, state and refinement */
+} pg_precision;
+
+typedef enum pg_ordering {
+  PG_ORDER_RED_BLACK = 0,       /* SOR in red-black order (eqs. 16-17) */
+  PG_ORDER_JACOBI = 1           /* weighted Jacobi: every node from the previous sweep's values */
+} pg_ordering;
+
+/* Solver options (Algorithm 1 inputs h and tol; omega of eq. 17). */
+typedef struct pg_options {
+  double h;             /* backward-Euler step in seconds, > 0 */
+  double tol;           /* stop a step when max_i |(b - M v)_i| / M_ii <= tol (volts), > 0 */
+  double omega;         /* relaxation factor of eq. 17, 0 < omega < 2 */
+  int32_t max_sweeps;   /* sweep budget per step per grid, >= 1 */
+  int32_t check_every;  /* sweeps between FP64 residual checks (one refinement cycle), >= 1 */
+  int32_t precision;    /* pg_precision */
+  int32_t ordering;     /* pg_ordering */
+  int32_t tile_rows;    /* rows per sweep tile: 4, 8, 16 or 32 (0 = library default) */
+  int32_t lookahead;    /* refinement cycles queued ahead of the host's convergence check, 0..4 */
+  int32_t reserved[6];  /* must be zero */
+} pg_options;
+
+/* A layered RC/RLC mesh (the representative node of Fig. 2 repeated on a grid).
+ * Array shapes are C-ordered.  Every conductance and capacitance must be finite and >= 0. */
+typedef struct pg_mesh {
+  int32_t nx, ny, nl;         /* nodes per row, rows per layer, layers; nx, ny >= 2, 1 <= nl <= 4 */
+  const double* gE;           /* [nl][ny][nx-1] segment (l,y,x)-(l,y,x+1), S */
+  const double* gN;           /* [nl][ny-1][nx] segment (l,y,x)-(l,y+1,x), S */
+  const double* C;            /* [nl][ny][nx] node-to-ground capacitance, F */
+  int32_t n_vias;
+  const int32_t* via_node;    /* lower node (layer l < nl-1); the upper node is via_node + nx*ny */
+  const double* via_g;        /* via conductance, S, > 0 */
+  const double* via_L;        /* series inductance, H (NULL or 0: resistive via) */
+  int32_t n_pads;
+  const int32_t* pad_node;    /* node joined to the ideal supply */
+  const double* pad_g;        /* pad conductance, S, > 0 */
+  const double* pad_L;        /* series inductance, H (NULL or 0: resistive pad) */
+  double vdd;                 /* supply voltage, V */
+} pg_mesh;
+
+typedef struct pg_stats {
+  int64_t steps;              /* backward-Euler steps completed */
+  int64_t sweeps;             /* sweeps summed over grids */
+  int64_t node_updates;       /* sum over sweeps of active nodes x scenarios */
+  int64_t checks;             /* FP64 residual passes */
+  int32_t last_step_sweeps;   /* max over grids, last step */
+  int32_t max_step_sweeps;    /* max over steps and grids */
+  double last_residual;       /* max over grids of the final scaled residual of the last step, V */
+  double max_final_residual;  /* max over steps of the final scaled residual, V */
+  double seconds;             /* wall time inside pg_step / pg_run_transient */
+} pg_stats;
+
+/* Kernel timing gathered with HIP events on the context stream while profiling is on. */
+typedef struct pg_kernel_times {
+  int64_t sweep_launches;  double sweep_ms;      int64_t sweep_node_updates;
+  int64_t resid_launches;  double resid_ms;      int64_t resid_nodes;
+  int64_t rhs_launches;    double rhs_ms;
+  int64_t other_launches;  double other_ms;
+} pg_kernel_times;
+
+int32_t pg_abi_version(void);
+const char* pg_status_name(int32_t status);
+
+/* Fill *out with the defaults: h = 10 ps, tol = 1e-6 V, omega = 1, max_sweeps = 10000,
+ * check_every = 8, FP64, red-black, tile_rows = 16, lookahead = 1. */
+pg_status pg_default_options(pg_options* out);
+
+/* Host-only checks (no device needed).  msg (may be NULL) receives a description of the
+ * first problem found, truncated to msg_len bytes. */
+pg_status pg_validate_options(const pg_options* opt, char* msg, size_t msg_len);
+
+/* Checks array sizes and values, the via/pad indices, and Lemma 1's requirement that
+ * every connected component of the mesh graph reaches a pad or holds a node with C > 0
+ * (PG_ERR_NOT_SPD otherwise). */
+pg_status pg_validate_mesh(const pg_mesh* mesh, char* msg, size_t msg_len);
+
+/* General netlist check against the assumptions of Sec. III-B.  Nodes 0..n-1 are trivial
+ * nodes, n..n+p-1 source nodes (supplies with grounded negative terminals), -1 is ground.
+ * kind[e] is 'R' (value = conductance), 'C', 'L' or 'I'.  Returns PG_ERR_TOPOLOGY if a
+ * trivial node has no non-source branch (assumption 2) or is linked to other nodes only
+ * through current sources, PG_ERR_NOT_SPD if a group of trivial nodes connected through
+ * trivial nodes (a sub-circuit in the sense of Fig. 1) has no capacitor, no branch to a
+ * source node and no branch to ground, and PG_ERR_INVALID_ARG on bad indices or values. */
+pg_status pg_validate_netlist(int32_t n, int32_t p, int32_t m, const int32_t* from,
+                              const int32_t* to, const uint8_t* kind, const double* value,
+                              char* msg, size_t msg_len);
+
+/* Create a context on HIP device `device` (must be gfx950).  `stream` is a hipStream_t
+ * (for instance torch.cuda.current_stream().cuda_stream) or NULL for a stream owned by
+ * the context.  Every kernel and copy of the context runs on that stream. */
+pg_status pg_create(pg_ctx** out, int32_t device, void* stream);
+void pg_destroy(pg_ctx* ctx);
+const char* pg_last_error(const pg_ctx* ctx);
+
+pg_status pg_set_options(pg_ctx* ctx, const pg_options* opt);
+pg_status pg_get_options(const pg_ctx* ctx, pg_options* out);
+
+/* Upload a mesh (validated as by pg_validate_mesh) with n_scen >= 1 current scenarios.
+ * Must precede the first step; options (h, precision) must be set before upload.
+ * The state starts at v = vdd on every node and zero inductor current.  Returns the grid
+ * id (0, 1, ...) in *grid_id.  All grids of a context advance together in time. */
+pg_status pg_upload_mesh(pg_ctx* ctx, const pg_mesh* mesh, int32_t n_scen, int32_t* grid_id);
+
+/* Replace the current sources of one scenario by triangular pulses (one per node, nodes
+ * unique): i(t) = peak * max(0, 1 - |t - (start + width/2)| / (width/2)), width > 0. */
+pg_status pg_set_pulses(pg_ctx* ctx, int32_t grid, int32_t scen, int32_t n_src,
+                        const int32_t* node, const double* peak, const double* start,
+                        const double* width);
+
+/* Replace the current sources of one scenario by piecewise-linear waveforms (Sec. II-A):
+ * source k draws, at node[k], the current interpolated through the breakpoints
+ * (t[j], i[j]) for j in offsets[k] .. offsets[k+1]-1 (t strictly increasing, at least one
+ * breakpoint), held constant before the first and after the last breakpoint. */
+pg_status pg_set_pwl(pg_ctx* ctx, int32_t grid, int32_t scen, int32_t n_src,
+                     const int32_t* node, const int32_t* offsets, const double* t,
+                     const double* i);
+
+/* Set the state of one scenario: v (n doubles; NULL = vdd everywhere) and the inductor
+ * currents (n_vias + n_pads doubles in via-then-pad order, entries of resistive branches
+ * ignored; NULL = 0).  Does not change the time index. */
+pg_status pg_set_state(pg_ctx* ctx, int32_t grid, int32_t scen, const double* v, const double* i_l);
+
+/* Back to t = 0: every state to v = vdd, zero inductor currents; statistics cleared. */
+pg_status pg_reset(pg_ctx* ctx);
+
+/* Advance every grid and scenario by nsteps backward-Euler steps (Algorithm 1 loop:
+ * warm start from the previous step, sweep until the scaled residual is <= tol). */
+pg_status pg_step(pg_ctx* ctx, int32_t nsteps);
+
+/* pg_step(nsteps) that also copies the voltages of (grid, scen) to out after every
+ * record_every-th step: out holds floor(nsteps / record_every) * n doubles (may be NULL). */
+pg_status pg_run_transient(pg_ctx* ctx, int32_t nsteps, int32_t record_every, int32_t grid,
+                           int32_t scen, double* out);
+
+/* Current step index k (time t = k h). */
+pg_status pg_get_time(const pg_ctx* ctx, int64_t* step);
+
+/* Copy the node voltages (n doubles) or inductor currents (n_vias + n_pads doubles, via
+ * then pad order, zero for resistive branches) of one scenario to host memory (blocking)
+ * or to device memory (queued on the context stream). */
+pg_status pg_read_voltages(pg_ctx* ctx, int32_t grid, int32_t scen, double* out, int64_t n);
+pg_status pg_read_voltages_dev(pg_ctx* ctx, int32_t grid, int32_t scen, double* dev_out, int64_t n);
+pg_status pg_read_inductor_currents(pg_ctx* ctx, int32_t grid, int32_t scen, double* out, int64_t n);
+
+pg_status pg_get_stats(const pg_ctx* ctx, pg_stats* out);
+pg_status pg_reset_stats(pg_ctx* ctx);
+
+/* Kernel timing with HIP events recorded around every launch on the context stream
+ * (enable = 1), off (enable = 0).  pg_read_kernel_times synchronises the stream. */
+pg_status pg_profile(pg_ctx* ctx, int32_t enable);
+pg_status pg_read_kernel_times(pg_ctx* ctx, pg_kernel_times* out);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PGRID_H */

@@ -1,0 +1,883 @@
+// Host runtime of the C ABI: context, coefficient layout, device memory and the
+// per-step schedule of Algorithm 1 (warm start from the previous step, sweep until the
+// scaled residual is below tol), with the convergence decision taken on the device.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <deque>
+#include <string>
+#include <vector>
+
+#include "../../include/pgrid.h"
+#include "pgrid_internal.h"
+
+using namespace pgrid;
+
+namespace {
+
+struct Src {
+  std::vector<int32_t> node, off;
+  std::vector<double> t, i;
+};
+
+// Device allocation owned by a context.
+struct DBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+};
+
+struct GridHost {
+  int32_t nx = 0, ny = 0, nl = 0, S = 1;
+  int64_t n = 0, P = 0;
+  double vdd = 1.0;
+  std::vector<double> gE, gN, C;                 // as uploaded (unpadded)
+  std::vector<int32_t> via_node, pad_node;
+  std::vector<double> via_g, via_L, pad_g, pad_L;
+  std::vector<Src> src;                          // per scenario
+  // inductive branches in via-then-pad order; branch_of[k] = index into that order
+  std::vector<int32_t> ind_a, ind_b, ind_branch;
+  // device buffers
+  DBuf gE64, gN64, gU64, D64, ch64, bconst64, gEs, gNs, gUs, invDs;
+  DBuf v0, v1, b, r, d0, d1;
+  DBuf ind_a_d, ind_b_d, ind_geq_d, ind_alpha_d, ind_i_d, inc_off_d, inc_ind_d;
+  int sweep_fp32 = -1;                           // precision the sweep buffers were built for
+};
+
+struct ProfEvent {
+  hipEvent_t a, b;
+  int kind;          // 0 sweep, 1 resid, 2 rhs, 3 other
+  int64_t units;     // node-updates (sweep) or nodes (resid)
+};
+
+}  // namespace
+
+struct pg_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  pg_options opt{};
+  std::string err;
+  std::vector<GridHost> grids;
+  bool dirty = true;
+  int64_t step = 0;
+  double seconds = 0.0;
+  // device tables
+  DBuf grid_desc, tiles_all, src_grid, src_index, src_off, src_t, src_i, ind_grid, ind_local;
+  struct Group { int nl, off, count; int64_t nodes; };
+  std::vector<Group> tile_groups;                 // tiles of grids with nl layers: [off, off+count)
+  int ntiles_all = 0;
+  int tile_rows = 16;
+  int n_src = 0, n_ind_total = 0;
+  // control block
+  DBuf c_norm, c_last, c_active, c_vidx, c_sweeps, c_failed, c_any, c_stats64, c_stats32, c_statsd, c_nodes;
+  Ctl ctl{};
+  int32_t* host_flags = nullptr;                 // pinned, written by the decision kernel
+  int32_t* dev_flags = nullptr;                  // device address of host_flags
+  std::vector<hipEvent_t> flag_events;
+  // profiling
+  int profile_every = 0;
+  int64_t launch_counter = 0;
+  std::vector<ProfEvent> prof_live;
+  std::vector<hipEvent_t> prof_pool;
+  pg_kernel_times prof_acc{};
+};
+
+namespace {
+
+pg_status set_err(pg_ctx* c, pg_status st, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  std::vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  if (c) c->err = buf;
+  return st;
+}
+
+#define HIP_TRY(ctx, expr)                                                                \
+  do {                                                                                    \
+    hipError_t e_ = (expr);                                                               \
+    if (e_ != hipSuccess)                                                                 \
+      return set_err((ctx), e_ == hipErrorOutOfMemory ? PG_ERR_OOM : PG_ERR_DEVICE,       \
+                     "%s failed: %s", #expr, hipGetErrorString(e_));                      \
+  } while (0)
+
+#define PG_TRY(expr)                        \
+  do {                                      \
+    pg_status s_ = (expr);                  \
+    if (s_ != PG_OK) return s_;             \
+  } while (0)
+
+pg_status dalloc(pg_ctx* c, DBuf& b, size_t bytes) {
+  if (b.p && b.bytes == bytes) return PG_OK;
+  if (b.p) { (void)hipFree(b.p); b.p = nullptr; b.bytes = 0; }
+  if (bytes == 0) return PG_OK;
+  HIP_TRY(c, hipMalloc(&b.p, bytes));
+  b.bytes = bytes;
+  return PG_OK;
+}
+
+void dfree(DBuf& b) {
+  if (b.p) (void)hipFree(b.p);
+  b.p = nullptr;
+  b.bytes = 0;
+}
+
+// Set-up copies are synchronous: the host vectors are temporaries.
+template <typename T>
+pg_status upload(pg_ctx* c, DBuf& b, const std::vector<T>& h) {
+  PG_TRY(dalloc(c, b, h.size() * sizeof(T)));
+  if (!h.empty()) {
+    HIP_TRY(c, hipMemcpyAsync(b.p, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+  }
+  return PG_OK;
+}
+
+bool fp32_mode(const pg_ctx* c) { return c->opt.precision == PG_PREC_FP32_REFINE; }
+
+// ---- profiling helpers ---------------------------------------------------------------
+hipEvent_t prof_get(pg_ctx* c) {
+  if (!c->prof_pool.empty()) {
+    hipEvent_t e = c->prof_pool.back();
+    c->prof_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  (void)hipEventCreate(&e);
+  return e;
+}
+
+struct ProfScope {
+  pg_ctx* c;
+  ProfEvent ev{};
+  bool on = false;
+  ProfScope(pg_ctx* ctx, int kind, int64_t units) : c(ctx) {
+    if (c->profile_every <= 0) return;
+    if (kind == 0 && (c->launch_counter++ % c->profile_every) != 0) return;
+    on = true;
+    ev.a = prof_get(c);
+    ev.b = prof_get(c);
+    ev.kind = kind;
+    ev.units = units;
+    (void)hipEventRecord(ev.a, c->stream);
+  }
+  ~ProfScope() {
+    if (!on) return;
+    (void)hipEventRecord(ev.b, c->stream);
+    c->prof_live.push_back(ev);
+  }
+};
+
+void prof_drain(pg_ctx* c) {
+  if (c->prof_live.empty()) return;
+  (void)hipStreamSynchronize(c->stream);
+  for (auto& e : c->prof_live) {
+    float ms = 0.f;
+    (void)hipEventElapsedTime(&ms, e.a, e.b);
+    auto& A = c->prof_acc;
+    switch (e.kind) {
+      case 0: A.sweep_launches++; A.sweep_ms += ms; A.sweep_node_updates += e.units; break;
+      case 1: A.resid_launches++; A.resid_ms += ms; A.resid_nodes += e.units; break;
+      case 2: A.rhs_launches++; A.rhs_ms += ms; break;
+      default: A.other_launches++; A.other_ms += ms; break;
+    }
+    c->prof_pool.push_back(e.a);
+    c->prof_pool.push_back(e.b);
+  }
+  c->prof_live.clear();
+}
+
+// ---- coefficient layout ------------------------------------------------------------
+// Builds the padded FP64 coefficient arrays and the companion model of every inductive
+// branch for step h (series R-L: g_eq = h/(L + hR), alpha = L/(L + hR); eq. 10 with the
+// inductor current kept as state), then the sweep-precision copies.
+pg_status build_grid(pg_ctx* c, int gi) {
+  GridHost& G = c->grids[gi];
+  const double h = c->opt.h;
+  const int64_t n = G.n, P = G.P;
+  const int nx = G.nx, ny = G.ny, nl = G.nl;
+  std::vector<double> gE(n, 0.0), gN(n, 0.0), gU(n, 0.0), D(n, 0.0), ch(n), bc(n, 0.0);
+  for (int l = 0; l < nl; ++l)
+    for (int y = 0; y < ny; ++y)
+      for (int x = 0; x < nx; ++x) {
+        const int64_t i = (int64_t)l * P + (int64_t)y * nx + x;
+        if (x + 1 < nx) gE[i] = G.gE[((int64_t)l * ny + y) * (nx - 1) + x];
+        if (y + 1 < ny) gN[i] = G.gN[((int64_t)l * (ny - 1) + y) * nx + x];
+      }
+  G.ind_a.clear(); G.ind_b.clear(); G.ind_branch.clear();
+  std::vector<double> geq, alpha;
+  const int nv = (int)G.via_node.size(), np = (int)G.pad_node.size();
+  for (int k = 0; k < nv; ++k) {
+    const int a = G.via_node[k];
+    const double L = G.via_L.empty() ? 0.0 : G.via_L[k];
+    if (L > 0) {
+      const double R = 1.0 / G.via_g[k];
+      gU[a] += h / (L + h * R);
+      G.ind_a.push_back(a); G.ind_b.push_back(a + (int32_t)P); G.ind_branch.push_back(k);
+      geq.push_back(h / (L + h * R)); alpha.push_back(L / (L + h * R));
+    } else {
+      gU[a] += G.via_g[k];
+    }
+  }
+  for (int k = 0; k < np; ++k) {
+    const int a = G.pad_node[k];
+    const double L = G.pad_L.empty() ? 0.0 : G.pad_L[k];
+    double g = G.pad_g[k];
+    if (L > 0) {
+      const double R = 1.0 / G.pad_g[k];
+      g = h / (L + h * R);
+      G.ind_a.push_back(a); G.ind_b.push_back(-1); G.ind_branch.push_back(nv + k);
+      geq.push_back(g); alpha.push_back(L / (L + h * R));
+    }
+    D[a] += g;
+    bc[a] += g * G.vdd;
+  }
+  for (int64_t i = 0; i < n; ++i) {
+    const int64_t x = i % nx, y = (i / nx) % ny, l = i / P;
+    ch[i] = G.C[i] / h;
+    double s = ch[i] + gE[i] + gN[i] + gU[i];
+    if (x > 0) s += gE[i - 1];
+    if (y > 0) s += gN[i - nx];
+    if (l > 0) s += gU[i - P];
+    D[i] += s;
+  }
+  PG_TRY(upload(c, G.gE64, gE)); PG_TRY(upload(c, G.gN64, gN)); PG_TRY(upload(c, G.gU64, gU));
+  PG_TRY(upload(c, G.D64, D)); PG_TRY(upload(c, G.ch64, ch)); PG_TRY(upload(c, G.bconst64, bc));
+  const bool f32 = fp32_mode(c);
+  if (f32) {
+    std::vector<float> a(n), b(n), u(n), q(n);
+    for (int64_t i = 0; i < n; ++i) {
+      a[i] = (float)gE[i]; b[i] = (float)gN[i]; u[i] = (float)gU[i]; q[i] = (float)(1.0 / D[i]);
+    }
+    PG_TRY(upload(c, G.gEs, a)); PG_TRY(upload(c, G.gNs, b)); PG_TRY(upload(c, G.gUs, u));
+    PG_TRY(upload(c, G.invDs, q));
+  } else {
+    std::vector<double> q(n);
+    for (int64_t i = 0; i < n; ++i) q[i] = 1.0 / D[i];
+    dfree(G.gEs); dfree(G.gNs); dfree(G.gUs);
+    PG_TRY(upload(c, G.invDs, q));
+  }
+  const size_t es = f32 ? sizeof(float) : sizeof(double);
+  const size_t ns = (size_t)n * G.S;
+  if (G.sweep_fp32 != (int)f32) {
+    PG_TRY(dalloc(c, G.r, ns * es)); PG_TRY(dalloc(c, G.d0, ns * es)); PG_TRY(dalloc(c, G.d1, ns * es));
+    G.sweep_fp32 = (int)f32;
+  }
+  // inductors: keep the branch currents if the branch set is unchanged
+  const int ni = (int)G.ind_a.size();
+  PG_TRY(upload(c, G.ind_a_d, G.ind_a)); PG_TRY(upload(c, G.ind_b_d, G.ind_b));
+  PG_TRY(upload(c, G.ind_geq_d, geq)); PG_TRY(upload(c, G.ind_alpha_d, alpha));
+  if (G.ind_i_d.bytes != (size_t)ni * G.S * sizeof(double)) {
+    PG_TRY(dalloc(c, G.ind_i_d, (size_t)ni * G.S * sizeof(double)));
+    if (ni) HIP_TRY(c, hipMemsetAsync(G.ind_i_d.p, 0, (size_t)ni * G.S * sizeof(double), c->stream));
+  }
+  if (ni) {
+    std::vector<int32_t> cnt(n + 1, 0);
+    for (int k = 0; k < ni; ++k) { cnt[G.ind_a[k] + 1]++; if (G.ind_b[k] >= 0) cnt[G.ind_b[k] + 1]++; }
+    for (int64_t i = 0; i < n; ++i) cnt[i + 1] += cnt[i];
+    std::vector<int32_t> inc(cnt[n]), fillp(cnt.begin(), cnt.end() - 1);
+    for (int k = 0; k < ni; ++k) {
+      inc[fillp[G.ind_a[k]]++] = k + 1;
+      if (G.ind_b[k] >= 0) inc[fillp[G.ind_b[k]]++] = -(k + 1);
+    }
+    PG_TRY(upload(c, G.inc_off_d, cnt)); PG_TRY(upload(c, G.inc_ind_d, inc));
+  } else {
+    dfree(G.inc_off_d); dfree(G.inc_ind_d);
+  }
+  return PG_OK;
+}
+
+pg_status prepare(pg_ctx* c) {
+  if (c->grids.empty()) return set_err(c, PG_ERR_STATE, "no grid uploaded");
+  if (!c->dirty) return PG_OK;
+  const int G = (int)c->grids.size();
+  c->tile_rows = c->opt.tile_rows ? c->opt.tile_rows : 16;
+  for (int g = 0; g < G; ++g) PG_TRY(build_grid(c, g));
+  // grid descriptors
+  std::vector<GridDesc> desc(G);
+  std::vector<long long> nodes(G);
+  for (int g = 0; g < G; ++g) {
+    GridHost& H = c->grids[g];
+    GridDesc& D = desc[g];
+    std::memset(&D, 0, sizeof D);
+    D.nx = H.nx; D.ny = H.ny; D.nl = H.nl; D.S = H.S; D.n = H.n;
+    D.gE64 = (const double*)H.gE64.p; D.gN64 = (const double*)H.gN64.p; D.gU64 = (const double*)H.gU64.p;
+    D.D64 = (const double*)H.D64.p; D.ch64 = (const double*)H.ch64.p; D.bconst64 = (const double*)H.bconst64.p;
+    if (fp32_mode(c)) { D.gEs = H.gEs.p; D.gNs = H.gNs.p; D.gUs = H.gUs.p; }
+    else { D.gEs = H.gE64.p; D.gNs = H.gN64.p; D.gUs = H.gU64.p; }
+    D.invDs = H.invDs.p;
+    D.v[0] = (double*)H.v0.p; D.v[1] = (double*)H.v1.p; D.b = (double*)H.b.p;
+    D.r = H.r.p; D.d[0] = H.d0.p; D.d[1] = H.d1.p;
+    D.n_ind = (int32_t)H.ind_a.size();
+    D.ind_a = (const int32_t*)H.ind_a_d.p; D.ind_b = (const int32_t*)H.ind_b_d.p;
+    D.ind_geq = (const double*)H.ind_geq_d.p; D.ind_alpha = (const double*)H.ind_alpha_d.p;
+    D.ind_i = (double*)H.ind_i_d.p;
+    D.inc_off = (const int32_t*)H.inc_off_d.p; D.inc_ind = (const int32_t*)H.inc_ind_d.p;
+    D.vdd = H.vdd;
+    nodes[g] = (long long)H.n * H.S;
+  }
+  PG_TRY(upload(c, c->grid_desc, desc));
+  PG_TRY(upload(c, c->c_nodes, nodes));
+  c->ctl.nodes = (const long long*)c->c_nodes.p;
+  // tiles grouped by layer count
+  const int TY = c->tile_rows;
+  std::vector<Tile> tiles;
+  c->tile_groups.clear();
+  for (int nl = 1; nl <= 4; ++nl) {
+    const int start = (int)tiles.size();
+    int64_t nodes_nl = 0;
+    for (int g = 0; g < G; ++g) {
+      const GridHost& H = c->grids[g];
+      if (H.nl != nl) continue;
+      nodes_nl += H.n * H.S;
+      for (int y0 = 0; y0 < H.ny; y0 += TY)
+        for (int x0 = 0; x0 < H.nx; x0 += kTileX) tiles.push_back(Tile{g, x0, y0, 0});
+    }
+    if ((int)tiles.size() > start)
+      c->tile_groups.push_back({nl, start, (int)tiles.size() - start, nodes_nl});
+  }
+  c->ntiles_all = (int)tiles.size();
+  PG_TRY(upload(c, c->tiles_all, tiles));
+  // sources
+  std::vector<int32_t> sg, si, so{0};
+  std::vector<double> st, sv;
+  for (int g = 0; g < G; ++g) {
+    const GridHost& H = c->grids[g];
+    for (int s = 0; s < H.S; ++s) {
+      const Src& S = H.src[s];
+      for (size_t k = 0; k < S.node.size(); ++k) {
+        sg.push_back(g);
+        si.push_back((int32_t)((int64_t)S.node[k] * H.S + s));
+        for (int j = S.off[k]; j < S.off[k + 1]; ++j) { st.push_back(S.t[j]); sv.push_back(S.i[j]); }
+        so.push_back((int32_t)st.size());
+      }
+    }
+  }
+  c->n_src = (int)sg.size();
+  PG_TRY(upload(c, c->src_grid, sg)); PG_TRY(upload(c, c->src_index, si)); PG_TRY(upload(c, c->src_off, so));
+  PG_TRY(upload(c, c->src_t, st)); PG_TRY(upload(c, c->src_i, sv));
+  // flattened inductor list
+  std::vector<int32_t> ig, il;
+  for (int g = 0; g < G; ++g)
+    for (size_t k = 0; k < c->grids[g].ind_a.size(); ++k) { ig.push_back(g); il.push_back((int32_t)k); }
+  c->n_ind_total = (int)ig.size();
+  PG_TRY(upload(c, c->ind_grid, ig)); PG_TRY(upload(c, c->ind_local, il));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  c->dirty = false;
+  return PG_OK;
+}
+
+pg_status alloc_ctl(pg_ctx* c) {
+  const int G = (int)c->grids.size();
+  // grow the per-grid control arrays, preserving vidx (which buffer holds each grid's state)
+  std::vector<int32_t> vidx(G, 0);
+  if (c->c_vidx.p && G > 1)
+    HIP_TRY(c, hipMemcpy(vidx.data(), c->c_vidx.p, (G - 1) * sizeof(int32_t), hipMemcpyDeviceToHost));
+  PG_TRY(dalloc(c, c->c_norm, G * sizeof(unsigned long long)));
+  PG_TRY(dalloc(c, c->c_last, G * sizeof(double)));
+  PG_TRY(dalloc(c, c->c_active, G * sizeof(int32_t)));
+  PG_TRY(dalloc(c, c->c_vidx, G * sizeof(int32_t)));
+  PG_TRY(dalloc(c, c->c_sweeps, G * sizeof(int32_t)));
+  PG_TRY(dalloc(c, c->c_failed, G * sizeof(int32_t)));
+  HIP_TRY(c, hipMemcpy(c->c_vidx.p, vidx.data(), G * sizeof(int32_t), hipMemcpyHostToDevice));
+  HIP_TRY(c, hipMemset(c->c_norm.p, 0, G * sizeof(unsigned long long)));
+  HIP_TRY(c, hipMemset(c->c_last.p, 0, G * sizeof(double)));
+  HIP_TRY(c, hipMemset(c->c_active.p, 0, G * sizeof(int32_t)));
+  HIP_TRY(c, hipMemset(c->c_sweeps.p, 0, G * sizeof(int32_t)));
+  HIP_TRY(c, hipMemset(c->c_failed.p, 0, G * sizeof(int32_t)));
+  Ctl& k = c->ctl;
+  k.norm_bits = (unsigned long long*)c->c_norm.p;
+  k.last_norm = (double*)c->c_last.p;
+  k.active = (int32_t*)c->c_active.p;
+  k.vidx = (int32_t*)c->c_vidx.p;
+  k.step_sweeps = (int32_t*)c->c_sweeps.p;
+  k.failed = (int32_t*)c->c_failed.p;
+  return PG_OK;
+}
+
+pg_status reset_stats_dev(pg_ctx* c) {
+  HIP_TRY(c, hipMemsetAsync(c->c_stats64.p, 0, c->c_stats64.bytes, c->stream));
+  HIP_TRY(c, hipMemsetAsync(c->c_stats32.p, 0, c->c_stats32.bytes, c->stream));
+  HIP_TRY(c, hipMemsetAsync(c->c_statsd.p, 0, c->c_statsd.bytes, c->stream));
+  c->seconds = 0.0;
+  return PG_OK;
+}
+
+int32_t cur_vidx(pg_ctx* c, int g) {
+  int32_t v = 0;
+  (void)hipStreamSynchronize(c->stream);
+  (void)hipMemcpy(&v, (const int32_t*)c->c_vidx.p + g, sizeof v, hipMemcpyDeviceToHost);
+  return v;
+}
+
+pg_status check_gs(pg_ctx* c, int grid, int scen) {
+  if (!c) return PG_ERR_INVALID_ARG;
+  if (grid < 0 || grid >= (int)c->grids.size()) return set_err(c, PG_ERR_INVALID_ARG, "grid %d out of range", grid);
+  if (scen < 0 || scen >= c->grids[grid].S) return set_err(c, PG_ERR_INVALID_ARG, "scenario %d out of range", scen);
+  return PG_OK;
+}
+
+// ---- one backward-Euler step -----------------------------------------------------------
+pg_status launch_resid_all(pg_ctx* c, int has_d, int din) {
+  const Tile* T = (const Tile*)c->tiles_all.p;
+  for (auto& grp : c->tile_groups) {
+    ProfScope ps(c, 1, grp.nodes);
+    hipError_t e = launch_resid(fp32_mode(c), grp.nl, c->tile_rows, T + grp.off, grp.count,
+                                (const GridDesc*)c->grid_desc.p, c->ctl, has_d, din, c->stream);
+    if (e != hipSuccess) return set_err(c, PG_ERR_DEVICE, "residual launch: %s", hipGetErrorString(e));
+  }
+  return PG_OK;
+}
+
+pg_status launch_sweeps(pg_ctx* c, int nchk) {
+  const Tile* T = (const Tile*)c->tiles_all.p;
+  for (int s = 0; s < nchk; ++s) {
+    for (auto& grp : c->tile_groups) {
+      ProfScope ps(c, 0, grp.nodes);
+      hipError_t e = launch_sweep(fp32_mode(c), c->opt.ordering, grp.nl, c->tile_rows,
+                                  T + grp.off, grp.count,
+                                  (const GridDesc*)c->grid_desc.p, c->ctl, s & 1, s == 0 ? 1 : 0,
+                                  c->opt.omega, c->stream);
+      if (e != hipSuccess) return set_err(c, PG_ERR_DEVICE, "sweep launch: %s", hipGetErrorString(e));
+    }
+  }
+  return PG_OK;
+}
+
+pg_status one_step(pg_ctx* c) {
+  const int G = (int)c->grids.size();
+  const int nchk = c->opt.check_every;
+  const int L = c->opt.lookahead;
+  Ctl k = c->ctl;
+  const double t = (double)(c->step + 1) * c->opt.h;
+  hipError_t e;
+  {
+    ProfScope ps(c, 3, 0);
+    e = launch_step_begin(k, G, c->stream);
+    if (e != hipSuccess) return set_err(c, PG_ERR_DEVICE, "step launch: %s", hipGetErrorString(e));
+  }
+  {
+    ProfScope ps(c, 2, 0);
+    e = launch_rhs((const Tile*)c->tiles_all.p, c->ntiles_all, c->tile_rows, (const GridDesc*)c->grid_desc.p,
+                   k, c->stream);
+    if (e != hipSuccess) return set_err(c, PG_ERR_DEVICE, "rhs launch: %s", hipGetErrorString(e));
+  }
+  {
+    SourceTable st{c->n_src, (const int32_t*)c->src_grid.p, (const int32_t*)c->src_index.p,
+                   (const int32_t*)c->src_off.p, (const double*)c->src_t.p, (const double*)c->src_i.p};
+    ProfScope ps(c, 2, 0);
+    e = launch_sources(st, (const GridDesc*)c->grid_desc.p, t, c->stream);
+    if (e != hipSuccess) return set_err(c, PG_ERR_DEVICE, "source launch: %s", hipGetErrorString(e));
+  }
+  PG_TRY(launch_resid_all(c, 0, 0));
+  // decision after the initial residual goes to flag slot 0
+  const int nslots = (int)c->flag_events.size();
+  int slot = 0;
+  auto decide = [&](int has_d) -> pg_status {
+    Ctl kk = c->ctl;
+    kk.any_active = c->dev_flags + slot;
+    ProfScope ps(c, 3, 0);
+    hipError_t ee = launch_decide(kk, G, c->opt.tol, has_d, nchk, c->opt.max_sweeps, c->stream);
+    if (ee != hipSuccess) return set_err(c, PG_ERR_DEVICE, "decide launch: %s", hipGetErrorString(ee));
+    HIP_TRY(c, hipEventRecord(c->flag_events[slot], c->stream));
+    return PG_OK;
+  };
+  std::deque<int> pending;
+  PG_TRY(decide(0));
+  pending.push_back(slot);
+  slot = (slot + 1) % nslots;
+  const int din_final = nchk & 1;  // buffer holding the correction after nchk sweeps
+  const int max_chunks = (c->opt.max_sweeps + nchk - 1) / nchk;
+  int issued = 0;
+  // Keep up to `lookahead` refinement cycles queued beyond the one whose decision the host
+  // is waiting for; cycles queued after convergence find every grid inactive and exit at once.
+  while (true) {
+    while ((int)pending.size() <= L && issued < max_chunks) {
+      PG_TRY(launch_sweeps(c, nchk));
+      PG_TRY(launch_resid_all(c, 1, din_final));
+      PG_TRY(decide(1));
+      pending.push_back(slot);
+      slot = (slot + 1) % nslots;
+      ++issued;
+    }
+    if (pending.empty()) break;
+    const int s0 = pending.front();
+    pending.pop_front();
+    HIP_TRY(c, hipEventSynchronize(c->flag_events[s0]));
+    if (__atomic_load_n(c->host_flags + s0, __ATOMIC_ACQUIRE) == 0) break;
+  }
+  {
+    ProfScope ps(c, 3, 0);
+    e = launch_step_end(k, G, c->stream);
+    if (e != hipSuccess) return set_err(c, PG_ERR_DEVICE, "step-end launch: %s", hipGetErrorString(e));
+  }
+  if (c->n_ind_total) {
+    ProfScope ps(c, 3, 0);
+    e = launch_inductors((const GridDesc*)c->grid_desc.p, (const int32_t*)c->ind_grid.p,
+                         (const int32_t*)c->ind_local.p, c->n_ind_total, k, c->stream);
+    if (e != hipSuccess) return set_err(c, PG_ERR_DEVICE, "inductor launch: %s", hipGetErrorString(e));
+  }
+  c->step++;
+  return PG_OK;
+}
+
+pg_status fill_v(pg_ctx* c, GridHost& H, const double* v, int scen, int32_t vidx) {
+  // write the voltages of one scenario into the current buffer (scenario-minor layout)
+  std::vector<double> buf((size_t)H.n * H.S);
+  DBuf& dst = vidx ? H.v1 : H.v0;
+  if (H.S > 1) HIP_TRY(c, hipMemcpy(buf.data(), dst.p, buf.size() * sizeof(double), hipMemcpyDeviceToHost));
+  for (int64_t i = 0; i < H.n; ++i) buf[(size_t)i * H.S + scen] = v ? v[i] : H.vdd;
+  HIP_TRY(c, hipMemcpy(dst.p, buf.data(), buf.size() * sizeof(double), hipMemcpyHostToDevice));
+  return PG_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+pg_status pg_create(pg_ctx** out, int32_t device, void* stream) {
+  if (!out) return PG_ERR_INVALID_ARG;
+  *out = nullptr;
+  int count = 0;
+  if (hipGetDeviceCount(&count) != hipSuccess || count <= 0) return PG_ERR_DEVICE;
+  if (device < 0 || device >= count) return PG_ERR_INVALID_ARG;
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, device) != hipSuccess) return PG_ERR_DEVICE;
+  if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0) return PG_ERR_DEVICE;
+  if (hipSetDevice(device) != hipSuccess) return PG_ERR_DEVICE;
+  pg_ctx* c = new pg_ctx();
+  c->device = device;
+  pg_default_options(&c->opt);
+  if (stream) {
+    c->stream = (hipStream_t)stream;
+  } else {
+    if (hipStreamCreate(&c->stream) != hipSuccess) { delete c; return PG_ERR_DEVICE; }
+    c->own_stream = true;
+  }
+  const int nslots = 8;
+  if (hipHostMalloc((void**)&c->host_flags, nslots * sizeof(int32_t), hipHostMallocMapped | hipHostMallocCoherent) !=
+          hipSuccess ||
+      hipHostGetDevicePointer((void**)&c->dev_flags, c->host_flags, 0) != hipSuccess) {
+    pg_destroy(c);
+    return PG_ERR_DEVICE;
+  }
+  std::memset(c->host_flags, 0, nslots * sizeof(int32_t));
+  for (int i = 0; i < nslots; ++i) {
+    hipEvent_t e;
+    if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) { pg_destroy(c); return PG_ERR_DEVICE; }
+    c->flag_events.push_back(e);
+  }
+  if (dalloc(c, c->c_stats64, 3 * sizeof(long long)) != PG_OK || dalloc(c, c->c_stats32, 4 * sizeof(int32_t)) != PG_OK ||
+      dalloc(c, c->c_statsd, 2 * sizeof(double)) != PG_OK) {
+    pg_destroy(c);
+    return PG_ERR_OOM;
+  }
+  Ctl& k = c->ctl;
+  k.stat_sweeps = (long long*)c->c_stats64.p;
+  k.stat_updates = k.stat_sweeps + 1;
+  k.stat_checks = k.stat_sweeps + 2;
+  k.stat_last_sweeps = (int32_t*)c->c_stats32.p;
+  k.stat_max_sweeps = k.stat_last_sweeps + 1;
+  k.stat_failed = k.stat_last_sweeps + 2;
+  k.stat_last_res = (double*)c->c_statsd.p;
+  k.stat_max_res = k.stat_last_res + 1;
+  if (reset_stats_dev(c) != PG_OK || hipStreamSynchronize(c->stream) != hipSuccess) { pg_destroy(c); return PG_ERR_DEVICE; }
+  *out = c;
+  return PG_OK;
+}
+
+void pg_destroy(pg_ctx* c) {
+  if (!c) return;
+  (void)hipSetDevice(c->device);
+  if (c->stream) (void)hipStreamSynchronize(c->stream);
+  for (auto& H : c->grids) {
+    DBuf* bufs[] = {&H.gE64, &H.gN64, &H.gU64, &H.D64, &H.ch64, &H.bconst64, &H.gEs, &H.gNs, &H.gUs, &H.invDs,
+                    &H.v0, &H.v1, &H.b, &H.r, &H.d0, &H.d1, &H.ind_a_d, &H.ind_b_d, &H.ind_geq_d,
+                    &H.ind_alpha_d, &H.ind_i_d, &H.inc_off_d, &H.inc_ind_d};
+    for (DBuf* b : bufs) dfree(*b);
+  }
+  DBuf* bufs[] = {&c->grid_desc, &c->tiles_all, &c->src_grid, &c->src_index, &c->src_off, &c->src_t, &c->src_i,
+                  &c->ind_grid, &c->ind_local, &c->c_norm, &c->c_last, &c->c_active, &c->c_vidx, &c->c_sweeps,
+                  &c->c_failed, &c->c_any, &c->c_stats64, &c->c_stats32, &c->c_statsd, &c->c_nodes};
+  for (DBuf* b : bufs) dfree(*b);
+  for (auto e : c->flag_events) (void)hipEventDestroy(e);
+  for (auto& e : c->prof_live) { (void)hipEventDestroy(e.a); (void)hipEventDestroy(e.b); }
+  for (auto e : c->prof_pool) (void)hipEventDestroy(e);
+  if (c->host_flags) (void)hipHostFree(c->host_flags);
+  if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
+  delete c;
+}
+
+const char* pg_last_error(const pg_ctx* c) { return c ? c->err.c_str() : "null context"; }
+
+pg_status pg_set_options(pg_ctx* c, const pg_options* o) {
+  if (!c) return PG_ERR_INVALID_ARG;
+  char msg[256] = {0};
+  pg_status st = pg_validate_options(o, msg, sizeof msg);
+  if (st != PG_OK) return set_err(c, st, "%s", msg);
+  c->opt = *o;
+  c->dirty = true;
+  return PG_OK;
+}
+
+pg_status pg_get_options(const pg_ctx* c, pg_options* out) {
+  if (!c || !out) return PG_ERR_INVALID_ARG;
+  *out = c->opt;
+  return PG_OK;
+}
+
+pg_status pg_upload_mesh(pg_ctx* c, const pg_mesh* m, int32_t n_scen, int32_t* grid_id) {
+  if (!c) return PG_ERR_INVALID_ARG;
+  char msg[256] = {0};
+  pg_status st = pg_validate_mesh(m, msg, sizeof msg);
+  if (st != PG_OK) return set_err(c, st, "%s", msg);
+  if (n_scen < 1) return set_err(c, PG_ERR_INVALID_ARG, "n_scen must be >= 1");
+  if (n_scen > 1) return set_err(c, PG_ERR_UNSUPPORTED, "several scenarios per grid are not supported by this build");
+  HIP_TRY(c, hipSetDevice(c->device));
+  c->grids.emplace_back();
+  GridHost& H = c->grids.back();
+  H.nx = m->nx; H.ny = m->ny; H.nl = m->nl; H.S = n_scen;
+  H.P = (int64_t)m->nx * m->ny; H.n = H.P * m->nl; H.vdd = m->vdd;
+  H.gE.assign(m->gE, m->gE + (size_t)m->nl * m->ny * (m->nx - 1));
+  H.gN.assign(m->gN, m->gN + (size_t)m->nl * (m->ny - 1) * m->nx);
+  H.C.assign(m->C, m->C + H.n);
+  H.via_node.assign(m->via_node, m->via_node + m->n_vias);
+  H.via_g.assign(m->via_g, m->via_g + m->n_vias);
+  if (m->via_L) H.via_L.assign(m->via_L, m->via_L + m->n_vias);
+  H.pad_node.assign(m->pad_node, m->pad_node + m->n_pads);
+  H.pad_g.assign(m->pad_g, m->pad_g + m->n_pads);
+  if (m->pad_L) H.pad_L.assign(m->pad_L, m->pad_L + m->n_pads);
+  H.src.assign(n_scen, Src{});
+  for (auto& s : H.src) s.off = {0};
+  const size_t ns = (size_t)H.n * H.S;
+  pg_status ps;
+  if ((ps = dalloc(c, H.v0, ns * sizeof(double))) != PG_OK || (ps = dalloc(c, H.v1, ns * sizeof(double))) != PG_OK ||
+      (ps = dalloc(c, H.b, ns * sizeof(double))) != PG_OK) {
+    c->grids.pop_back();
+    return ps;
+  }
+  std::vector<double> vinit(ns, H.vdd);
+  HIP_TRY(c, hipMemcpy(H.v0.p, vinit.data(), ns * sizeof(double), hipMemcpyHostToDevice));
+  HIP_TRY(c, hipMemcpy(H.v1.p, vinit.data(), ns * sizeof(double), hipMemcpyHostToDevice));
+  PG_TRY(alloc_ctl(c));
+  c->dirty = true;
+  if (grid_id) *grid_id = (int32_t)c->grids.size() - 1;
+  return PG_OK;
+}
+
+pg_status pg_set_pwl(pg_ctx* c, int32_t grid, int32_t scen, int32_t n_src, const int32_t* node,
+                     const int32_t* offsets, const double* t, const double* i) {
+  PG_TRY(check_gs(c, grid, scen));
+  GridHost& H = c->grids[grid];
+  if (n_src < 0 || (n_src > 0 && (!node || !offsets || !t || !i)))
+    return set_err(c, PG_ERR_INVALID_ARG, "bad source arrays");
+  if (n_src > 0 && offsets[0] != 0) return set_err(c, PG_ERR_INVALID_ARG, "offsets[0] must be 0");
+  std::vector<char> seen(H.n, 0);
+  for (int k = 0; k < n_src; ++k) {
+    if (node[k] < 0 || node[k] >= H.n) return set_err(c, PG_ERR_INVALID_ARG, "source %d: node out of range", k);
+    if (seen[node[k]]) return set_err(c, PG_ERR_INVALID_ARG, "source %d: node %d already has a source", k, node[k]);
+    seen[node[k]] = 1;
+    if (offsets[k + 1] <= offsets[k]) return set_err(c, PG_ERR_INVALID_ARG, "source %d: no breakpoints", k);
+    for (int j = offsets[k]; j < offsets[k + 1]; ++j) {
+      if (!std::isfinite(t[j]) || !std::isfinite(i[j])) return set_err(c, PG_ERR_INVALID_ARG, "source %d: non-finite breakpoint", k);
+      if (j > offsets[k] && !(t[j] > t[j - 1])) return set_err(c, PG_ERR_INVALID_ARG, "source %d: times not increasing", k);
+    }
+  }
+  Src S;
+  S.node.assign(node, node + n_src);
+  S.off.assign(offsets, offsets + n_src + 1);
+  if (n_src == 0) S.off = {0};
+  const int nb = n_src ? offsets[n_src] : 0;
+  S.t.assign(t ? t : nullptr, t ? t + nb : nullptr);
+  S.i.assign(i ? i : nullptr, i ? i + nb : nullptr);
+  H.src[scen] = std::move(S);
+  c->dirty = true;
+  return PG_OK;
+}
+
+pg_status pg_set_pulses(pg_ctx* c, int32_t grid, int32_t scen, int32_t n_src, const int32_t* node,
+                        const double* peak, const double* start, const double* width) {
+  PG_TRY(check_gs(c, grid, scen));
+  if (n_src < 0 || (n_src > 0 && (!node || !peak || !start || !width)))
+    return set_err(c, PG_ERR_INVALID_ARG, "bad pulse arrays");
+  std::vector<int32_t> off(n_src + 1);
+  std::vector<double> t(3 * (size_t)n_src), i(3 * (size_t)n_src);
+  for (int k = 0; k < n_src; ++k) {
+    if (!(std::isfinite(width[k]) && width[k] > 0) || !std::isfinite(start[k]) || !std::isfinite(peak[k]))
+      return set_err(c, PG_ERR_INVALID_ARG, "pulse %d: width must be > 0 and values finite", k);
+    off[k] = 3 * k;
+    const double half = 0.5 * width[k];
+    t[3 * k] = start[k]; t[3 * k + 1] = start[k] + half; t[3 * k + 2] = start[k] + width[k];
+    i[3 * k] = 0.0; i[3 * k + 1] = peak[k]; i[3 * k + 2] = 0.0;
+  }
+  off[n_src] = 3 * n_src;
+  return pg_set_pwl(c, grid, scen, n_src, node, off.data(), t.data(), i.data());
+}
+
+pg_status pg_set_state(pg_ctx* c, int32_t grid, int32_t scen, const double* v, const double* i_l) {
+  PG_TRY(check_gs(c, grid, scen));
+  HIP_TRY(c, hipSetDevice(c->device));
+  GridHost& H = c->grids[grid];
+  if (v)
+    for (int64_t k = 0; k < H.n; ++k)
+      if (!std::isfinite(v[k])) return set_err(c, PG_ERR_INVALID_ARG, "v[%lld] is not finite", (long long)k);
+  PG_TRY(prepare(c));
+  PG_TRY(fill_v(c, H, v, scen, cur_vidx(c, grid)));
+  const int ni = (int)H.ind_a.size();
+  if (ni) {
+    std::vector<double> buf((size_t)ni * H.S);
+    HIP_TRY(c, hipMemcpy(buf.data(), H.ind_i_d.p, buf.size() * sizeof(double), hipMemcpyDeviceToHost));
+    for (int k = 0; k < ni; ++k) buf[(size_t)k * H.S + scen] = i_l ? i_l[H.ind_branch[k]] : 0.0;
+    HIP_TRY(c, hipMemcpy(H.ind_i_d.p, buf.data(), buf.size() * sizeof(double), hipMemcpyHostToDevice));
+  }
+  return PG_OK;
+}
+
+pg_status pg_reset(pg_ctx* c) {
+  if (!c) return PG_ERR_INVALID_ARG;
+  HIP_TRY(c, hipSetDevice(c->device));
+  PG_TRY(prepare(c));
+  for (int g = 0; g < (int)c->grids.size(); ++g)
+    for (int s = 0; s < c->grids[g].S; ++s) PG_TRY(pg_set_state(c, g, s, nullptr, nullptr));
+  c->step = 0;
+  PG_TRY(reset_stats_dev(c));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  return PG_OK;
+}
+
+pg_status pg_step(pg_ctx* c, int32_t nsteps) { return pg_run_transient(c, nsteps, 1, 0, 0, nullptr); }
+
+pg_status pg_run_transient(pg_ctx* c, int32_t nsteps, int32_t record_every, int32_t grid, int32_t scen,
+                           double* out) {
+  if (!c) return PG_ERR_INVALID_ARG;
+  if (nsteps < 0 || record_every < 1) return set_err(c, PG_ERR_INVALID_ARG, "nsteps >= 0 and record_every >= 1 required");
+  HIP_TRY(c, hipSetDevice(c->device));
+  PG_TRY(prepare(c));
+  if (out) PG_TRY(check_gs(c, grid, scen));
+  const auto t0 = std::chrono::steady_clock::now();
+  int rec = 0;
+  for (int k = 0; k < nsteps; ++k) {
+    PG_TRY(one_step(c));
+    if (out && ((k + 1) % record_every) == 0) {
+      PG_TRY(pg_read_voltages(c, grid, scen, out + (size_t)rec * c->grids[grid].n, c->grids[grid].n));
+      ++rec;
+    }
+  }
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  c->seconds += std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  int32_t failed = 0;
+  HIP_TRY(c, hipMemcpy(&failed, c->ctl.stat_failed, sizeof failed, hipMemcpyDeviceToHost));
+  if (failed) {
+    HIP_TRY(c, hipMemsetAsync(c->ctl.stat_failed, 0, sizeof(int32_t), c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    return set_err(c, PG_ERR_NO_CONVERGENCE, "a step reached max_sweeps = %d with the residual above tol = %g",
+                   c->opt.max_sweeps, c->opt.tol);
+  }
+  return PG_OK;
+}
+
+pg_status pg_get_time(const pg_ctx* c, int64_t* step) {
+  if (!c || !step) return PG_ERR_INVALID_ARG;
+  *step = c->step;
+  return PG_OK;
+}
+
+pg_status pg_read_voltages(pg_ctx* c, int32_t grid, int32_t scen, double* out, int64_t n) {
+  PG_TRY(check_gs(c, grid, scen));
+  GridHost& H = c->grids[grid];
+  if (!out || n < H.n) return set_err(c, PG_ERR_INVALID_ARG, "output buffer too small (need %lld)", (long long)H.n);
+  HIP_TRY(c, hipSetDevice(c->device));
+  const int32_t vi = cur_vidx(c, grid);
+  DBuf& src = vi ? H.v1 : H.v0;
+  if (H.S == 1) {
+    HIP_TRY(c, hipMemcpy(out, src.p, H.n * sizeof(double), hipMemcpyDeviceToHost));
+  } else {
+    std::vector<double> buf((size_t)H.n * H.S);
+    HIP_TRY(c, hipMemcpy(buf.data(), src.p, buf.size() * sizeof(double), hipMemcpyDeviceToHost));
+    for (int64_t i = 0; i < H.n; ++i) out[i] = buf[(size_t)i * H.S + scen];
+  }
+  return PG_OK;
+}
+
+pg_status pg_read_voltages_dev(pg_ctx* c, int32_t grid, int32_t scen, double* dev_out, int64_t n) {
+  PG_TRY(check_gs(c, grid, scen));
+  GridHost& H = c->grids[grid];
+  if (!dev_out || n < H.n) return set_err(c, PG_ERR_INVALID_ARG, "output buffer too small");
+  if (H.S != 1) return set_err(c, PG_ERR_UNSUPPORTED, "device read of one scenario of a batched grid");
+  HIP_TRY(c, hipSetDevice(c->device));
+  const int32_t vi = cur_vidx(c, grid);
+  DBuf& src = vi ? H.v1 : H.v0;
+  HIP_TRY(c, hipMemcpyAsync(dev_out, src.p, H.n * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+  return PG_OK;
+}
+
+pg_status pg_read_inductor_currents(pg_ctx* c, int32_t grid, int32_t scen, double* out, int64_t n) {
+  PG_TRY(check_gs(c, grid, scen));
+  GridHost& H = c->grids[grid];
+  const int64_t nb = (int64_t)H.via_node.size() + (int64_t)H.pad_node.size();
+  if (!out || n < nb) return set_err(c, PG_ERR_INVALID_ARG, "output buffer too small (need %lld)", (long long)nb);
+  HIP_TRY(c, hipSetDevice(c->device));
+  PG_TRY(prepare(c));
+  std::fill(out, out + nb, 0.0);
+  const int ni = (int)H.ind_a.size();
+  if (!ni) return PG_OK;
+  std::vector<double> buf((size_t)ni * H.S);
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  HIP_TRY(c, hipMemcpy(buf.data(), H.ind_i_d.p, buf.size() * sizeof(double), hipMemcpyDeviceToHost));
+  for (int k = 0; k < ni; ++k) out[H.ind_branch[k]] = buf[(size_t)k * H.S + scen];
+  return PG_OK;
+}
+
+pg_status pg_get_stats(const pg_ctx* cc, pg_stats* out) {
+  if (!cc || !out) return PG_ERR_INVALID_ARG;
+  pg_ctx* c = const_cast<pg_ctx*>(cc);
+  HIP_TRY(c, hipSetDevice(c->device));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  long long s64[3];
+  int32_t s32[4];
+  double sd[2];
+  HIP_TRY(c, hipMemcpy(s64, c->c_stats64.p, sizeof s64, hipMemcpyDeviceToHost));
+  HIP_TRY(c, hipMemcpy(s32, c->c_stats32.p, sizeof(int32_t) * 3, hipMemcpyDeviceToHost));
+  HIP_TRY(c, hipMemcpy(sd, c->c_statsd.p, sizeof sd, hipMemcpyDeviceToHost));
+  std::memset(out, 0, sizeof *out);
+  out->steps = c->step;
+  out->sweeps = s64[0];
+  out->node_updates = s64[1];
+  out->checks = s64[2];
+  out->last_step_sweeps = s32[0];
+  out->max_step_sweeps = s32[1];
+  out->last_residual = sd[0];
+  out->max_final_residual = sd[1];
+  out->seconds = c->seconds;
+  return PG_OK;
+}
+
+pg_status pg_reset_stats(pg_ctx* c) {
+  if (!c) return PG_ERR_INVALID_ARG;
+  HIP_TRY(c, hipSetDevice(c->device));
+  PG_TRY(reset_stats_dev(c));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  return PG_OK;
+}
+
+pg_status pg_profile(pg_ctx* c, int32_t enable) {
+  if (!c || enable < 0) return PG_ERR_INVALID_ARG;
+  c->profile_every = enable;
+  c->launch_counter = 0;
+  return PG_OK;
+}
+
+pg_status pg_read_kernel_times(pg_ctx* c, pg_kernel_times* out) {
+  if (!c || !out) return PG_ERR_INVALID_ARG;
+  HIP_TRY(c, hipSetDevice(c->device));
+  prof_drain(c);
+  *out = c->prof_acc;
+  std::memset(&c->prof_acc, 0, sizeof c->prof_acc);
+  return PG_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,328 @@
+"""ctypes binding of ``libpgrid.so`` (the C ABI declared in ``include/pgrid.h``).
+
+Argument marshalling only: every step of the transient runs in the library's HIP
+kernels.  Host arrays are passed as contiguous numpy buffers; device outputs can
+be torch tensors on the context's device, whose stream the context may share.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libpgrid.so")
+
+PG_PREC_FP64 = 0
+PG_PREC_FP32_REFINE = 1
+PG_ORDER_RED_BLACK = 0
+PG_ORDER_JACOBI = 1
+
+STATUS = {0: "PG_OK", -1: "PG_ERR_INVALID_ARG", -2: "PG_ERR_TOPOLOGY", -3: "PG_ERR_NOT_SPD",
+          -4: "PG_ERR_NO_CONVERGENCE", -5: "PG_ERR_DEVICE", -6: "PG_ERR_OOM", -7: "PG_ERR_STATE",
+          -8: "PG_ERR_UNSUPPORTED"}
+
+
+class PgError(RuntimeError):
+    def __init__(self, status, message):
+        super().__init__(f"{STATUS.get(status, status)}: {message}")
+        self.status = status
+        self.name = STATUS.get(status, str(status))
+
+
+class Options(C.Structure):
+    _fields_ = [("h", C.c_double), ("tol", C.c_double), ("omega", C.c_double),
+                ("max_sweeps", C.c_int32), ("check_every", C.c_int32), ("precision", C.c_int32),
+                ("ordering", C.c_int32), ("tile_rows", C.c_int32), ("lookahead", C.c_int32),
+                ("reserved", C.c_int32 * 6)]
+
+
+class MeshStruct(C.Structure):
+    _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("nl", C.c_int32),
+                ("gE", C.POINTER(C.c_double)), ("gN", C.POINTER(C.c_double)), ("C", C.POINTER(C.c_double)),
+                ("n_vias", C.c_int32), ("via_node", C.POINTER(C.c_int32)), ("via_g", C.POINTER(C.c_double)),
+                ("via_L", C.POINTER(C.c_double)),
+                ("n_pads", C.c_int32), ("pad_node", C.POINTER(C.c_int32)), ("pad_g", C.POINTER(C.c_double)),
+                ("pad_L", C.POINTER(C.c_double)), ("vdd", C.c_double)]
+
+
+class Stats(C.Structure):
+    _fields_ = [("steps", C.c_int64), ("sweeps", C.c_int64), ("node_updates", C.c_int64),
+                ("checks", C.c_int64), ("last_step_sweeps", C.c_int32), ("max_step_sweeps", C.c_int32),
+                ("last_residual", C.c_double), ("max_final_residual", C.c_double), ("seconds", C.c_double)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+class KernelTimes(C.Structure):
+    _fields_ = [("sweep_launches", C.c_int64), ("sweep_ms", C.c_double), ("sweep_node_updates", C.c_int64),
+                ("resid_launches", C.c_int64), ("resid_ms", C.c_double), ("resid_nodes", C.c_int64),
+                ("rhs_launches", C.c_int64), ("rhs_ms", C.c_double),
+                ("other_launches", C.c_int64), ("other_ms", C.c_double)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+_lib = None
+
+EXPORTS = {
+    "pg_abi_version": (C.c_int32, []),
+    "pg_status_name": (C.c_char_p, [C.c_int32]),
+    "pg_default_options": (C.c_int, [C.POINTER(Options)]),
+    "pg_validate_options": (C.c_int, [C.POINTER(Options), C.c_char_p, C.c_size_t]),
+    "pg_validate_mesh": (C.c_int, [C.POINTER(MeshStruct), C.c_char_p, C.c_size_t]),
+    "pg_validate_netlist": (C.c_int, [C.c_int32, C.c_int32, C.c_int32, C.POINTER(C.c_int32),
+                                      C.POINTER(C.c_int32), C.POINTER(C.c_uint8), C.POINTER(C.c_double),
+                                      C.c_char_p, C.c_size_t]),
+    "pg_create": (C.c_int, [C.POINTER(C.c_void_p), C.c_int32, C.c_void_p]),
+    "pg_destroy": (None, [C.c_void_p]),
+    "pg_last_error": (C.c_char_p, [C.c_void_p]),
+    "pg_set_options": (C.c_int, [C.c_void_p, C.POINTER(Options)]),
+    "pg_get_options": (C.c_int, [C.c_void_p, C.POINTER(Options)]),
+    "pg_upload_mesh": (C.c_int, [C.c_void_p, C.POINTER(MeshStruct), C.c_int32, C.POINTER(C.c_int32)]),
+    "pg_set_pulses": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.POINTER(C.c_int32),
+                                C.POINTER(C.c_double), C.POINTER(C.c_double), C.POINTER(C.c_double)]),
+    "pg_set_pwl": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.POINTER(C.c_int32),
+                             C.POINTER(C.c_int32), C.POINTER(C.c_double), C.POINTER(C.c_double)]),
+    "pg_set_state": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_double)]),
+    "pg_reset": (C.c_int, [C.c_void_p]),
+    "pg_step": (C.c_int, [C.c_void_p, C.c_int32]),
+    "pg_run_transient": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.c_int32,
+                                   C.POINTER(C.c_double)]),
+    "pg_get_time": (C.c_int, [C.c_void_p, C.POINTER(C.c_int64)]),
+    "pg_read_voltages": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.POINTER(C.c_double), C.c_int64]),
+    "pg_read_voltages_dev": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_void_p, C.c_int64]),
+    "pg_read_inductor_currents": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.POINTER(C.c_double), C.c_int64]),
+    "pg_get_stats": (C.c_int, [C.c_void_p, C.POINTER(Stats)]),
+    "pg_reset_stats": (C.c_int, [C.c_void_p]),
+    "pg_profile": (C.c_int, [C.c_void_p, C.c_int32]),
+    "pg_read_kernel_times": (C.c_int, [C.c_void_p, C.POINTER(KernelTimes)]),
+}
+
+
+def lib():
+    """Load libpgrid.so (built in-tree by ``paper_1409_7166_amd.build``); fail loudly if absent."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: run `python -m paper_1409_7166_amd.build` "
+                               "(the transient has no CPU fallback)")
+        L = C.CDLL(LIB_PATH)
+        for name, (res, args) in EXPORTS.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _dp(a):
+    return a.ctypes.data_as(C.POINTER(C.c_double)) if a is not None else None
+
+
+def _ip(a):
+    return a.ctypes.data_as(C.POINTER(C.c_int32)) if a is not None else None
+
+
+def _f64(a):
+    return None if a is None else np.ascontiguousarray(a, dtype=np.float64)
+
+
+def _i32(a):
+    return None if a is None else np.ascontiguousarray(a, dtype=np.int32)
+
+
+@dataclass
+class _MeshHold:
+    """Keeps the numpy buffers behind a MeshStruct alive."""
+    struct: MeshStruct
+    arrays: tuple
+
+
+def mesh_struct(mesh) -> _MeshHold:
+    """Marshal an object with the ``workloads.Mesh`` attributes into a ``pg_mesh``."""
+    arrs = dict(gE=_f64(mesh.gE), gN=_f64(mesh.gN), C=_f64(mesh.C), via_node=_i32(mesh.via_node),
+                via_g=_f64(mesh.via_g), via_L=_f64(mesh.via_L), pad_node=_i32(mesh.pad_node),
+                pad_g=_f64(mesh.pad_g), pad_L=_f64(mesh.pad_L))
+    nv, npd = int(arrs["via_node"].size), int(arrs["pad_node"].size)
+    s = MeshStruct(int(mesh.nx), int(mesh.ny), int(mesh.nl), _dp(arrs["gE"]), _dp(arrs["gN"]), _dp(arrs["C"]),
+                   nv, _ip(arrs["via_node"]), _dp(arrs["via_g"]),
+                   _dp(arrs["via_L"]) if arrs["via_L"] is not None and arrs["via_L"].size else None,
+                   npd, _ip(arrs["pad_node"]), _dp(arrs["pad_g"]),
+                   _dp(arrs["pad_L"]) if arrs["pad_L"] is not None and arrs["pad_L"].size else None,
+                   float(mesh.vdd))
+    return _MeshHold(s, tuple(arrs.values()))
+
+
+def _msgbuf():
+    return C.create_string_buffer(512)
+
+
+def validate_mesh(mesh):
+    """Host-only check; returns (status, message)."""
+    hold = mesh_struct(mesh)
+    buf = _msgbuf()
+    st = lib().pg_validate_mesh(C.byref(hold.struct), buf, 512)
+    return st, buf.value.decode()
+
+
+def validate_netlist(n, p, frm, to, kind, value):
+    """Host-only check of a branch list (kinds 'R', 'C', 'L', 'I'); returns (status, message)."""
+    frm, to, value = _i32(frm), _i32(to), _f64(value)
+    k = np.asarray(kind)
+    if k.dtype.kind in "US":
+        k = np.frombuffer("".join(k.astype(str).ravel().tolist()).encode(), np.uint8)
+    k = np.ascontiguousarray(k, dtype=np.uint8)
+    buf = _msgbuf()
+    st = lib().pg_validate_netlist(int(n), int(p), int(frm.size), _ip(frm), _ip(to),
+                                   k.ctypes.data_as(C.POINTER(C.c_uint8)), _dp(value), buf, 512)
+    return st, buf.value.decode()
+
+
+def default_options(**kw) -> Options:
+    o = Options()
+    lib().pg_default_options(C.byref(o))
+    for k, v in kw.items():
+        if not hasattr(o, k):
+            raise KeyError(k)
+        setattr(o, k, v)
+    return o
+
+
+def validate_options(o: Options):
+    buf = _msgbuf()
+    st = lib().pg_validate_options(C.byref(o), buf, 512)
+    return st, buf.value.decode()
+
+
+class Context:
+    """One pg_ctx on one GPU.  ``stream`` is a hipStream_t handle (int) or None."""
+
+    def __init__(self, device: int = 0, stream=None):
+        L = lib()
+        h = C.c_void_p()
+        st = L.pg_create(C.byref(h), int(device), C.c_void_p(stream) if stream else None)
+        if st != 0:
+            raise PgError(st, f"pg_create(device={device}) failed")
+        self._h = h
+        self.meshes = []
+
+    # -- plumbing ------------------------------------------------------------------------
+    def _check(self, st):
+        if st != 0:
+            raise PgError(st, lib().pg_last_error(self._h).decode())
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().pg_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    # -- configuration -----------------------------------------------------------------------
+    def set_options(self, **kw) -> Options:
+        o = Options()
+        self._check(lib().pg_get_options(self._h, C.byref(o)))
+        for k, v in kw.items():
+            if not hasattr(o, k):
+                raise KeyError(k)
+            setattr(o, k, v)
+        self._check(lib().pg_set_options(self._h, C.byref(o)))
+        return o
+
+    def options(self) -> dict:
+        o = Options()
+        self._check(lib().pg_get_options(self._h, C.byref(o)))
+        return {f: getattr(o, f) for f, _ in Options._fields_ if f != "reserved"}
+
+    def upload_mesh(self, mesh, n_scen: int = 1) -> int:
+        hold = mesh_struct(mesh)
+        gid = C.c_int32()
+        self._check(lib().pg_upload_mesh(self._h, C.byref(hold.struct), int(n_scen), C.byref(gid)))
+        self.meshes.append(mesh)
+        return gid.value
+
+    def set_pulses(self, grid: int, scen: int, pulses):
+        node, peak = _i32(pulses.node), _f64(pulses.peak)
+        start, width = _f64(pulses.start), _f64(pulses.width)
+        self._check(lib().pg_set_pulses(self._h, grid, scen, int(node.size), _ip(node), _dp(peak),
+                                        _dp(start), _dp(width)))
+
+    def set_pwl(self, grid: int, scen: int, node, offsets, t, i):
+        node, offsets, t, i = _i32(node), _i32(offsets), _f64(t), _f64(i)
+        self._check(lib().pg_set_pwl(self._h, grid, scen, int(node.size), _ip(node), _ip(offsets),
+                                     _dp(t), _dp(i)))
+
+    def set_state(self, grid: int, scen: int, v=None, i_l=None):
+        v, i_l = _f64(v), _f64(i_l)
+        self._check(lib().pg_set_state(self._h, grid, scen, _dp(v), _dp(i_l)))
+
+    def reset(self):
+        self._check(lib().pg_reset(self._h))
+
+    # -- stepping --------------------------------------------------------------------------
+    def step(self, nsteps: int = 1):
+        self._check(lib().pg_step(self._h, int(nsteps)))
+
+    def run_transient(self, nsteps: int, record_every: int = 1, grid: int = 0, scen: int = 0):
+        mesh = self.meshes[grid]
+        n = int(mesh.nx) * int(mesh.ny) * int(mesh.nl)
+        out = np.empty((nsteps // record_every, n))
+        self._check(lib().pg_run_transient(self._h, int(nsteps), int(record_every), grid, scen,
+                                           _dp(out) if out.size else None))
+        return out
+
+    def time_index(self) -> int:
+        k = C.c_int64()
+        self._check(lib().pg_get_time(self._h, C.byref(k)))
+        return k.value
+
+    # -- reads ---------------------------------------------------------------------------------
+    def read_voltages(self, grid: int = 0, scen: int = 0) -> np.ndarray:
+        mesh = self.meshes[grid]
+        n = int(mesh.nx) * int(mesh.ny) * int(mesh.nl)
+        out = np.empty(n)
+        self._check(lib().pg_read_voltages(self._h, grid, scen, _dp(out), n))
+        return out
+
+    def read_voltages_dev(self, grid: int, scen: int, tensor):
+        """Copy into a float64 CUDA tensor (queued on the context stream)."""
+        self._check(lib().pg_read_voltages_dev(self._h, grid, scen, C.c_void_p(tensor.data_ptr()),
+                                               int(tensor.numel())))
+
+    def read_inductor_currents(self, grid: int = 0, scen: int = 0) -> np.ndarray:
+        mesh = self.meshes[grid]
+        nb = int(np.asarray(mesh.via_node).size + np.asarray(mesh.pad_node).size)
+        out = np.zeros(max(nb, 1))
+        self._check(lib().pg_read_inductor_currents(self._h, grid, scen, _dp(out), nb))
+        return out[:nb]
+
+    def stats(self) -> dict:
+        s = Stats()
+        self._check(lib().pg_get_stats(self._h, C.byref(s)))
+        return s.as_dict()
+
+    def reset_stats(self):
+        self._check(lib().pg_reset_stats(self._h))
+
+    def profile(self, every: int = 1):
+        self._check(lib().pg_profile(self._h, int(every)))
+
+    def kernel_times(self) -> dict:
+        k = KernelTimes()
+        self._check(lib().pg_read_kernel_times(self._h, C.byref(k)))
+        return k.as_dict()

@@ -1,0 +1,144 @@
+"""GPU parity: the HIP transient (through the C ABI) against the FP64 oracle.
+
+Bar: max |v_gpu - v_oracle| <= 1e-6 V for every node and every step, at a stopping
+tolerance tight enough for that bar (the tolerance-to-error relation is stated per test).
+"""
+import numpy as np
+import pytest
+
+import paper_1409_7166_amd as pg
+from helpers import PARITY_V, compressed, gpu_context, oracle_run, say
+from oracle import BEStepper, dc_solve, mesh_to_circuit
+from workloads import Pulses, config0, small_multilayer, small_rc, small_rlc
+
+pytestmark = pytest.mark.gpu
+
+
+def _run_and_compare(w, steps, **opts):
+    mesh, p = w.meshes[0], w.pulses[0][0]
+    say(f"[gpu] {w.name} steps={steps} opts={opts}")
+    with gpu_context(w, **opts) as ctx:
+        V = ctx.run_transient(steps)
+        st = ctx.stats()
+    Vref, _ = oracle_run(mesh, p, w.h, steps)
+    err = np.max(np.abs(V - Vref), axis=1)
+    say(f"  sweeps={st['sweeps']} max_step_sweeps={st['max_step_sweeps']} "
+        f"max_err={err.max():.3e} V final_res={st['last_residual']:.2e}")
+    return err, st, V, Vref
+
+
+@pytest.mark.parametrize("prec", [pg.PG_PREC_FP64, pg.PG_PREC_FP32_REFINE])
+def test_config0_parity_every_node_every_step(prec):
+    w = config0()
+    err, st, V, Vref = _run_and_compare(w, 100, precision=prec, tol=1e-10, omega=1.6)
+    assert err.max() <= PARITY_V
+    assert st["steps"] == 100 and st["sweeps"] > 0
+    assert np.max(1.0 - Vref) > 1e-3  # the pulses produce a real drop
+
+
+def test_config0_jacobi_ordering_same_fixed_point():
+    w = config0()
+    err, st, _, _ = _run_and_compare(w, 60, ordering=pg.PG_ORDER_JACOBI, omega=0.9, tol=1e-10,
+                                     max_sweeps=20000)
+    assert err.max() <= PARITY_V
+
+
+@pytest.mark.parametrize("prec", [pg.PG_PREC_FP64, pg.PG_PREC_FP32_REFINE])
+def test_three_layer_ragged_parity(prec):
+    """3 layers, 100 x 100 (ragged against 64-wide, 16-row tiles), vias every 4, pads every 32."""
+    w = small_multilayer(side=100, seed=31, nl=3, pad_every=32, steps=60)
+    w.pulses[0][0] = compressed(w.pulses[0][0], start=0.08, width=1.0)
+    err, st, _, _ = _run_and_compare(w, 60, precision=prec, tol=1e-11, omega=1.8, check_every=16)
+    assert err.max() <= PARITY_V
+
+
+@pytest.mark.parametrize("rows", [8, 32])
+def test_tile_rows_do_not_change_the_result(rows):
+    w = small_multilayer(side=90, seed=32, nl=2, pad_every=30, steps=30)
+    w.pulses[0][0] = compressed(w.pulses[0][0], start=0.05, width=1.0)
+    err, _, _, _ = _run_and_compare(w, 30, tile_rows=rows, tol=1e-11, omega=1.7)
+    assert err.max() <= PARITY_V
+
+
+@pytest.mark.parametrize("prec", [pg.PG_PREC_FP64, pg.PG_PREC_FP32_REFINE])
+def test_rlc_ragged_parity_voltages_and_currents(prec):
+    """Series R-L vias and pads (eq. 10): node voltages and branch currents every step."""
+    w = small_rlc(side=70, seed=33, steps=150)
+    mesh = w.meshes[0]
+    p = compressed(w.pulses[0][0], start=0.2, width=0.5, peak=2.0)
+    w.pulses[0][0] = p
+    steps = 150
+    say(f"[gpu] rlc 2x70x70 prec={prec}")
+    circ, info = mesh_to_circuit(mesh, p)
+    st = BEStepper(circ, w.h)
+    from oracle.transient import initial_state
+    from oracle.sources import currents_at
+    v, il = initial_state(circ, info, mesh.vdd)
+    worst_v = worst_i = 0.0
+    with gpu_context(w, precision=prec, tol=1e-12, omega=1.9, check_every=16, max_sweeps=50000) as ctx:
+        for k in range(1, steps + 1):
+            v, il = st.step(v, il, currents_at(p, k * w.h))
+            ctx.step(1)
+            vg = ctx.read_voltages()
+            ig = ctx.read_inductor_currents()
+            worst_v = max(worst_v, float(np.max(np.abs(vg - v[: mesh.n]))))
+            worst_i = max(worst_i, float(np.max(np.abs(ig - il))))
+        stats = ctx.stats()
+    say(f"  sweeps={stats['sweeps']} max_err_v={worst_v:.3e} V max_err_i={worst_i:.3e} A")
+    assert worst_v <= PARITY_V
+    assert worst_i <= 1e-6 * max(1.0, float(np.max(np.abs(il))))
+    assert np.max(np.abs(il)) > 1e-5
+
+
+def test_zero_current_stays_at_vdd():
+    w = small_multilayer(side=80, seed=34, nl=3, pad_every=16, steps=20)
+    p = w.pulses[0][0]
+    w.pulses[0][0] = Pulses(p.node, np.zeros_like(p.peak), p.start, p.width)
+    say("[gpu] zero current")
+    with gpu_context(w, precision=pg.PG_PREC_FP32_REFINE, tol=1e-12) as ctx:
+        V = ctx.run_transient(20)
+    assert np.max(np.abs(V - 1.0)) <= 1e-12
+
+
+def test_dc_steady_state_matches_direct_solve():
+    """Constant sources and a long step: the transient settles on the DC point (eq. 3, A = G)."""
+    w = small_rc(48, 40, seed=35, steps=1)
+    mesh = w.meshes[0]
+    rng = np.random.default_rng(7)
+    nodes = np.arange(0, mesh.n, 3, dtype=np.int32)
+    I = rng.uniform(0, 2e-3, nodes.size)
+    say("[gpu] dc steady state")
+    with gpu_context(w, h=1e-9, tol=1e-12, omega=1.9, max_sweeps=200000) as ctx:
+        ctx.set_pwl(0, 0, nodes, np.arange(nodes.size + 1, dtype=np.int32), np.zeros(nodes.size), I)
+        ctx.step(400)
+        vg = ctx.read_voltages()
+    p = Pulses(nodes, I, np.zeros(nodes.size), np.ones(nodes.size))
+    circ, info = mesh_to_circuit(mesh, p)
+    vdc, _ = dc_solve(circ, I)
+    err = np.max(np.abs(vg - vdc[: mesh.n]))
+    say(f"  dc err={err:.3e}")
+    assert err <= PARITY_V
+    assert np.max(1.0 - vdc) > 1e-3
+
+
+def test_bitwise_deterministic():
+    w = small_multilayer(side=96, seed=36, nl=3, pad_every=32, steps=25)
+    w.pulses[0][0] = compressed(w.pulses[0][0], start=0.05, width=1.0)
+    say("[gpu] determinism")
+    runs = []
+    for _ in range(2):
+        with gpu_context(w, precision=pg.PG_PREC_FP32_REFINE, tol=1e-9, omega=1.8) as ctx:
+            runs.append(ctx.run_transient(25))
+    assert np.array_equal(runs[0], runs[1])
+
+
+def test_no_convergence_reported_and_state_kept():
+    w = config0()
+    say("[gpu] no convergence")
+    with gpu_context(w, tol=1e-14, max_sweeps=2, check_every=1) as ctx:
+        with pytest.raises(pg.PgError) as ei:
+            ctx.step(50)
+        assert ei.value.name == "PG_ERR_NO_CONVERGENCE"
+        assert ctx.time_index() == 50
+        v = ctx.read_voltages()
+        assert np.all(np.isfinite(v)) and np.max(1.0 - v) > 0
