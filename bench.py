@@ -1,0 +1,195 @@
+#!/usr/bin/env python3
+"""Throughput of the backward-Euler relaxation transient on one MI355X.
+
+Default workload: the 3-layer 1024 x 1024 RC mesh (3,145,728 nodes; 1 S / 2 S / 4 S layers,
+5 S vias every 4 nodes, decaps and 30 % pulsing nodes on the bottom layer, 10 S pads every 64
+nodes on the top layer), h = 10 ps, FP32 correction sweeps with FP64 residual and refinement,
+stopping at a Jacobi-scaled residual of 1e-6 V.  One bench step is one backward-Euler time step
+(right-hand side, sources, sweeps and FP64 residual checks until convergence).  The warmup steps
+run first; the state is then reset to t = 0 and exactly K steps are timed, so the timed region is
+steps 1..K of the transient.  Inputs are resident on the GPU before timing starts.
+
+Prints one JSON line with the metric (node-updates/s), the roofline of the sweep kernel (its
+algorithmic bytes over its HIP-event-timed duration), and the FP64 CPU oracle timed on a bounded
+sample of the same workload.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK = 8.0e12  # B/s, MI355X HBM3E
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--workload", default="config1", choices=["config0", "config1", "config2", "config4",
+                                                             "config3b"])
+    ap.add_argument("--tol", type=float, default=1e-6)
+    ap.add_argument("--precision", default=None, choices=[None, "fp64", "fp32+ref"])
+    ap.add_argument("--omega", type=float, default=None)
+    ap.add_argument("--check-every", type=int, default=None)
+    ap.add_argument("--tile-rows", type=int, default=0)
+    ap.add_argument("--lookahead", type=int, default=1)
+    ap.add_argument("--profile-every", type=int, default=8,
+                    help="time every n-th sweep launch with HIP events during the timed region (0: off)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--extras", action="store_true", help="add side-by-side runs (plain FP64, parity tol)")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="run only a plain 1 GiB device copy (counter calibration) and exit")
+    return ap.parse_args()
+
+
+# Per-workload solver settings: omega near Young's optimum for the step matrix, sweeps per check.
+TUNED = {
+    "config0": dict(omega=1.6, check_every=8),
+    "config1": dict(omega=1.85, check_every=8),
+    "config2": dict(omega=1.9, check_every=16),
+    "config3b": dict(omega=1.6, check_every=8),
+    "config4": dict(omega=1.5, check_every=8),
+}
+
+
+def make_workload(name):
+    import workloads
+    return getattr(workloads, name)()
+
+
+def run_gpu(w, steps, warmup, precision, tol, omega, check_every, tile_rows, lookahead, profile_every):
+    import torch
+    import paper_1409_7166_amd as pg
+
+    torch.cuda.set_device(0)
+    stream = torch.cuda.current_stream().cuda_stream
+    ctx = pg.Context(0, stream)
+    ctx.set_options(h=w.h, tol=tol, omega=omega, check_every=check_every, max_sweeps=100000,
+                    precision=pg.PG_PREC_FP32_REFINE if precision == "fp32+ref" else pg.PG_PREC_FP64,
+                    tile_rows=tile_rows, lookahead=lookahead)
+    for g, (mesh, scen) in enumerate(zip(w.meshes, w.pulses)):
+        ctx.upload_mesh(mesh, len(scen))
+        for s, p in enumerate(scen):
+            ctx.set_pulses(g, s, p)
+    ctx.reset()
+    if warmup:
+        ctx.step(warmup)
+    ctx.reset()
+    ctx.kernel_times()  # drop anything recorded so far
+    ctx.profile(profile_every)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ctx.step(steps)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    ctx.profile(0)
+    st = ctx.stats()
+    kt = ctx.kernel_times()
+    ctx.close()
+    return elapsed, st, kt
+
+
+def cpu_baseline(workload_name, budget_steps=100):
+    """The FP64 oracle on a bounded sample: the same recipe on a reduced mesh, a few steps."""
+    import numpy as np
+    import workloads
+    from oracle import BEStepper, mesh_to_circuit
+    from oracle.sources import currents_at
+
+    if workload_name == "config1":
+        w = workloads.config1(side=256)
+        sample = "3-layer 256x256 mesh with the 1024x1024 recipe (196,608 nodes)"
+    elif workload_name == "config4":
+        w = workloads.config4(side=512)
+        sample = "512x512 mesh with the 1024x1024 recipe (262,144 nodes)"
+    elif workload_name == "config2":
+        w = workloads.config2(side=256)
+        sample = "2-layer 256x256 RLC mesh with the 512x512 recipe"
+    else:
+        w = make_workload(workload_name)
+        sample = "full workload"
+    mesh, p = w.meshes[0], w.pulses[0][0]
+    t0 = time.perf_counter()
+    circ, info = mesh_to_circuit(mesh, p)
+    st = BEStepper(circ, w.h)
+    t1 = time.perf_counter()
+    v = np.full(circ.n, mesh.vdd)
+    il = np.zeros(int(np.sum(circ.kind == "L")))
+    for k in range(1, budget_steps + 1):
+        v, il = st.step(v, il, currents_at(p, k * w.h))
+    t2 = time.perf_counter()
+    n = mesh.n
+    return {
+        "value": n * budget_steps / (t2 - t0), "unit": "node-steps/s", "cores": 1, "kind": "oracle",
+        "sample": f"{sample}, {budget_steps} backward-Euler steps incl. assembly and factorisation "
+                  f"({t1 - t0:.1f} s) and solves ({t2 - t1:.1f} s); SuperLU is single-threaded",
+        "solve_only_node_steps_per_s": n * budget_steps / (t2 - t1),
+    }
+
+
+def copy_probe():
+    import torch
+    n = 1 << 28  # 1 GiB of float32
+    a = torch.ones(n, device="cuda:0")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_probe_bytes_each_way": n * 4, "launches": 3}))
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the relaxation path is built and "
+              "measured for a single MI355X", file=sys.stderr)
+        sys.exit(2)
+    if args.copy_probe:
+        copy_probe()
+        return
+    name = args.workload
+    w = make_workload(name)
+    prec = args.precision or w.precision
+    tuned = TUNED[name]
+    omega = args.omega or tuned["omega"]
+    chk = args.check_every or tuned["check_every"]
+    elapsed, st, kt = run_gpu(w, args.steps, args.warmup, prec, args.tol, omega, chk, args.tile_rows,
+                              args.lookahead, args.profile_every)
+    nodes = sum(m.n * len(p) for m, p in zip(w.meshes, w.pulses))
+    value = st["node_updates"] / elapsed
+    roof = None
+    if kt["sweep_launches"]:
+        sweep_s = kt["sweep_ms"] * 1e-3
+        achieved = kt["sweep_bytes"] / sweep_s
+        roof = {"bound": "hbm", "achieved": achieved / 1e9, "peak": HBM_PEAK / 1e9, "unit": "GB/s",
+                "frac": achieved / HBM_PEAK, "traffic": None,
+                "kernel": "k_sweep_rb", "timed_launches": kt["sweep_launches"],
+                "avg_launch_us": kt["sweep_ms"] * 1e3 / kt["sweep_launches"],
+                "bytes_per_launch": kt["sweep_bytes"] / kt["sweep_launches"]}
+    out = {
+        "metric": "node-updates/s at 1e-6 V scaled residual",
+        "value": value, "unit": "node-updates/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": elapsed * 1e3 / args.steps, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32" if prec == "fp32+ref" else "f64", "data": "synthetic",
+        "config": {"workload": w.name, "nodes": nodes, "h_s": w.h, "tol_V": args.tol,
+                   "precision": prec, "omega": omega, "check_every": chk,
+                   "sweeps_per_step": st["sweeps"] / max(1, st["steps"]),
+                   "max_step_sweeps": st["max_step_sweeps"], "max_final_residual_V": st["max_final_residual"],
+                   "node_steps_per_s": nodes * args.steps / elapsed},
+        "roofline": roof,
+    }
+    if kt["resid_launches"]:
+        out["residual_kernel"] = {"avg_launch_us": kt["resid_ms"] * 1e3 / kt["resid_launches"],
+                                  "achieved_GBps": kt["resid_bytes"] / (kt["resid_ms"] * 1e-3) / 1e9}
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(name)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -71,7 +71,7 @@ typedef struct pg_options {
   int32_t check_every;  /* sweeps between FP64 residual checks (one refinement cycle), >= 1 */
   int32_t precision;    /* pg_precision */
   int32_t ordering;     /* pg_ordering */
-  int32_t tile_rows;    /* rows per sweep tile: 4, 8, 16 or 32 (0 = library default) */
+  int32_t tile_rows;    /* rows per 128-node-wide sweep tile: 4, 8 or 16 (0 = library default, 8) */
   int32_t lookahead;    /* refinement cycles queued ahead of the host's convergence check, 0..4 */
   int32_t reserved[6];  /* must be zero */
 } pg_options;
@@ -106,10 +106,15 @@ typedef struct pg_stats {
   double seconds;             /* wall time inside pg_step / pg_run_transient */
 } pg_stats;
 
-/* Kernel timing gathered with HIP events on the context stream while profiling is on. */
+/* Kernel timing gathered with HIP events on the context stream while profiling is on.
+ * *_bytes are algorithmic bytes of the timed launches: every array the kernel needs read once
+ * and every array it produces written once, with e = 4 (FP32 sweeps) or 8 (FP64) bytes:
+ *   sweep:    e * (gE + gN + invD + r + d_new [+ d_old unless it starts from zero])
+ *             + e * (nl-1)/nl (via conductances exist below the top layer only)   per node
+ *   residual: 8 * (v + b + D + gE + gN) + 8 * (nl-1)/nl + e * r [+ e * d + 8 * v_out]  per node */
 typedef struct pg_kernel_times {
-  int64_t sweep_launches;  double sweep_ms;      int64_t sweep_node_updates;
-  int64_t resid_launches;  double resid_ms;      int64_t resid_nodes;
+  int64_t sweep_launches;  double sweep_ms;      int64_t sweep_node_updates;  double sweep_bytes;
+  int64_t resid_launches;  double resid_ms;      int64_t resid_nodes;         double resid_bytes;
   int64_t rhs_launches;    double rhs_ms;
   int64_t other_launches;  double other_ms;
 } pg_kernel_times;
@@ -118,7 +123,7 @@ int32_t pg_abi_version(void);
 const char* pg_status_name(int32_t status);
 
 /* Fill *out with the defaults: h = 10 ps, tol = 1e-6 V, omega = 1, max_sweeps = 10000,
- * check_every = 8, FP64, red-black, tile_rows = 16, lookahead = 1. */
+ * check_every = 8, FP64, red-black, tile_rows = 8, lookahead = 1. */
 pg_status pg_default_options(pg_options* out);
 
 /* Host-only checks (no device needed).  msg (may be NULL) receives a description of the

@@ -11,19 +11,38 @@
 // red values.  Because the sweep is an affine stationary iteration, sweeping the correction
 // from d = 0 produces exactly the iterates of sweeping v itself (in exact arithmetic).
 //
-// Memory layout: every per-node array is padded to n = nl*ny*nx entries in natural order
-// (x fastest), so a 64-lane wavefront reads 64 consecutive nodes of one row.  A workgroup
-// owns a 64 x TY tile through all layers and stages the correction in LDS with a two-cell
-// halo; the red half-sweep is recomputed on a one-cell ring around the tile so the black
-// half-sweep sees exactly the red values a global red-black sweep would produce, which lets
-// one launch perform a whole sweep with ping-pong buffers and no grid-wide barrier.
+// Memory layout: per-node arrays in natural order with an aligned row pitch.  A workgroup
+// owns a 128 x TY tile through all layers; lane j of row-wave w owns the node pair
+// (x0 + 2j, x0 + 2j + 1) of tile row w.  Because x0 is even, exactly one node of every pair is
+// red, so both half-sweeps keep every lane busy, and all global traffic is 8- or 16-byte pair
+// accesses.  The old correction is staged in LDS with a two-node, two-row halo; the red
+// half-sweep is also evaluated on a one-node ring around the tile so the black half-sweep sees
+// exactly the red values a global red-black sweep produces.  One launch therefore performs a
+// whole sweep (ping-pong buffers, no grid-wide barrier), and the black node's coefficients,
+// loaded with its red partner's, stay in registers between the two halves.
 #include "pgrid_internal.h"
-
-#include <cfloat>
 
 namespace pgrid {
 
 namespace {
+
+template <typename T> struct Vec2;
+template <> struct Vec2<float> { using type = float2; };
+template <> struct Vec2<double> { using type = double2; };
+template <typename T> using V2 = typename Vec2<T>::type;
+
+template <typename T>
+__device__ __forceinline__ V2<T> ld2(const T* __restrict__ p, int64_t i) {
+  return *reinterpret_cast<const V2<T>*>(p + i);
+}
+template <typename T>
+__device__ __forceinline__ void st2(T* __restrict__ p, int64_t i, V2<T> v) {
+  *reinterpret_cast<V2<T>*>(p + i) = v;
+}
+template <typename V>
+__device__ __forceinline__ auto pick(const V& v, int e) -> decltype(v.x) { return e ? v.y : v.x; }
+template <typename T>
+__device__ __forceinline__ V2<T> zero2() { V2<T> z; z.x = T(0); z.y = T(0); return z; }
 
 // Tiles are numbered row-major over each grid.  Workgroups are dealt to the 8 XCDs round
 // robin, so block b runs on XCD b % 8; give each XCD a contiguous run of tiles so vertically
@@ -37,6 +56,60 @@ __device__ __forceinline__ int xcd_tile(int ntiles) {
 
 __device__ __forceinline__ double nan_max(double m, double x) {
   return (x > m || x != x) ? x : m;
+}
+
+// Coefficients of one node of a pair: the conductances to its six neighbours, 1/M_ii, r_i.
+template <typename T>
+struct NodeCoef {
+  T e, w, n, s, u, d, inv, r;
+};
+
+// Load the pair's coefficients and return those of element `e` (0: even node, 1: odd node);
+// `other` receives the partner's.  Conductances beyond the mesh are stored as zero, so only
+// the array bounds are guarded.
+template <typename T, int NL>
+__device__ __forceinline__ void load_pair(const GridDesc& G, const T* __restrict__ gE,
+                                          const T* __restrict__ gN, const T* __restrict__ gU,
+                                          const T* __restrict__ invD, const T* __restrict__ r,
+                                          int l, int y, int x, int e, NodeCoef<T>& mine,
+                                          NodeCoef<T>& other) {
+  const int64_t P = (int64_t)G.X * G.ny;
+  const int64_t i = l * P + (int64_t)y * G.X + x;
+  const V2<T> ge = ld2(gE, i), gn = ld2(gN, i), iv = ld2(invD, i), rr = ld2(r, i);
+  const V2<T> gs = y > 0 ? ld2(gN, i - G.X) : zero2<T>();
+  const T gw = x > 0 ? gE[i - 1] : T(0);
+  V2<T> gu = zero2<T>(), gd = zero2<T>();
+  if (NL > 1) {
+    if (l < NL - 1) gu = ld2(gU, i);
+    if (l > 0) gd = ld2(gU, i - P);
+  }
+  // element 0: west edge is gE[x-1]; element 1: west edge is element 0's east edge
+  NodeCoef<T> c0{ge.x, gw, gn.x, gs.x, gu.x, gd.x, iv.x, rr.x};
+  NodeCoef<T> c1{ge.y, ge.x, gn.y, gs.y, gu.y, gd.y, iv.y, rr.y};
+  mine = e ? c1 : c0;
+  other = e ? c0 : c1;
+}
+
+// SOR update of element e of the staged pair (l, hy, hp) from its staged neighbours.
+template <typename T, int NL, int HY, int HP>
+__device__ __forceinline__ T relax(const V2<T> (*sd)[HY][HP], int l, int hy, int hp, int e,
+                                   const NodeCoef<T>& k, T omega) {
+  const V2<T> own = sd[l][hy][hp];
+  const T old = pick(own, e);
+  const T east = e ? sd[l][hy][hp + 1].x : own.y;
+  const T west = e ? own.x : sd[l][hy][hp - 1].y;
+  T acc = k.r + k.e * east + k.w * west + k.n * pick(sd[l][hy + 1][hp], e) +
+          k.s * pick(sd[l][hy - 1][hp], e);
+  if (NL > 1) {
+    if (l < NL - 1) acc += k.u * pick(sd[l + 1][hy][hp], e);
+    if (l > 0) acc += k.d * pick(sd[l - 1][hy][hp], e);
+  }
+  return old + omega * (k.inv * acc - old);
+}
+
+template <typename V, typename T>
+__device__ __forceinline__ void put(V& v, int e, T val) {
+  if (e) v.y = val; else v.x = val;
 }
 
 }  // namespace
@@ -115,8 +188,8 @@ __global__ __launch_bounds__(kThreads) void k_rhs(const Tile* __restrict__ tiles
   if (ti < 0) return;
   const Tile tl = tiles[ti];
   const GridDesc& G = grids[tl.grid];
-  const int nx = G.nx, ny = G.ny, S = G.S;
-  const int64_t P = (int64_t)nx * ny;
+  const int X = G.X, ny = G.ny, S = G.S;
+  const int64_t P = (int64_t)X * ny;
   const double* __restrict__ v = G.v[c.vidx[tl.grid]];
   const int per_layer = kTileX * TY * S;
   const int total = per_layer * G.nl;
@@ -127,8 +200,8 @@ __global__ __launch_bounds__(kThreads) void k_rhs(const Tile* __restrict__ tiles
     const int s = rem - node_in * S;
     const int yy = node_in / kTileX, xx = node_in - yy * kTileX;
     const int x = tl.x0 + xx, y = tl.y0 + yy;
-    if (x >= nx || y >= ny) continue;
-    const int64_t i = l * P + (int64_t)y * nx + x;
+    if (x >= X || y >= ny) continue;
+    const int64_t i = l * P + (int64_t)y * X + x;
     const int64_t idx = i * S + s;
     double bb = G.ch64[i] * v[idx] + G.bconst64[i];
     if (G.n_ind) {
@@ -171,101 +244,120 @@ __global__ void k_sources(SourceTable src, const GridDesc* __restrict__ grids, d
 // FP64 residual r = b - M v' with v' = v + d, and the Jacobi-scaled norm max |r_i| / M_ii.
 // Writes v' into the other voltage buffer (the decision kernel flips the index), and r in
 // the sweep precision as the right-hand side of the next correction sweeps.
+// Block: 64 x TY threads, lane j of row w owns the pair (x0 + 2j, x0 + 2j + 1) of row y0 + w.
 // ------------------------------------------------------------------------------------
 template <typename T, int NL, int TY>
-__global__ __launch_bounds__(kThreads) void k_resid(const Tile* __restrict__ tiles, int ntiles,
-                                                   const GridDesc* __restrict__ grids, Ctl c,
-                                                   int has_d, int din) {
-  constexpr int TX = kTileX, HX = TX + 2, HY = TY + 2;
-  __shared__ double sv[NL][HY][HX];
-  __shared__ double wmax[kThreads / 64];
+__global__ __launch_bounds__(64 * TY) void k_resid(const Tile* __restrict__ tiles, int ntiles,
+                                                  const GridDesc* __restrict__ grids, Ctl c,
+                                                  int has_d, int din) {
+  constexpr int NP = kTileX / 2, HP = NP + 2, HY = TY + 2;
+  constexpr int NT = 64 * TY;
+  __shared__ double2 sv[NL][HY][HP];
+  __shared__ double wmax[NT / 64];
   const int ti = xcd_tile(ntiles);
   if (ti < 0) return;
   const Tile tl = tiles[ti];
   const int g = tl.grid;
   if (!c.active[g]) return;
   const GridDesc& G = grids[g];
-  const int nx = G.nx, ny = G.ny;
-  const int64_t P = (int64_t)nx * ny;
+  const int nx = G.nx, ny = G.ny, X = G.X;
+  const int64_t P = (int64_t)X * ny;
   const int vi = c.vidx[g];
   const double* __restrict__ v = G.v[vi];
   const T* __restrict__ d = static_cast<const T*>(G.d[din]);
   const int x0 = tl.x0, y0 = tl.y0;
 
-  for (int k = threadIdx.x; k < NL * HY * HX; k += kThreads) {
-    const int l = k / (HY * HX);
-    const int rem = k - l * (HY * HX);
-    const int yy = rem / HX, xx = rem - yy * HX;
-    const int x = x0 - 1 + xx, y = y0 - 1 + yy;
-    double val = 0.0;
-    if (x >= 0 && x < nx && y >= 0 && y < ny) {
-      const int64_t i = l * P + (int64_t)y * nx + x;
-      val = v[i];
-      if (has_d) val += (double)d[i];
+  // stage v + d on the tile with a one-pair, one-row halo (zero outside the storage)
+  for (int k = threadIdx.x; k < NL * HY * HP; k += NT) {
+    const int l = k / (HY * HP);
+    const int rem = k - l * (HY * HP);
+    const int hy = rem / HP, hp = rem - hy * HP;
+    const int x = x0 - 2 + 2 * hp, y = y0 - 1 + hy;
+    double2 val = make_double2(0.0, 0.0);
+    if (x >= 0 && x < X && y >= 0 && y < ny) {
+      const int64_t i = l * P + (int64_t)y * X + x;
+      val = ld2(v, i);
+      if (has_d) {
+        const V2<T> dd = ld2(d, i);
+        val.x += (double)dd.x;
+        val.y += (double)dd.y;
+      }
     }
-    sv[l][yy][xx] = val;
+    sv[l][hy][hp] = val;
   }
   __syncthreads();
 
-  const double* __restrict__ gE = G.gE64;
-  const double* __restrict__ gN = G.gN64;
-  const double* __restrict__ gU = G.gU64;
-  const double* __restrict__ D = G.D64;
-  const double* __restrict__ b = G.b;
-  double* __restrict__ vout = G.v[vi ^ 1];
-  T* __restrict__ r = static_cast<T*>(G.r);
+  const int lane = threadIdx.x & 63, row = threadIdx.x >> 6;
+  const int x = x0 + 2 * lane, y = y0 + row;
+  const int hp = lane + 1, hy = row + 1;
   double m = 0.0;
-  for (int k = threadIdx.x; k < NL * TY * TX; k += kThreads) {
-    const int l = k / (TY * TX);
-    const int rem = k - l * (TY * TX);
-    const int yy = rem / TX, xx = rem - yy * TX;
-    const int x = x0 + xx, y = y0 + yy;
-    if (x >= nx || y >= ny) continue;
-    const int64_t i = l * P + (int64_t)y * nx + x;
-    const int sx = xx + 1, sy = yy + 1;
-    const double vc = sv[l][sy][sx];
-    double acc = b[i] - D[i] * vc;
-    acc += gE[i] * sv[l][sy][sx + 1];
-    acc += gN[i] * sv[l][sy + 1][sx];
-    if (x > 0) acc += gE[i - 1] * sv[l][sy][sx - 1];
-    if (y > 0) acc += gN[i - nx] * sv[l][sy - 1][sx];
-    if (NL > 1) {
-      if (l < NL - 1) acc += gU[i] * sv[l + 1][sy][sx];
-      if (l > 0) acc += gU[i - P] * sv[l - 1][sy][sx];
+  if (x < X && y < ny) {
+    double* __restrict__ vout = G.v[vi ^ 1];
+    T* __restrict__ r = static_cast<T*>(G.r);
+#pragma unroll
+    for (int l = 0; l < NL; ++l) {
+      const int64_t i = l * P + (int64_t)y * X + x;
+      const double2 b2 = ld2(G.b, i), D2 = ld2(G.D64, i), ge = ld2(G.gE64, i), gn = ld2(G.gN64, i);
+      const double2 gs = y > 0 ? ld2(G.gN64, i - X) : make_double2(0.0, 0.0);
+      const double gw = x > 0 ? G.gE64[i - 1] : 0.0;
+      double2 gu = make_double2(0.0, 0.0), gd = make_double2(0.0, 0.0);
+      if (NL > 1) {
+        if (l < NL - 1) gu = ld2(G.gU64, i);
+        if (l > 0) gd = ld2(G.gU64, i - P);
+      }
+      const double2 own = sv[l][hy][hp], eastp = sv[l][hy][hp + 1], westp = sv[l][hy][hp - 1];
+      const double2 nth = sv[l][hy + 1][hp], sth = sv[l][hy - 1][hp];
+      double2 up = make_double2(0.0, 0.0), dn = make_double2(0.0, 0.0);
+      if (NL > 1) {
+        if (l < NL - 1) up = sv[l + 1][hy][hp];
+        if (l > 0) dn = sv[l - 1][hy][hp];
+      }
+      double r0 = b2.x - D2.x * own.x + ge.x * own.y + gw * westp.y + gn.x * nth.x + gs.x * sth.x +
+                  gu.x * up.x + gd.x * dn.x;
+      double r1 = b2.y - D2.y * own.y + ge.y * eastp.x + ge.x * own.x + gn.y * nth.y + gs.y * sth.y +
+                  gu.y * up.y + gd.y * dn.y;
+      if (x >= nx) r0 = 0.0;
+      if (x + 1 >= nx) r1 = 0.0;
+      if (has_d) st2(vout, i, own);
+      V2<T> rr;
+      rr.x = (T)r0;
+      rr.y = (T)r1;
+      st2(r, i, rr);
+      if (x < nx) m = nan_max(m, fabs(r0) / D2.x);
+      if (x + 1 < nx) m = nan_max(m, fabs(r1) / D2.y);
     }
-    if (has_d) vout[i] = vc;
-    r[i] = (T)acc;
-    m = nan_max(m, fabs(acc) / D[i]);
   }
   // wavefront max, then across the block, then one atomic per block
   for (int off = 32; off > 0; off >>= 1) m = nan_max(m, __shfl_xor(m, off, 64));
-  if ((threadIdx.x & 63) == 0) wmax[threadIdx.x >> 6] = m;
+  if (lane == 0) wmax[row] = m;
   __syncthreads();
   if (threadIdx.x == 0) {
     double bm = wmax[0];
-    for (int w = 1; w < kThreads / 64; ++w) bm = nan_max(bm, wmax[w]);
+    for (int w = 1; w < NT / 64; ++w) bm = nan_max(bm, wmax[w]);
     atomicMax(&c.norm_bits[g], (unsigned long long)__double_as_longlong(bm));
   }
 }
 
 // ------------------------------------------------------------------------------------
-// One red-black SOR sweep on M d = r (eqs. 16-17), whole sweep per launch.
+// One red-black SOR sweep on M d = r (eqs. 16-17), a whole sweep per launch.
 // ------------------------------------------------------------------------------------
 template <typename T, int NL, int TY>
-__global__ __launch_bounds__(kThreads) void k_sweep_rb(const Tile* __restrict__ tiles, int ntiles,
-                                                      const GridDesc* __restrict__ grids, Ctl c,
-                                                      int din, int zero_in, T omega) {
-  constexpr int TX = kTileX, HX = TX + 4, HY = TY + 4;   // two-cell halo
-  constexpr int RX = TX + 2, RY = TY + 2;                // red region: tile + one-cell ring
-  __shared__ T sd[NL][HY][HX];
+__global__ __launch_bounds__(64 * TY) void k_sweep_rb(const Tile* __restrict__ tiles, int ntiles,
+                                                     const GridDesc* __restrict__ grids, Ctl c,
+                                                     int din, int zero_in, T omega) {
+  constexpr int NP = kTileX / 2;      // pairs per tile row
+  constexpr int HP = NP + 2;          // staged pairs per row (one halo pair each side)
+  constexpr int HY = TY + 4;          // staged rows (two halo rows each side)
+  constexpr int NT = 64 * TY;
+  __shared__ V2<T> sd[NL][HY][HP];
   const int ti = xcd_tile(ntiles);
   if (ti < 0) return;
   const Tile tl = tiles[ti];
   const int g = tl.grid;
   if (!c.active[g]) return;
   const GridDesc& G = grids[g];
-  const int nx = G.nx, ny = G.ny;
-  const int64_t P = (int64_t)nx * ny;
+  const int ny = G.ny, X = G.X;
+  const int64_t P = (int64_t)X * ny;
   const int x0 = tl.x0, y0 = tl.y0;
   const T* __restrict__ dold = static_cast<const T*>(G.d[din]);
   T* __restrict__ dnew = static_cast<T*>(G.d[din ^ 1]);
@@ -275,84 +367,89 @@ __global__ __launch_bounds__(kThreads) void k_sweep_rb(const Tile* __restrict__ 
   const T* __restrict__ invD = static_cast<const T*>(G.invDs);
   const T* __restrict__ r = static_cast<const T*>(G.r);
 
-  // stage the old correction with a two-cell halo (zero outside the grid)
-  for (int k = threadIdx.x; k < NL * HY * HX; k += kThreads) {
-    const int l = k / (HY * HX);
-    const int rem = k - l * (HY * HX);
-    const int yy = rem / HX, xx = rem - yy * HX;
-    const int x = x0 - 2 + xx, y = y0 - 2 + yy;
-    T val = T(0);
-    if (!zero_in && x >= 0 && x < nx && y >= 0 && y < ny) val = dold[l * P + (int64_t)y * nx + x];
-    sd[l][yy][xx] = val;
+  // stage the old correction (zero outside the storage, and everywhere on a cold start)
+  for (int k = threadIdx.x; k < NL * HY * HP; k += NT) {
+    const int l = k / (HY * HP);
+    const int rem = k - l * (HY * HP);
+    const int hy = rem / HP, hp = rem - hy * HP;
+    const int x = x0 - 2 + 2 * hp, y = y0 - 2 + hy;
+    V2<T> val = zero2<T>();
+    if (!zero_in && x >= 0 && x < X && y >= 0 && y < ny) val = ld2(dold, l * P + (int64_t)y * X + x);
+    sd[l][hy][hp] = val;
   }
   __syncthreads();
 
-  // red half-sweep on the tile and its one-cell ring, from old black values
-  for (int k = threadIdx.x; k < NL * RY * RX; k += kThreads) {
-    const int l = k / (RY * RX);
-    const int rem = k - l * (RY * RX);
-    const int yy = rem / RX, xx = rem - yy * RX;
-    const int x = x0 - 1 + xx, y = y0 - 1 + yy;
-    if (((x + y + l) & 1) != 0) continue;
-    if (x < 0 || x >= nx || y < 0 || y >= ny) continue;
-    const int64_t i = l * P + (int64_t)y * nx + x;
-    const int sx = xx + 1, sy = yy + 1;
-    T acc = r[i];
-    acc += gE[i] * sd[l][sy][sx + 1];
-    acc += gN[i] * sd[l][sy + 1][sx];
-    if (x > 0) acc += gE[i - 1] * sd[l][sy][sx - 1];
-    if (y > 0) acc += gN[i - nx] * sd[l][sy - 1][sx];
-    if (NL > 1) {
-      if (l < NL - 1) acc += gU[i] * sd[l + 1][sy][sx];
-      if (l > 0) acc += gU[i - P] * sd[l - 1][sy][sx];
+  const int lane = threadIdx.x & 63, row = threadIdx.x >> 6;
+  const int x = x0 + 2 * lane, y = y0 + row;
+  const int hp = lane + 1, hy = row + 2;
+  const bool mine = x < X && y < ny;
+
+  // red half-sweep on the owned pairs; keep the black partner's coefficients
+  NodeCoef<T> keep[NL];
+  if (mine) {
+#pragma unroll
+    for (int l = 0; l < NL; ++l) {
+      const int er = (y + l) & 1;  // x is even: the pair's red node is x + er
+      NodeCoef<T> kr;
+      load_pair<T, NL>(G, gE, gN, gU, invD, r, l, y, x, er, kr, keep[l]);
+      const T nv = relax<T, NL, HY, HP>(sd, l, hy, hp, er, kr, omega);
+      put(sd[l][hy][hp], er, nv);
     }
-    const T old = sd[l][sy][sx];
-    sd[l][sy][sx] = old + omega * (invD[i] * acc - old);
+  }
+  // red half-sweep on the one-node ring: rows y0-1 and y0+TY (tile columns), and the
+  // columns x0-1 and x0+TX (tile rows).  Only the ring node of each edge pair is updated.
+  constexpr int NRING = 2 * NP + 2 * TY;
+  for (int k = threadIdx.x; k < NL * NRING; k += NT) {
+    const int l = k / NRING;
+    const int q = k - l * NRING;
+    int rhy, rhp, want;  // staged row, staged pair, element that must be red (-1: either)
+    if (q < 2 * NP) {
+      rhy = q < NP ? 1 : TY + 2;
+      rhp = 1 + (q < NP ? q : q - NP);
+      want = -1;
+    } else {
+      const int q2 = q - 2 * NP;
+      rhy = 2 + (q2 < TY ? q2 : q2 - TY);
+      rhp = q2 < TY ? 0 : NP + 1;
+      want = q2 < TY ? 1 : 0;
+    }
+    const int gx = x0 - 2 + 2 * rhp, gy = y0 - 2 + rhy;
+    if (gx < 0 || gx >= X || gy < 0 || gy >= ny) continue;
+    const int er = (gy + l) & 1;
+    if (want >= 0 && er != want) continue;
+    NodeCoef<T> kr, kb;
+    load_pair<T, NL>(G, gE, gN, gU, invD, r, l, gy, gx, er, kr, kb);
+    const T nv = relax<T, NL, HY, HP>(sd, l, rhy, rhp, er, kr, omega);
+    put(sd[l][rhy][rhp], er, nv);
   }
   __syncthreads();
 
-  // black half-sweep on the tile from the new red values; write the whole tile
-  for (int k = threadIdx.x; k < NL * TY * TX; k += kThreads) {
-    const int l = k / (TY * TX);
-    const int rem = k - l * (TY * TX);
-    const int yy = rem / TX, xx = rem - yy * TX;
-    const int x = x0 + xx, y = y0 + yy;
-    if (x >= nx || y >= ny) continue;
-    const int64_t i = l * P + (int64_t)y * nx + x;
-    const int sx = xx + 2, sy = yy + 2;
-    T val = sd[l][sy][sx];
-    if ((x + y + l) & 1) {
-      T acc = r[i];
-      acc += gE[i] * sd[l][sy][sx + 1];
-      acc += gN[i] * sd[l][sy + 1][sx];
-      if (x > 0) acc += gE[i - 1] * sd[l][sy][sx - 1];
-      if (y > 0) acc += gN[i - nx] * sd[l][sy - 1][sx];
-      if (NL > 1) {
-        if (l < NL - 1) acc += gU[i] * sd[l + 1][sy][sx];
-        if (l > 0) acc += gU[i - P] * sd[l - 1][sy][sx];
-      }
-      val = val + omega * (invD[i] * acc - val);
+  // black half-sweep on the owned pairs from the new red values; write both nodes
+  if (mine) {
+#pragma unroll
+    for (int l = 0; l < NL; ++l) {
+      const int eb = 1 - ((y + l) & 1);
+      V2<T> out = sd[l][hy][hp];
+      const T nv = relax<T, NL, HY, HP>(sd, l, hy, hp, eb, keep[l], omega);
+      put(out, eb, nv);
+      st2(dnew, l * P + (int64_t)y * X + x, out);
     }
-    dnew[i] = val;
   }
 }
 
-// Weighted Jacobi sweep: every node from the previous sweep's values.
-template <typename T, int NL, int TY>
+// Weighted Jacobi sweep: every node from the previous sweep's values (element-wise).
+template <typename T, int NL>
 __global__ __launch_bounds__(kThreads) void k_sweep_jacobi(const Tile* __restrict__ tiles, int ntiles,
-                                                          const GridDesc* __restrict__ grids, Ctl c,
-                                                          int din, int zero_in, T omega) {
-  constexpr int TX = kTileX, HX = TX + 2, HY = TY + 2;
-  __shared__ T sd[NL][HY][HX];
+                                                          int TY, const GridDesc* __restrict__ grids,
+                                                          Ctl c, int din, int zero_in, T omega) {
   const int ti = xcd_tile(ntiles);
   if (ti < 0) return;
   const Tile tl = tiles[ti];
   const int g = tl.grid;
   if (!c.active[g]) return;
   const GridDesc& G = grids[g];
-  const int nx = G.nx, ny = G.ny;
-  const int64_t P = (int64_t)nx * ny;
-  const int x0 = tl.x0, y0 = tl.y0;
+  const int ny = G.ny, X = G.X;
+  const int64_t P = (int64_t)X * ny;
   const T* __restrict__ dold = static_cast<const T*>(G.d[din]);
   T* __restrict__ dnew = static_cast<T*>(G.d[din ^ 1]);
   const T* __restrict__ gE = static_cast<const T*>(G.gEs);
@@ -360,34 +457,25 @@ __global__ __launch_bounds__(kThreads) void k_sweep_jacobi(const Tile* __restric
   const T* __restrict__ gU = static_cast<const T*>(G.gUs);
   const T* __restrict__ invD = static_cast<const T*>(G.invDs);
   const T* __restrict__ r = static_cast<const T*>(G.r);
-  for (int k = threadIdx.x; k < NL * HY * HX; k += kThreads) {
-    const int l = k / (HY * HX);
-    const int rem = k - l * (HY * HX);
-    const int yy = rem / HX, xx = rem - yy * HX;
-    const int x = x0 - 1 + xx, y = y0 - 1 + yy;
-    T val = T(0);
-    if (!zero_in && x >= 0 && x < nx && y >= 0 && y < ny) val = dold[l * P + (int64_t)y * nx + x];
-    sd[l][yy][xx] = val;
-  }
-  __syncthreads();
-  for (int k = threadIdx.x; k < NL * TY * TX; k += kThreads) {
-    const int l = k / (TY * TX);
-    const int rem = k - l * (TY * TX);
-    const int yy = rem / TX, xx = rem - yy * TX;
-    const int x = x0 + xx, y = y0 + yy;
-    if (x >= nx || y >= ny) continue;
-    const int64_t i = l * P + (int64_t)y * nx + x;
-    const int sx = xx + 1, sy = yy + 1;
+  for (int k = threadIdx.x; k < NL * TY * kTileX; k += kThreads) {
+    const int l = k / (TY * kTileX);
+    const int rem = k - l * (TY * kTileX);
+    const int yy = rem / kTileX, xx = rem - yy * kTileX;
+    const int x = tl.x0 + xx, y = tl.y0 + yy;
+    if (x >= X || y >= ny) continue;
+    const int64_t i = l * P + (int64_t)y * X + x;
     T acc = r[i];
-    acc += gE[i] * sd[l][sy][sx + 1];
-    acc += gN[i] * sd[l][sy + 1][sx];
-    if (x > 0) acc += gE[i - 1] * sd[l][sy][sx - 1];
-    if (y > 0) acc += gN[i - nx] * sd[l][sy - 1][sx];
-    if (NL > 1) {
-      if (l < NL - 1) acc += gU[i] * sd[l + 1][sy][sx];
-      if (l > 0) acc += gU[i - P] * sd[l - 1][sy][sx];
+    if (!zero_in) {
+      if (x + 1 < X) acc += gE[i] * dold[i + 1];
+      if (x > 0) acc += gE[i - 1] * dold[i - 1];
+      if (y + 1 < ny) acc += gN[i] * dold[i + X];
+      if (y > 0) acc += gN[i - X] * dold[i - X];
+      if (NL > 1) {
+        if (l < NL - 1) acc += gU[i] * dold[i + P];
+        if (l > 0) acc += gU[i - P] * dold[i - P];
+      }
     }
-    const T old = sd[l][sy][sx];
+    const T old = zero_in ? T(0) : dold[i];
     dnew[i] = old + omega * (invD[i] * acc - old);
   }
 }
@@ -460,7 +548,7 @@ hipError_t launch_inductors(const GridDesc* grids, const int32_t* ind_grid, cons
 template <typename T, int NL, int TY>
 static void resid_t(const Tile* tiles, int ntiles, const GridDesc* grids, const Ctl& c, int has_d,
                     int din, hipStream_t s) {
-  hipLaunchKernelGGL((k_resid<T, NL, TY>), dim3(xcd_blocks(ntiles)), dim3(kThreads), 0, s, tiles,
+  hipLaunchKernelGGL((k_resid<T, NL, TY>), dim3(xcd_blocks(ntiles)), dim3(64 * TY), 0, s, tiles,
                      ntiles, grids, c, has_d, din);
 }
 
@@ -468,27 +556,27 @@ template <typename T, int NL, int TY>
 static void sweep_t(int ordering, const Tile* tiles, int ntiles, const GridDesc* grids, const Ctl& c,
                     int din, int zero_in, double omega, hipStream_t s) {
   if (ordering == 1)
-    hipLaunchKernelGGL((k_sweep_jacobi<T, NL, TY>), dim3(xcd_blocks(ntiles)), dim3(kThreads), 0, s,
-                       tiles, ntiles, grids, c, din, zero_in, (T)omega);
+    hipLaunchKernelGGL((k_sweep_jacobi<T, NL>), dim3(xcd_blocks(ntiles)), dim3(kThreads), 0, s,
+                       tiles, ntiles, TY, grids, c, din, zero_in, (T)omega);
   else
-    hipLaunchKernelGGL((k_sweep_rb<T, NL, TY>), dim3(xcd_blocks(ntiles)), dim3(kThreads), 0, s,
+    hipLaunchKernelGGL((k_sweep_rb<T, NL, TY>), dim3(xcd_blocks(ntiles)), dim3(64 * TY), 0, s,
                        tiles, ntiles, grids, c, din, zero_in, (T)omega);
 }
 
 #define PG_DISPATCH_NL_TY(FN, T, ...)                                   \
   switch (nl * 100 + tile_rows) {                                       \
+    case 104: FN<T, 1, 4>(__VA_ARGS__); break;                          \
     case 108: FN<T, 1, 8>(__VA_ARGS__); break;                          \
     case 116: FN<T, 1, 16>(__VA_ARGS__); break;                         \
-    case 132: FN<T, 1, 32>(__VA_ARGS__); break;                         \
+    case 204: FN<T, 2, 4>(__VA_ARGS__); break;                          \
     case 208: FN<T, 2, 8>(__VA_ARGS__); break;                          \
     case 216: FN<T, 2, 16>(__VA_ARGS__); break;                         \
-    case 232: FN<T, 2, 32>(__VA_ARGS__); break;                         \
+    case 304: FN<T, 3, 4>(__VA_ARGS__); break;                          \
     case 308: FN<T, 3, 8>(__VA_ARGS__); break;                          \
     case 316: FN<T, 3, 16>(__VA_ARGS__); break;                         \
-    case 332: FN<T, 3, 32>(__VA_ARGS__); break;                         \
+    case 404: FN<T, 4, 4>(__VA_ARGS__); break;                          \
     case 408: FN<T, 4, 8>(__VA_ARGS__); break;                          \
     case 416: FN<T, 4, 16>(__VA_ARGS__); break;                         \
-    case 432: FN<T, 4, 32>(__VA_ARGS__); break;                         \
     default: return hipErrorInvalidValue;                               \
   }
 

@@ -6,15 +6,20 @@
 
 namespace pgrid {
 
-constexpr int kTileX = 64;        // nodes per tile row: one 64-lane wavefront wide
-constexpr int kThreads = 256;     // threads per workgroup for every tiled kernel
+constexpr int kTileX = 128;       // nodes per tile row: 64 lanes x one node pair
+constexpr int kThreads = 256;     // threads per workgroup of the element-wise kernels
+constexpr int kPitchAlign = 4;    // row pitch multiple (keeps pair and quad accesses aligned)
 
-// Per-grid device descriptor.  Coefficient arrays are padded to n = nl*ny*nx entries:
-// gE is zero at x = nx-1, gN at y = ny-1, gU on the top layer and wherever no via exists.
-// State arrays hold n*S entries, scenario-minor (index node*S + s).
+// Per-grid device descriptor.  Every per-node array is stored with a row pitch X >= nx
+// (a multiple of kPitchAlign): storage index (l*ny + y)*X + x.  Coefficients are zero in the
+// padding columns, at x = nx-1 (gE), y = ny-1 (gN), on the top layer (gU) and wherever no via
+// exists; invD is zero in the padding, so padding corrections stay zero.  State arrays hold
+// nstore*S entries, scenario-minor (index storage*S + s).
 struct GridDesc {
   int32_t nx, ny, nl, S;
-  int64_t n;                       // nodes per scenario
+  int32_t X;                       // row pitch
+  int32_t pad_;
+  int64_t nstore;                  // nl*ny*X storage slots per scenario
   // FP64 masters: conductances, diagonal of M, C/h, constant injection (pads x Vdd)
   const double* gE64;
   const double* gN64;

@@ -31,7 +31,13 @@ struct DBuf {
 
 struct GridHost {
   int32_t nx = 0, ny = 0, nl = 0, S = 1;
-  int64_t n = 0, P = 0;
+  int32_t X = 0;                                 // storage row pitch (>= nx, multiple of kPitchAlign)
+  int64_t n = 0, P = 0;                          // mesh nodes, nodes per layer
+  int64_t nstore = 0;                            // storage slots per scenario, nl*ny*X
+  int64_t storage(int64_t node) const {          // mesh node id -> storage slot
+    const int64_t l = node / P, rem = node - l * P, y = rem / nx, x = rem - y * nx;
+    return (l * ny + y) * X + x;
+  }
   double vdd = 1.0;
   std::vector<double> gE, gN, C;                 // as uploaded (unpadded)
   std::vector<int32_t> via_node, pad_node;
@@ -50,6 +56,7 @@ struct ProfEvent {
   hipEvent_t a, b;
   int kind;          // 0 sweep, 1 resid, 2 rhs, 3 other
   int64_t units;     // node-updates (sweep) or nodes (resid)
+  double bytes;      // algorithmic bytes of the launch
 };
 
 }  // namespace
@@ -67,6 +74,15 @@ struct pg_ctx {
   // device tables
   DBuf grid_desc, tiles_all, src_grid, src_index, src_off, src_t, src_i, ind_grid, ind_local;
   struct Group { int nl, off, count; int64_t nodes; };
+  // algorithmic bytes per node of one sweep / residual launch over a group (see pgrid.h)
+  double sweep_bytes_per_node(const Group& g, bool zero_in) const {
+    const double e = opt.precision == PG_PREC_FP32_REFINE ? 4.0 : 8.0;
+    return e * (5.0 + (zero_in ? 0.0 : 1.0) + (g.nl - 1.0) / g.nl);
+  }
+  double resid_bytes_per_node(const Group& g, bool has_d) const {
+    const double e = opt.precision == PG_PREC_FP32_REFINE ? 4.0 : 8.0;
+    return 8.0 * (5.0 + (g.nl - 1.0) / g.nl) + e + (has_d ? e + 8.0 : 0.0);
+  }
   std::vector<Group> tile_groups;                 // tiles of grids with nl layers: [off, off+count)
   int ntiles_all = 0;
   int tile_rows = 16;
@@ -155,7 +171,7 @@ struct ProfScope {
   pg_ctx* c;
   ProfEvent ev{};
   bool on = false;
-  ProfScope(pg_ctx* ctx, int kind, int64_t units) : c(ctx) {
+  ProfScope(pg_ctx* ctx, int kind, int64_t units, double bytes = 0.0) : c(ctx) {
     if (c->profile_every <= 0) return;
     if (kind == 0 && (c->launch_counter++ % c->profile_every) != 0) return;
     on = true;
@@ -163,6 +179,7 @@ struct ProfScope {
     ev.b = prof_get(c);
     ev.kind = kind;
     ev.units = units;
+    ev.bytes = bytes;
     (void)hipEventRecord(ev.a, c->stream);
   }
   ~ProfScope() {
@@ -180,8 +197,8 @@ void prof_drain(pg_ctx* c) {
     (void)hipEventElapsedTime(&ms, e.a, e.b);
     auto& A = c->prof_acc;
     switch (e.kind) {
-      case 0: A.sweep_launches++; A.sweep_ms += ms; A.sweep_node_updates += e.units; break;
-      case 1: A.resid_launches++; A.resid_ms += ms; A.resid_nodes += e.units; break;
+      case 0: A.sweep_launches++; A.sweep_ms += ms; A.sweep_node_updates += e.units; A.sweep_bytes += e.bytes; break;
+      case 1: A.resid_launches++; A.resid_ms += ms; A.resid_nodes += e.units; A.resid_bytes += e.bytes; break;
       case 2: A.rhs_launches++; A.rhs_ms += ms; break;
       default: A.other_launches++; A.other_ms += ms; break;
     }
@@ -198,73 +215,81 @@ void prof_drain(pg_ctx* c) {
 pg_status build_grid(pg_ctx* c, int gi) {
   GridHost& G = c->grids[gi];
   const double h = c->opt.h;
-  const int64_t n = G.n, P = G.P;
-  const int nx = G.nx, ny = G.ny, nl = G.nl;
-  std::vector<double> gE(n, 0.0), gN(n, 0.0), gU(n, 0.0), D(n, 0.0), ch(n), bc(n, 0.0);
+  const int nx = G.nx, ny = G.ny, nl = G.nl, X = G.X;
+  const int64_t ns = G.nstore, PS = (int64_t)X * ny;  // storage slots, storage layer stride
+  auto sidx = [&](int64_t node) { return G.storage(node); };
+  std::vector<double> gE(ns, 0.0), gN(ns, 0.0), gU(ns, 0.0), D(ns, 0.0), ch(ns, 0.0), bc(ns, 0.0);
   for (int l = 0; l < nl; ++l)
     for (int y = 0; y < ny; ++y)
       for (int x = 0; x < nx; ++x) {
-        const int64_t i = (int64_t)l * P + (int64_t)y * nx + x;
+        const int64_t i = (int64_t)l * PS + (int64_t)y * X + x;
         if (x + 1 < nx) gE[i] = G.gE[((int64_t)l * ny + y) * (nx - 1) + x];
         if (y + 1 < ny) gN[i] = G.gN[((int64_t)l * (ny - 1) + y) * nx + x];
+        ch[i] = G.C[((int64_t)l * ny + y) * nx + x] / h;
       }
   G.ind_a.clear(); G.ind_b.clear(); G.ind_branch.clear();
   std::vector<double> geq, alpha;
   const int nv = (int)G.via_node.size(), np = (int)G.pad_node.size();
   for (int k = 0; k < nv; ++k) {
-    const int a = G.via_node[k];
+    const int64_t a = sidx(G.via_node[k]);
     const double L = G.via_L.empty() ? 0.0 : G.via_L[k];
     if (L > 0) {
       const double R = 1.0 / G.via_g[k];
       gU[a] += h / (L + h * R);
-      G.ind_a.push_back(a); G.ind_b.push_back(a + (int32_t)P); G.ind_branch.push_back(k);
+      G.ind_a.push_back((int32_t)a); G.ind_b.push_back((int32_t)(a + PS)); G.ind_branch.push_back(k);
       geq.push_back(h / (L + h * R)); alpha.push_back(L / (L + h * R));
     } else {
       gU[a] += G.via_g[k];
     }
   }
   for (int k = 0; k < np; ++k) {
-    const int a = G.pad_node[k];
+    const int64_t a = sidx(G.pad_node[k]);
     const double L = G.pad_L.empty() ? 0.0 : G.pad_L[k];
     double g = G.pad_g[k];
     if (L > 0) {
       const double R = 1.0 / G.pad_g[k];
       g = h / (L + h * R);
-      G.ind_a.push_back(a); G.ind_b.push_back(-1); G.ind_branch.push_back(nv + k);
+      G.ind_a.push_back((int32_t)a); G.ind_b.push_back(-1); G.ind_branch.push_back(nv + k);
       geq.push_back(g); alpha.push_back(L / (L + h * R));
     }
     D[a] += g;
     bc[a] += g * G.vdd;
   }
-  for (int64_t i = 0; i < n; ++i) {
-    const int64_t x = i % nx, y = (i / nx) % ny, l = i / P;
-    ch[i] = G.C[i] / h;
-    double s = ch[i] + gE[i] + gN[i] + gU[i];
-    if (x > 0) s += gE[i - 1];
-    if (y > 0) s += gN[i - nx];
-    if (l > 0) s += gU[i - P];
-    D[i] += s;
-  }
+  // diagonal of M and its inverse; padding slots keep D = 0 and invD = 0
+  std::vector<double> inv(ns, 0.0);
+  for (int l = 0; l < nl; ++l)
+    for (int y = 0; y < ny; ++y)
+      for (int x = 0; x < nx; ++x) {
+        const int64_t i = (int64_t)l * PS + (int64_t)y * X + x;
+        double s = ch[i] + gE[i] + gN[i] + gU[i];
+        if (x > 0) s += gE[i - 1];
+        if (y > 0) s += gN[i - X];
+        if (l > 0) s += gU[i - PS];
+        D[i] += s;
+        inv[i] = 1.0 / D[i];
+      }
   PG_TRY(upload(c, G.gE64, gE)); PG_TRY(upload(c, G.gN64, gN)); PG_TRY(upload(c, G.gU64, gU));
   PG_TRY(upload(c, G.D64, D)); PG_TRY(upload(c, G.ch64, ch)); PG_TRY(upload(c, G.bconst64, bc));
   const bool f32 = fp32_mode(c);
   if (f32) {
-    std::vector<float> a(n), b(n), u(n), q(n);
-    for (int64_t i = 0; i < n; ++i) {
-      a[i] = (float)gE[i]; b[i] = (float)gN[i]; u[i] = (float)gU[i]; q[i] = (float)(1.0 / D[i]);
+    std::vector<float> a(ns), b(ns), u(ns), q(ns);
+    for (int64_t i = 0; i < ns; ++i) {
+      a[i] = (float)gE[i]; b[i] = (float)gN[i]; u[i] = (float)gU[i]; q[i] = (float)inv[i];
     }
     PG_TRY(upload(c, G.gEs, a)); PG_TRY(upload(c, G.gNs, b)); PG_TRY(upload(c, G.gUs, u));
     PG_TRY(upload(c, G.invDs, q));
   } else {
-    std::vector<double> q(n);
-    for (int64_t i = 0; i < n; ++i) q[i] = 1.0 / D[i];
     dfree(G.gEs); dfree(G.gNs); dfree(G.gUs);
-    PG_TRY(upload(c, G.invDs, q));
+    PG_TRY(upload(c, G.invDs, inv));
   }
   const size_t es = f32 ? sizeof(float) : sizeof(double);
-  const size_t ns = (size_t)n * G.S;
+  const size_t nss = (size_t)ns * G.S;
   if (G.sweep_fp32 != (int)f32) {
-    PG_TRY(dalloc(c, G.r, ns * es)); PG_TRY(dalloc(c, G.d0, ns * es)); PG_TRY(dalloc(c, G.d1, ns * es));
+    PG_TRY(dalloc(c, G.r, nss * es)); PG_TRY(dalloc(c, G.d0, nss * es)); PG_TRY(dalloc(c, G.d1, nss * es));
+    // padding slots of the correction and residual must read as zero
+    HIP_TRY(c, hipMemsetAsync(G.r.p, 0, nss * es, c->stream));
+    HIP_TRY(c, hipMemsetAsync(G.d0.p, 0, nss * es, c->stream));
+    HIP_TRY(c, hipMemsetAsync(G.d1.p, 0, nss * es, c->stream));
     G.sweep_fp32 = (int)f32;
   }
   // inductors: keep the branch currents if the branch set is unchanged
@@ -276,10 +301,10 @@ pg_status build_grid(pg_ctx* c, int gi) {
     if (ni) HIP_TRY(c, hipMemsetAsync(G.ind_i_d.p, 0, (size_t)ni * G.S * sizeof(double), c->stream));
   }
   if (ni) {
-    std::vector<int32_t> cnt(n + 1, 0);
+    std::vector<int32_t> cnt(ns + 1, 0);
     for (int k = 0; k < ni; ++k) { cnt[G.ind_a[k] + 1]++; if (G.ind_b[k] >= 0) cnt[G.ind_b[k] + 1]++; }
-    for (int64_t i = 0; i < n; ++i) cnt[i + 1] += cnt[i];
-    std::vector<int32_t> inc(cnt[n]), fillp(cnt.begin(), cnt.end() - 1);
+    for (int64_t i = 0; i < ns; ++i) cnt[i + 1] += cnt[i];
+    std::vector<int32_t> inc(cnt[ns]), fillp(cnt.begin(), cnt.end() - 1);
     for (int k = 0; k < ni; ++k) {
       inc[fillp[G.ind_a[k]]++] = k + 1;
       if (G.ind_b[k] >= 0) inc[fillp[G.ind_b[k]]++] = -(k + 1);
@@ -288,6 +313,7 @@ pg_status build_grid(pg_ctx* c, int gi) {
   } else {
     dfree(G.inc_off_d); dfree(G.inc_ind_d);
   }
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
   return PG_OK;
 }
 
@@ -295,7 +321,7 @@ pg_status prepare(pg_ctx* c) {
   if (c->grids.empty()) return set_err(c, PG_ERR_STATE, "no grid uploaded");
   if (!c->dirty) return PG_OK;
   const int G = (int)c->grids.size();
-  c->tile_rows = c->opt.tile_rows ? c->opt.tile_rows : 16;
+  c->tile_rows = c->opt.tile_rows ? c->opt.tile_rows : 8;
   for (int g = 0; g < G; ++g) PG_TRY(build_grid(c, g));
   // grid descriptors
   std::vector<GridDesc> desc(G);
@@ -304,7 +330,7 @@ pg_status prepare(pg_ctx* c) {
     GridHost& H = c->grids[g];
     GridDesc& D = desc[g];
     std::memset(&D, 0, sizeof D);
-    D.nx = H.nx; D.ny = H.ny; D.nl = H.nl; D.S = H.S; D.n = H.n;
+    D.nx = H.nx; D.ny = H.ny; D.nl = H.nl; D.S = H.S; D.X = H.X; D.nstore = H.nstore;
     D.gE64 = (const double*)H.gE64.p; D.gN64 = (const double*)H.gN64.p; D.gU64 = (const double*)H.gU64.p;
     D.D64 = (const double*)H.D64.p; D.ch64 = (const double*)H.ch64.p; D.bconst64 = (const double*)H.bconst64.p;
     if (fp32_mode(c)) { D.gEs = H.gEs.p; D.gNs = H.gNs.p; D.gUs = H.gUs.p; }
@@ -351,7 +377,7 @@ pg_status prepare(pg_ctx* c) {
       const Src& S = H.src[s];
       for (size_t k = 0; k < S.node.size(); ++k) {
         sg.push_back(g);
-        si.push_back((int32_t)((int64_t)S.node[k] * H.S + s));
+        si.push_back((int32_t)(H.storage(S.node[k]) * H.S + s));
         for (int j = S.off[k]; j < S.off[k + 1]; ++j) { st.push_back(S.t[j]); sv.push_back(S.i[j]); }
         so.push_back((int32_t)st.size());
       }
@@ -425,7 +451,7 @@ pg_status check_gs(pg_ctx* c, int grid, int scen) {
 pg_status launch_resid_all(pg_ctx* c, int has_d, int din) {
   const Tile* T = (const Tile*)c->tiles_all.p;
   for (auto& grp : c->tile_groups) {
-    ProfScope ps(c, 1, grp.nodes);
+    ProfScope ps(c, 1, grp.nodes, grp.nodes * c->resid_bytes_per_node(grp, has_d != 0));
     hipError_t e = launch_resid(fp32_mode(c), grp.nl, c->tile_rows, T + grp.off, grp.count,
                                 (const GridDesc*)c->grid_desc.p, c->ctl, has_d, din, c->stream);
     if (e != hipSuccess) return set_err(c, PG_ERR_DEVICE, "residual launch: %s", hipGetErrorString(e));
@@ -437,7 +463,7 @@ pg_status launch_sweeps(pg_ctx* c, int nchk) {
   const Tile* T = (const Tile*)c->tiles_all.p;
   for (int s = 0; s < nchk; ++s) {
     for (auto& grp : c->tile_groups) {
-      ProfScope ps(c, 0, grp.nodes);
+      ProfScope ps(c, 0, grp.nodes, grp.nodes * c->sweep_bytes_per_node(grp, s == 0));
       hipError_t e = launch_sweep(fp32_mode(c), c->opt.ordering, grp.nl, c->tile_rows,
                                   T + grp.off, grp.count,
                                   (const GridDesc*)c->grid_desc.p, c->ctl, s & 1, s == 0 ? 1 : 0,
@@ -526,11 +552,11 @@ pg_status one_step(pg_ctx* c) {
 }
 
 pg_status fill_v(pg_ctx* c, GridHost& H, const double* v, int scen, int32_t vidx) {
-  // write the voltages of one scenario into the current buffer (scenario-minor layout)
-  std::vector<double> buf((size_t)H.n * H.S);
+  // write the voltages of one scenario into the current buffer (storage layout, scenario-minor)
+  std::vector<double> buf((size_t)H.nstore * H.S);
   DBuf& dst = vidx ? H.v1 : H.v0;
-  if (H.S > 1) HIP_TRY(c, hipMemcpy(buf.data(), dst.p, buf.size() * sizeof(double), hipMemcpyDeviceToHost));
-  for (int64_t i = 0; i < H.n; ++i) buf[(size_t)i * H.S + scen] = v ? v[i] : H.vdd;
+  HIP_TRY(c, hipMemcpy(buf.data(), dst.p, buf.size() * sizeof(double), hipMemcpyDeviceToHost));
+  for (int64_t i = 0; i < H.n; ++i) buf[(size_t)H.storage(i) * H.S + scen] = v ? v[i] : H.vdd;
   HIP_TRY(c, hipMemcpy(dst.p, buf.data(), buf.size() * sizeof(double), hipMemcpyHostToDevice));
   return PG_OK;
 }
@@ -642,6 +668,8 @@ pg_status pg_upload_mesh(pg_ctx* c, const pg_mesh* m, int32_t n_scen, int32_t* g
   GridHost& H = c->grids.back();
   H.nx = m->nx; H.ny = m->ny; H.nl = m->nl; H.S = n_scen;
   H.P = (int64_t)m->nx * m->ny; H.n = H.P * m->nl; H.vdd = m->vdd;
+  H.X = (m->nx + kPitchAlign - 1) / kPitchAlign * kPitchAlign;
+  H.nstore = (int64_t)H.X * m->ny * m->nl;
   H.gE.assign(m->gE, m->gE + (size_t)m->nl * m->ny * (m->nx - 1));
   H.gN.assign(m->gN, m->gN + (size_t)m->nl * (m->ny - 1) * m->nx);
   H.C.assign(m->C, m->C + H.n);
@@ -653,7 +681,7 @@ pg_status pg_upload_mesh(pg_ctx* c, const pg_mesh* m, int32_t n_scen, int32_t* g
   if (m->pad_L) H.pad_L.assign(m->pad_L, m->pad_L + m->n_pads);
   H.src.assign(n_scen, Src{});
   for (auto& s : H.src) s.off = {0};
-  const size_t ns = (size_t)H.n * H.S;
+  const size_t ns = (size_t)H.nstore * H.S;
   pg_status ps;
   if ((ps = dalloc(c, H.v0, ns * sizeof(double))) != PG_OK || (ps = dalloc(c, H.v1, ns * sizeof(double))) != PG_OK ||
       (ps = dalloc(c, H.b, ns * sizeof(double))) != PG_OK) {
@@ -793,13 +821,9 @@ pg_status pg_read_voltages(pg_ctx* c, int32_t grid, int32_t scen, double* out, i
   HIP_TRY(c, hipSetDevice(c->device));
   const int32_t vi = cur_vidx(c, grid);
   DBuf& src = vi ? H.v1 : H.v0;
-  if (H.S == 1) {
-    HIP_TRY(c, hipMemcpy(out, src.p, H.n * sizeof(double), hipMemcpyDeviceToHost));
-  } else {
-    std::vector<double> buf((size_t)H.n * H.S);
-    HIP_TRY(c, hipMemcpy(buf.data(), src.p, buf.size() * sizeof(double), hipMemcpyDeviceToHost));
-    for (int64_t i = 0; i < H.n; ++i) out[i] = buf[(size_t)i * H.S + scen];
-  }
+  std::vector<double> buf((size_t)H.nstore * H.S);
+  HIP_TRY(c, hipMemcpy(buf.data(), src.p, buf.size() * sizeof(double), hipMemcpyDeviceToHost));
+  for (int64_t i = 0; i < H.n; ++i) out[i] = buf[(size_t)H.storage(i) * H.S + scen];
   return PG_OK;
 }
 
@@ -807,7 +831,8 @@ pg_status pg_read_voltages_dev(pg_ctx* c, int32_t grid, int32_t scen, double* de
   PG_TRY(check_gs(c, grid, scen));
   GridHost& H = c->grids[grid];
   if (!dev_out || n < H.n) return set_err(c, PG_ERR_INVALID_ARG, "output buffer too small");
-  if (H.S != 1) return set_err(c, PG_ERR_UNSUPPORTED, "device read of one scenario of a batched grid");
+  if (H.S != 1 || H.X != H.nx)
+    return set_err(c, PG_ERR_UNSUPPORTED, "device read needs one scenario and nx a multiple of %d", kPitchAlign);
   HIP_TRY(c, hipSetDevice(c->device));
   const int32_t vi = cur_vidx(c, grid);
   DBuf& src = vi ? H.v1 : H.v0;

@@ -74,7 +74,7 @@ pg_status pg_default_options(pg_options* o) {
   o->check_every = 8;
   o->precision = PG_PREC_FP64;
   o->ordering = PG_ORDER_RED_BLACK;
-  o->tile_rows = 16;
+  o->tile_rows = 8;
   o->lookahead = 1;
   return PG_OK;
 }
@@ -90,8 +90,8 @@ pg_status pg_validate_options(const pg_options* o, char* msg, size_t len) {
     return fail(PG_ERR_INVALID_ARG, msg, len, "unknown precision %d", o->precision);
   if (o->ordering != PG_ORDER_RED_BLACK && o->ordering != PG_ORDER_JACOBI)
     return fail(PG_ERR_INVALID_ARG, msg, len, "unknown ordering %d", o->ordering);
-  if (o->tile_rows != 0 && o->tile_rows != 8 && o->tile_rows != 16 && o->tile_rows != 32)
-    return fail(PG_ERR_INVALID_ARG, msg, len, "tile_rows must be 0, 8, 16 or 32 (got %d)", o->tile_rows);
+  if (o->tile_rows != 0 && o->tile_rows != 4 && o->tile_rows != 8 && o->tile_rows != 16)
+    return fail(PG_ERR_INVALID_ARG, msg, len, "tile_rows must be 0, 4, 8 or 16 (got %d)", o->tile_rows);
   if (o->lookahead < 0 || o->lookahead > 4) return fail(PG_ERR_INVALID_ARG, msg, len, "lookahead must be in 0..4");
   for (int i = 0; i < 6; ++i)
     if (o->reserved[i] != 0) return fail(PG_ERR_INVALID_ARG, msg, len, "reserved option fields must be zero");

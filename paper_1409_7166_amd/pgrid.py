@@ -59,7 +59,9 @@ class Stats(C.Structure):
 
 class KernelTimes(C.Structure):
     _fields_ = [("sweep_launches", C.c_int64), ("sweep_ms", C.c_double), ("sweep_node_updates", C.c_int64),
+                ("sweep_bytes", C.c_double),
                 ("resid_launches", C.c_int64), ("resid_ms", C.c_double), ("resid_nodes", C.c_int64),
+                ("resid_bytes", C.c_double),
                 ("rhs_launches", C.c_int64), ("rhs_ms", C.c_double),
                 ("other_launches", C.c_int64), ("other_ms", C.c_double)]
 
