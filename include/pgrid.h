@@ -106,7 +106,10 @@ typedef struct pg_stats {
   double seconds;             /* wall time inside pg_step / pg_run_transient */
 } pg_stats;
 
-/* Kernel timing gathered with HIP events on the context stream while profiling is on.
+/* Kernel timing gathered with HIP events on the context stream while profiling is on
+ * (pg_profile(ctx, k): every k-th block of back-to-back sweep launches of a refinement cycle is
+ * timed as one interval; residual and other launches are timed one by one).  Launches queued
+ * after a step had converged (which exit at once) are left out.
  * *_bytes are algorithmic bytes of the timed launches: every array the kernel needs read once
  * and every array it produces written once, with e = 4 (FP32 sweeps) or 8 (FP64) bytes:
  *   sweep:    e * (gE + gN + invD + r + d_new [+ d_old unless it starts from zero])
@@ -206,8 +209,8 @@ pg_status pg_read_inductor_currents(pg_ctx* ctx, int32_t grid, int32_t scen, dou
 pg_status pg_get_stats(const pg_ctx* ctx, pg_stats* out);
 pg_status pg_reset_stats(pg_ctx* ctx);
 
-/* Kernel timing with HIP events recorded around every launch on the context stream
- * (enable = 1), off (enable = 0).  pg_read_kernel_times synchronises the stream. */
+/* Kernel timing with HIP events on the context stream: enable = k > 0 times every k-th sweep
+ * block and every other launch, 0 turns it off.  pg_read_kernel_times synchronises the stream. */
 pg_status pg_profile(pg_ctx* ctx, int32_t enable);
 pg_status pg_read_kernel_times(pg_ctx* ctx, pg_kernel_times* out);
 

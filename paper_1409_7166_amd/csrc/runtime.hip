@@ -54,9 +54,11 @@ struct GridHost {
 
 struct ProfEvent {
   hipEvent_t a, b;
-  int kind;          // 0 sweep, 1 resid, 2 rhs, 3 other
+  int kind;          // 0 sweep, 1 resid, 2 rhs, 3 other, -1 idle (queued after convergence)
+  int chunk;         // refinement cycle of the step the launch belongs to (0: before any sweep)
   int64_t units;     // node-updates (sweep) or nodes (resid)
-  double bytes;      // algorithmic bytes of the launch
+  double bytes;      // algorithmic bytes of the launches
+  int launches;      // kernel launches between the two events
 };
 
 }  // namespace
@@ -96,6 +98,8 @@ struct pg_ctx {
   // profiling
   int profile_every = 0;
   int64_t launch_counter = 0;
+  int cur_chunk = 0;                             // refinement cycle being queued
+  int pred_chunks = 1;                           // cycles the previous step needed
   std::vector<ProfEvent> prof_live;
   std::vector<hipEvent_t> prof_pool;
   pg_kernel_times prof_acc{};
@@ -171,15 +175,17 @@ struct ProfScope {
   pg_ctx* c;
   ProfEvent ev{};
   bool on = false;
-  ProfScope(pg_ctx* ctx, int kind, int64_t units, double bytes = 0.0) : c(ctx) {
+  ProfScope(pg_ctx* ctx, int kind, int64_t units, double bytes = 0.0, int launches = 1) : c(ctx) {
     if (c->profile_every <= 0) return;
     if (kind == 0 && (c->launch_counter++ % c->profile_every) != 0) return;
     on = true;
     ev.a = prof_get(c);
     ev.b = prof_get(c);
     ev.kind = kind;
+    ev.chunk = c->cur_chunk;
     ev.units = units;
     ev.bytes = bytes;
+    ev.launches = launches;
     (void)hipEventRecord(ev.a, c->stream);
   }
   ~ProfScope() {
@@ -197,7 +203,8 @@ void prof_drain(pg_ctx* c) {
     (void)hipEventElapsedTime(&ms, e.a, e.b);
     auto& A = c->prof_acc;
     switch (e.kind) {
-      case 0: A.sweep_launches++; A.sweep_ms += ms; A.sweep_node_updates += e.units; A.sweep_bytes += e.bytes; break;
+      case -1: break;
+      case 0: A.sweep_launches += e.launches; A.sweep_ms += ms; A.sweep_node_updates += e.units; A.sweep_bytes += e.bytes; break;
       case 1: A.resid_launches++; A.resid_ms += ms; A.resid_nodes += e.units; A.resid_bytes += e.bytes; break;
       case 2: A.rhs_launches++; A.rhs_ms += ms; break;
       default: A.other_launches++; A.other_ms += ms; break;
@@ -459,11 +466,16 @@ pg_status launch_resid_all(pg_ctx* c, int has_d, int din) {
   return PG_OK;
 }
 
+// The nchk sweeps of a cycle over one tile group are timed as one block of back-to-back
+// launches (one event pair per block, so event overhead does not inflate the per-launch
+// average); every profile_every-th block is timed.
 pg_status launch_sweeps(pg_ctx* c, int nchk) {
   const Tile* T = (const Tile*)c->tiles_all.p;
-  for (int s = 0; s < nchk; ++s) {
-    for (auto& grp : c->tile_groups) {
-      ProfScope ps(c, 0, grp.nodes, grp.nodes * c->sweep_bytes_per_node(grp, s == 0));
+  for (auto& grp : c->tile_groups) {
+    const double bytes = grp.nodes * (c->sweep_bytes_per_node(grp, true) +
+                                      (nchk - 1) * c->sweep_bytes_per_node(grp, false));
+    ProfScope ps(c, 0, grp.nodes * nchk, bytes, nchk);
+    for (int s = 0; s < nchk; ++s) {
       hipError_t e = launch_sweep(fp32_mode(c), c->opt.ordering, grp.nl, c->tile_rows,
                                   T + grp.off, grp.count,
                                   (const GridDesc*)c->grid_desc.p, c->ctl, s & 1, s == 0 ? 1 : 0,
@@ -513,29 +525,43 @@ pg_status one_step(pg_ctx* c) {
     return PG_OK;
   };
   std::deque<int> pending;
+  const size_t prof_base = c->prof_live.size();
+  c->cur_chunk = 0;
   PG_TRY(decide(0));
   pending.push_back(slot);
   slot = (slot + 1) % nslots;
   const int din_final = nchk & 1;  // buffer holding the correction after nchk sweeps
   const int max_chunks = (c->opt.max_sweeps + nchk - 1) / nchk;
-  int issued = 0;
-  // Keep up to `lookahead` refinement cycles queued beyond the one whose decision the host
-  // is waiting for; cycles queued after convergence find every grid inactive and exit at once.
+  int issued = 0, consumed = 0, last = -1;
+  // Refinement cycle j (j >= 1) is nchk sweeps, a residual and a decision.  Queue as many
+  // cycles as the previous step needed before waiting; past that prediction keep `lookahead`
+  // cycles queued beyond the one whose decision the host waits for.  Cycles queued after
+  // convergence find every grid inactive and exit at once.
   while (true) {
-    while ((int)pending.size() <= L && issued < max_chunks) {
+    const int want = consumed <= c->pred_chunks ? c->pred_chunks : consumed + L;
+    while (issued < max_chunks && issued < want) {
+      c->cur_chunk = ++issued;
       PG_TRY(launch_sweeps(c, nchk));
       PG_TRY(launch_resid_all(c, 1, din_final));
       PG_TRY(decide(1));
       pending.push_back(slot);
       slot = (slot + 1) % nslots;
-      ++issued;
     }
     if (pending.empty()) break;
     const int s0 = pending.front();
     pending.pop_front();
     HIP_TRY(c, hipEventSynchronize(c->flag_events[s0]));
-    if (__atomic_load_n(c->host_flags + s0, __ATOMIC_ACQUIRE) == 0) break;
+    ++consumed;
+    if (__atomic_load_n(c->host_flags + s0, __ATOMIC_ACQUIRE) == 0) {
+      last = consumed - 1;
+      break;
+    }
   }
+  if (last < 0) last = issued;
+  c->pred_chunks = last;
+  c->cur_chunk = 0;
+  for (size_t q = prof_base; q < c->prof_live.size(); ++q)
+    if (c->prof_live[q].chunk > last) c->prof_live[q].kind = -1;
   {
     ProfScope ps(c, 3, 0);
     e = launch_step_end(k, G, c->stream);
