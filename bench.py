@@ -31,7 +31,7 @@ def parse():
     ap.add_argument("--steps", type=int, default=1000)
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--workload", default="config1", choices=["config0", "config1", "config2", "config4",
-                                                             "config3b"])
+                                                             "config3a", "config3b"])
     ap.add_argument("--tol", type=float, default=1e-6)
     ap.add_argument("--precision", default=None, choices=[None, "fp64", "fp32+ref"])
     ap.add_argument("--omega", type=float, default=None)
@@ -53,6 +53,7 @@ TUNED = {
     "config0": dict(omega=1.6, check_every=8),
     "config1": dict(omega=1.85, check_every=8),
     "config2": dict(omega=1.9, check_every=16),
+    "config3a": dict(omega=1.6, check_every=8),
     "config3b": dict(omega=1.6, check_every=8),
     "config4": dict(omega=1.5, check_every=8),
 }

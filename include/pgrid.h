@@ -111,10 +111,11 @@ typedef struct pg_stats {
  * timed as one interval; residual and other launches are timed one by one).  Launches queued
  * after a step had converged (which exit at once) are left out.
  * *_bytes are algorithmic bytes of the timed launches: every array the kernel needs read once
- * and every array it produces written once, with e = 4 (FP32 sweeps) or 8 (FP64) bytes:
- *   sweep:    e * (gE + gN + invD + r + d_new [+ d_old unless it starts from zero])
- *             + e * (nl-1)/nl (via conductances exist below the top layer only)   per node
- *   residual: 8 * (v + b + D + gE + gN) + 8 * (nl-1)/nl + e * r [+ e * d + 8 * v_out]  per node */
+ * and every array it produces written once, with e = 4 (FP32 sweeps) or 8 (FP64) bytes.  Per
+ * node and scenario: sweep e * (r + d_new [+ d_old unless it starts from zero]), residual
+ * 8 * (v + b) + e * r [+ e * d + 8 * v_out]; per mesh node (coefficients are shared by the
+ * scenarios of a grid): sweep e * (gE + gN + invD) + e * (nl-1)/nl (vias exist below the top
+ * layer only), residual 8 * (D + gE + gN) + 8 * (nl-1)/nl. */
 typedef struct pg_kernel_times {
   int64_t sweep_launches;  double sweep_ms;      int64_t sweep_node_updates;  double sweep_bytes;
   int64_t resid_launches;  double resid_ms;      int64_t resid_nodes;         double resid_bytes;

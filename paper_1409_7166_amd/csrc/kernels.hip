@@ -117,8 +117,8 @@ __device__ __forceinline__ void put(V& v, int e, T val) {
 // ------------------------------------------------------------------------------------
 // Step bookkeeping
 // ------------------------------------------------------------------------------------
-__global__ void k_step_begin(Ctl c, int G) {
-  for (int g = threadIdx.x; g < G; g += blockDim.x) {
+__global__ void k_step_begin(Ctl c, int I) {
+  for (int g = threadIdx.x; g < I; g += blockDim.x) {
     c.active[g] = 1;
     c.step_sweeps[g] = 0;
     c.failed[g] = 0;
@@ -126,12 +126,12 @@ __global__ void k_step_begin(Ctl c, int G) {
   }
 }
 
-__global__ void k_decide(Ctl c, int G, double tol, int has_d, int nchk, int max_sweeps) {
+__global__ void k_decide(Ctl c, int I, double tol, int has_d, int nchk, int max_sweeps) {
   __shared__ int any;
   __shared__ int worked;
   if (threadIdx.x == 0) { any = 0; worked = 0; }
   __syncthreads();
-  for (int g = threadIdx.x; g < G; g += blockDim.x) {
+  for (int g = threadIdx.x; g < I; g += blockDim.x) {
     if (c.active[g]) {
       atomicOr(&worked, 1);
       if (has_d) {
@@ -156,12 +156,12 @@ __global__ void k_decide(Ctl c, int G, double tol, int has_d, int nchk, int max_
   }
 }
 
-__global__ void k_step_end(Ctl c, int G) {
+__global__ void k_step_end(Ctl c, int I) {
   if (threadIdx.x != 0) return;
   long long sw = 0, upd = 0;
   int mx = 0, fail = 0;
   double res = 0.0;
-  for (int g = 0; g < G; ++g) {
+  for (int g = 0; g < I; ++g) {
     const int s = c.step_sweeps[g];
     sw += s;
     upd += (long long)s * c.nodes[g];
@@ -188,38 +188,38 @@ __global__ __launch_bounds__(kThreads) void k_rhs(const Tile* __restrict__ tiles
   if (ti < 0) return;
   const Tile tl = tiles[ti];
   const GridDesc& G = grids[tl.grid];
-  const int X = G.X, ny = G.ny, S = G.S;
+  const int X = G.X, ny = G.ny;
   const int64_t P = (int64_t)X * ny;
-  const double* __restrict__ v = G.v[c.vidx[tl.grid]];
-  const int per_layer = kTileX * TY * S;
-  const int total = per_layer * G.nl;
-  for (int k = threadIdx.x; k < total; k += kThreads) {
+  const int64_t off = (int64_t)tl.scen * G.nstore;
+  const double* __restrict__ v = G.v[c.vidx[tl.item]] + off;
+  double* __restrict__ b = G.b + off;
+  const double* __restrict__ il = G.ind_i + (int64_t)tl.scen * G.n_ind;
+  const int per_layer = kTileX * TY;
+  for (int k = threadIdx.x; k < per_layer * G.nl; k += kThreads) {
     const int l = k / per_layer;
     const int rem = k - l * per_layer;
-    const int node_in = rem / S;
-    const int s = rem - node_in * S;
-    const int yy = node_in / kTileX, xx = node_in - yy * kTileX;
+    const int yy = rem / kTileX, xx = rem - yy * kTileX;
     const int x = tl.x0 + xx, y = tl.y0 + yy;
     if (x >= X || y >= ny) continue;
     const int64_t i = l * P + (int64_t)y * X + x;
-    const int64_t idx = i * S + s;
-    double bb = G.ch64[i] * v[idx] + G.bconst64[i];
+    double bb = G.ch64[i] * v[i] + G.bconst64[i];
     if (G.n_ind) {
       for (int j = G.inc_off[i]; j < G.inc_off[i + 1]; ++j) {
         const int e = G.inc_ind[j];
         const int kk = (e > 0 ? e : -e) - 1;
-        const double term = G.ind_alpha[kk] * G.ind_i[(int64_t)kk * S + s];
+        const double term = G.ind_alpha[kk] * il[kk];
         bb += (e > 0) ? -term : term;
       }
     }
-    G.b[idx] = bb;
+    b[i] = bb;
   }
 }
 
 // Piecewise-linear current sources at time t, subtracted from b (one thread per source).
 __global__ void k_sources(SourceTable src, const GridDesc* __restrict__ grids, double t) {
-  const int k = blockIdx.x * blockDim.x + threadIdx.x;
-  if (k >= src.count) return;
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= src.n_always + src.win_count) return;
+  const int k = q < src.n_always ? q : src.win_begin + (q - src.n_always);
   const int a = src.off[k], e = src.off[k + 1];
   const double* __restrict__ ts = src.t;
   const double* __restrict__ is = src.i;
@@ -257,14 +257,16 @@ __global__ __launch_bounds__(64 * TY) void k_resid(const Tile* __restrict__ tile
   const int ti = xcd_tile(ntiles);
   if (ti < 0) return;
   const Tile tl = tiles[ti];
-  const int g = tl.grid;
-  if (!c.active[g]) return;
-  const GridDesc& G = grids[g];
+  const int item = tl.item;
+  if (!c.active[item]) return;
+  const GridDesc& G = grids[tl.grid];
   const int nx = G.nx, ny = G.ny, X = G.X;
   const int64_t P = (int64_t)X * ny;
-  const int vi = c.vidx[g];
-  const double* __restrict__ v = G.v[vi];
-  const T* __restrict__ d = static_cast<const T*>(G.d[din]);
+  const int64_t off = (int64_t)tl.scen * G.nstore;
+  const int vi = c.vidx[item];
+  const double* __restrict__ v = G.v[vi] + off;
+  const T* __restrict__ d = static_cast<const T*>(G.d[din]) + off;
+  const double* __restrict__ bvec = G.b + off;
   const int x0 = tl.x0, y0 = tl.y0;
 
   // stage v + d on the tile with a one-pair, one-row halo (zero outside the storage)
@@ -292,12 +294,12 @@ __global__ __launch_bounds__(64 * TY) void k_resid(const Tile* __restrict__ tile
   const int hp = lane + 1, hy = row + 1;
   double m = 0.0;
   if (x < X && y < ny) {
-    double* __restrict__ vout = G.v[vi ^ 1];
-    T* __restrict__ r = static_cast<T*>(G.r);
+    double* __restrict__ vout = G.v[vi ^ 1] + off;
+    T* __restrict__ r = static_cast<T*>(G.r) + off;
 #pragma unroll
     for (int l = 0; l < NL; ++l) {
       const int64_t i = l * P + (int64_t)y * X + x;
-      const double2 b2 = ld2(G.b, i), D2 = ld2(G.D64, i), ge = ld2(G.gE64, i), gn = ld2(G.gN64, i);
+      const double2 b2 = ld2(bvec, i), D2 = ld2(G.D64, i), ge = ld2(G.gE64, i), gn = ld2(G.gN64, i);
       const double2 gs = y > 0 ? ld2(G.gN64, i - X) : make_double2(0.0, 0.0);
       const double gw = x > 0 ? G.gE64[i - 1] : 0.0;
       double2 gu = make_double2(0.0, 0.0), gd = make_double2(0.0, 0.0);
@@ -334,7 +336,7 @@ __global__ __launch_bounds__(64 * TY) void k_resid(const Tile* __restrict__ tile
   if (threadIdx.x == 0) {
     double bm = wmax[0];
     for (int w = 1; w < NT / 64; ++w) bm = nan_max(bm, wmax[w]);
-    atomicMax(&c.norm_bits[g], (unsigned long long)__double_as_longlong(bm));
+    atomicMax(&c.norm_bits[item], (unsigned long long)__double_as_longlong(bm));
   }
 }
 
@@ -353,19 +355,19 @@ __global__ __launch_bounds__(64 * TY) void k_sweep_rb(const Tile* __restrict__ t
   const int ti = xcd_tile(ntiles);
   if (ti < 0) return;
   const Tile tl = tiles[ti];
-  const int g = tl.grid;
-  if (!c.active[g]) return;
-  const GridDesc& G = grids[g];
+  if (!c.active[tl.item]) return;
+  const GridDesc& G = grids[tl.grid];
   const int ny = G.ny, X = G.X;
   const int64_t P = (int64_t)X * ny;
+  const int64_t off = (int64_t)tl.scen * G.nstore;
   const int x0 = tl.x0, y0 = tl.y0;
-  const T* __restrict__ dold = static_cast<const T*>(G.d[din]);
-  T* __restrict__ dnew = static_cast<T*>(G.d[din ^ 1]);
+  const T* __restrict__ dold = static_cast<const T*>(G.d[din]) + off;
+  T* __restrict__ dnew = static_cast<T*>(G.d[din ^ 1]) + off;
   const T* __restrict__ gE = static_cast<const T*>(G.gEs);
   const T* __restrict__ gN = static_cast<const T*>(G.gNs);
   const T* __restrict__ gU = static_cast<const T*>(G.gUs);
   const T* __restrict__ invD = static_cast<const T*>(G.invDs);
-  const T* __restrict__ r = static_cast<const T*>(G.r);
+  const T* __restrict__ r = static_cast<const T*>(G.r) + off;
 
   // stage the old correction (zero outside the storage, and everywhere on a cold start)
   for (int k = threadIdx.x; k < NL * HY * HP; k += NT) {
@@ -445,18 +447,18 @@ __global__ __launch_bounds__(kThreads) void k_sweep_jacobi(const Tile* __restric
   const int ti = xcd_tile(ntiles);
   if (ti < 0) return;
   const Tile tl = tiles[ti];
-  const int g = tl.grid;
-  if (!c.active[g]) return;
-  const GridDesc& G = grids[g];
+  if (!c.active[tl.item]) return;
+  const GridDesc& G = grids[tl.grid];
   const int ny = G.ny, X = G.X;
   const int64_t P = (int64_t)X * ny;
-  const T* __restrict__ dold = static_cast<const T*>(G.d[din]);
-  T* __restrict__ dnew = static_cast<T*>(G.d[din ^ 1]);
+  const int64_t off = (int64_t)tl.scen * G.nstore;
+  const T* __restrict__ dold = static_cast<const T*>(G.d[din]) + off;
+  T* __restrict__ dnew = static_cast<T*>(G.d[din ^ 1]) + off;
   const T* __restrict__ gE = static_cast<const T*>(G.gEs);
   const T* __restrict__ gN = static_cast<const T*>(G.gNs);
   const T* __restrict__ gU = static_cast<const T*>(G.gUs);
   const T* __restrict__ invD = static_cast<const T*>(G.invDs);
-  const T* __restrict__ r = static_cast<const T*>(G.r);
+  const T* __restrict__ r = static_cast<const T*>(G.r) + off;
   for (int k = threadIdx.x; k < NL * TY * kTileX; k += kThreads) {
     const int l = k / (TY * kTileX);
     const int rem = k - l * (TY * kTileX);
@@ -488,17 +490,15 @@ __global__ void k_inductors(const GridDesc* __restrict__ grids, const int32_t* _
                             const int32_t* __restrict__ ind_local, int n_total, Ctl c) {
   const int j = blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= n_total) return;
-  const int g = ind_grid[j];
-  const GridDesc& G = grids[g];
+  const GridDesc& G = grids[ind_grid[j]];
   const int k = ind_local[j];
-  const int S = G.S;
-  const double* __restrict__ v = G.v[c.vidx[g]];
-  const int a = G.ind_a[k], bnode = G.ind_b[k];
+  const int a = G.ind_a[k], bslot = G.ind_b[k];
   const double geq = G.ind_geq[k], al = G.ind_alpha[k];
-  for (int s = 0; s < S; ++s) {
-    const double vb = bnode >= 0 ? v[(int64_t)bnode * S + s] : G.vdd;
-    const int64_t q = (int64_t)k * S + s;
-    G.ind_i[q] = al * G.ind_i[q] + geq * (v[(int64_t)a * S + s] - vb);
+  for (int s = 0; s < G.S; ++s) {
+    const double* __restrict__ v = G.v[c.vidx[G.item0 + s]] + (int64_t)s * G.nstore;
+    const double vb = bslot >= 0 ? v[bslot] : G.vdd;
+    double* q = G.ind_i + (int64_t)s * G.n_ind + k;
+    *q = al * *q + geq * (v[a] - vb);
   }
 }
 
@@ -507,19 +507,19 @@ __global__ void k_inductors(const GridDesc* __restrict__ grids, const int32_t* _
 // ------------------------------------------------------------------------------------
 static inline unsigned xcd_blocks(int ntiles) { return 8u * (unsigned)((ntiles + 7) / 8); }
 
-hipError_t launch_step_begin(const Ctl& c, int G, hipStream_t s) {
-  hipLaunchKernelGGL(k_step_begin, dim3(1), dim3(256), 0, s, c, G);
+hipError_t launch_step_begin(const Ctl& c, int I, hipStream_t s) {
+  hipLaunchKernelGGL(k_step_begin, dim3(1), dim3(256), 0, s, c, I);
   return hipGetLastError();
 }
 
-hipError_t launch_decide(const Ctl& c, int G, double tol, int has_d, int nchk, int max_sweeps,
+hipError_t launch_decide(const Ctl& c, int I, double tol, int has_d, int nchk, int max_sweeps,
                          hipStream_t s) {
-  hipLaunchKernelGGL(k_decide, dim3(1), dim3(256), 0, s, c, G, tol, has_d, nchk, max_sweeps);
+  hipLaunchKernelGGL(k_decide, dim3(1), dim3(256), 0, s, c, I, tol, has_d, nchk, max_sweeps);
   return hipGetLastError();
 }
 
-hipError_t launch_step_end(const Ctl& c, int G, hipStream_t s) {
-  hipLaunchKernelGGL(k_step_end, dim3(1), dim3(64), 0, s, c, G);
+hipError_t launch_step_end(const Ctl& c, int I, hipStream_t s) {
+  hipLaunchKernelGGL(k_step_end, dim3(1), dim3(64), 0, s, c, I);
   return hipGetLastError();
 }
 
@@ -532,8 +532,9 @@ hipError_t launch_rhs(const Tile* tiles, int ntiles, int tile_rows, const GridDe
 }
 
 hipError_t launch_sources(const SourceTable& src, const GridDesc* grids, double t, hipStream_t s) {
-  if (src.count <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_sources, dim3((src.count + 255) / 256), dim3(256), 0, s, src, grids, t);
+  const int n = src.n_always + src.win_count;
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_sources, dim3((n + 255) / 256), dim3(256), 0, s, src, grids, t);
   return hipGetLastError();
 }
 

@@ -11,14 +11,15 @@ constexpr int kThreads = 256;     // threads per workgroup of the element-wise k
 constexpr int kPitchAlign = 4;    // row pitch multiple (keeps pair and quad accesses aligned)
 
 // Per-grid device descriptor.  Every per-node array is stored with a row pitch X >= nx
-// (a multiple of kPitchAlign): storage index (l*ny + y)*X + x.  Coefficients are zero in the
-// padding columns, at x = nx-1 (gE), y = ny-1 (gN), on the top layer (gU) and wherever no via
-// exists; invD is zero in the padding, so padding corrections stay zero.  State arrays hold
-// nstore*S entries, scenario-minor (index storage*S + s).
+// (a multiple of kPitchAlign): slot (l*ny + y)*X + x.  Coefficients are zero in the padding
+// columns, at x = nx-1 (gE), y = ny-1 (gN), on the top layer (gU) and wherever no via exists;
+// invD is zero in the padding, so padding corrections stay zero.  A grid carries S current
+// scenarios that share its coefficients; state arrays are scenario-major (scenario s occupies
+// slots [s*nstore, (s+1)*nstore)), so one scenario is an ordinary contiguous field.
 struct GridDesc {
   int32_t nx, ny, nl, S;
   int32_t X;                       // row pitch
-  int32_t pad_;
+  int32_t item0;                   // control-block item of scenario 0 (item = item0 + s)
   int64_t nstore;                  // nl*ny*X storage slots per scenario
   // FP64 masters: conductances, diagonal of M, C/h, constant injection (pads x Vdd)
   const double* gE64;
@@ -32,50 +33,57 @@ struct GridDesc {
   const void* gNs;
   const void* gUs;
   const void* invDs;
-  // state
-  double* v[2];                    // ping-pong FP64 voltages; ctl.vidx selects the current one
+  // state, S * nstore entries each
+  double* v[2];                    // ping-pong FP64 voltages; ctl.vidx[item] selects the current one
   double* b;                       // right-hand side of the current step
   void* r;                         // residual b - M v at the last check (sweep precision)
   void* d[2];                      // correction ping-pong (sweep precision)
   // inductive branches (companion model); node-to-branch incidence in CSR form
   int32_t n_ind;
-  const int32_t* ind_a;            // near node
-  const int32_t* ind_b;            // far node, or -1 for the supply
+  const int32_t* ind_a;            // near slot
+  const int32_t* ind_b;            // far slot, or -1 for the supply
   const double* ind_geq;
   const double* ind_alpha;
-  double* ind_i;                   // [n_ind][S] branch currents
-  const int32_t* inc_off;          // [n+1] (null when n_ind == 0)
-  const int32_t* inc_ind;          // signed: k+1 if the node is ind_a[k], -(k+1) if ind_b[k]
+  double* ind_i;                   // [S][n_ind] branch currents
+  const int32_t* inc_off;          // [nstore+1] (null when n_ind == 0)
+  const int32_t* inc_ind;          // signed: k+1 if the slot is ind_a[k], -(k+1) if ind_b[k]
   double vdd;
 };
 
-// One 64 x rows tile of one grid (all layers, all scenarios).
+// One 128 x rows tile of one scenario of one grid (all layers).
 struct Tile {
   int32_t grid;
+  int32_t item;                    // control-block item (grid, scenario)
+  int32_t scen;
   int32_t x0;
   int32_t y0;
   int32_t pad;
 };
 
-// Flattened current sources of every grid and scenario.
+// Flattened current sources of every grid and scenario.  A step visits sources
+// [0, n_always) and [win_begin, win_begin + win_count).
 struct SourceTable {
   int32_t count;
   const int32_t* grid;
-  const int32_t* index;            // node*S + scenario within the grid's state arrays
+  const int32_t* index;            // scenario*nstore + slot within the grid's state arrays
   const int32_t* off;              // [count+1] into t / i
   const double* t;
   const double* i;
+  int32_t n_always;
+  int32_t win_begin;
+  int32_t win_count;
 };
 
-// Device-side control block: per-grid convergence state, decided on the device so the
-// host never has to read a residual before queueing the next refinement cycle.
+// Device-side control block.  An item is one scenario of one grid; every item converges on
+// its own (per-item masks), and the decision is taken on the device so the host never has to
+// read a residual before queueing the next refinement cycle.
 struct Ctl {
-  unsigned long long* norm_bits;   // [G] running max of the scaled residual (bits of a double >= 0)
-  double* last_norm;               // [G]
-  int32_t* active;                 // [G]
-  int32_t* vidx;                   // [G]
-  int32_t* step_sweeps;            // [G]
-  int32_t* failed;                 // [G]
+  unsigned long long* norm_bits;   // [I] running max of the scaled residual (bits of a double >= 0)
+  double* last_norm;               // [I]
+  int32_t* active;                 // [I]
+  int32_t* vidx;                   // [I]
+  int32_t* step_sweeps;            // [I]
+  int32_t* failed;                 // [I]
   int32_t* any_active;             // [1]
   // running statistics, updated once per step on the device
   long long* stat_sweeps;          // [1]
@@ -86,7 +94,7 @@ struct Ctl {
   double* stat_last_res;           // [1]
   double* stat_max_res;            // [1]
   int32_t* stat_failed;            // [1]
-  const long long* nodes;          // [G] n*S
+  const long long* nodes;          // [I] mesh nodes of the item's grid
 };
 
 // ---- launch wrappers (kernels.hip) ----

@@ -32,6 +32,7 @@ struct DBuf {
 struct GridHost {
   int32_t nx = 0, ny = 0, nl = 0, S = 1;
   int32_t X = 0;                                 // storage row pitch (>= nx, multiple of kPitchAlign)
+  int32_t item0 = 0;                             // control-block item of scenario 0
   int64_t n = 0, P = 0;                          // mesh nodes, nodes per layer
   int64_t nstore = 0;                            // storage slots per scenario, nl*ny*X
   int64_t storage(int64_t node) const {          // mesh node id -> storage slot
@@ -75,20 +76,25 @@ struct pg_ctx {
   double seconds = 0.0;
   // device tables
   DBuf grid_desc, tiles_all, src_grid, src_index, src_off, src_t, src_i, ind_grid, ind_local;
-  struct Group { int nl, off, count; int64_t nodes; };
-  // algorithmic bytes per node of one sweep / residual launch over a group (see pgrid.h)
-  double sweep_bytes_per_node(const Group& g, bool zero_in) const {
+  // nodes: mesh nodes x scenarios of the group's grids; mesh_nodes: mesh nodes (coefficients
+  // are shared by the scenarios of a grid)
+  struct Group { int nl, off, count; int64_t nodes, mesh_nodes; };
+  // algorithmic bytes of one sweep / residual launch over a group (see pgrid.h)
+  double sweep_bytes(const Group& g, bool zero_in) const {
     const double e = opt.precision == PG_PREC_FP32_REFINE ? 4.0 : 8.0;
-    return e * (5.0 + (zero_in ? 0.0 : 1.0) + (g.nl - 1.0) / g.nl);
+    return e * ((zero_in ? 2.0 : 3.0) * g.nodes + (3.0 + (g.nl - 1.0) / g.nl) * g.mesh_nodes);
   }
-  double resid_bytes_per_node(const Group& g, bool has_d) const {
+  double resid_bytes(const Group& g, bool has_d) const {
     const double e = opt.precision == PG_PREC_FP32_REFINE ? 4.0 : 8.0;
-    return 8.0 * (5.0 + (g.nl - 1.0) / g.nl) + e + (has_d ? e + 8.0 : 0.0);
+    return (16.0 + e + (has_d ? e + 8.0 : 0.0)) * g.nodes + 8.0 * (3.0 + (g.nl - 1.0) / g.nl) * g.mesh_nodes;
   }
   std::vector<Group> tile_groups;                 // tiles of grids with nl layers: [off, off+count)
   int ntiles_all = 0;
   int tile_rows = 16;
   int n_src = 0, n_ind_total = 0;
+  int n_src_always = 0;                          // sources at [0, n_src_always) run every step
+  std::vector<double> win_t0;                    // first breakpoint of each windowed source (sorted)
+  double win_maxw = 0.0;                         // widest window
   // control block
   DBuf c_norm, c_last, c_active, c_vidx, c_sweeps, c_failed, c_any, c_stats64, c_stats32, c_statsd, c_nodes;
   Ctl ctl{};
@@ -332,12 +338,12 @@ pg_status prepare(pg_ctx* c) {
   for (int g = 0; g < G; ++g) PG_TRY(build_grid(c, g));
   // grid descriptors
   std::vector<GridDesc> desc(G);
-  std::vector<long long> nodes(G);
+  std::vector<long long> nodes;
   for (int g = 0; g < G; ++g) {
     GridHost& H = c->grids[g];
     GridDesc& D = desc[g];
     std::memset(&D, 0, sizeof D);
-    D.nx = H.nx; D.ny = H.ny; D.nl = H.nl; D.S = H.S; D.X = H.X; D.nstore = H.nstore;
+    D.nx = H.nx; D.ny = H.ny; D.nl = H.nl; D.S = H.S; D.X = H.X; D.item0 = H.item0; D.nstore = H.nstore;
     D.gE64 = (const double*)H.gE64.p; D.gN64 = (const double*)H.gN64.p; D.gU64 = (const double*)H.gU64.p;
     D.D64 = (const double*)H.D64.p; D.ch64 = (const double*)H.ch64.p; D.bconst64 = (const double*)H.bconst64.p;
     if (fp32_mode(c)) { D.gEs = H.gEs.p; D.gNs = H.gNs.p; D.gUs = H.gUs.p; }
@@ -351,7 +357,7 @@ pg_status prepare(pg_ctx* c) {
     D.ind_i = (double*)H.ind_i_d.p;
     D.inc_off = (const int32_t*)H.inc_off_d.p; D.inc_ind = (const int32_t*)H.inc_ind_d.p;
     D.vdd = H.vdd;
-    nodes[g] = (long long)H.n * H.S;
+    for (int sc = 0; sc < H.S; ++sc) nodes.push_back((long long)H.n);
   }
   PG_TRY(upload(c, c->grid_desc, desc));
   PG_TRY(upload(c, c->c_nodes, nodes));
@@ -362,34 +368,53 @@ pg_status prepare(pg_ctx* c) {
   c->tile_groups.clear();
   for (int nl = 1; nl <= 4; ++nl) {
     const int start = (int)tiles.size();
-    int64_t nodes_nl = 0;
+    int64_t nodes_nl = 0, mesh_nl = 0;
     for (int g = 0; g < G; ++g) {
       const GridHost& H = c->grids[g];
       if (H.nl != nl) continue;
       nodes_nl += H.n * H.S;
-      for (int y0 = 0; y0 < H.ny; y0 += TY)
-        for (int x0 = 0; x0 < H.nx; x0 += kTileX) tiles.push_back(Tile{g, x0, y0, 0});
+      mesh_nl += H.n;
+      for (int sc = 0; sc < H.S; ++sc)
+        for (int y0 = 0; y0 < H.ny; y0 += TY)
+          for (int x0 = 0; x0 < H.nx; x0 += kTileX) tiles.push_back(Tile{g, H.item0 + sc, sc, x0, y0, 0});
     }
     if ((int)tiles.size() > start)
-      c->tile_groups.push_back({nl, start, (int)tiles.size() - start, nodes_nl});
+      c->tile_groups.push_back({nl, start, (int)tiles.size() - start, nodes_nl, mesh_nl});
   }
   c->ntiles_all = (int)tiles.size();
   PG_TRY(upload(c, c->tiles_all, tiles));
-  // sources
-  std::vector<int32_t> sg, si, so{0};
-  std::vector<double> st, sv;
+  // sources: first those that are non-zero outside their breakpoints ("always"), then the
+  // windowed ones (zero before the first and after the last breakpoint, like every triangle)
+  // sorted by their first breakpoint, so a step only visits the windows that can contain t.
+  struct SrcRef { double t0, t1; int g, s; size_t k; };
+  std::vector<SrcRef> always, windowed;
   for (int g = 0; g < G; ++g) {
     const GridHost& H = c->grids[g];
-    for (int s = 0; s < H.S; ++s) {
-      const Src& S = H.src[s];
+    for (int sc = 0; sc < H.S; ++sc) {
+      const Src& S = H.src[sc];
       for (size_t k = 0; k < S.node.size(); ++k) {
-        sg.push_back(g);
-        si.push_back((int32_t)(H.storage(S.node[k]) * H.S + s));
-        for (int j = S.off[k]; j < S.off[k + 1]; ++j) { st.push_back(S.t[j]); sv.push_back(S.i[j]); }
-        so.push_back((int32_t)st.size());
+        const int a = S.off[k], b = S.off[k + 1];
+        SrcRef ref{S.t[a], S.t[b - 1], g, sc, k};
+        if (S.i[a] == 0.0 && S.i[b - 1] == 0.0) windowed.push_back(ref); else always.push_back(ref);
       }
     }
   }
+  std::stable_sort(windowed.begin(), windowed.end(), [](const SrcRef& x, const SrcRef& y) { return x.t0 < y.t0; });
+  c->n_src_always = (int)always.size();
+  c->win_t0.clear();
+  c->win_maxw = 0.0;
+  for (auto& w : windowed) { c->win_t0.push_back(w.t0); c->win_maxw = std::max(c->win_maxw, w.t1 - w.t0); }
+  std::vector<int32_t> sg, si, so{0};
+  std::vector<double> st, sv;
+  for (const auto* list : {&always, &windowed})
+    for (const SrcRef& ref : *list) {
+      const GridHost& H = c->grids[ref.g];
+      const Src& S = H.src[ref.s];
+      sg.push_back(ref.g);
+      si.push_back((int32_t)((int64_t)ref.s * H.nstore + H.storage(S.node[ref.k])));
+      for (int j = S.off[ref.k]; j < S.off[ref.k + 1]; ++j) { st.push_back(S.t[j]); sv.push_back(S.i[j]); }
+      so.push_back((int32_t)st.size());
+    }
   c->n_src = (int)sg.size();
   PG_TRY(upload(c, c->src_grid, sg)); PG_TRY(upload(c, c->src_index, si)); PG_TRY(upload(c, c->src_off, so));
   PG_TRY(upload(c, c->src_t, st)); PG_TRY(upload(c, c->src_i, sv));
@@ -404,24 +429,31 @@ pg_status prepare(pg_ctx* c) {
   return PG_OK;
 }
 
+int n_items(const pg_ctx* c) {
+  int I = 0;
+  for (auto& H : c->grids) I += H.S;
+  return I;
+}
+
 pg_status alloc_ctl(pg_ctx* c) {
-  const int G = (int)c->grids.size();
-  // grow the per-grid control arrays, preserving vidx (which buffer holds each grid's state)
-  std::vector<int32_t> vidx(G, 0);
-  if (c->c_vidx.p && G > 1)
-    HIP_TRY(c, hipMemcpy(vidx.data(), c->c_vidx.p, (G - 1) * sizeof(int32_t), hipMemcpyDeviceToHost));
-  PG_TRY(dalloc(c, c->c_norm, G * sizeof(unsigned long long)));
-  PG_TRY(dalloc(c, c->c_last, G * sizeof(double)));
-  PG_TRY(dalloc(c, c->c_active, G * sizeof(int32_t)));
-  PG_TRY(dalloc(c, c->c_vidx, G * sizeof(int32_t)));
-  PG_TRY(dalloc(c, c->c_sweeps, G * sizeof(int32_t)));
-  PG_TRY(dalloc(c, c->c_failed, G * sizeof(int32_t)));
-  HIP_TRY(c, hipMemcpy(c->c_vidx.p, vidx.data(), G * sizeof(int32_t), hipMemcpyHostToDevice));
-  HIP_TRY(c, hipMemset(c->c_norm.p, 0, G * sizeof(unsigned long long)));
-  HIP_TRY(c, hipMemset(c->c_last.p, 0, G * sizeof(double)));
-  HIP_TRY(c, hipMemset(c->c_active.p, 0, G * sizeof(int32_t)));
-  HIP_TRY(c, hipMemset(c->c_sweeps.p, 0, G * sizeof(int32_t)));
-  HIP_TRY(c, hipMemset(c->c_failed.p, 0, G * sizeof(int32_t)));
+  // grow the per-item control arrays, preserving vidx (which buffer holds each item's state)
+  const int I = n_items(c);
+  const int I_old = (int)(c->c_vidx.bytes / sizeof(int32_t));
+  std::vector<int32_t> vidx(I, 0);
+  if (c->c_vidx.p && I_old > 0)
+    HIP_TRY(c, hipMemcpy(vidx.data(), c->c_vidx.p, std::min(I_old, I) * sizeof(int32_t), hipMemcpyDeviceToHost));
+  PG_TRY(dalloc(c, c->c_norm, I * sizeof(unsigned long long)));
+  PG_TRY(dalloc(c, c->c_last, I * sizeof(double)));
+  PG_TRY(dalloc(c, c->c_active, I * sizeof(int32_t)));
+  PG_TRY(dalloc(c, c->c_vidx, I * sizeof(int32_t)));
+  PG_TRY(dalloc(c, c->c_sweeps, I * sizeof(int32_t)));
+  PG_TRY(dalloc(c, c->c_failed, I * sizeof(int32_t)));
+  HIP_TRY(c, hipMemcpy(c->c_vidx.p, vidx.data(), I * sizeof(int32_t), hipMemcpyHostToDevice));
+  HIP_TRY(c, hipMemset(c->c_norm.p, 0, I * sizeof(unsigned long long)));
+  HIP_TRY(c, hipMemset(c->c_last.p, 0, I * sizeof(double)));
+  HIP_TRY(c, hipMemset(c->c_active.p, 0, I * sizeof(int32_t)));
+  HIP_TRY(c, hipMemset(c->c_sweeps.p, 0, I * sizeof(int32_t)));
+  HIP_TRY(c, hipMemset(c->c_failed.p, 0, I * sizeof(int32_t)));
   Ctl& k = c->ctl;
   k.norm_bits = (unsigned long long*)c->c_norm.p;
   k.last_norm = (double*)c->c_last.p;
@@ -440,10 +472,10 @@ pg_status reset_stats_dev(pg_ctx* c) {
   return PG_OK;
 }
 
-int32_t cur_vidx(pg_ctx* c, int g) {
+int32_t cur_vidx(pg_ctx* c, int item) {
   int32_t v = 0;
   (void)hipStreamSynchronize(c->stream);
-  (void)hipMemcpy(&v, (const int32_t*)c->c_vidx.p + g, sizeof v, hipMemcpyDeviceToHost);
+  (void)hipMemcpy(&v, (const int32_t*)c->c_vidx.p + item, sizeof v, hipMemcpyDeviceToHost);
   return v;
 }
 
@@ -458,7 +490,7 @@ pg_status check_gs(pg_ctx* c, int grid, int scen) {
 pg_status launch_resid_all(pg_ctx* c, int has_d, int din) {
   const Tile* T = (const Tile*)c->tiles_all.p;
   for (auto& grp : c->tile_groups) {
-    ProfScope ps(c, 1, grp.nodes, grp.nodes * c->resid_bytes_per_node(grp, has_d != 0));
+    ProfScope ps(c, 1, grp.nodes, c->resid_bytes(grp, has_d != 0));
     hipError_t e = launch_resid(fp32_mode(c), grp.nl, c->tile_rows, T + grp.off, grp.count,
                                 (const GridDesc*)c->grid_desc.p, c->ctl, has_d, din, c->stream);
     if (e != hipSuccess) return set_err(c, PG_ERR_DEVICE, "residual launch: %s", hipGetErrorString(e));
@@ -472,8 +504,7 @@ pg_status launch_resid_all(pg_ctx* c, int has_d, int din) {
 pg_status launch_sweeps(pg_ctx* c, int nchk) {
   const Tile* T = (const Tile*)c->tiles_all.p;
   for (auto& grp : c->tile_groups) {
-    const double bytes = grp.nodes * (c->sweep_bytes_per_node(grp, true) +
-                                      (nchk - 1) * c->sweep_bytes_per_node(grp, false));
+    const double bytes = c->sweep_bytes(grp, true) + (nchk - 1) * c->sweep_bytes(grp, false);
     ProfScope ps(c, 0, grp.nodes * nchk, bytes, nchk);
     for (int s = 0; s < nchk; ++s) {
       hipError_t e = launch_sweep(fp32_mode(c), c->opt.ordering, grp.nl, c->tile_rows,
@@ -487,7 +518,7 @@ pg_status launch_sweeps(pg_ctx* c, int nchk) {
 }
 
 pg_status one_step(pg_ctx* c) {
-  const int G = (int)c->grids.size();
+  const int G = n_items(c);
   const int nchk = c->opt.check_every;
   const int L = c->opt.lookahead;
   Ctl k = c->ctl;
@@ -505,8 +536,12 @@ pg_status one_step(pg_ctx* c) {
     if (e != hipSuccess) return set_err(c, PG_ERR_DEVICE, "rhs launch: %s", hipGetErrorString(e));
   }
   {
+    // windowed sources whose window can contain t: first breakpoint in [t - widest, t]
+    const auto lo = std::lower_bound(c->win_t0.begin(), c->win_t0.end(), t - c->win_maxw) - c->win_t0.begin();
+    const auto hi = std::upper_bound(c->win_t0.begin(), c->win_t0.end(), t) - c->win_t0.begin();
     SourceTable st{c->n_src, (const int32_t*)c->src_grid.p, (const int32_t*)c->src_index.p,
-                   (const int32_t*)c->src_off.p, (const double*)c->src_t.p, (const double*)c->src_i.p};
+                   (const int32_t*)c->src_off.p, (const double*)c->src_t.p, (const double*)c->src_i.p,
+                   c->n_src_always, c->n_src_always + (int32_t)lo, (int32_t)(hi - lo)};
     ProfScope ps(c, 2, 0);
     e = launch_sources(st, (const GridDesc*)c->grid_desc.p, t, c->stream);
     if (e != hipSuccess) return set_err(c, PG_ERR_DEVICE, "source launch: %s", hipGetErrorString(e));
@@ -578,12 +613,11 @@ pg_status one_step(pg_ctx* c) {
 }
 
 pg_status fill_v(pg_ctx* c, GridHost& H, const double* v, int scen, int32_t vidx) {
-  // write the voltages of one scenario into the current buffer (storage layout, scenario-minor)
-  std::vector<double> buf((size_t)H.nstore * H.S);
-  DBuf& dst = vidx ? H.v1 : H.v0;
-  HIP_TRY(c, hipMemcpy(buf.data(), dst.p, buf.size() * sizeof(double), hipMemcpyDeviceToHost));
-  for (int64_t i = 0; i < H.n; ++i) buf[(size_t)H.storage(i) * H.S + scen] = v ? v[i] : H.vdd;
-  HIP_TRY(c, hipMemcpy(dst.p, buf.data(), buf.size() * sizeof(double), hipMemcpyHostToDevice));
+  // write the voltages of one scenario into its slice of the current buffer
+  std::vector<double> buf((size_t)H.nstore, H.vdd);
+  for (int64_t i = 0; i < H.n; ++i) buf[(size_t)H.storage(i)] = v ? v[i] : H.vdd;
+  double* dst = (double*)(vidx ? H.v1.p : H.v0.p) + (size_t)scen * H.nstore;
+  HIP_TRY(c, hipMemcpy(dst, buf.data(), buf.size() * sizeof(double), hipMemcpyHostToDevice));
   return PG_OK;
 }
 
@@ -688,11 +722,10 @@ pg_status pg_upload_mesh(pg_ctx* c, const pg_mesh* m, int32_t n_scen, int32_t* g
   pg_status st = pg_validate_mesh(m, msg, sizeof msg);
   if (st != PG_OK) return set_err(c, st, "%s", msg);
   if (n_scen < 1) return set_err(c, PG_ERR_INVALID_ARG, "n_scen must be >= 1");
-  if (n_scen > 1) return set_err(c, PG_ERR_UNSUPPORTED, "several scenarios per grid are not supported by this build");
   HIP_TRY(c, hipSetDevice(c->device));
   c->grids.emplace_back();
   GridHost& H = c->grids.back();
-  H.nx = m->nx; H.ny = m->ny; H.nl = m->nl; H.S = n_scen;
+  H.nx = m->nx; H.ny = m->ny; H.nl = m->nl; H.S = n_scen; H.item0 = n_items(c) - n_scen;
   H.P = (int64_t)m->nx * m->ny; H.n = H.P * m->nl; H.vdd = m->vdd;
   H.X = (m->nx + kPitchAlign - 1) / kPitchAlign * kPitchAlign;
   H.nstore = (int64_t)H.X * m->ny * m->nl;
@@ -780,13 +813,13 @@ pg_status pg_set_state(pg_ctx* c, int32_t grid, int32_t scen, const double* v, c
     for (int64_t k = 0; k < H.n; ++k)
       if (!std::isfinite(v[k])) return set_err(c, PG_ERR_INVALID_ARG, "v[%lld] is not finite", (long long)k);
   PG_TRY(prepare(c));
-  PG_TRY(fill_v(c, H, v, scen, cur_vidx(c, grid)));
+  PG_TRY(fill_v(c, H, v, scen, cur_vidx(c, H.item0 + scen)));
   const int ni = (int)H.ind_a.size();
   if (ni) {
-    std::vector<double> buf((size_t)ni * H.S);
-    HIP_TRY(c, hipMemcpy(buf.data(), H.ind_i_d.p, buf.size() * sizeof(double), hipMemcpyDeviceToHost));
-    for (int k = 0; k < ni; ++k) buf[(size_t)k * H.S + scen] = i_l ? i_l[H.ind_branch[k]] : 0.0;
-    HIP_TRY(c, hipMemcpy(H.ind_i_d.p, buf.data(), buf.size() * sizeof(double), hipMemcpyHostToDevice));
+    std::vector<double> buf(ni);
+    for (int k = 0; k < ni; ++k) buf[k] = i_l ? i_l[H.ind_branch[k]] : 0.0;
+    HIP_TRY(c, hipMemcpy((double*)H.ind_i_d.p + (size_t)scen * ni, buf.data(), ni * sizeof(double),
+                         hipMemcpyHostToDevice));
   }
   return PG_OK;
 }
@@ -845,11 +878,15 @@ pg_status pg_read_voltages(pg_ctx* c, int32_t grid, int32_t scen, double* out, i
   GridHost& H = c->grids[grid];
   if (!out || n < H.n) return set_err(c, PG_ERR_INVALID_ARG, "output buffer too small (need %lld)", (long long)H.n);
   HIP_TRY(c, hipSetDevice(c->device));
-  const int32_t vi = cur_vidx(c, grid);
-  DBuf& src = vi ? H.v1 : H.v0;
-  std::vector<double> buf((size_t)H.nstore * H.S);
-  HIP_TRY(c, hipMemcpy(buf.data(), src.p, buf.size() * sizeof(double), hipMemcpyDeviceToHost));
-  for (int64_t i = 0; i < H.n; ++i) out[i] = buf[(size_t)H.storage(i) * H.S + scen];
+  const int32_t vi = cur_vidx(c, H.item0 + scen);
+  const double* src = (const double*)(vi ? H.v1.p : H.v0.p) + (size_t)scen * H.nstore;
+  if (H.X == H.nx) {
+    HIP_TRY(c, hipMemcpy(out, src, H.n * sizeof(double), hipMemcpyDeviceToHost));
+    return PG_OK;
+  }
+  std::vector<double> buf((size_t)H.nstore);
+  HIP_TRY(c, hipMemcpy(buf.data(), src, buf.size() * sizeof(double), hipMemcpyDeviceToHost));
+  for (int64_t i = 0; i < H.n; ++i) out[i] = buf[(size_t)H.storage(i)];
   return PG_OK;
 }
 
@@ -857,12 +894,12 @@ pg_status pg_read_voltages_dev(pg_ctx* c, int32_t grid, int32_t scen, double* de
   PG_TRY(check_gs(c, grid, scen));
   GridHost& H = c->grids[grid];
   if (!dev_out || n < H.n) return set_err(c, PG_ERR_INVALID_ARG, "output buffer too small");
-  if (H.S != 1 || H.X != H.nx)
-    return set_err(c, PG_ERR_UNSUPPORTED, "device read needs one scenario and nx a multiple of %d", kPitchAlign);
+  if (H.X != H.nx)
+    return set_err(c, PG_ERR_UNSUPPORTED, "device read needs nx to be a multiple of %d", kPitchAlign);
   HIP_TRY(c, hipSetDevice(c->device));
-  const int32_t vi = cur_vidx(c, grid);
-  DBuf& src = vi ? H.v1 : H.v0;
-  HIP_TRY(c, hipMemcpyAsync(dev_out, src.p, H.n * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+  const int32_t vi = cur_vidx(c, H.item0 + scen);
+  const double* src = (const double*)(vi ? H.v1.p : H.v0.p) + (size_t)scen * H.nstore;
+  HIP_TRY(c, hipMemcpyAsync(dev_out, src, H.n * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
   return PG_OK;
 }
 
@@ -876,10 +913,11 @@ pg_status pg_read_inductor_currents(pg_ctx* c, int32_t grid, int32_t scen, doubl
   std::fill(out, out + nb, 0.0);
   const int ni = (int)H.ind_a.size();
   if (!ni) return PG_OK;
-  std::vector<double> buf((size_t)ni * H.S);
+  std::vector<double> buf(ni);
   HIP_TRY(c, hipStreamSynchronize(c->stream));
-  HIP_TRY(c, hipMemcpy(buf.data(), H.ind_i_d.p, buf.size() * sizeof(double), hipMemcpyDeviceToHost));
-  for (int k = 0; k < ni; ++k) out[H.ind_branch[k]] = buf[(size_t)k * H.S + scen];
+  HIP_TRY(c, hipMemcpy(buf.data(), (const double*)H.ind_i_d.p + (size_t)scen * ni, ni * sizeof(double),
+                       hipMemcpyDeviceToHost));
+  for (int k = 0; k < ni; ++k) out[H.ind_branch[k]] = buf[k];
   return PG_OK;
 }
 

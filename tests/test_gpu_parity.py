@@ -142,3 +142,44 @@ def test_no_convergence_reported_and_state_kept():
         assert ctx.time_index() == 50
         v = ctx.read_voltages()
         assert np.all(np.isfinite(v)) and np.max(1.0 - v) > 0
+
+
+@pytest.mark.parametrize("prec", [pg.PG_PREC_FP64, pg.PG_PREC_FP32_REFINE])
+def test_batched_scenarios_share_one_mesh(prec):
+    """Six current scenarios on one 70 x 44 mesh in one context: every scenario against its own
+    oracle transient, and scenarios converge independently (per-item masks)."""
+    base = small_rc(70, 44, seed=41, scenarios=6, steps=40)
+    mesh = base.meshes[0]
+    scen = [compressed(p, start=0.4, width=1.0) for p in base.pulses[0]]
+    scen[3] = Pulses(scen[3].node, np.zeros_like(scen[3].peak), scen[3].start, scen[3].width)
+    base.pulses[0] = scen
+    say(f"[gpu] 6 scenarios prec={prec}")
+    with gpu_context(base, precision=prec, tol=1e-11, omega=1.6) as ctx:
+        ctx.step(40)
+        got = [ctx.read_voltages(0, s) for s in range(6)]
+    for s, p in enumerate(scen):
+        Vref, _ = oracle_run(mesh, p, base.h, 40)
+        err = np.max(np.abs(got[s] - Vref[-1]))
+        say(f"  scenario {s}: err={err:.3e}")
+        assert err <= PARITY_V
+    assert np.max(np.abs(got[3] - 1.0)) <= 1e-12
+
+
+def test_uneven_grids_batched_in_one_launch():
+    """Three grids of different sizes and layer counts stepped together in one context."""
+    ws = [small_rc(33, 70, seed=51, steps=30), small_multilayer(side=77, seed=52, nl=2, pad_every=16, steps=30),
+          small_rc(130, 9, seed=53, steps=30)]
+    from workloads import Workload
+    w = Workload("mixed", [x.meshes[0] for x in ws], [[compressed(x.pulses[0][0], start=0.3, width=1.0)] for x in ws],
+                 ws[0].h, 30)
+    say("[gpu] 3 uneven grids")
+    with gpu_context(w, precision=pg.PG_PREC_FP32_REFINE, tol=1e-11, omega=1.6) as ctx:
+        ctx.step(30)
+        got = [ctx.read_voltages(g, 0) for g in range(3)]
+        st = ctx.stats()
+    for g in range(3):
+        Vref, _ = oracle_run(w.meshes[g], w.pulses[g][0], w.h, 30)
+        err = np.max(np.abs(got[g] - Vref[-1]))
+        say(f"  grid {g}: err={err:.3e}")
+        assert err <= PARITY_V
+    assert st["node_updates"] > 0
