@@ -207,6 +207,31 @@ pg_status pg_read_voltages(pg_ctx* ctx, int32_t grid, int32_t scen, double* out,
 pg_status pg_read_voltages_dev(pg_ctx* ctx, int32_t grid, int32_t scen, double* dev_out, int64_t n);
 pg_status pg_read_inductor_currents(pg_ctx* ctx, int32_t grid, int32_t scen, double* out, int64_t n);
 
+/* Replace the conductances and capacitances of an uploaded grid (same shapes as in pg_mesh;
+ * a NULL array is left unchanged).  Topology, pads, vias, sources and state are kept; the
+ * coefficients are rebuilt before the next step. */
+pg_status pg_update_mesh_values(pg_ctx* ctx, int32_t grid, const double* gE, const double* gN,
+                                const double* C);
+
+/* Voltage-drop loss of a backward-Euler transient and its gradient by the reverse-time adjoint
+ * (RC grids only, PG_ERR_UNSUPPORTED otherwise).  From the current state at step k0,
+ * pg_loss_forward advances the whole context by nsteps steps (as pg_step) and returns
+ *     J = sum_{k=1..nsteps} sum_i softplus(Vdd - v_i(t_{k0+k}) - margin)^2,
+ * keeping the state of (grid, scen) every ckpt_every steps (FP64, on the device).
+ * pg_loss_backward then solves, for k = nsteps .. 1, the adjoint of the BE recurrence of eq. 2,
+ *     M lambda_k = dJ/dv_k + (C/h) lambda_{k+1},  lambda_{nsteps+1} = 0,
+ * with the same relaxation sweeps (M is symmetric, Lemma 1) until max |residual|/M_ii <= tol_adj
+ * (in lambda's units), recomputing the forward states of each checkpoint segment, and writes
+ *     dJ/dC_i  = sum_k lambda_k,i (v_{k-1,i} - v_k,i) / h             [nl][ny][nx]
+ *     dJ/dgE_e = -sum_k (lambda_a - lambda_b)(v_a - v_b) over east segments   [nl][ny][nx-1]
+ *     dJ/dgN_e = the same over north segments                                 [nl][ny-1][nx]
+ * to host memory (pg_loss_backward) or device memory (pg_loss_backward_dev).  Pads, vias and
+ * sources are held fixed.  The context is left at step k0 + nsteps with the forward end state. */
+pg_status pg_loss_forward(pg_ctx* ctx, int32_t grid, int32_t scen, int32_t nsteps, int32_t ckpt_every,
+                          double margin, double* J);
+pg_status pg_loss_backward(pg_ctx* ctx, double tol_adj, double* dJ_dC, double* dJ_dgE, double* dJ_dgN);
+pg_status pg_loss_backward_dev(pg_ctx* ctx, double tol_adj, double* dJ_dC, double* dJ_dgE, double* dJ_dgN);
+
 pg_status pg_get_stats(const pg_ctx* ctx, pg_stats* out);
 pg_status pg_reset_stats(pg_ctx* ctx);
 

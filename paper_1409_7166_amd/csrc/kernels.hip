@@ -117,9 +117,9 @@ __device__ __forceinline__ void put(V& v, int e, T val) {
 // ------------------------------------------------------------------------------------
 // Step bookkeeping
 // ------------------------------------------------------------------------------------
-__global__ void k_step_begin(Ctl c, int I) {
+__global__ void k_step_begin(Ctl c, int I, int only_item) {
   for (int g = threadIdx.x; g < I; g += blockDim.x) {
-    c.active[g] = 1;
+    c.active[g] = (only_item < 0 || g == only_item) ? 1 : 0;
     c.step_sweeps[g] = 0;
     c.failed[g] = 0;
     c.norm_bits[g] = 0ull;
@@ -503,12 +503,129 @@ __global__ void k_inductors(const GridDesc* __restrict__ grids, const int32_t* _
 }
 
 // ------------------------------------------------------------------------------------
+// Reverse-time adjoint of the softplus voltage-drop loss over a BE transient (RC grids):
+//   J = sum_k sum_i softplus(Vdd - v_k,i - margin)^2,
+//   M lambda_k = dJ/dv_k + (C/h) lambda_{k+1}   (M is symmetric, Lemma 1),
+//   dJ/dC_i += lambda_k,i (v_k-1,i - v_k,i) / h,  dJ/dg_e -= (lambda_a - lambda_b)(v_a - v_b).
+// All three kernels walk the tiles of one item; sums are per block in a fixed order.
+// ------------------------------------------------------------------------------------
+__device__ __forceinline__ double softplus(double u) { return fmax(u, 0.0) + log1p(exp(-fabs(u))); }
+__device__ __forceinline__ double sigmoid(double u) { return 1.0 / (1.0 + exp(-u)); }
+
+// Block b writes the loss of its tile's nodes at the item's current state to part[b].
+__global__ __launch_bounds__(kThreads) void k_loss(const Tile* __restrict__ tiles, int ntiles, int TY,
+                                                  const GridDesc* __restrict__ grids, Ctl c, double margin,
+                                                  double* __restrict__ part) {
+  __shared__ double red[kThreads / 64];
+  const int ti = blockIdx.x;
+  if (ti >= ntiles) return;
+  const Tile tl = tiles[ti];
+  const GridDesc& G = grids[tl.grid];
+  const int nx = G.nx, ny = G.ny, X = G.X;
+  const int64_t P = (int64_t)X * ny;
+  const double* __restrict__ v = G.v[c.vidx[tl.item]] + (int64_t)tl.scen * G.nstore;
+  double acc = 0.0;
+  const int per_layer = kTileX * TY;
+  for (int k = threadIdx.x; k < per_layer * G.nl; k += kThreads) {
+    const int l = k / per_layer, rem = k - l * per_layer;
+    const int yy = rem / kTileX, xx = rem - yy * kTileX;
+    const int x = tl.x0 + xx, y = tl.y0 + yy;
+    if (x >= nx || y >= ny) continue;
+    const double sp = softplus(G.vdd - v[l * P + (int64_t)y * X + x] - margin);
+    acc += sp * sp;
+  }
+  for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double s = 0.0;
+    for (int w = 0; w < kThreads / 64; ++w) s += red[w];
+    part[ti] = s;
+  }
+}
+
+// total[0] += sum of part[0..n) in a fixed order (one block).
+__global__ void k_sum_into(const double* __restrict__ part, int n, double* __restrict__ total) {
+  __shared__ double red[256];
+  double s = 0.0;
+  for (int i = threadIdx.x; i < n; i += 256) s += part[i];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) total[0] += red[0];
+}
+
+// Adjoint right-hand side dJ/dv_k + (C/h) lambda_{k+1} into `rhs` (one scenario slice).
+// Adjoint right-hand side dJ/dv_k + (C/h) lambda_{k+1} into b.  Runs on the adjoint view of the
+// grid, whose current state buffer holds lambda_{k+1}.
+__global__ __launch_bounds__(kThreads) void k_adj_rhs(const Tile* __restrict__ tiles, int ntiles, int TY,
+                                                     const GridDesc* __restrict__ grids, Ctl c,
+                                                     const double* __restrict__ vk, double margin) {
+  const int ti = blockIdx.x;
+  if (ti >= ntiles) return;
+  const Tile tl = tiles[ti];
+  const GridDesc& G = grids[tl.grid];
+  const int nx = G.nx, ny = G.ny, X = G.X;
+  const int64_t P = (int64_t)X * ny;
+  const int64_t off = (int64_t)tl.scen * G.nstore;
+  const double* __restrict__ lam_next = G.v[c.vidx[tl.item]] + off;
+  double* __restrict__ rhs = G.b + off;
+  const int per_layer = kTileX * TY;
+  for (int k = threadIdx.x; k < per_layer * G.nl; k += kThreads) {
+    const int l = k / per_layer, rem = k - l * per_layer;
+    const int yy = rem / kTileX, xx = rem - yy * kTileX;
+    const int x = tl.x0 + xx, y = tl.y0 + yy;
+    if (x >= X || y >= ny) continue;
+    const int64_t i = l * P + (int64_t)y * X + x;
+    double val = 0.0;
+    if (x < nx) {
+      const double u = G.vdd - vk[i] - margin;
+      val = -2.0 * softplus(u) * sigmoid(u) + G.ch64[i] * lam_next[i];
+    }
+    rhs[i] = val;
+  }
+}
+
+// Gradient accumulation for step k (FP64); each segment gradient belongs to its lower node.
+// Gradient accumulation for step k (FP64), on the adjoint view (current state = lambda_k).
+// Each segment's gradient belongs to its lower node.
+__global__ __launch_bounds__(kThreads) void k_adj_grad(const Tile* __restrict__ tiles, int ntiles, int TY,
+                                                      const GridDesc* __restrict__ grids, Ctl c,
+                                                      const double* __restrict__ vk,
+                                                      const double* __restrict__ vprev, double inv_h,
+                                                      double* __restrict__ dC, double* __restrict__ dgE,
+                                                      double* __restrict__ dgN) {
+  const int ti = blockIdx.x;
+  if (ti >= ntiles) return;
+  const Tile tl = tiles[ti];
+  const GridDesc& G = grids[tl.grid];
+  const int nx = G.nx, ny = G.ny, X = G.X;
+  const int64_t P = (int64_t)X * ny;
+  const double* __restrict__ lam = G.v[c.vidx[tl.item]] + (int64_t)tl.scen * G.nstore;
+  const int per_layer = kTileX * TY;
+  for (int k = threadIdx.x; k < per_layer * G.nl; k += kThreads) {
+    const int l = k / per_layer, rem = k - l * per_layer;
+    const int yy = rem / kTileX, xx = rem - yy * kTileX;
+    const int x = tl.x0 + xx, y = tl.y0 + yy;
+    if (x >= nx || y >= ny) continue;
+    const int64_t i = l * P + (int64_t)y * X + x;
+    const double li = lam[i], vi = vk[i];
+    dC[i] += li * (vprev[i] - vi) * inv_h;
+    if (x + 1 < nx) dgE[i] -= (li - lam[i + 1]) * (vi - vk[i + 1]);
+    if (y + 1 < ny) dgN[i] -= (li - lam[i + X]) * (vi - vk[i + X]);
+  }
+}
+
+// ------------------------------------------------------------------------------------
 // Launch wrappers
 // ------------------------------------------------------------------------------------
 static inline unsigned xcd_blocks(int ntiles) { return 8u * (unsigned)((ntiles + 7) / 8); }
 
-hipError_t launch_step_begin(const Ctl& c, int I, hipStream_t s) {
-  hipLaunchKernelGGL(k_step_begin, dim3(1), dim3(256), 0, s, c, I);
+hipError_t launch_step_begin(const Ctl& c, int I, int only_item, hipStream_t s) {
+  hipLaunchKernelGGL(k_step_begin, dim3(1), dim3(256), 0, s, c, I, only_item);
   return hipGetLastError();
 }
 
@@ -543,6 +660,74 @@ hipError_t launch_inductors(const GridDesc* grids, const int32_t* ind_grid, cons
   if (n_total <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_inductors, dim3((n_total + 255) / 256), dim3(256), 0, s, grids, ind_grid,
                      ind_local, n_total, c);
+  return hipGetLastError();
+}
+
+// Copy the current voltages of each tile's item to / from a plain per-scenario buffer.
+__global__ __launch_bounds__(kThreads) void k_state_copy(const Tile* __restrict__ tiles, int ntiles, int TY,
+                                                        const GridDesc* __restrict__ grids, Ctl c,
+                                                        double* __restrict__ buf, int to_buf) {
+  const int ti = blockIdx.x;
+  if (ti >= ntiles) return;
+  const Tile tl = tiles[ti];
+  const GridDesc& G = grids[tl.grid];
+  const int X = G.X, ny = G.ny;
+  const int64_t P = (int64_t)X * ny;
+  double* __restrict__ v = G.v[c.vidx[tl.item]] + (int64_t)tl.scen * G.nstore;
+  const int per_layer = kTileX * TY;
+  for (int k = threadIdx.x; k < per_layer * G.nl; k += kThreads) {
+    const int l = k / per_layer, rem = k - l * per_layer;
+    const int yy = rem / kTileX, xx = rem - yy * kTileX;
+    const int x = tl.x0 + xx, y = tl.y0 + yy;
+    if (x >= X || y >= ny) continue;
+    const int64_t i = l * P + (int64_t)y * X + x;
+    if (to_buf) buf[i] = v[i]; else v[i] = buf[i];
+  }
+}
+
+// Exchange the buffer index of one item with a saved value (switching between two state views).
+__global__ void k_swap_vidx(Ctl c, int item, int32_t* saved) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    const int32_t t = c.vidx[item];
+    c.vidx[item] = saved[0];
+    saved[0] = t;
+  }
+}
+
+hipError_t launch_state_copy(const Tile* tiles, int ntiles, int tile_rows, const GridDesc* grids, const Ctl& c,
+                             double* buf, int to_buf, hipStream_t s) {
+  if (ntiles <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_state_copy, dim3(ntiles), dim3(kThreads), 0, s, tiles, ntiles, tile_rows, grids, c, buf,
+                     to_buf);
+  return hipGetLastError();
+}
+
+hipError_t launch_swap_vidx(const Ctl& c, int item, int32_t* saved, hipStream_t s) {
+  hipLaunchKernelGGL(k_swap_vidx, dim3(1), dim3(64), 0, s, c, item, saved);
+  return hipGetLastError();
+}
+
+hipError_t launch_loss(const Tile* tiles, int ntiles, int tile_rows, const GridDesc* grids, const Ctl& c,
+                       double margin, double* part, double* total, hipStream_t s) {
+  if (ntiles <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_loss, dim3(ntiles), dim3(kThreads), 0, s, tiles, ntiles, tile_rows, grids, c, margin, part);
+  hipLaunchKernelGGL(k_sum_into, dim3(1), dim3(256), 0, s, part, ntiles, total);
+  return hipGetLastError();
+}
+
+hipError_t launch_adj_rhs(const Tile* tiles, int ntiles, int tile_rows, const GridDesc* grids, const Ctl& c,
+                          const double* vk, double margin, hipStream_t s) {
+  if (ntiles <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_adj_rhs, dim3(ntiles), dim3(kThreads), 0, s, tiles, ntiles, tile_rows, grids, c, vk, margin);
+  return hipGetLastError();
+}
+
+hipError_t launch_adj_grad(const Tile* tiles, int ntiles, int tile_rows, const GridDesc* grids, const Ctl& c,
+                           const double* vk, const double* vprev, double inv_h, double* dC, double* dgE,
+                           double* dgN, hipStream_t s) {
+  if (ntiles <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_adj_grad, dim3(ntiles), dim3(kThreads), 0, s, tiles, ntiles, tile_rows, grids, c, vk, vprev,
+                     inv_h, dC, dgE, dgN);
   return hipGetLastError();
 }
 

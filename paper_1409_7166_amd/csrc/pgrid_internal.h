@@ -98,7 +98,7 @@ struct Ctl {
 };
 
 // ---- launch wrappers (kernels.hip) ----
-hipError_t launch_step_begin(const Ctl& c, int G, hipStream_t s);
+hipError_t launch_step_begin(const Ctl& c, int G, int only_item, hipStream_t s);
 hipError_t launch_rhs(const Tile* tiles, int ntiles, int tile_rows, const GridDesc* grids,
                       const Ctl& c, hipStream_t s);
 hipError_t launch_sources(const SourceTable& src, const GridDesc* grids, double t, hipStream_t s);
@@ -110,6 +110,17 @@ hipError_t launch_sweep(bool fp32, int ordering, int nl, int tile_rows, const Ti
                         int ntiles, const GridDesc* grids, const Ctl& c, int din, int zero_in,
                         double omega, hipStream_t s);
 hipError_t launch_step_end(const Ctl& c, int G, hipStream_t s);
+// adjoint of the softplus loss (tiles of one item; vk, vprev and grads are plain slices)
+hipError_t launch_loss(const Tile* tiles, int ntiles, int tile_rows, const GridDesc* grids, const Ctl& c,
+                       double margin, double* part, double* total, hipStream_t s);
+hipError_t launch_adj_rhs(const Tile* tiles, int ntiles, int tile_rows, const GridDesc* grids, const Ctl& c,
+                          const double* vk, double margin, hipStream_t s);
+hipError_t launch_adj_grad(const Tile* tiles, int ntiles, int tile_rows, const GridDesc* grids, const Ctl& c,
+                           const double* vk, const double* vprev, double inv_h, double* dC, double* dgE,
+                           double* dgN, hipStream_t s);
+hipError_t launch_state_copy(const Tile* tiles, int ntiles, int tile_rows, const GridDesc* grids, const Ctl& c,
+                             double* buf, int to_buf, hipStream_t s);
+hipError_t launch_swap_vidx(const Ctl& c, int item, int32_t* saved, hipStream_t s);
 hipError_t launch_inductors(const GridDesc* grids, const int32_t* ind_grid,
                             const int32_t* ind_local, int n_total, const Ctl& c, hipStream_t s);
 

@@ -94,6 +94,17 @@ struct pg_ctx {
   int n_src = 0, n_ind_total = 0;
   int n_src_always = 0;                          // sources at [0, n_src_always) run every step
   std::vector<double> win_t0;                    // first breakpoint of each windowed source (sorted)
+  std::vector<int> item_tile_off, item_tile_cnt; // each item's tiles in tiles_all
+  std::vector<GridDesc> desc_host;               // descriptors as uploaded (forward view)
+  // recorded forward pass of the softplus-loss adjoint
+  struct Adj {
+    bool recorded = false;
+    int grid = -1, scen = 0, item = -1, K = 0, ckpt = 1, nseg = 0;
+    double margin = 0.0;
+    int64_t k0 = 0;
+    GridDesc view{};                             // the grid's descriptor with lambda as its state
+    DBuf ckpts, vend, seg, lam0, lam1, arhs, dC, dgE, dgN, part, J, saved_vidx;
+  } adj;
   double win_maxw = 0.0;                         // widest window
   // control block
   DBuf c_norm, c_last, c_active, c_vidx, c_sweeps, c_failed, c_any, c_stats64, c_stats32, c_statsd, c_nodes;
@@ -219,6 +230,12 @@ void prof_drain(pg_ctx* c) {
     c->prof_pool.push_back(e.b);
   }
   c->prof_live.clear();
+}
+
+int n_items(const pg_ctx* c) {
+  int I = 0;
+  for (auto& H : c->grids) I += H.S;
+  return I;
 }
 
 // ---- coefficient layout ------------------------------------------------------------
@@ -360,12 +377,16 @@ pg_status prepare(pg_ctx* c) {
     for (int sc = 0; sc < H.S; ++sc) nodes.push_back((long long)H.n);
   }
   PG_TRY(upload(c, c->grid_desc, desc));
+  c->desc_host = desc;
+  c->adj.recorded = false;
   PG_TRY(upload(c, c->c_nodes, nodes));
   c->ctl.nodes = (const long long*)c->c_nodes.p;
   // tiles grouped by layer count
   const int TY = c->tile_rows;
   std::vector<Tile> tiles;
   c->tile_groups.clear();
+  c->item_tile_off.assign(n_items(c), 0);
+  c->item_tile_cnt.assign(n_items(c), 0);
   for (int nl = 1; nl <= 4; ++nl) {
     const int start = (int)tiles.size();
     int64_t nodes_nl = 0, mesh_nl = 0;
@@ -374,9 +395,12 @@ pg_status prepare(pg_ctx* c) {
       if (H.nl != nl) continue;
       nodes_nl += H.n * H.S;
       mesh_nl += H.n;
-      for (int sc = 0; sc < H.S; ++sc)
+      for (int sc = 0; sc < H.S; ++sc) {
+        c->item_tile_off[H.item0 + sc] = (int)tiles.size();
         for (int y0 = 0; y0 < H.ny; y0 += TY)
           for (int x0 = 0; x0 < H.nx; x0 += kTileX) tiles.push_back(Tile{g, H.item0 + sc, sc, x0, y0, 0});
+        c->item_tile_cnt[H.item0 + sc] = (int)tiles.size() - c->item_tile_off[H.item0 + sc];
+      }
     }
     if ((int)tiles.size() > start)
       c->tile_groups.push_back({nl, start, (int)tiles.size() - start, nodes_nl, mesh_nl});
@@ -427,12 +451,6 @@ pg_status prepare(pg_ctx* c) {
   HIP_TRY(c, hipStreamSynchronize(c->stream));
   c->dirty = false;
   return PG_OK;
-}
-
-int n_items(const pg_ctx* c) {
-  int I = 0;
-  for (auto& H : c->grids) I += H.S;
-  return I;
 }
 
 pg_status alloc_ctl(pg_ctx* c) {
@@ -517,22 +535,24 @@ pg_status launch_sweeps(pg_ctx* c, int nchk) {
   return PG_OK;
 }
 
-pg_status one_step(pg_ctx* c) {
+// Begin a step at time (step + 1) h: activate every item (only_item < 0) or one item, form the
+// right-hand side on the active tiles, subtract the sources.
+pg_status begin_step(pg_ctx* c, int only_item) {
   const int G = n_items(c);
-  const int nchk = c->opt.check_every;
-  const int L = c->opt.lookahead;
   Ctl k = c->ctl;
   const double t = (double)(c->step + 1) * c->opt.h;
   hipError_t e;
   {
     ProfScope ps(c, 3, 0);
-    e = launch_step_begin(k, G, c->stream);
+    e = launch_step_begin(k, G, only_item, c->stream);
     if (e != hipSuccess) return set_err(c, PG_ERR_DEVICE, "step launch: %s", hipGetErrorString(e));
   }
   {
+    const Tile* T = (const Tile*)c->tiles_all.p;
+    int off = 0, cnt = c->ntiles_all;
+    if (only_item >= 0) { off = c->item_tile_off[only_item]; cnt = c->item_tile_cnt[only_item]; }
     ProfScope ps(c, 2, 0);
-    e = launch_rhs((const Tile*)c->tiles_all.p, c->ntiles_all, c->tile_rows, (const GridDesc*)c->grid_desc.p,
-                   k, c->stream);
+    e = launch_rhs(T + off, cnt, c->tile_rows, (const GridDesc*)c->grid_desc.p, k, c->stream);
     if (e != hipSuccess) return set_err(c, PG_ERR_DEVICE, "rhs launch: %s", hipGetErrorString(e));
   }
   {
@@ -546,6 +566,15 @@ pg_status one_step(pg_ctx* c) {
     e = launch_sources(st, (const GridDesc*)c->grid_desc.p, t, c->stream);
     if (e != hipSuccess) return set_err(c, PG_ERR_DEVICE, "source launch: %s", hipGetErrorString(e));
   }
+  return PG_OK;
+}
+
+// Algorithm 1's inner loop for every active item: FP64 residual, then refinement cycles of
+// check_every sweeps + residual until each item's scaled residual is <= tol.
+pg_status solve_active(pg_ctx* c, double tol) {
+  const int G = n_items(c);
+  const int nchk = c->opt.check_every;
+  const int L = c->opt.lookahead;
   PG_TRY(launch_resid_all(c, 0, 0));
   // decision after the initial residual goes to flag slot 0
   const int nslots = (int)c->flag_events.size();
@@ -554,7 +583,7 @@ pg_status one_step(pg_ctx* c) {
     Ctl kk = c->ctl;
     kk.any_active = c->dev_flags + slot;
     ProfScope ps(c, 3, 0);
-    hipError_t ee = launch_decide(kk, G, c->opt.tol, has_d, nchk, c->opt.max_sweeps, c->stream);
+    hipError_t ee = launch_decide(kk, G, tol, has_d, nchk, c->opt.max_sweeps, c->stream);
     if (ee != hipSuccess) return set_err(c, PG_ERR_DEVICE, "decide launch: %s", hipGetErrorString(ee));
     HIP_TRY(c, hipEventRecord(c->flag_events[slot], c->stream));
     return PG_OK;
@@ -571,7 +600,7 @@ pg_status one_step(pg_ctx* c) {
   // Refinement cycle j (j >= 1) is nchk sweeps, a residual and a decision.  Queue as many
   // cycles as the previous step needed before waiting; past that prediction keep `lookahead`
   // cycles queued beyond the one whose decision the host waits for.  Cycles queued after
-  // convergence find every grid inactive and exit at once.
+  // convergence find every item inactive and exit at once.
   while (true) {
     const int want = consumed <= c->pred_chunks ? c->pred_chunks : consumed + L;
     while (issued < max_chunks && issued < want) {
@@ -597,9 +626,16 @@ pg_status one_step(pg_ctx* c) {
   c->cur_chunk = 0;
   for (size_t q = prof_base; q < c->prof_live.size(); ++q)
     if (c->prof_live[q].chunk > last) c->prof_live[q].kind = -1;
+  return PG_OK;
+}
+
+// Close a step: statistics and the inductor branch currents.
+pg_status end_step(pg_ctx* c) {
+  Ctl k = c->ctl;
+  hipError_t e;
   {
     ProfScope ps(c, 3, 0);
-    e = launch_step_end(k, G, c->stream);
+    e = launch_step_end(k, n_items(c), c->stream);
     if (e != hipSuccess) return set_err(c, PG_ERR_DEVICE, "step-end launch: %s", hipGetErrorString(e));
   }
   if (c->n_ind_total) {
@@ -608,7 +644,110 @@ pg_status one_step(pg_ctx* c) {
                          (const int32_t*)c->ind_local.p, c->n_ind_total, k, c->stream);
     if (e != hipSuccess) return set_err(c, PG_ERR_DEVICE, "inductor launch: %s", hipGetErrorString(e));
   }
+  return PG_OK;
+}
+
+pg_status one_step(pg_ctx* c) {
+  PG_TRY(begin_step(c, -1));
+  PG_TRY(solve_active(c, c->opt.tol));
+  PG_TRY(end_step(c));
   c->step++;
+  return PG_OK;
+}
+
+// ---- adjoint helpers ----------------------------------------------------------------
+pg_status state_copy(pg_ctx* c, int item, double* buf, int to_buf) {
+  const Tile* T = (const Tile*)c->tiles_all.p + c->item_tile_off[item];
+  hipError_t e = launch_state_copy(T, c->item_tile_cnt[item], c->tile_rows, (const GridDesc*)c->grid_desc.p,
+                                   c->ctl, buf, to_buf, c->stream);
+  if (e != hipSuccess) return set_err(c, PG_ERR_DEVICE, "state copy: %s", hipGetErrorString(e));
+  return PG_OK;
+}
+
+// Switch grid adj.grid between its forward view (state = voltages) and its adjoint view
+// (state = lambda, right-hand side = adjoint right-hand side); the item's buffer index is
+// exchanged with the one saved for the other view.
+pg_status use_view(pg_ctx* c, bool adjoint) {
+  auto& A = c->adj;
+  const GridDesc* src = adjoint ? &A.view : &c->desc_host[A.grid];
+  HIP_TRY(c, hipMemcpyAsync((GridDesc*)c->grid_desc.p + A.grid, src, sizeof(GridDesc), hipMemcpyHostToDevice,
+                            c->stream));
+  hipError_t e = launch_swap_vidx(c->ctl, A.item, (int32_t*)A.saved_vidx.p, c->stream);
+  if (e != hipSuccess) return set_err(c, PG_ERR_DEVICE, "view switch: %s", hipGetErrorString(e));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  return PG_OK;
+}
+
+// Copy an item-slice array in storage layout to the caller's [nl][rows][cols] layout.
+pg_status unpad(pg_ctx* c, const GridHost& H, const double* src, double* dst, int cols, int rows, bool to_device) {
+  const hipMemcpyKind kind = to_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+  for (int l = 0; l < H.nl; ++l)
+    HIP_TRY(c, hipMemcpy2DAsync(dst + (size_t)l * rows * cols, cols * sizeof(double),
+                                src + (size_t)l * H.ny * H.X, H.X * sizeof(double), cols * sizeof(double), rows,
+                                kind, c->stream));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  return PG_OK;
+}
+
+pg_status loss_backward(pg_ctx* c, double tol_adj, double* dC, double* dgE, double* dgN, bool on_device) {
+  if (!c) return PG_ERR_INVALID_ARG;
+  auto& A = c->adj;
+  if (!A.recorded) return set_err(c, PG_ERR_STATE, "pg_loss_backward needs a recorded pg_loss_forward");
+  if (!(std::isfinite(tol_adj) && tol_adj > 0)) return set_err(c, PG_ERR_INVALID_ARG, "tol_adj must be > 0");
+  if (!dC || !dgE || !dgN) return set_err(c, PG_ERR_INVALID_ARG, "gradient outputs are NULL");
+  HIP_TRY(c, hipSetDevice(c->device));
+  GridHost& H = c->grids[A.grid];
+  const size_t ns = (size_t)H.nstore;
+  HIP_TRY(c, hipMemsetAsync(A.lam0.p, 0, A.lam0.bytes, c->stream));
+  HIP_TRY(c, hipMemsetAsync(A.lam1.p, 0, A.lam1.bytes, c->stream));
+  HIP_TRY(c, hipMemsetAsync(A.dC.p, 0, A.dC.bytes, c->stream));
+  HIP_TRY(c, hipMemsetAsync(A.dgE.p, 0, A.dgE.bytes, c->stream));
+  HIP_TRY(c, hipMemsetAsync(A.dgN.p, 0, A.dgN.bytes, c->stream));
+  HIP_TRY(c, hipMemsetAsync(A.saved_vidx.p, 0, sizeof(int32_t), c->stream));
+  double* ck = (double*)A.ckpts.p;
+  double* seg = (double*)A.seg.p;
+  const Tile* T = (const Tile*)c->tiles_all.p + c->item_tile_off[A.item];
+  const int nt = c->item_tile_cnt[A.item];
+  const GridDesc* gd = (const GridDesc*)c->grid_desc.p;
+  for (int j = A.nseg - 1; j >= 0; --j) {
+    const int kb = j * A.ckpt, ke = std::min(A.K, kb + A.ckpt), len = ke - kb;
+    // recompute the forward states of the segment from its checkpoint (only this item steps)
+    PG_TRY(state_copy(c, A.item, ck + (size_t)j * ns, 0));
+    HIP_TRY(c, hipMemcpyAsync(seg, ck + (size_t)j * ns, ns * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+    c->step = A.k0 + kb;
+    for (int q = 1; q <= len; ++q) {
+      PG_TRY(begin_step(c, A.item));
+      PG_TRY(solve_active(c, c->opt.tol));
+      c->step++;
+      PG_TRY(state_copy(c, A.item, seg + (size_t)q * ns, 1));
+    }
+    // reverse sweep over the segment on the adjoint view
+    PG_TRY(use_view(c, true));
+    for (int q = len; q >= 1; --q) {
+      hipError_t e = launch_adj_rhs(T, nt, c->tile_rows, gd, c->ctl, seg + (size_t)q * ns, A.margin, c->stream);
+      if (e != hipSuccess) return set_err(c, PG_ERR_DEVICE, "adjoint rhs: %s", hipGetErrorString(e));
+      e = launch_step_begin(c->ctl, n_items(c), A.item, c->stream);
+      if (e != hipSuccess) return set_err(c, PG_ERR_DEVICE, "adjoint step: %s", hipGetErrorString(e));
+      PG_TRY(solve_active(c, tol_adj));
+      e = launch_adj_grad(T, nt, c->tile_rows, gd, c->ctl, seg + (size_t)q * ns, seg + (size_t)(q - 1) * ns,
+                          1.0 / c->opt.h, (double*)A.dC.p, (double*)A.dgE.p, (double*)A.dgN.p, c->stream);
+      if (e != hipSuccess) return set_err(c, PG_ERR_DEVICE, "adjoint gradient: %s", hipGetErrorString(e));
+    }
+    PG_TRY(use_view(c, false));
+  }
+  // back to the state the forward pass ended in
+  PG_TRY(state_copy(c, A.item, (double*)A.vend.p, 0));
+  c->step = A.k0 + A.K;
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  int32_t failed = 0;
+  HIP_TRY(c, hipMemcpy(&failed, c->ctl.stat_failed, sizeof failed, hipMemcpyDeviceToHost));
+  PG_TRY(unpad(c, H, (const double*)A.dC.p, dC, H.nx, H.ny, on_device));
+  PG_TRY(unpad(c, H, (const double*)A.dgE.p, dgE, H.nx - 1, H.ny, on_device));
+  PG_TRY(unpad(c, H, (const double*)A.dgN.p, dgN, H.nx, H.ny - 1, on_device));
+  if (failed) {
+    HIP_TRY(c, hipMemset(c->ctl.stat_failed, 0, sizeof(int32_t)));
+    return set_err(c, PG_ERR_NO_CONVERGENCE, "an adjoint or recomputed step reached max_sweeps");
+  }
   return PG_OK;
 }
 
@@ -690,6 +829,9 @@ void pg_destroy(pg_ctx* c) {
                   &c->ind_grid, &c->ind_local, &c->c_norm, &c->c_last, &c->c_active, &c->c_vidx, &c->c_sweeps,
                   &c->c_failed, &c->c_any, &c->c_stats64, &c->c_stats32, &c->c_statsd, &c->c_nodes};
   for (DBuf* b : bufs) dfree(*b);
+  DBuf* abufs[] = {&c->adj.ckpts, &c->adj.vend, &c->adj.seg, &c->adj.lam0, &c->adj.lam1, &c->adj.arhs,
+                   &c->adj.dC, &c->adj.dgE, &c->adj.dgN, &c->adj.part, &c->adj.J, &c->adj.saved_vidx};
+  for (DBuf* b : abufs) dfree(*b);
   for (auto e : c->flag_events) (void)hipEventDestroy(e);
   for (auto& e : c->prof_live) { (void)hipEventDestroy(e.a); (void)hipEventDestroy(e.b); }
   for (auto e : c->prof_pool) (void)hipEventDestroy(e);
@@ -966,6 +1108,91 @@ pg_status pg_read_kernel_times(pg_ctx* c, pg_kernel_times* out) {
   prof_drain(c);
   *out = c->prof_acc;
   std::memset(&c->prof_acc, 0, sizeof c->prof_acc);
+  return PG_OK;
+}
+
+pg_status pg_loss_forward(pg_ctx* c, int32_t grid, int32_t scen, int32_t nsteps, int32_t ckpt_every,
+                          double margin, double* J) {
+  PG_TRY(check_gs(c, grid, scen));
+  if (nsteps < 1 || ckpt_every < 1 || !std::isfinite(margin))
+    return set_err(c, PG_ERR_INVALID_ARG, "need nsteps >= 1, ckpt_every >= 1 and a finite margin");
+  HIP_TRY(c, hipSetDevice(c->device));
+  PG_TRY(prepare(c));
+  GridHost& H = c->grids[grid];
+  if (!H.ind_a.empty())
+    return set_err(c, PG_ERR_UNSUPPORTED, "the loss adjoint covers RC grids (no inductive branches)");
+  auto& A = c->adj;
+  A.recorded = false;
+  A.grid = grid; A.scen = scen; A.item = H.item0 + scen; A.K = nsteps; A.ckpt = std::min(ckpt_every, nsteps);
+  A.nseg = (nsteps + A.ckpt - 1) / A.ckpt; A.margin = margin; A.k0 = c->step;
+  const size_t ns = (size_t)H.nstore, nfull = ns * H.S;
+  PG_TRY(dalloc(c, A.ckpts, (size_t)A.nseg * ns * sizeof(double)));
+  PG_TRY(dalloc(c, A.vend, ns * sizeof(double)));
+  PG_TRY(dalloc(c, A.seg, (size_t)(A.ckpt + 1) * ns * sizeof(double)));
+  PG_TRY(dalloc(c, A.lam0, nfull * sizeof(double)));
+  PG_TRY(dalloc(c, A.lam1, nfull * sizeof(double)));
+  PG_TRY(dalloc(c, A.arhs, nfull * sizeof(double)));
+  PG_TRY(dalloc(c, A.dC, ns * sizeof(double)));
+  PG_TRY(dalloc(c, A.dgE, ns * sizeof(double)));
+  PG_TRY(dalloc(c, A.dgN, ns * sizeof(double)));
+  PG_TRY(dalloc(c, A.part, (size_t)std::max(1, c->item_tile_cnt[A.item]) * sizeof(double)));
+  PG_TRY(dalloc(c, A.J, sizeof(double)));
+  PG_TRY(dalloc(c, A.saved_vidx, sizeof(int32_t)));
+  A.view = c->desc_host[grid];
+  A.view.v[0] = (double*)A.lam0.p;
+  A.view.v[1] = (double*)A.lam1.p;
+  A.view.b = (double*)A.arhs.p;
+  A.view.n_ind = 0;
+  HIP_TRY(c, hipMemsetAsync(A.J.p, 0, sizeof(double), c->stream));
+  const Tile* T = (const Tile*)c->tiles_all.p + c->item_tile_off[A.item];
+  const int nt = c->item_tile_cnt[A.item];
+  double* ck = (double*)A.ckpts.p;
+  PG_TRY(state_copy(c, A.item, ck, 1));
+  const auto t0 = std::chrono::steady_clock::now();
+  for (int k = 1; k <= nsteps; ++k) {
+    PG_TRY(one_step(c));
+    hipError_t e = launch_loss(T, nt, c->tile_rows, (const GridDesc*)c->grid_desc.p, c->ctl, margin,
+                               (double*)A.part.p, (double*)A.J.p, c->stream);
+    if (e != hipSuccess) return set_err(c, PG_ERR_DEVICE, "loss launch: %s", hipGetErrorString(e));
+    if (k % A.ckpt == 0 && k / A.ckpt < A.nseg) PG_TRY(state_copy(c, A.item, ck + (size_t)(k / A.ckpt) * ns, 1));
+  }
+  PG_TRY(state_copy(c, A.item, (double*)A.vend.p, 1));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  c->seconds += std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  if (J) HIP_TRY(c, hipMemcpy(J, A.J.p, sizeof(double), hipMemcpyDeviceToHost));
+  int32_t failed = 0;
+  HIP_TRY(c, hipMemcpy(&failed, c->ctl.stat_failed, sizeof failed, hipMemcpyDeviceToHost));
+  if (failed) {
+    HIP_TRY(c, hipMemset(c->ctl.stat_failed, 0, sizeof(int32_t)));
+    return set_err(c, PG_ERR_NO_CONVERGENCE, "a forward step reached max_sweeps");
+  }
+  A.recorded = true;
+  return PG_OK;
+}
+
+pg_status pg_loss_backward(pg_ctx* c, double tol_adj, double* dJ_dC, double* dJ_dgE, double* dJ_dgN) {
+  return loss_backward(c, tol_adj, dJ_dC, dJ_dgE, dJ_dgN, false);
+}
+
+pg_status pg_loss_backward_dev(pg_ctx* c, double tol_adj, double* dJ_dC, double* dJ_dgE, double* dJ_dgN) {
+  return loss_backward(c, tol_adj, dJ_dC, dJ_dgE, dJ_dgN, true);
+}
+
+pg_status pg_update_mesh_values(pg_ctx* c, int32_t grid, const double* gE, const double* gN, const double* C) {
+  PG_TRY(check_gs(c, grid, 0));
+  GridHost& H = c->grids[grid];
+  const size_t nE = (size_t)H.nl * H.ny * (H.nx - 1), nN = (size_t)H.nl * (H.ny - 1) * H.nx, nC = (size_t)H.n;
+  for (size_t k = 0; gE && k < nE; ++k)
+    if (!(std::isfinite(gE[k]) && gE[k] >= 0)) return set_err(c, PG_ERR_INVALID_ARG, "gE[%zu] invalid", k);
+  for (size_t k = 0; gN && k < nN; ++k)
+    if (!(std::isfinite(gN[k]) && gN[k] >= 0)) return set_err(c, PG_ERR_INVALID_ARG, "gN[%zu] invalid", k);
+  for (size_t k = 0; C && k < nC; ++k)
+    if (!(std::isfinite(C[k]) && C[k] >= 0)) return set_err(c, PG_ERR_INVALID_ARG, "C[%zu] invalid", k);
+  if (gE) H.gE.assign(gE, gE + nE);
+  if (gN) H.gN.assign(gN, gN + nN);
+  if (C) H.C.assign(C, C + nC);
+  c->dirty = true;
+  c->adj.recorded = false;
   return PG_OK;
 }
 

@@ -99,6 +99,13 @@ EXPORTS = {
     "pg_read_voltages": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.POINTER(C.c_double), C.c_int64]),
     "pg_read_voltages_dev": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_void_p, C.c_int64]),
     "pg_read_inductor_currents": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.POINTER(C.c_double), C.c_int64]),
+    "pg_update_mesh_values": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_double),
+                                        C.POINTER(C.c_double)]),
+    "pg_loss_forward": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_double,
+                                  C.POINTER(C.c_double)]),
+    "pg_loss_backward": (C.c_int, [C.c_void_p, C.c_double, C.POINTER(C.c_double), C.POINTER(C.c_double),
+                                   C.POINTER(C.c_double)]),
+    "pg_loss_backward_dev": (C.c_int, [C.c_void_p, C.c_double, C.c_void_p, C.c_void_p, C.c_void_p]),
     "pg_get_stats": (C.c_int, [C.c_void_p, C.POINTER(Stats)]),
     "pg_reset_stats": (C.c_int, [C.c_void_p]),
     "pg_profile": (C.c_int, [C.c_void_p, C.c_int32]),
@@ -312,6 +319,30 @@ class Context:
         out = np.zeros(max(nb, 1))
         self._check(lib().pg_read_inductor_currents(self._h, grid, scen, _dp(out), nb))
         return out[:nb]
+
+    # -- softplus voltage-drop loss and its adjoint ---------------------------------------------
+    def update_mesh_values(self, grid: int, gE=None, gN=None, C=None):
+        gE, gN, C = _f64(gE), _f64(gN), _f64(C)
+        self._check(lib().pg_update_mesh_values(self._h, grid, _dp(gE), _dp(gN), _dp(C)))
+
+    def loss_forward(self, grid: int, scen: int, nsteps: int, ckpt_every: int, margin: float) -> float:
+        J = C.c_double()
+        self._check(lib().pg_loss_forward(self._h, grid, scen, int(nsteps), int(ckpt_every), float(margin),
+                                          C.byref(J)))
+        return J.value
+
+    def loss_backward(self, tol_adj: float, grid: int = 0):
+        """Host arrays dJ/dC [nl,ny,nx], dJ/dgE [nl,ny,nx-1], dJ/dgN [nl,ny-1,nx]."""
+        m = self.meshes[grid]
+        nl, ny, nx = int(m.nl), int(m.ny), int(m.nx)
+        dC, dE, dN = np.empty((nl, ny, nx)), np.empty((nl, ny, nx - 1)), np.empty((nl, ny - 1, nx))
+        self._check(lib().pg_loss_backward(self._h, float(tol_adj), _dp(dC), _dp(dE), _dp(dN)))
+        return dC, dE, dN
+
+    def loss_backward_dev(self, tol_adj: float, dC, dE, dN):
+        """Gradients into float64 device tensors (contiguous, shapes as in loss_backward)."""
+        self._check(lib().pg_loss_backward_dev(self._h, float(tol_adj), C.c_void_p(dC.data_ptr()),
+                                               C.c_void_p(dE.data_ptr()), C.c_void_p(dN.data_ptr())))
 
     def stats(self) -> dict:
         s = Stats()

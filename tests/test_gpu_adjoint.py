@@ -1,0 +1,98 @@
+"""GPU reverse-time adjoint of the softplus voltage-drop loss against the oracle adjoint and
+against finite differences (gradient bar: 1e-4 relative per entry, floor 1e-3 * max|g|)."""
+import numpy as np
+import pytest
+
+import paper_1409_7166_amd as pg
+from helpers import compressed, gpu_context, say, torch_stream
+from oracle.adjoint import adjoint_gradients
+from workloads import Pulses, config4, small_multilayer
+
+pytestmark = pytest.mark.gpu
+
+REL = 1e-4
+
+
+def _close(g, ref, rel=REL):
+    floor = 1e-3 * np.max(np.abs(ref))
+    err = np.abs(g - ref) / np.maximum(np.abs(ref), floor)
+    return float(err.max())
+
+
+def _case(side_x=40, side_y=36, steps=30):
+    w = small_multilayer(side=side_x, seed=61, nl=1, pad_every=8, fraction=0.5, steps=steps,
+                         c_range=(0.1e-12, 5e-12))
+    p = compressed(w.pulses[0][0], start=0.4, width=1.0, peak=20.0)
+    w.pulses[0][0] = p
+    return w, w.meshes[0], p
+
+
+@pytest.mark.parametrize("prec", [pg.PG_PREC_FP64, pg.PG_PREC_FP32_REFINE])
+def test_adjoint_matches_oracle_adjoint(prec):
+    w, mesh, p = _case()
+    K, ck, margin = 30, 7, 0.05
+    say(f"[gpu] adjoint 40x40 prec={prec}")
+    with gpu_context(w, precision=prec, tol=1e-12, omega=1.5, max_sweeps=50000) as ctx:
+        J = ctx.loss_forward(0, 0, K, ck, margin)
+        dC, dE, dN = ctx.loss_backward(1e-10)
+        assert ctx.time_index() == K
+    Jr, rC, rE, rN = adjoint_gradients(mesh, p, w.h, K, margin)
+    errs = (_close(dC, rC), _close(dE, rE), _close(dN, rN))
+    say(f"  J={J:.10e} ref={Jr:.10e} grad rel err C/gE/gN = {errs}")
+    assert abs(J - Jr) <= 1e-9 * abs(Jr)
+    assert max(errs) <= REL
+
+
+def test_autograd_function_and_directional_difference():
+    import torch
+    from paper_1409_7166_amd.autograd import softplus_drop_loss
+    w, mesh, p = _case(32, 28, 24)
+    K, ck, margin = 24, 10, 0.05
+    torch_stream()
+    ctx = gpu_context(w, precision=pg.PG_PREC_FP64, tol=1e-13, omega=1.5, max_sweeps=100000)
+    dev = torch.device("cuda", 0)
+    Ct = torch.tensor(mesh.C, dtype=torch.float64, device=dev, requires_grad=True)
+    Et = torch.tensor(mesh.gE, dtype=torch.float64, device=dev, requires_grad=True)
+    Nt = torch.tensor(mesh.gN, dtype=torch.float64, device=dev, requires_grad=True)
+    J = softplus_drop_loss(Ct, Et, Nt, ctx, 0, K, ck, margin, 1e-11)
+    J.backward()
+    gC, gE, gN = (t.grad.cpu().numpy() for t in (Ct, Et, Nt))
+    Jr, rC, rE, rN = adjoint_gradients(mesh, p, w.h, K, margin)
+    errs = (_close(gC, rC), _close(gE, rE), _close(gN, rN))
+    say(f"[gpu] autograd J={J.item():.10e} ref={Jr:.10e} rel errs {errs}")
+    assert max(errs) <= REL
+    # central difference of the GPU's own forward along a random direction
+    rng = np.random.default_rng(3)
+    d = [rng.choice([-1.0, 1.0], size=a.shape) * a for a in (mesh.C, mesh.gE, mesh.gN)]
+    delta = 1e-5
+
+    def J_at(s):
+        with torch.no_grad():
+            Jv = softplus_drop_loss(torch.tensor(mesh.C + s * d[0], device=dev),
+                                    torch.tensor(mesh.gE + s * d[1], device=dev),
+                                    torch.tensor(mesh.gN + s * d[2], device=dev), ctx, 0, K, ck, margin, 1e-11)
+        return Jv.item()
+
+    fd = (J_at(delta) - J_at(-delta)) / (2 * delta)
+    an = float(np.sum(gC * d[0]) + np.sum(gE * d[1]) + np.sum(gN * d[2]))
+    say(f"  directional FD={fd:.8e} adjoint={an:.8e} rel={abs(fd - an) / abs(an):.2e}")
+    assert abs(fd - an) <= REL * abs(an)
+    ctx.close()
+
+
+def test_full_size_adjoint_first_40_steps():
+    """The 1024x1024 adjoint workload (FP64 gradients, checkpoints every 20 steps) over its first
+    40 steps, every gradient entry against the oracle adjoint."""
+    w = config4(steps=40)
+    mesh, p = w.meshes[0], w.pulses[0][0]
+    K, ck, margin = 40, 20, 0.05
+    say("[gpu] adjoint 1024x1024, 40 steps")
+    with gpu_context(w, precision=pg.PG_PREC_FP32_REFINE, tol=1e-11, omega=1.5, max_sweeps=100000) as ctx:
+        J = ctx.loss_forward(0, 0, K, ck, margin)
+        dC, dE, dN = ctx.loss_backward(1e-9)
+    say("  oracle adjoint ...")
+    Jr, rC, rE, rN = adjoint_gradients(mesh, p, w.h, K, margin)
+    errs = (_close(dC, rC), _close(dE, rE), _close(dN, rN))
+    say(f"  J={J:.10e} ref={Jr:.10e} rel errs {errs}")
+    assert abs(J - Jr) <= 1e-9 * abs(Jr)
+    assert max(errs) <= REL
