@@ -38,6 +38,8 @@ def parse():
     ap.add_argument("--check-every", type=int, default=None)
     ap.add_argument("--tile-rows", type=int, default=0)
     ap.add_argument("--lookahead", type=int, default=1)
+    ap.add_argument("--graphs", type=int, default=1, help="replay each step from captured HIP graphs (1) or "
+                                                          "launch kernels one by one (0)")
     ap.add_argument("--profile-every", type=int, default=1,
                     help="time every n-th block of back-to-back sweep launches with HIP events during "
                          "the timed region (0: off)")
@@ -84,7 +86,7 @@ def make_workload(name):
     return getattr(workloads, name)()
 
 
-def run_gpu(w, steps, warmup, precision, tol, omega, check_every, tile_rows, lookahead, profile_every):
+def run_gpu(w, steps, warmup, precision, tol, omega, check_every, tile_rows, lookahead, profile_every, graphs):
     import torch
     import paper_1409_7166_amd as pg
 
@@ -93,7 +95,7 @@ def run_gpu(w, steps, warmup, precision, tol, omega, check_every, tile_rows, loo
     ctx = pg.Context(0, stream)
     ctx.set_options(h=w.h, tol=tol, omega=omega, check_every=check_every, max_sweeps=100000,
                     precision=pg.PG_PREC_FP32_REFINE if precision == "fp32+ref" else pg.PG_PREC_FP64,
-                    tile_rows=tile_rows, lookahead=lookahead)
+                    tile_rows=tile_rows, lookahead=lookahead, graphs=graphs)
     for g, (mesh, scen) in enumerate(zip(w.meshes, w.pulses)):
         ctx.upload_mesh(mesh, len(scen))
         for s, p in enumerate(scen):
@@ -181,7 +183,7 @@ def main():
     omega = args.omega or tuned["omega"]
     chk = args.check_every or tuned["check_every"]
     elapsed, st, kt = run_gpu(w, args.steps, args.warmup, prec, args.tol, omega, chk, args.tile_rows,
-                              args.lookahead, args.profile_every)
+                              args.lookahead, args.profile_every, args.graphs)
     nodes = sum(m.n * len(p) for m, p in zip(w.meshes, w.pulses))
     value = st["node_updates"] / elapsed
     roof = None
@@ -201,7 +203,7 @@ def main():
         "ms_per_step": elapsed * 1e3 / args.steps, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f32" if prec == "fp32+ref" else "f64", "data": "synthetic",
         "config": {"workload": w.name, "nodes": nodes, "h_s": w.h, "tol_V": args.tol,
-                   "precision": prec, "omega": omega, "check_every": chk,
+                   "precision": prec, "omega": omega, "check_every": chk, "graphs": args.graphs,
                    "sweeps_per_step": st["sweeps"] / max(1, st["steps"]),
                    "max_step_sweeps": st["max_step_sweeps"], "max_final_residual_V": st["max_final_residual"],
                    "node_steps_per_s": nodes * args.steps / elapsed},

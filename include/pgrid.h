@@ -73,7 +73,8 @@ typedef struct pg_options {
   int32_t ordering;     /* pg_ordering */
   int32_t tile_rows;    /* rows per 128-node-wide sweep tile: 4, 8 or 16 (0 = library default, 8) */
   int32_t lookahead;    /* refinement cycles queued ahead of the host's convergence check, 0..4 */
-  int32_t reserved[6];  /* must be zero */
+  int32_t graphs;       /* 1: replay each step's launches from captured HIP graphs; 0: launch one by one */
+  int32_t reserved[5];  /* must be zero */
 } pg_options;
 
 /* A layered RC/RLC mesh (the representative node of Fig. 2 repeated on a grid).
@@ -127,7 +128,7 @@ int32_t pg_abi_version(void);
 const char* pg_status_name(int32_t status);
 
 /* Fill *out with the defaults: h = 10 ps, tol = 1e-6 V, omega = 1, max_sweeps = 10000,
- * check_every = 8, FP64, red-black, tile_rows = 8, lookahead = 1. */
+ * check_every = 8, FP64, red-black, tile_rows = 8, lookahead = 1, graphs = 0. */
 pg_status pg_default_options(pg_options* out);
 
 /* Host-only checks (no device needed).  msg (may be NULL) receives a description of the

@@ -117,16 +117,34 @@ __device__ __forceinline__ void put(V& v, int e, T val) {
 // ------------------------------------------------------------------------------------
 // Step bookkeeping
 // ------------------------------------------------------------------------------------
-__global__ void k_step_begin(Ctl c, int I, int only_item) {
+__global__ void k_step_begin(Ctl c, int I, int only_item, double h, SourceTable src) {
   for (int g = threadIdx.x; g < I; g += blockDim.x) {
     c.active[g] = (only_item < 0 || g == only_item) ? 1 : 0;
     c.step_sweeps[g] = 0;
     c.failed[g] = 0;
     c.norm_bits[g] = 0ull;
   }
+  if (threadIdx.x == 0) {
+    const double t = (double)(c.step[0] + 1) * h;
+    c.t_now[0] = t;
+    // windowed sources whose first breakpoint lies in [t - widest window, t]
+    int lo = 0, hi = src.n_window;
+    while (lo < hi) {  // first t0 >= t - maxw
+      const int mid = (lo + hi) >> 1;
+      if (src.win_t0[mid] < t - src.win_maxw) lo = mid + 1; else hi = mid;
+    }
+    int a = lo;
+    hi = src.n_window;
+    while (lo < hi) {  // first t0 > t
+      const int mid = (lo + hi) >> 1;
+      if (src.win_t0[mid] <= t) lo = mid + 1; else hi = mid;
+    }
+    c.src_window[0] = src.n_always + a;
+    c.src_window[1] = lo - a;
+  }
 }
 
-__global__ void k_decide(Ctl c, int I, double tol, int has_d, int nchk, int max_sweeps) {
+__global__ void k_decide(Ctl c, int I, double tol, int has_d, int nchk, int max_sweeps, int nslots) {
   __shared__ int any;
   __shared__ int worked;
   if (threadIdx.x == 0) { any = 0; worked = 0; }
@@ -151,12 +169,14 @@ __global__ void k_decide(Ctl c, int I, double tol, int has_d, int nchk, int max_
   }
   __syncthreads();
   if (threadIdx.x == 0) {
-    c.any_active[0] = any;
+    const int seq = c.flag_seq[0];
+    c.flag_seq[0] = seq + 1;
+    c.any_active[seq % nslots] = any;
     if (worked) c.stat_checks[0] += 1;
   }
 }
 
-__global__ void k_step_end(Ctl c, int I) {
+__global__ void k_step_end(Ctl c, int I, int count_step) {
   if (threadIdx.x != 0) return;
   long long sw = 0, upd = 0;
   int mx = 0, fail = 0;
@@ -169,13 +189,15 @@ __global__ void k_step_end(Ctl c, int I) {
     res = nan_max(res, c.last_norm[g]);
     fail |= c.failed[g];
   }
+  c.stat_failed[0] |= fail;
+  if (!count_step) return;
   c.stat_sweeps[0] += sw;
   c.stat_updates[0] += upd;
   c.stat_last_sweeps[0] = mx;
   if (mx > c.stat_max_sweeps[0]) c.stat_max_sweeps[0] = mx;
   c.stat_last_res[0] = res;
   c.stat_max_res[0] = nan_max(c.stat_max_res[0], res);
-  c.stat_failed[0] |= fail;
+  c.step[0] += 1;
 }
 
 // ------------------------------------------------------------------------------------
@@ -215,29 +237,33 @@ __global__ __launch_bounds__(kThreads) void k_rhs(const Tile* __restrict__ tiles
   }
 }
 
-// Piecewise-linear current sources at time t, subtracted from b (one thread per source).
-__global__ void k_sources(SourceTable src, const GridDesc* __restrict__ grids, double t) {
-  const int q = blockIdx.x * blockDim.x + threadIdx.x;
-  if (q >= src.n_always + src.win_count) return;
-  const int k = q < src.n_always ? q : src.win_begin + (q - src.n_always);
-  const int a = src.off[k], e = src.off[k + 1];
+// Piecewise-linear current sources at the step's time, subtracted from b.  Grid-stride over the
+// always-on sources and the window chosen by k_step_begin.
+__global__ void k_sources(SourceTable src, const GridDesc* __restrict__ grids, Ctl c) {
+  const double t = c.t_now[0];
+  const int wbeg = c.src_window[0], wcnt = c.src_window[1];
+  const int n = src.n_always + wcnt;
   const double* __restrict__ ts = src.t;
   const double* __restrict__ is = src.i;
-  double I;
-  if (t <= ts[a]) {
-    I = is[a];
-  } else if (t >= ts[e - 1]) {
-    I = is[e - 1];
-  } else {
-    int lo = a, hi = e - 1;  // ts[lo] < t < ts[hi]
-    while (hi - lo > 1) {
-      const int mid = (lo + hi) >> 1;
-      if (ts[mid] <= t) lo = mid; else hi = mid;
+  for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < n; q += gridDim.x * blockDim.x) {
+    const int k = q < src.n_always ? q : wbeg + (q - src.n_always);
+    const int a = src.off[k], e = src.off[k + 1];
+    double I;
+    if (t <= ts[a]) {
+      I = is[a];
+    } else if (t >= ts[e - 1]) {
+      I = is[e - 1];
+    } else {
+      int lo = a, hi = e - 1;  // ts[lo] < t < ts[hi]
+      while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (ts[mid] <= t) lo = mid; else hi = mid;
+      }
+      I = is[lo] + (is[hi] - is[lo]) * ((t - ts[lo]) / (ts[hi] - ts[lo]));
     }
-    I = is[lo] + (is[hi] - is[lo]) * ((t - ts[lo]) / (ts[hi] - ts[lo]));
+    const GridDesc& G = grids[src.grid[k]];
+    G.b[src.index[k]] -= I;
   }
-  const GridDesc& G = grids[src.grid[k]];
-  G.b[src.index[k]] -= I;
 }
 
 // ------------------------------------------------------------------------------------
@@ -624,19 +650,20 @@ __global__ __launch_bounds__(kThreads) void k_adj_grad(const Tile* __restrict__ 
 // ------------------------------------------------------------------------------------
 static inline unsigned xcd_blocks(int ntiles) { return 8u * (unsigned)((ntiles + 7) / 8); }
 
-hipError_t launch_step_begin(const Ctl& c, int I, int only_item, hipStream_t s) {
-  hipLaunchKernelGGL(k_step_begin, dim3(1), dim3(256), 0, s, c, I, only_item);
+hipError_t launch_step_begin(const Ctl& c, int I, int only_item, double h, const SourceTable& src,
+                             hipStream_t s) {
+  hipLaunchKernelGGL(k_step_begin, dim3(1), dim3(256), 0, s, c, I, only_item, h, src);
   return hipGetLastError();
 }
 
-hipError_t launch_decide(const Ctl& c, int I, double tol, int has_d, int nchk, int max_sweeps,
+hipError_t launch_decide(const Ctl& c, int I, double tol, int has_d, int nchk, int max_sweeps, int nslots,
                          hipStream_t s) {
-  hipLaunchKernelGGL(k_decide, dim3(1), dim3(256), 0, s, c, I, tol, has_d, nchk, max_sweeps);
+  hipLaunchKernelGGL(k_decide, dim3(1), dim3(256), 0, s, c, I, tol, has_d, nchk, max_sweeps, nslots);
   return hipGetLastError();
 }
 
-hipError_t launch_step_end(const Ctl& c, int I, hipStream_t s) {
-  hipLaunchKernelGGL(k_step_end, dim3(1), dim3(64), 0, s, c, I);
+hipError_t launch_step_end(const Ctl& c, int I, int count_step, hipStream_t s) {
+  hipLaunchKernelGGL(k_step_end, dim3(1), dim3(64), 0, s, c, I, count_step);
   return hipGetLastError();
 }
 
@@ -648,10 +675,10 @@ hipError_t launch_rhs(const Tile* tiles, int ntiles, int tile_rows, const GridDe
   return hipGetLastError();
 }
 
-hipError_t launch_sources(const SourceTable& src, const GridDesc* grids, double t, hipStream_t s) {
-  const int n = src.n_always + src.win_count;
-  if (n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_sources, dim3((n + 255) / 256), dim3(256), 0, s, src, grids, t);
+hipError_t launch_sources(const SourceTable& src, const GridDesc* grids, const Ctl& c, hipStream_t s) {
+  if (src.count <= 0) return hipSuccess;
+  const int blocks = (src.count + 255) / 256 < 2048 ? (src.count + 255) / 256 : 2048;
+  hipLaunchKernelGGL(k_sources, dim3(blocks), dim3(256), 0, s, src, grids, c);
   return hipGetLastError();
 }
 

@@ -60,8 +60,10 @@ struct Tile {
   int32_t pad;
 };
 
-// Flattened current sources of every grid and scenario.  A step visits sources
-// [0, n_always) and [win_begin, win_begin + win_count).
+// Flattened current sources of every grid and scenario: first the n_always sources that are
+// non-zero outside their breakpoints, then the windowed ones (zero before the first and after the
+// last breakpoint) sorted by first breakpoint; win_t0 holds those first breakpoints and win_maxw
+// the widest window, so a step only visits windowed sources with t0 in [t - win_maxw, t].
 struct SourceTable {
   int32_t count;
   const int32_t* grid;
@@ -70,8 +72,9 @@ struct SourceTable {
   const double* t;
   const double* i;
   int32_t n_always;
-  int32_t win_begin;
-  int32_t win_count;
+  int32_t n_window;
+  const double* win_t0;            // [n_window]
+  double win_maxw;
 };
 
 // Device-side control block.  An item is one scenario of one grid; every item converges on
@@ -84,7 +87,7 @@ struct Ctl {
   int32_t* vidx;                   // [I]
   int32_t* step_sweeps;            // [I]
   int32_t* failed;                 // [I]
-  int32_t* any_active;             // [1]
+  int32_t* any_active;             // [nslots] host-visible flags, one per outstanding decision
   // running statistics, updated once per step on the device
   long long* stat_sweeps;          // [1]
   long long* stat_updates;         // [1]
@@ -95,21 +98,30 @@ struct Ctl {
   double* stat_max_res;            // [1]
   int32_t* stat_failed;            // [1]
   const long long* nodes;          // [I] mesh nodes of the item's grid
+  // step clock: the step being solved advances on the device, so every launch of a step has
+  // fixed arguments (and the step's launches can be replayed from a captured graph)
+  long long* step;                 // [1] steps completed
+  double* t_now;                   // [1] time of the step being solved, (step + 1) h
+  int32_t* src_window;             // [2] first windowed source visited, number visited
+  int32_t* flag_seq;               // [1] decisions taken so far (selects the flag slot)
 };
 
 // ---- launch wrappers (kernels.hip) ----
-hipError_t launch_step_begin(const Ctl& c, int G, int only_item, hipStream_t s);
+hipError_t launch_step_begin(const Ctl& c, int G, int only_item, double h, const SourceTable& src,
+                             hipStream_t s);
 hipError_t launch_rhs(const Tile* tiles, int ntiles, int tile_rows, const GridDesc* grids,
                       const Ctl& c, hipStream_t s);
-hipError_t launch_sources(const SourceTable& src, const GridDesc* grids, double t, hipStream_t s);
+hipError_t launch_sources(const SourceTable& src, const GridDesc* grids, const Ctl& c, hipStream_t s);
 hipError_t launch_resid(bool fp32, int nl, int tile_rows, const Tile* tiles, int ntiles,
                         const GridDesc* grids, const Ctl& c, int has_d, int din, hipStream_t s);
-hipError_t launch_decide(const Ctl& c, int G, double tol, int has_d, int nchk, int max_sweeps,
+// The decision of a residual check writes "any item still active" to flag slot
+// (*flag_seq)++ % nslots of c.any_active (host-visible memory).
+hipError_t launch_decide(const Ctl& c, int G, double tol, int has_d, int nchk, int max_sweeps, int nslots,
                          hipStream_t s);
 hipError_t launch_sweep(bool fp32, int ordering, int nl, int tile_rows, const Tile* tiles,
                         int ntiles, const GridDesc* grids, const Ctl& c, int din, int zero_in,
                         double omega, hipStream_t s);
-hipError_t launch_step_end(const Ctl& c, int G, hipStream_t s);
+hipError_t launch_step_end(const Ctl& c, int G, int count_step, hipStream_t s);
 // adjoint of the softplus loss (tiles of one item; vk, vprev and grads are plain slices)
 hipError_t launch_loss(const Tile* tiles, int ntiles, int tile_rows, const GridDesc* grids, const Ctl& c,
                        double margin, double* part, double* total, hipStream_t s);

@@ -18,6 +18,8 @@ using namespace pgrid;
 
 namespace {
 
+constexpr int kFlagSlots = 32;  // host-visible decision flags (at most 31 decisions in flight)
+
 struct Src {
   std::vector<int32_t> node, off;
   std::vector<double> t, i;
@@ -92,8 +94,10 @@ struct pg_ctx {
   int ntiles_all = 0;
   int tile_rows = 16;
   int n_src = 0, n_ind_total = 0;
-  int n_src_always = 0;                          // sources at [0, n_src_always) run every step
-  std::vector<double> win_t0;                    // first breakpoint of each windowed source (sorted)
+  SourceTable src_table{};                       // device source tables (see pgrid_internal.h)
+  DBuf src_win_t0;
+  long long step_host = 0;                       // staging for the device step counter
+  DBuf c_clock;                                  // step (int64), t_now (double), window (2 x int32)
   std::vector<int> item_tile_off, item_tile_cnt; // each item's tiles in tiles_all
   std::vector<GridDesc> desc_host;               // descriptors as uploaded (forward view)
   // recorded forward pass of the softplus-loss adjoint
@@ -105,11 +109,16 @@ struct pg_ctx {
     GridDesc view{};                             // the grid's descriptor with lambda as its state
     DBuf ckpts, vend, seg, lam0, lam1, arhs, dC, dgE, dgN, part, J, saved_vidx;
   } adj;
-  double win_maxw = 0.0;                         // widest window
   // control block
   DBuf c_norm, c_last, c_active, c_vidx, c_sweeps, c_failed, c_any, c_stats64, c_stats32, c_statsd, c_nodes;
   Ctl ctl{};
   int32_t* host_flags = nullptr;                 // pinned, written by the decision kernel
+  uint64_t flag_seq_host = 0;                    // decisions queued so far (mirrors the device counter)
+  hipStream_t cap_stream = nullptr;              // private stream for graph capture
+  hipGraphExec_t g_prologue = nullptr, g_sweeps = nullptr, g_check = nullptr, g_epilogue = nullptr;
+  bool graphs_ready = false;
+  int64_t all_nodes = 0;                         // mesh nodes x scenarios over all grids
+  double cycle_sweep_bytes = 0.0;                // algorithmic bytes of one cycle's sweeps
   int32_t* dev_flags = nullptr;                  // device address of host_flags
   std::vector<hipEvent_t> flag_events;
   // profiling
@@ -123,6 +132,8 @@ struct pg_ctx {
 };
 
 namespace {
+
+void drop_graphs(pg_ctx* c);
 
 pg_status set_err(pg_ctx* c, pg_status st, const char* fmt, ...) {
   char buf[512];
@@ -350,6 +361,7 @@ pg_status build_grid(pg_ctx* c, int gi) {
 pg_status prepare(pg_ctx* c) {
   if (c->grids.empty()) return set_err(c, PG_ERR_STATE, "no grid uploaded");
   if (!c->dirty) return PG_OK;
+  drop_graphs(c);
   const int G = (int)c->grids.size();
   c->tile_rows = c->opt.tile_rows ? c->opt.tile_rows : 8;
   for (int g = 0; g < G; ++g) PG_TRY(build_grid(c, g));
@@ -406,6 +418,12 @@ pg_status prepare(pg_ctx* c) {
       c->tile_groups.push_back({nl, start, (int)tiles.size() - start, nodes_nl, mesh_nl});
   }
   c->ntiles_all = (int)tiles.size();
+  c->all_nodes = 0;
+  c->cycle_sweep_bytes = 0.0;
+  for (auto& grp : c->tile_groups) {
+    c->all_nodes += grp.nodes;
+    c->cycle_sweep_bytes += c->sweep_bytes(grp, true) + (c->opt.check_every - 1) * c->sweep_bytes(grp, false);
+  }
   PG_TRY(upload(c, c->tiles_all, tiles));
   // sources: first those that are non-zero outside their breakpoints ("always"), then the
   // windowed ones (zero before the first and after the last breakpoint, like every triangle)
@@ -424,10 +442,9 @@ pg_status prepare(pg_ctx* c) {
     }
   }
   std::stable_sort(windowed.begin(), windowed.end(), [](const SrcRef& x, const SrcRef& y) { return x.t0 < y.t0; });
-  c->n_src_always = (int)always.size();
-  c->win_t0.clear();
-  c->win_maxw = 0.0;
-  for (auto& w : windowed) { c->win_t0.push_back(w.t0); c->win_maxw = std::max(c->win_maxw, w.t1 - w.t0); }
+  std::vector<double> win_t0;
+  double win_maxw = 0.0;
+  for (auto& w : windowed) { win_t0.push_back(w.t0); win_maxw = std::max(win_maxw, w.t1 - w.t0); }
   std::vector<int32_t> sg, si, so{0};
   std::vector<double> st, sv;
   for (const auto* list : {&always, &windowed})
@@ -441,7 +458,11 @@ pg_status prepare(pg_ctx* c) {
     }
   c->n_src = (int)sg.size();
   PG_TRY(upload(c, c->src_grid, sg)); PG_TRY(upload(c, c->src_index, si)); PG_TRY(upload(c, c->src_off, so));
-  PG_TRY(upload(c, c->src_t, st)); PG_TRY(upload(c, c->src_i, sv));
+  PG_TRY(upload(c, c->src_t, st)); PG_TRY(upload(c, c->src_i, sv)); PG_TRY(upload(c, c->src_win_t0, win_t0));
+  c->src_table = SourceTable{c->n_src, (const int32_t*)c->src_grid.p, (const int32_t*)c->src_index.p,
+                             (const int32_t*)c->src_off.p, (const double*)c->src_t.p, (const double*)c->src_i.p,
+                             (int32_t)always.size(), (int32_t)windowed.size(), (const double*)c->src_win_t0.p,
+                             win_maxw};
   // flattened inductor list
   std::vector<int32_t> ig, il;
   for (int g = 0; g < G; ++g)
@@ -537,14 +558,22 @@ pg_status launch_sweeps(pg_ctx* c, int nchk) {
 
 // Begin a step at time (step + 1) h: activate every item (only_item < 0) or one item, form the
 // right-hand side on the active tiles, subtract the sources.
+// Set the step clock (host mirror and device counter).
+pg_status set_step(pg_ctx* c, int64_t k) {
+  c->step = k;
+  c->step_host = (long long)k;
+  HIP_TRY(c, hipMemcpyAsync(c->ctl.step, &c->step_host, sizeof(long long), hipMemcpyHostToDevice, c->stream));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  return PG_OK;
+}
+
 pg_status begin_step(pg_ctx* c, int only_item) {
   const int G = n_items(c);
   Ctl k = c->ctl;
-  const double t = (double)(c->step + 1) * c->opt.h;
   hipError_t e;
   {
     ProfScope ps(c, 3, 0);
-    e = launch_step_begin(k, G, only_item, c->stream);
+    e = launch_step_begin(k, G, only_item, c->opt.h, c->src_table, c->stream);
     if (e != hipSuccess) return set_err(c, PG_ERR_DEVICE, "step launch: %s", hipGetErrorString(e));
   }
   {
@@ -556,60 +585,71 @@ pg_status begin_step(pg_ctx* c, int only_item) {
     if (e != hipSuccess) return set_err(c, PG_ERR_DEVICE, "rhs launch: %s", hipGetErrorString(e));
   }
   {
-    // windowed sources whose window can contain t: first breakpoint in [t - widest, t]
-    const auto lo = std::lower_bound(c->win_t0.begin(), c->win_t0.end(), t - c->win_maxw) - c->win_t0.begin();
-    const auto hi = std::upper_bound(c->win_t0.begin(), c->win_t0.end(), t) - c->win_t0.begin();
-    SourceTable st{c->n_src, (const int32_t*)c->src_grid.p, (const int32_t*)c->src_index.p,
-                   (const int32_t*)c->src_off.p, (const double*)c->src_t.p, (const double*)c->src_i.p,
-                   c->n_src_always, c->n_src_always + (int32_t)lo, (int32_t)(hi - lo)};
     ProfScope ps(c, 2, 0);
-    e = launch_sources(st, (const GridDesc*)c->grid_desc.p, t, c->stream);
+    e = launch_sources(c->src_table, (const GridDesc*)c->grid_desc.p, k, c->stream);
     if (e != hipSuccess) return set_err(c, PG_ERR_DEVICE, "source launch: %s", hipGetErrorString(e));
   }
   return PG_OK;
 }
 
-// Algorithm 1's inner loop for every active item: FP64 residual, then refinement cycles of
-// check_every sweeps + residual until each item's scaled residual is <= tol.
-pg_status solve_active(pg_ctx* c, double tol) {
-  const int G = n_items(c);
+// Queue the decision of a residual check; returns its flag slot (the device picks the same slot
+// from its own sequence counter) and records the slot's event after it.
+pg_status issue_decide(pg_ctx* c, double tol, int has_d, int* slot_out) {
+  const int slot = (int)(c->flag_seq_host++ % kFlagSlots);
+  Ctl kk = c->ctl;
+  kk.any_active = c->dev_flags;
+  {
+    ProfScope ps(c, 3, 0);
+    hipError_t e = launch_decide(kk, n_items(c), tol, has_d, c->opt.check_every, c->opt.max_sweeps, kFlagSlots,
+                                 c->stream);
+    if (e != hipSuccess) return set_err(c, PG_ERR_DEVICE, "decide launch: %s", hipGetErrorString(e));
+  }
+  HIP_TRY(c, hipEventRecord(c->flag_events[slot], c->stream));
+  *slot_out = slot;
+  return PG_OK;
+}
+
+// One refinement cycle: check_every sweeps, the FP64 residual with v <- v + d, the decision.
+pg_status issue_cycle(pg_ctx* c, double tol, bool graphs, int* slot) {
+  const int nchk = c->opt.check_every;
+  if (graphs) {
+    {
+      ProfScope ps(c, 0, c->all_nodes * nchk, c->cycle_sweep_bytes, nchk * (int)c->tile_groups.size());
+      HIP_TRY(c, hipGraphLaunch(c->g_sweeps, c->stream));
+    }
+    {
+      ProfScope ps(c, 3, 0);
+      HIP_TRY(c, hipGraphLaunch(c->g_check, c->stream));
+    }
+    *slot = (int)(c->flag_seq_host++ % kFlagSlots);
+    HIP_TRY(c, hipEventRecord(c->flag_events[*slot], c->stream));
+    return PG_OK;
+  }
+  PG_TRY(launch_sweeps(c, nchk));
+  PG_TRY(launch_resid_all(c, 1, nchk & 1));
+  return issue_decide(c, tol, 1, slot);
+}
+
+// Algorithm 1's inner loop for every active item, after the initial check (its flag slot in
+// `first`) has been queued: refinement cycles until each item's scaled residual is <= tol.
+// The host queues as many cycles as the previous step needed before waiting; past that
+// prediction it keeps `lookahead` cycles queued beyond the one whose decision it waits for.
+// Cycles queued after convergence find every item inactive and exit at once.
+pg_status cycle_loop(pg_ctx* c, double tol, bool graphs, int first) {
   const int nchk = c->opt.check_every;
   const int L = c->opt.lookahead;
-  PG_TRY(launch_resid_all(c, 0, 0));
-  // decision after the initial residual goes to flag slot 0
-  const int nslots = (int)c->flag_events.size();
-  int slot = 0;
-  auto decide = [&](int has_d) -> pg_status {
-    Ctl kk = c->ctl;
-    kk.any_active = c->dev_flags + slot;
-    ProfScope ps(c, 3, 0);
-    hipError_t ee = launch_decide(kk, G, tol, has_d, nchk, c->opt.max_sweeps, c->stream);
-    if (ee != hipSuccess) return set_err(c, PG_ERR_DEVICE, "decide launch: %s", hipGetErrorString(ee));
-    HIP_TRY(c, hipEventRecord(c->flag_events[slot], c->stream));
-    return PG_OK;
-  };
-  std::deque<int> pending;
+  std::deque<int> pending{first};
   const size_t prof_base = c->prof_live.size();
-  c->cur_chunk = 0;
-  PG_TRY(decide(0));
-  pending.push_back(slot);
-  slot = (slot + 1) % nslots;
-  const int din_final = nchk & 1;  // buffer holding the correction after nchk sweeps
   const int max_chunks = (c->opt.max_sweeps + nchk - 1) / nchk;
   int issued = 0, consumed = 0, last = -1;
-  // Refinement cycle j (j >= 1) is nchk sweeps, a residual and a decision.  Queue as many
-  // cycles as the previous step needed before waiting; past that prediction keep `lookahead`
-  // cycles queued beyond the one whose decision the host waits for.  Cycles queued after
-  // convergence find every item inactive and exit at once.
   while (true) {
-    const int want = consumed <= c->pred_chunks ? c->pred_chunks : consumed + L;
+    int want = consumed <= c->pred_chunks ? c->pred_chunks : consumed + L;
+    want = std::min(want, consumed + kFlagSlots - 1);  // never reuse a slot still awaited
     while (issued < max_chunks && issued < want) {
       c->cur_chunk = ++issued;
-      PG_TRY(launch_sweeps(c, nchk));
-      PG_TRY(launch_resid_all(c, 1, din_final));
-      PG_TRY(decide(1));
+      int slot = 0;
+      PG_TRY(issue_cycle(c, tol, graphs, &slot));
       pending.push_back(slot);
-      slot = (slot + 1) % nslots;
     }
     if (pending.empty()) break;
     const int s0 = pending.front();
@@ -629,13 +669,22 @@ pg_status solve_active(pg_ctx* c, double tol) {
   return PG_OK;
 }
 
-// Close a step: statistics and the inductor branch currents.
-pg_status end_step(pg_ctx* c) {
+pg_status solve_active(pg_ctx* c, double tol) {
+  c->cur_chunk = 0;
+  PG_TRY(launch_resid_all(c, 0, 0));
+  int first = 0;
+  PG_TRY(issue_decide(c, tol, 0, &first));
+  return cycle_loop(c, tol, false, first);
+}
+
+// Close a step: advance the device clock, statistics (count_step = 1) and the inductor branch
+// currents.
+pg_status end_step(pg_ctx* c, int count_step = 1) {
   Ctl k = c->ctl;
   hipError_t e;
   {
     ProfScope ps(c, 3, 0);
-    e = launch_step_end(k, n_items(c), c->stream);
+    e = launch_step_end(k, n_items(c), count_step, c->stream);
     if (e != hipSuccess) return set_err(c, PG_ERR_DEVICE, "step-end launch: %s", hipGetErrorString(e));
   }
   if (c->n_ind_total) {
@@ -647,10 +696,85 @@ pg_status end_step(pg_ctx* c) {
   return PG_OK;
 }
 
+// Capture the launches queued by `body` on a private stream into an executable graph.
+template <typename F>
+pg_status capture(pg_ctx* c, hipGraphExec_t* out, F body) {
+  hipStream_t saved = c->stream;
+  const int saved_prof = c->profile_every;
+  c->stream = c->cap_stream;
+  c->profile_every = 0;
+  hipError_t e = hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal);
+  pg_status st = e == hipSuccess ? body() : PG_ERR_DEVICE;
+  hipGraph_t g = nullptr;
+  hipError_t e2 = hipStreamEndCapture(c->cap_stream, &g);
+  c->stream = saved;
+  c->profile_every = saved_prof;
+  if (e != hipSuccess || e2 != hipSuccess)
+    return set_err(c, PG_ERR_DEVICE, "graph capture failed: %s",
+                   hipGetErrorString(e != hipSuccess ? e : e2));
+  if (st != PG_OK) { (void)hipGraphDestroy(g); return st; }
+  e = hipGraphInstantiate(out, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  if (e != hipSuccess) return set_err(c, PG_ERR_DEVICE, "graph instantiation failed: %s", hipGetErrorString(e));
+  return PG_OK;
+}
+
+void drop_graphs(pg_ctx* c) {
+  for (hipGraphExec_t* g : {&c->g_prologue, &c->g_sweeps, &c->g_check, &c->g_epilogue})
+    if (*g) { (void)hipGraphExecDestroy(*g); *g = nullptr; }
+  c->graphs_ready = false;
+}
+
+// The four graphs of a step: prologue (begin, RHS, sources, first residual and decision), the
+// sweeps of a refinement cycle, its residual and decision, the epilogue.  Their launches have
+// fixed arguments because the step clock and the flag slot advance on the device.
+pg_status build_graphs(pg_ctx* c) {
+  drop_graphs(c);
+  const double tol = c->opt.tol;
+  int dummy = 0;
+  const uint64_t seq = c->flag_seq_host;
+  PG_TRY(capture(c, &c->g_prologue, [&]() -> pg_status {
+    PG_TRY(begin_step(c, -1));
+    PG_TRY(launch_resid_all(c, 0, 0));
+    Ctl kk = c->ctl;
+    kk.any_active = c->dev_flags;
+    hipError_t e = launch_decide(kk, n_items(c), tol, 0, c->opt.check_every, c->opt.max_sweeps, kFlagSlots,
+                                 c->stream);
+    return e == hipSuccess ? PG_OK : set_err(c, PG_ERR_DEVICE, "decide: %s", hipGetErrorString(e));
+  }));
+  PG_TRY(capture(c, &c->g_sweeps, [&]() { return launch_sweeps(c, c->opt.check_every); }));
+  PG_TRY(capture(c, &c->g_check, [&]() -> pg_status {
+    PG_TRY(launch_resid_all(c, 1, c->opt.check_every & 1));
+    Ctl kk = c->ctl;
+    kk.any_active = c->dev_flags;
+    hipError_t e = launch_decide(kk, n_items(c), tol, 1, c->opt.check_every, c->opt.max_sweeps, kFlagSlots,
+                                 c->stream);
+    return e == hipSuccess ? PG_OK : set_err(c, PG_ERR_DEVICE, "decide: %s", hipGetErrorString(e));
+  }));
+  PG_TRY(capture(c, &c->g_epilogue, [&]() { return end_step(c, 1); }));
+  (void)dummy;
+  c->flag_seq_host = seq;  // capture queued nothing on the device
+  c->graphs_ready = true;
+  return PG_OK;
+}
+
 pg_status one_step(pg_ctx* c) {
-  PG_TRY(begin_step(c, -1));
-  PG_TRY(solve_active(c, c->opt.tol));
-  PG_TRY(end_step(c));
+  if (c->opt.graphs) {
+    if (!c->graphs_ready) PG_TRY(build_graphs(c));
+    {
+      ProfScope ps(c, 3, 0);
+      HIP_TRY(c, hipGraphLaunch(c->g_prologue, c->stream));
+    }
+    const int first = (int)(c->flag_seq_host++ % kFlagSlots);
+    HIP_TRY(c, hipEventRecord(c->flag_events[first], c->stream));
+    c->cur_chunk = 0;
+    PG_TRY(cycle_loop(c, c->opt.tol, true, first));
+    HIP_TRY(c, hipGraphLaunch(c->g_epilogue, c->stream));
+  } else {
+    PG_TRY(begin_step(c, -1));
+    PG_TRY(solve_active(c, c->opt.tol));
+    PG_TRY(end_step(c));
+  }
   c->step++;
   return PG_OK;
 }
@@ -714,10 +838,12 @@ pg_status loss_backward(pg_ctx* c, double tol_adj, double* dC, double* dgE, doub
     // recompute the forward states of the segment from its checkpoint (only this item steps)
     PG_TRY(state_copy(c, A.item, ck + (size_t)j * ns, 0));
     HIP_TRY(c, hipMemcpyAsync(seg, ck + (size_t)j * ns, ns * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
-    c->step = A.k0 + kb;
+    PG_TRY(set_step(c, A.k0 + kb));
     for (int q = 1; q <= len; ++q) {
       PG_TRY(begin_step(c, A.item));
       PG_TRY(solve_active(c, c->opt.tol));
+      hipError_t e2 = launch_step_end(c->ctl, n_items(c), 2, c->stream);
+      if (e2 != hipSuccess) return set_err(c, PG_ERR_DEVICE, "step-end launch: %s", hipGetErrorString(e2));
       c->step++;
       PG_TRY(state_copy(c, A.item, seg + (size_t)q * ns, 1));
     }
@@ -726,7 +852,7 @@ pg_status loss_backward(pg_ctx* c, double tol_adj, double* dC, double* dgE, doub
     for (int q = len; q >= 1; --q) {
       hipError_t e = launch_adj_rhs(T, nt, c->tile_rows, gd, c->ctl, seg + (size_t)q * ns, A.margin, c->stream);
       if (e != hipSuccess) return set_err(c, PG_ERR_DEVICE, "adjoint rhs: %s", hipGetErrorString(e));
-      e = launch_step_begin(c->ctl, n_items(c), A.item, c->stream);
+      e = launch_step_begin(c->ctl, n_items(c), A.item, c->opt.h, c->src_table, c->stream);
       if (e != hipSuccess) return set_err(c, PG_ERR_DEVICE, "adjoint step: %s", hipGetErrorString(e));
       PG_TRY(solve_active(c, tol_adj));
       e = launch_adj_grad(T, nt, c->tile_rows, gd, c->ctl, seg + (size_t)q * ns, seg + (size_t)(q - 1) * ns,
@@ -737,7 +863,7 @@ pg_status loss_backward(pg_ctx* c, double tol_adj, double* dC, double* dgE, doub
   }
   // back to the state the forward pass ended in
   PG_TRY(state_copy(c, A.item, (double*)A.vend.p, 0));
-  c->step = A.k0 + A.K;
+  PG_TRY(set_step(c, A.k0 + A.K));
   HIP_TRY(c, hipStreamSynchronize(c->stream));
   int32_t failed = 0;
   HIP_TRY(c, hipMemcpy(&failed, c->ctl.stat_failed, sizeof failed, hipMemcpyDeviceToHost));
@@ -783,7 +909,7 @@ pg_status pg_create(pg_ctx** out, int32_t device, void* stream) {
     if (hipStreamCreate(&c->stream) != hipSuccess) { delete c; return PG_ERR_DEVICE; }
     c->own_stream = true;
   }
-  const int nslots = 8;
+  const int nslots = kFlagSlots;
   if (hipHostMalloc((void**)&c->host_flags, nslots * sizeof(int32_t), hipHostMallocMapped | hipHostMallocCoherent) !=
           hipSuccess ||
       hipHostGetDevicePointer((void**)&c->dev_flags, c->host_flags, 0) != hipSuccess) {
@@ -801,7 +927,19 @@ pg_status pg_create(pg_ctx** out, int32_t device, void* stream) {
     pg_destroy(c);
     return PG_ERR_OOM;
   }
+  if (dalloc(c, c->c_clock, 32) != PG_OK || hipMemset(c->c_clock.p, 0, 32) != hipSuccess) {
+    pg_destroy(c);
+    return PG_ERR_OOM;
+  }
   Ctl& k = c->ctl;
+  k.step = (long long*)c->c_clock.p;
+  k.t_now = (double*)((char*)c->c_clock.p + 8);
+  k.src_window = (int32_t*)((char*)c->c_clock.p + 16);
+  k.flag_seq = (int32_t*)((char*)c->c_clock.p + 24);
+  if (hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking) != hipSuccess) {
+    pg_destroy(c);
+    return PG_ERR_DEVICE;
+  }
   k.stat_sweeps = (long long*)c->c_stats64.p;
   k.stat_updates = k.stat_sweeps + 1;
   k.stat_checks = k.stat_sweeps + 2;
@@ -827,7 +965,8 @@ void pg_destroy(pg_ctx* c) {
   }
   DBuf* bufs[] = {&c->grid_desc, &c->tiles_all, &c->src_grid, &c->src_index, &c->src_off, &c->src_t, &c->src_i,
                   &c->ind_grid, &c->ind_local, &c->c_norm, &c->c_last, &c->c_active, &c->c_vidx, &c->c_sweeps,
-                  &c->c_failed, &c->c_any, &c->c_stats64, &c->c_stats32, &c->c_statsd, &c->c_nodes};
+                  &c->c_failed, &c->c_any, &c->c_stats64, &c->c_stats32, &c->c_statsd, &c->c_nodes,
+                  &c->c_clock, &c->src_win_t0};
   for (DBuf* b : bufs) dfree(*b);
   DBuf* abufs[] = {&c->adj.ckpts, &c->adj.vend, &c->adj.seg, &c->adj.lam0, &c->adj.lam1, &c->adj.arhs,
                    &c->adj.dC, &c->adj.dgE, &c->adj.dgN, &c->adj.part, &c->adj.J, &c->adj.saved_vidx};
@@ -836,6 +975,8 @@ void pg_destroy(pg_ctx* c) {
   for (auto& e : c->prof_live) { (void)hipEventDestroy(e.a); (void)hipEventDestroy(e.b); }
   for (auto e : c->prof_pool) (void)hipEventDestroy(e);
   if (c->host_flags) (void)hipHostFree(c->host_flags);
+  drop_graphs(c);
+  if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
   if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
   delete c;
 }
@@ -972,7 +1113,7 @@ pg_status pg_reset(pg_ctx* c) {
   PG_TRY(prepare(c));
   for (int g = 0; g < (int)c->grids.size(); ++g)
     for (int s = 0; s < c->grids[g].S; ++s) PG_TRY(pg_set_state(c, g, s, nullptr, nullptr));
-  c->step = 0;
+  PG_TRY(set_step(c, 0));
   PG_TRY(reset_stats_dev(c));
   HIP_TRY(c, hipStreamSynchronize(c->stream));
   return PG_OK;

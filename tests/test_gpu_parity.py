@@ -183,3 +183,30 @@ def test_uneven_grids_batched_in_one_launch():
         say(f"  grid {g}: err={err:.3e}")
         assert err <= PARITY_V
     assert st["node_updates"] > 0
+
+
+@pytest.mark.parametrize("case", ["rc32", "three_layer", "batched"])
+def test_graph_replay_matches_eager_every_step(case):
+    """Replaying the captured step graphs gives bitwise the eager launches' voltages after every
+    step (host reads and synchronisations happen between replays)."""
+    if case == "rc32":
+        w, prec = config0(), pg.PG_PREC_FP64
+    elif case == "three_layer":
+        w, prec = small_multilayer(side=100, seed=71, nl=3, pad_every=32, steps=30), pg.PG_PREC_FP32_REFINE
+        w.pulses[0][0] = compressed(w.pulses[0][0], start=0.08, width=1.0)
+    else:
+        w, prec = small_rc(70, 44, seed=72, scenarios=4, steps=30), pg.PG_PREC_FP32_REFINE
+        w.pulses[0] = [compressed(p, start=0.4, width=1.0) for p in w.pulses[0]]
+    steps = 30
+    out = {}
+    for graphs in (0, 1):
+        say(f"[gpu] graphs={graphs} case={case}")
+        with gpu_context(w, precision=prec, tol=1e-10, omega=1.6, graphs=graphs) as ctx:
+            V = []
+            for k in range(steps):
+                ctx.step(1)
+                V.append(np.stack([ctx.read_voltages(0, s) for s in range(len(w.pulses[0]))]))
+            out[graphs] = (np.array(V), ctx.stats())
+    assert np.array_equal(out[0][0], out[1][0])
+    assert out[0][1]["sweeps"] == out[1][1]["sweeps"]
+    assert out[0][1]["node_updates"] == out[1][1]["node_updates"]
