@@ -198,8 +198,22 @@ pg_status pg_step(pg_ctx* ctx, int32_t nsteps);
 pg_status pg_run_transient(pg_ctx* ctx, int32_t nsteps, int32_t record_every, int32_t grid,
                            int32_t scen, double* out);
 
-/* Current step index k (time t = k h). */
+/* Current step index k (time t = k h); pg_set_time moves the clock without touching the state. */
 pg_status pg_get_time(const pg_ctx* ctx, int64_t* step);
+pg_status pg_set_time(pg_ctx* ctx, int64_t step);
+
+/* Number of uploaded grids, and the sizes of one (any output pointer may be NULL). */
+pg_status pg_num_grids(const pg_ctx* ctx, int32_t* count);
+pg_status pg_grid_info(const pg_ctx* ctx, int32_t grid, int32_t* nx, int32_t* ny, int32_t* nl, int32_t* n_scen,
+                       int32_t* n_vias, int32_t* n_pads);
+
+/* Autotuner: times `nsteps` steps from the current state for candidate settings (omega, sweeps
+ * per residual check, tile rows, graph replay), by coordinate descent from the current options,
+ * restoring the state and clock after every trial, and sets the fastest.  The winner is cached in
+ * the JSON file `cache_path` (may be NULL: no cache) under a key built from the grid shapes,
+ * scenario counts, precision, h, tolerance and the GPU architecture; a cached entry is applied
+ * without timing.  *chosen (may be NULL) receives the options set. */
+pg_status pg_autotune(pg_ctx* ctx, int32_t nsteps, const char* cache_path, pg_options* chosen);
 
 /* Copy the node voltages (n doubles) or inductor currents (n_vias + n_pads doubles, via
  * then pad order, zero for resistive branches) of one scenario to host memory (blocking)

@@ -18,11 +18,11 @@ Parity status per function is listed in the module headers.
 from .circuit import Circuit, GROUND, mesh_to_circuit
 from .sources import triangle_current, currents_at
 from .linsolve import factor
-from .transient import (BEStepper, be_transient, dc_solve, three_level_transient,
+from .transient import (BESystem, BEStepper, be_transient, dc_solve, three_level_transient,
                         scaled_residual, mesh_voltages)
 from .adjoint import softplus_loss, adjoint_gradients, tangent_linear
 
 __all__ = ["Circuit", "GROUND", "mesh_to_circuit", "triangle_current", "currents_at",
-           "factor", "BEStepper", "be_transient", "dc_solve", "three_level_transient",
+           "factor", "BESystem", "BEStepper", "be_transient", "dc_solve", "three_level_transient",
            "scaled_residual", "mesh_voltages", "softplus_loss", "adjoint_gradients",
            "tangent_linear"]

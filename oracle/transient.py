@@ -27,18 +27,16 @@ from .linsolve import factor
 from .sources import currents_at
 
 
-class BEStepper:
-    """One backward-Euler step of eq. 10 with the system matrix factored once."""
+class BESystem:
+    """The assembled backward-Euler system of eq. 10 (system matrix and right-hand side)."""
 
-    def __init__(self, circ, h: float, dense_max: int | None = None):
+    def __init__(self, circ, h: float):
         self.circ = circ
         self.h = float(h)
         mats = circ.matrices()
         self.mats = mats
         self.Ch = (mats["C"] / self.h).tocsr()
         self.M = (self.Ch + mats["G"] + self.h * mats["L"]).tocsc()
-        kw = {} if dense_max is None else {"dense_max": dense_max}
-        self.fac = factor(self.M, spd=True, **kw)
         vd = circ.vd
         # constant part of the right-hand side: -h L_s v_d - G_s v_d
         self.const = -(self.h * (mats["Ls"] @ vd)) - (mats["Gs"] @ vd)
@@ -52,6 +50,15 @@ class BEStepper:
         if I_next.size:
             b = b - mats["Ai"].T @ I_next
         return b
+
+
+class BEStepper(BESystem):
+    """One backward-Euler step of eq. 10 with the system matrix factored once."""
+
+    def __init__(self, circ, h: float, dense_max: int | None = None):
+        super().__init__(circ, h)
+        kw = {} if dense_max is None else {"dense_max": dense_max}
+        self.fac = factor(self.M, spd=True, **kw)
 
     def step(self, v, il, I_next):
         b = self.rhs(v, il, I_next)
@@ -150,7 +157,7 @@ def three_level_transient(circ, pulses, h, steps, v0, v1):
     return np.array(out)
 
 
-def scaled_residual(stepper: BEStepper, v_prev, il_prev, v_next, I_next):
+def scaled_residual(stepper: BESystem, v_prev, il_prev, v_next, I_next):
     """max_i |(b - M v_next)_i| / M_ii, the Jacobi-scaled backward-Euler residual (volts)."""
     b = stepper.rhs(v_prev, il_prev, I_next)
     r = b - stepper.M @ v_next

@@ -119,6 +119,7 @@ struct pg_ctx {
   bool graphs_ready = false;
   int64_t all_nodes = 0;                         // mesh nodes x scenarios over all grids
   double cycle_sweep_bytes = 0.0;                // algorithmic bytes of one cycle's sweeps
+  double check_resid_bytes = 0.0;                // algorithmic bytes of one cycle's residual pass
   int32_t* dev_flags = nullptr;                  // device address of host_flags
   std::vector<hipEvent_t> flag_events;
   // profiling
@@ -419,11 +420,7 @@ pg_status prepare(pg_ctx* c) {
   }
   c->ntiles_all = (int)tiles.size();
   c->all_nodes = 0;
-  c->cycle_sweep_bytes = 0.0;
-  for (auto& grp : c->tile_groups) {
-    c->all_nodes += grp.nodes;
-    c->cycle_sweep_bytes += c->sweep_bytes(grp, true) + (c->opt.check_every - 1) * c->sweep_bytes(grp, false);
-  }
+  for (auto& grp : c->tile_groups) c->all_nodes += grp.nodes;
   PG_TRY(upload(c, c->tiles_all, tiles));
   // sources: first those that are non-zero outside their breakpoints ("always"), then the
   // windowed ones (zero before the first and after the last breakpoint, like every triangle)
@@ -618,7 +615,7 @@ pg_status issue_cycle(pg_ctx* c, double tol, bool graphs, int* slot) {
       HIP_TRY(c, hipGraphLaunch(c->g_sweeps, c->stream));
     }
     {
-      ProfScope ps(c, 3, 0);
+      ProfScope ps(c, 1, c->all_nodes, c->check_resid_bytes);  // residual (+ the one-block decision)
       HIP_TRY(c, hipGraphLaunch(c->g_check, c->stream));
     }
     *slot = (int)(c->flag_seq_host++ % kFlagSlots);
@@ -730,6 +727,12 @@ void drop_graphs(pg_ctx* c) {
 // fixed arguments because the step clock and the flag slot advance on the device.
 pg_status build_graphs(pg_ctx* c) {
   drop_graphs(c);
+  c->cycle_sweep_bytes = 0.0;
+  c->check_resid_bytes = 0.0;
+  for (auto& grp : c->tile_groups) {
+    c->check_resid_bytes += c->resid_bytes(grp, true);
+    c->cycle_sweep_bytes += c->sweep_bytes(grp, true) + (c->opt.check_every - 1) * c->sweep_bytes(grp, false);
+  }
   const double tol = c->opt.tol;
   int dummy = 0;
   const uint64_t seq = c->flag_seq_host;
@@ -988,8 +991,11 @@ pg_status pg_set_options(pg_ctx* c, const pg_options* o) {
   char msg[256] = {0};
   pg_status st = pg_validate_options(o, msg, sizeof msg);
   if (st != PG_OK) return set_err(c, st, "%s", msg);
+  // h and precision change the coefficients, tile_rows the tiles: rebuild; anything else only
+  // invalidates the captured graphs
+  if (o->h != c->opt.h || o->precision != c->opt.precision || o->tile_rows != c->opt.tile_rows) c->dirty = true;
+  drop_graphs(c);
   c->opt = *o;
-  c->dirty = true;
   return PG_OK;
 }
 
@@ -1153,6 +1159,31 @@ pg_status pg_run_transient(pg_ctx* c, int32_t nsteps, int32_t record_every, int3
 pg_status pg_get_time(const pg_ctx* c, int64_t* step) {
   if (!c || !step) return PG_ERR_INVALID_ARG;
   *step = c->step;
+  return PG_OK;
+}
+
+pg_status pg_set_time(pg_ctx* c, int64_t step) {
+  if (!c || step < 0) return PG_ERR_INVALID_ARG;
+  HIP_TRY(c, hipSetDevice(c->device));
+  return set_step(c, step);
+}
+
+pg_status pg_num_grids(const pg_ctx* c, int32_t* count) {
+  if (!c || !count) return PG_ERR_INVALID_ARG;
+  *count = (int32_t)c->grids.size();
+  return PG_OK;
+}
+
+pg_status pg_grid_info(const pg_ctx* c, int32_t grid, int32_t* nx, int32_t* ny, int32_t* nl, int32_t* n_scen,
+                       int32_t* n_vias, int32_t* n_pads) {
+  if (!c || grid < 0 || grid >= (int)c->grids.size()) return PG_ERR_INVALID_ARG;
+  const GridHost& H = c->grids[grid];
+  if (nx) *nx = H.nx;
+  if (ny) *ny = H.ny;
+  if (nl) *nl = H.nl;
+  if (n_scen) *n_scen = H.S;
+  if (n_vias) *n_vias = (int32_t)H.via_node.size();
+  if (n_pads) *n_pads = (int32_t)H.pad_node.size();
   return PG_OK;
 }
 
@@ -1338,3 +1369,189 @@ pg_status pg_update_mesh_values(pg_ctx* c, int32_t grid, const double* gE, const
 }
 
 }  // extern "C"
+
+// ---- autotuner ------------------------------------------------------------------------------
+namespace {
+
+struct Snapshot {
+  std::vector<std::vector<double>> v, il;
+  int64_t step = 0;
+};
+
+pg_status take_snapshot(pg_ctx* c, Snapshot& sn) {
+  sn.v.clear();
+  sn.il.clear();
+  for (int g = 0; g < (int)c->grids.size(); ++g) {
+    const GridHost& H = c->grids[g];
+    const int64_t nb = (int64_t)H.via_node.size() + (int64_t)H.pad_node.size();
+    for (int s = 0; s < H.S; ++s) {
+      sn.v.emplace_back(H.n);
+      sn.il.emplace_back(std::max<int64_t>(nb, 1));
+      PG_TRY(pg_read_voltages(c, g, s, sn.v.back().data(), H.n));
+      PG_TRY(pg_read_inductor_currents(c, g, s, sn.il.back().data(), nb));
+    }
+  }
+  sn.step = c->step;
+  return PG_OK;
+}
+
+pg_status restore_snapshot(pg_ctx* c, const Snapshot& sn) {
+  size_t k = 0;
+  for (int g = 0; g < (int)c->grids.size(); ++g)
+    for (int s = 0; s < c->grids[g].S; ++s, ++k) PG_TRY(pg_set_state(c, g, s, sn.v[k].data(), sn.il[k].data()));
+  PG_TRY(set_step(c, sn.step));
+  PG_TRY(reset_stats_dev(c));
+  return PG_OK;
+}
+
+std::string tune_key(pg_ctx* c) {
+  hipDeviceProp_t prop;
+  std::string arch = "unknown";
+  if (hipGetDeviceProperties(&prop, c->device) == hipSuccess) arch = std::string(prop.gcnArchName).substr(0, 6);
+  char buf[256];
+  std::string key;
+  for (auto& H : c->grids) {
+    std::snprintf(buf, sizeof buf, "%dx%dx%d*%d;", H.nx, H.ny, H.nl, H.S);
+    key += buf;
+  }
+  std::snprintf(buf, sizeof buf, "prec%d;h%.6g;tol%.3g;%s", c->opt.precision, c->opt.h, c->opt.tol, arch.c_str());
+  return key + buf;
+}
+
+// The cache is a flat JSON object {"key": {"omega": w, "check_every": n, "tile_rows": r,
+// "graphs": g, "seconds": t}, ...} written and read only by this library.
+bool cache_lookup(const char* path, const std::string& key, pg_options* o) {
+  if (!path) return false;
+  FILE* f = std::fopen(path, "r");
+  if (!f) return false;
+  std::string text;
+  char buf[4096];
+  size_t nread;
+  while ((nread = std::fread(buf, 1, sizeof buf, f)) > 0) text.append(buf, nread);
+  std::fclose(f);
+  const std::string needle = "\"" + key + "\"";
+  const size_t at = text.find(needle);
+  if (at == std::string::npos) return false;
+  const size_t end = text.find('}', at);
+  const std::string entry = text.substr(at, end - at);
+  auto num = [&](const char* name, double* out) {
+    const size_t p = entry.find(std::string("\"") + name + "\"");
+    if (p == std::string::npos) return false;
+    const size_t colon = entry.find(':', p);
+    *out = std::strtod(entry.c_str() + colon + 1, nullptr);
+    return true;
+  };
+  double w, ce, tr, gr;
+  if (!num("omega", &w) || !num("check_every", &ce) || !num("tile_rows", &tr) || !num("graphs", &gr)) return false;
+  o->omega = w;
+  o->check_every = (int32_t)ce;
+  o->tile_rows = (int32_t)tr;
+  o->graphs = (int32_t)gr;
+  return true;
+}
+
+void cache_store(const char* path, const std::string& key, const pg_options& o, double seconds) {
+  if (!path) return;
+  std::string text;
+  if (FILE* f = std::fopen(path, "r")) {
+    char buf[4096];
+    size_t nread;
+    while ((nread = std::fread(buf, 1, sizeof buf, f)) > 0) text.append(buf, nread);
+    std::fclose(f);
+  }
+  char entry[512];
+  std::snprintf(entry, sizeof entry,
+                "\"%s\": {\"omega\": %.4f, \"check_every\": %d, \"tile_rows\": %d, \"graphs\": %d, \"seconds\": %.6f}",
+                key.c_str(), o.omega, o.check_every, o.tile_rows, o.graphs, seconds);
+  const std::string needle = "\"" + key + "\"";
+  const size_t at = text.find(needle);
+  if (at != std::string::npos) {
+    const size_t end = text.find('}', at);
+    text.replace(at, end + 1 - at, entry);
+  } else {
+    const size_t close = text.rfind('}');
+    if (close == std::string::npos || text.find('{') == std::string::npos) {
+      text = std::string("{\n  ") + entry + "\n}\n";
+    } else {
+      const bool empty = text.find('"') == std::string::npos;
+      text.insert(close, std::string(empty ? "  " : ",\n  ") + entry + "\n");
+    }
+  }
+  if (FILE* f = std::fopen(path, "w")) {
+    std::fwrite(text.data(), 1, text.size(), f);
+    std::fclose(f);
+  }
+}
+
+}  // namespace
+
+extern "C" pg_status pg_autotune(pg_ctx* c, int32_t nsteps, const char* cache_path, pg_options* chosen) {
+  if (!c || nsteps < 1) return PG_ERR_INVALID_ARG;
+  HIP_TRY(c, hipSetDevice(c->device));
+  PG_TRY(prepare(c));
+  const std::string key = tune_key(c);
+  pg_options best = c->opt;
+  if (cache_lookup(cache_path, key, &best)) {
+    PG_TRY(pg_set_options(c, &best));
+    if (chosen) *chosen = best;
+    return PG_OK;
+  }
+  Snapshot sn;
+  PG_TRY(take_snapshot(c, sn));
+  auto trial = [&](const pg_options& o, double* secs) -> pg_status {
+    PG_TRY(pg_set_options(c, &o));
+    PG_TRY(prepare(c));
+    PG_TRY(restore_snapshot(c, sn));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    const auto t0 = std::chrono::steady_clock::now();
+    pg_status st = PG_OK;
+    for (int k = 0; k < nsteps && st == PG_OK; ++k) st = one_step(c);
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    int32_t failed = 0;
+    HIP_TRY(c, hipMemcpy(&failed, c->ctl.stat_failed, sizeof failed, hipMemcpyDeviceToHost));
+    if (failed) HIP_TRY(c, hipMemset(c->ctl.stat_failed, 0, sizeof(int32_t)));
+    if (st != PG_OK && st != PG_ERR_NO_CONVERGENCE) return st;
+    *secs = (st == PG_OK && !failed) ? std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count()
+                                     : 1e30;
+    return PG_OK;
+  };
+  double best_t = 0.0;
+  PG_TRY(trial(best, &best_t));
+  const double omegas[] = {1.0, 1.2, 1.4, 1.5, 1.6, 1.7, 1.8, 1.85, 1.9, 1.95};
+  const int checks[] = {4, 8, 12, 16, 24};
+  const int rows[] = {4, 8, 16};
+  for (double w : omegas) {
+    pg_options o = best;
+    o.omega = w;
+    double t;
+    PG_TRY(trial(o, &t));
+    if (t < best_t) { best_t = t; best = o; }
+  }
+  for (int ce : checks) {
+    pg_options o = best;
+    o.check_every = ce;
+    double t;
+    PG_TRY(trial(o, &t));
+    if (t < best_t) { best_t = t; best = o; }
+  }
+  for (int r : rows) {
+    pg_options o = best;
+    o.tile_rows = r;
+    double t;
+    PG_TRY(trial(o, &t));
+    if (t < best_t) { best_t = t; best = o; }
+  }
+  for (int g = 0; g <= 1; ++g) {
+    pg_options o = best;
+    o.graphs = g;
+    double t;
+    PG_TRY(trial(o, &t));
+    if (t < best_t) { best_t = t; best = o; }
+  }
+  PG_TRY(pg_set_options(c, &best));
+  PG_TRY(prepare(c));
+  PG_TRY(restore_snapshot(c, sn));
+  if (best_t < 1e29) cache_store(cache_path, key, best, best_t);
+  if (chosen) *chosen = best;
+  return best_t < 1e29 ? PG_OK : set_err(c, PG_ERR_NO_CONVERGENCE, "no candidate converged");
+}

@@ -96,6 +96,10 @@ EXPORTS = {
     "pg_run_transient": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.c_int32,
                                    C.POINTER(C.c_double)]),
     "pg_get_time": (C.c_int, [C.c_void_p, C.POINTER(C.c_int64)]),
+    "pg_set_time": (C.c_int, [C.c_void_p, C.c_int64]),
+    "pg_num_grids": (C.c_int, [C.c_void_p, C.POINTER(C.c_int32)]),
+    "pg_grid_info": (C.c_int, [C.c_void_p, C.c_int32] + [C.POINTER(C.c_int32)] * 6),
+    "pg_autotune": (C.c_int, [C.c_void_p, C.c_int32, C.c_char_p, C.POINTER(Options)]),
     "pg_read_voltages": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.POINTER(C.c_double), C.c_int64]),
     "pg_read_voltages_dev": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_void_p, C.c_int64]),
     "pg_read_inductor_currents": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.POINTER(C.c_double), C.c_int64]),
@@ -294,6 +298,21 @@ class Context:
         self._check(lib().pg_run_transient(self._h, int(nsteps), int(record_every), grid, scen,
                                            _dp(out) if out.size else None))
         return out
+
+    def set_time_index(self, step: int):
+        self._check(lib().pg_set_time(self._h, int(step)))
+
+    def grid_info(self, grid: int = 0) -> dict:
+        vals = [C.c_int32() for _ in range(6)]
+        self._check(lib().pg_grid_info(self._h, grid, *[C.byref(v) for v in vals]))
+        return dict(zip(("nx", "ny", "nl", "n_scen", "n_vias", "n_pads"), (v.value for v in vals)))
+
+    def autotune(self, nsteps: int = 20, cache_path=None) -> dict:
+        """Time candidate settings over `nsteps` steps from the current state and keep the fastest."""
+        o = Options()
+        self._check(lib().pg_autotune(self._h, int(nsteps), cache_path.encode() if cache_path else None,
+                                      C.byref(o)))
+        return {f: getattr(o, f) for f, _ in Options._fields_ if f != "reserved"}
 
     def time_index(self) -> int:
         k = C.c_int64()

@@ -1,0 +1,117 @@
+"""Parity at the full workload sizes, in the launch configuration bench.py times (its tuned omega
+and sweeps per check, graph replay).  Where the oracle cannot factor the system quickly (the
+3-layer 1024x1024 mesh), the check is the backward-Euler residual of the GPU's consecutive states
+evaluated with the oracle's own assembly; elsewhere every node of every step (or of sampled
+scenarios / grids) is compared with the oracle's direct solution."""
+import numpy as np
+import pytest
+
+import paper_1409_7166_amd as pg
+from bench import TUNED
+from helpers import PARITY_V, gpu_context, oracle_run, say
+from oracle import BESystem, BEStepper, mesh_to_circuit, scaled_residual
+from oracle.sources import currents_at
+from oracle.transient import initial_state
+from workloads import config1, config2, config3a, config3b, config4
+
+pytestmark = pytest.mark.gpu
+
+
+def _opts(name, prec, tol):
+    t = TUNED[name]
+    return dict(precision=prec, tol=tol, omega=t["omega"], check_every=t["check_every"], graphs=1,
+                max_sweeps=200000)
+
+
+@pytest.mark.timeout(600)
+def test_config1_full_size_residual_of_every_sampled_step():
+    w = config1(steps=70)
+    mesh, p = w.meshes[0], w.pulses[0][0]
+    tol = 1e-9
+    say("[gpu] 3x1024x1024, 70 steps, residual property")
+    samples = {10, 25, 40, 55, 70}
+    got = {}
+    with gpu_context(w, **_opts("config1", pg.PG_PREC_FP32_REFINE, tol)) as ctx:
+        prev = ctx.read_voltages()
+        for k in range(1, 71):
+            ctx.step(1)
+            if k in samples:
+                got[k] = (prev, ctx.read_voltages())
+            if k + 1 in samples:
+                prev = ctx.read_voltages()
+        st = ctx.stats()
+    say(f"  sweeps/step {st['sweeps'] / 70:.1f}; assembling the oracle system ...")
+    circ, info = mesh_to_circuit(mesh, p)
+    sysm = BESystem(circ, w.h)
+    worst = 0.0
+    for k, (vp, vk) in sorted(got.items()):
+        res = scaled_residual(sysm, vp, np.zeros(0), vk, currents_at(p, k * w.h))
+        say(f"  step {k}: oracle-assembled scaled residual {res:.3e} V, max drop {1 - vk.min():.3e} V")
+        worst = max(worst, res)
+    assert worst <= 1.01 * tol
+    assert 1.0 - got[40][1].min() > 1e-3
+
+
+@pytest.mark.timeout(600)
+def test_config4_full_size_every_node_every_step():
+    w = config4(steps=40)
+    mesh, p = w.meshes[0], w.pulses[0][0]
+    say("[gpu] 1024x1024 FP64, 40 steps vs oracle")
+    with gpu_context(w, **_opts("config4", pg.PG_PREC_FP64, 1e-10)) as ctx:
+        V = ctx.run_transient(40)
+    Vref, _ = oracle_run(mesh, p, w.h, 40)
+    err = np.max(np.abs(V - Vref))
+    say(f"  max err {err:.3e} V, max drop {1 - Vref.min():.3e} V")
+    assert err <= PARITY_V
+
+
+@pytest.mark.timeout(600)
+def test_config2_full_size_rlc_first_100_steps():
+    w = config2(steps=100)
+    mesh, p = w.meshes[0], w.pulses[0][0]
+    say("[gpu] RLC 2x512x512, 100 steps vs oracle (voltages and inductor currents)")
+    circ, info = mesh_to_circuit(mesh, p)
+    st = BEStepper(circ, w.h)
+    v, il = initial_state(circ, info, mesh.vdd)
+    worst_v = worst_i = 0.0
+    with gpu_context(w, **_opts("config2", pg.PG_PREC_FP32_REFINE, 1e-11)) as ctx:
+        for k in range(1, 101):
+            v, il = st.step(v, il, currents_at(p, k * w.h))
+            ctx.step(1)
+            if k % 5 == 0 or k <= 5:
+                worst_v = max(worst_v, float(np.max(np.abs(ctx.read_voltages() - v[: mesh.n]))))
+                worst_i = max(worst_i, float(np.max(np.abs(ctx.read_inductor_currents() - il))))
+    say(f"  max err v {worst_v:.3e} V, i {worst_i:.3e} A, max |i| {np.max(np.abs(il)):.3e} A")
+    assert worst_v <= PARITY_V
+    assert worst_i <= 1e-6 * max(1.0, float(np.max(np.abs(il))))
+
+
+@pytest.mark.timeout(600)
+def test_config3a_full_batch_sampled_scenarios():
+    w = config3a(steps=60)
+    mesh = w.meshes[0]
+    say("[gpu] 256 scenarios x 256x256, 60 steps")
+    with gpu_context(w, **_opts("config3a", pg.PG_PREC_FP32_REFINE, 1e-10)) as ctx:
+        ctx.step(60)
+        picks = (0, 97, 200, 255)
+        got = {s: ctx.read_voltages(0, s) for s in picks}
+    for s in picks:
+        Vref, _ = oracle_run(mesh, w.pulses[0][s], w.h, 60)
+        err = np.max(np.abs(got[s] - Vref[-1]))
+        say(f"  scenario {s}: err {err:.3e} V")
+        assert err <= PARITY_V
+
+
+@pytest.mark.timeout(600)
+def test_config3b_full_batch_sampled_grids():
+    w = config3b(steps=60)
+    say("[gpu] 64 uneven grids, 60 steps")
+    with gpu_context(w, **_opts("config3b", pg.PG_PREC_FP32_REFINE, 1e-10)) as ctx:
+        ctx.step(60)
+        picks = (0, 21, 42, 63)
+        got = {g: ctx.read_voltages(g, 0) for g in picks}
+    for g in picks:
+        Vref, _ = oracle_run(w.meshes[g], w.pulses[g][0], w.h, 60)
+        err = np.max(np.abs(got[g] - Vref[-1]))
+        say(f"  grid {g} ({w.meshes[g].nx}^2): err {err:.3e} V")
+        assert err <= PARITY_V

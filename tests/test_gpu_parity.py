@@ -210,3 +210,27 @@ def test_graph_replay_matches_eager_every_step(case):
     assert np.array_equal(out[0][0], out[1][0])
     assert out[0][1]["sweeps"] == out[1][1]["sweeps"]
     assert out[0][1]["node_updates"] == out[1][1]["node_updates"]
+
+
+def test_autotune_restores_state_and_caches(tmp_path):
+    w = small_multilayer(side=96, seed=81, nl=2, pad_every=32, steps=20)
+    w.pulses[0][0] = compressed(w.pulses[0][0], start=0.05, width=1.0)
+    cache = str(tmp_path / "tune.json")
+    say("[gpu] autotune")
+    with gpu_context(w, precision=pg.PG_PREC_FP32_REFINE, tol=1e-10, omega=1.0) as ctx:
+        ctx.step(5)
+        v5 = ctx.read_voltages()
+        chosen = ctx.autotune(4, cache)
+        assert ctx.time_index() == 5
+        assert np.array_equal(ctx.read_voltages(), v5)
+        assert 0 < chosen["omega"] < 2 and chosen["check_every"] >= 1 and chosen["tile_rows"] in (4, 8, 16)
+        ctx.step(15)
+        V = ctx.read_voltages()
+    import json
+    entry = list(json.load(open(cache)).values())[0]
+    assert entry["omega"] == pytest.approx(chosen["omega"])
+    Vref, _ = oracle_run(w.meshes[0], w.pulses[0][0], w.h, 20)
+    assert np.max(np.abs(V - Vref[-1])) <= PARITY_V
+    with gpu_context(w, precision=pg.PG_PREC_FP32_REFINE, tol=1e-10, omega=1.0) as ctx:
+        again = ctx.autotune(4, cache)
+    assert again["omega"] == pytest.approx(chosen["omega"]) and again["check_every"] == chosen["check_every"]

@@ -237,3 +237,21 @@ def test_incidence_matches_definition():
         for j in range(2):
             want = (1 if circ.frm[e] == 3 + j else 0) - (1 if circ.to[e] == 3 + j else 0)
             assert As[e, j] == want
+
+
+def test_scaled_residual_of_exact_step_is_roundoff_and_detects_error():
+    """The assembled-system residual (no factorisation) vanishes on the direct solution and
+    equals |delta| * M_ii / M_ii = |delta| for a perturbation of one node by delta."""
+    from oracle import BESystem, scaled_residual
+    w = small_multilayer(side=12, seed=8, nl=3, via_every=4, pad_every=6, steps=3)
+    mesh, p = w.meshes[0], w.pulses[0][0]
+    circ, info = mesh_to_circuit(mesh, p)
+    st = BEStepper(circ, w.h)
+    v0 = np.full(circ.n, mesh.vdd)
+    I1 = currents_at(p, w.h)
+    v1, _ = st.step(v0, np.zeros(0), I1)
+    sysm = BESystem(circ, w.h)
+    assert scaled_residual(sysm, v0, np.zeros(0), v1, I1) < 1e-14
+    v1b = v1.copy()
+    v1b[7] += 1e-6
+    assert abs(scaled_residual(sysm, v0, np.zeros(0), v1b, I1) - 1e-6) < 1e-12
