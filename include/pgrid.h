@@ -74,7 +74,9 @@ typedef struct pg_options {
   int32_t tile_rows;    /* rows per 128-node-wide sweep tile: 4, 8 or 16 (0 = library default, 8) */
   int32_t lookahead;    /* refinement cycles queued ahead of the host's convergence check, 0..4 */
   int32_t graphs;       /* 1: replay each step's launches from captured HIP graphs; 0: launch one by one */
-  int32_t reserved[5];  /* must be zero */
+  int32_t scen_block;   /* scenarios per sweep/residual workgroup on grids that carry several
+                           scenarios (coefficients are loaded once per block): 1..16 (0 = 8) */
+  int32_t reserved[4];  /* must be zero */
 } pg_options;
 
 /* A layered RC/RLC mesh (the representative node of Fig. 2 repeated on a grid).
@@ -109,14 +111,17 @@ typedef struct pg_stats {
 
 /* Kernel timing gathered with HIP events on the context stream while profiling is on
  * (pg_profile(ctx, k): every k-th block of back-to-back sweep launches of a refinement cycle is
- * timed as one interval; residual and other launches are timed one by one).  Launches queued
- * after a step had converged (which exit at once) are left out.
- * *_bytes are algorithmic bytes of the timed launches: every array the kernel needs read once
+ * timed as one interval; the residual passes over all tile groups, and other launches, are
+ * timed one interval each).  Launches queued after a step had converged (which exit at once)
+ * are left out.
+ * *_bytes are algorithmic bytes of the timed launches, charged for the (grid, scenario) items
+ * that were still iterating (the rest exit at once): every array the kernel needs read once
  * and every array it produces written once, with e = 4 (FP32 sweeps) or 8 (FP64) bytes.  Per
- * node and scenario: sweep e * (r + d_new [+ d_old unless it starts from zero]), residual
- * 8 * (v + b) + e * r [+ e * d + 8 * v_out]; per mesh node (coefficients are shared by the
- * scenarios of a grid): sweep e * (gE + gN + invD) + e * (nl-1)/nl (vias exist below the top
- * layer only), residual 8 * (D + gE + gN) + 8 * (nl-1)/nl. */
+ * active node and scenario: sweep e * (r + d_new [+ d_old unless it starts from zero]),
+ * residual 8 * (v + b) + e * r [+ e * d + 8 * v_out]; per mesh node of a grid with an active
+ * scenario (coefficients are shared by the scenarios of a grid): sweep e * (gE + gN + invD)
+ * + e * (nl-1)/nl (vias exist below the top layer only), residual 8 * (D + gE + gN)
+ * + 8 * (nl-1)/nl. */
 typedef struct pg_kernel_times {
   int64_t sweep_launches;  double sweep_ms;      int64_t sweep_node_updates;  double sweep_bytes;
   int64_t resid_launches;  double resid_ms;      int64_t resid_nodes;         double resid_bytes;
@@ -128,7 +133,7 @@ int32_t pg_abi_version(void);
 const char* pg_status_name(int32_t status);
 
 /* Fill *out with the defaults: h = 10 ps, tol = 1e-6 V, omega = 1, max_sweeps = 10000,
- * check_every = 8, FP64, red-black, tile_rows = 8, lookahead = 1, graphs = 0. */
+ * check_every = 8, FP64, red-black, tile_rows = 8, lookahead = 1, graphs = 0, scen_block = 8. */
 pg_status pg_default_options(pg_options* out);
 
 /* Host-only checks (no device needed).  msg (may be NULL) receives a description of the

@@ -64,18 +64,17 @@ struct NodeCoef {
   T e, w, n, s, u, d, inv, r;
 };
 
-// Load the pair's coefficients and return those of element `e` (0: even node, 1: odd node);
-// `other` receives the partner's.  Conductances beyond the mesh are stored as zero, so only
-// the array bounds are guarded.
+// Load the pair's coefficients without the right-hand side and return those of element `e`
+// (0: even node, 1: odd node); `other` receives the partner's.  Conductances beyond the mesh
+// are stored as zero, so only the array bounds are guarded.
 template <typename T, int NL>
-__device__ __forceinline__ void load_pair(const GridDesc& G, const T* __restrict__ gE,
-                                          const T* __restrict__ gN, const T* __restrict__ gU,
-                                          const T* __restrict__ invD, const T* __restrict__ r,
-                                          int l, int y, int x, int e, NodeCoef<T>& mine,
-                                          NodeCoef<T>& other) {
+__device__ __forceinline__ void load_pair_coef(const GridDesc& G, const T* __restrict__ gE,
+                                               const T* __restrict__ gN, const T* __restrict__ gU,
+                                               const T* __restrict__ invD, int l, int y, int x, int e,
+                                               NodeCoef<T>& mine, NodeCoef<T>& other) {
   const int64_t P = (int64_t)G.X * G.ny;
   const int64_t i = l * P + (int64_t)y * G.X + x;
-  const V2<T> ge = ld2(gE, i), gn = ld2(gN, i), iv = ld2(invD, i), rr = ld2(r, i);
+  const V2<T> ge = ld2(gE, i), gn = ld2(gN, i), iv = ld2(invD, i);
   const V2<T> gs = y > 0 ? ld2(gN, i - G.X) : zero2<T>();
   const T gw = x > 0 ? gE[i - 1] : T(0);
   V2<T> gu = zero2<T>(), gd = zero2<T>();
@@ -84,10 +83,23 @@ __device__ __forceinline__ void load_pair(const GridDesc& G, const T* __restrict
     if (l > 0) gd = ld2(gU, i - P);
   }
   // element 0: west edge is gE[x-1]; element 1: west edge is element 0's east edge
-  NodeCoef<T> c0{ge.x, gw, gn.x, gs.x, gu.x, gd.x, iv.x, rr.x};
-  NodeCoef<T> c1{ge.y, ge.x, gn.y, gs.y, gu.y, gd.y, iv.y, rr.y};
+  NodeCoef<T> c0{ge.x, gw, gn.x, gs.x, gu.x, gd.x, iv.x, T(0)};
+  NodeCoef<T> c1{ge.y, ge.x, gn.y, gs.y, gu.y, gd.y, iv.y, T(0)};
   mine = e ? c1 : c0;
   other = e ? c0 : c1;
+}
+
+// load_pair_coef plus the pair's right-hand side r.
+template <typename T, int NL>
+__device__ __forceinline__ void load_pair(const GridDesc& G, const T* __restrict__ gE,
+                                          const T* __restrict__ gN, const T* __restrict__ gU,
+                                          const T* __restrict__ invD, const T* __restrict__ r,
+                                          int l, int y, int x, int e, NodeCoef<T>& mine,
+                                          NodeCoef<T>& other) {
+  load_pair_coef<T, NL>(G, gE, gN, gU, invD, l, y, x, e, mine, other);
+  const V2<T> rr = ld2(r, l * (int64_t)G.X * G.ny + (int64_t)y * G.X + x);
+  mine.r = pick(rr, e);
+  other.r = pick(rr, 1 - e);
 }
 
 // SOR update of element e of the staged pair (l, hy, hp) from its staged neighbours.
@@ -144,10 +156,12 @@ __global__ void k_step_begin(Ctl c, int I, int only_item, double h, SourceTable 
   }
 }
 
-__global__ void k_decide(Ctl c, int I, double tol, int has_d, int nchk, int max_sweeps, int nslots) {
+__global__ void k_decide(Ctl c, int I, const GridDesc* __restrict__ grids, int G, double tol, int has_d, int nchk,
+                         int max_sweeps, int nslots) {
   __shared__ int any;
   __shared__ int worked;
-  if (threadIdx.x == 0) { any = 0; worked = 0; }
+  __shared__ unsigned long long act_nodes, act_coef;
+  if (threadIdx.x == 0) { any = 0; worked = 0; act_nodes = 0ull; act_coef = 0ull; }
   __syncthreads();
   for (int g = threadIdx.x; g < I; g += blockDim.x) {
     if (c.active[g]) {
@@ -168,9 +182,24 @@ __global__ void k_decide(Ctl c, int I, double tol, int has_d, int nchk, int max_
     c.norm_bits[g] = 0ull;
   }
   __syncthreads();
+  // the work the next sweeps will do: active scenarios, and the coefficients of their grids
+  for (int gi = threadIdx.x; gi < G; gi += blockDim.x) {
+    const GridDesc& D = grids[gi];
+    int cnt = 0;
+    for (int sc = 0; sc < D.S; ++sc) cnt += c.active[D.item0 + sc];
+    if (cnt) {
+      const unsigned long long plane = (unsigned long long)D.nx * D.ny, n = plane * D.nl;
+      atomicAdd(&act_nodes, n * cnt);
+      atomicAdd(&act_coef, 3ull * n + plane * (D.nl - 1));
+    }
+  }
+  __syncthreads();
   if (threadIdx.x == 0) {
     const int seq = c.flag_seq[0];
     c.flag_seq[0] = seq + 1;
+    c.acct[2 * (seq % nslots)] = (long long)act_nodes;
+    c.acct[2 * (seq % nslots) + 1] = (long long)act_coef;
+    __threadfence_system();
     c.any_active[seq % nslots] = any;
     if (worked) c.stat_checks[0] += 1;
   }
@@ -465,6 +494,231 @@ __global__ __launch_bounds__(64 * TY) void k_sweep_rb(const Tile* __restrict__ t
   }
 }
 
+// ------------------------------------------------------------------------------------
+// Scenario blocks: the tiles of a grid that carries several current scenarios cover
+// tl.pad consecutive scenarios.  The workgroup loads the tile's coefficients (shared by the
+// scenarios) once and then, scenario by scenario, streams only that scenario's r and d (and,
+// in the residual, v and b), so coefficient traffic is divided by the block size.
+// ------------------------------------------------------------------------------------
+template <typename T, int NL, int TY>
+__global__ __launch_bounds__(64 * TY) void k_sweep_rb_multi(const Tile* __restrict__ tiles, int ntiles,
+                                                           const GridDesc* __restrict__ grids, Ctl c,
+                                                           int din, int zero_in, T omega) {
+  constexpr int NP = kTileX / 2, HP = NP + 2, HY = TY + 4, NT = 64 * TY;
+  constexpr int NRING = 2 * NP + 2 * TY;
+  constexpr int RT = (NL * NRING + NT - 1) / NT;  // ring tasks per thread
+  __shared__ V2<T> sd[NL][HY][HP];
+  const int ti = xcd_tile(ntiles);
+  if (ti < 0) return;
+  const Tile tl = tiles[ti];
+  const GridDesc& G = grids[tl.grid];
+  const int ny = G.ny, X = G.X;
+  const int64_t P = (int64_t)X * ny;
+  const int x0 = tl.x0, y0 = tl.y0;
+  const T* __restrict__ gE = static_cast<const T*>(G.gEs);
+  const T* __restrict__ gN = static_cast<const T*>(G.gNs);
+  const T* __restrict__ gU = static_cast<const T*>(G.gUs);
+  const T* __restrict__ invD = static_cast<const T*>(G.invDs);
+  const int lane = threadIdx.x & 63, row = threadIdx.x >> 6;
+  const int x = x0 + 2 * lane, y = y0 + row;
+  const int hp = lane + 1, hy = row + 2;
+  const bool mine = x < X && y < ny;
+
+  // the owned pair on every layer (red node and black partner)
+  NodeCoef<T> kr[NL], kb[NL];
+  if (mine) {
+#pragma unroll
+    for (int l = 0; l < NL; ++l) load_pair_coef<T, NL>(G, gE, gN, gU, invD, l, y, x, (y + l) & 1, kr[l], kb[l]);
+  }
+  // this thread's ring tasks (red ring nodes around the tile)
+  NodeCoef<T> kring[RT];
+  int ring_l[RT], ring_hy[RT], ring_hp[RT], ring_e[RT];
+  int64_t ring_i[RT];
+#pragma unroll
+  for (int t = 0; t < RT; ++t) {
+    ring_e[t] = -1;
+    const int k = threadIdx.x + t * NT;
+    if (k >= NL * NRING) continue;
+    const int l = k / NRING;
+    const int q = k - l * NRING;
+    int rhy, rhp, want;
+    if (q < 2 * NP) {
+      rhy = q < NP ? 1 : TY + 2;
+      rhp = 1 + (q < NP ? q : q - NP);
+      want = -1;
+    } else {
+      const int q2 = q - 2 * NP;
+      rhy = 2 + (q2 < TY ? q2 : q2 - TY);
+      rhp = q2 < TY ? 0 : NP + 1;
+      want = q2 < TY ? 1 : 0;
+    }
+    const int gx = x0 - 2 + 2 * rhp, gy = y0 - 2 + rhy;
+    if (gx < 0 || gx >= X || gy < 0 || gy >= ny) continue;
+    const int er = (gy + l) & 1;
+    if (want >= 0 && er != want) continue;
+    NodeCoef<T> unused;
+    load_pair_coef<T, NL>(G, gE, gN, gU, invD, l, gy, gx, er, kring[t], unused);
+    ring_l[t] = l;
+    ring_hy[t] = rhy;
+    ring_hp[t] = rhp;
+    ring_e[t] = er;
+    ring_i[t] = l * P + (int64_t)gy * X + gx + er;
+  }
+
+  for (int sc = 0; sc < tl.pad; ++sc) {
+    if (!c.active[tl.item + sc]) continue;  // uniform across the block
+    const int64_t off = (int64_t)(tl.scen + sc) * G.nstore;
+    const T* __restrict__ dold = static_cast<const T*>(G.d[din]) + off;
+    T* __restrict__ dnew = static_cast<T*>(G.d[din ^ 1]) + off;
+    const T* __restrict__ r = static_cast<const T*>(G.r) + off;
+    __syncthreads();  // the previous scenario's readers are done with sd
+    for (int k = threadIdx.x; k < NL * HY * HP; k += NT) {
+      const int l = k / (HY * HP);
+      const int rem = k - l * (HY * HP);
+      const int shy = rem / HP, shp = rem - shy * HP;
+      const int sx = x0 - 2 + 2 * shp, sy = y0 - 2 + shy;
+      V2<T> val = zero2<T>();
+      if (!zero_in && sx >= 0 && sx < X && sy >= 0 && sy < ny) val = ld2(dold, l * P + (int64_t)sy * X + sx);
+      sd[l][shy][shp] = val;
+    }
+    __syncthreads();
+    if (mine) {
+#pragma unroll
+      for (int l = 0; l < NL; ++l) {
+        const int er = (y + l) & 1;
+        const V2<T> rr = ld2(r, l * P + (int64_t)y * X + x);
+        kr[l].r = pick(rr, er);
+        kb[l].r = pick(rr, 1 - er);
+        const T nv = relax<T, NL, HY, HP>(sd, l, hy, hp, er, kr[l], omega);
+        put(sd[l][hy][hp], er, nv);
+      }
+    }
+#pragma unroll
+    for (int t = 0; t < RT; ++t) {
+      if (ring_e[t] < 0) continue;
+      kring[t].r = r[ring_i[t]];
+      const T nv = relax<T, NL, HY, HP>(sd, ring_l[t], ring_hy[t], ring_hp[t], ring_e[t], kring[t], omega);
+      put(sd[ring_l[t]][ring_hy[t]][ring_hp[t]], ring_e[t], nv);
+    }
+    __syncthreads();
+    if (mine) {
+#pragma unroll
+      for (int l = 0; l < NL; ++l) {
+        const int eb = 1 - ((y + l) & 1);
+        V2<T> out = sd[l][hy][hp];
+        const T nv = relax<T, NL, HY, HP>(sd, l, hy, hp, eb, kb[l], omega);
+        put(out, eb, nv);
+        st2(dnew, l * P + (int64_t)y * X + x, out);
+      }
+    }
+  }
+}
+
+// FP64 residual over a scenario block (see k_resid): coefficients once, v, d, b per scenario.
+template <typename T, int NL, int TY>
+__global__ __launch_bounds__(64 * TY) void k_resid_multi(const Tile* __restrict__ tiles, int ntiles,
+                                                        const GridDesc* __restrict__ grids, Ctl c,
+                                                        int has_d, int din) {
+  constexpr int NP = kTileX / 2, HP = NP + 2, HY = TY + 2, NT = 64 * TY;
+  __shared__ double2 sv[NL][HY][HP];
+  __shared__ double wmax[NT / 64];
+  const int ti = xcd_tile(ntiles);
+  if (ti < 0) return;
+  const Tile tl = tiles[ti];
+  const GridDesc& G = grids[tl.grid];
+  const int nx = G.nx, ny = G.ny, X = G.X;
+  const int64_t P = (int64_t)X * ny;
+  const int x0 = tl.x0, y0 = tl.y0;
+  const int lane = threadIdx.x & 63, row = threadIdx.x >> 6;
+  const int x = x0 + 2 * lane, y = y0 + row;
+  const int hp = lane + 1, hy = row + 1;
+  const bool mine = x < X && y < ny;
+  double2 D2[NL], ge[NL], gn[NL], gs[NL], gu[NL], gd[NL];
+  double gw[NL];
+#pragma unroll
+  for (int l = 0; l < NL; ++l) {
+    D2[l] = ge[l] = gn[l] = gs[l] = gu[l] = gd[l] = make_double2(0.0, 0.0);
+    gw[l] = 0.0;
+    if (!mine) continue;
+    const int64_t i = l * P + (int64_t)y * X + x;
+    D2[l] = ld2(G.D64, i);
+    ge[l] = ld2(G.gE64, i);
+    gn[l] = ld2(G.gN64, i);
+    if (y > 0) gs[l] = ld2(G.gN64, i - X);
+    if (x > 0) gw[l] = G.gE64[i - 1];
+    if (NL > 1) {
+      if (l < NL - 1) gu[l] = ld2(G.gU64, i);
+      if (l > 0) gd[l] = ld2(G.gU64, i - P);
+    }
+  }
+  for (int sc = 0; sc < tl.pad; ++sc) {
+    const int item = tl.item + sc;
+    if (!c.active[item]) continue;  // uniform across the block
+    const int64_t off = (int64_t)(tl.scen + sc) * G.nstore;
+    const int vi = c.vidx[item];
+    const double* __restrict__ v = G.v[vi] + off;
+    const T* __restrict__ d = static_cast<const T*>(G.d[din]) + off;
+    __syncthreads();
+    for (int k = threadIdx.x; k < NL * HY * HP; k += NT) {
+      const int l = k / (HY * HP);
+      const int rem = k - l * (HY * HP);
+      const int shy = rem / HP, shp = rem - shy * HP;
+      const int sx = x0 - 2 + 2 * shp, sy = y0 - 1 + shy;
+      double2 val = make_double2(0.0, 0.0);
+      if (sx >= 0 && sx < X && sy >= 0 && sy < ny) {
+        const int64_t i = l * P + (int64_t)sy * X + sx;
+        val = ld2(v, i);
+        if (has_d) {
+          const V2<T> dd = ld2(d, i);
+          val.x += (double)dd.x;
+          val.y += (double)dd.y;
+        }
+      }
+      sv[l][shy][shp] = val;
+    }
+    __syncthreads();
+    double m = 0.0;
+    if (mine) {
+      double* __restrict__ vout = G.v[vi ^ 1] + off;
+      T* __restrict__ r = static_cast<T*>(G.r) + off;
+      const double* __restrict__ bvec = G.b + off;
+#pragma unroll
+      for (int l = 0; l < NL; ++l) {
+        const int64_t i = l * P + (int64_t)y * X + x;
+        const double2 b2 = ld2(bvec, i);
+        const double2 own = sv[l][hy][hp], eastp = sv[l][hy][hp + 1], westp = sv[l][hy][hp - 1];
+        const double2 nth = sv[l][hy + 1][hp], sth = sv[l][hy - 1][hp];
+        double2 up = make_double2(0.0, 0.0), dn = make_double2(0.0, 0.0);
+        if (NL > 1) {
+          if (l < NL - 1) up = sv[l + 1][hy][hp];
+          if (l > 0) dn = sv[l - 1][hy][hp];
+        }
+        double r0 = b2.x - D2[l].x * own.x + ge[l].x * own.y + gw[l] * westp.y + gn[l].x * nth.x +
+                    gs[l].x * sth.x + gu[l].x * up.x + gd[l].x * dn.x;
+        double r1 = b2.y - D2[l].y * own.y + ge[l].y * eastp.x + ge[l].x * own.x + gn[l].y * nth.y +
+                    gs[l].y * sth.y + gu[l].y * up.y + gd[l].y * dn.y;
+        if (x >= nx) r0 = 0.0;
+        if (x + 1 >= nx) r1 = 0.0;
+        if (has_d) st2(vout, i, own);
+        V2<T> rr;
+        rr.x = (T)r0;
+        rr.y = (T)r1;
+        st2(r, i, rr);
+        if (x < nx) m = nan_max(m, fabs(r0) / D2[l].x);
+        if (x + 1 < nx) m = nan_max(m, fabs(r1) / D2[l].y);
+      }
+    }
+    for (int o = 32; o > 0; o >>= 1) m = nan_max(m, __shfl_xor(m, o, 64));
+    if (lane == 0) wmax[row] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double bm = wmax[0];
+      for (int w = 1; w < NT / 64; ++w) bm = nan_max(bm, wmax[w]);
+      atomicMax(&c.norm_bits[item], (unsigned long long)__double_as_longlong(bm));
+    }
+  }
+}
+
 // Weighted Jacobi sweep: every node from the previous sweep's values (element-wise).
 template <typename T, int NL>
 __global__ __launch_bounds__(kThreads) void k_sweep_jacobi(const Tile* __restrict__ tiles, int ntiles,
@@ -473,38 +727,40 @@ __global__ __launch_bounds__(kThreads) void k_sweep_jacobi(const Tile* __restric
   const int ti = xcd_tile(ntiles);
   if (ti < 0) return;
   const Tile tl = tiles[ti];
-  if (!c.active[tl.item]) return;
   const GridDesc& G = grids[tl.grid];
   const int ny = G.ny, X = G.X;
   const int64_t P = (int64_t)X * ny;
-  const int64_t off = (int64_t)tl.scen * G.nstore;
-  const T* __restrict__ dold = static_cast<const T*>(G.d[din]) + off;
-  T* __restrict__ dnew = static_cast<T*>(G.d[din ^ 1]) + off;
   const T* __restrict__ gE = static_cast<const T*>(G.gEs);
   const T* __restrict__ gN = static_cast<const T*>(G.gNs);
   const T* __restrict__ gU = static_cast<const T*>(G.gUs);
   const T* __restrict__ invD = static_cast<const T*>(G.invDs);
-  const T* __restrict__ r = static_cast<const T*>(G.r) + off;
-  for (int k = threadIdx.x; k < NL * TY * kTileX; k += kThreads) {
-    const int l = k / (TY * kTileX);
-    const int rem = k - l * (TY * kTileX);
-    const int yy = rem / kTileX, xx = rem - yy * kTileX;
-    const int x = tl.x0 + xx, y = tl.y0 + yy;
-    if (x >= X || y >= ny) continue;
-    const int64_t i = l * P + (int64_t)y * X + x;
-    T acc = r[i];
-    if (!zero_in) {
-      if (x + 1 < X) acc += gE[i] * dold[i + 1];
-      if (x > 0) acc += gE[i - 1] * dold[i - 1];
-      if (y + 1 < ny) acc += gN[i] * dold[i + X];
-      if (y > 0) acc += gN[i - X] * dold[i - X];
-      if (NL > 1) {
-        if (l < NL - 1) acc += gU[i] * dold[i + P];
-        if (l > 0) acc += gU[i - P] * dold[i - P];
+  for (int sc = 0; sc < tl.pad; ++sc) {  // the scenarios of a scenario block
+    if (!c.active[tl.item + sc]) continue;
+    const int64_t off = (int64_t)(tl.scen + sc) * G.nstore;
+    const T* __restrict__ dold = static_cast<const T*>(G.d[din]) + off;
+    T* __restrict__ dnew = static_cast<T*>(G.d[din ^ 1]) + off;
+    const T* __restrict__ r = static_cast<const T*>(G.r) + off;
+    for (int k = threadIdx.x; k < NL * TY * kTileX; k += kThreads) {
+      const int l = k / (TY * kTileX);
+      const int rem = k - l * (TY * kTileX);
+      const int yy = rem / kTileX, xx = rem - yy * kTileX;
+      const int x = tl.x0 + xx, y = tl.y0 + yy;
+      if (x >= X || y >= ny) continue;
+      const int64_t i = l * P + (int64_t)y * X + x;
+      T acc = r[i];
+      if (!zero_in) {
+        if (x + 1 < X) acc += gE[i] * dold[i + 1];
+        if (x > 0) acc += gE[i - 1] * dold[i - 1];
+        if (y + 1 < ny) acc += gN[i] * dold[i + X];
+        if (y > 0) acc += gN[i - X] * dold[i - X];
+        if (NL > 1) {
+          if (l < NL - 1) acc += gU[i] * dold[i + P];
+          if (l > 0) acc += gU[i - P] * dold[i - P];
+        }
       }
+      const T old = zero_in ? T(0) : dold[i];
+      dnew[i] = old + omega * (invD[i] * acc - old);
     }
-    const T old = zero_in ? T(0) : dold[i];
-    dnew[i] = old + omega * (invD[i] * acc - old);
   }
 }
 
@@ -656,9 +912,9 @@ hipError_t launch_step_begin(const Ctl& c, int I, int only_item, double h, const
   return hipGetLastError();
 }
 
-hipError_t launch_decide(const Ctl& c, int I, double tol, int has_d, int nchk, int max_sweeps, int nslots,
-                         hipStream_t s) {
-  hipLaunchKernelGGL(k_decide, dim3(1), dim3(256), 0, s, c, I, tol, has_d, nchk, max_sweeps, nslots);
+hipError_t launch_decide(const Ctl& c, int I, const GridDesc* grids, int G, double tol, int has_d, int nchk,
+                         int max_sweeps, int nslots, hipStream_t s) {
+  hipLaunchKernelGGL(k_decide, dim3(1), dim3(256), 0, s, c, I, grids, G, tol, has_d, nchk, max_sweeps, nslots);
   return hipGetLastError();
 }
 
@@ -759,18 +1015,25 @@ hipError_t launch_adj_grad(const Tile* tiles, int ntiles, int tile_rows, const G
 }
 
 template <typename T, int NL, int TY>
-static void resid_t(const Tile* tiles, int ntiles, const GridDesc* grids, const Ctl& c, int has_d,
+static void resid_t(bool multi, const Tile* tiles, int ntiles, const GridDesc* grids, const Ctl& c, int has_d,
                     int din, hipStream_t s) {
-  hipLaunchKernelGGL((k_resid<T, NL, TY>), dim3(xcd_blocks(ntiles)), dim3(64 * TY), 0, s, tiles,
-                     ntiles, grids, c, has_d, din);
+  if (multi)
+    hipLaunchKernelGGL((k_resid_multi<T, NL, TY>), dim3(xcd_blocks(ntiles)), dim3(64 * TY), 0, s, tiles,
+                       ntiles, grids, c, has_d, din);
+  else
+    hipLaunchKernelGGL((k_resid<T, NL, TY>), dim3(xcd_blocks(ntiles)), dim3(64 * TY), 0, s, tiles,
+                       ntiles, grids, c, has_d, din);
 }
 
 template <typename T, int NL, int TY>
-static void sweep_t(int ordering, const Tile* tiles, int ntiles, const GridDesc* grids, const Ctl& c,
+static void sweep_t(bool multi, int ordering, const Tile* tiles, int ntiles, const GridDesc* grids, const Ctl& c,
                     int din, int zero_in, double omega, hipStream_t s) {
-  if (ordering == 1)
+  if (ordering == 1)  // element-wise; loops over the scenarios of a block itself
     hipLaunchKernelGGL((k_sweep_jacobi<T, NL>), dim3(xcd_blocks(ntiles)), dim3(kThreads), 0, s,
                        tiles, ntiles, TY, grids, c, din, zero_in, (T)omega);
+  else if (multi)
+    hipLaunchKernelGGL((k_sweep_rb_multi<T, NL, TY>), dim3(xcd_blocks(ntiles)), dim3(64 * TY), 0, s,
+                       tiles, ntiles, grids, c, din, zero_in, (T)omega);
   else
     hipLaunchKernelGGL((k_sweep_rb<T, NL, TY>), dim3(xcd_blocks(ntiles)), dim3(64 * TY), 0, s,
                        tiles, ntiles, grids, c, din, zero_in, (T)omega);
@@ -793,25 +1056,25 @@ static void sweep_t(int ordering, const Tile* tiles, int ntiles, const GridDesc*
     default: return hipErrorInvalidValue;                               \
   }
 
-hipError_t launch_resid(bool fp32, int nl, int tile_rows, const Tile* tiles, int ntiles,
+hipError_t launch_resid(bool fp32, bool multi, int nl, int tile_rows, const Tile* tiles, int ntiles,
                         const GridDesc* grids, const Ctl& c, int has_d, int din, hipStream_t s) {
   if (ntiles <= 0) return hipSuccess;
   if (fp32) {
-    PG_DISPATCH_NL_TY(resid_t, float, tiles, ntiles, grids, c, has_d, din, s)
+    PG_DISPATCH_NL_TY(resid_t, float, multi, tiles, ntiles, grids, c, has_d, din, s)
   } else {
-    PG_DISPATCH_NL_TY(resid_t, double, tiles, ntiles, grids, c, has_d, din, s)
+    PG_DISPATCH_NL_TY(resid_t, double, multi, tiles, ntiles, grids, c, has_d, din, s)
   }
   return hipGetLastError();
 }
 
-hipError_t launch_sweep(bool fp32, int ordering, int nl, int tile_rows, const Tile* tiles, int ntiles,
-                        const GridDesc* grids, const Ctl& c, int din, int zero_in, double omega,
+hipError_t launch_sweep(bool fp32, bool multi, int ordering, int nl, int tile_rows, const Tile* tiles,
+                        int ntiles, const GridDesc* grids, const Ctl& c, int din, int zero_in, double omega,
                         hipStream_t s) {
   if (ntiles <= 0) return hipSuccess;
   if (fp32) {
-    PG_DISPATCH_NL_TY(sweep_t, float, ordering, tiles, ntiles, grids, c, din, zero_in, omega, s)
+    PG_DISPATCH_NL_TY(sweep_t, float, multi, ordering, tiles, ntiles, grids, c, din, zero_in, omega, s)
   } else {
-    PG_DISPATCH_NL_TY(sweep_t, double, ordering, tiles, ntiles, grids, c, din, zero_in, omega, s)
+    PG_DISPATCH_NL_TY(sweep_t, double, multi, ordering, tiles, ntiles, grids, c, din, zero_in, omega, s)
   }
   return hipGetLastError();
 }

@@ -8,6 +8,7 @@ namespace pgrid {
 
 constexpr int kTileX = 128;       // nodes per tile row: 64 lanes x one node pair
 constexpr int kThreads = 256;     // threads per workgroup of the element-wise kernels
+constexpr int kScenBlock = 8;     // scenarios per sweep/residual workgroup on multi-scenario grids
 constexpr int kPitchAlign = 4;    // row pitch multiple (keeps pair and quad accesses aligned)
 
 // Per-grid device descriptor.  Every per-node array is stored with a row pitch X >= nx
@@ -50,14 +51,16 @@ struct GridDesc {
   double vdd;
 };
 
-// One 128 x rows tile of one scenario of one grid (all layers).
+// One 128 x rows tile of one grid (all layers) for scenario `scen`, or, in the scenario-block
+// lists used by the sweeps and residuals of multi-scenario grids, for scenarios
+// scen .. scen + pad - 1 (items item .. item + pad - 1).
 struct Tile {
   int32_t grid;
   int32_t item;                    // control-block item (grid, scenario)
   int32_t scen;
   int32_t x0;
   int32_t y0;
-  int32_t pad;
+  int32_t pad;                     // scenarios in the block (1 outside scenario-block lists)
 };
 
 // Flattened current sources of every grid and scenario: first the n_always sources that are
@@ -88,6 +91,10 @@ struct Ctl {
   int32_t* step_sweeps;            // [I]
   int32_t* failed;                 // [I]
   int32_t* any_active;             // [nslots] host-visible flags, one per outstanding decision
+  // [nslots][2] host-visible, beside each flag: the items left active by the decision, as
+  // mesh nodes x scenarios (state words per sweep) and as the coefficient words of the grids
+  // with at least one active item (each read once per sweep)
+  long long* acct;
   // running statistics, updated once per step on the device
   long long* stat_sweeps;          // [1]
   long long* stat_updates;         // [1]
@@ -112,13 +119,14 @@ hipError_t launch_step_begin(const Ctl& c, int G, int only_item, double h, const
 hipError_t launch_rhs(const Tile* tiles, int ntiles, int tile_rows, const GridDesc* grids,
                       const Ctl& c, hipStream_t s);
 hipError_t launch_sources(const SourceTable& src, const GridDesc* grids, const Ctl& c, hipStream_t s);
-hipError_t launch_resid(bool fp32, int nl, int tile_rows, const Tile* tiles, int ntiles,
+// multi: the tiles are scenario blocks (Tile.pad consecutive scenarios of one grid)
+hipError_t launch_resid(bool fp32, bool multi, int nl, int tile_rows, const Tile* tiles, int ntiles,
                         const GridDesc* grids, const Ctl& c, int has_d, int din, hipStream_t s);
 // The decision of a residual check writes "any item still active" to flag slot
 // (*flag_seq)++ % nslots of c.any_active (host-visible memory).
-hipError_t launch_decide(const Ctl& c, int G, double tol, int has_d, int nchk, int max_sweeps, int nslots,
-                         hipStream_t s);
-hipError_t launch_sweep(bool fp32, int ordering, int nl, int tile_rows, const Tile* tiles,
+hipError_t launch_decide(const Ctl& c, int I, const GridDesc* grids, int G, double tol, int has_d, int nchk,
+                         int max_sweeps, int nslots, hipStream_t s);
+hipError_t launch_sweep(bool fp32, bool multi, int ordering, int nl, int tile_rows, const Tile* tiles,
                         int ntiles, const GridDesc* grids, const Ctl& c, int din, int zero_in,
                         double omega, hipStream_t s);
 hipError_t launch_step_end(const Ctl& c, int G, int count_step, hipStream_t s);

@@ -77,20 +77,23 @@ struct pg_ctx {
   int64_t step = 0;
   double seconds = 0.0;
   // device tables
-  DBuf grid_desc, tiles_all, src_grid, src_index, src_off, src_t, src_i, ind_grid, ind_local;
+  DBuf grid_desc, tiles_all, tiles_sweep, src_grid, src_index, src_off, src_t, src_i, ind_grid, ind_local;
   // nodes: mesh nodes x scenarios of the group's grids; mesh_nodes: mesh nodes (coefficients
   // are shared by the scenarios of a grid)
-  struct Group { int nl, off, count; int64_t nodes, mesh_nodes; };
-  // algorithmic bytes of one sweep / residual launch over a group (see pgrid.h)
-  double sweep_bytes(const Group& g, bool zero_in) const {
+  // multi: the group's tiles are scenario blocks (Tile.pad consecutive scenarios of a grid)
+  struct Group { int nl, off, count; int64_t nodes, mesh_nodes; bool multi; };
+  // Algorithmic bytes (see pgrid.h) for `an` active mesh nodes x scenarios whose grids hold
+  // `coef` coefficient words: a cycle of nchk sweeps (the first starts from d = 0 and reads no
+  // old correction), and one residual pass.
+  double cycle_bytes(int64_t an, int64_t coef, int nchk) const {
     const double e = opt.precision == PG_PREC_FP32_REFINE ? 4.0 : 8.0;
-    return e * ((zero_in ? 2.0 : 3.0) * g.nodes + (3.0 + (g.nl - 1.0) / g.nl) * g.mesh_nodes);
+    return e * ((2.0 + 3.0 * (nchk - 1)) * an + (double)nchk * coef);
   }
-  double resid_bytes(const Group& g, bool has_d) const {
+  double resid_bytes(int64_t an, int64_t coef, bool has_d) const {
     const double e = opt.precision == PG_PREC_FP32_REFINE ? 4.0 : 8.0;
-    return (16.0 + e + (has_d ? e + 8.0 : 0.0)) * g.nodes + 8.0 * (3.0 + (g.nl - 1.0) / g.nl) * g.mesh_nodes;
+    return (16.0 + e + (has_d ? e + 8.0 : 0.0)) * an + 8.0 * coef;
   }
-  std::vector<Group> tile_groups;                 // tiles of grids with nl layers: [off, off+count)
+  std::vector<Group> tile_groups;                 // sweep/residual tiles by (layers, block): [off, off+count) of tiles_sweep
   int ntiles_all = 0;
   int tile_rows = 16;
   int n_src = 0, n_ind_total = 0;
@@ -98,7 +101,7 @@ struct pg_ctx {
   DBuf src_win_t0;
   long long step_host = 0;                       // staging for the device step counter
   DBuf c_clock;                                  // step (int64), t_now (double), window (2 x int32)
-  std::vector<int> item_tile_off, item_tile_cnt; // each item's tiles in tiles_all
+  std::vector<int> item_tile_off, item_tile_cnt; // each item's tiles in tiles_all (one scenario per tile)
   std::vector<GridDesc> desc_host;               // descriptors as uploaded (forward view)
   // recorded forward pass of the softplus-loss adjoint
   struct Adj {
@@ -118,8 +121,10 @@ struct pg_ctx {
   hipGraphExec_t g_prologue = nullptr, g_sweeps = nullptr, g_check = nullptr, g_epilogue = nullptr;
   bool graphs_ready = false;
   int64_t all_nodes = 0;                         // mesh nodes x scenarios over all grids
-  double cycle_sweep_bytes = 0.0;                // algorithmic bytes of one cycle's sweeps
-  double check_resid_bytes = 0.0;                // algorithmic bytes of one cycle's residual pass
+  int64_t all_coef = 0;                          // coefficient words over all grids
+  int64_t begin_nodes = 0, begin_coef = 0;       // work of the step's first residual (items begun)
+  long long* host_acct = nullptr;                // pinned [slots][2]: active work after each decision
+  long long* dev_acct = nullptr;
   int32_t* dev_flags = nullptr;                  // device address of host_flags
   std::vector<hipEvent_t> flag_events;
   // profiling
@@ -234,7 +239,7 @@ void prof_drain(pg_ctx* c) {
     switch (e.kind) {
       case -1: break;
       case 0: A.sweep_launches += e.launches; A.sweep_ms += ms; A.sweep_node_updates += e.units; A.sweep_bytes += e.bytes; break;
-      case 1: A.resid_launches++; A.resid_ms += ms; A.resid_nodes += e.units; A.resid_bytes += e.bytes; break;
+      case 1: A.resid_launches += e.launches; A.resid_ms += ms; A.resid_nodes += e.units; A.resid_bytes += e.bytes; break;
       case 2: A.rhs_launches++; A.rhs_ms += ms; break;
       default: A.other_launches++; A.other_ms += ms; break;
     }
@@ -394,33 +399,51 @@ pg_status prepare(pg_ctx* c) {
   c->adj.recorded = false;
   PG_TRY(upload(c, c->c_nodes, nodes));
   c->ctl.nodes = (const long long*)c->c_nodes.p;
-  // tiles grouped by layer count
+  // tiles_all: one tile per (scenario, tile) grouped by layer count, for the right-hand side,
+  // the state copies and the loss kernels.  tiles_sweep: the sweep and residual tiles; a grid
+  // with several scenarios is covered by scenario blocks of up to scen_block scenarios, whose
+  // workgroups load the shared coefficients once per block.
   const int TY = c->tile_rows;
-  std::vector<Tile> tiles;
+  const int SB = c->opt.scen_block ? c->opt.scen_block : kScenBlock;
+  std::vector<Tile> tiles, sweep;
   c->tile_groups.clear();
   c->item_tile_off.assign(n_items(c), 0);
   c->item_tile_cnt.assign(n_items(c), 0);
   for (int nl = 1; nl <= 4; ++nl) {
-    const int start = (int)tiles.size();
-    int64_t nodes_nl = 0, mesh_nl = 0;
     for (int g = 0; g < G; ++g) {
       const GridHost& H = c->grids[g];
       if (H.nl != nl) continue;
-      nodes_nl += H.n * H.S;
-      mesh_nl += H.n;
       for (int sc = 0; sc < H.S; ++sc) {
         c->item_tile_off[H.item0 + sc] = (int)tiles.size();
         for (int y0 = 0; y0 < H.ny; y0 += TY)
-          for (int x0 = 0; x0 < H.nx; x0 += kTileX) tiles.push_back(Tile{g, H.item0 + sc, sc, x0, y0, 0});
+          for (int x0 = 0; x0 < H.nx; x0 += kTileX) tiles.push_back(Tile{g, H.item0 + sc, sc, x0, y0, 1});
         c->item_tile_cnt[H.item0 + sc] = (int)tiles.size() - c->item_tile_off[H.item0 + sc];
       }
     }
-    if ((int)tiles.size() > start)
-      c->tile_groups.push_back({nl, start, (int)tiles.size() - start, nodes_nl, mesh_nl});
+    for (int multi = 0; multi <= 1; ++multi) {
+      const int start = (int)sweep.size();
+      int64_t nodes_g = 0, mesh_g = 0;
+      for (int g = 0; g < G; ++g) {
+        const GridHost& H = c->grids[g];
+        if (H.nl != nl || (H.S > 1) != (multi == 1)) continue;
+        nodes_g += H.n * H.S;
+        mesh_g += H.n;
+        for (int s0 = 0; s0 < H.S; s0 += SB) {
+          const int nb = std::min(SB, H.S - s0);
+          for (int y0 = 0; y0 < H.ny; y0 += TY)
+            for (int x0 = 0; x0 < H.nx; x0 += kTileX) sweep.push_back(Tile{g, H.item0 + s0, s0, x0, y0, nb});
+        }
+      }
+      if ((int)sweep.size() > start)
+        c->tile_groups.push_back({nl, start, (int)sweep.size() - start, nodes_g, mesh_g, multi == 1});
+    }
   }
   c->ntiles_all = (int)tiles.size();
   c->all_nodes = 0;
+  c->all_coef = 0;
   for (auto& grp : c->tile_groups) c->all_nodes += grp.nodes;
+  for (auto& H : c->grids) c->all_coef += 3 * H.n + (int64_t)H.nx * H.ny * (H.nl - 1);
+  PG_TRY(upload(c, c->tiles_sweep, sweep));
   PG_TRY(upload(c, c->tiles_all, tiles));
   // sources: first those that are non-zero outside their breakpoints ("always"), then the
   // windowed ones (zero before the first and after the last breakpoint, like every triangle)
@@ -523,27 +546,28 @@ pg_status check_gs(pg_ctx* c, int grid, int scen) {
 }
 
 // ---- one backward-Euler step -----------------------------------------------------------
+// Profiled as one block: the work is charged once the active items are known (cycle_loop).
 pg_status launch_resid_all(pg_ctx* c, int has_d, int din) {
-  const Tile* T = (const Tile*)c->tiles_all.p;
+  const Tile* T = (const Tile*)c->tiles_sweep.p;
+  ProfScope ps(c, 1, c->begin_nodes, c->resid_bytes(c->begin_nodes, c->begin_coef, has_d != 0),
+               (int)c->tile_groups.size());
   for (auto& grp : c->tile_groups) {
-    ProfScope ps(c, 1, grp.nodes, c->resid_bytes(grp, has_d != 0));
-    hipError_t e = launch_resid(fp32_mode(c), grp.nl, c->tile_rows, T + grp.off, grp.count,
+    hipError_t e = launch_resid(fp32_mode(c), grp.multi, grp.nl, c->tile_rows, T + grp.off, grp.count,
                                 (const GridDesc*)c->grid_desc.p, c->ctl, has_d, din, c->stream);
     if (e != hipSuccess) return set_err(c, PG_ERR_DEVICE, "residual launch: %s", hipGetErrorString(e));
   }
   return PG_OK;
 }
 
-// The nchk sweeps of a cycle over one tile group are timed as one block of back-to-back
-// launches (one event pair per block, so event overhead does not inflate the per-launch
-// average); every profile_every-th block is timed.
+// The nchk sweeps of a cycle are timed as one block of back-to-back launches (one event pair
+// per block, so event overhead does not inflate the per-launch average); every
+// profile_every-th block is timed.  Its work is charged in cycle_loop from the active items.
 pg_status launch_sweeps(pg_ctx* c, int nchk) {
-  const Tile* T = (const Tile*)c->tiles_all.p;
+  const Tile* T = (const Tile*)c->tiles_sweep.p;
+  ProfScope ps(c, 0, 0, 0.0, nchk * (int)c->tile_groups.size());
   for (auto& grp : c->tile_groups) {
-    const double bytes = c->sweep_bytes(grp, true) + (nchk - 1) * c->sweep_bytes(grp, false);
-    ProfScope ps(c, 0, grp.nodes * nchk, bytes, nchk);
     for (int s = 0; s < nchk; ++s) {
-      hipError_t e = launch_sweep(fp32_mode(c), c->opt.ordering, grp.nl, c->tile_rows,
+      hipError_t e = launch_sweep(fp32_mode(c), grp.multi, c->opt.ordering, grp.nl, c->tile_rows,
                                   T + grp.off, grp.count,
                                   (const GridDesc*)c->grid_desc.p, c->ctl, s & 1, s == 0 ? 1 : 0,
                                   c->opt.omega, c->stream);
@@ -566,6 +590,15 @@ pg_status set_step(pg_ctx* c, int64_t k) {
 
 pg_status begin_step(pg_ctx* c, int only_item) {
   const int G = n_items(c);
+  c->begin_nodes = c->all_nodes;
+  c->begin_coef = c->all_coef;
+  if (only_item >= 0) {
+    for (auto& H : c->grids)
+      if (only_item >= H.item0 && only_item < H.item0 + H.S) {
+        c->begin_nodes = H.n;
+        c->begin_coef = 3 * H.n + (int64_t)H.nx * H.ny * (H.nl - 1);
+      }
+  }
   Ctl k = c->ctl;
   hipError_t e;
   {
@@ -595,9 +628,10 @@ pg_status issue_decide(pg_ctx* c, double tol, int has_d, int* slot_out) {
   const int slot = (int)(c->flag_seq_host++ % kFlagSlots);
   Ctl kk = c->ctl;
   kk.any_active = c->dev_flags;
+  kk.acct = c->dev_acct;
   {
     ProfScope ps(c, 3, 0);
-    hipError_t e = launch_decide(kk, n_items(c), tol, has_d, c->opt.check_every, c->opt.max_sweeps, kFlagSlots,
+    hipError_t e = launch_decide(kk, n_items(c), (const GridDesc*)c->grid_desc.p, (int)c->grids.size(), tol, has_d, c->opt.check_every, c->opt.max_sweeps, kFlagSlots,
                                  c->stream);
     if (e != hipSuccess) return set_err(c, PG_ERR_DEVICE, "decide launch: %s", hipGetErrorString(e));
   }
@@ -611,11 +645,11 @@ pg_status issue_cycle(pg_ctx* c, double tol, bool graphs, int* slot) {
   const int nchk = c->opt.check_every;
   if (graphs) {
     {
-      ProfScope ps(c, 0, c->all_nodes * nchk, c->cycle_sweep_bytes, nchk * (int)c->tile_groups.size());
+      ProfScope ps(c, 0, 0, 0.0, nchk * (int)c->tile_groups.size());
       HIP_TRY(c, hipGraphLaunch(c->g_sweeps, c->stream));
     }
     {
-      ProfScope ps(c, 1, c->all_nodes, c->check_resid_bytes);  // residual (+ the one-block decision)
+      ProfScope ps(c, 1, 0, 0.0, (int)c->tile_groups.size());  // residual (+ the one-block decision)
       HIP_TRY(c, hipGraphLaunch(c->g_check, c->stream));
     }
     *slot = (int)(c->flag_seq_host++ % kFlagSlots);
@@ -639,6 +673,7 @@ pg_status cycle_loop(pg_ctx* c, double tol, bool graphs, int first) {
   const size_t prof_base = c->prof_live.size();
   const int max_chunks = (c->opt.max_sweeps + nchk - 1) / nchk;
   int issued = 0, consumed = 0, last = -1;
+  std::vector<std::pair<int64_t, int64_t>> work;  // active work after decision j (0: the initial check)
   while (true) {
     int want = consumed <= c->pred_chunks ? c->pred_chunks : consumed + L;
     want = std::min(want, consumed + kFlagSlots - 1);  // never reuse a slot still awaited
@@ -653,6 +688,8 @@ pg_status cycle_loop(pg_ctx* c, double tol, bool graphs, int first) {
     pending.pop_front();
     HIP_TRY(c, hipEventSynchronize(c->flag_events[s0]));
     ++consumed;
+    work.emplace_back(__atomic_load_n(c->host_acct + 2 * s0, __ATOMIC_ACQUIRE),
+                      __atomic_load_n(c->host_acct + 2 * s0 + 1, __ATOMIC_ACQUIRE));
     if (__atomic_load_n(c->host_flags + s0, __ATOMIC_ACQUIRE) == 0) {
       last = consumed - 1;
       break;
@@ -661,8 +698,21 @@ pg_status cycle_loop(pg_ctx* c, double tol, bool graphs, int first) {
   if (last < 0) last = issued;
   c->pred_chunks = last;
   c->cur_chunk = 0;
-  for (size_t q = prof_base; q < c->prof_live.size(); ++q)
-    if (c->prof_live[q].chunk > last) c->prof_live[q].kind = -1;
+  // charge cycle k's sweeps and residual with the items the decision before it left active;
+  // launches queued after convergence did no work
+  for (size_t q = prof_base; q < c->prof_live.size(); ++q) {
+    ProfEvent& ev = c->prof_live[q];
+    if (ev.chunk > last) { ev.kind = -1; continue; }
+    if (ev.chunk < 1 || (ev.kind != 0 && ev.kind != 1)) continue;
+    const auto& wk = work[ev.chunk - 1];
+    if (ev.kind == 0) {
+      ev.units = wk.first * nchk;
+      ev.bytes = c->cycle_bytes(wk.first, wk.second, nchk);
+    } else {
+      ev.units = wk.first;
+      ev.bytes = c->resid_bytes(wk.first, wk.second, true);
+    }
+  }
   return PG_OK;
 }
 
@@ -727,12 +777,6 @@ void drop_graphs(pg_ctx* c) {
 // fixed arguments because the step clock and the flag slot advance on the device.
 pg_status build_graphs(pg_ctx* c) {
   drop_graphs(c);
-  c->cycle_sweep_bytes = 0.0;
-  c->check_resid_bytes = 0.0;
-  for (auto& grp : c->tile_groups) {
-    c->check_resid_bytes += c->resid_bytes(grp, true);
-    c->cycle_sweep_bytes += c->sweep_bytes(grp, true) + (c->opt.check_every - 1) * c->sweep_bytes(grp, false);
-  }
   const double tol = c->opt.tol;
   int dummy = 0;
   const uint64_t seq = c->flag_seq_host;
@@ -741,7 +785,8 @@ pg_status build_graphs(pg_ctx* c) {
     PG_TRY(launch_resid_all(c, 0, 0));
     Ctl kk = c->ctl;
     kk.any_active = c->dev_flags;
-    hipError_t e = launch_decide(kk, n_items(c), tol, 0, c->opt.check_every, c->opt.max_sweeps, kFlagSlots,
+    kk.acct = c->dev_acct;
+    hipError_t e = launch_decide(kk, n_items(c), (const GridDesc*)c->grid_desc.p, (int)c->grids.size(), tol, 0, c->opt.check_every, c->opt.max_sweeps, kFlagSlots,
                                  c->stream);
     return e == hipSuccess ? PG_OK : set_err(c, PG_ERR_DEVICE, "decide: %s", hipGetErrorString(e));
   }));
@@ -750,7 +795,8 @@ pg_status build_graphs(pg_ctx* c) {
     PG_TRY(launch_resid_all(c, 1, c->opt.check_every & 1));
     Ctl kk = c->ctl;
     kk.any_active = c->dev_flags;
-    hipError_t e = launch_decide(kk, n_items(c), tol, 1, c->opt.check_every, c->opt.max_sweeps, kFlagSlots,
+    kk.acct = c->dev_acct;
+    hipError_t e = launch_decide(kk, n_items(c), (const GridDesc*)c->grid_desc.p, (int)c->grids.size(), tol, 1, c->opt.check_every, c->opt.max_sweeps, kFlagSlots,
                                  c->stream);
     return e == hipSuccess ? PG_OK : set_err(c, PG_ERR_DEVICE, "decide: %s", hipGetErrorString(e));
   }));
@@ -920,6 +966,13 @@ pg_status pg_create(pg_ctx** out, int32_t device, void* stream) {
     return PG_ERR_DEVICE;
   }
   std::memset(c->host_flags, 0, nslots * sizeof(int32_t));
+  if (hipHostMalloc((void**)&c->host_acct, 2 * nslots * sizeof(long long), hipHostMallocMapped | hipHostMallocCoherent) !=
+          hipSuccess ||
+      hipHostGetDevicePointer((void**)&c->dev_acct, c->host_acct, 0) != hipSuccess) {
+    pg_destroy(c);
+    return PG_ERR_DEVICE;
+  }
+  std::memset(c->host_acct, 0, 2 * nslots * sizeof(long long));
   for (int i = 0; i < nslots; ++i) {
     hipEvent_t e;
     if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) { pg_destroy(c); return PG_ERR_DEVICE; }
@@ -966,7 +1019,7 @@ void pg_destroy(pg_ctx* c) {
                     &H.ind_alpha_d, &H.ind_i_d, &H.inc_off_d, &H.inc_ind_d};
     for (DBuf* b : bufs) dfree(*b);
   }
-  DBuf* bufs[] = {&c->grid_desc, &c->tiles_all, &c->src_grid, &c->src_index, &c->src_off, &c->src_t, &c->src_i,
+  DBuf* bufs[] = {&c->grid_desc, &c->tiles_all, &c->tiles_sweep, &c->src_grid, &c->src_index, &c->src_off, &c->src_t, &c->src_i,
                   &c->ind_grid, &c->ind_local, &c->c_norm, &c->c_last, &c->c_active, &c->c_vidx, &c->c_sweeps,
                   &c->c_failed, &c->c_any, &c->c_stats64, &c->c_stats32, &c->c_statsd, &c->c_nodes,
                   &c->c_clock, &c->src_win_t0};
@@ -978,6 +1031,7 @@ void pg_destroy(pg_ctx* c) {
   for (auto& e : c->prof_live) { (void)hipEventDestroy(e.a); (void)hipEventDestroy(e.b); }
   for (auto e : c->prof_pool) (void)hipEventDestroy(e);
   if (c->host_flags) (void)hipHostFree(c->host_flags);
+  if (c->host_acct) (void)hipHostFree(c->host_acct);
   drop_graphs(c);
   if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
   if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
@@ -991,9 +1045,12 @@ pg_status pg_set_options(pg_ctx* c, const pg_options* o) {
   char msg[256] = {0};
   pg_status st = pg_validate_options(o, msg, sizeof msg);
   if (st != PG_OK) return set_err(c, st, "%s", msg);
-  // h and precision change the coefficients, tile_rows the tiles: rebuild; anything else only
+  // h and precision change the coefficients, tile_rows and scen_block the tiles: rebuild;
+  // anything else only
   // invalidates the captured graphs
-  if (o->h != c->opt.h || o->precision != c->opt.precision || o->tile_rows != c->opt.tile_rows) c->dirty = true;
+  if (o->h != c->opt.h || o->precision != c->opt.precision || o->tile_rows != c->opt.tile_rows ||
+      o->scen_block != c->opt.scen_block)
+    c->dirty = true;
   drop_graphs(c);
   c->opt = *o;
   return PG_OK;

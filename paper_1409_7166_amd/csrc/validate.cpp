@@ -94,7 +94,9 @@ pg_status pg_validate_options(const pg_options* o, char* msg, size_t len) {
     return fail(PG_ERR_INVALID_ARG, msg, len, "tile_rows must be 0, 4, 8 or 16 (got %d)", o->tile_rows);
   if (o->lookahead < 0 || o->lookahead > 4) return fail(PG_ERR_INVALID_ARG, msg, len, "lookahead must be in 0..4");
   if (o->graphs != 0 && o->graphs != 1) return fail(PG_ERR_INVALID_ARG, msg, len, "graphs must be 0 or 1");
-  for (int i = 0; i < 5; ++i)
+  if (o->scen_block < 0 || o->scen_block > 16)
+    return fail(PG_ERR_INVALID_ARG, msg, len, "scen_block must be 0 (default) or 1..16");
+  for (int i = 0; i < 4; ++i)
     if (o->reserved[i] != 0) return fail(PG_ERR_INVALID_ARG, msg, len, "reserved option fields must be zero");
   return PG_OK;
 }

@@ -36,7 +36,8 @@ class Options(C.Structure):
     _fields_ = [("h", C.c_double), ("tol", C.c_double), ("omega", C.c_double),
                 ("max_sweeps", C.c_int32), ("check_every", C.c_int32), ("precision", C.c_int32),
                 ("ordering", C.c_int32), ("tile_rows", C.c_int32), ("lookahead", C.c_int32),
-                ("graphs", C.c_int32), ("reserved", C.c_int32 * 5)]
+                ("graphs", C.c_int32), ("scen_block", C.c_int32),
+                ("reserved", C.c_int32 * 4)]
 
 
 class MeshStruct(C.Structure):

@@ -165,6 +165,32 @@ def test_batched_scenarios_share_one_mesh(prec):
     assert np.max(np.abs(got[3] - 1.0)) <= 1e-12
 
 
+@pytest.mark.parametrize("prec,ordering,rows,block,nl", [
+    (pg.PG_PREC_FP64, pg.PG_ORDER_RED_BLACK, 4, 3, 4),
+    (pg.PG_PREC_FP32_REFINE, pg.PG_ORDER_RED_BLACK, 16, 2, 3),
+    (pg.PG_PREC_FP32_REFINE, pg.PG_ORDER_RED_BLACK, 8, 16, 2),
+    (pg.PG_PREC_FP64, pg.PG_ORDER_JACOBI, 8, 4, 2),
+])
+def test_scenario_blocks_on_layered_meshes(prec, ordering, rows, block, nl):
+    """Five scenarios on one layered 77 x 77 mesh, swept in scenario blocks (ragged blocks,
+    blocks larger than the batch, every layer count's ring tasks), each against its own oracle."""
+    lg = (1.0, 2.0, 4.0, 8.0)[:nl]
+    w = small_multilayer(side=77, seed=81, nl=nl, layer_g=lg, pad_every=16, steps=25)
+    w.pulses[0] = [compressed(small_multilayer(side=77, seed=90 + s, nl=nl, layer_g=lg, pad_every=16).pulses[0][0],
+                              start=0.25, width=1.0) for s in range(5)]
+    say(f"[gpu] scenario blocks prec={prec} ordering={ordering} rows={rows} block={block} nl={nl}")
+    omega = 0.9 if ordering == pg.PG_ORDER_JACOBI else 1.6
+    with gpu_context(w, precision=prec, tol=1e-11, omega=omega, tile_rows=rows, scen_block=block,
+                     ordering=ordering, max_sweeps=20000) as ctx:
+        ctx.step(25)
+        got = [ctx.read_voltages(0, s) for s in range(5)]
+    for s, p in enumerate(w.pulses[0]):
+        Vref, _ = oracle_run(w.meshes[0], p, w.h, 25)
+        err = np.max(np.abs(got[s] - Vref[-1]))
+        say(f"  scenario {s}: err={err:.3e}")
+        assert err <= PARITY_V
+
+
 def test_uneven_grids_batched_in_one_launch():
     """Three grids of different sizes and layer counts stepped together in one context."""
     ws = [small_rc(33, 70, seed=51, steps=30), small_multilayer(side=77, seed=52, nl=2, pad_every=16, steps=30),
