@@ -37,6 +37,8 @@ def parse():
     ap.add_argument("--omega", type=float, default=None)
     ap.add_argument("--check-every", type=int, default=None)
     ap.add_argument("--tile-rows", type=int, default=0)
+    ap.add_argument("--sweeps-per-launch", type=int, default=0,
+                    help="red-black sweeps fused per kernel launch, 1 or 2 (0: library default)")
     ap.add_argument("--scen-block", type=int, default=0,
                     help="scenarios per sweep workgroup on multi-scenario grids (0: library default)")
     ap.add_argument("--lookahead", type=int, default=1)
@@ -88,15 +90,18 @@ def make_workload(name):
     return getattr(workloads, name)()
 
 
-def sweep_kernel_name(w):
-    """The red-black sweep kernel(s) the workload runs: scenario blocks for multi-scenario grids."""
+def sweep_kernel_name(w, sweeps_per_launch):
+    """The red-black sweep kernel(s) the workload runs: two fused sweeps per launch, or one per
+    launch with scenario blocks for multi-scenario grids."""
+    if sweeps_per_launch == 2:
+        return "k_sweep_rb2"
     multi = {len(p) > 1 for p in w.pulses}
     names = {False: "k_sweep_rb", True: "k_sweep_rb_multi"}
     return " + ".join(names[m] for m in sorted(multi))
 
 
 def run_gpu(w, steps, warmup, precision, tol, omega, check_every, tile_rows, lookahead, profile_every, graphs,
-            scen_block=0):
+            scen_block=0, sweeps_per_launch=0):
     import torch
     import paper_1409_7166_amd as pg
 
@@ -105,7 +110,8 @@ def run_gpu(w, steps, warmup, precision, tol, omega, check_every, tile_rows, loo
     ctx = pg.Context(0, stream)
     ctx.set_options(h=w.h, tol=tol, omega=omega, check_every=check_every, max_sweeps=100000,
                     precision=pg.PG_PREC_FP32_REFINE if precision == "fp32+ref" else pg.PG_PREC_FP64,
-                    tile_rows=tile_rows, lookahead=lookahead, graphs=graphs, scen_block=scen_block)
+                    tile_rows=tile_rows, lookahead=lookahead, graphs=graphs, scen_block=scen_block,
+                    sweeps_per_launch=sweeps_per_launch)
     for g, (mesh, scen) in enumerate(zip(w.meshes, w.pulses)):
         ctx.upload_mesh(mesh, len(scen))
         for s, p in enumerate(scen):
@@ -194,9 +200,11 @@ def main():
     omega = args.omega or tuned["omega"]
     chk = args.check_every or tuned["check_every"]
     elapsed, st, kt = run_gpu(w, args.steps, args.warmup, prec, args.tol, omega, chk, args.tile_rows,
-                              args.lookahead, args.profile_every, args.graphs, args.scen_block)
+                              args.lookahead, args.profile_every, args.graphs, args.scen_block,
+                              args.sweeps_per_launch)
     nodes = sum(m.n * len(p) for m, p in zip(w.meshes, w.pulses))
     value = st["node_updates"] / elapsed
+    spl = st["options"]["sweeps_per_launch"] or 1
     roof = None
     if kt["sweep_launches"]:
         sweep_s = kt["sweep_ms"] * 1e-3
@@ -205,7 +213,7 @@ def main():
         traffic = counter_traffic(per_launch) if name == "config1" and prec == "fp32+ref" else None
         roof = {"bound": "hbm", "achieved": achieved / 1e9, "peak": HBM_PEAK / 1e9, "unit": "GB/s",
                 "frac": achieved / HBM_PEAK, "traffic": traffic,
-                "kernel": sweep_kernel_name(w), "timed_launches": kt["sweep_launches"],
+                "kernel": sweep_kernel_name(w, spl), "timed_launches": kt["sweep_launches"],
                 "avg_launch_us": kt["sweep_ms"] * 1e3 / kt["sweep_launches"],
                 "bytes_per_launch": kt["sweep_bytes"] / kt["sweep_launches"]}
     out = {
@@ -216,7 +224,8 @@ def main():
         "config": {"workload": w.name, "nodes": nodes, "h_s": w.h, "tol_V": args.tol,
                    "precision": prec, "omega": omega, "check_every": chk, "graphs": args.graphs,
                    "tile_rows": st["options"]["tile_rows"] or 8,
-                   "scen_block": (st["options"]["scen_block"] or 8) if "k_sweep_rb_multi" in sweep_kernel_name(w)
+                   "sweeps_per_launch": spl,
+                   "scen_block": (st["options"]["scen_block"] or 8) if any(len(p) > 1 for p in w.pulses)
                    else None,
                    "sweeps_per_step": st["sweeps"] / max(1, st["steps"]),
                    "max_step_sweeps": st["max_step_sweeps"], "max_final_residual_V": st["max_final_residual"],

@@ -76,7 +76,10 @@ typedef struct pg_options {
   int32_t graphs;       /* 1: replay each step's launches from captured HIP graphs; 0: launch one by one */
   int32_t scen_block;   /* scenarios per sweep/residual workgroup on grids that carry several
                            scenarios (coefficients are loaded once per block): 1..16 (0 = 8) */
-  int32_t reserved[4];  /* must be zero */
+  int32_t sweeps_per_launch; /* red-black sweeps fused into one kernel launch: 1 or 2 (0 = 1); two
+                           sweeps stage a wider halo and recompute its rings, and move the bytes
+                           of one sweep.  Results are identical.  Jacobi ordering always uses 1 */
+  int32_t reserved[3];  /* must be zero */
 } pg_options;
 
 /* A layered RC/RLC mesh (the representative node of Fig. 2 repeated on a grid).
@@ -133,7 +136,8 @@ int32_t pg_abi_version(void);
 const char* pg_status_name(int32_t status);
 
 /* Fill *out with the defaults: h = 10 ps, tol = 1e-6 V, omega = 1, max_sweeps = 10000,
- * check_every = 8, FP64, red-black, tile_rows = 8, lookahead = 1, graphs = 0, scen_block = 8. */
+ * check_every = 8, FP64, red-black, tile_rows = 8, lookahead = 1, graphs = 0, scen_block = 8,
+ * sweeps_per_launch = 1. */
 pg_status pg_default_options(pg_options* out);
 
 /* Host-only checks (no device needed).  msg (may be NULL) receives a description of the
@@ -213,7 +217,8 @@ pg_status pg_grid_info(const pg_ctx* ctx, int32_t grid, int32_t* nx, int32_t* ny
                        int32_t* n_vias, int32_t* n_pads);
 
 /* Autotuner: times `nsteps` steps from the current state for candidate settings (omega, sweeps
- * per residual check, tile rows, graph replay), by coordinate descent from the current options,
+ * per residual check, tile rows, sweeps per launch, scenario block size when a grid carries
+ * several scenarios, graph replay), by coordinate descent from the current options,
  * restoring the state and clock after every trial, and sets the fastest.  The winner is cached in
  * the JSON file `cache_path` (may be NULL: no cache) under a key built from the grid shapes,
  * scenario counts, precision, h, tolerance and the GPU architecture; a cached entry is applied

@@ -719,6 +719,142 @@ __global__ __launch_bounds__(64 * TY) void k_resid_multi(const Tile* __restrict_
   }
 }
 
+// ------------------------------------------------------------------------------------
+// Two red-black SOR sweeps per launch (overlapped temporal blocking).  The old correction is
+// staged with a four-node halo; the first red half-sweep is also computed on a three-node
+// ring around the tile, the first black half-sweep on a two-node ring and the second red one
+// on a one-node ring, so the second black half-sweep of the owned nodes reads exactly the
+// values two separate sweeps would give.  A launch reads and writes the bytes of one sweep.
+// Tiles may be scenario blocks (Tile.pad scenarios sharing the coefficients, kept in
+// registers for the owned pairs).
+// ------------------------------------------------------------------------------------
+
+// One half-sweep of `colour` on the ring of width k around the tile (all layers); the ring's
+// coefficients and right-hand side come from global memory (mostly L2: they belong to the
+// neighbouring tiles).  Top and bottom bands visit only cells of the colour; the narrow side
+// bands visit every cell and skip the other colour.
+template <typename T, int NL, int TY, int HY, int HP>
+__device__ __forceinline__ void ring_half(V2<T> (*sd)[HY][HP], const GridDesc& G, const T* __restrict__ gE,
+                                          const T* __restrict__ gN, const T* __restrict__ gU,
+                                          const T* __restrict__ invD, const T* __restrict__ r, int x0,
+                                          int y0, int k, int colour, T omega) {
+  constexpr int NT = 64 * TY, HALO = 4;
+  const int W = kTileX + 2 * k;
+  const int band = k * (W / 2);  // cells of the colour in the top (or bottom) band of a layer
+  const int side = k * TY;       // cells in the left (or right) band of a layer
+  const int per_layer = 2 * band + 2 * side;
+  const int X = G.X, ny = G.ny;
+  const int64_t P = (int64_t)X * ny;
+  for (int q = threadIdx.x; q < NL * per_layer; q += NT) {
+    const int l = q / per_layer;
+    int rem = q - l * per_layer;
+    int gx, gy;
+    if (rem < 2 * band) {
+      const int b = rem >= band;  // 0: top band, 1: bottom band
+      rem -= b * band;
+      const int rr = rem / (W / 2), j = rem - rr * (W / 2);
+      gy = b ? y0 + TY + rr : y0 - k + rr;
+      const int xs = x0 - k;
+      gx = xs + ((colour + gy + l + xs) & 1) + 2 * j;
+    } else {
+      rem -= 2 * band;
+      const int b = rem >= side;  // 0: left band, 1: right band
+      rem -= b * side;
+      const int rr = rem / k, cc = rem - rr * k;
+      gy = y0 + rr;
+      gx = b ? x0 + kTileX + cc : x0 - k + cc;
+      if (((gx + gy + l) & 1) != colour) continue;
+    }
+    if (gx < 0 || gx >= X || gy < 0 || gy >= ny) continue;
+    const int e = gx & 1, px = gx - e;
+    NodeCoef<T> mine, other;
+    load_pair_coef<T, NL>(G, gE, gN, gU, invD, l, gy, px, e, mine, other);
+    mine.r = r[l * P + (int64_t)gy * X + gx];
+    const int hy = gy - y0 + HALO, hp = (px - x0 + HALO) >> 1;
+    const T nv = relax<T, NL, HY, HP>(sd, l, hy, hp, e, mine, omega);
+    put(sd[l][hy][hp], e, nv);
+  }
+}
+
+template <typename T, int NL, int TY>
+__global__ __launch_bounds__(64 * TY) void k_sweep_rb2(const Tile* __restrict__ tiles, int ntiles,
+                                                      const GridDesc* __restrict__ grids, Ctl c,
+                                                      int din, int zero_in, T omega) {
+  constexpr int HALO = 4;                       // staged nodes beyond the tile on every side
+  constexpr int NP = kTileX / 2, HP = NP + HALO, HY = TY + 2 * HALO, NT = 64 * TY;
+  __shared__ V2<T> sd[NL][HY][HP];
+  const int ti = xcd_tile(ntiles);
+  if (ti < 0) return;
+  const Tile tl = tiles[ti];
+  const GridDesc& G = grids[tl.grid];
+  const int ny = G.ny, X = G.X;
+  const int64_t P = (int64_t)X * ny;
+  const int x0 = tl.x0, y0 = tl.y0;
+  const T* __restrict__ gE = static_cast<const T*>(G.gEs);
+  const T* __restrict__ gN = static_cast<const T*>(G.gNs);
+  const T* __restrict__ gU = static_cast<const T*>(G.gUs);
+  const T* __restrict__ invD = static_cast<const T*>(G.invDs);
+  const int lane = threadIdx.x & 63, row = threadIdx.x >> 6;
+  const int x = x0 + 2 * lane, y = y0 + row;
+  const int hp = lane + HALO / 2, hy = row + HALO;
+  const bool mine = x < X && y < ny;
+
+  NodeCoef<T> kr[NL], kb[NL];  // the owned pair on every layer: red node and black partner
+  if (mine) {
+#pragma unroll
+    for (int l = 0; l < NL; ++l) load_pair_coef<T, NL>(G, gE, gN, gU, invD, l, y, x, (y + l) & 1, kr[l], kb[l]);
+  }
+  for (int sc = 0; sc < tl.pad; ++sc) {
+    if (!c.active[tl.item + sc]) continue;  // uniform across the block
+    const int64_t off = (int64_t)(tl.scen + sc) * G.nstore;
+    const T* __restrict__ dold = static_cast<const T*>(G.d[din]) + off;
+    T* __restrict__ dnew = static_cast<T*>(G.d[din ^ 1]) + off;
+    const T* __restrict__ r = static_cast<const T*>(G.r) + off;
+    __syncthreads();  // the previous scenario is done with sd
+    for (int k = threadIdx.x; k < NL * HY * HP; k += NT) {
+      const int l = k / (HY * HP);
+      const int rem = k - l * (HY * HP);
+      const int shy = rem / HP, shp = rem - shy * HP;
+      const int sx = x0 - HALO + 2 * shp, sy = y0 - HALO + shy;
+      V2<T> val = zero2<T>();
+      if (!zero_in && sx >= 0 && sx < X && sy >= 0 && sy < ny) val = ld2(dold, l * P + (int64_t)sy * X + sx);
+      sd[l][shy][shp] = val;
+    }
+    if (mine) {
+#pragma unroll
+      for (int l = 0; l < NL; ++l) {
+        const int er = (y + l) & 1;
+        const V2<T> rr = ld2(r, l * P + (int64_t)y * X + x);
+        kr[l].r = pick(rr, er);
+        kb[l].r = pick(rr, 1 - er);
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int half = 0; half < 4; ++half) {  // red, black, red, black
+      const int colour = half & 1;
+      if (mine) {
+#pragma unroll
+        for (int l = 0; l < NL; ++l) {
+          const int ec = ((y + l) & 1) ^ colour;  // element of the pair with this colour
+          const T nv = relax<T, NL, HY, HP>(sd, l, hy, hp, ec, colour ? kb[l] : kr[l], omega);
+          if (half < 3) {
+            put(sd[l][hy][hp], ec, nv);
+          } else {
+            V2<T> out = sd[l][hy][hp];
+            put(out, ec, nv);
+            st2(dnew, l * P + (int64_t)y * X + x, out);
+          }
+        }
+      }
+      if (half < 3) {
+        ring_half<T, NL, TY, HY, HP>(sd, G, gE, gN, gU, invD, r, x0, y0, 3 - half, colour, omega);
+        __syncthreads();
+      }
+    }
+  }
+}
+
 // Weighted Jacobi sweep: every node from the previous sweep's values (element-wise).
 template <typename T, int NL>
 __global__ __launch_bounds__(kThreads) void k_sweep_jacobi(const Tile* __restrict__ tiles, int ntiles,
@@ -1039,6 +1175,13 @@ static void sweep_t(bool multi, int ordering, const Tile* tiles, int ntiles, con
                        tiles, ntiles, grids, c, din, zero_in, (T)omega);
 }
 
+template <typename T, int NL, int TY>
+static void sweep2_t(const Tile* tiles, int ntiles, const GridDesc* grids, const Ctl& c, int din, int zero_in,
+                     double omega, hipStream_t s) {
+  hipLaunchKernelGGL((k_sweep_rb2<T, NL, TY>), dim3(xcd_blocks(ntiles)), dim3(64 * TY), 0, s, tiles, ntiles,
+                     grids, c, din, zero_in, (T)omega);
+}
+
 #define PG_DISPATCH_NL_TY(FN, T, ...)                                   \
   switch (nl * 100 + tile_rows) {                                       \
     case 104: FN<T, 1, 4>(__VA_ARGS__); break;                          \
@@ -1075,6 +1218,17 @@ hipError_t launch_sweep(bool fp32, bool multi, int ordering, int nl, int tile_ro
     PG_DISPATCH_NL_TY(sweep_t, float, multi, ordering, tiles, ntiles, grids, c, din, zero_in, omega, s)
   } else {
     PG_DISPATCH_NL_TY(sweep_t, double, multi, ordering, tiles, ntiles, grids, c, din, zero_in, omega, s)
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_sweep2(bool fp32, int nl, int tile_rows, const Tile* tiles, int ntiles, const GridDesc* grids,
+                         const Ctl& c, int din, int zero_in, double omega, hipStream_t s) {
+  if (ntiles <= 0) return hipSuccess;
+  if (fp32) {
+    PG_DISPATCH_NL_TY(sweep2_t, float, tiles, ntiles, grids, c, din, zero_in, omega, s)
+  } else {
+    PG_DISPATCH_NL_TY(sweep2_t, double, tiles, ntiles, grids, c, din, zero_in, omega, s)
   }
   return hipGetLastError();
 }

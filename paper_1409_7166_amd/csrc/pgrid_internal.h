@@ -126,6 +126,9 @@ hipError_t launch_resid(bool fp32, bool multi, int nl, int tile_rows, const Tile
 // (*flag_seq)++ % nslots of c.any_active (host-visible memory).
 hipError_t launch_decide(const Ctl& c, int I, const GridDesc* grids, int G, double tol, int has_d, int nchk,
                          int max_sweeps, int nslots, hipStream_t s);
+// Two red-black sweeps in one launch (tiles may be scenario blocks); reads d[din], writes d[din ^ 1].
+hipError_t launch_sweep2(bool fp32, int nl, int tile_rows, const Tile* tiles, int ntiles, const GridDesc* grids,
+                         const Ctl& c, int din, int zero_in, double omega, hipStream_t s);
 hipError_t launch_sweep(bool fp32, bool multi, int ordering, int nl, int tile_rows, const Tile* tiles,
                         int ntiles, const GridDesc* grids, const Ctl& c, int din, int zero_in,
                         double omega, hipStream_t s);

@@ -83,11 +83,11 @@ struct pg_ctx {
   // multi: the group's tiles are scenario blocks (Tile.pad consecutive scenarios of a grid)
   struct Group { int nl, off, count; int64_t nodes, mesh_nodes; bool multi; };
   // Algorithmic bytes (see pgrid.h) for `an` active mesh nodes x scenarios whose grids hold
-  // `coef` coefficient words: a cycle of nchk sweeps (the first starts from d = 0 and reads no
-  // old correction), and one residual pass.
-  double cycle_bytes(int64_t an, int64_t coef, int nchk) const {
+  // `coef` coefficient words: a cycle of L sweep launches (the first starts from d = 0 and reads
+  // no old correction; a launch of two fused sweeps moves the bytes of one), and one residual pass.
+  double cycle_bytes(int64_t an, int64_t coef, int L) const {
     const double e = opt.precision == PG_PREC_FP32_REFINE ? 4.0 : 8.0;
-    return e * ((2.0 + 3.0 * (nchk - 1)) * an + (double)nchk * coef);
+    return e * ((2.0 + 3.0 * (L - 1)) * an + (double)L * coef);
   }
   double resid_bytes(int64_t an, int64_t coef, bool has_d) const {
     const double e = opt.precision == PG_PREC_FP32_REFINE ? 4.0 : 8.0;
@@ -559,18 +559,38 @@ pg_status launch_resid_all(pg_ctx* c, int has_d, int din) {
   return PG_OK;
 }
 
+// Sweeps fused per launch (1 or 2); Jacobi sweeps are always launched one by one.
+int sweeps_per_launch(const pg_ctx* c) {
+  if (c->opt.ordering != PG_ORDER_RED_BLACK) return 1;
+  return c->opt.sweeps_per_launch ? c->opt.sweeps_per_launch : 1;
+}
+
+// Kernel launches per tile group in a cycle of nchk sweeps; the cycle's result is in d[launches & 1].
+int cycle_launches(const pg_ctx* c, int nchk) {
+  const int spl = sweeps_per_launch(c);
+  return (nchk + spl - 1) / spl;
+}
+
 // The nchk sweeps of a cycle are timed as one block of back-to-back launches (one event pair
 // per block, so event overhead does not inflate the per-launch average); every
 // profile_every-th block is timed.  Its work is charged in cycle_loop from the active items.
 pg_status launch_sweeps(pg_ctx* c, int nchk) {
   const Tile* T = (const Tile*)c->tiles_sweep.p;
-  ProfScope ps(c, 0, 0, 0.0, nchk * (int)c->tile_groups.size());
+  const int spl = sweeps_per_launch(c);
+  ProfScope ps(c, 0, 0, 0.0, cycle_launches(c, nchk) * (int)c->tile_groups.size());
   for (auto& grp : c->tile_groups) {
-    for (int s = 0; s < nchk; ++s) {
-      hipError_t e = launch_sweep(fp32_mode(c), grp.multi, c->opt.ordering, grp.nl, c->tile_rows,
-                                  T + grp.off, grp.count,
-                                  (const GridDesc*)c->grid_desc.p, c->ctl, s & 1, s == 0 ? 1 : 0,
-                                  c->opt.omega, c->stream);
+    for (int s = 0, j = 0; s < nchk; ++j) {
+      const int zero_in = s == 0 ? 1 : 0;
+      hipError_t e;
+      if (spl == 2 && nchk - s >= 2) {
+        e = launch_sweep2(fp32_mode(c), grp.nl, c->tile_rows, T + grp.off, grp.count,
+                          (const GridDesc*)c->grid_desc.p, c->ctl, j & 1, zero_in, c->opt.omega, c->stream);
+        s += 2;
+      } else {
+        e = launch_sweep(fp32_mode(c), grp.multi, c->opt.ordering, grp.nl, c->tile_rows, T + grp.off, grp.count,
+                         (const GridDesc*)c->grid_desc.p, c->ctl, j & 1, zero_in, c->opt.omega, c->stream);
+        s += 1;
+      }
       if (e != hipSuccess) return set_err(c, PG_ERR_DEVICE, "sweep launch: %s", hipGetErrorString(e));
     }
   }
@@ -645,7 +665,7 @@ pg_status issue_cycle(pg_ctx* c, double tol, bool graphs, int* slot) {
   const int nchk = c->opt.check_every;
   if (graphs) {
     {
-      ProfScope ps(c, 0, 0, 0.0, nchk * (int)c->tile_groups.size());
+      ProfScope ps(c, 0, 0, 0.0, cycle_launches(c, nchk) * (int)c->tile_groups.size());
       HIP_TRY(c, hipGraphLaunch(c->g_sweeps, c->stream));
     }
     {
@@ -657,7 +677,7 @@ pg_status issue_cycle(pg_ctx* c, double tol, bool graphs, int* slot) {
     return PG_OK;
   }
   PG_TRY(launch_sweeps(c, nchk));
-  PG_TRY(launch_resid_all(c, 1, nchk & 1));
+  PG_TRY(launch_resid_all(c, 1, cycle_launches(c, nchk) & 1));
   return issue_decide(c, tol, 1, slot);
 }
 
@@ -707,7 +727,7 @@ pg_status cycle_loop(pg_ctx* c, double tol, bool graphs, int first) {
     const auto& wk = work[ev.chunk - 1];
     if (ev.kind == 0) {
       ev.units = wk.first * nchk;
-      ev.bytes = c->cycle_bytes(wk.first, wk.second, nchk);
+      ev.bytes = c->cycle_bytes(wk.first, wk.second, cycle_launches(c, nchk));
     } else {
       ev.units = wk.first;
       ev.bytes = c->resid_bytes(wk.first, wk.second, true);
@@ -792,7 +812,7 @@ pg_status build_graphs(pg_ctx* c) {
   }));
   PG_TRY(capture(c, &c->g_sweeps, [&]() { return launch_sweeps(c, c->opt.check_every); }));
   PG_TRY(capture(c, &c->g_check, [&]() -> pg_status {
-    PG_TRY(launch_resid_all(c, 1, c->opt.check_every & 1));
+    PG_TRY(launch_resid_all(c, 1, cycle_launches(c, c->opt.check_every) & 1));
     Ctl kk = c->ctl;
     kk.any_active = c->dev_flags;
     kk.acct = c->dev_acct;
@@ -1476,7 +1496,8 @@ std::string tune_key(pg_ctx* c) {
 }
 
 // The cache is a flat JSON object {"key": {"omega": w, "check_every": n, "tile_rows": r,
-// "graphs": g, "seconds": t}, ...} written and read only by this library.
+// "graphs": g, "sweeps_per_launch": f, "scen_block": b, "seconds": t}, ...} written and read
+// only by this library.
 bool cache_lookup(const char* path, const std::string& key, pg_options* o) {
   if (!path) return false;
   FILE* f = std::fopen(path, "r");
@@ -1504,6 +1525,9 @@ bool cache_lookup(const char* path, const std::string& key, pg_options* o) {
   o->check_every = (int32_t)ce;
   o->tile_rows = (int32_t)tr;
   o->graphs = (int32_t)gr;
+  double spl = 0.0, blk = 0.0;
+  o->sweeps_per_launch = num("sweeps_per_launch", &spl) ? (int32_t)spl : 0;
+  o->scen_block = num("scen_block", &blk) ? (int32_t)blk : 0;
   return true;
 }
 
@@ -1518,8 +1542,10 @@ void cache_store(const char* path, const std::string& key, const pg_options& o, 
   }
   char entry[512];
   std::snprintf(entry, sizeof entry,
-                "\"%s\": {\"omega\": %.4f, \"check_every\": %d, \"tile_rows\": %d, \"graphs\": %d, \"seconds\": %.6f}",
-                key.c_str(), o.omega, o.check_every, o.tile_rows, o.graphs, seconds);
+                "\"%s\": {\"omega\": %.4f, \"check_every\": %d, \"tile_rows\": %d, \"graphs\": %d, "
+                "\"sweeps_per_launch\": %d, \"scen_block\": %d, \"seconds\": %.6f}",
+                key.c_str(), o.omega, o.check_every, o.tile_rows, o.graphs, o.sweeps_per_launch, o.scen_block,
+                seconds);
   const std::string needle = "\"" + key + "\"";
   const size_t at = text.find(needle);
   if (at != std::string::npos) {
@@ -1594,6 +1620,23 @@ extern "C" pg_status pg_autotune(pg_ctx* c, int32_t nsteps, const char* cache_pa
   for (int r : rows) {
     pg_options o = best;
     o.tile_rows = r;
+    double t;
+    PG_TRY(trial(o, &t));
+    if (t < best_t) { best_t = t; best = o; }
+  }
+  for (int f = 1; f <= 2 && best.ordering == PG_ORDER_RED_BLACK; ++f) {
+    pg_options o = best;
+    o.sweeps_per_launch = f;
+    double t;
+    PG_TRY(trial(o, &t));
+    if (t < best_t) { best_t = t; best = o; }
+  }
+  bool batched = false;
+  for (auto& H : c->grids) batched = batched || H.S > 1;
+  for (int b : {4, 8, 16}) {
+    if (!batched) break;
+    pg_options o = best;
+    o.scen_block = b;
     double t;
     PG_TRY(trial(o, &t));
     if (t < best_t) { best_t = t; best = o; }

@@ -96,7 +96,9 @@ pg_status pg_validate_options(const pg_options* o, char* msg, size_t len) {
   if (o->graphs != 0 && o->graphs != 1) return fail(PG_ERR_INVALID_ARG, msg, len, "graphs must be 0 or 1");
   if (o->scen_block < 0 || o->scen_block > 16)
     return fail(PG_ERR_INVALID_ARG, msg, len, "scen_block must be 0 (default) or 1..16");
-  for (int i = 0; i < 4; ++i)
+  if (o->sweeps_per_launch < 0 || o->sweeps_per_launch > 2)
+    return fail(PG_ERR_INVALID_ARG, msg, len, "sweeps_per_launch must be 0 (default), 1 or 2");
+  for (int i = 0; i < 3; ++i)
     if (o->reserved[i] != 0) return fail(PG_ERR_INVALID_ARG, msg, len, "reserved option fields must be zero");
   return PG_OK;
 }

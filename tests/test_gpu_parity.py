@@ -191,6 +191,45 @@ def test_scenario_blocks_on_layered_meshes(prec, ordering, rows, block, nl):
         assert err <= PARITY_V
 
 
+@pytest.mark.parametrize("case", ["rc32_fp64", "three_layer_fp32", "blocks_fp32", "four_layer_fp64"])
+def test_two_sweeps_per_launch_equal_two_launches(case):
+    """Fusing two red-black sweeps into one launch (four-node halo, recomputed rings) gives the
+    voltages of two separate sweeps bit for bit, including an odd cycle length (one single-sweep
+    launch at the end of each cycle), ragged tiles and scenario blocks."""
+    lg4 = (1.0, 2.0, 4.0, 8.0)
+    if case == "rc32_fp64":
+        w, prec, rows, chk, block = config0(), pg.PG_PREC_FP64, 8, 7, 0
+    elif case == "three_layer_fp32":
+        w, prec, rows, chk, block = (small_multilayer(side=100, seed=31, nl=3, pad_every=32, steps=20),
+                                     pg.PG_PREC_FP32_REFINE, 16, 8, 0)
+        w.pulses[0][0] = compressed(w.pulses[0][0], start=0.08, width=1.0)
+    elif case == "blocks_fp32":
+        w = small_multilayer(side=77, seed=81, nl=2, layer_g=lg4[:2], pad_every=16, steps=20)
+        w.pulses[0] = [compressed(small_multilayer(side=77, seed=90 + s, nl=2, layer_g=lg4[:2],
+                                                   pad_every=16).pulses[0][0], start=0.25, width=1.0)
+                       for s in range(5)]
+        prec, rows, chk, block = pg.PG_PREC_FP32_REFINE, 4, 5, 3
+    else:
+        w = small_multilayer(side=77, seed=82, nl=4, layer_g=lg4, pad_every=16, steps=20)
+        w.pulses[0][0] = compressed(w.pulses[0][0], start=0.25, width=1.0)
+        prec, rows, chk, block = pg.PG_PREC_FP64, 4, 9, 0
+    steps = 20
+    res = {}
+    for spl in (1, 2):
+        say(f"[gpu] fused sweeps case={case} sweeps_per_launch={spl}")
+        with gpu_context(w, precision=prec, tol=1e-11, omega=1.6, tile_rows=rows, check_every=chk,
+                         scen_block=block, sweeps_per_launch=spl) as ctx:
+            ctx.step(steps)
+            res[spl] = ([ctx.read_voltages(0, s) for s in range(len(w.pulses[0]))], ctx.stats())
+    for a, b in zip(res[1][0], res[2][0]):
+        assert np.array_equal(a, b), np.max(np.abs(a - b))
+    assert res[1][1]["sweeps"] == res[2][1]["sweeps"]
+    Vref, _ = oracle_run(w.meshes[0], w.pulses[0][0], w.h, steps)
+    err = np.max(np.abs(res[2][0][0] - Vref[-1]))
+    say(f"  sweeps={res[2][1]['sweeps']} err={err:.3e}")
+    assert err <= PARITY_V
+
+
 def test_uneven_grids_batched_in_one_launch():
     """Three grids of different sizes and layer counts stepped together in one context."""
     ws = [small_rc(33, 70, seed=51, steps=30), small_multilayer(side=77, seed=52, nl=2, pad_every=16, steps=30),
@@ -250,6 +289,7 @@ def test_autotune_restores_state_and_caches(tmp_path):
         assert ctx.time_index() == 5
         assert np.array_equal(ctx.read_voltages(), v5)
         assert 0 < chosen["omega"] < 2 and chosen["check_every"] >= 1 and chosen["tile_rows"] in (4, 8, 16)
+        assert chosen["sweeps_per_launch"] in (1, 2)
         ctx.step(15)
         V = ctx.read_voltages()
     import json
@@ -260,3 +300,4 @@ def test_autotune_restores_state_and_caches(tmp_path):
     with gpu_context(w, precision=pg.PG_PREC_FP32_REFINE, tol=1e-10, omega=1.0) as ctx:
         again = ctx.autotune(4, cache)
     assert again["omega"] == pytest.approx(chosen["omega"]) and again["check_every"] == chosen["check_every"]
+    assert again["sweeps_per_launch"] == chosen["sweeps_per_launch"] and again["tile_rows"] == chosen["tile_rows"]
