@@ -113,10 +113,10 @@ typedef struct pg_stats {
 } pg_stats;
 
 /* Kernel timing gathered with HIP events on the context stream while profiling is on
- * (pg_profile(ctx, k): every k-th block of back-to-back sweep launches of a refinement cycle is
- * timed as one interval; the residual passes over all tile groups, and other launches, are
- * timed one interval each).  Launches queued after a step had converged (which exit at once)
- * are left out.
+ * (pg_profile(ctx, k): the back-to-back sweep launches of a refinement cycle form one interval,
+ * a residual pass over all tile groups another, and other launches one each; every k-th
+ * interval of each kind is timed).  Launches queued after a step had converged (which exit at
+ * once) are left out.
  * *_bytes are algorithmic bytes of the timed launches, charged for the (grid, scenario) items
  * that were still iterating (the rest exit at once): every array the kernel needs read once
  * and every array it produces written once, with e = 4 (FP32 sweeps) or 8 (FP64) bytes.  Per
@@ -260,8 +260,9 @@ pg_status pg_loss_backward_dev(pg_ctx* ctx, double tol_adj, double* dJ_dC, doubl
 pg_status pg_get_stats(const pg_ctx* ctx, pg_stats* out);
 pg_status pg_reset_stats(pg_ctx* ctx);
 
-/* Kernel timing with HIP events on the context stream: enable = k > 0 times every k-th sweep
- * block and every other launch, 0 turns it off.  pg_read_kernel_times synchronises the stream. */
+/* Kernel timing with HIP events on the context stream: enable = k > 0 times every k-th interval
+ * of each kind (see pg_kernel_times), 0 turns it off.  Each timed interval adds two event records
+ * to the stream.  pg_read_kernel_times synchronises the stream. */
 pg_status pg_profile(pg_ctx* ctx, int32_t enable);
 pg_status pg_read_kernel_times(pg_ctx* ctx, pg_kernel_times* out);
 

@@ -129,6 +129,24 @@ __device__ __forceinline__ void put(V& v, int e, T val) {
 // ------------------------------------------------------------------------------------
 // Step bookkeeping
 // ------------------------------------------------------------------------------------
+// First index i in [0, n] with a[i] >= key (a[i] > key if strict) of the ascending array a,
+// found by the whole block: every round probes blockDim.x evenly spaced entries of the remaining
+// range, so a search takes log_blockDim(n) rounds of one load each.  Called by every thread.
+__device__ int block_lower_bound(const double* __restrict__ a, int n, double key, bool strict) {
+  int lo = 0, hi = n;
+  while (lo < hi) {
+    const int step = (hi - lo + (int)blockDim.x - 1) / (int)blockDim.x;
+    const int p = lo + (int)threadIdx.x * step;
+    int below = 0;
+    if (p < hi) below = strict ? (a[p] <= key) : (a[p] < key);
+    const int k = __syncthreads_count(below);  // probes 0..k-1 lie below the answer
+    const int nlo = k == 0 ? lo : lo + (k - 1) * step + 1;
+    hi = min(hi, lo + k * step);
+    lo = nlo;
+  }
+  return lo;
+}
+
 __global__ void k_step_begin(Ctl c, int I, int only_item, double h, SourceTable src) {
   for (int g = threadIdx.x; g < I; g += blockDim.x) {
     c.active[g] = (only_item < 0 || g == only_item) ? 1 : 0;
@@ -136,23 +154,14 @@ __global__ void k_step_begin(Ctl c, int I, int only_item, double h, SourceTable 
     c.failed[g] = 0;
     c.norm_bits[g] = 0ull;
   }
+  const double t = (double)(c.step[0] + 1) * h;
+  // windowed sources whose first breakpoint lies in [t - widest window, t]
+  const int a = block_lower_bound(src.win_t0, src.n_window, t - src.win_maxw, false);
+  const int b = block_lower_bound(src.win_t0, src.n_window, t, true);
   if (threadIdx.x == 0) {
-    const double t = (double)(c.step[0] + 1) * h;
     c.t_now[0] = t;
-    // windowed sources whose first breakpoint lies in [t - widest window, t]
-    int lo = 0, hi = src.n_window;
-    while (lo < hi) {  // first t0 >= t - maxw
-      const int mid = (lo + hi) >> 1;
-      if (src.win_t0[mid] < t - src.win_maxw) lo = mid + 1; else hi = mid;
-    }
-    int a = lo;
-    hi = src.n_window;
-    while (lo < hi) {  // first t0 > t
-      const int mid = (lo + hi) >> 1;
-      if (src.win_t0[mid] <= t) lo = mid + 1; else hi = mid;
-    }
     c.src_window[0] = src.n_always + a;
-    c.src_window[1] = lo - a;
+    c.src_window[1] = b - a;
   }
 }
 
@@ -200,7 +209,7 @@ __global__ void k_decide(Ctl c, int I, const GridDesc* __restrict__ grids, int G
     c.acct[2 * (seq % nslots)] = (long long)act_nodes;
     c.acct[2 * (seq % nslots) + 1] = (long long)act_coef;
     __threadfence_system();
-    c.any_active[seq % nslots] = any;
+    c.any_active[seq % nslots] = (int32_t)(((uint32_t)seq & 0x3fffffffu) << 1 | (uint32_t)any);
     if (worked) c.stat_checks[0] += 1;
   }
 }

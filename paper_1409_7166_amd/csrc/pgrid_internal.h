@@ -122,8 +122,9 @@ hipError_t launch_sources(const SourceTable& src, const GridDesc* grids, const C
 // multi: the tiles are scenario blocks (Tile.pad consecutive scenarios of one grid)
 hipError_t launch_resid(bool fp32, bool multi, int nl, int tile_rows, const Tile* tiles, int ntiles,
                         const GridDesc* grids, const Ctl& c, int has_d, int din, hipStream_t s);
-// The decision of a residual check writes "any item still active" to flag slot
-// (*flag_seq)++ % nslots of c.any_active (host-visible memory).
+// The decision of a residual check, with sequence number q = (*flag_seq)++, writes
+// ((q & 0x3fffffff) << 1) | (any item still active) to slot q % nslots of c.any_active
+// (host-visible memory), after the slot's accounting words.
 hipError_t launch_decide(const Ctl& c, int I, const GridDesc* grids, int G, double tol, int has_d, int nchk,
                          int max_sweeps, int nslots, hipStream_t s);
 // Two red-black sweeps in one launch (tiles may be scenario blocks); reads d[din], writes d[din ^ 1].

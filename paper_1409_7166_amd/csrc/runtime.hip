@@ -19,6 +19,7 @@ using namespace pgrid;
 namespace {
 
 constexpr int kFlagSlots = 32;  // host-visible decision flags (at most 31 decisions in flight)
+constexpr uint32_t kTagMask = 0x3fffffffu;  // a decision's tag: its sequence number, masked
 
 struct Src {
   std::vector<int32_t> node, off;
@@ -129,7 +130,7 @@ struct pg_ctx {
   std::vector<hipEvent_t> flag_events;
   // profiling
   int profile_every = 0;
-  int64_t launch_counter = 0;
+  int64_t prof_count[4] = {0, 0, 0, 0};          // intervals seen per kind (sampling)
   int cur_chunk = 0;                             // refinement cycle being queued
   int pred_chunks = 1;                           // cycles the previous step needed
   std::vector<ProfEvent> prof_live;
@@ -211,7 +212,7 @@ struct ProfScope {
   bool on = false;
   ProfScope(pg_ctx* ctx, int kind, int64_t units, double bytes = 0.0, int launches = 1) : c(ctx) {
     if (c->profile_every <= 0) return;
-    if (kind == 0 && (c->launch_counter++ % c->profile_every) != 0) return;
+    if ((c->prof_count[kind]++ % c->profile_every) != 0) return;  // every k-th interval of each kind
     on = true;
     ev.a = prof_get(c);
     ev.b = prof_get(c);
@@ -642,10 +643,42 @@ pg_status begin_step(pg_ctx* c, int only_item) {
   return PG_OK;
 }
 
-// Queue the decision of a residual check; returns its flag slot (the device picks the same slot
-// from its own sequence counter) and records the slot's event after it.
-pg_status issue_decide(pg_ctx* c, double tol, int has_d, int* slot_out) {
-  const int slot = (int)(c->flag_seq_host++ % kFlagSlots);
+// Reserve the next decision: returns its tag; its flag slot is tag % kFlagSlots.  The device
+// numbers its decisions with its own counter, which this host counter mirrors.
+int next_tag(pg_ctx* c) { return (int)(c->flag_seq_host++ & kTagMask); }
+
+// Wait for the decision `tag`: spin on its host-visible flag, which the decision kernel sets to
+// (tag << 1) | any after writing its accounting words; every so often ask the slot's event
+// whether the decision has run, so a flag that can no longer arrive is reported, not awaited.
+pg_status wait_decision(pg_ctx* c, int tag, int* any) {
+  const int slot = tag % kFlagSlots;
+  const uint32_t want = (uint32_t)tag;
+  for (long spin = 1;; ++spin) {
+    const uint32_t f = (uint32_t)__atomic_load_n(c->host_flags + slot, __ATOMIC_ACQUIRE);
+    if ((f >> 1) == want) {
+      *any = (int)(f & 1u);
+      return PG_OK;
+    }
+    if ((spin & 1023) == 0) {
+      const hipError_t q = hipEventQuery(c->flag_events[slot]);
+      if (q == hipSuccess) {
+        const uint32_t g = (uint32_t)__atomic_load_n(c->host_flags + slot, __ATOMIC_ACQUIRE);
+        if ((g >> 1) == want) {
+          *any = (int)(g & 1u);
+          return PG_OK;
+        }
+        return set_err(c, PG_ERR_STATE, "decision %d: flag out of sequence", tag);
+      }
+      if (q != hipErrorNotReady) return set_err(c, PG_ERR_DEVICE, "decision wait: %s", hipGetErrorString(q));
+    }
+    __builtin_ia32_pause();
+  }
+}
+
+// Queue the decision of a residual check; returns its tag and records the slot's event after it.
+pg_status issue_decide(pg_ctx* c, double tol, int has_d, int* tag_out) {
+  const int tag = next_tag(c);
+  const int slot = tag % kFlagSlots;
   Ctl kk = c->ctl;
   kk.any_active = c->dev_flags;
   kk.acct = c->dev_acct;
@@ -656,12 +689,12 @@ pg_status issue_decide(pg_ctx* c, double tol, int has_d, int* slot_out) {
     if (e != hipSuccess) return set_err(c, PG_ERR_DEVICE, "decide launch: %s", hipGetErrorString(e));
   }
   HIP_TRY(c, hipEventRecord(c->flag_events[slot], c->stream));
-  *slot_out = slot;
+  *tag_out = tag;
   return PG_OK;
 }
 
 // One refinement cycle: check_every sweeps, the FP64 residual with v <- v + d, the decision.
-pg_status issue_cycle(pg_ctx* c, double tol, bool graphs, int* slot) {
+pg_status issue_cycle(pg_ctx* c, double tol, bool graphs, int* tag) {
   const int nchk = c->opt.check_every;
   if (graphs) {
     {
@@ -672,16 +705,16 @@ pg_status issue_cycle(pg_ctx* c, double tol, bool graphs, int* slot) {
       ProfScope ps(c, 1, 0, 0.0, (int)c->tile_groups.size());  // residual (+ the one-block decision)
       HIP_TRY(c, hipGraphLaunch(c->g_check, c->stream));
     }
-    *slot = (int)(c->flag_seq_host++ % kFlagSlots);
-    HIP_TRY(c, hipEventRecord(c->flag_events[*slot], c->stream));
+    *tag = next_tag(c);
+    HIP_TRY(c, hipEventRecord(c->flag_events[*tag % kFlagSlots], c->stream));
     return PG_OK;
   }
   PG_TRY(launch_sweeps(c, nchk));
   PG_TRY(launch_resid_all(c, 1, cycle_launches(c, nchk) & 1));
-  return issue_decide(c, tol, 1, slot);
+  return issue_decide(c, tol, 1, tag);
 }
 
-// Algorithm 1's inner loop for every active item, after the initial check (its flag slot in
+// Algorithm 1's inner loop for every active item, after the initial check (its decision tag in
 // `first`) has been queued: refinement cycles until each item's scaled residual is <= tol.
 // The host queues as many cycles as the previous step needed before waiting; past that
 // prediction it keeps `lookahead` cycles queued beyond the one whose decision it waits for.
@@ -699,18 +732,20 @@ pg_status cycle_loop(pg_ctx* c, double tol, bool graphs, int first) {
     want = std::min(want, consumed + kFlagSlots - 1);  // never reuse a slot still awaited
     while (issued < max_chunks && issued < want) {
       c->cur_chunk = ++issued;
-      int slot = 0;
-      PG_TRY(issue_cycle(c, tol, graphs, &slot));
-      pending.push_back(slot);
+      int tag = 0;
+      PG_TRY(issue_cycle(c, tol, graphs, &tag));
+      pending.push_back(tag);
     }
     if (pending.empty()) break;
-    const int s0 = pending.front();
+    const int t0 = pending.front();
     pending.pop_front();
-    HIP_TRY(c, hipEventSynchronize(c->flag_events[s0]));
+    int any = 0;
+    PG_TRY(wait_decision(c, t0, &any));
     ++consumed;
+    const int s0 = t0 % kFlagSlots;
     work.emplace_back(__atomic_load_n(c->host_acct + 2 * s0, __ATOMIC_ACQUIRE),
                       __atomic_load_n(c->host_acct + 2 * s0 + 1, __ATOMIC_ACQUIRE));
-    if (__atomic_load_n(c->host_flags + s0, __ATOMIC_ACQUIRE) == 0) {
+    if (!any) {
       last = consumed - 1;
       break;
     }
@@ -834,8 +869,8 @@ pg_status one_step(pg_ctx* c) {
       ProfScope ps(c, 3, 0);
       HIP_TRY(c, hipGraphLaunch(c->g_prologue, c->stream));
     }
-    const int first = (int)(c->flag_seq_host++ % kFlagSlots);
-    HIP_TRY(c, hipEventRecord(c->flag_events[first], c->stream));
+    const int first = next_tag(c);
+    HIP_TRY(c, hipEventRecord(c->flag_events[first % kFlagSlots], c->stream));
     c->cur_chunk = 0;
     PG_TRY(cycle_loop(c, c->opt.tol, true, first));
     HIP_TRY(c, hipGraphLaunch(c->g_epilogue, c->stream));
@@ -985,7 +1020,7 @@ pg_status pg_create(pg_ctx** out, int32_t device, void* stream) {
     pg_destroy(c);
     return PG_ERR_DEVICE;
   }
-  std::memset(c->host_flags, 0, nslots * sizeof(int32_t));
+  std::memset(c->host_flags, 0xff, nslots * sizeof(int32_t));  // no tag matches before a decision runs
   if (hipHostMalloc((void**)&c->host_acct, 2 * nslots * sizeof(long long), hipHostMallocMapped | hipHostMallocCoherent) !=
           hipSuccess ||
       hipHostGetDevicePointer((void**)&c->dev_acct, c->host_acct, 0) != hipSuccess) {
@@ -1347,7 +1382,7 @@ pg_status pg_reset_stats(pg_ctx* c) {
 pg_status pg_profile(pg_ctx* c, int32_t enable) {
   if (!c || enable < 0) return PG_ERR_INVALID_ARG;
   c->profile_every = enable;
-  c->launch_counter = 0;
+  for (auto& n : c->prof_count) n = 0;
   return PG_OK;
 }
 

@@ -1,6 +1,7 @@
-"""Parity at the full workload sizes, in the launch configuration bench.py times (its tuned omega
-and sweeps per check, graph replay).  Where the oracle cannot factor the system quickly (the
-3-layer 1024x1024 mesh), the check is the backward-Euler residual of the GPU's consecutive states
+"""Parity at the full workload sizes, in the launch configuration bench.py times (its tuned omega,
+sweeps per check, tile rows, scenario blocks and graph replay choice).  Where the oracle cannot
+factor the system quickly (the 3-layer 1024x1024 mesh), the check is the backward-Euler residual
+of the GPU's consecutive states
 evaluated with the oracle's own assembly; elsewhere every node of every step (or of sampled
 scenarios / grids) is compared with the oracle's direct solution."""
 import numpy as np
@@ -19,8 +20,8 @@ pytestmark = pytest.mark.gpu
 
 def _opts(name, prec, tol):
     t = TUNED[name]
-    return dict(precision=prec, tol=tol, omega=t["omega"], check_every=t["check_every"], graphs=1,
-                max_sweeps=200000)
+    return dict(precision=prec, tol=tol, omega=t["omega"], check_every=t["check_every"], graphs=t["graphs"],
+                max_sweeps=200000, tile_rows=t.get("tile_rows", 0), scen_block=t.get("scen_block", 0))
 
 
 @pytest.mark.timeout(600)
