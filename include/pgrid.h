@@ -160,6 +160,34 @@ pg_status pg_validate_netlist(int32_t n, int32_t p, int32_t m, const int32_t* fr
                               const int32_t* to, const uint8_t* kind, const double* value,
                               char* msg, size_t msg_len);
 
+/* The layered-mesh form of a netlist given as in pg_validate_netlist (Sec. III, eqs. 4-6; R values
+ * are conductances).  mesh_dims = {nx, ny, nl}: trivial node (layer*ny + y)*nx + x is the mesh
+ * node (x, y, layer) for the first nx*ny*nl trivial nodes; any further trivial node must be the
+ * internal node of one series R-L branch (exactly one R and one L incident).  The mapping:
+ *   R between in-layer neighbours          -> gE / gN segment (parallel resistors add),
+ *   R between (x, y, l) and (x, y, l+1)     -> via (parallel resistors add),
+ *   R from a mesh node to a source node     -> pad (parallel resistors add),
+ *   R - internal node - L (either order) between vertical neighbours, or from a mesh node to a
+ *   source node                             -> via / pad with series inductance,
+ *   C from a mesh node to ground            -> node capacitance (parallel capacitors add),
+ *   I from a mesh node to ground            -> marks a current-source position (waveforms come
+ *                                              from pg_set_pwl / pg_set_pulses).
+ * Vias come out sorted by lower node, pads by node; vdd is the common source voltage (0 when
+ * p = 0).  Anything else (a resistor to ground or between non-neighbours, a capacitor between
+ * two nodes, an inductor without its series resistor, sources at different voltages, an
+ * inductive branch in parallel with another) is PG_ERR_UNSUPPORTED; the checks of
+ * pg_validate_netlist come first.  Host-only.  pg_netlist_mesh_counts gives the via and pad
+ * counts; pg_netlist_to_mesh fills caller arrays shaped as in pg_mesh. */
+pg_status pg_netlist_mesh_counts(int32_t n, int32_t p, const double* source_v, int32_t m, const int32_t* from,
+                                 const int32_t* to, const uint8_t* kind, const double* value,
+                                 const int32_t* mesh_dims, int32_t* n_vias, int32_t* n_pads, char* msg,
+                                 size_t msg_len);
+pg_status pg_netlist_to_mesh(int32_t n, int32_t p, const double* source_v, int32_t m, const int32_t* from,
+                             const int32_t* to, const uint8_t* kind, const double* value,
+                             const int32_t* mesh_dims, double* gE, double* gN, double* C, int32_t* via_node,
+                             double* via_g, double* via_L, int32_t* pad_node, double* pad_g, double* pad_L,
+                             double* vdd, char* msg, size_t msg_len);
+
 /* Create a context on HIP device `device` (must be gfx950).  `stream` is a hipStream_t
  * (for instance torch.cuda.current_stream().cuda_stream) or NULL for a stream owned by
  * the context.  Every kernel and copy of the context runs on that stream. */
@@ -175,6 +203,13 @@ pg_status pg_get_options(const pg_ctx* ctx, pg_options* out);
  * The state starts at v = vdd on every node and zero inductor current.  Returns the grid
  * id (0, 1, ...) in *grid_id.  All grids of a context advance together in time. */
 pg_status pg_upload_mesh(pg_ctx* ctx, const pg_mesh* mesh, int32_t n_scen, int32_t* grid_id);
+
+/* Upload a netlist (Sec. III branch form) through its layered-mesh form (pg_netlist_to_mesh),
+ * then as pg_upload_mesh.  Errors as in pg_netlist_to_mesh, with the message in
+ * pg_last_error. */
+pg_status pg_upload_netlist(pg_ctx* ctx, int32_t n, int32_t p, const double* source_v, int32_t m,
+                            const int32_t* from, const int32_t* to, const uint8_t* kind, const double* value,
+                            const int32_t* mesh_dims, int32_t n_scen, int32_t* grid_id);
 
 /* Replace the current sources of one scenario by triangular pulses (one per node, nodes
  * unique): i(t) = peak * max(0, 1 - |t - (start + width/2)| / (width/2)), width > 0. */

@@ -5,10 +5,10 @@ refinement, inductor update) runs in the gfx950 kernels of ``libpgrid.so``;
 ``pgrid`` is its ctypes binding.  Build the library with
 ``python -m paper_1409_7166_amd.build``.
 """
-from .pgrid import (Context, Options, PgError, default_options, lib, validate_mesh,
-                    validate_netlist, validate_options, PG_PREC_FP64, PG_PREC_FP32_REFINE,
+from .pgrid import (Context, NetlistMesh, Options, PgError, default_options, lib, netlist_to_mesh,
+                    validate_mesh, validate_netlist, validate_options, PG_PREC_FP64, PG_PREC_FP32_REFINE,
                     PG_ORDER_RED_BLACK, PG_ORDER_JACOBI)
 
-__all__ = ["Context", "Options", "PgError", "default_options", "lib", "validate_mesh",
-           "validate_netlist", "validate_options", "PG_PREC_FP64", "PG_PREC_FP32_REFINE",
+__all__ = ["Context", "NetlistMesh", "Options", "PgError", "default_options", "lib", "netlist_to_mesh",
+           "validate_mesh", "validate_netlist", "validate_options", "PG_PREC_FP64", "PG_PREC_FP32_REFINE",
            "PG_ORDER_RED_BLACK", "PG_ORDER_JACOBI"]

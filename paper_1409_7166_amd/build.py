@@ -19,7 +19,7 @@ OBJ = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libpgrid.so")
 
 HIP_SOURCES = ["kernels.hip", "runtime.hip"]
-HOST_SOURCES = ["validate.cpp"]
+HOST_SOURCES = ["validate.cpp", "netlist.cpp"]
 ARCH = "gfx950"
 
 HIPCC_FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",

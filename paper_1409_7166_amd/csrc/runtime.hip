@@ -152,6 +152,17 @@ pg_status set_err(pg_ctx* c, pg_status st, const char* fmt, ...) {
   return st;
 }
 
+}  // namespace
+
+namespace pgrid {
+// Records a message as the context's last error (used by the host-side netlist mapping).
+__attribute__((visibility("hidden"))) pg_status report_error(pg_ctx* c, pg_status st, const char* msg) {
+  return set_err(c, st, "%s", msg);
+}
+}  // namespace pgrid
+
+namespace {
+
 #define HIP_TRY(ctx, expr)                                                                \
   do {                                                                                    \
     hipError_t e_ = (expr);                                                               \

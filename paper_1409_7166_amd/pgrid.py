@@ -81,12 +81,27 @@ EXPORTS = {
     "pg_validate_netlist": (C.c_int, [C.c_int32, C.c_int32, C.c_int32, C.POINTER(C.c_int32),
                                       C.POINTER(C.c_int32), C.POINTER(C.c_uint8), C.POINTER(C.c_double),
                                       C.c_char_p, C.c_size_t]),
+    "pg_netlist_mesh_counts": (C.c_int, [C.c_int32, C.c_int32, C.POINTER(C.c_double), C.c_int32,
+                                         C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.POINTER(C.c_uint8),
+                                         C.POINTER(C.c_double), C.POINTER(C.c_int32), C.POINTER(C.c_int32),
+                                         C.POINTER(C.c_int32), C.c_char_p, C.c_size_t]),
+    "pg_netlist_to_mesh": (C.c_int, [C.c_int32, C.c_int32, C.POINTER(C.c_double), C.c_int32,
+                                     C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.POINTER(C.c_uint8),
+                                     C.POINTER(C.c_double), C.POINTER(C.c_int32), C.POINTER(C.c_double),
+                                     C.POINTER(C.c_double), C.POINTER(C.c_double), C.POINTER(C.c_int32),
+                                     C.POINTER(C.c_double), C.POINTER(C.c_double), C.POINTER(C.c_int32),
+                                     C.POINTER(C.c_double), C.POINTER(C.c_double), C.POINTER(C.c_double),
+                                     C.c_char_p, C.c_size_t]),
     "pg_create": (C.c_int, [C.POINTER(C.c_void_p), C.c_int32, C.c_void_p]),
     "pg_destroy": (None, [C.c_void_p]),
     "pg_last_error": (C.c_char_p, [C.c_void_p]),
     "pg_set_options": (C.c_int, [C.c_void_p, C.POINTER(Options)]),
     "pg_get_options": (C.c_int, [C.c_void_p, C.POINTER(Options)]),
     "pg_upload_mesh": (C.c_int, [C.c_void_p, C.POINTER(MeshStruct), C.c_int32, C.POINTER(C.c_int32)]),
+    "pg_upload_netlist": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.POINTER(C.c_double), C.c_int32,
+                                    C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.POINTER(C.c_uint8),
+                                    C.POINTER(C.c_double), C.POINTER(C.c_int32), C.c_int32,
+                                    C.POINTER(C.c_int32)]),
     "pg_set_pulses": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.POINTER(C.c_int32),
                                 C.POINTER(C.c_double), C.POINTER(C.c_double), C.POINTER(C.c_double)]),
     "pg_set_pwl": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.POINTER(C.c_int32),
@@ -184,17 +199,76 @@ def validate_mesh(mesh):
     return st, buf.value.decode()
 
 
-def validate_netlist(n, p, frm, to, kind, value):
-    """Host-only check of a branch list (kinds 'R', 'C', 'L', 'I'); returns (status, message)."""
-    frm, to, value = _i32(frm), _i32(to), _f64(value)
+def _kinds(kind):
     k = np.asarray(kind)
     if k.dtype.kind in "US":
         k = np.frombuffer("".join(k.astype(str).ravel().tolist()).encode(), np.uint8)
-    k = np.ascontiguousarray(k, dtype=np.uint8)
+    return np.ascontiguousarray(k, dtype=np.uint8)
+
+
+def validate_netlist(n, p, frm, to, kind, value):
+    """Host-only check of a branch list (kinds 'R', 'C', 'L', 'I'); returns (status, message)."""
+    frm, to, value = _i32(frm), _i32(to), _f64(value)
+    k = _kinds(kind)
     buf = _msgbuf()
     st = lib().pg_validate_netlist(int(n), int(p), int(frm.size), _ip(frm), _ip(to),
                                    k.ctypes.data_as(C.POINTER(C.c_uint8)), _dp(value), buf, 512)
     return st, buf.value.decode()
+
+
+@dataclass
+class NetlistMesh:
+    """The layered-mesh form of a netlist (the fields of a ``pg_mesh``)."""
+    nx: int
+    ny: int
+    nl: int
+    gE: np.ndarray
+    gN: np.ndarray
+    C: np.ndarray
+    via_node: np.ndarray
+    via_g: np.ndarray
+    via_L: np.ndarray
+    pad_node: np.ndarray
+    pad_g: np.ndarray
+    pad_L: np.ndarray
+    vdd: float
+
+    @property
+    def n(self) -> int:
+        return self.nl * self.ny * self.nx
+
+
+def _netlist_args(n, p, source_v, frm, to, kind, value, dims):
+    return (int(n), int(p), _f64(np.asarray(source_v, float).reshape(-1)), _i32(frm), _i32(to), _kinds(kind),
+            _f64(value), _i32(np.asarray(dims).reshape(3)))
+
+
+def netlist_to_mesh(n, p, source_v, frm, to, kind, value, dims):
+    """Host-only: the mesh form of a netlist (pg_netlist_to_mesh); raises PGError if it has none."""
+    n, p, sv, frm, to, k, value, dims = _netlist_args(n, p, source_v, frm, to, kind, value, dims)
+    buf = _msgbuf()
+    nv, npd = C.c_int32(), C.c_int32()
+    kp = k.ctypes.data_as(C.POINTER(C.c_uint8))
+    st = lib().pg_netlist_mesh_counts(n, p, _dp(sv), int(frm.size), _ip(frm), _ip(to), kp, _dp(value), _ip(dims),
+                                      C.byref(nv), C.byref(npd), buf, 512)
+    if st != 0:
+        raise PgError(st, buf.value.decode())
+    nx, ny, nl = (int(d) for d in dims)
+    out = NetlistMesh(nx, ny, nl, np.zeros(nl * ny * (nx - 1)), np.zeros(nl * (ny - 1) * nx), np.zeros(nx * ny * nl),
+                      np.zeros(nv.value, np.int32), np.zeros(nv.value), np.zeros(nv.value),
+                      np.zeros(npd.value, np.int32), np.zeros(npd.value), np.zeros(npd.value), 0.0)
+    vdd = C.c_double()
+    st = lib().pg_netlist_to_mesh(n, p, _dp(sv), int(frm.size), _ip(frm), _ip(to), kp, _dp(value), _ip(dims),
+                                  _dp(out.gE), _dp(out.gN), _dp(out.C), _ip(out.via_node), _dp(out.via_g),
+                                  _dp(out.via_L), _ip(out.pad_node), _dp(out.pad_g), _dp(out.pad_L),
+                                  C.byref(vdd), buf, 512)
+    if st != 0:
+        raise PgError(st, buf.value.decode())
+    out.vdd = vdd.value
+    out.gE = out.gE.reshape(nl, ny, nx - 1)
+    out.gN = out.gN.reshape(nl, ny - 1, nx)
+    out.C = out.C.reshape(nl, ny, nx)
+    return out
 
 
 def default_options(**kw) -> Options:
@@ -267,6 +341,17 @@ class Context:
         hold = mesh_struct(mesh)
         gid = C.c_int32()
         self._check(lib().pg_upload_mesh(self._h, C.byref(hold.struct), int(n_scen), C.byref(gid)))
+        self.meshes.append(mesh)
+        return gid.value
+
+    def upload_netlist(self, n, p, source_v, frm, to, kind, value, dims, n_scen: int = 1) -> int:
+        """Upload a netlist through its layered-mesh form (pg_upload_netlist)."""
+        mesh = netlist_to_mesh(n, p, source_v, frm, to, kind, value, dims)  # shapes for later reads
+        n, p, sv, frm, to, k, value, dims = _netlist_args(n, p, source_v, frm, to, kind, value, dims)
+        gid = C.c_int32()
+        self._check(lib().pg_upload_netlist(self._h, n, p, _dp(sv), int(frm.size), _ip(frm), _ip(to),
+                                            k.ctypes.data_as(C.POINTER(C.c_uint8)), _dp(value), _ip(dims),
+                                            int(n_scen), C.byref(gid)))
         self.meshes.append(mesh)
         return gid.value
 

@@ -7,7 +7,7 @@ import numpy as np
 import pytest
 
 import paper_1409_7166_amd as pg
-from helpers import PARITY_V, compressed, gpu_context, oracle_run, say
+from helpers import PARITY_V, compressed, gpu_context, oracle_run, say, torch_stream
 from oracle import BEStepper, dc_solve, mesh_to_circuit
 from workloads import Pulses, config0, small_multilayer, small_rc, small_rlc
 
@@ -228,6 +228,34 @@ def test_two_sweeps_per_launch_equal_two_launches(case):
     err = np.max(np.abs(res[2][0][0] - Vref[-1]))
     say(f"  sweeps={res[2][1]['sweeps']} err={err:.3e}")
     assert err <= PARITY_V
+
+
+def test_netlist_upload_equals_mesh_upload():
+    """An RLC grid uploaded as the oracle's branch list (pg_upload_netlist) steps bit for bit like
+    the same grid uploaded as a mesh, and both match the oracle."""
+    w = small_rlc(side=40, seed=61, steps=25)
+    mesh = w.meshes[0]
+    p = compressed(w.pulses[0][0], start=0.02, width=0.2)
+    w.pulses[0][0] = p
+    circ, _ = mesh_to_circuit(mesh, p)
+    say("[gpu] netlist upload vs mesh upload (RLC 2x40x40)")
+    opts = dict(precision=pg.PG_PREC_FP64, tol=1e-11, omega=1.6)
+    with gpu_context(w, **opts) as ctx:
+        ctx.step(25)
+        v_mesh, i_mesh = ctx.read_voltages(), ctx.read_inductor_currents()
+    ctx = pg.Context(0, torch_stream())
+    base = dict(h=w.h, check_every=8)
+    base.update(opts)
+    ctx.set_options(**base)
+    with ctx:
+        gid = ctx.upload_netlist(circ.n, circ.p, circ.vd, circ.frm, circ.to, circ.kind, circ.value,
+                                 (mesh.nx, mesh.ny, mesh.nl))
+        ctx.set_pulses(gid, 0, p)
+        ctx.step(25)
+        v_net, i_net = ctx.read_voltages(), ctx.read_inductor_currents()
+    assert np.array_equal(v_mesh, v_net) and np.array_equal(i_mesh, i_net)
+    Vref, _ = oracle_run(mesh, p, w.h, 25)
+    assert np.max(np.abs(v_net - Vref[-1])) <= PARITY_V
 
 
 def test_uneven_grids_batched_in_one_launch():
