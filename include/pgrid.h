@@ -233,6 +233,18 @@ pg_status pg_set_state(pg_ctx* ctx, int32_t grid, int32_t scen, const double* v,
 /* Back to t = 0: every state to v = vdd, zero inductor currents; statistics cleared. */
 pg_status pg_reset(pg_ctx* ctx);
 
+/* DC operating point with the sources at time index k (t = k h; Sec. II-A eq. 3 with the
+ * capacitors open, and each series R-L branch reduced to its resistor since an inductor is a
+ * short at DC), solved for every grid and scenario by the same relaxation sweeps from the
+ * current state, with the given omega (0: the context's; the DC matrix is worse conditioned
+ * than a step's, so its best omega is larger), tol and max_sweeps.  Sets every state to the DC
+ * voltages and branch currents i = g (v_a - v_b), and the time index to k, so that pg_step
+ * continues the transient from that operating point (the initial-condition recipe with
+ * non-zero loads at the start).  PG_ERR_NOT_SPD if a connected part of a grid reaches no pad
+ * (the DC matrix is singular); PG_ERR_NO_CONVERGENCE leaves the last iterate as the state and
+ * the time index unchanged. */
+pg_status pg_dc_operating_point(pg_ctx* ctx, int64_t k, double omega, double tol, int32_t max_sweeps);
+
 /* Advance every grid and scenario by nsteps backward-Euler steps (Algorithm 1 loop:
  * warm start from the previous step, sweep until the scaled residual is <= tol). */
 pg_status pg_step(pg_ctx* ctx, int32_t nsteps);

@@ -75,6 +75,7 @@ struct pg_ctx {
   std::string err;
   std::vector<GridHost> grids;
   bool dirty = true;
+  bool dc_mode = false;                          // coefficients of the DC matrix (C open, L shorted)
   int64_t step = 0;
   double seconds = 0.0;
   // device tables
@@ -274,6 +275,9 @@ int n_items(const pg_ctx* c) {
 pg_status build_grid(pg_ctx* c, int gi) {
   GridHost& G = c->grids[gi];
   const double h = c->opt.h;
+  // DC matrix (the limit h -> infinity): no C/h, and a series R-L branch is its resistor
+  // (g_eq -> 1/R, alpha -> 0), so the branch update gives the DC current g (v_a - v_b)
+  const bool dc = c->dc_mode;
   const int nx = G.nx, ny = G.ny, nl = G.nl, X = G.X;
   const int64_t ns = G.nstore, PS = (int64_t)X * ny;  // storage slots, storage layer stride
   auto sidx = [&](int64_t node) { return G.storage(node); };
@@ -284,7 +288,7 @@ pg_status build_grid(pg_ctx* c, int gi) {
         const int64_t i = (int64_t)l * PS + (int64_t)y * X + x;
         if (x + 1 < nx) gE[i] = G.gE[((int64_t)l * ny + y) * (nx - 1) + x];
         if (y + 1 < ny) gN[i] = G.gN[((int64_t)l * (ny - 1) + y) * nx + x];
-        ch[i] = G.C[((int64_t)l * ny + y) * nx + x] / h;
+        ch[i] = dc ? 0.0 : G.C[((int64_t)l * ny + y) * nx + x] / h;
       }
   G.ind_a.clear(); G.ind_b.clear(); G.ind_branch.clear();
   std::vector<double> geq, alpha;
@@ -294,9 +298,10 @@ pg_status build_grid(pg_ctx* c, int gi) {
     const double L = G.via_L.empty() ? 0.0 : G.via_L[k];
     if (L > 0) {
       const double R = 1.0 / G.via_g[k];
-      gU[a] += h / (L + h * R);
+      const double g = dc ? G.via_g[k] : h / (L + h * R);
+      gU[a] += g;
       G.ind_a.push_back((int32_t)a); G.ind_b.push_back((int32_t)(a + PS)); G.ind_branch.push_back(k);
-      geq.push_back(h / (L + h * R)); alpha.push_back(L / (L + h * R));
+      geq.push_back(g); alpha.push_back(dc ? 0.0 : L / (L + h * R));
     } else {
       gU[a] += G.via_g[k];
     }
@@ -307,9 +312,9 @@ pg_status build_grid(pg_ctx* c, int gi) {
     double g = G.pad_g[k];
     if (L > 0) {
       const double R = 1.0 / G.pad_g[k];
-      g = h / (L + h * R);
+      if (!dc) g = h / (L + h * R);
       G.ind_a.push_back((int32_t)a); G.ind_b.push_back(-1); G.ind_branch.push_back(nv + k);
-      geq.push_back(g); alpha.push_back(L / (L + h * R));
+      geq.push_back(g); alpha.push_back(dc ? 0.0 : L / (L + h * R));
     }
     D[a] += g;
     bc[a] += g * G.vdd;
@@ -1246,6 +1251,82 @@ pg_status pg_reset(pg_ctx* c) {
   PG_TRY(reset_stats_dev(c));
   HIP_TRY(c, hipStreamSynchronize(c->stream));
   return PG_OK;
+}
+
+namespace {
+
+// With capacitors open, every connected part of a grid's conductance graph must reach a pad,
+// or the DC matrix is singular.
+bool dc_anchored(const GridHost& G) {
+  const int64_t n = G.n, plane = (int64_t)G.nx * G.ny;
+  std::vector<int64_t> parent(n);
+  for (int64_t i = 0; i < n; ++i) parent[i] = i;
+  auto find = [&](int64_t i) {
+    while (parent[i] != i) i = parent[i] = parent[parent[i]];
+    return i;
+  };
+  auto unite = [&](int64_t a, int64_t b) { parent[find(a)] = find(b); };
+  for (int l = 0; l < G.nl; ++l)
+    for (int y = 0; y < G.ny; ++y)
+      for (int x = 0; x < G.nx; ++x) {
+        const int64_t i = (int64_t)l * plane + (int64_t)y * G.nx + x;
+        if (x + 1 < G.nx && G.gE[((int64_t)l * G.ny + y) * (G.nx - 1) + x] > 0) unite(i, i + 1);
+        if (y + 1 < G.ny && G.gN[((int64_t)l * (G.ny - 1) + y) * G.nx + x] > 0) unite(i, i + G.nx);
+      }
+  for (int32_t v : G.via_node) unite(v, v + plane);
+  std::vector<char> ok(n, 0);
+  for (int32_t p : G.pad_node) ok[find(p)] = 1;
+  for (int64_t i = 0; i < n; ++i)
+    if (!ok[find(i)]) return false;
+  return true;
+}
+
+}  // namespace
+
+pg_status pg_dc_operating_point(pg_ctx* c, int64_t k, double omega, double tol, int32_t max_sweeps) {
+  if (!c) return PG_ERR_INVALID_ARG;
+  if (k < 0 || !(std::isfinite(tol) && tol > 0) || max_sweeps < 1 || !(omega >= 0 && omega < 2))
+    return set_err(c, PG_ERR_INVALID_ARG, "need k >= 0, tol > 0, max_sweeps >= 1 and 0 <= omega < 2");
+  HIP_TRY(c, hipSetDevice(c->device));
+  PG_TRY(prepare(c));
+  for (int g = 0; g < (int)c->grids.size(); ++g)
+    if (!dc_anchored(c->grids[g]))
+      return set_err(c, PG_ERR_NOT_SPD, "grid %d: a connected part reaches no pad, so the DC matrix is singular", g);
+  const pg_options saved = c->opt;
+  const int64_t saved_step = c->step;
+  const int saved_pred = c->pred_chunks;
+  drop_graphs(c);
+  c->dc_mode = true;
+  pg_status st = PG_OK;
+  for (int g = 0; g < (int)c->grids.size() && st == PG_OK; ++g) st = build_grid(c, g);
+  if (omega > 0) c->opt.omega = omega;
+  c->opt.tol = tol;
+  c->opt.max_sweeps = max_sweeps;
+  c->pred_chunks = 1;
+  // the sources at t = k h: the step clock's next time is (step + 1) h
+  if (st == PG_OK) st = set_step(c, k - 1);
+  if (st == PG_OK) st = begin_step(c, -1);
+  if (st == PG_OK) st = solve_active(c, tol);
+  if (st == PG_OK) st = end_step(c, 0);  // branch currents g (v_a - v_b); no step, no statistics
+  // back to the transient matrix, even after a failure
+  c->dc_mode = false;
+  c->opt = saved;
+  c->pred_chunks = saved_pred;
+  for (int g = 0; g < (int)c->grids.size(); ++g) {
+    const pg_status s2 = build_grid(c, g);
+    if (st == PG_OK) st = s2;
+  }
+  PG_TRY(st);
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  int32_t failed = 0;
+  HIP_TRY(c, hipMemcpy(&failed, c->ctl.stat_failed, sizeof failed, hipMemcpyDeviceToHost));
+  if (failed) {
+    HIP_TRY(c, hipMemset(c->ctl.stat_failed, 0, sizeof(int32_t)));
+    PG_TRY(set_step(c, saved_step));
+    return set_err(c, PG_ERR_NO_CONVERGENCE, "the DC solve reached max_sweeps = %d with the residual above tol = %g",
+                   max_sweeps, tol);
+  }
+  return set_step(c, k);
 }
 
 pg_status pg_step(pg_ctx* c, int32_t nsteps) { return pg_run_transient(c, nsteps, 1, 0, 0, nullptr); }

@@ -108,6 +108,7 @@ EXPORTS = {
                              C.POINTER(C.c_int32), C.POINTER(C.c_double), C.POINTER(C.c_double)]),
     "pg_set_state": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_double)]),
     "pg_reset": (C.c_int, [C.c_void_p]),
+    "pg_dc_operating_point": (C.c_int, [C.c_void_p, C.c_int64, C.c_double, C.c_double, C.c_int32]),
     "pg_step": (C.c_int, [C.c_void_p, C.c_int32]),
     "pg_run_transient": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.c_int32,
                                    C.POINTER(C.c_double)]),
@@ -372,6 +373,10 @@ class Context:
 
     def reset(self):
         self._check(lib().pg_reset(self._h))
+
+    def dc_operating_point(self, k: int = 0, omega: float = 0.0, tol: float = 1e-10, max_sweeps: int = 100000):
+        """Set every state to the DC point with the sources at t = k h, and the clock to k."""
+        self._check(lib().pg_dc_operating_point(self._h, int(k), float(omega), float(tol), int(max_sweeps)))
 
     # -- stepping --------------------------------------------------------------------------
     def step(self, nsteps: int = 1):
