@@ -245,6 +245,26 @@ pg_status pg_reset(pg_ctx* ctx);
  * the time index unchanged. */
 pg_status pg_dc_operating_point(pg_ctx* ctx, int64_t k, double omega, double tol, int32_t max_sweeps);
 
+/* Spectral radius rho of the Jacobi iteration matrix I - D^-1 M of grid `grid`'s step matrix
+ * (dc = 1: of its DC matrix), by `iters` (>= 32, rounded up to a multiple of 16) power
+ * iterations of a Jacobi sweep on the device, and Young's optimal relaxation factor for the
+ * red-black ordering, omega_opt = 2 / (1 + sqrt(1 - rho^2)) (eq. 17's omega; the mesh graph
+ * is bipartite, so the red-black ordered matrix is consistently ordered).  The estimate is the
+ * growth of the max-norm over the last 16 applications; its error falls like the ratio of the
+ * two largest eigenvalue magnitudes to the power of the iteration count.  The grid's correction
+ * buffers are overwritten (the state is not).  PG_ERR_NOT_SPD for dc = 1 as in
+ * pg_dc_operating_point. */
+pg_status pg_estimate_omega(pg_ctx* ctx, int32_t grid, int32_t dc, int32_t iters, double* rho,
+                            double* omega_opt);
+
+/* Error-bound factor kappa = ||M^-1 D||_inf of grid `grid`'s step matrix (D its diagonal),
+ * computed as max_i x_i of the solution of M x = D 1 (M is an M-matrix, so M^-1 >= 0) by the
+ * relaxation sweeps to a scaled residual of rel_tol (so kappa carries a relative error of
+ * about rel_tol * kappa).  A step stopped at a scaled residual max_i |r_i| / M_ii <= tol is
+ * within kappa * tol volts of the exact backward-Euler solution, so tol = err / kappa asks for
+ * a voltage error err (the adaptive tolerance).  The state of the grid is restored. */
+pg_status pg_error_bound_factor(pg_ctx* ctx, int32_t grid, double rel_tol, double* kappa);
+
 /* Advance every grid and scenario by nsteps backward-Euler steps (Algorithm 1 loop:
  * warm start from the previous step, sweep until the scaled residual is <= tol). */
 pg_status pg_step(pg_ctx* ctx, int32_t nsteps);

@@ -1114,6 +1114,53 @@ __global__ __launch_bounds__(kThreads) void k_state_copy(const Tile* __restrict_
 }
 
 // Exchange the buffer index of one item with a saved value (switching between two state views).
+// Vector utilities on one item's tiles (one workgroup per tile): op 0 sets d[which] to 1 on the
+// mesh nodes (0 in the padding) and r to 0; op 1 takes max |d[which]| and op 4 max |v| over
+// the mesh nodes into norm_bits[item]; op 2 scales d[which] by s; op 3 sets v = 0 and b = M_ii.
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_item_vec(const Tile* __restrict__ tiles, int ntiles, int TY,
+                                                      const GridDesc* __restrict__ grids, Ctl c, int op,
+                                                      int which, double s) {
+  __shared__ double wmax[kThreads / 64];
+  const int ti = blockIdx.x;
+  if (ti >= ntiles) return;
+  const Tile tl = tiles[ti];
+  const GridDesc& G = grids[tl.grid];
+  const int nx = G.nx, X = G.X, ny = G.ny;
+  const int64_t P = (int64_t)X * ny;
+  const int64_t off = (int64_t)tl.scen * G.nstore;
+  T* __restrict__ d = static_cast<T*>(G.d[which]) + off;
+  T* __restrict__ r = static_cast<T*>(G.r) + off;
+  double* __restrict__ v = G.v[c.vidx[tl.item]] + off;
+  double* __restrict__ b = G.b + off;
+  const int per_layer = kTileX * TY;
+  double m = 0.0;
+  for (int k = threadIdx.x; k < per_layer * G.nl; k += kThreads) {
+    const int l = k / per_layer, rem = k - l * per_layer;
+    const int yy = rem / kTileX, xx = rem - yy * kTileX;
+    const int x = tl.x0 + xx, y = tl.y0 + yy;
+    if (x >= X || y >= ny) continue;
+    const int64_t i = l * P + (int64_t)y * X + x;
+    const bool real = x < nx;
+    switch (op) {
+      case 0: d[i] = real ? T(1) : T(0); r[i] = T(0); break;
+      case 1: if (real) m = fmax(m, fabs((double)d[i])); break;
+      case 2: d[i] = (T)((double)d[i] * s); break;
+      case 3: v[i] = 0.0; b[i] = real ? G.D64[i] : 0.0; break;
+      default: if (real) m = fmax(m, fabs(v[i])); break;
+    }
+  }
+  if (op != 1 && op != 4) return;
+  for (int o = 32; o > 0; o >>= 1) m = fmax(m, __shfl_xor(m, o, 64));
+  if ((threadIdx.x & 63) == 0) wmax[threadIdx.x >> 6] = m;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double bm = wmax[0];
+    for (int w = 1; w < kThreads / 64; ++w) bm = fmax(bm, wmax[w]);
+    atomicMax(&c.norm_bits[tl.item], (unsigned long long)__double_as_longlong(bm));
+  }
+}
+
 __global__ void k_swap_vidx(Ctl c, int item, int32_t* saved) {
   if (threadIdx.x == 0 && blockIdx.x == 0) {
     const int32_t t = c.vidx[item];
@@ -1127,6 +1174,18 @@ hipError_t launch_state_copy(const Tile* tiles, int ntiles, int tile_rows, const
   if (ntiles <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_state_copy, dim3(ntiles), dim3(kThreads), 0, s, tiles, ntiles, tile_rows, grids, c, buf,
                      to_buf);
+  return hipGetLastError();
+}
+
+hipError_t launch_item_vec(bool fp32, const Tile* tiles, int ntiles, int tile_rows, const GridDesc* grids,
+                           const Ctl& c, int op, int which, double s, hipStream_t st) {
+  if (ntiles <= 0) return hipSuccess;
+  if (fp32)
+    hipLaunchKernelGGL(k_item_vec<float>, dim3(ntiles), dim3(kThreads), 0, st, tiles, ntiles, tile_rows, grids, c,
+                       op, which, s);
+  else
+    hipLaunchKernelGGL(k_item_vec<double>, dim3(ntiles), dim3(kThreads), 0, st, tiles, ntiles, tile_rows, grids, c,
+                       op, which, s);
   return hipGetLastError();
 }
 

@@ -144,6 +144,9 @@ hipError_t launch_adj_grad(const Tile* tiles, int ntiles, int tile_rows, const G
                            double* dgN, hipStream_t s);
 hipError_t launch_state_copy(const Tile* tiles, int ntiles, int tile_rows, const GridDesc* grids, const Ctl& c,
                              double* buf, int to_buf, hipStream_t s);
+// One item's vector utilities (op codes at k_item_vec); tiles are the item's tiles.
+hipError_t launch_item_vec(bool fp32, const Tile* tiles, int ntiles, int tile_rows, const GridDesc* grids,
+                           const Ctl& c, int op, int which, double s, hipStream_t st);
 hipError_t launch_swap_vidx(const Ctl& c, int item, int32_t* saved, hipStream_t s);
 hipError_t launch_inductors(const GridDesc* grids, const int32_t* ind_grid,
                             const int32_t* ind_local, int n_total, const Ctl& c, hipStream_t s);

@@ -1329,6 +1329,120 @@ pg_status pg_dc_operating_point(pg_ctx* c, int64_t k, double omega, double tol, 
   return set_step(c, k);
 }
 
+namespace {
+
+// One item's vector utility (k_item_vec) on its own tiles.
+pg_status item_vec(pg_ctx* c, int item, int op, int which, double scale) {
+  const Tile* T = (const Tile*)c->tiles_all.p + c->item_tile_off[item];
+  hipError_t e = launch_item_vec(fp32_mode(c), T, c->item_tile_cnt[item], c->tile_rows,
+                                 (const GridDesc*)c->grid_desc.p, c->ctl, op, which, scale, c->stream);
+  return e == hipSuccess ? PG_OK : set_err(c, PG_ERR_DEVICE, "vector kernel: %s", hipGetErrorString(e));
+}
+
+// max |d[which]| (op 1) or max |v| (op 4) over the item's mesh nodes.
+pg_status item_absmax(pg_ctx* c, int item, int op, int which, double* out) {
+  HIP_TRY(c, hipMemsetAsync((unsigned long long*)c->c_norm.p + item, 0, sizeof(unsigned long long), c->stream));
+  PG_TRY(item_vec(c, item, op, which, 0.0));
+  unsigned long long bits = 0;
+  HIP_TRY(c, hipMemcpyAsync(&bits, (unsigned long long*)c->c_norm.p + item, sizeof bits, hipMemcpyDeviceToHost,
+                            c->stream));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  std::memcpy(out, &bits, sizeof bits);
+  return PG_OK;
+}
+
+// Activate one item (the others exit at once) without forming a right-hand side.
+pg_status activate_only(pg_ctx* c, int item) {
+  hipError_t e = launch_step_begin(c->ctl, n_items(c), item, c->opt.h, c->src_table, c->stream);
+  return e == hipSuccess ? PG_OK : set_err(c, PG_ERR_DEVICE, "activation: %s", hipGetErrorString(e));
+}
+
+}  // namespace
+
+pg_status pg_estimate_omega(pg_ctx* c, int32_t grid, int32_t dc, int32_t iters, double* rho, double* omega_opt) {
+  PG_TRY(check_gs(c, grid, 0));
+  if (iters < 32 || (dc != 0 && dc != 1) || !rho || !omega_opt)
+    return set_err(c, PG_ERR_INVALID_ARG, "need iters >= 32, dc in {0, 1} and output pointers");
+  HIP_TRY(c, hipSetDevice(c->device));
+  PG_TRY(prepare(c));
+  if (dc && !dc_anchored(c->grids[grid]))
+    return set_err(c, PG_ERR_NOT_SPD, "grid %d: a connected part reaches no pad, so the DC matrix is singular", grid);
+  const int item = c->grids[grid].item0;
+  drop_graphs(c);
+  c->dc_mode = dc != 0;
+  pg_status st = PG_OK;
+  if (dc)
+    for (int g = 0; g < (int)c->grids.size() && st == PG_OK; ++g) st = build_grid(c, g);
+  // power iteration with the Jacobi operator J = D^-1 (D - M) (a weighted Jacobi sweep with
+  // omega = 1 on M d = 0), renormalised every 16 applications; J^16 has the eigenvalues
+  // lambda^16 >= 0, so the growth over a block estimates rho(J)^16 without the sign flips of
+  // the +-lambda pairs of a bipartite graph
+  const Tile* T = (const Tile*)c->tiles_sweep.p;
+  double est = 0.0;
+  if (st == PG_OK) st = activate_only(c, item);
+  if (st == PG_OK) st = item_vec(c, item, 0, 0, 0.0);
+  const int blocks = (iters + 15) / 16;
+  for (int blk = 0; blk < blocks && st == PG_OK; ++blk) {
+    for (int k = 0; k < 16 && st == PG_OK; ++k)
+      for (auto& grp : c->tile_groups) {
+        hipError_t e = launch_sweep(fp32_mode(c), grp.multi, PG_ORDER_JACOBI, grp.nl, c->tile_rows, T + grp.off,
+                                    grp.count, (const GridDesc*)c->grid_desc.p, c->ctl, k & 1, 0, 1.0, c->stream);
+        if (e != hipSuccess) st = set_err(c, PG_ERR_DEVICE, "Jacobi launch: %s", hipGetErrorString(e));
+      }
+    double nrm = 0.0;
+    if (st == PG_OK) st = item_absmax(c, item, 1, 0, &nrm);  // 16 applications end in d[0]
+    if (st != PG_OK) break;
+    if (!(nrm > 0) || !std::isfinite(nrm)) { est = 0.0; break; }
+    est = std::pow(nrm, 1.0 / 16.0);
+    st = item_vec(c, item, 2, 0, 1.0 / nrm);
+  }
+  if (c->dc_mode) {
+    c->dc_mode = false;
+    for (int g = 0; g < (int)c->grids.size(); ++g) {
+      const pg_status s2 = build_grid(c, g);
+      if (st == PG_OK) st = s2;
+    }
+  }
+  PG_TRY(st);
+  *rho = est;
+  *omega_opt = est < 1.0 ? 2.0 / (1.0 + std::sqrt(1.0 - est * est)) : 1.99;
+  return PG_OK;
+}
+
+pg_status pg_error_bound_factor(pg_ctx* c, int32_t grid, double rel_tol, double* kappa) {
+  PG_TRY(check_gs(c, grid, 0));
+  if (!(std::isfinite(rel_tol) && rel_tol > 0) || !kappa)
+    return set_err(c, PG_ERR_INVALID_ARG, "need rel_tol > 0 and an output pointer");
+  HIP_TRY(c, hipSetDevice(c->device));
+  PG_TRY(prepare(c));
+  GridHost& H = c->grids[grid];
+  const int item = H.item0;
+  DBuf keep;
+  PG_TRY(dalloc(c, keep, (size_t)H.nstore * sizeof(double)));
+  PG_TRY(state_copy(c, item, (double*)keep.p, 1));
+  const int saved_pred = c->pred_chunks;
+  c->pred_chunks = 1;
+  // x = M^-1 D 1 from x = 0: b = diag(M); every entry of x is >= 1 and its maximum is the
+  // infinity norm of M^-1 D (M is an M-matrix, so M^-1 >= 0 entrywise)
+  pg_status st = activate_only(c, item);
+  if (st == PG_OK) st = item_vec(c, item, 3, 0, 0.0);
+  if (st == PG_OK) st = solve_active(c, rel_tol);
+  double k = 0.0;
+  if (st == PG_OK) st = item_absmax(c, item, 4, 0, &k);
+  c->pred_chunks = saved_pred;
+  const pg_status s2 = state_copy(c, item, (double*)keep.p, 0);
+  if (st == PG_OK) st = s2;
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  dfree(keep);
+  PG_TRY(st);
+  int32_t item_failed = 0;
+  HIP_TRY(c, hipMemcpy(&item_failed, (int32_t*)c->c_failed.p + item, sizeof item_failed, hipMemcpyDeviceToHost));
+  if (item_failed)
+    return set_err(c, PG_ERR_NO_CONVERGENCE, "the solve for M^-1 D 1 reached max_sweeps = %d", c->opt.max_sweeps);
+  *kappa = k;
+  return PG_OK;
+}
+
 pg_status pg_step(pg_ctx* c, int32_t nsteps) { return pg_run_transient(c, nsteps, 1, 0, 0, nullptr); }
 
 pg_status pg_run_transient(pg_ctx* c, int32_t nsteps, int32_t record_every, int32_t grid, int32_t scen,

@@ -109,6 +109,9 @@ EXPORTS = {
     "pg_set_state": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_double)]),
     "pg_reset": (C.c_int, [C.c_void_p]),
     "pg_dc_operating_point": (C.c_int, [C.c_void_p, C.c_int64, C.c_double, C.c_double, C.c_int32]),
+    "pg_estimate_omega": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.POINTER(C.c_double),
+                                    C.POINTER(C.c_double)]),
+    "pg_error_bound_factor": (C.c_int, [C.c_void_p, C.c_int32, C.c_double, C.POINTER(C.c_double)]),
     "pg_step": (C.c_int, [C.c_void_p, C.c_int32]),
     "pg_run_transient": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.c_int32,
                                    C.POINTER(C.c_double)]),
@@ -373,6 +376,18 @@ class Context:
 
     def reset(self):
         self._check(lib().pg_reset(self._h))
+
+    def estimate_omega(self, grid: int = 0, dc: bool = False, iters: int = 512):
+        """(rho_J, Young's omega) of the grid's step (or DC) matrix."""
+        rho, w = C.c_double(), C.c_double()
+        self._check(lib().pg_estimate_omega(self._h, grid, int(bool(dc)), int(iters), C.byref(rho), C.byref(w)))
+        return rho.value, w.value
+
+    def error_bound_factor(self, grid: int = 0, rel_tol: float = 1e-8) -> float:
+        """||M^-1 D||_inf of the grid's step matrix: tol = err / kappa bounds a step's error by err."""
+        k = C.c_double()
+        self._check(lib().pg_error_bound_factor(self._h, grid, float(rel_tol), C.byref(k)))
+        return k.value
 
     def dc_operating_point(self, k: int = 0, omega: float = 0.0, tol: float = 1e-10, max_sweeps: int = 100000):
         """Set every state to the DC point with the sources at t = k h, and the clock to k."""

@@ -8,8 +8,8 @@ arrays, so any disagreement between them comes from the method, not the inputs.
 """
 from .grids import (Mesh, Pulses, Workload, config0, config1, config2, config3a,
                     config3b, config4, small_rc, small_rlc, small_multilayer,
-                    pulse_draw, CONFIGS)
+                    uniform_diagonal_mesh, pulse_draw, CONFIGS)
 
 __all__ = ["Mesh", "Pulses", "Workload", "config0", "config1", "config2",
            "config3a", "config3b", "config4", "small_rc", "small_rlc",
-           "small_multilayer", "pulse_draw", "CONFIGS"]
+           "small_multilayer", "uniform_diagonal_mesh", "pulse_draw", "CONFIGS"]

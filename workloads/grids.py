@@ -153,6 +153,24 @@ def small_rc(nx=32, ny=32, seed=0, pad_every=8, g_range=(0.5, 2.0), c_range=(0.5
     return Workload(name or f"rc_{nx}x{ny}_s{seed}", [mesh], [scen], h, steps)
 
 
+def uniform_diagonal_mesh(nx=24, ny=24, g=1.0, C=2 * PF, h=10 * PS, steps=10, vdd=1.0) -> Workload:
+    """One layer of equal segments g, equal capacitance C, and a pad of k*g on every boundary
+    node that misses k of its four neighbours, so every diagonal entry of the step matrix is
+    C/h + 4g.  No current sources (scenarios are added by the caller)."""
+    gE = np.full((1, ny, nx - 1), float(g))
+    gN = np.full((1, ny - 1, nx), float(g))
+    Cm = np.full((1, ny, nx), float(C))
+    x, y = np.meshgrid(np.arange(nx), np.arange(ny))
+    missing = (x == 0).astype(int) + (x == nx - 1) + (y == 0) + (y == ny - 1)
+    node = (y * nx + x).ravel()
+    k = missing.ravel()
+    pads = node[k > 0].astype(np.int32)
+    mesh = Mesh(nx, ny, 1, gE, gN, Cm, _empty_i(), _empty_f(), _empty_f(), pads, g * k[k > 0].astype(float),
+                np.zeros(pads.size), vdd)
+    empty = Pulses(_empty_i(), _empty_f(), _empty_f(), _empty_f())
+    return Workload(f"uniform_diag_{nx}x{ny}", [mesh], [[empty]], h, steps)
+
+
 def config0() -> Workload:
     """RC 32x32 single layer, FP64, h=10 ps, 100 steps."""
     w = small_rc(32, 32, seed=0, name="rc_32x32_fp64")
