@@ -165,6 +165,16 @@ __global__ void k_step_begin(Ctl c, int I, int only_item, double h, SourceTable 
   }
 }
 
+// Sum / max over the 64 lanes of a wavefront (every lane gets the result).
+__device__ __forceinline__ long long wave_sum(long long v) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+__device__ __forceinline__ int wave_max(int v) {
+  for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o, 64));
+  return v;
+}
+
 __global__ void k_decide(Ctl c, int I, const GridDesc* __restrict__ grids, int G, double tol, int has_d, int nchk,
                          int max_sweeps, int nslots) {
   __shared__ int any;
@@ -191,14 +201,34 @@ __global__ void k_decide(Ctl c, int I, const GridDesc* __restrict__ grids, int G
     c.norm_bits[g] = 0ull;
   }
   __syncthreads();
-  // the work the next sweeps will do: active scenarios, and the coefficients of their grids
+  // the work the next sweeps will do: active scenarios, and the coefficients of the grids with
+  // an active scenario (marked in a bitmap of grids)
+  constexpr int kMaxGridWords = 1024;
+  __shared__ unsigned int gbits[kMaxGridWords];
+  const bool bitmap = G <= 32 * kMaxGridWords;
+  const int nwords = bitmap ? (G + 31) / 32 : 0;
+  for (int w = threadIdx.x; w < nwords; w += blockDim.x) gbits[w] = 0u;
+  __syncthreads();
+  long long mine = 0;
+  for (int g = threadIdx.x; g < I; g += blockDim.x) {
+    if (!c.active[g]) continue;
+    mine += c.nodes[g];
+    const int gi = c.item_grid[g];
+    if (bitmap) atomicOr(&gbits[gi >> 5], 1u << (gi & 31));
+  }
+  mine = wave_sum(mine);
+  if ((threadIdx.x & 63) == 0 && mine) atomicAdd(&act_nodes, (unsigned long long)mine);
+  __syncthreads();
   for (int gi = threadIdx.x; gi < G; gi += blockDim.x) {
     const GridDesc& D = grids[gi];
-    int cnt = 0;
-    for (int sc = 0; sc < D.S; ++sc) cnt += c.active[D.item0 + sc];
-    if (cnt) {
+    bool any_in_grid = false;
+    if (bitmap) {
+      any_in_grid = (gbits[gi >> 5] >> (gi & 31)) & 1u;
+    } else {
+      for (int sc = 0; sc < D.S && !any_in_grid; ++sc) any_in_grid = c.active[D.item0 + sc] != 0;
+    }
+    if (any_in_grid) {
       const unsigned long long plane = (unsigned long long)D.nx * D.ny, n = plane * D.nl;
-      atomicAdd(&act_nodes, n * cnt);
       atomicAdd(&act_coef, 3ull * n + plane * (D.nl - 1));
     }
   }
@@ -215,17 +245,32 @@ __global__ void k_decide(Ctl c, int I, const GridDesc* __restrict__ grids, int G
 }
 
 __global__ void k_step_end(Ctl c, int I, int count_step) {
-  if (threadIdx.x != 0) return;
+  __shared__ long long s_sw[4], s_upd[4];
+  __shared__ int s_mx[4], s_fail[4];
+  __shared__ double s_res[4];
   long long sw = 0, upd = 0;
   int mx = 0, fail = 0;
   double res = 0.0;
-  for (int g = 0; g < I; ++g) {
+  for (int g = threadIdx.x; g < I; g += blockDim.x) {
     const int s = c.step_sweeps[g];
     sw += s;
     upd += (long long)s * c.nodes[g];
     mx = s > mx ? s : mx;
     res = nan_max(res, c.last_norm[g]);
     fail |= c.failed[g];
+  }
+  // reduce within each wavefront, then over the block's four wavefronts
+  sw = wave_sum(sw);
+  upd = wave_sum(upd);
+  mx = wave_max(mx);
+  fail = wave_max(fail);
+  for (int o = 32; o > 0; o >>= 1) res = nan_max(res, __shfl_xor(res, o, 64));
+  const int w = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) { s_sw[w] = sw; s_upd[w] = upd; s_mx[w] = mx; s_fail[w] = fail; s_res[w] = res; }
+  __syncthreads();
+  if (threadIdx.x != 0) return;
+  for (int k = 1; k < (int)(blockDim.x >> 6); ++k) {
+    sw += s_sw[k]; upd += s_upd[k]; mx = max(mx, s_mx[k]); fail |= s_fail[k]; res = nan_max(res, s_res[k]);
   }
   c.stat_failed[0] |= fail;
   if (!count_step) return;

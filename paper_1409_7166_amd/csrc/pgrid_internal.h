@@ -105,6 +105,7 @@ struct Ctl {
   double* stat_max_res;            // [1]
   int32_t* stat_failed;            // [1]
   const long long* nodes;          // [I] mesh nodes of the item's grid
+  const int32_t* item_grid;        // [I] grid of the item
   // step clock: the step being solved advances on the device, so every launch of a step has
   // fixed arguments (and the step's launches can be replayed from a captured graph)
   long long* step;                 // [1] steps completed

@@ -115,7 +115,7 @@ struct pg_ctx {
     DBuf ckpts, vend, seg, lam0, lam1, arhs, dC, dgE, dgN, part, J, saved_vidx;
   } adj;
   // control block
-  DBuf c_norm, c_last, c_active, c_vidx, c_sweeps, c_failed, c_any, c_stats64, c_stats32, c_statsd, c_nodes;
+  DBuf c_norm, c_last, c_active, c_vidx, c_sweeps, c_failed, c_any, c_stats64, c_stats32, c_statsd, c_nodes, c_item_grid;
   Ctl ctl{};
   int32_t* host_flags = nullptr;                 // pinned, written by the decision kernel
   uint64_t flag_seq_host = 0;                    // decisions queued so far (mirrors the device counter)
@@ -416,6 +416,11 @@ pg_status prepare(pg_ctx* c) {
   c->adj.recorded = false;
   PG_TRY(upload(c, c->c_nodes, nodes));
   c->ctl.nodes = (const long long*)c->c_nodes.p;
+  std::vector<int32_t> item_grid;
+  for (int g = 0; g < G; ++g)
+    for (int sc = 0; sc < c->grids[g].S; ++sc) item_grid.push_back(g);
+  PG_TRY(upload(c, c->c_item_grid, item_grid));
+  c->ctl.item_grid = (const int32_t*)c->c_item_grid.p;
   // tiles_all: one tile per (scenario, tile) grouped by layer count, for the right-hand side,
   // the state copies and the loss kernels.  tiles_sweep: the sweep and residual tiles; a grid
   // with several scenarios is covered by scenario blocks of up to scen_block scenarios, whose
@@ -463,25 +468,36 @@ pg_status prepare(pg_ctx* c) {
   PG_TRY(upload(c, c->tiles_sweep, sweep));
   PG_TRY(upload(c, c->tiles_all, tiles));
   // sources: first those that are non-zero outside their breakpoints ("always"), then the
-  // windowed ones (zero before the first and after the last breakpoint, like every triangle)
-  // sorted by their first breakpoint, so a step only visits the windows that can contain t.
-  struct SrcRef { double t0, t1; int g, s; size_t k; };
+  // windowed ones (zero before the first and after the last breakpoint, like every triangle),
+  // so a step only visits the windows that can contain t.  Windowed sources are grouped in
+  // buckets of their first breakpoint, 8 steps wide, and ordered by target slot inside a
+  // bucket (and the "always" ones by slot), so the scattered updates of b touch memory in
+  // order; the window test uses the bucket start and is widened by one bucket (the extra
+  // sources add zero).
+  struct SrcRef { double t0, t1, bucket; int g, s; size_t k; int64_t slot; };
   std::vector<SrcRef> always, windowed;
+  const double bw = 8.0 * c->opt.h;
   for (int g = 0; g < G; ++g) {
     const GridHost& H = c->grids[g];
     for (int sc = 0; sc < H.S; ++sc) {
       const Src& S = H.src[sc];
       for (size_t k = 0; k < S.node.size(); ++k) {
         const int a = S.off[k], b = S.off[k + 1];
-        SrcRef ref{S.t[a], S.t[b - 1], g, sc, k};
+        SrcRef ref{S.t[a], S.t[b - 1], std::floor(S.t[a] / bw), g, sc, k,
+                   (int64_t)sc * H.nstore + H.storage(S.node[k])};
         if (S.i[a] == 0.0 && S.i[b - 1] == 0.0) windowed.push_back(ref); else always.push_back(ref);
       }
     }
   }
-  std::stable_sort(windowed.begin(), windowed.end(), [](const SrcRef& x, const SrcRef& y) { return x.t0 < y.t0; });
+  auto by_slot = [](const SrcRef& x, const SrcRef& y) { return x.g != y.g ? x.g < y.g : x.slot < y.slot; };
+  std::sort(always.begin(), always.end(), by_slot);
+  std::sort(windowed.begin(), windowed.end(), [&](const SrcRef& x, const SrcRef& y) {
+    return x.bucket != y.bucket ? x.bucket < y.bucket : by_slot(x, y);
+  });
   std::vector<double> win_t0;
   double win_maxw = 0.0;
-  for (auto& w : windowed) { win_t0.push_back(w.t0); win_maxw = std::max(win_maxw, w.t1 - w.t0); }
+  for (auto& w : windowed) { win_t0.push_back(w.bucket * bw); win_maxw = std::max(win_maxw, w.t1 - w.t0); }
+  if (!windowed.empty()) win_maxw += bw;
   std::vector<int32_t> sg, si, so{0};
   std::vector<double> st, sv;
   for (const auto* list : {&always, &windowed})
@@ -489,7 +505,7 @@ pg_status prepare(pg_ctx* c) {
       const GridHost& H = c->grids[ref.g];
       const Src& S = H.src[ref.s];
       sg.push_back(ref.g);
-      si.push_back((int32_t)((int64_t)ref.s * H.nstore + H.storage(S.node[ref.k])));
+      si.push_back((int32_t)ref.slot);
       for (int j = S.off[ref.k]; j < S.off[ref.k + 1]; ++j) { st.push_back(S.t[j]); sv.push_back(S.i[j]); }
       so.push_back((int32_t)st.size());
     }
@@ -1092,7 +1108,7 @@ void pg_destroy(pg_ctx* c) {
   }
   DBuf* bufs[] = {&c->grid_desc, &c->tiles_all, &c->tiles_sweep, &c->src_grid, &c->src_index, &c->src_off, &c->src_t, &c->src_i,
                   &c->ind_grid, &c->ind_local, &c->c_norm, &c->c_last, &c->c_active, &c->c_vidx, &c->c_sweeps,
-                  &c->c_failed, &c->c_any, &c->c_stats64, &c->c_stats32, &c->c_statsd, &c->c_nodes,
+                  &c->c_failed, &c->c_any, &c->c_stats64, &c->c_stats32, &c->c_statsd, &c->c_nodes, &c->c_item_grid,
                   &c->c_clock, &c->src_win_t0};
   for (DBuf* b : bufs) dfree(*b);
   DBuf* abufs[] = {&c->adj.ckpts, &c->adj.vend, &c->adj.seg, &c->adj.lam0, &c->adj.lam1, &c->adj.arhs,
