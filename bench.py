@@ -49,7 +49,9 @@ def parse():
                     help="time every n-th sweep block, residual pass and other launch with HIP events "
                          "during the timed region (0: off)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--extras", action="store_true", help="add side-by-side runs (plain FP64, parity tol)")
+    ap.add_argument("--side-by-side", action="store_true",
+                    help="instead of the one headline line, print one JSON line per workload and precision "
+                         "(plain FP64, FP32 + FP64 refinement, batched; 1e-6 V and a parity tolerance)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="run only a plain 1 GiB device copy (counter calibration) and exit")
     return ap.parse_args()
@@ -186,27 +188,29 @@ def copy_probe():
     print(json.dumps({"copy_probe_bytes_each_way": n * 4, "launches": 3}))
 
 
-def main():
-    args = parse()
-    if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the relaxation path is built and "
-              "measured for a single MI355X", file=sys.stderr)
-        sys.exit(2)
-    if args.copy_probe:
-        copy_probe()
-        return
-    name = args.workload
+# (workload, precision, tolerance, steps) of the side-by-side report
+SIDE_BY_SIDE = [
+    ("config1", "fp32+ref", 1e-6, 1000), ("config1", "fp64", 1e-6, 1000), ("config1", "fp32+ref", 1e-9, 300),
+    ("config3a", "fp32+ref", 1e-6, 500), ("config3b", "fp32+ref", 1e-6, 500),
+    ("config2", "fp64", 1e-6, 2000), ("config2", "fp32+ref", 1e-6, 2000),
+    ("config4", "fp64", 1e-6, 200), ("config0", "fp64", 1e-6, 100),
+]
+
+
+def measure(name, prec, tol, steps, args):
+    """One timed run: the JSON record of bench.py for workload `name`."""
     w = make_workload(name)
-    prec = args.precision or w.precision
+    prec = prec or w.precision
     tuned = TUNED[name]
     omega = args.omega or tuned["omega"]
     chk = args.check_every or tuned["check_every"]
     rows = args.tile_rows or tuned.get("tile_rows", 0)
-    if args.graphs < 0:
-        args.graphs = tuned["graphs"]
+    if prec == "fp64" and rows == 16 and w.meshes[0].nl > 1:
+        rows = 8  # FP64 layered tiles of 16 rows need more registers than one wave slot allows
+    graphs = tuned["graphs"] if args.graphs < 0 else args.graphs
     block = args.scen_block or tuned.get("scen_block", 0)
-    elapsed, st, kt = run_gpu(w, args.steps, args.warmup, prec, args.tol, omega, chk, rows,
-                              args.lookahead, args.profile_every, args.graphs, block,
+    elapsed, st, kt = run_gpu(w, steps, args.warmup, prec, tol, omega, chk, rows,
+                              args.lookahead, args.profile_every, graphs, block,
                               args.sweeps_per_launch)
     nodes = sum(m.n * len(p) for m, p in zip(w.meshes, w.pulses))
     value = st["node_updates"] / elapsed
@@ -224,25 +228,42 @@ def main():
                 "bytes_per_launch": kt["sweep_bytes"] / kt["sweep_launches"]}
     out = {
         "metric": "node-updates/s at 1e-6 V scaled residual",
-        "value": value, "unit": "node-updates/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
-        "ms_per_step": elapsed * 1e3 / args.steps, "higher_is_better": True, "scaling": "weak",
+        "value": value, "unit": "node-updates/s", "n_gpus": 1, "steps": steps, "warmup": args.warmup,
+        "ms_per_step": elapsed * 1e3 / steps, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f32" if prec == "fp32+ref" else "f64", "data": "synthetic",
-        "config": {"workload": w.name, "nodes": nodes, "h_s": w.h, "tol_V": args.tol,
-                   "precision": prec, "omega": omega, "check_every": chk, "graphs": args.graphs,
+        "config": {"workload": w.name, "nodes": nodes, "h_s": w.h, "tol_V": tol,
+                   "precision": prec, "omega": omega, "check_every": chk, "graphs": graphs,
                    "tile_rows": st["options"]["tile_rows"] or 8,
                    "sweeps_per_launch": spl,
                    "scen_block": (st["options"]["scen_block"] or 8) if any(len(p) > 1 for p in w.pulses)
                    else None,
                    "sweeps_per_step": st["sweeps"] / max(1, st["steps"]),
                    "max_step_sweeps": st["max_step_sweeps"], "max_final_residual_V": st["max_final_residual"],
-                   "node_steps_per_s": nodes * args.steps / elapsed},
+                   "node_steps_per_s": nodes * steps / elapsed},
         "roofline": roof,
     }
     if kt["resid_launches"]:
         out["residual_kernel"] = {"avg_launch_us": kt["resid_ms"] * 1e3 / kt["resid_launches"],
                                   "achieved_GBps": kt["resid_bytes"] / (kt["resid_ms"] * 1e-3) / 1e9}
+    return out
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the relaxation path is built and "
+              "measured for a single MI355X", file=sys.stderr)
+        sys.exit(2)
+    if args.copy_probe:
+        copy_probe()
+        return
+    if args.side_by_side:
+        for name, prec, tol, steps in SIDE_BY_SIDE:
+            print(json.dumps(measure(name, prec, tol, steps, args)), flush=True)
+        return
+    out = measure(args.workload, args.precision, args.tol, args.steps, args)
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(name)
+        out["cpu_baseline"] = cpu_baseline(args.workload)
     print(json.dumps(out), flush=True)
 
 
