@@ -147,7 +147,10 @@ __device__ int block_lower_bound(const double* __restrict__ a, int n, double key
   return lo;
 }
 
-__global__ void k_step_begin(Ctl c, int I, int only_item, double h, SourceTable src) {
+// Open a step on the device (the whole block): activate every item (only_item < 0) or one item,
+// reset its per-step control, set t = (step + 1) h and the window of sources that can be
+// non-zero at t.
+__device__ void step_begin_block(const Ctl& c, int I, int only_item, double h, const SourceTable& src) {
   for (int g = threadIdx.x; g < I; g += blockDim.x) {
     c.active[g] = (only_item < 0 || g == only_item) ? 1 : 0;
     c.step_sweeps[g] = 0;
@@ -165,6 +168,11 @@ __global__ void k_step_begin(Ctl c, int I, int only_item, double h, SourceTable 
   }
 }
 
+__global__ void k_step_begin(Ctl c, int I, int only_item, double h, SourceTable src) {
+  if (*c.stall) return;
+  step_begin_block(c, I, only_item, h, src);
+}
+
 // Sum / max over the 64 lanes of a wavefront (every lane gets the result).
 __device__ __forceinline__ long long wave_sum(long long v) {
   for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
@@ -175,11 +183,28 @@ __device__ __forceinline__ int wave_max(int v) {
   return v;
 }
 
-__global__ void k_decide(Ctl c, int I, const GridDesc* __restrict__ grids, int G, double tol, int has_d, int nchk,
-                         int max_sweeps, int nslots) {
+// The decision after a residual pass (one block): per item,
+// converged when its scaled residual is <= tol, failed when its sweep budget is spent; writes
+// the accounting words and the tagged flag of this decision to host-visible memory.
+__device__ void decide_block(const Ctl& c, const DecideArgs& da) {
+  const int I = da.I, G = da.G, has_d = da.has_d, nchk = da.nchk, max_sweeps = da.max_sweeps;
+  const int nslots = da.nslots;
+  const double tol = da.tol;
+  const GridDesc* __restrict__ grids = da.grids;
   __shared__ int any;
   __shared__ int worked;
   __shared__ unsigned long long act_nodes, act_coef;
+  if (*c.stall) {  // a stalled opening: keep the sequence, report the decision as skipped
+    if (threadIdx.x == 0) {
+      const int seq = c.flag_seq[0];
+      c.flag_seq[0] = seq + 1;
+      c.acct[2 * (seq % nslots)] = 0;
+      c.acct[2 * (seq % nslots) + 1] = 0;
+      __threadfence_system();
+      c.any_active[seq % nslots] = (int32_t)(((uint32_t)seq & 0x1fffffffu) << 2 | 2u);
+    }
+    return;
+  }
   if (threadIdx.x == 0) { any = 0; worked = 0; act_nodes = 0ull; act_coef = 0ull; }
   __syncthreads();
   for (int g = threadIdx.x; g < I; g += blockDim.x) {
@@ -189,7 +214,9 @@ __global__ void k_decide(Ctl c, int I, const GridDesc* __restrict__ grids, int G
         c.vidx[g] ^= 1;
         c.step_sweeps[g] += nchk;
       }
-      const double nm = __longlong_as_double((long long)c.norm_bits[g]);
+      // the other workgroups' atomicMax results, read at device scope (not from a stale L1 line)
+      const double nm = __longlong_as_double(
+          (long long)__hip_atomic_load(&c.norm_bits[g], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
       c.last_norm[g] = nm;
       const bool conv = nm <= tol;                 // false for NaN
       const bool spent = c.step_sweeps[g] >= max_sweeps;
@@ -239,17 +266,25 @@ __global__ void k_decide(Ctl c, int I, const GridDesc* __restrict__ grids, int G
     c.acct[2 * (seq % nslots)] = (long long)act_nodes;
     c.acct[2 * (seq % nslots) + 1] = (long long)act_coef;
     __threadfence_system();
-    c.any_active[seq % nslots] = (int32_t)(((uint32_t)seq & 0x3fffffffu) << 1 | (uint32_t)any);
+    c.any_active[seq % nslots] = (int32_t)(((uint32_t)seq & 0x1fffffffu) << 2 | (uint32_t)any);
     if (worked) c.stat_checks[0] += 1;
   }
 }
 
-__global__ void k_step_end(Ctl c, int I, int count_step) {
+__global__ void k_decide(Ctl c, DecideArgs da) { decide_block(c, da); }
+
+
+// Close a step: count_step 1 adds the step's statistics and advances the clock, 2 only advances
+// the clock, 0 does neither; the failure flag is always gathered.  Items still iterating mean the
+// close was queued ahead of the step's last decision: set the stall flag and do nothing.  With
+// begin_next the same block then opens the next step (step_begin_block for every item).
+__global__ void k_step_end(Ctl c, int I, int count_step, int begin_next, double h, SourceTable src) {
   __shared__ long long s_sw[4], s_upd[4];
-  __shared__ int s_mx[4], s_fail[4];
+  __shared__ int s_mx[4], s_fail[4], s_act[4];
   __shared__ double s_res[4];
+  if (*c.stall) return;
   long long sw = 0, upd = 0;
-  int mx = 0, fail = 0;
+  int mx = 0, fail = 0, act = 0;
   double res = 0.0;
   for (int g = threadIdx.x; g < I; g += blockDim.x) {
     const int s = c.step_sweeps[g];
@@ -258,29 +293,47 @@ __global__ void k_step_end(Ctl c, int I, int count_step) {
     mx = s > mx ? s : mx;
     res = nan_max(res, c.last_norm[g]);
     fail |= c.failed[g];
+    act |= c.active[g];
   }
-  // reduce within each wavefront, then over the block's four wavefronts
+  // reduce within each wavefront, then over the block's wavefronts
+  act = wave_max(act);
   sw = wave_sum(sw);
   upd = wave_sum(upd);
   mx = wave_max(mx);
   fail = wave_max(fail);
   for (int o = 32; o > 0; o >>= 1) res = nan_max(res, __shfl_xor(res, o, 64));
   const int w = threadIdx.x >> 6;
-  if ((threadIdx.x & 63) == 0) { s_sw[w] = sw; s_upd[w] = upd; s_mx[w] = mx; s_fail[w] = fail; s_res[w] = res; }
+  if ((threadIdx.x & 63) == 0) {
+    s_sw[w] = sw; s_upd[w] = upd; s_mx[w] = mx; s_fail[w] = fail; s_res[w] = res; s_act[w] = act;
+  }
   __syncthreads();
-  if (threadIdx.x != 0) return;
+  // thread 0 completes the statistics from the other wavefronts' partial results; the
+  // still-iterating test must be the same for every thread, since the block either returns
+  // as a whole or goes on to the barriers of the next step's opening
   for (int k = 1; k < (int)(blockDim.x >> 6); ++k) {
     sw += s_sw[k]; upd += s_upd[k]; mx = max(mx, s_mx[k]); fail |= s_fail[k]; res = nan_max(res, s_res[k]);
   }
-  c.stat_failed[0] |= fail;
-  if (!count_step) return;
-  c.stat_sweeps[0] += sw;
-  c.stat_updates[0] += upd;
-  c.stat_last_sweeps[0] = mx;
-  if (mx > c.stat_max_sweeps[0]) c.stat_max_sweeps[0] = mx;
-  c.stat_last_res[0] = res;
-  c.stat_max_res[0] = nan_max(c.stat_max_res[0], res);
-  c.step[0] += 1;
+  int any_active = 0;
+  for (int k = 0; k < (int)(blockDim.x >> 6); ++k) any_active |= s_act[k];
+  if (any_active) {  // the step is still iterating: this close (and what was queued after it) must wait
+    if (threadIdx.x == 0) c.stall[0] = 1;
+    return;
+  }
+  if (threadIdx.x == 0) {
+    c.stat_failed[0] |= fail;
+    if (count_step == 1) {
+      c.stat_sweeps[0] += sw;
+      c.stat_updates[0] += upd;
+      c.stat_last_sweeps[0] = mx;
+      if (mx > c.stat_max_sweeps[0]) c.stat_max_sweeps[0] = mx;
+      c.stat_last_res[0] = res;
+      c.stat_max_res[0] = nan_max(c.stat_max_res[0], res);
+    }
+    if (count_step) c.step[0] += 1;
+  }
+  if (!begin_next) return;
+  __syncthreads();  // the new step index is visible to the block
+  step_begin_block(c, I, -1, h, src);
 }
 
 // ------------------------------------------------------------------------------------
@@ -289,6 +342,7 @@ __global__ void k_step_end(Ctl c, int I, int count_step) {
 // ------------------------------------------------------------------------------------
 __global__ __launch_bounds__(kThreads) void k_rhs(const Tile* __restrict__ tiles, int ntiles,
                                                  const GridDesc* __restrict__ grids, Ctl c, int TY) {
+  if (*c.stall) return;  // a stalled step opening
   const int ti = xcd_tile(ntiles);
   if (ti < 0) return;
   const Tile tl = tiles[ti];
@@ -323,6 +377,7 @@ __global__ __launch_bounds__(kThreads) void k_rhs(const Tile* __restrict__ tiles
 // Piecewise-linear current sources at the step's time, subtracted from b.  Grid-stride over the
 // always-on sources and the window chosen by k_step_begin.
 __global__ void k_sources(SourceTable src, const GridDesc* __restrict__ grids, Ctl c) {
+  if (*c.stall) return;
   const double t = c.t_now[0];
   const int wbeg = c.src_window[0], wcnt = c.src_window[1];
   const int n = src.n_always + wcnt;
@@ -356,15 +411,12 @@ __global__ void k_sources(SourceTable src, const GridDesc* __restrict__ grids, C
 // Block: 64 x TY threads, lane j of row w owns the pair (x0 + 2j, x0 + 2j + 1) of row y0 + w.
 // ------------------------------------------------------------------------------------
 template <typename T, int NL, int TY>
-__global__ __launch_bounds__(64 * TY) void k_resid(const Tile* __restrict__ tiles, int ntiles,
-                                                  const GridDesc* __restrict__ grids, Ctl c,
-                                                  int has_d, int din) {
+__device__ void resid_tile(const Tile* __restrict__ tiles, int ti, const GridDesc* __restrict__ grids,
+                           const Ctl& c, int has_d, int din) {
   constexpr int NP = kTileX / 2, HP = NP + 2, HY = TY + 2;
   constexpr int NT = 64 * TY;
   __shared__ double2 sv[NL][HY][HP];
   __shared__ double wmax[NT / 64];
-  const int ti = xcd_tile(ntiles);
-  if (ti < 0) return;
   const Tile tl = tiles[ti];
   const int item = tl.item;
   if (!c.active[item]) return;
@@ -447,6 +499,14 @@ __global__ __launch_bounds__(64 * TY) void k_resid(const Tile* __restrict__ tile
     for (int w = 1; w < NT / 64; ++w) bm = nan_max(bm, wmax[w]);
     atomicMax(&c.norm_bits[item], (unsigned long long)__double_as_longlong(bm));
   }
+}
+
+template <typename T, int NL, int TY>
+__global__ __launch_bounds__(64 * TY) void k_resid(const Tile* __restrict__ tiles, int ntiles,
+                                                  const GridDesc* __restrict__ grids, Ctl c,
+                                                  int has_d, int din) {
+  const int ti = xcd_tile(ntiles);
+  if (!*c.stall && ti >= 0) resid_tile<T, NL, TY>(tiles, ti, grids, c, has_d, din);
 }
 
 // ------------------------------------------------------------------------------------
@@ -670,14 +730,11 @@ __global__ __launch_bounds__(64 * TY) void k_sweep_rb_multi(const Tile* __restri
 
 // FP64 residual over a scenario block (see k_resid): coefficients once, v, d, b per scenario.
 template <typename T, int NL, int TY>
-__global__ __launch_bounds__(64 * TY) void k_resid_multi(const Tile* __restrict__ tiles, int ntiles,
-                                                        const GridDesc* __restrict__ grids, Ctl c,
-                                                        int has_d, int din) {
+__device__ void resid_multi_tile(const Tile* __restrict__ tiles, int ti, const GridDesc* __restrict__ grids,
+                                 const Ctl& c, int has_d, int din) {
   constexpr int NP = kTileX / 2, HP = NP + 2, HY = TY + 2, NT = 64 * TY;
   __shared__ double2 sv[NL][HY][HP];
   __shared__ double wmax[NT / 64];
-  const int ti = xcd_tile(ntiles);
-  if (ti < 0) return;
   const Tile tl = tiles[ti];
   const GridDesc& G = grids[tl.grid];
   const int nx = G.nx, ny = G.ny, X = G.X;
@@ -771,6 +828,14 @@ __global__ __launch_bounds__(64 * TY) void k_resid_multi(const Tile* __restrict_
       atomicMax(&c.norm_bits[item], (unsigned long long)__double_as_longlong(bm));
     }
   }
+}
+
+template <typename T, int NL, int TY>
+__global__ __launch_bounds__(64 * TY) void k_resid_multi(const Tile* __restrict__ tiles, int ntiles,
+                                                        const GridDesc* __restrict__ grids, Ctl c,
+                                                        int has_d, int din) {
+  const int ti = xcd_tile(ntiles);
+  if (!*c.stall && ti >= 0) resid_multi_tile<T, NL, TY>(tiles, ti, grids, c, has_d, din);
 }
 
 // ------------------------------------------------------------------------------------
@@ -960,6 +1025,7 @@ __global__ __launch_bounds__(kThreads) void k_sweep_jacobi(const Tile* __restric
 // ------------------------------------------------------------------------------------
 __global__ void k_inductors(const GridDesc* __restrict__ grids, const int32_t* __restrict__ ind_grid,
                             const int32_t* __restrict__ ind_local, int n_total, Ctl c) {
+  if (*c.stall) return;  // the step's close is waiting for more sweeps
   const int j = blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= n_total) return;
   const GridDesc& G = grids[ind_grid[j]];
@@ -1102,14 +1168,9 @@ hipError_t launch_step_begin(const Ctl& c, int I, int only_item, double h, const
   return hipGetLastError();
 }
 
-hipError_t launch_decide(const Ctl& c, int I, const GridDesc* grids, int G, double tol, int has_d, int nchk,
-                         int max_sweeps, int nslots, hipStream_t s) {
-  hipLaunchKernelGGL(k_decide, dim3(1), dim3(256), 0, s, c, I, grids, G, tol, has_d, nchk, max_sweeps, nslots);
-  return hipGetLastError();
-}
-
-hipError_t launch_step_end(const Ctl& c, int I, int count_step, hipStream_t s) {
-  hipLaunchKernelGGL(k_step_end, dim3(1), dim3(64), 0, s, c, I, count_step);
+hipError_t launch_step_end(const Ctl& c, int I, int count_step, int begin_next, double h, const SourceTable& src,
+                           hipStream_t s) {
+  hipLaunchKernelGGL(k_step_end, dim3(1), dim3(256), 0, s, c, I, count_step, begin_next, h, src);
   return hipGetLastError();
 }
 
@@ -1231,6 +1292,20 @@ hipError_t launch_item_vec(bool fp32, const Tile* tiles, int ntiles, int tile_ro
   else
     hipLaunchKernelGGL(k_item_vec<double>, dim3(ntiles), dim3(kThreads), 0, st, tiles, ntiles, tile_rows, grids, c,
                        op, which, s);
+  return hipGetLastError();
+}
+
+__global__ void k_resume(Ctl c) {
+  if (threadIdx.x == 0) c.stall[0] = 0;
+}
+
+hipError_t launch_decide(const Ctl& c, const DecideArgs& da, hipStream_t s) {
+  hipLaunchKernelGGL(k_decide, dim3(1), dim3(256), 0, s, c, da);
+  return hipGetLastError();
+}
+
+hipError_t launch_resume(const Ctl& c, hipStream_t s) {
+  hipLaunchKernelGGL(k_resume, dim3(1), dim3(64), 0, s, c);
   return hipGetLastError();
 }
 

@@ -112,6 +112,23 @@ struct Ctl {
   double* t_now;                   // [1] time of the step being solved, (step + 1) h
   int32_t* src_window;             // [2] first windowed source visited, number visited
   int32_t* flag_seq;               // [1] decisions taken so far (selects the flag slot)
+  // [1] set by k_step_end when it finds items still iterating (the host queued the close of a
+  // step, and the next step's opening, ahead of the step's last decision); every kernel of a
+  // step's close and opening does nothing while it is set, until k_resume clears it
+  int32_t* stall;
+};
+
+// Arguments of the decision after a residual pass.
+struct DecideArgs {
+  int on;
+  int I;                           // items
+  int G;                           // grids
+  int has_d;                       // the pass added a correction (a refinement cycle ended)
+  int nchk;                        // sweeps in the cycle
+  int max_sweeps;
+  int nslots;                      // host-visible flag slots
+  double tol;
+  const GridDesc* grids;
 };
 
 // ---- launch wrappers (kernels.hip) ----
@@ -123,18 +140,20 @@ hipError_t launch_sources(const SourceTable& src, const GridDesc* grids, const C
 // multi: the tiles are scenario blocks (Tile.pad consecutive scenarios of one grid)
 hipError_t launch_resid(bool fp32, bool multi, int nl, int tile_rows, const Tile* tiles, int ntiles,
                         const GridDesc* grids, const Ctl& c, int has_d, int din, hipStream_t s);
-// The decision of a residual check, with sequence number q = (*flag_seq)++, writes
-// ((q & 0x3fffffff) << 1) | (any item still active) to slot q % nslots of c.any_active
-// (host-visible memory), after the slot's accounting words.
-hipError_t launch_decide(const Ctl& c, int I, const GridDesc* grids, int G, double tol, int has_d, int nchk,
-                         int max_sweeps, int nslots, hipStream_t s);
+// The decision after a residual pass, with sequence number q = (*flag_seq)++, writes
+// ((q & 0x1fffffff) << 2) | (skipped << 1) | (any item still active) to slot q % nslots of
+// c.any_active (host-visible memory), after the slot's accounting words; `skipped` marks a
+// decision that found the stall flag set and took no action.
+hipError_t launch_decide(const Ctl& c, const DecideArgs& da, hipStream_t s);
 // Two red-black sweeps in one launch (tiles may be scenario blocks); reads d[din], writes d[din ^ 1].
 hipError_t launch_sweep2(bool fp32, int nl, int tile_rows, const Tile* tiles, int ntiles, const GridDesc* grids,
                          const Ctl& c, int din, int zero_in, double omega, hipStream_t s);
 hipError_t launch_sweep(bool fp32, bool multi, int ordering, int nl, int tile_rows, const Tile* tiles,
                         int ntiles, const GridDesc* grids, const Ctl& c, int din, int zero_in,
                         double omega, hipStream_t s);
-hipError_t launch_step_end(const Ctl& c, int G, int count_step, hipStream_t s);
+// count_step: 1 statistics and clock, 2 clock only, 0 neither; begin_next opens the next step.
+hipError_t launch_step_end(const Ctl& c, int G, int count_step, int begin_next, double h, const SourceTable& src,
+                           hipStream_t s);
 // adjoint of the softplus loss (tiles of one item; vk, vprev and grads are plain slices)
 hipError_t launch_loss(const Tile* tiles, int ntiles, int tile_rows, const GridDesc* grids, const Ctl& c,
                        double margin, double* part, double* total, hipStream_t s);
@@ -148,6 +167,8 @@ hipError_t launch_state_copy(const Tile* tiles, int ntiles, int tile_rows, const
 // One item's vector utilities (op codes at k_item_vec); tiles are the item's tiles.
 hipError_t launch_item_vec(bool fp32, const Tile* tiles, int ntiles, int tile_rows, const GridDesc* grids,
                            const Ctl& c, int op, int which, double s, hipStream_t st);
+// Clear the stall flag (after the host has re-queued a stalled step's remaining work).
+hipError_t launch_resume(const Ctl& c, hipStream_t s);
 hipError_t launch_swap_vidx(const Ctl& c, int item, int32_t* saved, hipStream_t s);
 hipError_t launch_inductors(const GridDesc* grids, const int32_t* ind_grid,
                             const int32_t* ind_local, int n_total, const Ctl& c, hipStream_t s);

@@ -19,7 +19,7 @@ using namespace pgrid;
 namespace {
 
 constexpr int kFlagSlots = 32;  // host-visible decision flags (at most 31 decisions in flight)
-constexpr uint32_t kTagMask = 0x3fffffffu;  // a decision's tag: its sequence number, masked
+constexpr uint32_t kTagMask = 0x1fffffffu;  // a decision's tag: its sequence number, masked
 
 struct Src {
   std::vector<int32_t> node, off;
@@ -128,12 +128,16 @@ struct pg_ctx {
   long long* host_acct = nullptr;                // pinned [slots][2]: active work after each decision
   long long* dev_acct = nullptr;
   int32_t* dev_flags = nullptr;                  // device address of host_flags
-  std::vector<hipEvent_t> flag_events;
   // profiling
   int profile_every = 0;
   int64_t prof_count[4] = {0, 0, 0, 0};          // intervals seen per kind (sampling)
   int cur_chunk = 0;                             // refinement cycle being queued
   int pred_chunks = 1;                           // cycles the previous step needed
+  bool opening_queued = false;                   // the next step's opening is already queued
+  int opening_tag = 0;                           // ... and the tag of its first decision
+  bool maybe_stalled = false;                    // a speculative close may have stalled the device
+  bool begun_next = false;                       // the last close also began the next step
+  std::vector<double> win_t0_host;               // bucket starts of the windowed sources (host copy)
   std::vector<ProfEvent> prof_live;
   std::vector<hipEvent_t> prof_pool;
   pg_kernel_times prof_acc{};
@@ -512,6 +516,7 @@ pg_status prepare(pg_ctx* c) {
   c->n_src = (int)sg.size();
   PG_TRY(upload(c, c->src_grid, sg)); PG_TRY(upload(c, c->src_index, si)); PG_TRY(upload(c, c->src_off, so));
   PG_TRY(upload(c, c->src_t, st)); PG_TRY(upload(c, c->src_i, sv)); PG_TRY(upload(c, c->src_win_t0, win_t0));
+  c->win_t0_host = win_t0;
   c->src_table = SourceTable{c->n_src, (const int32_t*)c->src_grid.p, (const int32_t*)c->src_index.p,
                              (const int32_t*)c->src_off.p, (const double*)c->src_t.p, (const double*)c->src_i.p,
                              (int32_t)always.size(), (int32_t)windowed.size(), (const double*)c->src_win_t0.p,
@@ -580,15 +585,27 @@ pg_status check_gs(pg_ctx* c, int grid, int scen) {
 
 // ---- one backward-Euler step -----------------------------------------------------------
 // Profiled as one block: the work is charged once the active items are known (cycle_loop).
-pg_status launch_resid_all(pg_ctx* c, int has_d, int din) {
+// Reserve the next decision: returns its tag; its flag slot is tag % kFlagSlots.  The device
+// numbers its decisions with its own counter, which this host counter mirrors.
+int next_tag(pg_ctx* c) { return (int)(c->flag_seq_host++ & kTagMask); }
+
+// One residual pass over every tile group; with `tag`, followed by its decision (see
+// pgrid_internal.h), whose tag is returned.
+pg_status launch_resid_all(pg_ctx* c, int has_d, int din, double tol = 0.0, int* tag = nullptr) {
   const Tile* T = (const Tile*)c->tiles_sweep.p;
   ProfScope ps(c, 1, c->begin_nodes, c->resid_bytes(c->begin_nodes, c->begin_coef, has_d != 0),
-               (int)c->tile_groups.size());
+               (int)c->tile_groups.size() + (tag ? 1 : 0));
   for (auto& grp : c->tile_groups) {
     hipError_t e = launch_resid(fp32_mode(c), grp.multi, grp.nl, c->tile_rows, T + grp.off, grp.count,
                                 (const GridDesc*)c->grid_desc.p, c->ctl, has_d, din, c->stream);
     if (e != hipSuccess) return set_err(c, PG_ERR_DEVICE, "residual launch: %s", hipGetErrorString(e));
   }
+  if (!tag) return PG_OK;
+  const DecideArgs da{1, n_items(c), (int)c->grids.size(), has_d, c->opt.check_every, c->opt.max_sweeps,
+                      kFlagSlots, tol, (const GridDesc*)c->grid_desc.p};
+  hipError_t e = launch_decide(c->ctl, da, c->stream);
+  if (e != hipSuccess) return set_err(c, PG_ERR_DEVICE, "decision launch: %s", hipGetErrorString(e));
+  *tag = next_tag(c);
   return PG_OK;
 }
 
@@ -630,18 +647,33 @@ pg_status launch_sweeps(pg_ctx* c, int nchk) {
   return PG_OK;
 }
 
-// Begin a step at time (step + 1) h: activate every item (only_item < 0) or one item, form the
-// right-hand side on the active tiles, subtract the sources.
 // Set the step clock (host mirror and device counter).
 pg_status set_step(pg_ctx* c, int64_t k) {
   c->step = k;
+  c->begun_next = false;     // a clock change voids any step opened ahead
+  c->opening_queued = false;
   c->step_host = (long long)k;
   HIP_TRY(c, hipMemcpyAsync(c->ctl.step, &c->step_host, sizeof(long long), hipMemcpyHostToDevice, c->stream));
   HIP_TRY(c, hipStreamSynchronize(c->stream));
   return PG_OK;
 }
 
-pg_status begin_step(pg_ctx* c, int only_item) {
+// Whether any source can be non-zero at the time of step index `dev_step` (t = (dev_step + 1) h),
+// judged from the host copy of the window table with one step of slack on either side.
+bool sources_may_act(const pg_ctx* c, int64_t dev_step) {
+  if (c->src_table.n_always > 0) return true;
+  if (c->win_t0_host.empty()) return false;
+  const double h = c->opt.h, t = (double)(dev_step + 1) * h;
+  const auto lo = std::lower_bound(c->win_t0_host.begin(), c->win_t0_host.end(), t - c->src_table.win_maxw - h);
+  const auto hi = std::upper_bound(c->win_t0_host.begin(), c->win_t0_host.end(), t + h);
+  return lo < hi;
+}
+
+// Begin a step at time (step + 1) h: activate every item (only_item < 0) or one item, form the
+// right-hand side on the active tiles, subtract the sources.  `begun`: the previous close has
+// already opened the clock and the items.  dev_step >= 0 (the device step index the opening
+// will see) lets the source launch be left out when no source can be non-zero.
+pg_status begin_step(pg_ctx* c, int only_item, bool begun = false, int64_t dev_step = -1) {
   const int G = n_items(c);
   c->begin_nodes = c->all_nodes;
   c->begin_coef = c->all_coef;
@@ -654,7 +686,7 @@ pg_status begin_step(pg_ctx* c, int only_item) {
   }
   Ctl k = c->ctl;
   hipError_t e;
-  {
+  if (!begun) {
     ProfScope ps(c, 3, 0);
     e = launch_step_begin(k, G, only_item, c->opt.h, c->src_table, c->stream);
     if (e != hipSuccess) return set_err(c, PG_ERR_DEVICE, "step launch: %s", hipGetErrorString(e));
@@ -667,7 +699,7 @@ pg_status begin_step(pg_ctx* c, int only_item) {
     e = launch_rhs(T + off, cnt, c->tile_rows, (const GridDesc*)c->grid_desc.p, k, c->stream);
     if (e != hipSuccess) return set_err(c, PG_ERR_DEVICE, "rhs launch: %s", hipGetErrorString(e));
   }
-  {
+  if (dev_step < 0 || sources_may_act(c, dev_step)) {
     ProfScope ps(c, 2, 0);
     e = launch_sources(c->src_table, (const GridDesc*)c->grid_desc.p, k, c->stream);
     if (e != hipSuccess) return set_err(c, PG_ERR_DEVICE, "source launch: %s", hipGetErrorString(e));
@@ -675,28 +707,30 @@ pg_status begin_step(pg_ctx* c, int only_item) {
   return PG_OK;
 }
 
-// Reserve the next decision: returns its tag; its flag slot is tag % kFlagSlots.  The device
-// numbers its decisions with its own counter, which this host counter mirrors.
-int next_tag(pg_ctx* c) { return (int)(c->flag_seq_host++ & kTagMask); }
 
-// Wait for the decision `tag`: spin on its host-visible flag, which the decision kernel sets to
-// (tag << 1) | any after writing its accounting words; every so often ask the slot's event
-// whether the decision has run, so a flag that can no longer arrive is reported, not awaited.
-pg_status wait_decision(pg_ctx* c, int tag, int* any) {
+// Wait for the decision `tag`: spin on its host-visible flag, which the decision sets to
+// (tag << 2) | (skipped << 1) | any after writing its accounting words; every so often ask
+// whether the stream still has work, so a flag that can no longer arrive is reported, not
+// awaited.
+pg_status wait_decision(pg_ctx* c, int tag, int* any, int* skipped = nullptr) {
   const int slot = tag % kFlagSlots;
   const uint32_t want = (uint32_t)tag;
+  auto take = [&](uint32_t f) {
+    *any = (int)(f & 1u);
+    if (skipped) *skipped = (int)((f >> 1) & 1u);
+  };
   for (long spin = 1;; ++spin) {
     const uint32_t f = (uint32_t)__atomic_load_n(c->host_flags + slot, __ATOMIC_ACQUIRE);
-    if ((f >> 1) == want) {
-      *any = (int)(f & 1u);
+    if ((f >> 2) == want) {
+      take(f);
       return PG_OK;
     }
     if ((spin & 1023) == 0) {
-      const hipError_t q = hipEventQuery(c->flag_events[slot]);
+      const hipError_t q = hipStreamQuery(c->stream);  // idle stream: the flag can no longer arrive
       if (q == hipSuccess) {
         const uint32_t g = (uint32_t)__atomic_load_n(c->host_flags + slot, __ATOMIC_ACQUIRE);
-        if ((g >> 1) == want) {
-          *any = (int)(g & 1u);
+        if ((g >> 2) == want) {
+          take(g);
           return PG_OK;
         }
         return set_err(c, PG_ERR_STATE, "decision %d: flag out of sequence", tag);
@@ -705,24 +739,6 @@ pg_status wait_decision(pg_ctx* c, int tag, int* any) {
     }
     __builtin_ia32_pause();
   }
-}
-
-// Queue the decision of a residual check; returns its tag and records the slot's event after it.
-pg_status issue_decide(pg_ctx* c, double tol, int has_d, int* tag_out) {
-  const int tag = next_tag(c);
-  const int slot = tag % kFlagSlots;
-  Ctl kk = c->ctl;
-  kk.any_active = c->dev_flags;
-  kk.acct = c->dev_acct;
-  {
-    ProfScope ps(c, 3, 0);
-    hipError_t e = launch_decide(kk, n_items(c), (const GridDesc*)c->grid_desc.p, (int)c->grids.size(), tol, has_d, c->opt.check_every, c->opt.max_sweeps, kFlagSlots,
-                                 c->stream);
-    if (e != hipSuccess) return set_err(c, PG_ERR_DEVICE, "decide launch: %s", hipGetErrorString(e));
-  }
-  HIP_TRY(c, hipEventRecord(c->flag_events[slot], c->stream));
-  *tag_out = tag;
-  return PG_OK;
 }
 
 // One refinement cycle: check_every sweeps, the FP64 residual with v <- v + d, the decision.
@@ -734,16 +750,14 @@ pg_status issue_cycle(pg_ctx* c, double tol, bool graphs, int* tag) {
       HIP_TRY(c, hipGraphLaunch(c->g_sweeps, c->stream));
     }
     {
-      ProfScope ps(c, 1, 0, 0.0, (int)c->tile_groups.size());  // residual (+ the one-block decision)
+      ProfScope ps(c, 1, 0, 0.0, (int)c->tile_groups.size());  // residual pass and its decision
       HIP_TRY(c, hipGraphLaunch(c->g_check, c->stream));
     }
     *tag = next_tag(c);
-    HIP_TRY(c, hipEventRecord(c->flag_events[*tag % kFlagSlots], c->stream));
     return PG_OK;
   }
   PG_TRY(launch_sweeps(c, nchk));
-  PG_TRY(launch_resid_all(c, 1, cycle_launches(c, nchk) & 1));
-  return issue_decide(c, tol, 1, tag);
+  return launch_resid_all(c, 1, cycle_launches(c, nchk) & 1, tol, tag);
 }
 
 // Algorithm 1's inner loop for every active item, after the initial check (its decision tag in
@@ -751,7 +765,18 @@ pg_status issue_cycle(pg_ctx* c, double tol, bool graphs, int* tag) {
 // The host queues as many cycles as the previous step needed before waiting; past that
 // prediction it keeps `lookahead` cycles queued beyond the one whose decision it waits for.
 // Cycles queued after convergence find every item inactive and exit at once.
-pg_status cycle_loop(pg_ctx* c, double tol, bool graphs, int first) {
+pg_status queue_opening(pg_ctx* c, int* first, int ahead);
+pg_status queue_close(pg_ctx* c, bool open_next);
+
+pg_status resume(pg_ctx* c) {
+  hipError_t e = launch_resume(c->ctl, c->stream);
+  if (e != hipSuccess) return set_err(c, PG_ERR_DEVICE, "resume launch: %s", hipGetErrorString(e));
+  c->maybe_stalled = false;
+  return PG_OK;
+}
+
+pg_status cycle_loop(pg_ctx* c, double tol, bool graphs, int first, bool speculate = false,
+                     int* next_first = nullptr) {
   const int nchk = c->opt.check_every;
   const int L = c->opt.lookahead;
   std::deque<int> pending{first};
@@ -759,14 +784,35 @@ pg_status cycle_loop(pg_ctx* c, double tol, bool graphs, int first) {
   const int max_chunks = (c->opt.max_sweeps + nchk - 1) / nchk;
   int issued = 0, consumed = 0, last = -1;
   std::vector<std::pair<int64_t, int64_t>> work;  // active work after decision j (0: the initial check)
+  // Speculation: after the predicted cycles, queue this step's close and the next step's opening
+  // before waiting.  If a decision queued before them converges, the step is done and the next
+  // opening is already on its way; if none does, the close stalls the device, the opening does
+  // nothing, and the host resumes and queues more cycles.
+  bool spec_tried = false, spec_live = false;
+  int spec_tag = -1;
+  size_t spec_b = 0, spec_e = 0;
+  if (next_first) *next_first = -1;
   while (true) {
-    int want = consumed <= c->pred_chunks ? c->pred_chunks : consumed + L;
-    want = std::min(want, consumed + kFlagSlots - 1);  // never reuse a slot still awaited
-    while (issued < max_chunks && issued < want) {
-      c->cur_chunk = ++issued;
-      int tag = 0;
-      PG_TRY(issue_cycle(c, tol, graphs, &tag));
-      pending.push_back(tag);
+    if (!spec_live) {
+      int want = consumed <= c->pred_chunks ? c->pred_chunks : consumed + L;
+      want = std::min(want, consumed + kFlagSlots - 2);  // never reuse a slot still awaited
+      while (issued < max_chunks && issued < want) {
+        c->cur_chunk = ++issued;
+        int tag = 0;
+        PG_TRY(issue_cycle(c, tol, graphs, &tag));
+        pending.push_back(tag);
+      }
+    }
+    if (speculate && !spec_tried) {
+      spec_tried = true;
+      const int saved_chunk = c->cur_chunk;
+      spec_b = c->prof_live.size();
+      c->maybe_stalled = true;
+      PG_TRY(queue_close(c, true));
+      PG_TRY(queue_opening(c, &spec_tag, 1));
+      spec_e = c->prof_live.size();
+      c->cur_chunk = saved_chunk;
+      spec_live = true;
     }
     if (pending.empty()) break;
     const int t0 = pending.front();
@@ -781,6 +827,20 @@ pg_status cycle_loop(pg_ctx* c, double tol, bool graphs, int first) {
       last = consumed - 1;
       break;
     }
+    if (spec_live && pending.empty()) {
+      // the speculative close found the step still iterating: wait until the stalled opening's
+      // decision has reported itself skipped, then let the device go on
+      int a2 = 0, skipped = 0;
+      PG_TRY(wait_decision(c, spec_tag, &a2, &skipped));
+      if (!skipped) return set_err(c, PG_ERR_STATE, "a step was closed before it converged");
+      PG_TRY(resume(c));
+      spec_live = false;
+      for (size_t q = spec_b; q < spec_e; ++q) c->prof_live[q].kind = -1;
+    }
+  }
+  if (spec_live) {
+    c->maybe_stalled = false;
+    if (next_first) *next_first = spec_tag;
   }
   if (last < 0) last = issued;
   c->pred_chunks = last;
@@ -788,6 +848,7 @@ pg_status cycle_loop(pg_ctx* c, double tol, bool graphs, int first) {
   // charge cycle k's sweeps and residual with the items the decision before it left active;
   // launches queued after convergence did no work
   for (size_t q = prof_base; q < c->prof_live.size(); ++q) {
+    if (q >= spec_b && q < spec_e) continue;  // the close and the next opening
     ProfEvent& ev = c->prof_live[q];
     if (ev.chunk > last) { ev.kind = -1; continue; }
     if (ev.chunk < 1 || (ev.kind != 0 && ev.kind != 1)) continue;
@@ -805,20 +866,19 @@ pg_status cycle_loop(pg_ctx* c, double tol, bool graphs, int first) {
 
 pg_status solve_active(pg_ctx* c, double tol) {
   c->cur_chunk = 0;
-  PG_TRY(launch_resid_all(c, 0, 0));
   int first = 0;
-  PG_TRY(issue_decide(c, tol, 0, &first));
+  PG_TRY(launch_resid_all(c, 0, 0, tol, &first));
   return cycle_loop(c, tol, false, first);
 }
 
 // Close a step: advance the device clock, statistics (count_step = 1) and the inductor branch
 // currents.
-pg_status end_step(pg_ctx* c, int count_step = 1) {
+pg_status end_step(pg_ctx* c, int count_step = 1, int begin_next = 0) {
   Ctl k = c->ctl;
   hipError_t e;
   {
     ProfScope ps(c, 3, 0);
-    e = launch_step_end(k, n_items(c), count_step, c->stream);
+    e = launch_step_end(k, n_items(c), count_step, begin_next, c->opt.h, c->src_table, c->stream);
     if (e != hipSuccess) return set_err(c, PG_ERR_DEVICE, "step-end launch: %s", hipGetErrorString(e));
   }
   if (c->n_ind_total) {
@@ -869,23 +929,11 @@ pg_status build_graphs(pg_ctx* c) {
   const uint64_t seq = c->flag_seq_host;
   PG_TRY(capture(c, &c->g_prologue, [&]() -> pg_status {
     PG_TRY(begin_step(c, -1));
-    PG_TRY(launch_resid_all(c, 0, 0));
-    Ctl kk = c->ctl;
-    kk.any_active = c->dev_flags;
-    kk.acct = c->dev_acct;
-    hipError_t e = launch_decide(kk, n_items(c), (const GridDesc*)c->grid_desc.p, (int)c->grids.size(), tol, 0, c->opt.check_every, c->opt.max_sweeps, kFlagSlots,
-                                 c->stream);
-    return e == hipSuccess ? PG_OK : set_err(c, PG_ERR_DEVICE, "decide: %s", hipGetErrorString(e));
+    return launch_resid_all(c, 0, 0, tol, &dummy);
   }));
   PG_TRY(capture(c, &c->g_sweeps, [&]() { return launch_sweeps(c, c->opt.check_every); }));
   PG_TRY(capture(c, &c->g_check, [&]() -> pg_status {
-    PG_TRY(launch_resid_all(c, 1, cycle_launches(c, c->opt.check_every) & 1));
-    Ctl kk = c->ctl;
-    kk.any_active = c->dev_flags;
-    kk.acct = c->dev_acct;
-    hipError_t e = launch_decide(kk, n_items(c), (const GridDesc*)c->grid_desc.p, (int)c->grids.size(), tol, 1, c->opt.check_every, c->opt.max_sweeps, kFlagSlots,
-                                 c->stream);
-    return e == hipSuccess ? PG_OK : set_err(c, PG_ERR_DEVICE, "decide: %s", hipGetErrorString(e));
+    return launch_resid_all(c, 1, cycle_launches(c, c->opt.check_every) & 1, tol, &dummy);
   }));
   PG_TRY(capture(c, &c->g_epilogue, [&]() { return end_step(c, 1); }));
   (void)dummy;
@@ -894,22 +942,55 @@ pg_status build_graphs(pg_ctx* c) {
   return PG_OK;
 }
 
-pg_status one_step(pg_ctx* c) {
+// Queue the opening of a step: clock and activation, right-hand side, sources, first residual
+// and its decision (tag in *first).
+pg_status queue_opening(pg_ctx* c, int* first, int ahead) {
+  c->cur_chunk = 0;
   if (c->opt.graphs) {
     if (!c->graphs_ready) PG_TRY(build_graphs(c));
     {
       ProfScope ps(c, 3, 0);
       HIP_TRY(c, hipGraphLaunch(c->g_prologue, c->stream));
     }
-    const int first = next_tag(c);
-    HIP_TRY(c, hipEventRecord(c->flag_events[first % kFlagSlots], c->stream));
-    c->cur_chunk = 0;
-    PG_TRY(cycle_loop(c, c->opt.tol, true, first));
+    *first = next_tag(c);
+    return PG_OK;
+  }
+  const bool begun = c->begun_next;  // the previous close already opened the clock and the items
+  c->begun_next = false;
+  PG_TRY(begin_step(c, -1, begun, c->step + ahead));
+  return launch_resid_all(c, 0, 0, c->opt.tol, first);
+}
+
+// Queue the close of a step: statistics and clock, inductor branch currents; with open_next
+// (plain launches) the same kernel also opens the next step's clock and items.
+pg_status queue_close(pg_ctx* c, bool open_next) {
+  if (c->opt.graphs) {
     HIP_TRY(c, hipGraphLaunch(c->g_epilogue, c->stream));
+    return PG_OK;
+  }
+  PG_TRY(end_step(c, 1, open_next ? 1 : 0));
+  c->begun_next = open_next;
+  return PG_OK;
+}
+
+// One BE step of every item.  With `speculate`, the next step's opening is queued ahead (see
+// cycle_loop) and picked up by the next call.
+pg_status one_step(pg_ctx* c, bool speculate = false) {
+  int first = 0;
+  if (c->opening_queued) {
+    first = c->opening_tag;
+    c->opening_queued = false;
   } else {
-    PG_TRY(begin_step(c, -1));
-    PG_TRY(solve_active(c, c->opt.tol));
-    PG_TRY(end_step(c));
+    if (c->maybe_stalled) PG_TRY(resume(c));  // an earlier call stopped on an error mid-speculation
+    PG_TRY(queue_opening(c, &first, 0));
+  }
+  int next = -1;
+  PG_TRY(cycle_loop(c, c->opt.tol, c->opt.graphs != 0, first, speculate, &next));
+  if (next >= 0) {
+    c->opening_queued = true;
+    c->opening_tag = next;
+  } else {
+    PG_TRY(queue_close(c, speculate));
   }
   c->step++;
   return PG_OK;
@@ -978,7 +1059,7 @@ pg_status loss_backward(pg_ctx* c, double tol_adj, double* dC, double* dgE, doub
     for (int q = 1; q <= len; ++q) {
       PG_TRY(begin_step(c, A.item));
       PG_TRY(solve_active(c, c->opt.tol));
-      hipError_t e2 = launch_step_end(c->ctl, n_items(c), 2, c->stream);
+      hipError_t e2 = launch_step_end(c->ctl, n_items(c), 2, 0, c->opt.h, c->src_table, c->stream);
       if (e2 != hipSuccess) return set_err(c, PG_ERR_DEVICE, "step-end launch: %s", hipGetErrorString(e2));
       c->step++;
       PG_TRY(state_copy(c, A.item, seg + (size_t)q * ns, 1));
@@ -1060,17 +1141,13 @@ pg_status pg_create(pg_ctx** out, int32_t device, void* stream) {
     return PG_ERR_DEVICE;
   }
   std::memset(c->host_acct, 0, 2 * nslots * sizeof(long long));
-  for (int i = 0; i < nslots; ++i) {
-    hipEvent_t e;
-    if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) { pg_destroy(c); return PG_ERR_DEVICE; }
-    c->flag_events.push_back(e);
-  }
+
   if (dalloc(c, c->c_stats64, 3 * sizeof(long long)) != PG_OK || dalloc(c, c->c_stats32, 4 * sizeof(int32_t)) != PG_OK ||
       dalloc(c, c->c_statsd, 2 * sizeof(double)) != PG_OK) {
     pg_destroy(c);
     return PG_ERR_OOM;
   }
-  if (dalloc(c, c->c_clock, 32) != PG_OK || hipMemset(c->c_clock.p, 0, 32) != hipSuccess) {
+  if (dalloc(c, c->c_clock, 64) != PG_OK || hipMemset(c->c_clock.p, 0, 64) != hipSuccess) {
     pg_destroy(c);
     return PG_ERR_OOM;
   }
@@ -1079,6 +1156,9 @@ pg_status pg_create(pg_ctx** out, int32_t device, void* stream) {
   k.t_now = (double*)((char*)c->c_clock.p + 8);
   k.src_window = (int32_t*)((char*)c->c_clock.p + 16);
   k.flag_seq = (int32_t*)((char*)c->c_clock.p + 24);
+  k.stall = (int32_t*)((char*)c->c_clock.p + 28);
+  k.any_active = c->dev_flags;
+  k.acct = c->dev_acct;
   if (hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking) != hipSuccess) {
     pg_destroy(c);
     return PG_ERR_DEVICE;
@@ -1114,7 +1194,6 @@ void pg_destroy(pg_ctx* c) {
   DBuf* abufs[] = {&c->adj.ckpts, &c->adj.vend, &c->adj.seg, &c->adj.lam0, &c->adj.lam1, &c->adj.arhs,
                    &c->adj.dC, &c->adj.dgE, &c->adj.dgN, &c->adj.part, &c->adj.J, &c->adj.saved_vidx};
   for (DBuf* b : abufs) dfree(*b);
-  for (auto e : c->flag_events) (void)hipEventDestroy(e);
   for (auto& e : c->prof_live) { (void)hipEventDestroy(e.a); (void)hipEventDestroy(e.b); }
   for (auto e : c->prof_pool) (void)hipEventDestroy(e);
   if (c->host_flags) (void)hipHostFree(c->host_flags);
@@ -1471,7 +1550,7 @@ pg_status pg_run_transient(pg_ctx* c, int32_t nsteps, int32_t record_every, int3
   const auto t0 = std::chrono::steady_clock::now();
   int rec = 0;
   for (int k = 0; k < nsteps; ++k) {
-    PG_TRY(one_step(c));
+    PG_TRY(one_step(c, k + 1 < nsteps));
     if (out && ((k + 1) % record_every) == 0) {
       PG_TRY(pg_read_voltages(c, grid, scen, out + (size_t)rec * c->grids[grid].n, c->grids[grid].n));
       ++rec;
@@ -1845,7 +1924,7 @@ extern "C" pg_status pg_autotune(pg_ctx* c, int32_t nsteps, const char* cache_pa
     HIP_TRY(c, hipStreamSynchronize(c->stream));
     const auto t0 = std::chrono::steady_clock::now();
     pg_status st = PG_OK;
-    for (int k = 0; k < nsteps && st == PG_OK; ++k) st = one_step(c);
+    for (int k = 0; k < nsteps && st == PG_OK; ++k) st = one_step(c, k + 1 < nsteps);
     HIP_TRY(c, hipStreamSynchronize(c->stream));
     int32_t failed = 0;
     HIP_TRY(c, hipMemcpy(&failed, c->ctl.stat_failed, sizeof failed, hipMemcpyDeviceToHost));

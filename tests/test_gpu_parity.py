@@ -258,6 +258,30 @@ def test_netlist_upload_equals_mesh_upload():
     assert np.max(np.abs(v_net - Vref[-1])) <= PARITY_V
 
 
+@pytest.mark.parametrize("graphs", [0, 1])
+def test_queued_openings_change_nothing(graphs):
+    """pg_step(n) queues each step's close and the next step's opening before the step's last
+    decision (and backs off when the step needs more sweeps); stepping one call per step never
+    does.  Both give the same voltages bit for bit and the same sweep counts, on a batch whose
+    steps alternate between converging at once and needing several cycles."""
+    w = small_rc(70, 44, seed=43, scenarios=3, steps=60)
+    w.pulses[0] = [compressed(p, start=0.5, width=1.0) for p in w.pulses[0]]
+    res = []
+    for mode in ("one call", "per step"):
+        say(f"[gpu] queued openings graphs={graphs} mode={mode}")
+        with gpu_context(w, precision=pg.PG_PREC_FP32_REFINE, tol=1e-9, omega=1.6, graphs=graphs) as ctx:
+            if mode == "one call":
+                ctx.step(60)
+            else:
+                for _ in range(60):
+                    ctx.step(1)
+            res.append(([ctx.read_voltages(0, s) for s in range(3)], ctx.stats(), ctx.time_index()))
+    for a, b in zip(res[0][0], res[1][0]):
+        assert np.array_equal(a, b)
+    assert res[0][1]["sweeps"] == res[1][1]["sweeps"] and res[0][1]["steps"] == res[1][1]["steps"] == 60
+    assert res[0][2] == res[1][2] == 60
+
+
 def test_uneven_grids_batched_in_one_launch():
     """Three grids of different sizes and layer counts stepped together in one context."""
     ws = [small_rc(33, 70, seed=51, steps=30), small_multilayer(side=77, seed=52, nl=2, pad_every=16, steps=30),
