@@ -31,7 +31,7 @@ def parse():
     ap.add_argument("--steps", type=int, default=1000)
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--workload", default="config1", choices=["config0", "config1", "config2", "config4",
-                                                             "config3a", "config3b"])
+                                                             "config3a", "config3b", "graph1", "graph_mesh1"])
     ap.add_argument("--tol", type=float, default=1e-6)
     ap.add_argument("--precision", default=None, choices=[None, "fp64", "fp32+ref"])
     ap.add_argument("--omega", type=float, default=None)
@@ -66,6 +66,8 @@ TUNED = {
     "config3a": dict(omega=1.7, check_every=8, tile_rows=16, scen_block=16, graphs=0),
     "config3b": dict(omega=1.6, check_every=8, graphs=0),
     "config4": dict(omega=1.6, check_every=6, graphs=0),
+    "graph1": dict(omega=1.6, check_every=8, graphs=0),
+    "graph_mesh1": dict(omega=1.6, check_every=8, graphs=0),
 }
 
 
@@ -94,9 +96,15 @@ def make_workload(name):
     return getattr(workloads, name)()
 
 
+def is_netlist(w):
+    return hasattr(w, "nets")
+
+
 def sweep_kernel_name(w, sweeps_per_launch):
     """The red-black sweep kernel(s) the workload runs: two fused sweeps per launch, or one per
-    launch with scenario blocks for multi-scenario grids."""
+    launch with scenario blocks for multi-scenario grids; the colour kernel for netlists."""
+    if is_netlist(w):
+        return "k_graph_sweep"
     if sweeps_per_launch == 2:
         return "k_sweep_rb2"
     multi = {len(p) > 1 for p in w.pulses}
@@ -116,8 +124,13 @@ def run_gpu(w, steps, warmup, precision, tol, omega, check_every, tile_rows, loo
                     precision=pg.PG_PREC_FP32_REFINE if precision == "fp32+ref" else pg.PG_PREC_FP64,
                     tile_rows=tile_rows, lookahead=lookahead, graphs=graphs, scen_block=scen_block,
                     sweeps_per_launch=sweeps_per_launch)
-    for g, (mesh, scen) in enumerate(zip(w.meshes, w.pulses)):
-        ctx.upload_mesh(mesh, len(scen))
+    grids = w.nets if is_netlist(w) else w.meshes
+    for g, (grid, scen) in enumerate(zip(grids, w.pulses)):
+        if is_netlist(w):
+            ctx.upload_netlist(grid.n, grid.p, grid.source_v, grid.frm, grid.to, grid.kind, grid.value, None,
+                               len(scen))
+        else:
+            ctx.upload_mesh(grid, len(scen))
         for s, p in enumerate(scen):
             ctx.set_pulses(g, s, p)
     ctx.reset()
@@ -146,6 +159,23 @@ def cpu_baseline(workload_name, budget_steps=100):
     from oracle import BEStepper, mesh_to_circuit
     from oracle.sources import currents_at
 
+    if workload_name in ("graph1", "graph_mesh1"):
+        from oracle import BEStepper, Circuit
+        w = getattr(workloads, workload_name)(side=256)
+        net, p = w.nets[0], w.pulses[0][0]
+        sample = f"{w.name}: the 1024x1024 recipe at 256x256 ({net.n:,} nodes)"
+        t0 = time.perf_counter()
+        circ = Circuit(net.n, net.source_v, net.frm.astype(np.int64), net.to.astype(np.int64), net.kind, net.value)
+        st = BEStepper(circ, w.h)
+        t1 = time.perf_counter()
+        v, il = np.full(net.n, net.source_v[0]), np.zeros(int(np.sum(net.kind == "L")))
+        for k in range(1, budget_steps + 1):
+            v, il = st.step(v, il, currents_at(p, k * w.h))
+        t2 = time.perf_counter()
+        return {"value": net.n * budget_steps / (t2 - t0), "unit": "node-steps/s", "cores": 1, "kind": "oracle",
+                "sample": f"{sample}, {budget_steps} backward-Euler steps incl. assembly and factorisation "
+                          f"({t1 - t0:.1f} s) and solves ({t2 - t1:.1f} s); SuperLU is single-threaded",
+                "solve_only_node_steps_per_s": net.n * budget_steps / (t2 - t1)}
     if workload_name == "config1":
         w = workloads.config1(side=256)
         sample = "3-layer 256x256 mesh with the 1024x1024 recipe (196,608 nodes)"
@@ -205,14 +235,14 @@ def measure(name, prec, tol, steps, args):
     omega = args.omega or tuned["omega"]
     chk = args.check_every or tuned["check_every"]
     rows = args.tile_rows or tuned.get("tile_rows", 0)
-    if prec == "fp64" and rows == 16 and w.meshes[0].nl > 1:
+    if prec == "fp64" and rows == 16 and not is_netlist(w) and w.meshes[0].nl > 1:
         rows = 8  # FP64 layered tiles of 16 rows need more registers than one wave slot allows
     graphs = tuned["graphs"] if args.graphs < 0 else args.graphs
     block = args.scen_block or tuned.get("scen_block", 0)
     elapsed, st, kt = run_gpu(w, steps, args.warmup, prec, tol, omega, chk, rows,
                               args.lookahead, args.profile_every, graphs, block,
                               args.sweeps_per_launch)
-    nodes = sum(m.n * len(p) for m, p in zip(w.meshes, w.pulses))
+    nodes = w.nodes
     value = st["node_updates"] / elapsed
     spl = st["options"]["sweeps_per_launch"] or 1
     roof = None

@@ -188,6 +188,15 @@ pg_status pg_netlist_to_mesh(int32_t n, int32_t p, const double* source_v, int32
                              double* via_g, double* via_L, int32_t* pad_node, double* pad_g, double* pad_L,
                              double* vdd, char* msg, size_t msg_len);
 
+/* The colouring used for a general netlist (host only, no device): color[i] in 0..n_colors-1
+ * for trivial node i, with no R, L or C branch joining two nodes of one colour (two colours when
+ * the node graph is bipartite, else the greedy colouring in node order), and the storage slot of
+ * each node: colours in order, node order inside a colour, each colour padded to a multiple of
+ * 64 slots (n_slots in all).  color and slot are caller arrays of n entries or NULL. */
+pg_status pg_netlist_coloring(int32_t n, int32_t p, const double* source_v, int32_t m, const int32_t* from,
+                              const int32_t* to, const uint8_t* kind, const double* value, int32_t* color,
+                              int32_t* slot, int32_t* n_colors, int64_t* n_slots, char* msg, size_t msg_len);
+
 /* Create a context on HIP device `device` (must be gfx950).  `stream` is a hipStream_t
  * (for instance torch.cuda.current_stream().cuda_stream) or NULL for a stream owned by
  * the context.  Every kernel and copy of the context runs on that stream. */
@@ -204,9 +213,25 @@ pg_status pg_get_options(const pg_ctx* ctx, pg_options* out);
  * id (0, 1, ...) in *grid_id.  All grids of a context advance together in time. */
 pg_status pg_upload_mesh(pg_ctx* ctx, const pg_mesh* mesh, int32_t n_scen, int32_t* grid_id);
 
-/* Upload a netlist (Sec. III branch form) through its layered-mesh form (pg_netlist_to_mesh),
- * then as pg_upload_mesh.  Errors as in pg_netlist_to_mesh, with the message in
- * pg_last_error. */
+/* Upload a netlist (Sec. III branch form, as in pg_validate_netlist).
+ * mesh_dims != NULL: through its layered-mesh form (pg_netlist_to_mesh), then as pg_upload_mesh;
+ * errors as in pg_netlist_to_mesh.
+ * mesh_dims == NULL: as a general graph (any topology the checks of pg_validate_netlist accept),
+ * swept by the colour-ordered kernels: the trivial nodes are coloured (pg_netlist_coloring) and
+ * one sweep updates the colours in order (eqs. 16-17; Theorem 1 covers any order).  Element
+ * rules (eqs. 8-11, inductor current kept as state): R to a supply or ground and C to a supply or
+ * ground act on the diagonal (a supply's voltage enters the right-hand side); C between two
+ * trivial nodes is a coupling capacitor (an off-diagonal term of C/h in M and in the right-hand
+ * side); every L is a pure inductor with companion g = h/L, alpha = 1 (a series R-L branch is
+ * its R and L through an internal trivial node); I branches only mark positions, the waveforms
+ * come from pg_set_pwl / pg_set_pulses with node = trivial node (current drawn to ground).  The
+ * state starts at v = source_v[0] (0 if p = 0).  Inductor currents (pg_read_inductor_currents,
+ * pg_set_state) are per L branch in netlist order, positive from `from` to `to`.  Built for
+ * such grids: stepping, pg_run_transient, reads, pg_set_state, graphs and scenarios, and
+ * pg_dc_operating_point when the grid has no inductor; pg_estimate_omega,
+ * pg_error_bound_factor, the loss adjoint and pg_update_mesh_values return
+ * PG_ERR_UNSUPPORTED, as does the Jacobi ordering.
+ * Errors are reported with the message in pg_last_error. */
 pg_status pg_upload_netlist(pg_ctx* ctx, int32_t n, int32_t p, const double* source_v, int32_t m,
                             const int32_t* from, const int32_t* to, const uint8_t* kind, const double* value,
                             const int32_t* mesh_dims, int32_t n_scen, int32_t* grid_id);
@@ -292,9 +317,15 @@ pg_status pg_grid_info(const pg_ctx* ctx, int32_t grid, int32_t* nx, int32_t* ny
  * without timing.  *chosen (may be NULL) receives the options set. */
 pg_status pg_autotune(pg_ctx* ctx, int32_t nsteps, const char* cache_path, pg_options* chosen);
 
-/* Copy the node voltages (n doubles) or inductor currents (n_vias + n_pads doubles, via
- * then pad order, zero for resistive branches) of one scenario to host memory (blocking)
- * or to device memory (queued on the context stream). */
+/* Size of a general-netlist grid: trivial nodes, colours, storage slots, off-diagonal entries
+ * of M (both directions) and L branches.  PG_ERR_INVALID_ARG for a mesh grid. */
+pg_status pg_graph_info(const pg_ctx* ctx, int32_t grid, int32_t* n_nodes, int32_t* n_colors, int64_t* n_slots,
+                        int64_t* nnz, int32_t* n_inductors);
+
+/* Copy the node voltages (n doubles) or inductor currents of one scenario to host memory
+ * (blocking) or to device memory (queued on the context stream).  Inductor currents of a mesh:
+ * n_vias + n_pads doubles, via then pad order, zero for resistive branches; of a general
+ * netlist: one per L branch in netlist order. */
 pg_status pg_read_voltages(pg_ctx* ctx, int32_t grid, int32_t scen, double* out, int64_t n);
 pg_status pg_read_voltages_dev(pg_ctx* ctx, int32_t grid, int32_t scen, double* dev_out, int64_t n);
 pg_status pg_read_inductor_currents(pg_ctx* ctx, int32_t grid, int32_t scen, double* out, int64_t n);

@@ -18,8 +18,8 @@ ROOT = os.path.dirname(HERE)
 OBJ = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libpgrid.so")
 
-HIP_SOURCES = ["kernels.hip", "runtime.hip"]
-HOST_SOURCES = ["validate.cpp", "netlist.cpp"]
+HIP_SOURCES = ["kernels.hip", "kernels_graph.hip", "runtime.hip"]
+HOST_SOURCES = ["validate.cpp", "netlist.cpp", "graph.cpp"]
 ARCH = "gfx950"
 
 HIPCC_FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",

@@ -44,19 +44,6 @@ __device__ __forceinline__ auto pick(const V& v, int e) -> decltype(v.x) { retur
 template <typename T>
 __device__ __forceinline__ V2<T> zero2() { V2<T> z; z.x = T(0); z.y = T(0); return z; }
 
-// Tiles are numbered row-major over each grid.  Workgroups are dealt to the 8 XCDs round
-// robin, so block b runs on XCD b % 8; give each XCD a contiguous run of tiles so vertically
-// adjacent tiles (which re-read each other's halo rows) share that XCD's L2.
-__device__ __forceinline__ int xcd_tile(int ntiles) {
-  const int per = (int)(gridDim.x / 8u);
-  const int b = (int)blockIdx.x;
-  const int t = (b % 8) * per + b / 8;
-  return t < ntiles ? t : -1;
-}
-
-__device__ __forceinline__ double nan_max(double m, double x) {
-  return (x > m || x != x) ? x : m;
-}
 
 // Coefficients of one node of a pair: the conductances to its six neighbours, 1/M_ii, r_i.
 template <typename T>
@@ -254,10 +241,7 @@ __device__ void decide_block(const Ctl& c, const DecideArgs& da) {
     } else {
       for (int sc = 0; sc < D.S && !any_in_grid; ++sc) any_in_grid = c.active[D.item0 + sc] != 0;
     }
-    if (any_in_grid) {
-      const unsigned long long plane = (unsigned long long)D.nx * D.ny, n = plane * D.nl;
-      atomicAdd(&act_coef, 3ull * n + plane * (D.nl - 1));
-    }
+    if (any_in_grid) atomicAdd(&act_coef, (unsigned long long)D.coef_words);
   }
   __syncthreads();
   if (threadIdx.x == 0) {
@@ -1034,7 +1018,7 @@ __global__ void k_inductors(const GridDesc* __restrict__ grids, const int32_t* _
   const double geq = G.ind_geq[k], al = G.ind_alpha[k];
   for (int s = 0; s < G.S; ++s) {
     const double* __restrict__ v = G.v[c.vidx[G.item0 + s]] + (int64_t)s * G.nstore;
-    const double vb = bslot >= 0 ? v[bslot] : G.vdd;
+    const double vb = bslot >= 0 ? v[bslot] : (G.ind_vfar ? G.ind_vfar[k] : G.vdd);
     double* q = G.ind_i + (int64_t)s * G.n_ind + k;
     *q = al * *q + geq * (v[a] - vb);
   }
@@ -1160,7 +1144,6 @@ __global__ __launch_bounds__(kThreads) void k_adj_grad(const Tile* __restrict__ 
 // ------------------------------------------------------------------------------------
 // Launch wrappers
 // ------------------------------------------------------------------------------------
-static inline unsigned xcd_blocks(int ntiles) { return 8u * (unsigned)((ntiles + 7) / 8); }
 
 hipError_t launch_step_begin(const Ctl& c, int I, int only_item, double h, const SourceTable& src,
                              hipStream_t s) {

@@ -1,0 +1,176 @@
+// gfx950 kernels for general netlists (Sec. III): the same backward-Euler step and
+// correction sweeps as the mesh kernels, on an arbitrary node graph.
+//
+// The nodes are stored colour by colour (no branch joins two nodes of one colour), so all
+// nodes of a colour update independently: one launch per colour, in colour order, is one
+// Gauss-Seidel/SOR sweep of eqs. 16-17 in that node order (Theorem 1), done in place.
+// Neighbours come from a sliced-ELL table with 64-slot slices: lane j of a wavefront owns
+// slot 64 s + j and reads entry k of its row at sl_off[s] + 64 k + j, so the table streams
+// with unit stride and only the neighbour values are gathered (from L2 for graphs whose node
+// numbering keeps neighbours close).
+#include "pgrid_internal.h"
+
+namespace pgrid {
+
+namespace {
+
+// b = (C/h) v + G0 v_s + (h/L) v_s - inductor history, with C/h's off-diagonal coupling terms.
+__global__ __launch_bounds__(kChunk) void k_graph_rhs(const GraphChunk* __restrict__ chunks, int n,
+                                                     const GridDesc* __restrict__ grids, Ctl c) {
+  if (*c.stall) return;  // a stalled step opening
+  const int ci = xcd_tile(n);
+  if (ci < 0) return;
+  const GraphChunk ch = chunks[ci];
+  if ((int)threadIdx.x >= ch.count) return;
+  const GridDesc& G = grids[ch.grid];
+  const int64_t off = (int64_t)ch.scen * G.nstore;
+  const int i = ch.slot0 + (int)threadIdx.x;
+  const double* __restrict__ v = G.v[c.vidx[ch.item]] + off;
+  double bb = G.ch64[i] * v[i] + G.bconst64[i];
+  if (G.sl_cap) {
+    const int base = G.sl_off[i >> 6], w = (G.sl_off[(i >> 6) + 1] - base) >> 6;
+    for (int k = 0; k < w; ++k) {
+      const int e = base + (k << 6) + (i & 63);
+      bb -= G.sl_cap[e] * v[G.sl_col[e]];
+    }
+  }
+  if (G.n_ind) {
+    const double* __restrict__ il = G.ind_i + (int64_t)ch.scen * G.n_ind;
+    for (int j = G.inc_off[i]; j < G.inc_off[i + 1]; ++j) {
+      const int e = G.inc_ind[j];
+      const int kk = (e > 0 ? e : -e) - 1;
+      const double term = G.ind_alpha[kk] * il[kk];
+      bb += (e > 0) ? -term : term;
+    }
+  }
+  G.b[off + i] = bb;
+}
+
+// One colour of a sweep on M d = r: d_i <- d_i + omega ((r_i + sum_j w_ij d_j) / M_ii - d_i).
+// zero_in: the sweep starts a refinement cycle from d = 0, so the old d_i and every neighbour
+// not yet updated in this sweep (slot >= lim) count as zero.
+template <typename T>
+__global__ __launch_bounds__(kChunk) void k_graph_sweep(const GraphChunk* __restrict__ chunks, int n,
+                                                       const GridDesc* __restrict__ grids, Ctl c, int zero_in,
+                                                       T omega) {
+  const int ci = xcd_tile(n);
+  if (ci < 0) return;
+  const GraphChunk ch = chunks[ci];
+  if (!c.active[ch.item] || (int)threadIdx.x >= ch.count) return;
+  const GridDesc& G = grids[ch.grid];
+  const int64_t off = (int64_t)ch.scen * G.nstore;
+  const int i = ch.slot0 + (int)threadIdx.x;
+  T* __restrict__ d = static_cast<T*>(G.d[0]) + off;
+  const T* __restrict__ r = static_cast<const T*>(G.r) + off;
+  const T* __restrict__ wv = static_cast<const T*>(G.sl_ws);
+  const int base = G.sl_off[i >> 6], w = (G.sl_off[(i >> 6) + 1] - base) >> 6;
+  T acc = r[i];
+  if (zero_in) {
+    for (int k = 0; k < w; ++k) {
+      const int e = base + (k << 6) + (i & 63);
+      const int j = G.sl_col[e];
+      if (j < ch.lim) acc += wv[e] * d[j];
+    }
+  } else {
+    for (int k = 0; k < w; ++k) {
+      const int e = base + (k << 6) + (i & 63);
+      acc += wv[e] * d[G.sl_col[e]];
+    }
+  }
+  const T inv = static_cast<const T*>(G.invDs)[i];
+  const T old = zero_in ? T(0) : d[i];
+  d[i] = old + omega * (inv * acc - old);
+}
+
+// FP64 residual r = b - M v' with v' = v + d[0] (has_d) written to the other voltage buffer, r in
+// the sweep precision, and the Jacobi-scaled norm max |r_i| / M_ii of the chunk's item.
+template <typename T>
+__global__ __launch_bounds__(kChunk) void k_graph_resid(const GraphChunk* __restrict__ chunks, int n,
+                                                       const GridDesc* __restrict__ grids, Ctl c, int has_d) {
+  __shared__ double wmax[kChunk / 64];
+  if (*c.stall) return;
+  const int ci = xcd_tile(n);
+  if (ci < 0) return;
+  const GraphChunk ch = chunks[ci];
+  if (!c.active[ch.item]) return;  // uniform over the block
+  const GridDesc& G = grids[ch.grid];
+  const int64_t off = (int64_t)ch.scen * G.nstore;
+  const int vi = c.vidx[ch.item];
+  const double* __restrict__ v = G.v[vi] + off;
+  const T* __restrict__ d = static_cast<const T*>(G.d[0]) + off;
+  double m = 0.0;
+  if ((int)threadIdx.x < ch.count) {
+    const int i = ch.slot0 + (int)threadIdx.x;
+    const double D = G.D64[i];
+    const double own = has_d ? v[i] + (double)d[i] : v[i];
+    double acc = G.b[off + i] - D * own;
+    const int base = G.sl_off[i >> 6], w = (G.sl_off[(i >> 6) + 1] - base) >> 6;
+    if (has_d) {
+      for (int k = 0; k < w; ++k) {
+        const int e = base + (k << 6) + (i & 63);
+        const int j = G.sl_col[e];
+        acc += G.sl_w64[e] * (v[j] + (double)d[j]);
+      }
+      G.v[vi ^ 1][off + i] = own;
+    } else {
+      for (int k = 0; k < w; ++k) {
+        const int e = base + (k << 6) + (i & 63);
+        acc += G.sl_w64[e] * v[G.sl_col[e]];
+      }
+    }
+    static_cast<T*>(G.r)[off + i] = (T)acc;
+    if (D > 0.0) m = fabs(acc) / D;  // padding slots (D = 0) carry r = 0
+  }
+  for (int o = 32; o > 0; o >>= 1) m = nan_max(m, __shfl_xor(m, o, 64));
+  if ((threadIdx.x & 63) == 0) wmax[threadIdx.x >> 6] = m;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double bm = wmax[0];
+    for (int k = 1; k < kChunk / 64; ++k) bm = nan_max(bm, wmax[k]);
+    atomicMax(&c.norm_bits[ch.item], (unsigned long long)__double_as_longlong(bm));
+  }
+}
+
+__global__ void k_gather(const double* __restrict__ src, const int32_t* __restrict__ slot,
+                         double* __restrict__ dst, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) dst[i] = src[slot[i]];
+}
+
+}  // namespace
+
+hipError_t launch_graph_rhs(const GraphChunk* ch, int n, const GridDesc* grids, const Ctl& c, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_graph_rhs, dim3(xcd_blocks(n)), dim3(kChunk), 0, s, ch, n, grids, c);
+  return hipGetLastError();
+}
+
+hipError_t launch_graph_sweep(bool fp32, const GraphChunk* ch, int n, const GridDesc* grids, const Ctl& c,
+                              int zero_in, double omega, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  if (fp32)
+    hipLaunchKernelGGL(k_graph_sweep<float>, dim3(xcd_blocks(n)), dim3(kChunk), 0, s, ch, n, grids, c, zero_in,
+                       (float)omega);
+  else
+    hipLaunchKernelGGL(k_graph_sweep<double>, dim3(xcd_blocks(n)), dim3(kChunk), 0, s, ch, n, grids, c, zero_in,
+                       omega);
+  return hipGetLastError();
+}
+
+hipError_t launch_graph_resid(bool fp32, const GraphChunk* ch, int n, const GridDesc* grids, const Ctl& c,
+                              int has_d, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  if (fp32)
+    hipLaunchKernelGGL(k_graph_resid<float>, dim3(xcd_blocks(n)), dim3(kChunk), 0, s, ch, n, grids, c, has_d);
+  else
+    hipLaunchKernelGGL(k_graph_resid<double>, dim3(xcd_blocks(n)), dim3(kChunk), 0, s, ch, n, grids, c, has_d);
+  return hipGetLastError();
+}
+
+hipError_t launch_gather(const double* src, const int32_t* slot, double* dst, int64_t n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_gather, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, src, slot, dst, n);
+  return hipGetLastError();
+}
+
+}  // namespace pgrid

@@ -14,6 +14,7 @@
 #include <vector>
 
 #include "../../include/pgrid.h"
+#include "graph_form.h"
 
 namespace pgrid {
 // Records a message as the context's last error (runtime.hip).
@@ -188,6 +189,12 @@ pg_status pg_upload_netlist(pg_ctx* ctx, int32_t n, int32_t p, const double* sou
                             const int32_t* mesh_dims, int32_t n_scen, int32_t* grid_id) {
   if (!ctx) return PG_ERR_INVALID_ARG;
   char msg[256] = {0};
+  if (!mesh_dims) {  // a general netlist: colour-ordered graph form
+    pgrid::GraphForm g;
+    pg_status st = pgrid::build_graph_form(n, p, source_v, m, from, to, kind, value, g, msg, sizeof msg);
+    if (st != PG_OK) return pgrid::report_error(ctx, st, msg);
+    return pgrid::upload_graph(ctx, g, p > 0 ? source_v[0] : 0.0, n_scen, grid_id);
+  }
   MeshForm f;
   pg_status st = map_netlist(n, p, source_v, m, from, to, kind, value, mesh_dims, f, msg, sizeof msg);
   if (st != PG_OK) return pgrid::report_error(ctx, st, msg);

@@ -11,13 +11,35 @@ constexpr int kThreads = 256;     // threads per workgroup of the element-wise k
 constexpr int kScenBlock = 8;     // scenarios per sweep/residual workgroup on multi-scenario grids
 constexpr int kPitchAlign = 4;    // row pitch multiple (keeps pair and quad accesses aligned)
 
-// Per-grid device descriptor.  Every per-node array is stored with a row pitch X >= nx
-// (a multiple of kPitchAlign): slot (l*ny + y)*X + x.  Coefficients are zero in the padding
-// columns, at x = nx-1 (gE), y = ny-1 (gN), on the top layer (gU) and wherever no via exists;
-// invD is zero in the padding, so padding corrections stay zero.  A grid carries S current
-// scenarios that share its coefficients; state arrays are scenario-major (scenario s occupies
-// slots [s*nstore, (s+1)*nstore)), so one scenario is an ordinary contiguous field.
+// Work items (tiles, chunks) are numbered in storage order.  Workgroups are dealt to the 8 XCDs
+// round robin, so block b runs on XCD b % 8; give each XCD a contiguous run of work items so
+// neighbouring ones (which re-read each other's halo or neighbour values) share that XCD's L2.
+// Launch xcd_blocks(n) blocks.
+__device__ __forceinline__ int xcd_tile(int ntiles) {
+  const int per = (int)(gridDim.x / 8u);
+  const int b = (int)blockIdx.x;
+  const int t = (b % 8) * per + b / 8;
+  return t < ntiles ? t : -1;
+}
+inline unsigned xcd_blocks(int ntiles) { return 8u * (unsigned)((ntiles + 7) / 8); }
+
+// max that keeps a NaN (a diverged residual must never read as converged)
+__device__ __forceinline__ double nan_max(double m, double x) {
+  return (x > m || x != x) ? x : m;
+}
+
+// Per-grid device descriptor.  A layered mesh (kind 0) stores every per-node array with a row
+// pitch X >= nx (a multiple of kPitchAlign): slot (l*ny + y)*X + x.  Coefficients are zero in
+// the padding columns, at x = nx-1 (gE), y = ny-1 (gN), on the top layer (gU) and wherever no
+// via exists; invD is zero in the padding, so padding corrections stay zero.  A general graph
+// (kind 1, nx = nodes, ny = nl = 1) stores its nodes colour by colour, each colour padded to
+// whole 64-slot slices, and M's off-diagonal part as a sliced-ELL neighbour table (entry k of
+// slot i at sl_off[i/64] + 64 k + i%64; w = -M_ij > 0, padding entries point at their own slot
+// with w = 0); its padding slots have D = invD = 0.  A grid carries S current scenarios that
+// share its coefficients; state arrays are scenario-major (scenario s occupies slots
+// [s*nstore, (s+1)*nstore)), so one scenario is an ordinary contiguous field.
 struct GridDesc {
+  int32_t kind;                    // 0 layered mesh, 1 general graph
   int32_t nx, ny, nl, S;
   int32_t X;                       // row pitch
   int32_t item0;                   // control-block item of scenario 0 (item = item0 + s)
@@ -48,8 +70,25 @@ struct GridDesc {
   double* ind_i;                   // [S][n_ind] branch currents
   const int32_t* inc_off;          // [nstore+1] (null when n_ind == 0)
   const int32_t* inc_ind;          // signed: k+1 if the slot is ind_a[k], -(k+1) if ind_b[k]
+  const double* ind_vfar;          // far-end voltage of a branch with ind_b = -1 (null: vdd)
   double vdd;
+  // general graph: neighbour table (see above) and coupling capacitances C_ij / h per entry
+  const int32_t* sl_off;
+  const int32_t* sl_col;
+  const double* sl_w64;
+  const void* sl_ws;               // w in the sweep precision
+  const double* sl_cap;            // null when no capacitor joins two nodes
+  // coefficient words one sweep reads (for the activity accounting of the decision)
+  int64_t coef_words;
 };
+
+// 256 consecutive slots of one scenario of a general-graph grid, all of one colour in the sweep
+// lists; lim is the first slot of that colour (slots at or above it have not been updated yet
+// in the current sweep).
+struct GraphChunk {
+  int32_t grid, item, scen, slot0, count, lim;
+};
+constexpr int kChunk = 256;
 
 // One 128 x rows tile of one grid (all layers) for scenario `scen`, or, in the scenario-block
 // lists used by the sweeps and residuals of multi-scenario grids, for scenarios
@@ -169,6 +208,14 @@ hipError_t launch_item_vec(bool fp32, const Tile* tiles, int ntiles, int tile_ro
                            const Ctl& c, int op, int which, double s, hipStream_t st);
 // Clear the stall flag (after the host has re-queued a stalled step's remaining work).
 hipError_t launch_resume(const Ctl& c, hipStream_t s);
+// general graphs: right-hand side, one colour of a sweep (in place on d[0]), FP64 residual
+// with v <- v + d[0] and its scaled norm, and the gather of one scenario's voltages into node order
+hipError_t launch_graph_rhs(const GraphChunk* ch, int n, const GridDesc* grids, const Ctl& c, hipStream_t s);
+hipError_t launch_graph_sweep(bool fp32, const GraphChunk* ch, int n, const GridDesc* grids, const Ctl& c,
+                              int zero_in, double omega, hipStream_t s);
+hipError_t launch_graph_resid(bool fp32, const GraphChunk* ch, int n, const GridDesc* grids, const Ctl& c,
+                              int has_d, hipStream_t s);
+hipError_t launch_gather(const double* src, const int32_t* slot, double* dst, int64_t n, hipStream_t s);
 hipError_t launch_swap_vidx(const Ctl& c, int item, int32_t* saved, hipStream_t s);
 hipError_t launch_inductors(const GridDesc* grids, const int32_t* ind_grid,
                             const int32_t* ind_local, int n_total, const Ctl& c, hipStream_t s);

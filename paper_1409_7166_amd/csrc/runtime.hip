@@ -12,6 +12,7 @@
 #include <vector>
 
 #include "../../include/pgrid.h"
+#include "graph_form.h"
 #include "pgrid_internal.h"
 
 using namespace pgrid;
@@ -33,12 +34,14 @@ struct DBuf {
 };
 
 struct GridHost {
+  int kind = 0;                                  // 0 layered mesh, 1 general graph (form below)
   int32_t nx = 0, ny = 0, nl = 0, S = 1;
   int32_t X = 0;                                 // storage row pitch (>= nx, multiple of kPitchAlign)
   int32_t item0 = 0;                             // control-block item of scenario 0
   int64_t n = 0, P = 0;                          // mesh nodes, nodes per layer
   int64_t nstore = 0;                            // storage slots per scenario, nl*ny*X
-  int64_t storage(int64_t node) const {          // mesh node id -> storage slot
+  int64_t storage(int64_t node) const {          // node id -> storage slot
+    if (kind) return form.slot[node];
     const int64_t l = node / P, rem = node - l * P, y = rem / nx, x = rem - y * nx;
     return (l * ny + y) * X + x;
   }
@@ -47,12 +50,17 @@ struct GridHost {
   std::vector<int32_t> via_node, pad_node;
   std::vector<double> via_g, via_L, pad_g, pad_L;
   std::vector<Src> src;                          // per scenario
-  // inductive branches in via-then-pad order; branch_of[k] = index into that order
+  GraphForm form;                                // general graph: colouring, slots, neighbour table
+  // inductive branches in via-then-pad order (mesh) or netlist order (graph); ind_branch[k] =
+  // index into that order; ind_sign[k] turns the stored near -> far current into the branch's
   std::vector<int32_t> ind_a, ind_b, ind_branch;
+  std::vector<double> ind_sign;
+  int64_t coef_words = 0;                        // coefficient words of one sweep (accounting)
   // device buffers
   DBuf gE64, gN64, gU64, D64, ch64, bconst64, gEs, gNs, gUs, invDs;
   DBuf v0, v1, b, r, d0, d1;
-  DBuf ind_a_d, ind_b_d, ind_geq_d, ind_alpha_d, ind_i_d, inc_off_d, inc_ind_d;
+  DBuf ind_a_d, ind_b_d, ind_geq_d, ind_alpha_d, ind_i_d, inc_off_d, inc_ind_d, ind_vfar_d;
+  DBuf slot_d, sl_off_d, sl_col_d, sl_w64_d, sl_ws_d, sl_cap_d;
   int sweep_fp32 = -1;                           // precision the sweep buffers were built for
 };
 
@@ -98,6 +106,12 @@ struct pg_ctx {
   std::vector<Group> tile_groups;                 // sweep/residual tiles by (layers, block): [off, off+count) of tiles_sweep
   int ntiles_all = 0;
   int tile_rows = 16;
+  // general-graph chunks: all slots (right-hand side, residual) and, per colour index, the
+  // chunks of that colour over every graph grid ([off, off+count) of g_chunks_sweep)
+  DBuf g_chunks_all, g_chunks_sweep;
+  int n_gchunks_all = 0;
+  std::vector<std::pair<int, int>> gcolor;
+  std::vector<int> item_gchunk_off, item_gchunk_cnt;
   int n_src = 0, n_ind_total = 0;
   SourceTable src_table{};                       // device source tables (see pgrid_internal.h)
   DBuf src_win_t0;
@@ -276,7 +290,51 @@ int n_items(const pg_ctx* c) {
 // Builds the padded FP64 coefficient arrays and the companion model of every inductive
 // branch for step h (series R-L: g_eq = h/(L + hR), alpha = L/(L + hR); eq. 10 with the
 // inductor current kept as state), then the sweep-precision copies.
-pg_status build_grid(pg_ctx* c, int gi) {
+// Residual and correction buffers in the sweep precision (zero, so padding slots read as zero).
+pg_status alloc_sweep_bufs(pg_ctx* c, GridHost& G, bool f32) {
+  const size_t es = f32 ? sizeof(float) : sizeof(double);
+  const size_t nss = (size_t)G.nstore * G.S;
+  if (G.sweep_fp32 != (int)f32) {
+    PG_TRY(dalloc(c, G.r, nss * es)); PG_TRY(dalloc(c, G.d0, nss * es)); PG_TRY(dalloc(c, G.d1, nss * es));
+    HIP_TRY(c, hipMemsetAsync(G.r.p, 0, nss * es, c->stream));
+    HIP_TRY(c, hipMemsetAsync(G.d0.p, 0, nss * es, c->stream));
+    HIP_TRY(c, hipMemsetAsync(G.d1.p, 0, nss * es, c->stream));
+    G.sweep_fp32 = (int)f32;
+  }
+  return PG_OK;
+}
+
+// Inductive branches (G.ind_a / ind_b filled): companion values, per-branch far voltages
+// (vfar, or null for the grid's vdd), the branch currents (kept when the branch set is
+// unchanged) and the slot -> branch incidence in CSR form.
+pg_status upload_inductors(pg_ctx* c, GridHost& G, const std::vector<double>& geq,
+                           const std::vector<double>& alpha, const std::vector<double>* vfar) {
+  const int64_t ns = G.nstore;
+  const int ni = (int)G.ind_a.size();
+  PG_TRY(upload(c, G.ind_a_d, G.ind_a)); PG_TRY(upload(c, G.ind_b_d, G.ind_b));
+  PG_TRY(upload(c, G.ind_geq_d, geq)); PG_TRY(upload(c, G.ind_alpha_d, alpha));
+  if (vfar) PG_TRY(upload(c, G.ind_vfar_d, *vfar)); else dfree(G.ind_vfar_d);
+  if (G.ind_i_d.bytes != (size_t)ni * G.S * sizeof(double)) {
+    PG_TRY(dalloc(c, G.ind_i_d, (size_t)ni * G.S * sizeof(double)));
+    if (ni) HIP_TRY(c, hipMemsetAsync(G.ind_i_d.p, 0, (size_t)ni * G.S * sizeof(double), c->stream));
+  }
+  if (ni) {
+    std::vector<int32_t> cnt(ns + 1, 0);
+    for (int k = 0; k < ni; ++k) { cnt[G.ind_a[k] + 1]++; if (G.ind_b[k] >= 0) cnt[G.ind_b[k] + 1]++; }
+    for (int64_t i = 0; i < ns; ++i) cnt[i + 1] += cnt[i];
+    std::vector<int32_t> inc(cnt[ns]), fillp(cnt.begin(), cnt.end() - 1);
+    for (int k = 0; k < ni; ++k) {
+      inc[fillp[G.ind_a[k]]++] = k + 1;
+      if (G.ind_b[k] >= 0) inc[fillp[G.ind_b[k]]++] = -(k + 1);
+    }
+    PG_TRY(upload(c, G.inc_off_d, cnt)); PG_TRY(upload(c, G.inc_ind_d, inc));
+  } else {
+    dfree(G.inc_off_d); dfree(G.inc_ind_d);
+  }
+  return PG_OK;
+}
+
+pg_status build_mesh_grid(pg_ctx* c, int gi) {
   GridHost& G = c->grids[gi];
   const double h = c->opt.h;
   // DC matrix (the limit h -> infinity): no C/h, and a series R-L branch is its resistor
@@ -350,43 +408,136 @@ pg_status build_grid(pg_ctx* c, int gi) {
     dfree(G.gEs); dfree(G.gNs); dfree(G.gUs);
     PG_TRY(upload(c, G.invDs, inv));
   }
-  const size_t es = f32 ? sizeof(float) : sizeof(double);
-  const size_t nss = (size_t)ns * G.S;
-  if (G.sweep_fp32 != (int)f32) {
-    PG_TRY(dalloc(c, G.r, nss * es)); PG_TRY(dalloc(c, G.d0, nss * es)); PG_TRY(dalloc(c, G.d1, nss * es));
-    // padding slots of the correction and residual must read as zero
-    HIP_TRY(c, hipMemsetAsync(G.r.p, 0, nss * es, c->stream));
-    HIP_TRY(c, hipMemsetAsync(G.d0.p, 0, nss * es, c->stream));
-    HIP_TRY(c, hipMemsetAsync(G.d1.p, 0, nss * es, c->stream));
-    G.sweep_fp32 = (int)f32;
+  PG_TRY(alloc_sweep_bufs(c, G, f32));
+  G.ind_sign.assign(G.ind_a.size(), 1.0);
+  PG_TRY(upload_inductors(c, G, geq, alpha, nullptr));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  return PG_OK;
+}
+
+// General graph: the same quantities from the graph form.  Diagonal D_i = C_i/h + the
+// conductances at i + h/L of every inductor at i; off-diagonal w_ij = g_ij + h/L_ij + C_ij/h
+// (eq. 11, M = C/h + G + hL, with the inductor current kept as state: alpha = 1, g_eq = h/L).
+pg_status build_graph_grid(pg_ctx* c, int gi) {
+  GridHost& G = c->grids[gi];
+  const GraphForm& F = G.form;
+  const double h = c->opt.h;
+  const bool dc = c->dc_mode;
+  if (dc && !F.ind_near.empty())
+    return set_err(c, PG_ERR_UNSUPPORTED,
+                   "grid %d: an inductor is a short circuit at DC; the DC point of a general netlist with "
+                   "inductors is not built", gi);
+  const int64_t ns = G.nstore;
+  std::vector<double> D(ns, 0.0), ch(ns, 0.0), bc(ns, 0.0), inv(ns, 0.0);
+  for (int32_t i = 0; i < F.n; ++i) {
+    const int32_t s = F.slot[i];
+    ch[s] = dc ? 0.0 : F.c_diag[i] / h;
+    D[s] = ch[s] + F.g_diag[i];
+    bc[s] = F.b_res[i];
   }
-  // inductors: keep the branch currents if the branch set is unchanged
-  const int ni = (int)G.ind_a.size();
-  PG_TRY(upload(c, G.ind_a_d, G.ind_a)); PG_TRY(upload(c, G.ind_b_d, G.ind_b));
-  PG_TRY(upload(c, G.ind_geq_d, geq)); PG_TRY(upload(c, G.ind_alpha_d, alpha));
-  if (G.ind_i_d.bytes != (size_t)ni * G.S * sizeof(double)) {
-    PG_TRY(dalloc(c, G.ind_i_d, (size_t)ni * G.S * sizeof(double)));
-    if (ni) HIP_TRY(c, hipMemsetAsync(G.ind_i_d.p, 0, (size_t)ni * G.S * sizeof(double), c->stream));
+  G.ind_a.clear(); G.ind_b.clear(); G.ind_branch.clear(); G.ind_sign.clear();
+  std::vector<double> geq, alpha, vfar;
+  for (size_t k = 0; k < F.ind_near.size(); ++k) {
+    const double g = h * F.ind_inv_l[k];
+    const int32_t a = F.slot[F.ind_near[k]];
+    D[a] += g;
+    if (F.ind_far[k] >= 0) D[F.slot[F.ind_far[k]]] += g;
+    else bc[a] += g * F.ind_far_v[k];
+    G.ind_a.push_back(a);
+    G.ind_b.push_back(F.ind_far[k] >= 0 ? F.slot[F.ind_far[k]] : -1);
+    G.ind_branch.push_back((int32_t)k);
+    G.ind_sign.push_back((double)F.ind_sign[k]);
+    geq.push_back(g); alpha.push_back(1.0); vfar.push_back(F.ind_far_v[k]);
   }
-  if (ni) {
-    std::vector<int32_t> cnt(ns + 1, 0);
-    for (int k = 0; k < ni; ++k) { cnt[G.ind_a[k] + 1]++; if (G.ind_b[k] >= 0) cnt[G.ind_b[k] + 1]++; }
-    for (int64_t i = 0; i < ns; ++i) cnt[i + 1] += cnt[i];
-    std::vector<int32_t> inc(cnt[ns]), fillp(cnt.begin(), cnt.end() - 1);
-    for (int k = 0; k < ni; ++k) {
-      inc[fillp[G.ind_a[k]]++] = k + 1;
-      if (G.ind_b[k] >= 0) inc[fillp[G.ind_b[k]]++] = -(k + 1);
-    }
-    PG_TRY(upload(c, G.inc_off_d, cnt)); PG_TRY(upload(c, G.inc_ind_d, inc));
+  for (int64_t s = 0; s < ns; ++s) inv[s] = D[s] > 0.0 ? 1.0 / D[s] : 0.0;
+  const size_t ne = F.col.size();
+  std::vector<double> w(ne), cap;
+  for (size_t e = 0; e < ne; ++e) w[e] = F.g[e] + h * F.inv_l[e] + (dc ? 0.0 : F.cc[e] / h);
+  if (F.has_coupling) {  // same size at DC (zeros: capacitors open), so the buffer stays put
+    cap.assign(ne, 0.0);
+    if (!dc)
+      for (size_t e = 0; e < ne; ++e) cap[e] = F.cc[e] / h;
+  }
+  PG_TRY(upload(c, G.D64, D)); PG_TRY(upload(c, G.ch64, ch)); PG_TRY(upload(c, G.bconst64, bc));
+  PG_TRY(upload(c, G.sl_off_d, F.soff)); PG_TRY(upload(c, G.sl_col_d, F.col)); PG_TRY(upload(c, G.sl_w64_d, w));
+  PG_TRY(upload(c, G.slot_d, F.slot));
+  if (cap.empty()) dfree(G.sl_cap_d); else PG_TRY(upload(c, G.sl_cap_d, cap));
+  const bool f32 = fp32_mode(c);
+  if (f32) {
+    std::vector<float> wf(ne), qf(ns);
+    for (size_t e = 0; e < ne; ++e) wf[e] = (float)w[e];
+    for (int64_t i = 0; i < ns; ++i) qf[i] = (float)inv[i];
+    PG_TRY(upload(c, G.sl_ws_d, wf)); PG_TRY(upload(c, G.invDs, qf));
   } else {
-    dfree(G.inc_off_d); dfree(G.inc_ind_d);
+    dfree(G.sl_ws_d);
+    PG_TRY(upload(c, G.invDs, inv));
   }
+  PG_TRY(alloc_sweep_bufs(c, G, f32));
+  PG_TRY(upload_inductors(c, G, geq, alpha, &vfar));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  return PG_OK;
+}
+
+pg_status sync_desc(pg_ctx* c, int gi);
+
+pg_status build_grid(pg_ctx* c, int gi) {
+  PG_TRY(c->grids[gi].kind ? build_graph_grid(c, gi) : build_mesh_grid(c, gi));
+  return sync_desc(c, gi);
+}
+
+// The device descriptor of a grid (pointers to its current buffers).
+GridDesc make_desc(pg_ctx* c, GridHost& H) {
+  GridDesc D;
+  std::memset(&D, 0, sizeof D);
+  D.kind = H.kind;
+  D.nx = H.nx; D.ny = H.ny; D.nl = H.nl; D.S = H.S; D.X = H.X; D.item0 = H.item0; D.nstore = H.nstore;
+  D.gE64 = (const double*)H.gE64.p; D.gN64 = (const double*)H.gN64.p; D.gU64 = (const double*)H.gU64.p;
+  D.D64 = (const double*)H.D64.p; D.ch64 = (const double*)H.ch64.p; D.bconst64 = (const double*)H.bconst64.p;
+  if (fp32_mode(c)) { D.gEs = H.gEs.p; D.gNs = H.gNs.p; D.gUs = H.gUs.p; }
+  else { D.gEs = H.gE64.p; D.gNs = H.gN64.p; D.gUs = H.gU64.p; }
+  D.invDs = H.invDs.p;
+  D.v[0] = (double*)H.v0.p; D.v[1] = (double*)H.v1.p; D.b = (double*)H.b.p;
+  D.r = H.r.p; D.d[0] = H.d0.p; D.d[1] = H.d1.p;
+  D.n_ind = (int32_t)H.ind_a.size();
+  D.ind_a = (const int32_t*)H.ind_a_d.p; D.ind_b = (const int32_t*)H.ind_b_d.p;
+  D.ind_geq = (const double*)H.ind_geq_d.p; D.ind_alpha = (const double*)H.ind_alpha_d.p;
+  D.ind_i = (double*)H.ind_i_d.p;
+  D.inc_off = (const int32_t*)H.inc_off_d.p; D.inc_ind = (const int32_t*)H.inc_ind_d.p;
+  D.ind_vfar = (const double*)H.ind_vfar_d.p;
+  D.vdd = H.vdd;
+  if (H.kind) {
+    D.sl_off = (const int32_t*)H.sl_off_d.p; D.sl_col = (const int32_t*)H.sl_col_d.p;
+    D.sl_w64 = (const double*)H.sl_w64_d.p;
+    D.sl_ws = fp32_mode(c) ? H.sl_ws_d.p : H.sl_w64_d.p;
+    D.sl_cap = (const double*)H.sl_cap_d.p;
+    // invD, w (the column indices count as half a word in FP64 residuals)
+    H.coef_words = H.nstore + (3 * H.form.nnz) / 2;
+  } else {
+    H.coef_words = 3 * H.n + (int64_t)H.nx * H.ny * (H.nl - 1);
+  }
+  D.coef_words = H.coef_words;
+  return D;
+}
+
+// After a rebuild outside prepare (the DC matrix and back), re-upload the grid's descriptor
+// if any of its buffers moved, so no launch reads through a stale pointer.
+pg_status sync_desc(pg_ctx* c, int gi) {
+  if (c->dirty || gi >= (int)c->desc_host.size() || !c->grid_desc.p) return PG_OK;
+  const GridDesc D = make_desc(c, c->grids[gi]);
+  if (std::memcmp(&D, &c->desc_host[gi], sizeof D) == 0) return PG_OK;
+  c->desc_host[gi] = D;
+  HIP_TRY(c, hipMemcpyAsync((GridDesc*)c->grid_desc.p + gi, &c->desc_host[gi], sizeof D, hipMemcpyHostToDevice,
+                            c->stream));
   HIP_TRY(c, hipStreamSynchronize(c->stream));
   return PG_OK;
 }
 
 pg_status prepare(pg_ctx* c) {
   if (c->grids.empty()) return set_err(c, PG_ERR_STATE, "no grid uploaded");
+  for (int g = 0; g < (int)c->grids.size(); ++g)
+    if (c->grids[g].kind && c->opt.ordering != PG_ORDER_RED_BLACK)
+      return set_err(c, PG_ERR_UNSUPPORTED, "grid %d: general netlists are swept in colour order; the Jacobi "
+                     "ordering is built for meshes only", g);
   if (!c->dirty) return PG_OK;
   drop_graphs(c);
   const int G = (int)c->grids.size();
@@ -397,22 +548,7 @@ pg_status prepare(pg_ctx* c) {
   std::vector<long long> nodes;
   for (int g = 0; g < G; ++g) {
     GridHost& H = c->grids[g];
-    GridDesc& D = desc[g];
-    std::memset(&D, 0, sizeof D);
-    D.nx = H.nx; D.ny = H.ny; D.nl = H.nl; D.S = H.S; D.X = H.X; D.item0 = H.item0; D.nstore = H.nstore;
-    D.gE64 = (const double*)H.gE64.p; D.gN64 = (const double*)H.gN64.p; D.gU64 = (const double*)H.gU64.p;
-    D.D64 = (const double*)H.D64.p; D.ch64 = (const double*)H.ch64.p; D.bconst64 = (const double*)H.bconst64.p;
-    if (fp32_mode(c)) { D.gEs = H.gEs.p; D.gNs = H.gNs.p; D.gUs = H.gUs.p; }
-    else { D.gEs = H.gE64.p; D.gNs = H.gN64.p; D.gUs = H.gU64.p; }
-    D.invDs = H.invDs.p;
-    D.v[0] = (double*)H.v0.p; D.v[1] = (double*)H.v1.p; D.b = (double*)H.b.p;
-    D.r = H.r.p; D.d[0] = H.d0.p; D.d[1] = H.d1.p;
-    D.n_ind = (int32_t)H.ind_a.size();
-    D.ind_a = (const int32_t*)H.ind_a_d.p; D.ind_b = (const int32_t*)H.ind_b_d.p;
-    D.ind_geq = (const double*)H.ind_geq_d.p; D.ind_alpha = (const double*)H.ind_alpha_d.p;
-    D.ind_i = (double*)H.ind_i_d.p;
-    D.inc_off = (const int32_t*)H.inc_off_d.p; D.inc_ind = (const int32_t*)H.inc_ind_d.p;
-    D.vdd = H.vdd;
+    desc[g] = make_desc(c, H);
     for (int sc = 0; sc < H.S; ++sc) nodes.push_back((long long)H.n);
   }
   PG_TRY(upload(c, c->grid_desc, desc));
@@ -438,7 +574,7 @@ pg_status prepare(pg_ctx* c) {
   for (int nl = 1; nl <= 4; ++nl) {
     for (int g = 0; g < G; ++g) {
       const GridHost& H = c->grids[g];
-      if (H.nl != nl) continue;
+      if (H.nl != nl || H.kind) continue;
       for (int sc = 0; sc < H.S; ++sc) {
         c->item_tile_off[H.item0 + sc] = (int)tiles.size();
         for (int y0 = 0; y0 < H.ny; y0 += TY)
@@ -451,7 +587,7 @@ pg_status prepare(pg_ctx* c) {
       int64_t nodes_g = 0, mesh_g = 0;
       for (int g = 0; g < G; ++g) {
         const GridHost& H = c->grids[g];
-        if (H.nl != nl || (H.S > 1) != (multi == 1)) continue;
+        if (H.nl != nl || H.kind || (H.S > 1) != (multi == 1)) continue;
         nodes_g += H.n * H.S;
         mesh_g += H.n;
         for (int s0 = 0; s0 < H.S; s0 += SB) {
@@ -468,7 +604,44 @@ pg_status prepare(pg_ctx* c) {
   c->all_nodes = 0;
   c->all_coef = 0;
   for (auto& grp : c->tile_groups) c->all_nodes += grp.nodes;
-  for (auto& H : c->grids) c->all_coef += 3 * H.n + (int64_t)H.nx * H.ny * (H.nl - 1);
+  for (auto& H : c->grids) {
+    c->all_coef += H.coef_words;
+    if (H.kind) c->all_nodes += H.n * H.S;
+  }
+  // general-graph chunks: every slot of every scenario (right-hand side, residual), and the
+  // sweep chunks colour by colour
+  std::vector<GraphChunk> gall, gsweep;
+  c->gcolor.clear();
+  c->item_gchunk_off.assign(n_items(c), 0);
+  c->item_gchunk_cnt.assign(n_items(c), 0);
+  int maxc = 0;
+  for (int g = 0; g < G; ++g) {
+    const GridHost& H = c->grids[g];
+    if (!H.kind) continue;
+    maxc = std::max(maxc, H.form.ncolors);
+    for (int sc = 0; sc < H.S; ++sc) {
+      c->item_gchunk_off[H.item0 + sc] = (int)gall.size();
+      for (int64_t s0 = 0; s0 < H.nstore; s0 += kChunk)
+        gall.push_back(GraphChunk{g, H.item0 + sc, sc, (int32_t)s0, (int32_t)std::min<int64_t>(kChunk, H.nstore - s0), 0});
+      c->item_gchunk_cnt[H.item0 + sc] = (int)gall.size() - c->item_gchunk_off[H.item0 + sc];
+    }
+  }
+  for (int k = 0; k < maxc; ++k) {
+    const int start = (int)gsweep.size();
+    for (int g = 0; g < G; ++g) {
+      const GridHost& H = c->grids[g];
+      if (!H.kind || H.form.ncolors <= k) continue;
+      const int64_t a = H.form.cstart[k], b = H.form.cstart[k + 1];
+      for (int sc = 0; sc < H.S; ++sc)
+        for (int64_t s0 = a; s0 < b; s0 += kChunk)
+          gsweep.push_back(GraphChunk{g, H.item0 + sc, sc, (int32_t)s0, (int32_t)std::min<int64_t>(kChunk, b - s0),
+                                      (int32_t)a});
+    }
+    c->gcolor.emplace_back(start, (int)gsweep.size() - start);
+  }
+  c->n_gchunks_all = (int)gall.size();
+  PG_TRY(upload(c, c->g_chunks_all, gall));
+  PG_TRY(upload(c, c->g_chunks_sweep, gsweep));
   PG_TRY(upload(c, c->tiles_sweep, sweep));
   PG_TRY(upload(c, c->tiles_all, tiles));
   // sources: first those that are non-zero outside their breakpoints ("always"), then the
@@ -583,6 +756,19 @@ pg_status check_gs(pg_ctx* c, int grid, int scen) {
   return PG_OK;
 }
 
+// Entry points built for layered meshes only.
+pg_status mesh_only(pg_ctx* c, int grid, const char* what) {
+  if (c->grids[grid].kind)
+    return set_err(c, PG_ERR_UNSUPPORTED, "grid %d is a general netlist; %s is built for layered meshes", grid, what);
+  return PG_OK;
+}
+
+// Inductive branches reported by pg_read_inductor_currents.
+int64_t n_branches(const GridHost& H) {
+  if (H.kind) return (int64_t)H.form.ind_near.size();
+  return (int64_t)H.via_node.size() + (int64_t)H.pad_node.size();
+}
+
 // ---- one backward-Euler step -----------------------------------------------------------
 // Profiled as one block: the work is charged once the active items are known (cycle_loop).
 // Reserve the next decision: returns its tag; its flag slot is tag % kFlagSlots.  The device
@@ -594,10 +780,15 @@ int next_tag(pg_ctx* c) { return (int)(c->flag_seq_host++ & kTagMask); }
 pg_status launch_resid_all(pg_ctx* c, int has_d, int din, double tol = 0.0, int* tag = nullptr) {
   const Tile* T = (const Tile*)c->tiles_sweep.p;
   ProfScope ps(c, 1, c->begin_nodes, c->resid_bytes(c->begin_nodes, c->begin_coef, has_d != 0),
-               (int)c->tile_groups.size() + (tag ? 1 : 0));
+               (int)c->tile_groups.size() + (c->n_gchunks_all ? 1 : 0) + (tag ? 1 : 0));
   for (auto& grp : c->tile_groups) {
     hipError_t e = launch_resid(fp32_mode(c), grp.multi, grp.nl, c->tile_rows, T + grp.off, grp.count,
                                 (const GridDesc*)c->grid_desc.p, c->ctl, has_d, din, c->stream);
+    if (e != hipSuccess) return set_err(c, PG_ERR_DEVICE, "residual launch: %s", hipGetErrorString(e));
+  }
+  if (c->n_gchunks_all) {
+    hipError_t e = launch_graph_resid(fp32_mode(c), (const GraphChunk*)c->g_chunks_all.p, c->n_gchunks_all,
+                                      (const GridDesc*)c->grid_desc.p, c->ctl, has_d, c->stream);
     if (e != hipSuccess) return set_err(c, PG_ERR_DEVICE, "residual launch: %s", hipGetErrorString(e));
   }
   if (!tag) return PG_OK;
@@ -616,9 +807,15 @@ int sweeps_per_launch(const pg_ctx* c) {
 }
 
 // Kernel launches per tile group in a cycle of nchk sweeps; the cycle's result is in d[launches & 1].
+// (General graphs sweep in place in d[0], one launch per colour.)
 int cycle_launches(const pg_ctx* c, int nchk) {
   const int spl = sweeps_per_launch(c);
   return (nchk + spl - 1) / spl;
+}
+
+// All kernel launches of a cycle of nchk sweeps.
+int cycle_launches_all(const pg_ctx* c, int nchk) {
+  return cycle_launches(c, nchk) * (int)c->tile_groups.size() + nchk * (int)c->gcolor.size();
 }
 
 // The nchk sweeps of a cycle are timed as one block of back-to-back launches (one event pair
@@ -627,7 +824,7 @@ int cycle_launches(const pg_ctx* c, int nchk) {
 pg_status launch_sweeps(pg_ctx* c, int nchk) {
   const Tile* T = (const Tile*)c->tiles_sweep.p;
   const int spl = sweeps_per_launch(c);
-  ProfScope ps(c, 0, 0, 0.0, cycle_launches(c, nchk) * (int)c->tile_groups.size());
+  ProfScope ps(c, 0, 0, 0.0, cycle_launches_all(c, nchk));
   for (auto& grp : c->tile_groups) {
     for (int s = 0, j = 0; s < nchk; ++j) {
       const int zero_in = s == 0 ? 1 : 0;
@@ -644,6 +841,14 @@ pg_status launch_sweeps(pg_ctx* c, int nchk) {
       if (e != hipSuccess) return set_err(c, PG_ERR_DEVICE, "sweep launch: %s", hipGetErrorString(e));
     }
   }
+  // general graphs: one launch per colour and sweep, colours in order
+  const GraphChunk* GC = (const GraphChunk*)c->g_chunks_sweep.p;
+  for (int s = 0; s < nchk && !c->gcolor.empty(); ++s)
+    for (auto& cr : c->gcolor) {
+      hipError_t e = launch_graph_sweep(fp32_mode(c), GC + cr.first, cr.second, (const GridDesc*)c->grid_desc.p,
+                                        c->ctl, s == 0 ? 1 : 0, c->opt.omega, c->stream);
+      if (e != hipSuccess) return set_err(c, PG_ERR_DEVICE, "sweep launch: %s", hipGetErrorString(e));
+    }
   return PG_OK;
 }
 
@@ -681,7 +886,7 @@ pg_status begin_step(pg_ctx* c, int only_item, bool begun = false, int64_t dev_s
     for (auto& H : c->grids)
       if (only_item >= H.item0 && only_item < H.item0 + H.S) {
         c->begin_nodes = H.n;
-        c->begin_coef = 3 * H.n + (int64_t)H.nx * H.ny * (H.nl - 1);
+        c->begin_coef = H.coef_words;
       }
   }
   Ctl k = c->ctl;
@@ -695,8 +900,12 @@ pg_status begin_step(pg_ctx* c, int only_item, bool begun = false, int64_t dev_s
     const Tile* T = (const Tile*)c->tiles_all.p;
     int off = 0, cnt = c->ntiles_all;
     if (only_item >= 0) { off = c->item_tile_off[only_item]; cnt = c->item_tile_cnt[only_item]; }
-    ProfScope ps(c, 2, 0);
+    const GraphChunk* GC = (const GraphChunk*)c->g_chunks_all.p;
+    int goff = 0, gcnt = c->n_gchunks_all;
+    if (only_item >= 0) { goff = c->item_gchunk_off[only_item]; gcnt = c->item_gchunk_cnt[only_item]; }
+    ProfScope ps(c, 2, 0, 0.0, (cnt > 0 ? 1 : 0) + (gcnt > 0 ? 1 : 0));
     e = launch_rhs(T + off, cnt, c->tile_rows, (const GridDesc*)c->grid_desc.p, k, c->stream);
+    if (e == hipSuccess) e = launch_graph_rhs(GC + goff, gcnt, (const GridDesc*)c->grid_desc.p, k, c->stream);
     if (e != hipSuccess) return set_err(c, PG_ERR_DEVICE, "rhs launch: %s", hipGetErrorString(e));
   }
   if (dev_step < 0 || sources_may_act(c, dev_step)) {
@@ -746,11 +955,11 @@ pg_status issue_cycle(pg_ctx* c, double tol, bool graphs, int* tag) {
   const int nchk = c->opt.check_every;
   if (graphs) {
     {
-      ProfScope ps(c, 0, 0, 0.0, cycle_launches(c, nchk) * (int)c->tile_groups.size());
+      ProfScope ps(c, 0, 0, 0.0, cycle_launches_all(c, nchk));
       HIP_TRY(c, hipGraphLaunch(c->g_sweeps, c->stream));
     }
     {
-      ProfScope ps(c, 1, 0, 0.0, (int)c->tile_groups.size());  // residual pass and its decision
+      ProfScope ps(c, 1, 0, 0.0, (int)c->tile_groups.size() + (c->n_gchunks_all ? 1 : 0));  // residual pass and its decision
       HIP_TRY(c, hipGraphLaunch(c->g_check, c->stream));
     }
     *tag = next_tag(c);
@@ -1105,6 +1314,39 @@ pg_status fill_v(pg_ctx* c, GridHost& H, const double* v, int scen, int32_t vidx
 
 }  // namespace
 
+namespace pgrid {
+
+pg_status upload_graph(pg_ctx* c, GraphForm& form, double vdd, int32_t n_scen, int32_t* grid_id) {
+  if (n_scen < 1) return set_err(c, PG_ERR_INVALID_ARG, "n_scen must be >= 1");
+  HIP_TRY(c, hipSetDevice(c->device));
+  c->grids.emplace_back();
+  GridHost& H = c->grids.back();
+  H.kind = 1;
+  H.nx = form.n; H.ny = 1; H.nl = 1; H.S = n_scen; H.item0 = n_items(c) - n_scen;
+  H.P = form.n; H.n = form.n; H.vdd = vdd;
+  H.X = (int32_t)form.nslots;
+  H.nstore = form.nslots;
+  H.form = std::move(form);
+  H.src.assign(n_scen, Src{});
+  for (auto& s : H.src) s.off = {0};
+  const size_t ns = (size_t)H.nstore * H.S;
+  pg_status ps;
+  if ((ps = dalloc(c, H.v0, ns * sizeof(double))) != PG_OK || (ps = dalloc(c, H.v1, ns * sizeof(double))) != PG_OK ||
+      (ps = dalloc(c, H.b, ns * sizeof(double))) != PG_OK) {
+    c->grids.pop_back();
+    return ps;
+  }
+  std::vector<double> vinit(ns, H.vdd);
+  HIP_TRY(c, hipMemcpy(H.v0.p, vinit.data(), ns * sizeof(double), hipMemcpyHostToDevice));
+  HIP_TRY(c, hipMemcpy(H.v1.p, vinit.data(), ns * sizeof(double), hipMemcpyHostToDevice));
+  PG_TRY(alloc_ctl(c));
+  c->dirty = true;
+  if (grid_id) *grid_id = (int32_t)c->grids.size() - 1;
+  return PG_OK;
+}
+
+}  // namespace pgrid
+
 extern "C" {
 
 pg_status pg_create(pg_ctx** out, int32_t device, void* stream) {
@@ -1268,6 +1510,19 @@ pg_status pg_upload_mesh(pg_ctx* c, const pg_mesh* m, int32_t n_scen, int32_t* g
   return PG_OK;
 }
 
+pg_status pg_graph_info(const pg_ctx* c, int32_t grid, int32_t* n_nodes, int32_t* n_colors, int64_t* n_slots,
+                        int64_t* nnz, int32_t* n_inductors) {
+  if (!c || grid < 0 || grid >= (int)c->grids.size()) return PG_ERR_INVALID_ARG;
+  const GridHost& H = c->grids[grid];
+  if (!H.kind) return PG_ERR_INVALID_ARG;
+  if (n_nodes) *n_nodes = (int32_t)H.n;
+  if (n_colors) *n_colors = H.form.ncolors;
+  if (n_slots) *n_slots = H.form.nslots;
+  if (nnz) *nnz = H.form.nnz;
+  if (n_inductors) *n_inductors = (int32_t)H.form.ind_near.size();
+  return PG_OK;
+}
+
 pg_status pg_set_pwl(pg_ctx* c, int32_t grid, int32_t scen, int32_t n_src, const int32_t* node,
                      const int32_t* offsets, const double* t, const double* i) {
   PG_TRY(check_gs(c, grid, scen));
@@ -1329,7 +1584,7 @@ pg_status pg_set_state(pg_ctx* c, int32_t grid, int32_t scen, const double* v, c
   const int ni = (int)H.ind_a.size();
   if (ni) {
     std::vector<double> buf(ni);
-    for (int k = 0; k < ni; ++k) buf[k] = i_l ? i_l[H.ind_branch[k]] : 0.0;
+    for (int k = 0; k < ni; ++k) buf[k] = i_l ? H.ind_sign[k] * i_l[H.ind_branch[k]] : 0.0;
     HIP_TRY(c, hipMemcpy((double*)H.ind_i_d.p + (size_t)scen * ni, buf.data(), ni * sizeof(double),
                          hipMemcpyHostToDevice));
   }
@@ -1353,6 +1608,7 @@ namespace {
 // With capacitors open, every connected part of a grid's conductance graph must reach a pad,
 // or the DC matrix is singular.
 bool dc_anchored(const GridHost& G) {
+  if (G.kind) return G.form.dc_anchored;
   const int64_t n = G.n, plane = (int64_t)G.nx * G.ny;
   std::vector<int64_t> parent(n);
   for (int64_t i = 0; i < n; ++i) parent[i] = i;
@@ -1456,6 +1712,7 @@ pg_status activate_only(pg_ctx* c, int item) {
 
 pg_status pg_estimate_omega(pg_ctx* c, int32_t grid, int32_t dc, int32_t iters, double* rho, double* omega_opt) {
   PG_TRY(check_gs(c, grid, 0));
+  PG_TRY(mesh_only(c, grid, "pg_estimate_omega"));
   if (iters < 32 || (dc != 0 && dc != 1) || !rho || !omega_opt)
     return set_err(c, PG_ERR_INVALID_ARG, "need iters >= 32, dc in {0, 1} and output pointers");
   HIP_TRY(c, hipSetDevice(c->device));
@@ -1506,6 +1763,7 @@ pg_status pg_estimate_omega(pg_ctx* c, int32_t grid, int32_t dc, int32_t iters, 
 
 pg_status pg_error_bound_factor(pg_ctx* c, int32_t grid, double rel_tol, double* kappa) {
   PG_TRY(check_gs(c, grid, 0));
+  PG_TRY(mesh_only(c, grid, "pg_error_bound_factor"));
   if (!(std::isfinite(rel_tol) && rel_tol > 0) || !kappa)
     return set_err(c, PG_ERR_INVALID_ARG, "need rel_tol > 0 and an output pointer");
   HIP_TRY(c, hipSetDevice(c->device));
@@ -1607,7 +1865,7 @@ pg_status pg_read_voltages(pg_ctx* c, int32_t grid, int32_t scen, double* out, i
   HIP_TRY(c, hipSetDevice(c->device));
   const int32_t vi = cur_vidx(c, H.item0 + scen);
   const double* src = (const double*)(vi ? H.v1.p : H.v0.p) + (size_t)scen * H.nstore;
-  if (H.X == H.nx) {
+  if (!H.kind && H.X == H.nx) {
     HIP_TRY(c, hipMemcpy(out, src, H.n * sizeof(double), hipMemcpyDeviceToHost));
     return PG_OK;
   }
@@ -1621,11 +1879,17 @@ pg_status pg_read_voltages_dev(pg_ctx* c, int32_t grid, int32_t scen, double* de
   PG_TRY(check_gs(c, grid, scen));
   GridHost& H = c->grids[grid];
   if (!dev_out || n < H.n) return set_err(c, PG_ERR_INVALID_ARG, "output buffer too small");
-  if (H.X != H.nx)
+  if (!H.kind && H.X != H.nx)
     return set_err(c, PG_ERR_UNSUPPORTED, "device read needs nx to be a multiple of %d", kPitchAlign);
   HIP_TRY(c, hipSetDevice(c->device));
+  PG_TRY(prepare(c));
   const int32_t vi = cur_vidx(c, H.item0 + scen);
   const double* src = (const double*)(vi ? H.v1.p : H.v0.p) + (size_t)scen * H.nstore;
+  if (H.kind) {
+    hipError_t e = launch_gather(src, (const int32_t*)H.slot_d.p, dev_out, H.n, c->stream);
+    if (e != hipSuccess) return set_err(c, PG_ERR_DEVICE, "gather launch: %s", hipGetErrorString(e));
+    return PG_OK;
+  }
   HIP_TRY(c, hipMemcpyAsync(dev_out, src, H.n * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
   return PG_OK;
 }
@@ -1633,8 +1897,8 @@ pg_status pg_read_voltages_dev(pg_ctx* c, int32_t grid, int32_t scen, double* de
 pg_status pg_read_inductor_currents(pg_ctx* c, int32_t grid, int32_t scen, double* out, int64_t n) {
   PG_TRY(check_gs(c, grid, scen));
   GridHost& H = c->grids[grid];
-  const int64_t nb = (int64_t)H.via_node.size() + (int64_t)H.pad_node.size();
-  if (!out || n < nb) return set_err(c, PG_ERR_INVALID_ARG, "output buffer too small (need %lld)", (long long)nb);
+  const int64_t nb = n_branches(H);
+  if ((!out && nb > 0) || n < nb) return set_err(c, PG_ERR_INVALID_ARG, "output buffer too small (need %lld)", (long long)nb);
   HIP_TRY(c, hipSetDevice(c->device));
   PG_TRY(prepare(c));
   std::fill(out, out + nb, 0.0);
@@ -1644,7 +1908,7 @@ pg_status pg_read_inductor_currents(pg_ctx* c, int32_t grid, int32_t scen, doubl
   HIP_TRY(c, hipStreamSynchronize(c->stream));
   HIP_TRY(c, hipMemcpy(buf.data(), (const double*)H.ind_i_d.p + (size_t)scen * ni, ni * sizeof(double),
                        hipMemcpyDeviceToHost));
-  for (int k = 0; k < ni; ++k) out[H.ind_branch[k]] = buf[k];
+  for (int k = 0; k < ni; ++k) out[H.ind_branch[k]] = H.ind_sign[k] * buf[k];
   return PG_OK;
 }
 
@@ -1699,6 +1963,7 @@ pg_status pg_read_kernel_times(pg_ctx* c, pg_kernel_times* out) {
 pg_status pg_loss_forward(pg_ctx* c, int32_t grid, int32_t scen, int32_t nsteps, int32_t ckpt_every,
                           double margin, double* J) {
   PG_TRY(check_gs(c, grid, scen));
+  PG_TRY(mesh_only(c, grid, "the loss adjoint"));
   if (nsteps < 1 || ckpt_every < 1 || !std::isfinite(margin))
     return set_err(c, PG_ERR_INVALID_ARG, "need nsteps >= 1, ckpt_every >= 1 and a finite margin");
   HIP_TRY(c, hipSetDevice(c->device));
@@ -1765,6 +2030,7 @@ pg_status pg_loss_backward_dev(pg_ctx* c, double tol_adj, double* dJ_dC, double*
 
 pg_status pg_update_mesh_values(pg_ctx* c, int32_t grid, const double* gE, const double* gN, const double* C) {
   PG_TRY(check_gs(c, grid, 0));
+  PG_TRY(mesh_only(c, grid, "pg_update_mesh_values"));
   GridHost& H = c->grids[grid];
   const size_t nE = (size_t)H.nl * H.ny * (H.nx - 1), nN = (size_t)H.nl * (H.ny - 1) * H.nx, nC = (size_t)H.n;
   for (size_t k = 0; gE && k < nE; ++k)
@@ -1796,7 +2062,7 @@ pg_status take_snapshot(pg_ctx* c, Snapshot& sn) {
   sn.il.clear();
   for (int g = 0; g < (int)c->grids.size(); ++g) {
     const GridHost& H = c->grids[g];
-    const int64_t nb = (int64_t)H.via_node.size() + (int64_t)H.pad_node.size();
+    const int64_t nb = n_branches(H);
     for (int s = 0; s < H.S; ++s) {
       sn.v.emplace_back(H.n);
       sn.il.emplace_back(std::max<int64_t>(nb, 1));
@@ -1824,7 +2090,10 @@ std::string tune_key(pg_ctx* c) {
   char buf[256];
   std::string key;
   for (auto& H : c->grids) {
-    std::snprintf(buf, sizeof buf, "%dx%dx%d*%d;", H.nx, H.ny, H.nl, H.S);
+    if (H.kind)
+      std::snprintf(buf, sizeof buf, "graph%lldn%lldc%d*%d;", (long long)H.n, (long long)H.form.nnz, H.form.ncolors, H.S);
+    else
+      std::snprintf(buf, sizeof buf, "%dx%dx%d*%d;", H.nx, H.ny, H.nl, H.S);
     key += buf;
   }
   std::snprintf(buf, sizeof buf, "prec%d;h%.6g;tol%.3g;%s", c->opt.precision, c->opt.h, c->opt.tol, arch.c_str());

@@ -92,6 +92,10 @@ EXPORTS = {
                                      C.POINTER(C.c_double), C.POINTER(C.c_double), C.POINTER(C.c_int32),
                                      C.POINTER(C.c_double), C.POINTER(C.c_double), C.POINTER(C.c_double),
                                      C.c_char_p, C.c_size_t]),
+    "pg_netlist_coloring": (C.c_int, [C.c_int32, C.c_int32, C.POINTER(C.c_double), C.c_int32,
+                                      C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.POINTER(C.c_uint8),
+                                      C.POINTER(C.c_double), C.POINTER(C.c_int32), C.POINTER(C.c_int32),
+                                      C.POINTER(C.c_int32), C.POINTER(C.c_int64), C.c_char_p, C.c_size_t]),
     "pg_create": (C.c_int, [C.POINTER(C.c_void_p), C.c_int32, C.c_void_p]),
     "pg_destroy": (None, [C.c_void_p]),
     "pg_last_error": (C.c_char_p, [C.c_void_p]),
@@ -119,6 +123,8 @@ EXPORTS = {
     "pg_set_time": (C.c_int, [C.c_void_p, C.c_int64]),
     "pg_num_grids": (C.c_int, [C.c_void_p, C.POINTER(C.c_int32)]),
     "pg_grid_info": (C.c_int, [C.c_void_p, C.c_int32] + [C.POINTER(C.c_int32)] * 6),
+    "pg_graph_info": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_int32),
+                                C.POINTER(C.c_int64), C.POINTER(C.c_int64), C.POINTER(C.c_int32)]),
     "pg_autotune": (C.c_int, [C.c_void_p, C.c_int32, C.c_char_p, C.POINTER(Options)]),
     "pg_read_voltages": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.POINTER(C.c_double), C.c_int64]),
     "pg_read_voltages_dev": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_void_p, C.c_int64]),
@@ -244,7 +250,31 @@ class NetlistMesh:
 
 def _netlist_args(n, p, source_v, frm, to, kind, value, dims):
     return (int(n), int(p), _f64(np.asarray(source_v, float).reshape(-1)), _i32(frm), _i32(to), _kinds(kind),
-            _f64(value), _i32(np.asarray(dims).reshape(3)))
+            _f64(value), None if dims is None else _i32(np.asarray(dims).reshape(3)))
+
+
+@dataclass
+class GraphShape:
+    """Sizes of a general-netlist grid (pg_graph_info)."""
+    n: int
+    n_colors: int
+    n_slots: int
+    nnz: int
+    n_inductors: int
+
+
+def netlist_coloring(n, p, source_v, frm, to, kind, value):
+    """Host-only: (color[n], slot[n], n_colors, n_slots) of a general netlist (pg_netlist_coloring)."""
+    n, p, sv, frm, to, k, value, _ = _netlist_args(n, p, source_v, frm, to, kind, value, None)
+    color, slot = np.zeros(n, np.int32), np.zeros(n, np.int32)
+    nc, ns = C.c_int32(), C.c_int64()
+    buf = _msgbuf()
+    st = lib().pg_netlist_coloring(n, p, _dp(sv), int(frm.size), _ip(frm), _ip(to),
+                                   k.ctypes.data_as(C.POINTER(C.c_uint8)), _dp(value), _ip(color), _ip(slot),
+                                   C.byref(nc), C.byref(ns), buf, 512)
+    if st != 0:
+        raise PgError(st, buf.value.decode())
+    return color, slot, nc.value, ns.value
 
 
 def netlist_to_mesh(n, p, source_v, frm, to, kind, value, dims):
@@ -348,16 +378,34 @@ class Context:
         self.meshes.append(mesh)
         return gid.value
 
-    def upload_netlist(self, n, p, source_v, frm, to, kind, value, dims, n_scen: int = 1) -> int:
-        """Upload a netlist through its layered-mesh form (pg_upload_netlist)."""
-        mesh = netlist_to_mesh(n, p, source_v, frm, to, kind, value, dims)  # shapes for later reads
+    def upload_netlist(self, n, p, source_v, frm, to, kind, value, dims=None, n_scen: int = 1) -> int:
+        """Upload a netlist (pg_upload_netlist): through its layered-mesh form when ``dims`` =
+        (nx, ny, nl) is given, else as a general graph swept in colour order."""
+        mesh = None if dims is None else netlist_to_mesh(n, p, source_v, frm, to, kind, value, dims)
         n, p, sv, frm, to, k, value, dims = _netlist_args(n, p, source_v, frm, to, kind, value, dims)
         gid = C.c_int32()
         self._check(lib().pg_upload_netlist(self._h, n, p, _dp(sv), int(frm.size), _ip(frm), _ip(to),
-                                            k.ctypes.data_as(C.POINTER(C.c_uint8)), _dp(value), _ip(dims),
-                                            int(n_scen), C.byref(gid)))
-        self.meshes.append(mesh)
+                                            k.ctypes.data_as(C.POINTER(C.c_uint8)), _dp(value),
+                                            _ip(dims) if dims is not None else None, int(n_scen), C.byref(gid)))
+        self.meshes.append(mesh if mesh is not None else self.graph_info(gid.value))
         return gid.value
+
+    def graph_info(self, grid: int) -> GraphShape:
+        n, nc, ni = C.c_int32(), C.c_int32(), C.c_int32()
+        ns, nnz = C.c_int64(), C.c_int64()
+        self._check(lib().pg_graph_info(self._h, grid, C.byref(n), C.byref(nc), C.byref(ns), C.byref(nnz),
+                                        C.byref(ni)))
+        return GraphShape(n.value, nc.value, ns.value, nnz.value, ni.value)
+
+    def _n_nodes(self, grid: int) -> int:
+        m = self.meshes[grid]
+        return int(m.n) if isinstance(m, GraphShape) else int(m.nx) * int(m.ny) * int(m.nl)
+
+    def _n_branches(self, grid: int) -> int:
+        m = self.meshes[grid]
+        if isinstance(m, GraphShape):
+            return int(m.n_inductors)
+        return int(np.asarray(m.via_node).size + np.asarray(m.pad_node).size)
 
     def set_pulses(self, grid: int, scen: int, pulses):
         node, peak = _i32(pulses.node), _f64(pulses.peak)
@@ -398,8 +446,7 @@ class Context:
         self._check(lib().pg_step(self._h, int(nsteps)))
 
     def run_transient(self, nsteps: int, record_every: int = 1, grid: int = 0, scen: int = 0):
-        mesh = self.meshes[grid]
-        n = int(mesh.nx) * int(mesh.ny) * int(mesh.nl)
+        n = self._n_nodes(grid)
         out = np.empty((nsteps // record_every, n))
         self._check(lib().pg_run_transient(self._h, int(nsteps), int(record_every), grid, scen,
                                            _dp(out) if out.size else None))
@@ -427,8 +474,7 @@ class Context:
 
     # -- reads ---------------------------------------------------------------------------------
     def read_voltages(self, grid: int = 0, scen: int = 0) -> np.ndarray:
-        mesh = self.meshes[grid]
-        n = int(mesh.nx) * int(mesh.ny) * int(mesh.nl)
+        n = self._n_nodes(grid)
         out = np.empty(n)
         self._check(lib().pg_read_voltages(self._h, grid, scen, _dp(out), n))
         return out
@@ -439,8 +485,7 @@ class Context:
                                                int(tensor.numel())))
 
     def read_inductor_currents(self, grid: int = 0, scen: int = 0) -> np.ndarray:
-        mesh = self.meshes[grid]
-        nb = int(np.asarray(mesh.via_node).size + np.asarray(mesh.pad_node).size)
+        nb = self._n_branches(grid)
         out = np.zeros(max(nb, 1))
         self._check(lib().pg_read_inductor_currents(self._h, grid, scen, _dp(out), nb))
         return out[:nb]

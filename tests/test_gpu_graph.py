@@ -1,0 +1,177 @@
+"""GPU parity of the colour-ordered path for general netlists (through the C ABI) against the
+FP64 oracle, which assembles the same branch list (Sec. III, eqs. 9-11) and solves every step
+directly.
+
+Bar: max |v_gpu - v_oracle| <= 1e-6 V for every node and every step (and inductor currents
+within 1e-6 relative), at stopping tolerances tight enough for that bar.
+"""
+import numpy as np
+import pytest
+
+import paper_1409_7166_amd as pg
+from helpers import PARITY_V, compressed, say, torch_stream
+from oracle import BEStepper, Circuit, be_transient, dc_solve, mesh_to_circuit
+from oracle.sources import currents_at
+from workloads import Pulses, irregular_grid, mesh_netlist, small_multilayer
+
+pytestmark = pytest.mark.gpu
+
+H = 10e-12
+
+
+def _circuit(net):
+    return Circuit(net.n, net.source_v, net.frm.astype(np.int64), net.to.astype(np.int64), net.kind, net.value)
+
+
+def _ctx(**opts):
+    ctx = pg.Context(0, torch_stream())
+    base = dict(h=H, tol=1e-10, omega=1.5, check_every=8, precision=pg.PG_PREC_FP64)
+    base.update(opts)
+    ctx.set_options(**base)
+    return ctx
+
+
+def _upload(ctx, net, scen):
+    g = ctx.upload_netlist(net.n, net.p, net.source_v, net.frm, net.to, net.kind, net.value, None, len(scen))
+    for s, p in enumerate(scen):
+        ctx.set_pulses(g, s, p)
+    return g
+
+
+def _oracle(net, p, steps, h=H):
+    circ = _circuit(net)
+    nL = int(np.sum(net.kind == "L"))
+    return be_transient(circ, None, p, h, steps, v0=np.full(net.n, net.source_v[0]), il0=np.zeros(nL))
+
+
+@pytest.mark.parametrize("prec", [pg.PG_PREC_FP64, pg.PG_PREC_FP32_REFINE])
+def test_irregular_rc_two_scenarios_every_node_every_step(prec):
+    """Dropped segments, diagonal straps (4 colours), coupling capacitors, leaks to ground, two
+    supply voltages, shuffled node ids, two current scenarios."""
+    net, scen = irregular_grid(side=40, nl=2, seed=21, scenarios=2)
+    steps = 60
+    info = None
+    say(f"[gpu] graph rc n={net.n} prec={prec}")
+    with _ctx(precision=prec, tol=1e-11, omega=1.7) as ctx:
+        g = _upload(ctx, net, scen)
+        info = ctx.graph_info(g)
+        refs = [_oracle(net, p, steps)[0] for p in scen]
+        worst = 0.0
+        for k in range(steps):
+            ctx.step(1)
+            for s in range(2):
+                worst = max(worst, float(np.max(np.abs(ctx.read_voltages(g, s) - refs[s][k]))))
+        st = ctx.stats()
+    say(f"  colours={info.n_colors} slots={info.n_slots} nnz={info.nnz} sweeps={st['sweeps']} max_err={worst:.3e} V")
+    assert info.n_colors >= 3 and info.n == net.n
+    assert worst <= PARITY_V
+    assert np.max(np.abs(refs[0] - refs[1])) > 1e-4  # the scenarios differ
+    assert np.max(net.source_v[1] - refs[0]) > 1e-3  # the loads pull the grid down
+
+
+@pytest.mark.parametrize("prec", [pg.PG_PREC_FP64, pg.PG_PREC_FP32_REFINE])
+def test_irregular_rlc_voltages_and_inductor_currents(prec):
+    """Series R-L vias through internal nodes and pure-L pads (companion g = h/L, alpha = 1)."""
+    net, scen = irregular_grid(side=32, nl=3, seed=22, rlc=True)
+    p = compressed(scen[0], start=0.3, width=0.6, peak=2.0)
+    steps = 80
+    circ = _circuit(net)
+    stp = BEStepper(circ, H)
+    v, il = np.full(net.n, net.source_v[0]), np.zeros(int(np.sum(net.kind == "L")))
+    worst_v = worst_i = 0.0
+    say(f"[gpu] graph rlc n={net.n} L={il.size} prec={prec}")
+    with _ctx(precision=prec, tol=1e-12, omega=1.8, check_every=16, max_sweeps=50000) as ctx:
+        g = _upload(ctx, net, [p])
+        for k in range(1, steps + 1):
+            v, il = stp.step(v, il, currents_at(p, k * H))
+            ctx.step(1)
+            worst_v = max(worst_v, float(np.max(np.abs(ctx.read_voltages(g) - v))))
+            worst_i = max(worst_i, float(np.max(np.abs(ctx.read_inductor_currents(g) - il))))
+        st = ctx.stats()
+    say(f"  sweeps={st['sweeps']} max_err_v={worst_v:.3e} V max_err_i={worst_i:.3e} A (max |i| {np.max(np.abs(il)):.2e})")
+    assert worst_v <= PARITY_V
+    assert worst_i <= 1e-6 * max(1.0, float(np.max(np.abs(il))))
+    assert np.max(np.abs(il)) > 1e-5
+
+
+def test_mesh_and_its_branch_list_in_one_context():
+    """The same 3-layer mesh as a mesh grid (red-black tiles) and as a general netlist
+    (colour-ordered chunks) in one context: both match the oracle every step."""
+    w = small_multilayer(side=50, seed=23, nl=3, pad_every=16, steps=40)
+    mesh = w.meshes[0]
+    p = compressed(w.pulses[0][0], start=0.1, width=1.0)
+    net = mesh_netlist(mesh, p)
+    circ, info = mesh_to_circuit(mesh, p)
+    Vref, _ = be_transient(circ, info, p, w.h, 40)
+    say("[gpu] mesh + graph in one context")
+    with _ctx(h=w.h, precision=pg.PG_PREC_FP32_REFINE, tol=1e-11, omega=1.7) as ctx:
+        gm = ctx.upload_mesh(mesh, 1)
+        ctx.set_pulses(gm, 0, p)
+        gg = _upload(ctx, net, [p])
+        assert ctx.graph_info(gg).n_colors == 2
+        em = eg = 0.0
+        for k in range(40):
+            ctx.step(1)
+            em = max(em, float(np.max(np.abs(ctx.read_voltages(gm) - Vref[k, : mesh.n]))))
+            eg = max(eg, float(np.max(np.abs(ctx.read_voltages(gg) - Vref[k]))))
+    say(f"  mesh err={em:.3e} graph err={eg:.3e}")
+    assert em <= PARITY_V and eg <= PARITY_V
+
+
+def test_graph_replay_matches_plain_launches_and_device_read():
+    net, scen = irregular_grid(side=30, nl=2, seed=24)
+    steps = 40
+    Vref, _ = _oracle(net, scen[0], steps)
+    runs = []
+    for graphs in (0, 1):
+        with _ctx(tol=1e-11, omega=1.7, graphs=graphs) as ctx:
+            g = _upload(ctx, net, scen)
+            V = ctx.run_transient(steps, grid=g)
+            import torch
+            t = torch.empty(net.n, dtype=torch.float64, device="cuda")
+            ctx.read_voltages_dev(g, 0, t)
+            torch.cuda.synchronize()
+            assert np.array_equal(t.cpu().numpy(), ctx.read_voltages(g))
+        runs.append(V)
+        say(f"[gpu] graph replay graphs={graphs}: err={np.max(np.abs(V - Vref)):.3e}")
+        assert np.max(np.abs(V - Vref)) <= PARITY_V
+    assert np.array_equal(runs[0], runs[1])
+
+
+def test_graph_dc_operating_point_then_transient():
+    net, scen = irregular_grid(side=36, nl=2, seed=25)
+    p = compressed(scen[0], start=0.2, width=2.0, peak=3.0)
+    k0 = 15
+    circ = _circuit(net)
+    I0 = currents_at(p, k0 * H)
+    assert np.count_nonzero(I0) > 50
+    vdc, _ = dc_solve(circ, I0)
+    say(f"[gpu] graph dc point n={net.n}")
+    with _ctx(tol=1e-12, omega=1.6, max_sweeps=200000) as ctx:
+        g = _upload(ctx, net, [p])
+        ctx.dc_operating_point(k0, omega=1.95, tol=1e-12, max_sweeps=400000)
+        err = float(np.max(np.abs(ctx.read_voltages(g) - vdc)))
+        stp = BEStepper(circ, H)
+        v, il = vdc.copy(), np.zeros(0)
+        worst = 0.0
+        for j in range(1, 11):
+            v, il = stp.step(v, il, currents_at(p, (k0 + j) * H))
+            ctx.step(1)
+            worst = max(worst, float(np.max(np.abs(ctx.read_voltages(g) - v))))
+    say(f"  dc err={err:.3e}, transient err={worst:.3e}")
+    assert err <= PARITY_V and worst <= PARITY_V
+
+
+def test_graph_unsupported_calls_report_errors():
+    net, scen = irregular_grid(side=16, nl=2, seed=26, rlc=True)
+    with _ctx() as ctx:
+        g = _upload(ctx, net, scen)
+        for call in (lambda: ctx.estimate_omega(g), lambda: ctx.error_bound_factor(g),
+                     lambda: ctx.loss_forward(g, 0, 2, 1, 0.05), lambda: ctx.dc_operating_point(0)):
+            with pytest.raises(pg.PgError) as e:
+                call()
+            assert e.value.status == -8
+        ctx.set_options(ordering=pg.PG_ORDER_JACOBI)
+        with pytest.raises(pg.PgError) as e:
+            ctx.step(1)
+        assert e.value.status == -8
