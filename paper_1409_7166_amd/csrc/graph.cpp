@@ -8,6 +8,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <deque>
+#include <set>
 #include <utility>
 #include <vector>
 
@@ -27,9 +28,42 @@ pg_status gfail(pg_status st, char* msg, size_t len, const char* fmt, ...) {
   return st;
 }
 
+// DSATUR: repeatedly colour the uncoloured node whose neighbours already show the most distinct
+// colours (ties: smallest node id) with the smallest colour none of them holds.  Returns the
+// number of colours, or 0 if a node would need a colour beyond 63 (the caller then falls back).
+int dsatur(int32_t n, const std::vector<int64_t>& off, const std::vector<int32_t>& adj, std::vector<int32_t>& color) {
+  color.assign(n, -1);
+  std::vector<uint64_t> seen(n, 0);  // colours held by coloured neighbours
+  std::vector<int> sat(n, 0);
+  std::vector<std::set<int32_t>> bucket(1);
+  for (int32_t i = 0; i < n; ++i) bucket[0].insert(bucket[0].end(), i);
+  int top = 0, nc = 0;
+  for (int32_t done = 0; done < n; ++done) {
+    while (bucket[top].empty()) --top;
+    const int32_t u = *bucket[top].begin();
+    bucket[top].erase(bucket[top].begin());
+    if (~seen[u] == 0) return 0;
+    const int c = __builtin_ctzll(~seen[u]);
+    color[u] = c;
+    nc = std::max(nc, c + 1);
+    const uint64_t bit = 1ull << c;
+    for (int64_t k = off[u]; k < off[u + 1]; ++k) {
+      const int32_t w = adj[k];
+      if (color[w] >= 0 || (seen[w] & bit)) continue;
+      seen[w] |= bit;
+      bucket[sat[w]].erase(w);
+      ++sat[w];
+      if ((int)bucket.size() <= sat[w]) bucket.resize(sat[w] + 1);
+      bucket[sat[w]].insert(w);
+      top = std::max(top, sat[w]);
+    }
+  }
+  return nc;
+}
+
 // Two colours when the node graph is bipartite (breadth-first parity per connected part),
-// else the greedy colouring in node order (each node takes the smallest colour none of its
-// earlier neighbours holds).
+// else DSATUR (or, should that run past 64 colours, the greedy colouring in node order: each
+// node takes the smallest colour none of its earlier neighbours holds).
 int colour_nodes(int32_t n, const std::vector<int64_t>& off, const std::vector<int32_t>& adj,
                  std::vector<int32_t>& color) {
   color.assign(n, -1);
@@ -58,6 +92,35 @@ int colour_nodes(int32_t n, const std::vector<int64_t>& off, const std::vector<i
     int nc = 0;
     for (int32_t i = 0; i < n; ++i) nc = std::max(nc, color[i] + 1);
     return nc;
+  }
+  int nd = dsatur(n, off, adj, color);
+  if (nd > 0) {
+    // iterated greedy (Culberson): recolour greedily, taking the colour classes as blocks in
+    // reverse order (nodes in id order inside a class); this never adds a colour and often
+    // empties the last, smallest classes
+    std::vector<int32_t> order(n), mark;
+    for (int pass = 0; pass < 16 && nd > 2; ++pass) {
+      std::vector<int64_t> cnt(nd + 1, 0);
+      for (int32_t i = 0; i < n; ++i) cnt[nd - 1 - color[i] + 1]++;
+      for (int c = 0; c < nd; ++c) cnt[c + 1] += cnt[c];
+      for (int32_t i = 0; i < n; ++i) order[cnt[nd - 1 - color[i]]++] = i;
+      std::vector<int32_t> nc2(n, -1);
+      mark.assign(nd + 1, -1);
+      int used = 0;
+      for (int32_t u : order) {
+        for (int64_t k = off[u]; k < off[u + 1]; ++k)
+          if (nc2[adj[k]] >= 0) mark[nc2[adj[k]]] = u;
+        int cu = 0;
+        while (mark[cu] == u) ++cu;
+        nc2[u] = cu;
+        used = std::max(used, cu + 1);
+      }
+      const bool better = used < nd;
+      color.swap(nc2);
+      nd = used;
+      if (!better && pass >= 3) break;
+    }
+    return nd;
   }
   color.assign(n, -1);
   int nc = 0;
@@ -234,6 +297,32 @@ pg_status build_graph_form(int32_t n, int32_t p, const double* source_v, int32_t
         }
       }
     }
+  }
+  // coupling-capacitor table
+  f.csoff.assign(nsl + 1, 0);
+  int64_t ctotal = 0;
+  std::vector<std::vector<std::pair<int32_t, double>>> crow(kSlice);
+  for (int64_t s = 0; s < nsl; ++s) {
+    int64_t w = 0;
+    for (int j = 0; j < kSlice; ++j) {
+      const int32_t i = node_at[s * kSlice + j];
+      crow[j].clear();
+      if (i >= 0)
+        for (int64_t k = off[i]; k < off[i + 1]; ++k)
+          if (pairs[pid[k]].c > 0) crow[j].emplace_back(f.slot[adj[k]], pairs[pid[k]].c);
+      std::sort(crow[j].begin(), crow[j].end());
+      w = std::max<int64_t>(w, (int64_t)crow[j].size());
+    }
+    for (int64_t k = 0; k < w; ++k)
+      for (int j = 0; j < kSlice; ++j) {
+        const bool has = k < (int64_t)crow[j].size();
+        f.ccol.push_back(has ? crow[j][k].first : (int32_t)(s * kSlice + j));
+        f.cval.push_back(has ? crow[j][k].second : 0.0);
+      }
+    ctotal += w * kSlice;
+    if (ctotal > (int64_t)INT32_MAX)
+      return gfail(PG_ERR_UNSUPPORTED, msg, len, "the padded capacitor table exceeds 2^31 entries");
+    f.csoff[s + 1] = (int32_t)ctotal;
   }
   return PG_OK;
 }

@@ -30,6 +30,10 @@ struct GraphForm {
   std::vector<double> inv_l;         // sum of 1 / L over the inductors joining the pair, 1/H
   std::vector<double> cc;            // sum of the capacitors joining the pair, F
   int64_t nnz = 0;                   // off-diagonal pattern entries (both directions, no padding)
+  // the pairs joined by a capacitor alone, as a second sliced-ELL table of the same layout
+  // (most slices are empty), for the off-diagonal part of (C/h) v in the right-hand side
+  std::vector<int32_t> csoff, ccol;
+  std::vector<double> cval;          // F
   // per trivial node (node order)
   std::vector<double> c_diag;        // every capacitor at the node (to ground, a supply or a node), F
   std::vector<double> g_diag;        // every resistor at the node, S

@@ -27,12 +27,9 @@ __global__ __launch_bounds__(kChunk) void k_graph_rhs(const GraphChunk* __restri
   const int i = ch.slot0 + (int)threadIdx.x;
   const double* __restrict__ v = G.v[c.vidx[ch.item]] + off;
   double bb = G.ch64[i] * v[i] + G.bconst64[i];
-  if (G.sl_cap) {
-    const int base = G.sl_off[i >> 6], w = (G.sl_off[(i >> 6) + 1] - base) >> 6;
-    for (int k = 0; k < w; ++k) {
-      const int e = base + (k << 6) + (i & 63);
-      bb -= G.sl_cap[e] * v[G.sl_col[e]];
-    }
+  if (G.cap_off) {
+    const int base = G.cap_off[i >> 6] + (i & 63), w = (G.cap_off[(i >> 6) + 1] - G.cap_off[i >> 6]) >> 6;
+    for (int k = 0; k < w; ++k) bb -= G.cap_val[base + (k << 6)] * v[G.cap_col[base + (k << 6)]];
   }
   if (G.n_ind) {
     const double* __restrict__ il = G.ind_i + (int64_t)ch.scen * G.n_ind;
@@ -63,19 +60,27 @@ __global__ __launch_bounds__(kChunk) void k_graph_sweep(const GraphChunk* __rest
   T* __restrict__ d = static_cast<T*>(G.d[0]) + off;
   const T* __restrict__ r = static_cast<const T*>(G.r) + off;
   const T* __restrict__ wv = static_cast<const T*>(G.sl_ws);
-  const int base = G.sl_off[i >> 6], w = (G.sl_off[(i >> 6) + 1] - base) >> 6;
+  const int base = G.sl_off[i >> 6] + (i & 63), w = (G.sl_off[(i >> 6) + 1] - G.sl_off[i >> 6]) >> 6;
+  // zero_in: only neighbours already updated in this sweep (slot < lim) carry a value
+  const int lim = zero_in ? ch.lim : 0x7fffffff;
   T acc = r[i];
-  if (zero_in) {
-    for (int k = 0; k < w; ++k) {
-      const int e = base + (k << 6) + (i & 63);
-      const int j = G.sl_col[e];
-      if (j < ch.lim) acc += wv[e] * d[j];
+  int k = 0;
+  for (; k + 4 <= w; k += 4) {  // four table entries, then their four gathers, in flight together
+    int j[4];
+    T g[4], dj[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      j[q] = G.sl_col[base + ((k + q) << 6)];
+      g[q] = wv[base + ((k + q) << 6)];
     }
-  } else {
-    for (int k = 0; k < w; ++k) {
-      const int e = base + (k << 6) + (i & 63);
-      acc += wv[e] * d[G.sl_col[e]];
-    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) dj[q] = j[q] < lim ? d[j[q]] : T(0);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) acc += g[q] * dj[q];
+  }
+  for (; k < w; ++k) {
+    const int j = G.sl_col[base + (k << 6)];
+    if (j < lim) acc += wv[base + (k << 6)] * d[j];
   }
   const T inv = static_cast<const T*>(G.invDs)[i];
   const T old = zero_in ? T(0) : d[i];
@@ -104,20 +109,26 @@ __global__ __launch_bounds__(kChunk) void k_graph_resid(const GraphChunk* __rest
     const double D = G.D64[i];
     const double own = has_d ? v[i] + (double)d[i] : v[i];
     double acc = G.b[off + i] - D * own;
-    const int base = G.sl_off[i >> 6], w = (G.sl_off[(i >> 6) + 1] - base) >> 6;
-    if (has_d) {
-      for (int k = 0; k < w; ++k) {
-        const int e = base + (k << 6) + (i & 63);
-        const int j = G.sl_col[e];
-        acc += G.sl_w64[e] * (v[j] + (double)d[j]);
+    const int base = G.sl_off[i >> 6] + (i & 63), w = (G.sl_off[(i >> 6) + 1] - G.sl_off[i >> 6]) >> 6;
+    int k = 0;
+    for (; k + 4 <= w; k += 4) {  // four table entries, then their gathers, in flight together
+      int j[4];
+      double g[4], x[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        j[q] = G.sl_col[base + ((k + q) << 6)];
+        g[q] = G.sl_w64[base + ((k + q) << 6)];
       }
-      G.v[vi ^ 1][off + i] = own;
-    } else {
-      for (int k = 0; k < w; ++k) {
-        const int e = base + (k << 6) + (i & 63);
-        acc += G.sl_w64[e] * v[G.sl_col[e]];
-      }
+#pragma unroll
+      for (int q = 0; q < 4; ++q) x[q] = has_d ? v[j[q]] + (double)d[j[q]] : v[j[q]];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) acc += g[q] * x[q];
     }
+    for (; k < w; ++k) {
+      const int j = G.sl_col[base + (k << 6)];
+      acc += G.sl_w64[base + (k << 6)] * (has_d ? v[j] + (double)d[j] : v[j]);
+    }
+    if (has_d) G.v[vi ^ 1][off + i] = own;
     static_cast<T*>(G.r)[off + i] = (T)acc;
     if (D > 0.0) m = fabs(acc) / D;  // padding slots (D = 0) carry r = 0
   }
@@ -127,7 +138,7 @@ __global__ __launch_bounds__(kChunk) void k_graph_resid(const GraphChunk* __rest
   if (threadIdx.x == 0) {
     double bm = wmax[0];
     for (int k = 1; k < kChunk / 64; ++k) bm = nan_max(bm, wmax[k]);
-    atomicMax(&c.norm_bits[ch.item], (unsigned long long)__double_as_longlong(bm));
+    raise_max(&c.norm_bits[ch.item], bm);
   }
 }
 

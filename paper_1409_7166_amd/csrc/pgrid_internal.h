@@ -28,6 +28,14 @@ __device__ __forceinline__ double nan_max(double m, double x) {
   return (x > m || x != x) ? x : m;
 }
 
+// Raise a running maximum stored as the bits of a double >= 0 (NaN above +inf) to x >= 0.  The
+// stored value only grows while a pass runs, so a workgroup whose x does not exceed what it reads
+// skips the atomic: thousands of workgroups of one item would otherwise serialize on one word.
+__device__ __forceinline__ void raise_max(unsigned long long* p, double x) {
+  const unsigned long long b = (unsigned long long)__double_as_longlong(x);
+  if (b > __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) atomicMax(p, b);
+}
+
 // Per-grid device descriptor.  A layered mesh (kind 0) stores every per-node array with a row
 // pitch X >= nx (a multiple of kPitchAlign): slot (l*ny + y)*X + x.  Coefficients are zero in
 // the padding columns, at x = nx-1 (gE), y = ny-1 (gN), on the top layer (gU) and wherever no
@@ -72,12 +80,15 @@ struct GridDesc {
   const int32_t* inc_ind;          // signed: k+1 if the slot is ind_a[k], -(k+1) if ind_b[k]
   const double* ind_vfar;          // far-end voltage of a branch with ind_b = -1 (null: vdd)
   double vdd;
-  // general graph: neighbour table (see above) and coupling capacitances C_ij / h per entry
+  // general graph: neighbour table (see above), and the table of the pairs joined by
+  // capacitors (same layout, values C_ij / h; cap_off null when there are none)
   const int32_t* sl_off;
   const int32_t* sl_col;
   const double* sl_w64;
   const void* sl_ws;               // w in the sweep precision
-  const double* sl_cap;            // null when no capacitor joins two nodes
+  const int32_t* cap_off;
+  const int32_t* cap_col;
+  const double* cap_val;
   // coefficient words one sweep reads (for the activity accounting of the decision)
   int64_t coef_words;
 };

@@ -60,7 +60,7 @@ struct GridHost {
   DBuf gE64, gN64, gU64, D64, ch64, bconst64, gEs, gNs, gUs, invDs;
   DBuf v0, v1, b, r, d0, d1;
   DBuf ind_a_d, ind_b_d, ind_geq_d, ind_alpha_d, ind_i_d, inc_off_d, inc_ind_d, ind_vfar_d;
-  DBuf slot_d, sl_off_d, sl_col_d, sl_w64_d, sl_ws_d, sl_cap_d;
+  DBuf slot_d, sl_off_d, sl_col_d, sl_w64_d, sl_ws_d, cap_off_d, cap_col_d, cap_val_d;
   int sweep_fp32 = -1;                           // precision the sweep buffers were built for
 };
 
@@ -454,14 +454,18 @@ pg_status build_graph_grid(pg_ctx* c, int gi) {
   std::vector<double> w(ne), cap;
   for (size_t e = 0; e < ne; ++e) w[e] = F.g[e] + h * F.inv_l[e] + (dc ? 0.0 : F.cc[e] / h);
   if (F.has_coupling) {  // same size at DC (zeros: capacitors open), so the buffer stays put
-    cap.assign(ne, 0.0);
+    cap.assign(F.cval.size(), 0.0);
     if (!dc)
-      for (size_t e = 0; e < ne; ++e) cap[e] = F.cc[e] / h;
+      for (size_t e = 0; e < cap.size(); ++e) cap[e] = F.cval[e] / h;
   }
   PG_TRY(upload(c, G.D64, D)); PG_TRY(upload(c, G.ch64, ch)); PG_TRY(upload(c, G.bconst64, bc));
   PG_TRY(upload(c, G.sl_off_d, F.soff)); PG_TRY(upload(c, G.sl_col_d, F.col)); PG_TRY(upload(c, G.sl_w64_d, w));
   PG_TRY(upload(c, G.slot_d, F.slot));
-  if (cap.empty()) dfree(G.sl_cap_d); else PG_TRY(upload(c, G.sl_cap_d, cap));
+  if (!F.has_coupling) {
+    dfree(G.cap_off_d); dfree(G.cap_col_d); dfree(G.cap_val_d);
+  } else {
+    PG_TRY(upload(c, G.cap_off_d, F.csoff)); PG_TRY(upload(c, G.cap_col_d, F.ccol)); PG_TRY(upload(c, G.cap_val_d, cap));
+  }
   const bool f32 = fp32_mode(c);
   if (f32) {
     std::vector<float> wf(ne), qf(ns);
@@ -509,7 +513,8 @@ GridDesc make_desc(pg_ctx* c, GridHost& H) {
     D.sl_off = (const int32_t*)H.sl_off_d.p; D.sl_col = (const int32_t*)H.sl_col_d.p;
     D.sl_w64 = (const double*)H.sl_w64_d.p;
     D.sl_ws = fp32_mode(c) ? H.sl_ws_d.p : H.sl_w64_d.p;
-    D.sl_cap = (const double*)H.sl_cap_d.p;
+    D.cap_off = (const int32_t*)H.cap_off_d.p; D.cap_col = (const int32_t*)H.cap_col_d.p;
+    D.cap_val = (const double*)H.cap_val_d.p;
     // invD, w (the column indices count as half a word in FP64 residuals)
     H.coef_words = H.nstore + (3 * H.form.nnz) / 2;
   } else {

@@ -77,6 +77,43 @@ def _pulses(rng_node, rng_shape, nodes, fraction, peak_max, start_max, wmin, wma
     return Pulses(sel, peak, start, width)
 
 
+def _reconnect(rng, side, keepE, keepN):
+    from scipy.sparse import coo_matrix
+    from scipy.sparse.csgraph import connected_components
+    P = side * side
+    ids = np.arange(P).reshape(side, side)
+    for l in range(keepE.shape[0]):
+        a = np.concatenate([ids[:, :-1][keepE[l]], ids[:-1, :][keepN[l]]])
+        b = np.concatenate([ids[:, 1:][keepE[l]], ids[1:, :][keepN[l]]])
+        ncomp, lab = connected_components(coo_matrix((np.ones(a.size), (a, b)), shape=(P, P)), directed=False)
+        if ncomp == 1:
+            continue
+        # dropped segments as (kind, y, x), visited in a random order, Kruskal-style
+        dE = np.argwhere(~keepE[l]); dN = np.argwhere(~keepN[l])
+        cand = [(0, y, x) for y, x in dE] + [(1, y, x) for y, x in dN]
+        parent = list(range(ncomp))
+
+        def find(i):
+            while parent[i] != i:
+                parent[i] = parent[parent[i]]
+                i = parent[i]
+            return i
+        for j in rng.permutation(len(cand)):
+            k, y, x = cand[j]
+            u = ids[y, x]
+            v = ids[y, x + 1] if k == 0 else ids[y + 1, x]
+            cu, cv = find(lab[u]), find(lab[v])
+            if cu != cv:
+                parent[cu] = cv
+                if k == 0:
+                    keepE[l, y, x] = True
+                else:
+                    keepN[l, y, x] = True
+                ncomp -= 1
+                if ncomp == 1:
+                    break
+
+
 def irregular_grid(side=40, nl=2, seed=11, drop=0.1, diag=0.05, coupling=0.05, leak=0.01,
                    layer_g=(1.0, 2.0, 4.0, 8.0), via_every=4, via_g=5.0, pad_every=8, pad_g=10.0,
                    supplies=(1.0, 1.05), c_range=(0.1 * PF, 5.0 * PF), rlc=False, fraction=0.3,
@@ -88,16 +125,12 @@ def irregular_grid(side=40, nl=2, seed=11, drop=0.1, diag=0.05, coupling=0.05, l
     nmesh = nl * P
     ids = np.arange(nmesh, dtype=np.int64).reshape(nl, side, side)
     br = _Branches()
-    # in-layer segments, a fraction dropped; a node left without any segment gets its east
-    # (or west) segment back, so every node keeps a resistive neighbour
+    # in-layer segments, a fraction dropped; dropped segments are then restored (in a random
+    # order) wherever they join two otherwise separate parts of a layer, so every layer stays
+    # connected and the DC matrix stays non-singular
     keepE = rs[0].random((nl, side, side - 1)) >= drop
     keepN = rs[0].random((nl, side - 1, side)) >= drop
-    deg = np.zeros((nl, side, side), int)
-    deg[:, :, :-1] += keepE; deg[:, :, 1:] += keepE; deg[:, :-1, :] += keepN; deg[:, 1:, :] += keepN
-    lone = np.argwhere(deg == 0)
-    for l, y, x in lone:
-        if x + 1 < side: keepE[l, y, x] = True
-        else: keepE[l, y, x - 1] = True
+    _reconnect(rs[0], side, keepE, keepN)
     lg = np.asarray(layer_g)[:nl, None, None]
     gE = rs[1].uniform(0.5, 2.0, (nl, side, side - 1)) * lg
     gN = rs[1].uniform(0.5, 2.0, (nl, side - 1, side)) * lg
@@ -221,6 +254,7 @@ class NetWorkload:
     steps: int
     precision: str = "fp32+ref"
     note: str = ""
+    dc_start: bool = False   # start from the DC operating point at t = 0 (not v = source_v[0])
 
     @property
     def nodes(self) -> int:
@@ -231,11 +265,13 @@ def graph1(side=1024, steps=1000) -> NetWorkload:
     """A 3-layer irregular RC grid at the scale of the 3-layer 1024 x 1024 mesh: 3,145,728 nodes,
     10 % of segments dropped, 5 % diagonal straps, 5 % coupling capacitors, 1 % leaks, 5 S vias
     every 4 nodes, 10 S pads every 64 nodes on the top layer alternating between 1.0 V and
-    1.05 V, 30 % of the bottom layer pulsing; natural (geometric) node numbering."""
+    1.05 V, 30 % of the bottom layer pulsing; natural (geometric) node numbering.  With two supply
+    voltages v = 1.0 V is not a steady state, so the transient starts from the DC operating point
+    at t = 0 (no load is on at t = 0)."""
     net, scen = irregular_grid(side=side, nl=3, seed=41, via_every=4, pad_every=64, fraction=0.3,
                                shuffle=False, start_max=500 * PS)
     return NetWorkload(f"graph_irregular_3x{side}", [net], [scen], 10 * PS, steps,
-                       note="irregular 3-layer RC netlist, colour-ordered sweeps")
+                       note="irregular 3-layer RC netlist, colour-ordered sweeps", dc_start=True)
 
 
 def graph_mesh1(side=1024, steps=1000) -> NetWorkload:
