@@ -233,6 +233,7 @@ SIDE_BY_SIDE = [
     ("config3a", "fp32+ref", 1e-6, 500), ("config3b", "fp32+ref", 1e-6, 500),
     ("config2", "fp64", 1e-6, 2000), ("config2", "fp32+ref", 1e-6, 2000),
     ("config4", "fp64", 1e-6, 200), ("config0", "fp64", 1e-6, 100),
+    ("graph1", "fp32+ref", 1e-6, 1000), ("graph_mesh1", "fp32+ref", 1e-6, 1000),
 ]
 
 
