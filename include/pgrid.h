@@ -348,12 +348,19 @@ pg_status pg_update_mesh_values(pg_ctx* ctx, int32_t grid, const double* gE, con
  *     dJ/dC_i  = sum_k lambda_k,i (v_{k-1,i} - v_k,i) / h             [nl][ny][nx]
  *     dJ/dgE_e = -sum_k (lambda_a - lambda_b)(v_a - v_b) over east segments   [nl][ny][nx-1]
  *     dJ/dgN_e = the same over north segments                                 [nl][ny-1][nx]
- * to host memory (pg_loss_backward) or device memory (pg_loss_backward_dev).  Pads, vias and
- * sources are held fixed.  The context is left at step k0 + nsteps with the forward end state. */
+ * to host memory (pg_loss_backward) or device memory (pg_loss_backward_dev).  Sources are held
+ * fixed.  The context is left at step k0 + nsteps with the forward end state.
+ * The same reverse pass also accumulates the gradients with respect to the via and pad
+ * conductances, which pg_loss_branch_gradients copies to host arrays in the mesh's via and pad
+ * order (n_vias and n_pads doubles; a via joins two layers like a segment, and a pad of
+ * conductance g at node a adds g to M_aa and g Vdd to the right-hand side):
+ *     dJ/dvia_g = -sum_k (lambda_a - lambda_b)(v_a - v_b),  dJ/dpad_g = sum_k lambda_a (Vdd - v_a).
+ * PG_ERR_STATE before a completed pg_loss_backward(_dev). */
 pg_status pg_loss_forward(pg_ctx* ctx, int32_t grid, int32_t scen, int32_t nsteps, int32_t ckpt_every,
                           double margin, double* J);
 pg_status pg_loss_backward(pg_ctx* ctx, double tol_adj, double* dJ_dC, double* dJ_dgE, double* dJ_dgN);
 pg_status pg_loss_backward_dev(pg_ctx* ctx, double tol_adj, double* dJ_dC, double* dJ_dgE, double* dJ_dgN);
+pg_status pg_loss_branch_gradients(pg_ctx* ctx, double* dJ_dvia_g, double* dJ_dpad_g);
 
 pg_status pg_get_stats(const pg_ctx* ctx, pg_stats* out);
 pg_status pg_reset_stats(pg_ctx* ctx);

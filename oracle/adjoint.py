@@ -14,7 +14,10 @@ and the gradients with respect to a node capacitance C_i and a mesh segment
 conductance g_e between nodes a and b are
   dJ/dC_i = sum_k lambda_{k,i} (v_{k-1,i} - v_{k,i}) / h,
   dJ/dg_e = - sum_k (lambda_{k,a} - lambda_{k,b}) (v_{k,a} - v_{k,b}).
-Pads, vias and source waveforms are held fixed.
+A via is such a branch between (x, y, l) and (x, y, l+1); a pad of conductance g_p at node a
+adds g_p to M_aa and g_p Vdd to f_k, so
+  dJ/dg_p = sum_k lambda_{k,a} (Vdd - v_{k,a}).
+Source waveforms are held fixed.
 """
 from __future__ import annotations
 
@@ -64,6 +67,15 @@ def forward_states(mesh, pulses, h, steps):
 
 def adjoint_gradients(mesh, pulses, h, steps, margin):
     """Return (J, dJ/dC [nl,ny,nx], dJ/dgE [nl,ny,nx-1], dJ/dgN [nl,ny-1,nx])."""
+    return _adjoint(mesh, pulses, h, steps, margin)[:4]
+
+
+def adjoint_branch_gradients(mesh, pulses, h, steps, margin):
+    """Return (dJ/dvia_g [n_vias], dJ/dpad_g [n_pads]) in the mesh's via and pad order."""
+    return _adjoint(mesh, pulses, h, steps, margin)[4:]
+
+
+def _adjoint(mesh, pulses, h, steps, margin):
     st, V = forward_states(mesh, pulses, h, steps)
     vdd = mesh.vdd
     J = softplus_loss(V[1:], vdd, margin)
@@ -71,6 +83,10 @@ def adjoint_gradients(mesh, pulses, h, steps, margin):
     dC = np.zeros(mesh.n)
     dgE = np.zeros(ea.shape)
     dgN = np.zeros(na.shape)
+    va = np.asarray(mesh.via_node, np.int64); vb = va + mesh.nx * mesh.ny
+    pa = np.asarray(mesh.pad_node, np.int64)
+    dvia = np.zeros(va.size)
+    dpad = np.zeros(pa.size)
     lam_next = np.zeros(mesh.n)
     for k in range(steps, 0, -1):
         lam = st.fac.solve(_dloss(V[k], vdd, margin) + st.Ch @ lam_next)
@@ -78,9 +94,11 @@ def adjoint_gradients(mesh, pulses, h, steps, margin):
         dC += lam * (V[k - 1] - vk) / h
         dgE -= (lam[ea] - lam[eb]) * (vk[ea] - vk[eb])
         dgN -= (lam[na] - lam[nb]) * (vk[na] - vk[nb])
+        dvia -= (lam[va] - lam[vb]) * (vk[va] - vk[vb])
+        dpad += lam[pa] * (vdd - vk[pa])
         lam_next = lam
     shape = (mesh.nl, mesh.ny, mesh.nx)
-    return J, dC.reshape(shape), dgE, dgN
+    return J, dC.reshape(shape), dgE, dgN, dvia, dpad
 
 
 def tangent_linear(mesh, pulses, h, steps, margin, dC, dgE, dgN):

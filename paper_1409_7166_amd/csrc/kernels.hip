@@ -1141,6 +1141,27 @@ __global__ __launch_bounds__(kThreads) void k_adj_grad(const Tile* __restrict__ 
   }
 }
 
+// Gradients with respect to the pad and via conductances at one reverse step: a pad at slot a
+// adds g to M_aa and g Vdd to the right-hand side, so dJ/dg += lambda_a (Vdd - v_a); a via joins
+// slots a and a + P, so dJ/dg -= (lambda_a - lambda_b)(v_a - v_b).  One thread per branch.
+__global__ void k_adj_branch_grad(const GridDesc* __restrict__ grids, int grid, int item, int scen, Ctl c,
+                                  const double* __restrict__ vk, const int32_t* __restrict__ pad_slot, int n_pads,
+                                  const int32_t* __restrict__ via_slot, int n_vias, int64_t P,
+                                  double* __restrict__ dpad, double* __restrict__ dvia) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= n_pads + n_vias) return;
+  const GridDesc& G = grids[grid];
+  const double* __restrict__ lam = G.v[c.vidx[item]] + (int64_t)scen * G.nstore;
+  if (j < n_pads) {
+    const int a = pad_slot[j];
+    dpad[j] += lam[a] * (G.vdd - vk[a]);
+  } else {
+    const int q = j - n_pads;
+    const int64_t a = via_slot[q], b = a + P;
+    dvia[q] -= (lam[a] - lam[b]) * (vk[a] - vk[b]);
+  }
+}
+
 // ------------------------------------------------------------------------------------
 // Launch wrappers
 // ------------------------------------------------------------------------------------
@@ -1309,6 +1330,15 @@ hipError_t launch_adj_rhs(const Tile* tiles, int ntiles, int tile_rows, const Gr
                           const double* vk, double margin, hipStream_t s) {
   if (ntiles <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_adj_rhs, dim3(ntiles), dim3(kThreads), 0, s, tiles, ntiles, tile_rows, grids, c, vk, margin);
+  return hipGetLastError();
+}
+
+hipError_t launch_adj_branch_grad(const GridDesc* grids, int grid, int item, int scen, const Ctl& c,
+                                  const double* vk, const int32_t* pad_slot, int n_pads, const int32_t* via_slot,
+                                  int n_vias, int64_t P, double* dpad, double* dvia, hipStream_t s) {
+  if (n_pads + n_vias <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_adj_branch_grad, dim3((n_pads + n_vias + 255) / 256), dim3(256), 0, s, grids, grid, item,
+                     scen, c, vk, pad_slot, n_pads, via_slot, n_vias, P, dpad, dvia);
   return hipGetLastError();
 }
 

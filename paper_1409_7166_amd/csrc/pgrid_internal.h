@@ -212,6 +212,10 @@ hipError_t launch_adj_rhs(const Tile* tiles, int ntiles, int tile_rows, const Gr
 hipError_t launch_adj_grad(const Tile* tiles, int ntiles, int tile_rows, const GridDesc* grids, const Ctl& c,
                            const double* vk, const double* vprev, double inv_h, double* dC, double* dgE,
                            double* dgN, hipStream_t s);
+// pad and via conductance gradients of one reverse step (slots of the item's grid; P = layer stride)
+hipError_t launch_adj_branch_grad(const GridDesc* grids, int grid, int item, int scen, const Ctl& c,
+                                  const double* vk, const int32_t* pad_slot, int n_pads, const int32_t* via_slot,
+                                  int n_vias, int64_t P, double* dpad, double* dvia, hipStream_t s);
 hipError_t launch_state_copy(const Tile* tiles, int ntiles, int tile_rows, const GridDesc* grids, const Ctl& c,
                              double* buf, int to_buf, hipStream_t s);
 // One item's vector utilities (op codes at k_item_vec); tiles are the item's tiles.

@@ -127,6 +127,9 @@ struct pg_ctx {
     int64_t k0 = 0;
     GridDesc view{};                             // the grid's descriptor with lambda as its state
     DBuf ckpts, vend, seg, lam0, lam1, arhs, dC, dgE, dgN, part, J, saved_vidx;
+    DBuf pad_slot, via_slot, dpad, dvia;         // pad and via conductance gradients
+    int n_pads = 0, n_vias = 0;
+    bool branch_ready = false;                   // dpad / dvia hold the last backward pass
   } adj;
   // control block
   DBuf c_norm, c_last, c_active, c_vidx, c_sweeps, c_failed, c_any, c_stats64, c_stats32, c_statsd, c_nodes, c_item_grid;
@@ -1258,6 +1261,9 @@ pg_status loss_backward(pg_ctx* c, double tol_adj, double* dC, double* dgE, doub
   HIP_TRY(c, hipMemsetAsync(A.dC.p, 0, A.dC.bytes, c->stream));
   HIP_TRY(c, hipMemsetAsync(A.dgE.p, 0, A.dgE.bytes, c->stream));
   HIP_TRY(c, hipMemsetAsync(A.dgN.p, 0, A.dgN.bytes, c->stream));
+  if (A.dpad.bytes) HIP_TRY(c, hipMemsetAsync(A.dpad.p, 0, A.dpad.bytes, c->stream));
+  if (A.dvia.bytes) HIP_TRY(c, hipMemsetAsync(A.dvia.p, 0, A.dvia.bytes, c->stream));
+  A.branch_ready = false;
   HIP_TRY(c, hipMemsetAsync(A.saved_vidx.p, 0, sizeof(int32_t), c->stream));
   double* ck = (double*)A.ckpts.p;
   double* seg = (double*)A.seg.p;
@@ -1288,6 +1294,10 @@ pg_status loss_backward(pg_ctx* c, double tol_adj, double* dC, double* dgE, doub
       PG_TRY(solve_active(c, tol_adj));
       e = launch_adj_grad(T, nt, c->tile_rows, gd, c->ctl, seg + (size_t)q * ns, seg + (size_t)(q - 1) * ns,
                           1.0 / c->opt.h, (double*)A.dC.p, (double*)A.dgE.p, (double*)A.dgN.p, c->stream);
+      if (e == hipSuccess)
+        e = launch_adj_branch_grad(gd, A.grid, A.item, A.scen, c->ctl, seg + (size_t)q * ns,
+                                   (const int32_t*)A.pad_slot.p, A.n_pads, (const int32_t*)A.via_slot.p, A.n_vias,
+                                   (int64_t)H.X * H.ny, (double*)A.dpad.p, (double*)A.dvia.p, c->stream);
       if (e != hipSuccess) return set_err(c, PG_ERR_DEVICE, "adjoint gradient: %s", hipGetErrorString(e));
     }
     PG_TRY(use_view(c, false));
@@ -1305,6 +1315,7 @@ pg_status loss_backward(pg_ctx* c, double tol_adj, double* dC, double* dgE, doub
     HIP_TRY(c, hipMemset(c->ctl.stat_failed, 0, sizeof(int32_t)));
     return set_err(c, PG_ERR_NO_CONVERGENCE, "an adjoint or recomputed step reached max_sweeps");
   }
+  A.branch_ready = true;
   return PG_OK;
 }
 
@@ -1439,7 +1450,8 @@ void pg_destroy(pg_ctx* c) {
                   &c->c_clock, &c->src_win_t0};
   for (DBuf* b : bufs) dfree(*b);
   DBuf* abufs[] = {&c->adj.ckpts, &c->adj.vend, &c->adj.seg, &c->adj.lam0, &c->adj.lam1, &c->adj.arhs,
-                   &c->adj.dC, &c->adj.dgE, &c->adj.dgN, &c->adj.part, &c->adj.J, &c->adj.saved_vidx};
+                   &c->adj.dC, &c->adj.dgE, &c->adj.dgN, &c->adj.part, &c->adj.J, &c->adj.saved_vidx,
+                   &c->adj.pad_slot, &c->adj.via_slot, &c->adj.dpad, &c->adj.dvia};
   for (DBuf* b : abufs) dfree(*b);
   for (auto& e : c->prof_live) { (void)hipEventDestroy(e.a); (void)hipEventDestroy(e.b); }
   for (auto e : c->prof_pool) (void)hipEventDestroy(e);
@@ -1990,6 +2002,16 @@ pg_status pg_loss_forward(pg_ctx* c, int32_t grid, int32_t scen, int32_t nsteps,
   PG_TRY(dalloc(c, A.dC, ns * sizeof(double)));
   PG_TRY(dalloc(c, A.dgE, ns * sizeof(double)));
   PG_TRY(dalloc(c, A.dgN, ns * sizeof(double)));
+  {
+    std::vector<int32_t> ps, vs;
+    for (int32_t p : H.pad_node) ps.push_back((int32_t)H.storage(p));
+    for (int32_t v : H.via_node) vs.push_back((int32_t)H.storage(v));
+    A.n_pads = (int)ps.size();
+    A.n_vias = (int)vs.size();
+    PG_TRY(upload(c, A.pad_slot, ps)); PG_TRY(upload(c, A.via_slot, vs));
+    PG_TRY(dalloc(c, A.dpad, ps.size() * sizeof(double))); PG_TRY(dalloc(c, A.dvia, vs.size() * sizeof(double)));
+    A.branch_ready = false;
+  }
   PG_TRY(dalloc(c, A.part, (size_t)std::max(1, c->item_tile_cnt[A.item]) * sizeof(double)));
   PG_TRY(dalloc(c, A.J, sizeof(double)));
   PG_TRY(dalloc(c, A.saved_vidx, sizeof(int32_t)));
@@ -2031,6 +2053,20 @@ pg_status pg_loss_backward(pg_ctx* c, double tol_adj, double* dJ_dC, double* dJ_
 
 pg_status pg_loss_backward_dev(pg_ctx* c, double tol_adj, double* dJ_dC, double* dJ_dgE, double* dJ_dgN) {
   return loss_backward(c, tol_adj, dJ_dC, dJ_dgE, dJ_dgN, true);
+}
+
+pg_status pg_loss_branch_gradients(pg_ctx* c, double* dJ_dvia_g, double* dJ_dpad_g) {
+  if (!c) return PG_ERR_INVALID_ARG;
+  auto& A = c->adj;
+  if (!A.recorded || !A.branch_ready)
+    return set_err(c, PG_ERR_STATE, "pg_loss_branch_gradients needs a completed pg_loss_backward");
+  if ((A.n_vias && !dJ_dvia_g) || (A.n_pads && !dJ_dpad_g))
+    return set_err(c, PG_ERR_INVALID_ARG, "gradient outputs are NULL");
+  HIP_TRY(c, hipSetDevice(c->device));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  if (A.n_vias) HIP_TRY(c, hipMemcpy(dJ_dvia_g, A.dvia.p, A.n_vias * sizeof(double), hipMemcpyDeviceToHost));
+  if (A.n_pads) HIP_TRY(c, hipMemcpy(dJ_dpad_g, A.dpad.p, A.n_pads * sizeof(double), hipMemcpyDeviceToHost));
+  return PG_OK;
 }
 
 pg_status pg_update_mesh_values(pg_ctx* c, int32_t grid, const double* gE, const double* gN, const double* C) {

@@ -96,3 +96,29 @@ def test_full_size_adjoint_first_40_steps():
     say(f"  J={J:.10e} ref={Jr:.10e} rel errs {errs}")
     assert abs(J - Jr) <= 1e-9 * abs(Jr)
     assert max(errs) <= REL
+
+
+def test_via_and_pad_gradients_match_oracle():
+    """Two layers: the same reverse pass gives dJ/d(via g) and dJ/d(pad g) (oracle pinned by
+    central differences)."""
+    from oracle.adjoint import adjoint_branch_gradients
+    w = small_multilayer(side=30, seed=62, nl=2, via_every=3, pad_every=6, fraction=0.5, steps=20,
+                         c_range=(0.1e-12, 5e-12))
+    p = compressed(w.pulses[0][0], start=0.4, width=1.0, peak=20.0)
+    w.pulses[0][0] = p
+    mesh = w.meshes[0]
+    K, ck, margin = 20, 6, 0.05
+    say("[gpu] adjoint branch gradients 2x30x30")
+    with gpu_context(w, precision=pg.PG_PREC_FP64, tol=1e-12, omega=1.5, max_sweeps=50000) as ctx:
+        ctx.loss_forward(0, 0, K, ck, margin)
+        with pytest.raises(pg.PgError) as e:
+            ctx.loss_branch_gradients(0)
+        assert e.value.status == -7
+        dC, dE, dN = ctx.loss_backward(1e-10)
+        dv, dp = ctx.loss_branch_gradients(0)
+    Jr, rC, rE, rN = adjoint_gradients(mesh, p, w.h, K, margin)
+    rv, rp = adjoint_branch_gradients(mesh, p, w.h, K, margin)
+    errs = (_close(dC, rC), _close(dE, rE), _close(dN, rN), _close(dv, rv), _close(dp, rp))
+    say(f"  rel err C/gE/gN/via/pad = {errs}; |dpad| max {np.max(np.abs(rp)):.3e}")
+    assert dv.size == mesh.via_node.size and dp.size == mesh.pad_node.size
+    assert max(errs) <= REL and np.max(np.abs(rp)) > 0

@@ -3,7 +3,8 @@ transient per parameter, and the tangent-linear / adjoint identity."""
 import numpy as np
 import pytest
 
-from oracle.adjoint import adjoint_gradients, forward_states, softplus_loss, tangent_linear
+from oracle.adjoint import adjoint_branch_gradients, adjoint_gradients, forward_states, softplus_loss, \
+    tangent_linear
 from workloads import Pulses, small_rc, small_multilayer
 
 
@@ -40,6 +41,26 @@ def test_adjoint_matches_central_differences():
             assert abs(fd - g) <= 1e-6 * max(abs(g), 1e-3 * np.max(np.abs(grad))), (fd, g)
             checks += 1
     assert checks == 24
+
+
+def test_via_and_pad_gradients_match_central_differences():
+    """Two layers with vias every 2 nodes and pads every 3: dJ/dg of every via and every pad."""
+    w = small_multilayer(side=6, seed=19, nl=2, via_every=2, pad_every=3, fraction=1.0, steps=14)
+    mesh, p = w.meshes[0], w.pulses[0][0]
+    p = Pulses(p.node, p.peak * 400, p.start * 0.2, p.width * 0.5)
+    h, K, margin = w.h, 14, 0.05
+    dvia, dpad = adjoint_branch_gradients(mesh, p, h, K, margin)
+    assert dvia.size == mesh.via_node.size and dpad.size == mesh.pad_node.size
+    for arr, grad in ((mesh.via_g, dvia), (mesh.pad_g, dpad)):
+        for j in range(arr.size):
+            base = arr[j]
+            step = 1e-5 * base
+            arr[j] = base + step; Jp = _J(mesh, p, h, K, margin)
+            arr[j] = base - step; Jm = _J(mesh, p, h, K, margin)
+            arr[j] = base
+            fd = (Jp - Jm) / (2 * step)
+            assert abs(fd - grad[j]) <= 1e-6 * max(abs(grad[j]), 1e-3 * np.max(np.abs(grad))), (fd, grad[j])
+    assert np.max(np.abs(dpad)) > 0 and np.max(np.abs(dvia)) > 0
 
 
 def test_tangent_linear_equals_adjoint_projection():
