@@ -62,6 +62,21 @@ typedef enum pg_ordering {
   PG_ORDER_JACOBI = 1           /* weighted Jacobi: every node from the previous sweep's values */
 } pg_ordering;
 
+typedef enum pg_recurrence {
+  /* backward Euler with every inductor current kept as state (eq. 10, companion form) */
+  PG_REC_TWO_LEVEL = 0,
+  /* the three-level recurrence of eq. 11 / eq. 14 with the inductor currents eliminated:
+   *   (C/h + G + hL) v(t+h) = (2C/h + G) v(t) - (C/h) v(t-h) - h L_s v_d - (I(t+h) - I(t)),
+   * same matrix, so the same sweeps.  The first step after the state is set (upload, reset,
+   * pg_set_state, pg_dc_operating_point, pg_set_time) is a two-level step, which supplies
+   * v(t-h).  The recurrence has a root at 1 for solver error (each step's residual is carried
+   * forward, not damped); pg_recurrence_drift measures what it has accumulated.  The inductor
+   * currents are still updated (i(t+h) = i(t) + (h/L)(v_a - v_b)(t+h)) so they can be read.
+   * General-netlist grids only, plain launches only (graphs = 0); PG_ERR_UNSUPPORTED
+   * otherwise. */
+  PG_REC_THREE_LEVEL = 1
+} pg_recurrence;
+
 /* Solver options (Algorithm 1 inputs h and tol; omega of eq. 17). */
 typedef struct pg_options {
   double h;             /* backward-Euler step in seconds, > 0 */
@@ -79,7 +94,8 @@ typedef struct pg_options {
   int32_t sweeps_per_launch; /* red-black sweeps fused into one kernel launch: 1 or 2 (0 = 1); two
                            sweeps stage a wider halo and recompute its rings, and move the bytes
                            of one sweep.  Results are identical.  Jacobi ordering always uses 1 */
-  int32_t reserved[3];  /* must be zero */
+  int32_t recurrence;   /* PG_REC_TWO_LEVEL (default) or PG_REC_THREE_LEVEL (general netlists only) */
+  int32_t reserved[2];  /* must be zero */
 } pg_options;
 
 /* A layered RC/RLC mesh (the representative node of Fig. 2 repeated on a grid).
@@ -326,6 +342,15 @@ pg_status pg_graph_info(const pg_ctx* ctx, int32_t grid, int32_t* n_nodes, int32
  * (blocking) or to device memory (queued on the context stream).  Inductor currents of a mesh:
  * n_vias + n_pads doubles, via then pad order, zero for resistive branches; of a general
  * netlist: one per L branch in netlist order. */
+/* Under PG_REC_THREE_LEVEL, after at least one step: the Jacobi-scaled residual of Kirchhoff's
+ * current law at the current time t_k with the backward-Euler capacitor currents and the
+ * inductor currents the library keeps updating,
+ *   max_i |C (v_k - v_{k-1})/h + G v_k + G_s v_d + A_l^T i_k + A_i^T I(t_k)|_i / M_ii   (volts),
+ * for (grid, scen).  Under the two-level recurrence this would be the step's own residual (at most
+ * tol); under the three-level one it also holds the solver error the recurrence has carried
+ * forward.  Queued on the context stream and waited for; PG_ERR_STATE before a three-level step
+ * or under the two-level recurrence. */
+pg_status pg_recurrence_drift(pg_ctx* ctx, int32_t grid, int32_t scen, double* drift);
 pg_status pg_read_voltages(pg_ctx* ctx, int32_t grid, int32_t scen, double* out, int64_t n);
 pg_status pg_read_voltages_dev(pg_ctx* ctx, int32_t grid, int32_t scen, double* dev_out, int64_t n);
 pg_status pg_read_inductor_currents(pg_ctx* ctx, int32_t grid, int32_t scen, double* out, int64_t n);

@@ -9,9 +9,9 @@ inductor update) runs in the gfx950 kernels of ``libpgrid.so``;
 from .pgrid import (Context, GraphShape, NetlistMesh, Options, PgError, default_options, lib, netlist_coloring,
                     netlist_to_mesh,
                     validate_mesh, validate_netlist, validate_options, PG_PREC_FP64, PG_PREC_FP32_REFINE,
-                    PG_ORDER_RED_BLACK, PG_ORDER_JACOBI)
+                    PG_ORDER_RED_BLACK, PG_ORDER_JACOBI, PG_REC_TWO_LEVEL, PG_REC_THREE_LEVEL)
 
 __all__ = ["Context", "GraphShape", "NetlistMesh", "Options", "PgError", "default_options", "lib",
            "netlist_coloring", "netlist_to_mesh",
            "validate_mesh", "validate_netlist", "validate_options", "PG_PREC_FP64", "PG_PREC_FP32_REFINE",
-           "PG_ORDER_RED_BLACK", "PG_ORDER_JACOBI"]
+           "PG_ORDER_RED_BLACK", "PG_ORDER_JACOBI", "PG_REC_TWO_LEVEL", "PG_REC_THREE_LEVEL"]

@@ -358,11 +358,13 @@ __global__ __launch_bounds__(kThreads) void k_rhs(const Tile* __restrict__ tiles
   }
 }
 
-// Piecewise-linear current sources at the step's time, subtracted from b.  Grid-stride over the
-// always-on sources and the window chosen by k_step_begin.
-__global__ void k_sources(SourceTable src, const GridDesc* __restrict__ grids, Ctl c) {
+// Piecewise-linear current sources: b -= sign * I(t) at t = t_now + shift (sign 1, shift 0: the
+// step's loads; the three-level recurrence also adds back the previous step's, shift -h and
+// sign -1, which the window still covers because it is widened by a bucket of 8 steps).
+// Grid-stride over the always-on sources and the window chosen by k_step_begin.
+__global__ void k_sources(SourceTable src, const GridDesc* __restrict__ grids, Ctl c, double shift, double sign) {
   if (*c.stall) return;
-  const double t = c.t_now[0];
+  const double t = c.t_now[0] + shift;
   const int wbeg = c.src_window[0], wcnt = c.src_window[1];
   const int n = src.n_always + wcnt;
   const double* __restrict__ ts = src.t;
@@ -384,7 +386,7 @@ __global__ void k_sources(SourceTable src, const GridDesc* __restrict__ grids, C
       I = is[lo] + (is[hi] - is[lo]) * ((t - ts[lo]) / (ts[hi] - ts[lo]));
     }
     const GridDesc& G = grids[src.grid[k]];
-    G.b[src.index[k]] -= I;
+    G.b[src.index[k]] -= sign * I;
   }
 }
 
@@ -1186,10 +1188,11 @@ hipError_t launch_rhs(const Tile* tiles, int ntiles, int tile_rows, const GridDe
   return hipGetLastError();
 }
 
-hipError_t launch_sources(const SourceTable& src, const GridDesc* grids, const Ctl& c, hipStream_t s) {
+hipError_t launch_sources(const SourceTable& src, const GridDesc* grids, const Ctl& c, double shift, double sign,
+                          hipStream_t s) {
   if (src.count <= 0) return hipSuccess;
   const int blocks = (src.count + 255) / 256 < 2048 ? (src.count + 255) / 256 : 2048;
-  hipLaunchKernelGGL(k_sources, dim3(blocks), dim3(256), 0, s, src, grids, c);
+  hipLaunchKernelGGL(k_sources, dim3(blocks), dim3(256), 0, s, src, grids, c, shift, sign);
   return hipGetLastError();
 }
 

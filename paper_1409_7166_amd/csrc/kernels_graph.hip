@@ -16,7 +16,7 @@ namespace {
 
 // b = (C/h) v + G0 v_s + (h/L) v_s - inductor history, with C/h's off-diagonal coupling terms.
 __global__ __launch_bounds__(kChunk) void k_graph_rhs(const GraphChunk* __restrict__ chunks, int n,
-                                                     const GridDesc* __restrict__ grids, Ctl c) {
+                                                     const GridDesc* __restrict__ grids, Ctl c, int save_prev) {
   if (*c.stall) return;  // a stalled step opening
   const int ci = xcd_tile(n);
   if (ci < 0) return;
@@ -41,6 +41,102 @@ __global__ __launch_bounds__(kChunk) void k_graph_rhs(const GraphChunk* __restri
     }
   }
   G.b[off + i] = bb;
+  if (save_prev) G.vprev[(c.step[0] + 1) & 1][off + i] = v[i];
+}
+
+// Three-level right-hand side (eq. 11 / eq. 14) without the sources:
+//   b = (C/h)(2 v(t) - v(t-h)) + G v(t) + (h/L) v_s,
+// G being the resistor part of M (diagonal incl. resistors to supplies and ground); v(t) is
+// kept as the next step's v(t-h) in the other vprev buffer.
+__global__ __launch_bounds__(kChunk) void k_graph_rhs3(const GraphChunk* __restrict__ chunks, int n,
+                                                      const GridDesc* __restrict__ grids, Ctl c) {
+  if (*c.stall) return;
+  const int ci = xcd_tile(n);
+  if (ci < 0) return;
+  const GraphChunk ch = chunks[ci];
+  if ((int)threadIdx.x >= ch.count) return;
+  const GridDesc& G = grids[ch.grid];
+  const int64_t off = (int64_t)ch.scen * G.nstore;
+  const int i = ch.slot0 + (int)threadIdx.x;
+  const double* __restrict__ v = G.v[c.vidx[ch.item]] + off;
+  const long long k0 = c.step[0];
+  const double* __restrict__ vp = G.vprev[k0 & 1] + off;
+  const double vi = v[i];
+  double bb = G.ch64[i] * (2.0 * vi - vp[i]) + G.g3diag[i] * vi + G.bl64[i];
+  {
+    const int base = G.sl_off[i >> 6] + (i & 63), w = (G.sl_off[(i >> 6) + 1] - G.sl_off[i >> 6]) >> 6;
+    for (int k = 0; k < w; ++k) bb -= G.sl_g64[base + (k << 6)] * v[G.sl_col[base + (k << 6)]];
+  }
+  if (G.cap_off) {
+    const int base = G.cap_off[i >> 6] + (i & 63), w = (G.cap_off[(i >> 6) + 1] - G.cap_off[i >> 6]) >> 6;
+    for (int k = 0; k < w; ++k) {
+      const int j = G.cap_col[base + (k << 6)];
+      bb -= G.cap_val[base + (k << 6)] * (2.0 * v[j] - vp[j]);
+    }
+  }
+  G.b[off + i] = bb;
+  G.vprev[(k0 + 1) & 1][off + i] = vi;
+}
+
+// Kirchhoff's current law at the current time with backward-Euler capacitor currents and the
+// tracked inductor currents, without the sources (added next by the source kernel):
+//   b = (C/h)(v - v(t-h)) + G v - G0 v_s + A_l^T i.
+__global__ __launch_bounds__(kChunk) void k_graph_kcl(const GraphChunk* __restrict__ chunks, int n,
+                                                     const GridDesc* __restrict__ grids, Ctl c) {
+  const int ci = xcd_tile(n);
+  if (ci < 0) return;
+  const GraphChunk ch = chunks[ci];
+  if ((int)threadIdx.x >= ch.count) return;
+  const GridDesc& G = grids[ch.grid];
+  const int64_t off = (int64_t)ch.scen * G.nstore;
+  const int i = ch.slot0 + (int)threadIdx.x;
+  const double* __restrict__ v = G.v[c.vidx[ch.item]] + off;
+  const double* __restrict__ vp = G.vprev[c.step[0] & 1] + off;
+  double res = G.ch64[i] * (v[i] - vp[i]) + G.g3diag[i] * v[i] - G.bres64[i];
+  {
+    const int base = G.sl_off[i >> 6] + (i & 63), w = (G.sl_off[(i >> 6) + 1] - G.sl_off[i >> 6]) >> 6;
+    for (int k = 0; k < w; ++k) res -= G.sl_g64[base + (k << 6)] * v[G.sl_col[base + (k << 6)]];
+  }
+  if (G.cap_off) {
+    const int base = G.cap_off[i >> 6] + (i & 63), w = (G.cap_off[(i >> 6) + 1] - G.cap_off[i >> 6]) >> 6;
+    for (int k = 0; k < w; ++k) {
+      const int j = G.cap_col[base + (k << 6)];
+      res -= G.cap_val[base + (k << 6)] * (v[j] - vp[j]);
+    }
+  }
+  if (G.n_ind) {
+    const double* __restrict__ il = G.ind_i + (int64_t)ch.scen * G.n_ind;
+    for (int j = G.inc_off[i]; j < G.inc_off[i + 1]; ++j) {
+      const int e = G.inc_ind[j];
+      const int kk = (e > 0 ? e : -e) - 1;
+      res += (e > 0) ? il[kk] : -il[kk];  // current leaving through the near end
+    }
+  }
+  G.b[off + i] = res;
+}
+
+// max_i |b_i| / M_ii of each chunk's item into c.norm_bits[item].
+__global__ __launch_bounds__(kChunk) void k_graph_absmax_b(const GraphChunk* __restrict__ chunks, int n,
+                                                          const GridDesc* __restrict__ grids, Ctl c) {
+  __shared__ double wmax[kChunk / 64];
+  const int ci = xcd_tile(n);
+  if (ci < 0) return;
+  const GraphChunk ch = chunks[ci];
+  const GridDesc& G = grids[ch.grid];
+  double m = 0.0;
+  if ((int)threadIdx.x < ch.count) {
+    const int i = ch.slot0 + (int)threadIdx.x;
+    const double D = G.D64[i];
+    if (D > 0.0) m = fabs(G.b[(int64_t)ch.scen * G.nstore + i]) / D;
+  }
+  for (int o = 32; o > 0; o >>= 1) m = nan_max(m, __shfl_xor(m, o, 64));
+  if ((threadIdx.x & 63) == 0) wmax[threadIdx.x >> 6] = m;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double bm = wmax[0];
+    for (int k = 1; k < kChunk / 64; ++k) bm = nan_max(bm, wmax[k]);
+    raise_max(&c.norm_bits[ch.item], bm);
+  }
 }
 
 // One colour of a sweep on M d = r: d_i <- d_i + omega ((r_i + sum_j w_ij d_j) / M_ii - d_i).
@@ -150,9 +246,28 @@ __global__ void k_gather(const double* __restrict__ src, const int32_t* __restri
 
 }  // namespace
 
-hipError_t launch_graph_rhs(const GraphChunk* ch, int n, const GridDesc* grids, const Ctl& c, hipStream_t s) {
+hipError_t launch_graph_rhs(const GraphChunk* ch, int n, const GridDesc* grids, const Ctl& c, int save_prev,
+                            hipStream_t s) {
   if (n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_graph_rhs, dim3(xcd_blocks(n)), dim3(kChunk), 0, s, ch, n, grids, c);
+  hipLaunchKernelGGL(k_graph_rhs, dim3(xcd_blocks(n)), dim3(kChunk), 0, s, ch, n, grids, c, save_prev);
+  return hipGetLastError();
+}
+
+hipError_t launch_graph_rhs3(const GraphChunk* ch, int n, const GridDesc* grids, const Ctl& c, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_graph_rhs3, dim3(xcd_blocks(n)), dim3(kChunk), 0, s, ch, n, grids, c);
+  return hipGetLastError();
+}
+
+hipError_t launch_graph_kcl(const GraphChunk* ch, int n, const GridDesc* grids, const Ctl& c, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_graph_kcl, dim3(xcd_blocks(n)), dim3(kChunk), 0, s, ch, n, grids, c);
+  return hipGetLastError();
+}
+
+hipError_t launch_graph_absmax_b(const GraphChunk* ch, int n, const GridDesc* grids, const Ctl& c, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_graph_absmax_b, dim3(xcd_blocks(n)), dim3(kChunk), 0, s, ch, n, grids, c);
   return hipGetLastError();
 }
 

@@ -89,6 +89,16 @@ struct GridDesc {
   const int32_t* cap_off;
   const int32_t* cap_col;
   const double* cap_val;
+  // three-level recurrence (general graphs): v(t-h) per scenario in vprev[k & 1] while step
+  // k + 1 is opened (k = steps completed; the opening writes v(t) into vprev[(k + 1) & 1]), the
+  // conductance part of M (diagonal incl. resistors to supplies and ground, and w's resistor
+  // part per entry), and the constant injections of resistors (G0 v_s) and of inductors
+  // (h/L v_s) to supplies
+  double* vprev[2];
+  const double* g3diag;
+  const double* sl_g64;
+  const double* bres64;
+  const double* bl64;
   // coefficient words one sweep reads (for the activity accounting of the decision)
   int64_t coef_words;
 };
@@ -186,7 +196,9 @@ hipError_t launch_step_begin(const Ctl& c, int G, int only_item, double h, const
                              hipStream_t s);
 hipError_t launch_rhs(const Tile* tiles, int ntiles, int tile_rows, const GridDesc* grids,
                       const Ctl& c, hipStream_t s);
-hipError_t launch_sources(const SourceTable& src, const GridDesc* grids, const Ctl& c, hipStream_t s);
+// b -= sign * I(t_now + shift) at every source in the window of the step being opened
+hipError_t launch_sources(const SourceTable& src, const GridDesc* grids, const Ctl& c, double shift, double sign,
+                          hipStream_t s);
 // multi: the tiles are scenario blocks (Tile.pad consecutive scenarios of one grid)
 hipError_t launch_resid(bool fp32, bool multi, int nl, int tile_rows, const Tile* tiles, int ntiles,
                         const GridDesc* grids, const Ctl& c, int has_d, int din, hipStream_t s);
@@ -225,7 +237,15 @@ hipError_t launch_item_vec(bool fp32, const Tile* tiles, int ntiles, int tile_ro
 hipError_t launch_resume(const Ctl& c, hipStream_t s);
 // general graphs: right-hand side, one colour of a sweep (in place on d[0]), FP64 residual
 // with v <- v + d[0] and its scaled norm, and the gather of one scenario's voltages into node order
-hipError_t launch_graph_rhs(const GraphChunk* ch, int n, const GridDesc* grids, const Ctl& c, hipStream_t s);
+// save_prev: also copy v into vprev (the first step of the three-level recurrence)
+hipError_t launch_graph_rhs(const GraphChunk* ch, int n, const GridDesc* grids, const Ctl& c, int save_prev,
+                            hipStream_t s);
+// three-level right-hand side (eq. 11 / 14, sources added separately); then vprev <- v
+hipError_t launch_graph_rhs3(const GraphChunk* ch, int n, const GridDesc* grids, const Ctl& c, hipStream_t s);
+// b <- KCL residual at t_now without the sources (see pg_recurrence_drift); sources are added
+// by launch_sources(shift 0, sign -1); then max |b_i| / M_ii into c.norm_bits[item]
+hipError_t launch_graph_kcl(const GraphChunk* ch, int n, const GridDesc* grids, const Ctl& c, hipStream_t s);
+hipError_t launch_graph_absmax_b(const GraphChunk* ch, int n, const GridDesc* grids, const Ctl& c, hipStream_t s);
 hipError_t launch_graph_sweep(bool fp32, const GraphChunk* ch, int n, const GridDesc* grids, const Ctl& c,
                               int zero_in, double omega, hipStream_t s);
 hipError_t launch_graph_resid(bool fp32, const GraphChunk* ch, int n, const GridDesc* grids, const Ctl& c,

@@ -61,6 +61,7 @@ struct GridHost {
   DBuf v0, v1, b, r, d0, d1;
   DBuf ind_a_d, ind_b_d, ind_geq_d, ind_alpha_d, ind_i_d, inc_off_d, inc_ind_d, ind_vfar_d;
   DBuf slot_d, sl_off_d, sl_col_d, sl_w64_d, sl_ws_d, cap_off_d, cap_col_d, cap_val_d;
+  DBuf vprev0, vprev1, g3diag_d, sl_g64_d, bres_d, bl_d;  // three-level recurrence
   int sweep_fp32 = -1;                           // precision the sweep buffers were built for
 };
 
@@ -154,6 +155,7 @@ struct pg_ctx {
   int opening_tag = 0;                           // ... and the tag of its first decision
   bool maybe_stalled = false;                    // a speculative close may have stalled the device
   bool begun_next = false;                       // the last close also began the next step
+  bool prev_valid = false;                       // graph grids' vprev holds v(t-h) (three-level)
   std::vector<double> win_t0_host;               // bucket starts of the windowed sources (host copy)
   std::vector<ProfEvent> prof_live;
   std::vector<hipEvent_t> prof_pool;
@@ -481,6 +483,17 @@ pg_status build_graph_grid(pg_ctx* c, int gi) {
   }
   PG_TRY(alloc_sweep_bufs(c, G, f32));
   PG_TRY(upload_inductors(c, G, geq, alpha, &vfar));
+  if (c->opt.recurrence == PG_REC_THREE_LEVEL) {
+    // the conductance part of M and the two constant injections, for the three-level recurrence
+    std::vector<double> gd(ns, 0.0), br(ns, 0.0), bl(ns, 0.0);
+    for (int32_t i = 0; i < F.n; ++i) { gd[F.slot[i]] = F.g_diag[i]; br[F.slot[i]] = F.b_res[i]; }
+    for (size_t k = 0; k < F.ind_near.size(); ++k)
+      if (F.ind_far[k] < 0) bl[F.slot[F.ind_near[k]]] += h * F.ind_inv_l[k] * F.ind_far_v[k];
+    PG_TRY(upload(c, G.g3diag_d, gd)); PG_TRY(upload(c, G.bres_d, br)); PG_TRY(upload(c, G.bl_d, bl));
+    PG_TRY(upload(c, G.sl_g64_d, F.g));
+    PG_TRY(dalloc(c, G.vprev0, (size_t)ns * G.S * sizeof(double)));
+    PG_TRY(dalloc(c, G.vprev1, (size_t)ns * G.S * sizeof(double)));
+  }
   HIP_TRY(c, hipStreamSynchronize(c->stream));
   return PG_OK;
 }
@@ -518,6 +531,9 @@ GridDesc make_desc(pg_ctx* c, GridHost& H) {
     D.sl_ws = fp32_mode(c) ? H.sl_ws_d.p : H.sl_w64_d.p;
     D.cap_off = (const int32_t*)H.cap_off_d.p; D.cap_col = (const int32_t*)H.cap_col_d.p;
     D.cap_val = (const double*)H.cap_val_d.p;
+    D.vprev[0] = (double*)H.vprev0.p; D.vprev[1] = (double*)H.vprev1.p;
+    D.g3diag = (const double*)H.g3diag_d.p; D.sl_g64 = (const double*)H.sl_g64_d.p;
+    D.bres64 = (const double*)H.bres_d.p; D.bl64 = (const double*)H.bl_d.p;
     // invD, w (the column indices count as half a word in FP64 residuals)
     H.coef_words = H.nstore + (3 * H.form.nnz) / 2;
   } else {
@@ -542,11 +558,15 @@ pg_status sync_desc(pg_ctx* c, int gi) {
 
 pg_status prepare(pg_ctx* c) {
   if (c->grids.empty()) return set_err(c, PG_ERR_STATE, "no grid uploaded");
-  for (int g = 0; g < (int)c->grids.size(); ++g)
+  for (int g = 0; g < (int)c->grids.size(); ++g) {
     if (c->grids[g].kind && c->opt.ordering != PG_ORDER_RED_BLACK)
       return set_err(c, PG_ERR_UNSUPPORTED, "grid %d: general netlists are swept in colour order; the Jacobi "
                      "ordering is built for meshes only", g);
+    if (!c->grids[g].kind && c->opt.recurrence == PG_REC_THREE_LEVEL)
+      return set_err(c, PG_ERR_UNSUPPORTED, "grid %d: the three-level recurrence is built for general netlists", g);
+  }
   if (!c->dirty) return PG_OK;
+  c->prev_valid = false;
   drop_graphs(c);
   const int G = (int)c->grids.size();
   c->tile_rows = c->opt.tile_rows ? c->opt.tile_rows : 8;
@@ -863,6 +883,7 @@ pg_status launch_sweeps(pg_ctx* c, int nchk) {
 // Set the step clock (host mirror and device counter).
 pg_status set_step(pg_ctx* c, int64_t k) {
   c->step = k;
+  c->prev_valid = false;     // the three-level recurrence restarts with a two-level step
   c->begun_next = false;     // a clock change voids any step opened ahead
   c->opening_queued = false;
   c->step_host = (long long)k;
@@ -899,6 +920,7 @@ pg_status begin_step(pg_ctx* c, int only_item, bool begun = false, int64_t dev_s
   }
   Ctl k = c->ctl;
   hipError_t e;
+  const bool three = c->opt.recurrence == PG_REC_THREE_LEVEL && c->n_gchunks_all > 0;
   if (!begun) {
     ProfScope ps(c, 3, 0);
     e = launch_step_begin(k, G, only_item, c->opt.h, c->src_table, c->stream);
@@ -913,14 +935,23 @@ pg_status begin_step(pg_ctx* c, int only_item, bool begun = false, int64_t dev_s
     if (only_item >= 0) { goff = c->item_gchunk_off[only_item]; gcnt = c->item_gchunk_cnt[only_item]; }
     ProfScope ps(c, 2, 0, 0.0, (cnt > 0 ? 1 : 0) + (gcnt > 0 ? 1 : 0));
     e = launch_rhs(T + off, cnt, c->tile_rows, (const GridDesc*)c->grid_desc.p, k, c->stream);
-    if (e == hipSuccess) e = launch_graph_rhs(GC + goff, gcnt, (const GridDesc*)c->grid_desc.p, k, c->stream);
+    if (e == hipSuccess) {
+      if (three && c->prev_valid)
+        e = launch_graph_rhs3(GC + goff, gcnt, (const GridDesc*)c->grid_desc.p, k, c->stream);
+      else
+        e = launch_graph_rhs(GC + goff, gcnt, (const GridDesc*)c->grid_desc.p, k, three ? 1 : 0, c->stream);
+    }
     if (e != hipSuccess) return set_err(c, PG_ERR_DEVICE, "rhs launch: %s", hipGetErrorString(e));
   }
   if (dev_step < 0 || sources_may_act(c, dev_step)) {
     ProfScope ps(c, 2, 0);
-    e = launch_sources(c->src_table, (const GridDesc*)c->grid_desc.p, k, c->stream);
+    e = launch_sources(c->src_table, (const GridDesc*)c->grid_desc.p, k, 0.0, 1.0, c->stream);
+    // the three-level right-hand side takes the change of the loads: add back I(t - h)
+    if (e == hipSuccess && three && c->prev_valid)
+      e = launch_sources(c->src_table, (const GridDesc*)c->grid_desc.p, k, -c->opt.h, -1.0, c->stream);
     if (e != hipSuccess) return set_err(c, PG_ERR_DEVICE, "source launch: %s", hipGetErrorString(e));
   }
+  if (three) c->prev_valid = true;
   return PG_OK;
 }
 
@@ -1320,6 +1351,7 @@ pg_status loss_backward(pg_ctx* c, double tol_adj, double* dC, double* dgE, doub
 }
 
 pg_status fill_v(pg_ctx* c, GridHost& H, const double* v, int scen, int32_t vidx) {
+  c->prev_valid = false;
   // write the voltages of one scenario into its slice of the current buffer
   std::vector<double> buf((size_t)H.nstore, H.vdd);
   for (int64_t i = 0; i < H.n; ++i) buf[(size_t)H.storage(i)] = v ? v[i] : H.vdd;
@@ -1441,10 +1473,13 @@ void pg_destroy(pg_ctx* c) {
   for (auto& H : c->grids) {
     DBuf* bufs[] = {&H.gE64, &H.gN64, &H.gU64, &H.D64, &H.ch64, &H.bconst64, &H.gEs, &H.gNs, &H.gUs, &H.invDs,
                     &H.v0, &H.v1, &H.b, &H.r, &H.d0, &H.d1, &H.ind_a_d, &H.ind_b_d, &H.ind_geq_d,
-                    &H.ind_alpha_d, &H.ind_i_d, &H.inc_off_d, &H.inc_ind_d};
+                    &H.ind_alpha_d, &H.ind_i_d, &H.inc_off_d, &H.inc_ind_d, &H.ind_vfar_d,
+                    &H.slot_d, &H.sl_off_d, &H.sl_col_d, &H.sl_w64_d, &H.sl_ws_d, &H.cap_off_d, &H.cap_col_d,
+                    &H.cap_val_d, &H.vprev0, &H.vprev1, &H.g3diag_d, &H.sl_g64_d, &H.bres_d, &H.bl_d};
     for (DBuf* b : bufs) dfree(*b);
   }
   DBuf* bufs[] = {&c->grid_desc, &c->tiles_all, &c->tiles_sweep, &c->src_grid, &c->src_index, &c->src_off, &c->src_t, &c->src_i,
+                  &c->g_chunks_all, &c->g_chunks_sweep,
                   &c->ind_grid, &c->ind_local, &c->c_norm, &c->c_last, &c->c_active, &c->c_vidx, &c->c_sweeps,
                   &c->c_failed, &c->c_any, &c->c_stats64, &c->c_stats32, &c->c_statsd, &c->c_nodes, &c->c_item_grid,
                   &c->c_clock, &c->src_win_t0};
@@ -1470,11 +1505,10 @@ pg_status pg_set_options(pg_ctx* c, const pg_options* o) {
   char msg[256] = {0};
   pg_status st = pg_validate_options(o, msg, sizeof msg);
   if (st != PG_OK) return set_err(c, st, "%s", msg);
-  // h and precision change the coefficients, tile_rows and scen_block the tiles: rebuild;
-  // anything else only
-  // invalidates the captured graphs
+  // h and precision change the coefficients, tile_rows and scen_block the tiles, the recurrence
+  // the buffers of general netlists: rebuild; anything else only invalidates the captured graphs
   if (o->h != c->opt.h || o->precision != c->opt.precision || o->tile_rows != c->opt.tile_rows ||
-      o->scen_block != c->opt.scen_block)
+      o->scen_block != c->opt.scen_block || o->recurrence != c->opt.recurrence)
     c->dirty = true;
   drop_graphs(c);
   c->opt = *o;
@@ -1537,6 +1571,33 @@ pg_status pg_graph_info(const pg_ctx* c, int32_t grid, int32_t* n_nodes, int32_t
   if (n_slots) *n_slots = H.form.nslots;
   if (nnz) *nnz = H.form.nnz;
   if (n_inductors) *n_inductors = (int32_t)H.form.ind_near.size();
+  return PG_OK;
+}
+
+pg_status pg_recurrence_drift(pg_ctx* c, int32_t grid, int32_t scen, double* drift) {
+  PG_TRY(check_gs(c, grid, scen));
+  if (!drift) return set_err(c, PG_ERR_INVALID_ARG, "drift output is NULL");
+  GridHost& H = c->grids[grid];
+  if (!H.kind || c->opt.recurrence != PG_REC_THREE_LEVEL || !c->prev_valid || c->opening_queued || c->dirty)
+    return set_err(c, PG_ERR_STATE, "pg_recurrence_drift needs a general netlist stepped under the three-level "
+                   "recurrence");
+  HIP_TRY(c, hipSetDevice(c->device));
+  const int item = H.item0 + scen;
+  const GraphChunk* GC = (const GraphChunk*)c->g_chunks_all.p + c->item_gchunk_off[item];
+  const int n = c->item_gchunk_cnt[item];
+  const GridDesc* gd = (const GridDesc*)c->grid_desc.p;
+  unsigned long long* nb = (unsigned long long*)c->c_norm.p + item;
+  // the right-hand sides are rebuilt at the next step, so b serves as scratch here
+  HIP_TRY(c, hipMemsetAsync(nb, 0, sizeof *nb, c->stream));
+  hipError_t e = launch_graph_kcl(GC, n, gd, c->ctl, c->stream);
+  if (e == hipSuccess) e = launch_sources(c->src_table, gd, c->ctl, 0.0, -1.0, c->stream);
+  if (e == hipSuccess) e = launch_graph_absmax_b(GC, n, gd, c->ctl, c->stream);
+  if (e != hipSuccess) return set_err(c, PG_ERR_DEVICE, "drift launch: %s", hipGetErrorString(e));
+  unsigned long long bits = 0;
+  HIP_TRY(c, hipMemcpyAsync(&bits, nb, sizeof bits, hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(c, hipMemsetAsync(nb, 0, sizeof *nb, c->stream));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  std::memcpy(drift, &bits, sizeof bits);
   return PG_OK;
 }
 

@@ -98,7 +98,11 @@ pg_status pg_validate_options(const pg_options* o, char* msg, size_t len) {
     return fail(PG_ERR_INVALID_ARG, msg, len, "scen_block must be 0 (default) or 1..16");
   if (o->sweeps_per_launch < 0 || o->sweeps_per_launch > 2)
     return fail(PG_ERR_INVALID_ARG, msg, len, "sweeps_per_launch must be 0 (default), 1 or 2");
-  for (int i = 0; i < 3; ++i)
+  if (o->recurrence != PG_REC_TWO_LEVEL && o->recurrence != PG_REC_THREE_LEVEL)
+    return fail(PG_ERR_INVALID_ARG, msg, len, "unknown recurrence %d", o->recurrence);
+  if (o->recurrence == PG_REC_THREE_LEVEL && o->graphs)
+    return fail(PG_ERR_UNSUPPORTED, msg, len, "the three-level recurrence runs with plain launches (graphs = 0)");
+  for (int i = 0; i < 2; ++i)
     if (o->reserved[i] != 0) return fail(PG_ERR_INVALID_ARG, msg, len, "reserved option fields must be zero");
   return PG_OK;
 }

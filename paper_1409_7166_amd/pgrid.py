@@ -19,6 +19,8 @@ PG_PREC_FP64 = 0
 PG_PREC_FP32_REFINE = 1
 PG_ORDER_RED_BLACK = 0
 PG_ORDER_JACOBI = 1
+PG_REC_TWO_LEVEL = 0
+PG_REC_THREE_LEVEL = 1
 
 STATUS = {0: "PG_OK", -1: "PG_ERR_INVALID_ARG", -2: "PG_ERR_TOPOLOGY", -3: "PG_ERR_NOT_SPD",
           -4: "PG_ERR_NO_CONVERGENCE", -5: "PG_ERR_DEVICE", -6: "PG_ERR_OOM", -7: "PG_ERR_STATE",
@@ -37,7 +39,8 @@ class Options(C.Structure):
                 ("max_sweeps", C.c_int32), ("check_every", C.c_int32), ("precision", C.c_int32),
                 ("ordering", C.c_int32), ("tile_rows", C.c_int32), ("lookahead", C.c_int32),
                 ("graphs", C.c_int32), ("scen_block", C.c_int32),
-                ("sweeps_per_launch", C.c_int32), ("reserved", C.c_int32 * 3)]
+                ("sweeps_per_launch", C.c_int32), ("recurrence", C.c_int32),
+                ("reserved", C.c_int32 * 2)]
 
 
 class MeshStruct(C.Structure):
@@ -123,6 +126,7 @@ EXPORTS = {
     "pg_set_time": (C.c_int, [C.c_void_p, C.c_int64]),
     "pg_num_grids": (C.c_int, [C.c_void_p, C.POINTER(C.c_int32)]),
     "pg_grid_info": (C.c_int, [C.c_void_p, C.c_int32] + [C.POINTER(C.c_int32)] * 6),
+    "pg_recurrence_drift": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.POINTER(C.c_double)]),
     "pg_graph_info": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_int32),
                                 C.POINTER(C.c_int64), C.POINTER(C.c_int64), C.POINTER(C.c_int32)]),
     "pg_autotune": (C.c_int, [C.c_void_p, C.c_int32, C.c_char_p, C.POINTER(Options)]),
@@ -390,6 +394,12 @@ class Context:
                                             _ip(dims) if dims is not None else None, int(n_scen), C.byref(gid)))
         self.meshes.append(mesh if mesh is not None else self.graph_info(gid.value))
         return gid.value
+
+    def recurrence_drift(self, grid: int = 0, scen: int = 0) -> float:
+        """KCL residual of the current state with the tracked inductor currents (three-level mode)."""
+        d = C.c_double()
+        self._check(lib().pg_recurrence_drift(self._h, grid, scen, C.byref(d)))
+        return d.value
 
     def graph_info(self, grid: int) -> GraphShape:
         n, nc, ni = C.c_int32(), C.c_int32(), C.c_int32()

@@ -103,7 +103,11 @@ def test_options_validation():
     assert (o.h, o.tol, o.omega, o.check_every) == (10e-12, 1e-6, 1.0, 8)
     for k, v in (("omega", 2.0), ("omega", 0.0), ("h", 0.0), ("h", float("nan")), ("tol", -1.0),
                  ("max_sweeps", 0), ("check_every", 0), ("precision", 5), ("ordering", 3),
-                 ("tile_rows", 12), ("lookahead", 9)):
+                 ("tile_rows", 12), ("lookahead", 9), ("recurrence", 2)):
         bad = pg.default_options(**{k: v})
         st, msg = pg.validate_options(bad)
         assert st == -1, (k, v)
+    # the three-level recurrence runs with plain launches only
+    st, msg = pg.validate_options(pg.default_options(recurrence=pg.PG_REC_THREE_LEVEL, graphs=1))
+    assert st == -8 and "plain launches" in msg
+    assert pg.validate_options(pg.default_options(recurrence=pg.PG_REC_THREE_LEVEL))[0] == 0

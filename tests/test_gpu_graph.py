@@ -175,3 +175,49 @@ def test_graph_unsupported_calls_report_errors():
         with pytest.raises(pg.PgError) as e:
             ctx.step(1)
         assert e.value.status == -8
+
+
+@pytest.mark.parametrize("prec", [pg.PG_PREC_FP64, pg.PG_PREC_FP32_REFINE])
+def test_three_level_recurrence_matches_oracle(prec):
+    """Eq. 11 / eq. 14 on the GPU: step 1 is a backward-Euler step (it supplies v(t - h)), every
+    later step the three-level recurrence; against the oracle's recurrence seeded the same way,
+    and against the two-level path."""
+    from oracle import three_level_transient
+    net, scen = irregular_grid(side=24, nl=2, seed=27, rlc=True)
+    p = compressed(scen[0], start=0.3, width=0.6, peak=2.0)
+    steps = 60
+    circ = _circuit(net)
+    stp = BEStepper(circ, H)
+    v0 = np.full(net.n, net.source_v[0])
+    v1, _ = stp.step(v0, np.zeros(int(np.sum(net.kind == "L"))), currents_at(p, H))
+    V3 = three_level_transient(circ, p, H, steps, v0, v1)  # steps 2..K
+    V2, _ = _oracle(net, p, steps)
+    say(f"[gpu] three-level n={net.n} prec={prec}")
+    with _ctx(precision=prec, tol=1e-12, omega=1.8, check_every=16, max_sweeps=50000,
+              recurrence=pg.PG_REC_THREE_LEVEL) as ctx:
+        g = _upload(ctx, net, [p])
+        with pytest.raises(pg.PgError) as e:
+            ctx.recurrence_drift(g)
+        assert e.value.status == -7
+        ctx.step(1)
+        e1 = float(np.max(np.abs(ctx.read_voltages(g) - v1)))
+        worst = 0.0
+        for k in range(2, steps + 1):
+            ctx.step(1)
+            worst = max(worst, float(np.max(np.abs(ctx.read_voltages(g) - V3[k - 2]))))
+        drift = ctx.recurrence_drift(g)
+        vend = ctx.read_voltages(g)
+    gap = float(np.max(np.abs(V3[-1] - V2[-1])))
+    say(f"  step1 err={e1:.3e} max err={worst:.3e} V drift={drift:.3e} V oracle 3-level vs 2-level {gap:.3e}")
+    assert e1 <= PARITY_V and worst <= PARITY_V
+    assert np.max(np.abs(vend - V2[-1])) <= PARITY_V
+    assert 0.0 <= drift <= 1e-6
+
+
+def test_three_level_recurrence_needs_general_netlists():
+    w = small_multilayer(side=20, seed=28, nl=2, pad_every=8, steps=2)
+    with _ctx(recurrence=pg.PG_REC_THREE_LEVEL) as ctx:
+        ctx.upload_mesh(w.meshes[0], 1)
+        with pytest.raises(pg.PgError) as e:
+            ctx.step(1)
+        assert e.value.status == -8
