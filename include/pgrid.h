@@ -362,12 +362,15 @@ pg_status pg_update_mesh_values(pg_ctx* ctx, int32_t grid, const double* gE, con
                                 const double* C);
 
 /* Voltage-drop loss of a backward-Euler transient and its gradient by the reverse-time adjoint
- * (RC grids only, PG_ERR_UNSUPPORTED otherwise).  From the current state at step k0,
- * pg_loss_forward advances the whole context by nsteps steps (as pg_step) and returns
+ * (mesh grids, RC or with series R-L vias and pads; PG_ERR_UNSUPPORTED for general netlists).
+ * From the current state at step k0, pg_loss_forward advances the whole context by nsteps
+ * steps (as pg_step) and returns
  *     J = sum_{k=1..nsteps} sum_i softplus(Vdd - v_i(t_{k0+k}) - margin)^2,
- * keeping the state of (grid, scen) every ckpt_every steps (FP64, on the device).
- * pg_loss_backward then solves, for k = nsteps .. 1, the adjoint of the BE recurrence of eq. 2,
- *     M lambda_k = dJ/dv_k + (C/h) lambda_{k+1},  lambda_{nsteps+1} = 0,
+ * keeping the state of (grid, scen) (voltages and inductor currents) every ckpt_every steps
+ * (FP64, on the device).  pg_loss_backward then solves, for k = nsteps .. 1, the adjoint of the
+ * BE recurrence of eq. 2 / eq. 10 (companion form: i_k = alpha i_{k-1} + g_eq (A v_k - v_far)),
+ *     mu_k = alpha (mu_{k+1} - A lambda_{k+1}),
+ *     M lambda_k = dJ/dv_k + (C/h) lambda_{k+1} + g_eq A^T mu_k,  lambda_{nsteps+1} = mu_{nsteps+1} = 0,
  * with the same relaxation sweeps (M is symmetric, Lemma 1) until max |residual|/M_ii <= tol_adj
  * (in lambda's units), recomputing the forward states of each checkpoint segment, and writes
  *     dJ/dC_i  = sum_k lambda_k,i (v_{k-1,i} - v_k,i) / h             [nl][ny][nx]
@@ -375,17 +378,21 @@ pg_status pg_update_mesh_values(pg_ctx* ctx, int32_t grid, const double* gE, con
  *     dJ/dgN_e = the same over north segments                                 [nl][ny-1][nx]
  * to host memory (pg_loss_backward) or device memory (pg_loss_backward_dev).  Sources are held
  * fixed.  The context is left at step k0 + nsteps with the forward end state.
- * The same reverse pass also accumulates the gradients with respect to the via and pad
- * conductances, which pg_loss_branch_gradients copies to host arrays in the mesh's via and pad
- * order (n_vias and n_pads doubles; a via joins two layers like a segment, and a pad of
- * conductance g at node a adds g to M_aa and g Vdd to the right-hand side):
- *     dJ/dvia_g = -sum_k (lambda_a - lambda_b)(v_a - v_b),  dJ/dpad_g = sum_k lambda_a (Vdd - v_a).
- * PG_ERR_STATE before a completed pg_loss_backward(_dev). */
+ * The same reverse pass accumulates, for every via and pad (g in series with L, g_eq =
+ * h g / (g L + h), alpha = g L / (g L + h); a resistive branch has L = 0), the gradients with
+ * respect to g and L:
+ *     dJ/dtheta = sum_k (mu_k - A lambda_k) (dg_eq/dtheta (A v_k - v_far) + dalpha/dtheta i_{k-1}),
+ * which for a resistive branch is -sum_k (A lambda_k)(A v_k - v_far) (a via joins two layers like
+ * a segment, a pad joins its node to Vdd).  pg_loss_branch_gradients (g) and
+ * pg_loss_inductance_gradients (L; zero for resistive branches) copy them to host arrays in the
+ * mesh's via and pad order (n_vias and n_pads doubles).  PG_ERR_STATE before a completed
+ * pg_loss_backward(_dev). */
 pg_status pg_loss_forward(pg_ctx* ctx, int32_t grid, int32_t scen, int32_t nsteps, int32_t ckpt_every,
                           double margin, double* J);
 pg_status pg_loss_backward(pg_ctx* ctx, double tol_adj, double* dJ_dC, double* dJ_dgE, double* dJ_dgN);
 pg_status pg_loss_backward_dev(pg_ctx* ctx, double tol_adj, double* dJ_dC, double* dJ_dgE, double* dJ_dgN);
 pg_status pg_loss_branch_gradients(pg_ctx* ctx, double* dJ_dvia_g, double* dJ_dpad_g);
+pg_status pg_loss_inductance_gradients(pg_ctx* ctx, double* dJ_dvia_L, double* dJ_dpad_L);
 
 pg_status pg_get_stats(const pg_ctx* ctx, pg_stats* out);
 pg_status pg_reset_stats(pg_ctx* ctx);

@@ -1087,7 +1087,8 @@ __global__ void k_sum_into(const double* __restrict__ part, int n, double* __res
 // grid, whose current state buffer holds lambda_{k+1}.
 __global__ __launch_bounds__(kThreads) void k_adj_rhs(const Tile* __restrict__ tiles, int ntiles, int TY,
                                                      const GridDesc* __restrict__ grids, Ctl c,
-                                                     const double* __restrict__ vk, double margin) {
+                                                     const double* __restrict__ vk, double margin,
+                                                     const double* __restrict__ mu, int nind) {
   const int ti = blockIdx.x;
   if (ti >= ntiles) return;
   const Tile tl = tiles[ti];
@@ -1108,6 +1109,13 @@ __global__ __launch_bounds__(kThreads) void k_adj_rhs(const Tile* __restrict__ t
     if (x < nx) {
       const double u = G.vdd - vk[i] - margin;
       val = -2.0 * softplus(u) * sigmoid(u) + G.ch64[i] * lam_next[i];
+      // inductive branches: + g_eq A^T mu_k (near end +, far end -)
+      for (int j = nind ? G.inc_off[i] : 0, je = nind ? G.inc_off[i + 1] : 0; j < je; ++j) {
+        const int e = G.inc_ind[j];
+        const int kk = (e > 0 ? e : -e) - 1;
+        const double t = G.ind_geq[kk] * mu[kk];
+        val += (e > 0) ? t : -t;
+      }
     }
     rhs[i] = val;
   }
@@ -1143,25 +1151,62 @@ __global__ __launch_bounds__(kThreads) void k_adj_grad(const Tile* __restrict__ 
   }
 }
 
-// Gradients with respect to the pad and via conductances at one reverse step: a pad at slot a
-// adds g to M_aa and g Vdd to the right-hand side, so dJ/dg += lambda_a (Vdd - v_a); a via joins
-// slots a and a + P, so dJ/dg -= (lambda_a - lambda_b)(v_a - v_b).  One thread per branch.
-__global__ void k_adj_branch_grad(const GridDesc* __restrict__ grids, int grid, int item, int scen, Ctl c,
-                                  const double* __restrict__ vk, const int32_t* __restrict__ pad_slot, int n_pads,
-                                  const int32_t* __restrict__ via_slot, int n_vias, int64_t P,
-                                  double* __restrict__ dpad, double* __restrict__ dvia) {
-  const int j = blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= n_pads + n_vias) return;
+// The adjoint of the inductor-current recurrence i_k = alpha i_{k-1} + g_eq (A v_k - v_far):
+// mu_k = alpha (mu_{k+1} - A lambda_{k+1}), with lambda_{k+1} the item's current adjoint state.
+// One thread per inductive branch of the grid.
+__global__ void k_adj_mu(const GridDesc* __restrict__ grids, int grid, int item, int scen, Ctl c,
+                         double* __restrict__ mu, int nind) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= nind) return;
   const GridDesc& G = grids[grid];
   const double* __restrict__ lam = G.v[c.vidx[item]] + (int64_t)scen * G.nstore;
-  if (j < n_pads) {
-    const int a = pad_slot[j];
-    dpad[j] += lam[a] * (G.vdd - vk[a]);
-  } else {
-    const int q = j - n_pads;
-    const int64_t a = via_slot[q], b = a + P;
-    dvia[q] -= (lam[a] - lam[b]) * (vk[a] - vk[b]);
+  const int a = G.ind_a[k], b = G.ind_b[k];
+  const double el = lam[a] - (b >= 0 ? lam[b] : 0.0);
+  mu[k] = G.ind_alpha[k] * (mu[k] - el);
+}
+
+// Gradients with respect to the conductance g and the series inductance L of every via and pad
+// at one reverse step (branches: vias, then pads).  With e the branch's incidence (a via joins
+// slots a and a + P; a pad joins slot a to the supply), g_eq = h g / (g L + h) and
+// alpha = g L / (g L + h) (a plain resistor: g_eq = g, alpha = 0, mu = 0):
+//   dJ/dtheta += (mu_k - e.lambda_k) (dg_eq/dtheta (e.v_k - v_far) + dalpha/dtheta i_{k-1}).
+// For a resistor this is -(e.lambda_k)(e.v_k - v_far).  One thread per branch.
+__global__ void k_adj_branch_grad(const GridDesc* __restrict__ grids, int grid, int item, int scen, Ctl c,
+                                  const double* __restrict__ vk, const int32_t* __restrict__ br_slot,
+                                  const int32_t* __restrict__ br_ind, const double* __restrict__ br_g,
+                                  const double* __restrict__ br_L, int n_vias, int n_br, int64_t P, double h,
+                                  const double* __restrict__ mu, const double* __restrict__ iprev,
+                                  double* __restrict__ dg, double* __restrict__ dL) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= n_br) return;
+  const GridDesc& G = grids[grid];
+  const double* __restrict__ lam = G.v[c.vidx[item]] + (int64_t)scen * G.nstore;
+  const int64_t a = br_slot[j];
+  const bool via = j < n_vias;
+  const double el = lam[a] - (via ? lam[a + P] : 0.0);
+  const double ev = vk[a] - (via ? vk[a + P] : G.vdd);
+  const int k = br_ind[j];
+  if (k < 0) {
+    dg[j] -= el * ev;
+    return;
   }
+  const double g = br_g[j], L = br_L[j], den = g * L + h, den2 = den * den;
+  const double m = mu[k] - el, ip = iprev[k];
+  dg[j] += m * (h * h / den2 * ev + h * L / den2 * ip);
+  dL[j] += m * (-h * g * g / den2 * ev + g * h / den2 * ip);
+}
+
+// The inductor update of one scenario of one grid (the other items stand still while a segment
+// of the adjoint's forward pass is recomputed).
+__global__ void k_ind_update_item(const GridDesc* __restrict__ grids, int grid, int item, int scen, Ctl c, int nind) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= nind) return;
+  const GridDesc& G = grids[grid];
+  const double* __restrict__ v = G.v[c.vidx[item]] + (int64_t)scen * G.nstore;
+  const int a = G.ind_a[k], b = G.ind_b[k];
+  const double vb = b >= 0 ? v[b] : (G.ind_vfar ? G.ind_vfar[k] : G.vdd);
+  double* q = G.ind_i + (int64_t)scen * G.n_ind + k;
+  *q = G.ind_alpha[k] * *q + G.ind_geq[k] * (v[a] - vb);
 }
 
 // ------------------------------------------------------------------------------------
@@ -1330,18 +1375,34 @@ hipError_t launch_loss(const Tile* tiles, int ntiles, int tile_rows, const GridD
 }
 
 hipError_t launch_adj_rhs(const Tile* tiles, int ntiles, int tile_rows, const GridDesc* grids, const Ctl& c,
-                          const double* vk, double margin, hipStream_t s) {
+                          const double* vk, double margin, const double* mu, int nind, hipStream_t s) {
   if (ntiles <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_adj_rhs, dim3(ntiles), dim3(kThreads), 0, s, tiles, ntiles, tile_rows, grids, c, vk, margin);
+  hipLaunchKernelGGL(k_adj_rhs, dim3(ntiles), dim3(kThreads), 0, s, tiles, ntiles, tile_rows, grids, c, vk, margin,
+                     mu, nind);
   return hipGetLastError();
 }
 
-hipError_t launch_adj_branch_grad(const GridDesc* grids, int grid, int item, int scen, const Ctl& c,
-                                  const double* vk, const int32_t* pad_slot, int n_pads, const int32_t* via_slot,
-                                  int n_vias, int64_t P, double* dpad, double* dvia, hipStream_t s) {
-  if (n_pads + n_vias <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_adj_branch_grad, dim3((n_pads + n_vias + 255) / 256), dim3(256), 0, s, grids, grid, item,
-                     scen, c, vk, pad_slot, n_pads, via_slot, n_vias, P, dpad, dvia);
+hipError_t launch_adj_mu(const GridDesc* grids, int grid, int item, int scen, const Ctl& c, double* mu, int nind,
+                         hipStream_t s) {
+  if (nind <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_adj_mu, dim3((nind + 255) / 256), dim3(256), 0, s, grids, grid, item, scen, c, mu, nind);
+  return hipGetLastError();
+}
+
+hipError_t launch_adj_branch_grad(const GridDesc* grids, int grid, int item, int scen, const Ctl& c, const double* vk,
+                                  const int32_t* br_slot, const int32_t* br_ind, const double* br_g,
+                                  const double* br_L, int n_vias, int n_br, int64_t P, double h, const double* mu,
+                                  const double* iprev, double* dg, double* dL, hipStream_t s) {
+  if (n_br <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_adj_branch_grad, dim3((n_br + 255) / 256), dim3(256), 0, s, grids, grid, item, scen, c, vk,
+                     br_slot, br_ind, br_g, br_L, n_vias, n_br, P, h, mu, iprev, dg, dL);
+  return hipGetLastError();
+}
+
+hipError_t launch_ind_update_item(const GridDesc* grids, int grid, int item, int scen, const Ctl& c, int nind,
+                                  hipStream_t s) {
+  if (nind <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_ind_update_item, dim3((nind + 255) / 256), dim3(256), 0, s, grids, grid, item, scen, c, nind);
   return hipGetLastError();
 }
 

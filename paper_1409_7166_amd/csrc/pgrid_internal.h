@@ -219,15 +219,25 @@ hipError_t launch_step_end(const Ctl& c, int G, int count_step, int begin_next, 
 // adjoint of the softplus loss (tiles of one item; vk, vprev and grads are plain slices)
 hipError_t launch_loss(const Tile* tiles, int ntiles, int tile_rows, const GridDesc* grids, const Ctl& c,
                        double margin, double* part, double* total, hipStream_t s);
+// adjoint right-hand side dJ/dv_k + (C/h) lambda_{k+1} (+ g_eq A^T mu_k over the nind inductive
+// branches of the grid when nind > 0)
 hipError_t launch_adj_rhs(const Tile* tiles, int ntiles, int tile_rows, const GridDesc* grids, const Ctl& c,
-                          const double* vk, double margin, hipStream_t s);
+                          const double* vk, double margin, const double* mu, int nind, hipStream_t s);
+// mu_k = alpha (mu_{k+1} - A lambda_{k+1}) for the grid's inductive branches
+hipError_t launch_adj_mu(const GridDesc* grids, int grid, int item, int scen, const Ctl& c, double* mu, int nind,
+                         hipStream_t s);
+// the inductor update of one scenario of one grid
+hipError_t launch_ind_update_item(const GridDesc* grids, int grid, int item, int scen, const Ctl& c, int nind,
+                                  hipStream_t s);
 hipError_t launch_adj_grad(const Tile* tiles, int ntiles, int tile_rows, const GridDesc* grids, const Ctl& c,
                            const double* vk, const double* vprev, double inv_h, double* dC, double* dgE,
                            double* dgN, hipStream_t s);
-// pad and via conductance gradients of one reverse step (slots of the item's grid; P = layer stride)
-hipError_t launch_adj_branch_grad(const GridDesc* grids, int grid, int item, int scen, const Ctl& c,
-                                  const double* vk, const int32_t* pad_slot, int n_pads, const int32_t* via_slot,
-                                  int n_vias, int64_t P, double* dpad, double* dvia, hipStream_t s);
+// conductance and inductance gradients of every via and pad at one reverse step (branches: vias
+// then pads; br_ind: index among the grid's inductive branches or -1; P = layer stride)
+hipError_t launch_adj_branch_grad(const GridDesc* grids, int grid, int item, int scen, const Ctl& c, const double* vk,
+                                  const int32_t* br_slot, const int32_t* br_ind, const double* br_g,
+                                  const double* br_L, int n_vias, int n_br, int64_t P, double h, const double* mu,
+                                  const double* iprev, double* dg, double* dL, hipStream_t s);
 hipError_t launch_state_copy(const Tile* tiles, int ntiles, int tile_rows, const GridDesc* grids, const Ctl& c,
                              double* buf, int to_buf, hipStream_t s);
 // One item's vector utilities (op codes at k_item_vec); tiles are the item's tiles.

@@ -128,9 +128,14 @@ struct pg_ctx {
     int64_t k0 = 0;
     GridDesc view{};                             // the grid's descriptor with lambda as its state
     DBuf ckpts, vend, seg, lam0, lam1, arhs, dC, dgE, dgN, part, J, saved_vidx;
-    DBuf pad_slot, via_slot, dpad, dvia;         // pad and via conductance gradients
-    int n_pads = 0, n_vias = 0;
-    bool branch_ready = false;                   // dpad / dvia hold the last backward pass
+    // vias then pads: storage slot, index among the inductive branches (-1: resistive), g, L,
+    // and the gradients with respect to g and L
+    DBuf br_slot, br_ind, br_g, br_L, dbr_g, dbr_L;
+    int n_pads = 0, n_vias = 0, n_ind = 0;
+    // inductor currents of the item at the checkpoints, per step of a segment, at the end, and
+    // the adjoint mu of the current recurrence
+    DBuf ickpts, iseg, iend, mu;
+    bool branch_ready = false;                   // dbr_g / dbr_L hold the last backward pass
   } adj;
   // control block
   DBuf c_norm, c_last, c_active, c_vidx, c_sweeps, c_failed, c_any, c_stats64, c_stats32, c_statsd, c_nodes, c_item_grid;
@@ -1292,9 +1297,13 @@ pg_status loss_backward(pg_ctx* c, double tol_adj, double* dC, double* dgE, doub
   HIP_TRY(c, hipMemsetAsync(A.dC.p, 0, A.dC.bytes, c->stream));
   HIP_TRY(c, hipMemsetAsync(A.dgE.p, 0, A.dgE.bytes, c->stream));
   HIP_TRY(c, hipMemsetAsync(A.dgN.p, 0, A.dgN.bytes, c->stream));
-  if (A.dpad.bytes) HIP_TRY(c, hipMemsetAsync(A.dpad.p, 0, A.dpad.bytes, c->stream));
-  if (A.dvia.bytes) HIP_TRY(c, hipMemsetAsync(A.dvia.p, 0, A.dvia.bytes, c->stream));
+  if (A.dbr_g.bytes) HIP_TRY(c, hipMemsetAsync(A.dbr_g.p, 0, A.dbr_g.bytes, c->stream));
+  if (A.dbr_L.bytes) HIP_TRY(c, hipMemsetAsync(A.dbr_L.p, 0, A.dbr_L.bytes, c->stream));
+  if (A.mu.bytes) HIP_TRY(c, hipMemsetAsync(A.mu.p, 0, A.mu.bytes, c->stream));
   A.branch_ready = false;
+  const int ni = A.n_ind;
+  double* icur = (double*)H.ind_i_d.p + (size_t)A.scen * ni;  // the item's inductor currents
+  double* isg = (double*)A.iseg.p;
   HIP_TRY(c, hipMemsetAsync(A.saved_vidx.p, 0, sizeof(int32_t), c->stream));
   double* ck = (double*)A.ckpts.p;
   double* seg = (double*)A.seg.p;
@@ -1306,19 +1315,32 @@ pg_status loss_backward(pg_ctx* c, double tol_adj, double* dC, double* dgE, doub
     // recompute the forward states of the segment from its checkpoint (only this item steps)
     PG_TRY(state_copy(c, A.item, ck + (size_t)j * ns, 0));
     HIP_TRY(c, hipMemcpyAsync(seg, ck + (size_t)j * ns, ns * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+    if (ni) {
+      HIP_TRY(c, hipMemcpyAsync(icur, (const double*)A.ickpts.p + (size_t)j * ni, ni * sizeof(double),
+                                hipMemcpyDeviceToDevice, c->stream));
+      HIP_TRY(c, hipMemcpyAsync(isg, icur, ni * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+    }
     PG_TRY(set_step(c, A.k0 + kb));
     for (int q = 1; q <= len; ++q) {
       PG_TRY(begin_step(c, A.item));
       PG_TRY(solve_active(c, c->opt.tol));
       hipError_t e2 = launch_step_end(c->ctl, n_items(c), 2, 0, c->opt.h, c->src_table, c->stream);
+      if (e2 == hipSuccess) e2 = launch_ind_update_item(gd, A.grid, A.item, A.scen, c->ctl, ni, c->stream);
       if (e2 != hipSuccess) return set_err(c, PG_ERR_DEVICE, "step-end launch: %s", hipGetErrorString(e2));
       c->step++;
       PG_TRY(state_copy(c, A.item, seg + (size_t)q * ns, 1));
+      if (ni)
+        HIP_TRY(c, hipMemcpyAsync(isg + (size_t)q * ni, icur, ni * sizeof(double), hipMemcpyDeviceToDevice,
+                                  c->stream));
     }
     // reverse sweep over the segment on the adjoint view
     PG_TRY(use_view(c, true));
     for (int q = len; q >= 1; --q) {
-      hipError_t e = launch_adj_rhs(T, nt, c->tile_rows, gd, c->ctl, seg + (size_t)q * ns, A.margin, c->stream);
+      // mu_k from mu_{k+1} and lambda_{k+1} (the adjoint state before this step's solve)
+      hipError_t e = launch_adj_mu(gd, A.grid, A.item, A.scen, c->ctl, (double*)A.mu.p, ni, c->stream);
+      if (e == hipSuccess)
+        e = launch_adj_rhs(T, nt, c->tile_rows, gd, c->ctl, seg + (size_t)q * ns, A.margin, (const double*)A.mu.p,
+                           ni, c->stream);
       if (e != hipSuccess) return set_err(c, PG_ERR_DEVICE, "adjoint rhs: %s", hipGetErrorString(e));
       e = launch_step_begin(c->ctl, n_items(c), A.item, c->opt.h, c->src_table, c->stream);
       if (e != hipSuccess) return set_err(c, PG_ERR_DEVICE, "adjoint step: %s", hipGetErrorString(e));
@@ -1327,14 +1349,17 @@ pg_status loss_backward(pg_ctx* c, double tol_adj, double* dC, double* dgE, doub
                           1.0 / c->opt.h, (double*)A.dC.p, (double*)A.dgE.p, (double*)A.dgN.p, c->stream);
       if (e == hipSuccess)
         e = launch_adj_branch_grad(gd, A.grid, A.item, A.scen, c->ctl, seg + (size_t)q * ns,
-                                   (const int32_t*)A.pad_slot.p, A.n_pads, (const int32_t*)A.via_slot.p, A.n_vias,
-                                   (int64_t)H.X * H.ny, (double*)A.dpad.p, (double*)A.dvia.p, c->stream);
+                                   (const int32_t*)A.br_slot.p, (const int32_t*)A.br_ind.p, (const double*)A.br_g.p,
+                                   (const double*)A.br_L.p, A.n_vias, A.n_vias + A.n_pads, (int64_t)H.X * H.ny,
+                                   c->opt.h, (const double*)A.mu.p, isg + (size_t)(q - 1) * ni,
+                                   (double*)A.dbr_g.p, (double*)A.dbr_L.p, c->stream);
       if (e != hipSuccess) return set_err(c, PG_ERR_DEVICE, "adjoint gradient: %s", hipGetErrorString(e));
     }
     PG_TRY(use_view(c, false));
   }
   // back to the state the forward pass ended in
   PG_TRY(state_copy(c, A.item, (double*)A.vend.p, 0));
+  if (ni) HIP_TRY(c, hipMemcpyAsync(icur, A.iend.p, ni * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
   PG_TRY(set_step(c, A.k0 + A.K));
   HIP_TRY(c, hipStreamSynchronize(c->stream));
   int32_t failed = 0;
@@ -1486,7 +1511,8 @@ void pg_destroy(pg_ctx* c) {
   for (DBuf* b : bufs) dfree(*b);
   DBuf* abufs[] = {&c->adj.ckpts, &c->adj.vend, &c->adj.seg, &c->adj.lam0, &c->adj.lam1, &c->adj.arhs,
                    &c->adj.dC, &c->adj.dgE, &c->adj.dgN, &c->adj.part, &c->adj.J, &c->adj.saved_vidx,
-                   &c->adj.pad_slot, &c->adj.via_slot, &c->adj.dpad, &c->adj.dvia};
+                   &c->adj.br_slot, &c->adj.br_ind, &c->adj.br_g, &c->adj.br_L, &c->adj.dbr_g, &c->adj.dbr_L,
+                   &c->adj.ickpts, &c->adj.iseg, &c->adj.iend, &c->adj.mu};
   for (DBuf* b : abufs) dfree(*b);
   for (auto& e : c->prof_live) { (void)hipEventDestroy(e.a); (void)hipEventDestroy(e.b); }
   for (auto e : c->prof_pool) (void)hipEventDestroy(e);
@@ -2047,8 +2073,6 @@ pg_status pg_loss_forward(pg_ctx* c, int32_t grid, int32_t scen, int32_t nsteps,
   HIP_TRY(c, hipSetDevice(c->device));
   PG_TRY(prepare(c));
   GridHost& H = c->grids[grid];
-  if (!H.ind_a.empty())
-    return set_err(c, PG_ERR_UNSUPPORTED, "the loss adjoint covers RC grids (no inductive branches)");
   auto& A = c->adj;
   A.recorded = false;
   A.grid = grid; A.scen = scen; A.item = H.item0 + scen; A.K = nsteps; A.ckpt = std::min(ckpt_every, nsteps);
@@ -2064,13 +2088,30 @@ pg_status pg_loss_forward(pg_ctx* c, int32_t grid, int32_t scen, int32_t nsteps,
   PG_TRY(dalloc(c, A.dgE, ns * sizeof(double)));
   PG_TRY(dalloc(c, A.dgN, ns * sizeof(double)));
   {
-    std::vector<int32_t> ps, vs;
-    for (int32_t p : H.pad_node) ps.push_back((int32_t)H.storage(p));
-    for (int32_t v : H.via_node) vs.push_back((int32_t)H.storage(v));
-    A.n_pads = (int)ps.size();
-    A.n_vias = (int)vs.size();
-    PG_TRY(upload(c, A.pad_slot, ps)); PG_TRY(upload(c, A.via_slot, vs));
-    PG_TRY(dalloc(c, A.dpad, ps.size() * sizeof(double))); PG_TRY(dalloc(c, A.dvia, vs.size() * sizeof(double)));
+    // branches: vias then pads (the order of the inductive-branch index ind_branch)
+    const int nv = (int)H.via_node.size(), np = (int)H.pad_node.size();
+    std::vector<int32_t> slot, ind(nv + np, -1);
+    std::vector<double> g, L;
+    for (int k = 0; k < nv; ++k) {
+      slot.push_back((int32_t)H.storage(H.via_node[k])); g.push_back(H.via_g[k]);
+      L.push_back(H.via_L.empty() ? 0.0 : H.via_L[k]);
+    }
+    for (int k = 0; k < np; ++k) {
+      slot.push_back((int32_t)H.storage(H.pad_node[k])); g.push_back(H.pad_g[k]);
+      L.push_back(H.pad_L.empty() ? 0.0 : H.pad_L[k]);
+    }
+    for (size_t k = 0; k < H.ind_branch.size(); ++k) ind[H.ind_branch[k]] = (int32_t)k;
+    A.n_vias = nv;
+    A.n_pads = np;
+    A.n_ind = (int)H.ind_a.size();
+    PG_TRY(upload(c, A.br_slot, slot)); PG_TRY(upload(c, A.br_ind, ind));
+    PG_TRY(upload(c, A.br_g, g)); PG_TRY(upload(c, A.br_L, L));
+    PG_TRY(dalloc(c, A.dbr_g, (size_t)(nv + np) * sizeof(double)));
+    PG_TRY(dalloc(c, A.dbr_L, (size_t)(nv + np) * sizeof(double)));
+    PG_TRY(dalloc(c, A.ickpts, (size_t)A.nseg * A.n_ind * sizeof(double)));
+    PG_TRY(dalloc(c, A.iseg, (size_t)(A.ckpt + 1) * A.n_ind * sizeof(double)));
+    PG_TRY(dalloc(c, A.iend, (size_t)A.n_ind * sizeof(double)));
+    PG_TRY(dalloc(c, A.mu, (size_t)A.n_ind * sizeof(double)));
     A.branch_ready = false;
   }
   PG_TRY(dalloc(c, A.part, (size_t)std::max(1, c->item_tile_cnt[A.item]) * sizeof(double)));
@@ -2085,16 +2126,28 @@ pg_status pg_loss_forward(pg_ctx* c, int32_t grid, int32_t scen, int32_t nsteps,
   const Tile* T = (const Tile*)c->tiles_all.p + c->item_tile_off[A.item];
   const int nt = c->item_tile_cnt[A.item];
   double* ck = (double*)A.ckpts.p;
+  // the item's inductor currents travel with its voltages at every checkpoint
+  const int ni = A.n_ind;
+  const double* icur = (const double*)H.ind_i_d.p + (size_t)scen * ni;
+  auto save_i = [&](void* dst) -> pg_status {
+    if (ni) HIP_TRY(c, hipMemcpyAsync(dst, icur, ni * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+    return PG_OK;
+  };
   PG_TRY(state_copy(c, A.item, ck, 1));
+  PG_TRY(save_i(A.ickpts.p));
   const auto t0 = std::chrono::steady_clock::now();
   for (int k = 1; k <= nsteps; ++k) {
     PG_TRY(one_step(c));
     hipError_t e = launch_loss(T, nt, c->tile_rows, (const GridDesc*)c->grid_desc.p, c->ctl, margin,
                                (double*)A.part.p, (double*)A.J.p, c->stream);
     if (e != hipSuccess) return set_err(c, PG_ERR_DEVICE, "loss launch: %s", hipGetErrorString(e));
-    if (k % A.ckpt == 0 && k / A.ckpt < A.nseg) PG_TRY(state_copy(c, A.item, ck + (size_t)(k / A.ckpt) * ns, 1));
+    if (k % A.ckpt == 0 && k / A.ckpt < A.nseg) {
+      PG_TRY(state_copy(c, A.item, ck + (size_t)(k / A.ckpt) * ns, 1));
+      PG_TRY(save_i((double*)A.ickpts.p + (size_t)(k / A.ckpt) * ni));
+    }
   }
   PG_TRY(state_copy(c, A.item, (double*)A.vend.p, 1));
+  PG_TRY(save_i(A.iend.p));
   HIP_TRY(c, hipStreamSynchronize(c->stream));
   c->seconds += std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
   if (J) HIP_TRY(c, hipMemcpy(J, A.J.p, sizeof(double), hipMemcpyDeviceToHost));
@@ -2116,18 +2169,25 @@ pg_status pg_loss_backward_dev(pg_ctx* c, double tol_adj, double* dJ_dC, double*
   return loss_backward(c, tol_adj, dJ_dC, dJ_dgE, dJ_dgN, true);
 }
 
-pg_status pg_loss_branch_gradients(pg_ctx* c, double* dJ_dvia_g, double* dJ_dpad_g) {
+static pg_status loss_branch_outputs(pg_ctx* c, const DBuf& src, double* dvia, double* dpad, const char* what) {
   if (!c) return PG_ERR_INVALID_ARG;
   auto& A = c->adj;
-  if (!A.recorded || !A.branch_ready)
-    return set_err(c, PG_ERR_STATE, "pg_loss_branch_gradients needs a completed pg_loss_backward");
-  if ((A.n_vias && !dJ_dvia_g) || (A.n_pads && !dJ_dpad_g))
-    return set_err(c, PG_ERR_INVALID_ARG, "gradient outputs are NULL");
+  if (!A.recorded || !A.branch_ready) return set_err(c, PG_ERR_STATE, "%s needs a completed pg_loss_backward", what);
+  if ((A.n_vias && !dvia) || (A.n_pads && !dpad)) return set_err(c, PG_ERR_INVALID_ARG, "gradient outputs are NULL");
   HIP_TRY(c, hipSetDevice(c->device));
   HIP_TRY(c, hipStreamSynchronize(c->stream));
-  if (A.n_vias) HIP_TRY(c, hipMemcpy(dJ_dvia_g, A.dvia.p, A.n_vias * sizeof(double), hipMemcpyDeviceToHost));
-  if (A.n_pads) HIP_TRY(c, hipMemcpy(dJ_dpad_g, A.dpad.p, A.n_pads * sizeof(double), hipMemcpyDeviceToHost));
+  if (A.n_vias) HIP_TRY(c, hipMemcpy(dvia, src.p, A.n_vias * sizeof(double), hipMemcpyDeviceToHost));
+  if (A.n_pads)
+    HIP_TRY(c, hipMemcpy(dpad, (const double*)src.p + A.n_vias, A.n_pads * sizeof(double), hipMemcpyDeviceToHost));
   return PG_OK;
+}
+
+pg_status pg_loss_branch_gradients(pg_ctx* c, double* dJ_dvia_g, double* dJ_dpad_g) {
+  return loss_branch_outputs(c, c ? c->adj.dbr_g : DBuf{}, dJ_dvia_g, dJ_dpad_g, "pg_loss_branch_gradients");
+}
+
+pg_status pg_loss_inductance_gradients(pg_ctx* c, double* dJ_dvia_L, double* dJ_dpad_L) {
+  return loss_branch_outputs(c, c ? c->adj.dbr_L : DBuf{}, dJ_dvia_L, dJ_dpad_L, "pg_loss_inductance_gradients");
 }
 
 pg_status pg_update_mesh_values(pg_ctx* c, int32_t grid, const double* gE, const double* gN, const double* C) {

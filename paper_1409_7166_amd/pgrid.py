@@ -141,6 +141,7 @@ EXPORTS = {
                                    C.POINTER(C.c_double)]),
     "pg_loss_backward_dev": (C.c_int, [C.c_void_p, C.c_double, C.c_void_p, C.c_void_p, C.c_void_p]),
     "pg_loss_branch_gradients": (C.c_int, [C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_double)]),
+    "pg_loss_inductance_gradients": (C.c_int, [C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_double)]),
     "pg_get_stats": (C.c_int, [C.c_void_p, C.POINTER(Stats)]),
     "pg_reset_stats": (C.c_int, [C.c_void_p]),
     "pg_profile": (C.c_int, [C.c_void_p, C.c_int32]),
@@ -520,12 +521,20 @@ class Context:
         self._check(lib().pg_loss_backward(self._h, float(tol_adj), _dp(dC), _dp(dE), _dp(dN)))
         return dC, dE, dN
 
+    def _branch_out(self, fn, grid):
+        m = self.meshes[grid]
+        nv, npd = np.asarray(m.via_node).size, np.asarray(m.pad_node).size
+        dv, dp = np.zeros(max(1, nv)), np.zeros(max(1, npd))
+        self._check(fn(self._h, _dp(dv), _dp(dp)))
+        return dv[:nv], dp[:npd]
+
     def loss_branch_gradients(self, grid: int = 0):
         """(dJ/dvia_g [n_vias], dJ/dpad_g [n_pads]) of the last loss_backward."""
-        m = self.meshes[grid]
-        dv, dp = np.zeros(max(1, np.asarray(m.via_node).size)), np.zeros(max(1, np.asarray(m.pad_node).size))
-        self._check(lib().pg_loss_branch_gradients(self._h, _dp(dv), _dp(dp)))
-        return dv[: np.asarray(m.via_node).size], dp[: np.asarray(m.pad_node).size]
+        return self._branch_out(lib().pg_loss_branch_gradients, grid)
+
+    def loss_inductance_gradients(self, grid: int = 0):
+        """(dJ/dvia_L [n_vias], dJ/dpad_L [n_pads]) of the last loss_backward (0 for resistive branches)."""
+        return self._branch_out(lib().pg_loss_inductance_gradients, grid)
 
     def loss_backward_dev(self, tol_adj: float, dC, dE, dN):
         """Gradients into float64 device tensors (contiguous, shapes as in loss_backward)."""

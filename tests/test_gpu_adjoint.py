@@ -122,3 +122,59 @@ def test_via_and_pad_gradients_match_oracle():
     say(f"  rel err C/gE/gN/via/pad = {errs}; |dpad| max {np.max(np.abs(rp)):.3e}")
     assert dv.size == mesh.via_node.size and dp.size == mesh.pad_node.size
     assert max(errs) <= REL and np.max(np.abs(rp)) > 0
+
+
+def _J_oracle(mesh, p, h, K, margin):
+    from oracle import be_transient, mesh_to_circuit
+    from oracle.adjoint import softplus_loss
+    circ, info = mesh_to_circuit(mesh, p)
+    V, _ = be_transient(circ, info, p, h, K)
+    return softplus_loss(V[:, : mesh.n], mesh.vdd, margin)
+
+
+def test_rlc_adjoint_matches_central_differences_of_the_oracle():
+    """Series R-L vias and pads (half the vias resistive): every gradient the reverse pass gives
+    (C, gE, gN sampled; g and L of every via and pad) against central differences of the
+    oracle's own backward-Euler transient (assembled with an internal node per series R-L)."""
+    w = small_multilayer(side=12, seed=64, nl=2, layer_g=(1.0, 4.0), via_every=3, pad_every=4, fraction=0.5,
+                         h=1e-12, steps=30, via_L_range=(1e-12, 10e-12), pad_L_range=(1e-12, 10e-12))
+    mesh = w.meshes[0]
+    mesh.via_L[::2] = 0.0
+    p = compressed(w.pulses[0][0], start=0.02, width=0.2, peak=30.0)
+    w.pulses[0][0] = p
+    K, ck, margin = 30, 7, 0.05
+    say("[gpu] RLC adjoint 2x12x12")
+    with gpu_context(w, precision=pg.PG_PREC_FP64, tol=1e-13, omega=1.5, max_sweeps=100000) as ctx:
+        J = ctx.loss_forward(0, 0, K, ck, margin)
+        dC, dE, dN = ctx.loss_backward(1e-13)
+        dvg, dpg = ctx.loss_branch_gradients(0)
+        dvL, dpL = ctx.loss_inductance_gradients(0)
+        assert ctx.time_index() == K
+    Jr = _J_oracle(mesh, p, w.h, K, margin)
+    assert abs(J - Jr) <= 1e-9 * abs(Jr)
+    rng = np.random.default_rng(1)
+    worst = {}
+    for name, arr, grad, idx in (
+            ("C", mesh.C.reshape(-1), dC.reshape(-1), rng.choice(np.nonzero(mesh.C.reshape(-1) > 0)[0], 6,
+                                                                   replace=False)),
+            ("gE", mesh.gE.reshape(-1), dE.reshape(-1), rng.choice(mesh.gE.size, 4, replace=False)),
+            ("gN", mesh.gN.reshape(-1), dN.reshape(-1), rng.choice(mesh.gN.size, 4, replace=False)),
+            ("via_g", mesh.via_g, dvg, np.arange(mesh.via_g.size)),
+            ("via_L", mesh.via_L, dvL, np.nonzero(mesh.via_L > 0)[0]),
+            ("pad_g", mesh.pad_g, dpg, np.arange(mesh.pad_g.size)),
+            ("pad_L", mesh.pad_L, dpL, np.arange(mesh.pad_L.size))):
+        fd = np.zeros(len(idx))
+        for t, j in enumerate(idx):
+            # J ~ 4e3, so a relative step of 1e-5 leaves ~1e-8 of rounding noise in a difference
+            # quotient; 1e-4 keeps both the noise and the O(step^2) truncation below 1e-6 relative
+            base = arr[j]
+            step = 1e-4 * base
+            arr[j] = base + step; Jp = _J_oracle(mesh, p, w.h, K, margin)
+            arr[j] = base - step; Jm = _J_oracle(mesh, p, w.h, K, margin)
+            arr[j] = base
+            fd[t] = (Jp - Jm) / (2 * step)
+        worst[name] = _close(grad[idx], fd)
+        assert np.max(np.abs(fd)) > 0, name
+    assert np.all(dvL[mesh.via_L == 0] == 0.0)
+    say(f"  J={J:.10e} ref={Jr:.10e}; rel err vs central differences {worst}")
+    assert max(worst.values()) <= REL
