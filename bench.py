@@ -42,6 +42,8 @@ def parse():
     ap.add_argument("--scen-block", type=int, default=0,
                     help="scenarios per sweep workgroup on multi-scenario grids (0: library default)")
     ap.add_argument("--lookahead", type=int, default=1)
+    ap.add_argument("--recurrence", type=int, default=0,
+                    help="0: two-level backward Euler; 1: the three-level recurrence (general netlists)")
     ap.add_argument("--graphs", type=int, default=-1, help="replay each step from captured HIP graphs (1) or "
                                                            "launch kernels one by one (0); -1: the workload's "
                                                            "tuned choice")
@@ -113,7 +115,7 @@ def sweep_kernel_name(w, sweeps_per_launch):
 
 
 def run_gpu(w, steps, warmup, precision, tol, omega, check_every, tile_rows, lookahead, profile_every, graphs,
-            scen_block=0, sweeps_per_launch=0):
+            scen_block=0, sweeps_per_launch=0, recurrence=0):
     import torch
     import paper_1409_7166_amd as pg
 
@@ -123,7 +125,7 @@ def run_gpu(w, steps, warmup, precision, tol, omega, check_every, tile_rows, loo
     ctx.set_options(h=w.h, tol=tol, omega=omega, check_every=check_every, max_sweeps=100000,
                     precision=pg.PG_PREC_FP32_REFINE if precision == "fp32+ref" else pg.PG_PREC_FP64,
                     tile_rows=tile_rows, lookahead=lookahead, graphs=graphs, scen_block=scen_block,
-                    sweeps_per_launch=sweeps_per_launch)
+                    sweeps_per_launch=sweeps_per_launch, recurrence=recurrence)
     grids = w.nets if is_netlist(w) else w.meshes
     for g, (grid, scen) in enumerate(zip(grids, w.pulses)):
         if is_netlist(w):
@@ -251,7 +253,7 @@ def measure(name, prec, tol, steps, args):
     block = args.scen_block or tuned.get("scen_block", 0)
     elapsed, st, kt = run_gpu(w, steps, args.warmup, prec, tol, omega, chk, rows,
                               args.lookahead, args.profile_every, graphs, block,
-                              args.sweeps_per_launch)
+                              args.sweeps_per_launch, args.recurrence)
     nodes = w.nodes
     value = st["node_updates"] / elapsed
     spl = st["options"]["sweeps_per_launch"] or 1
@@ -277,6 +279,7 @@ def measure(name, prec, tol, steps, args):
                    "sweeps_per_launch": spl,
                    "scen_block": (st["options"]["scen_block"] or 8) if any(len(p) > 1 for p in w.pulses)
                    else None,
+                   "recurrence": "three-level" if args.recurrence else "two-level",
                    "sweeps_per_step": st["sweeps"] / max(1, st["steps"]),
                    "max_step_sweeps": st["max_step_sweeps"], "max_final_residual_V": st["max_final_residual"],
                    "node_steps_per_s": nodes * steps / elapsed},
