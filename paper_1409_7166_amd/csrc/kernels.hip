@@ -398,7 +398,7 @@ __global__ void k_sources(SourceTable src, const GridDesc* __restrict__ grids, C
 // ------------------------------------------------------------------------------------
 template <typename T, int NL, int TY>
 __device__ void resid_tile(const Tile* __restrict__ tiles, int ti, const GridDesc* __restrict__ grids,
-                           const Ctl& c, int has_d, int din) {
+                           const Ctl& c, int has_d, int din, int fuse_rhs) {
   constexpr int NP = kTileX / 2, HP = NP + 2, HY = TY + 2;
   constexpr int NT = 64 * TY;
   __shared__ double2 sv[NL][HY][HP];
@@ -446,7 +446,32 @@ __device__ void resid_tile(const Tile* __restrict__ tiles, int ti, const GridDes
 #pragma unroll
     for (int l = 0; l < NL; ++l) {
       const int64_t i = l * P + (int64_t)y * X + x;
-      const double2 b2 = ld2(bvec, i), D2 = ld2(G.D64, i), ge = ld2(G.gE64, i), gn = ld2(G.gN64, i);
+      const double2 own = sv[l][hy][hp];
+      double2 b2;
+      if (fuse_rhs) {
+        // the step's right-hand side formed here (the first pass of a step whose sources are all
+        // zero): b = (C/h) v + G0 Vdd - inductor history, exactly as k_rhs forms it
+        const double2 ch2 = ld2(G.ch64, i), bc2 = ld2(G.bconst64, i);
+        b2.x = ch2.x * own.x + bc2.x;
+        b2.y = ch2.y * own.y + bc2.y;
+        if (G.n_ind) {
+          const double* __restrict__ il = G.ind_i + (int64_t)tl.scen * G.n_ind;
+          for (int q = 0; q < 2; ++q) {
+            double bb = q ? b2.y : b2.x;
+            for (int j = G.inc_off[i + q]; j < G.inc_off[i + q + 1]; ++j) {
+              const int e = G.inc_ind[j];
+              const int kk = (e > 0 ? e : -e) - 1;
+              const double term = G.ind_alpha[kk] * il[kk];
+              bb += (e > 0) ? -term : term;
+            }
+            if (q) b2.y = bb; else b2.x = bb;
+          }
+        }
+        st2(G.b + off, i, b2);
+      } else {
+        b2 = ld2(bvec, i);
+      }
+      const double2 D2 = ld2(G.D64, i), ge = ld2(G.gE64, i), gn = ld2(G.gN64, i);
       const double2 gs = y > 0 ? ld2(G.gN64, i - X) : make_double2(0.0, 0.0);
       const double gw = x > 0 ? G.gE64[i - 1] : 0.0;
       double2 gu = make_double2(0.0, 0.0), gd = make_double2(0.0, 0.0);
@@ -454,7 +479,7 @@ __device__ void resid_tile(const Tile* __restrict__ tiles, int ti, const GridDes
         if (l < NL - 1) gu = ld2(G.gU64, i);
         if (l > 0) gd = ld2(G.gU64, i - P);
       }
-      const double2 own = sv[l][hy][hp], eastp = sv[l][hy][hp + 1], westp = sv[l][hy][hp - 1];
+      const double2 eastp = sv[l][hy][hp + 1], westp = sv[l][hy][hp - 1];
       const double2 nth = sv[l][hy + 1][hp], sth = sv[l][hy - 1][hp];
       double2 up = make_double2(0.0, 0.0), dn = make_double2(0.0, 0.0);
       if (NL > 1) {
@@ -490,9 +515,9 @@ __device__ void resid_tile(const Tile* __restrict__ tiles, int ti, const GridDes
 template <typename T, int NL, int TY>
 __global__ __launch_bounds__(64 * TY) void k_resid(const Tile* __restrict__ tiles, int ntiles,
                                                   const GridDesc* __restrict__ grids, Ctl c,
-                                                  int has_d, int din) {
+                                                  int has_d, int din, int fuse_rhs) {
   const int ti = xcd_tile(ntiles);
-  if (!*c.stall && ti >= 0) resid_tile<T, NL, TY>(tiles, ti, grids, c, has_d, din);
+  if (!*c.stall && ti >= 0) resid_tile<T, NL, TY>(tiles, ti, grids, c, has_d, din, fuse_rhs);
 }
 
 // ------------------------------------------------------------------------------------
@@ -1417,13 +1442,13 @@ hipError_t launch_adj_grad(const Tile* tiles, int ntiles, int tile_rows, const G
 
 template <typename T, int NL, int TY>
 static void resid_t(bool multi, const Tile* tiles, int ntiles, const GridDesc* grids, const Ctl& c, int has_d,
-                    int din, hipStream_t s) {
+                    int din, int fuse_rhs, hipStream_t s) {
   if (multi)
     hipLaunchKernelGGL((k_resid_multi<T, NL, TY>), dim3(xcd_blocks(ntiles)), dim3(64 * TY), 0, s, tiles,
                        ntiles, grids, c, has_d, din);
   else
     hipLaunchKernelGGL((k_resid<T, NL, TY>), dim3(xcd_blocks(ntiles)), dim3(64 * TY), 0, s, tiles,
-                       ntiles, grids, c, has_d, din);
+                       ntiles, grids, c, has_d, din, fuse_rhs);
 }
 
 template <typename T, int NL, int TY>
@@ -1465,12 +1490,12 @@ static void sweep2_t(const Tile* tiles, int ntiles, const GridDesc* grids, const
   }
 
 hipError_t launch_resid(bool fp32, bool multi, int nl, int tile_rows, const Tile* tiles, int ntiles,
-                        const GridDesc* grids, const Ctl& c, int has_d, int din, hipStream_t s) {
+                        const GridDesc* grids, const Ctl& c, int has_d, int din, int fuse_rhs, hipStream_t s) {
   if (ntiles <= 0) return hipSuccess;
   if (fp32) {
-    PG_DISPATCH_NL_TY(resid_t, float, multi, tiles, ntiles, grids, c, has_d, din, s)
+    PG_DISPATCH_NL_TY(resid_t, float, multi, tiles, ntiles, grids, c, has_d, din, fuse_rhs, s)
   } else {
-    PG_DISPATCH_NL_TY(resid_t, double, multi, tiles, ntiles, grids, c, has_d, din, s)
+    PG_DISPATCH_NL_TY(resid_t, double, multi, tiles, ntiles, grids, c, has_d, din, fuse_rhs, s)
   }
   return hipGetLastError();
 }

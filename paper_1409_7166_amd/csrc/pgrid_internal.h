@@ -199,9 +199,11 @@ hipError_t launch_rhs(const Tile* tiles, int ntiles, int tile_rows, const GridDe
 // b -= sign * I(t_now + shift) at every source in the window of the step being opened
 hipError_t launch_sources(const SourceTable& src, const GridDesc* grids, const Ctl& c, double shift, double sign,
                           hipStream_t s);
-// multi: the tiles are scenario blocks (Tile.pad consecutive scenarios of one grid)
+// multi: the tiles are scenario blocks (Tile.pad consecutive scenarios of one grid).
+// fuse_rhs (single-scenario tiles, has_d = 0): also form and store the step's right-hand side,
+// as k_rhs would, for a step whose sources are all zero (no k_rhs or k_sources launch before it)
 hipError_t launch_resid(bool fp32, bool multi, int nl, int tile_rows, const Tile* tiles, int ntiles,
-                        const GridDesc* grids, const Ctl& c, int has_d, int din, hipStream_t s);
+                        const GridDesc* grids, const Ctl& c, int has_d, int din, int fuse_rhs, hipStream_t s);
 // The decision after a residual pass, with sequence number q = (*flag_seq)++, writes
 // ((q & 0x1fffffff) << 2) | (skipped << 1) | (any item still active) to slot q % nslots of
 // c.any_active (host-visible memory), after the slot's accounting words; `skipped` marks a

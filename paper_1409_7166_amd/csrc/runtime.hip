@@ -100,9 +100,10 @@ struct pg_ctx {
     const double e = opt.precision == PG_PREC_FP32_REFINE ? 4.0 : 8.0;
     return e * ((2.0 + 3.0 * (L - 1)) * an + (double)L * coef);
   }
-  double resid_bytes(int64_t an, int64_t coef, bool has_d) const {
+  double resid_bytes(int64_t an, int64_t coef, bool has_d, bool fused_rhs = false) const {
     const double e = opt.precision == PG_PREC_FP32_REFINE ? 4.0 : 8.0;
-    return (16.0 + e + (has_d ? e + 8.0 : 0.0)) * an + 8.0 * coef;
+    // a pass that forms the right-hand side reads C/h and G0 Vdd and writes b instead of reading it
+    return (16.0 + e + (has_d ? e + 8.0 : 0.0) + (fused_rhs ? 16.0 : 0.0)) * an + 8.0 * coef;
   }
   std::vector<Group> tile_groups;                 // sweep/residual tiles by (layers, block): [off, off+count) of tiles_sweep
   int ntiles_all = 0;
@@ -161,6 +162,7 @@ struct pg_ctx {
   bool maybe_stalled = false;                    // a speculative close may have stalled the device
   bool begun_next = false;                       // the last close also began the next step
   bool prev_valid = false;                       // graph grids' vprev holds v(t-h) (three-level)
+  bool fuse_rhs_next = false;                    // the next residual pass also forms the mesh RHS
   std::vector<double> win_t0_host;               // bucket starts of the windowed sources (host copy)
   std::vector<ProfEvent> prof_live;
   std::vector<hipEvent_t> prof_pool;
@@ -812,11 +814,13 @@ int next_tag(pg_ctx* c) { return (int)(c->flag_seq_host++ & kTagMask); }
 // pgrid_internal.h), whose tag is returned.
 pg_status launch_resid_all(pg_ctx* c, int has_d, int din, double tol = 0.0, int* tag = nullptr) {
   const Tile* T = (const Tile*)c->tiles_sweep.p;
-  ProfScope ps(c, 1, c->begin_nodes, c->resid_bytes(c->begin_nodes, c->begin_coef, has_d != 0),
+  const int fuse = (!has_d && c->fuse_rhs_next) ? 1 : 0;
+  c->fuse_rhs_next = false;
+  ProfScope ps(c, 1, c->begin_nodes, c->resid_bytes(c->begin_nodes, c->begin_coef, has_d != 0, fuse != 0),
                (int)c->tile_groups.size() + (c->n_gchunks_all ? 1 : 0) + (tag ? 1 : 0));
   for (auto& grp : c->tile_groups) {
     hipError_t e = launch_resid(fp32_mode(c), grp.multi, grp.nl, c->tile_rows, T + grp.off, grp.count,
-                                (const GridDesc*)c->grid_desc.p, c->ctl, has_d, din, c->stream);
+                                (const GridDesc*)c->grid_desc.p, c->ctl, has_d, din, fuse, c->stream);
     if (e != hipSuccess) return set_err(c, PG_ERR_DEVICE, "residual launch: %s", hipGetErrorString(e));
   }
   if (c->n_gchunks_all) {
@@ -931,13 +935,20 @@ pg_status begin_step(pg_ctx* c, int only_item, bool begun = false, int64_t dev_s
     e = launch_step_begin(k, G, only_item, c->opt.h, c->src_table, c->stream);
     if (e != hipSuccess) return set_err(c, PG_ERR_DEVICE, "step launch: %s", hipGetErrorString(e));
   }
-  {
-    const Tile* T = (const Tile*)c->tiles_all.p;
-    int off = 0, cnt = c->ntiles_all;
-    if (only_item >= 0) { off = c->item_tile_off[only_item]; cnt = c->item_tile_cnt[only_item]; }
-    const GraphChunk* GC = (const GraphChunk*)c->g_chunks_all.p;
-    int goff = 0, gcnt = c->n_gchunks_all;
-    if (only_item >= 0) { goff = c->item_gchunk_off[only_item]; gcnt = c->item_gchunk_cnt[only_item]; }
+  // A step opened from the host's clock (dev_step >= 0) with no source that can be non-zero
+  // needs no separate right-hand-side pass on single-scenario meshes: the step's first residual
+  // pass forms b itself (launch_resid_all picks up fuse_rhs_next).
+  const bool loads = dev_step < 0 || sources_may_act(c, dev_step);
+  bool fuse = only_item < 0 && !loads && c->ntiles_all > 0;
+  for (auto& grp : c->tile_groups) fuse = fuse && !grp.multi;
+  c->fuse_rhs_next = fuse;
+  const Tile* T = (const Tile*)c->tiles_all.p;
+  int off = 0, cnt = fuse ? 0 : c->ntiles_all;
+  if (only_item >= 0) { off = c->item_tile_off[only_item]; cnt = c->item_tile_cnt[only_item]; }
+  const GraphChunk* GC = (const GraphChunk*)c->g_chunks_all.p;
+  int goff = 0, gcnt = c->n_gchunks_all;
+  if (only_item >= 0) { goff = c->item_gchunk_off[only_item]; gcnt = c->item_gchunk_cnt[only_item]; }
+  if (cnt > 0 || gcnt > 0) {
     ProfScope ps(c, 2, 0, 0.0, (cnt > 0 ? 1 : 0) + (gcnt > 0 ? 1 : 0));
     e = launch_rhs(T + off, cnt, c->tile_rows, (const GridDesc*)c->grid_desc.p, k, c->stream);
     if (e == hipSuccess) {
@@ -948,7 +959,7 @@ pg_status begin_step(pg_ctx* c, int only_item, bool begun = false, int64_t dev_s
     }
     if (e != hipSuccess) return set_err(c, PG_ERR_DEVICE, "rhs launch: %s", hipGetErrorString(e));
   }
-  if (dev_step < 0 || sources_may_act(c, dev_step)) {
+  if (loads) {
     ProfScope ps(c, 2, 0);
     e = launch_sources(c->src_table, (const GridDesc*)c->grid_desc.p, k, 0.0, 1.0, c->stream);
     // the three-level right-hand side takes the change of the loads: add back I(t - h)
