@@ -136,8 +136,10 @@ __device__ int block_lower_bound(const double* __restrict__ a, int n, double key
 
 // Open a step on the device (the whole block): activate every item (only_item < 0) or one item,
 // reset its per-step control, set t = (step + 1) h and the window of sources that can be
-// non-zero at t.
-__device__ void step_begin_block(const Ctl& c, int I, int only_item, double h, const SourceTable& src) {
+// non-zero at t.  win_a >= 0: the window's bounds [win_a, win_b) in the windowed sources, found
+// by the host for the step it knows will be opened; else searched here.
+__device__ void step_begin_block(const Ctl& c, int I, int only_item, double h, const SourceTable& src,
+                                 int win_a, int win_b) {
   for (int g = threadIdx.x; g < I; g += blockDim.x) {
     c.active[g] = (only_item < 0 || g == only_item) ? 1 : 0;
     c.step_sweeps[g] = 0;
@@ -146,8 +148,8 @@ __device__ void step_begin_block(const Ctl& c, int I, int only_item, double h, c
   }
   const double t = (double)(c.step[0] + 1) * h;
   // windowed sources whose first breakpoint lies in [t - widest window, t]
-  const int a = block_lower_bound(src.win_t0, src.n_window, t - src.win_maxw, false);
-  const int b = block_lower_bound(src.win_t0, src.n_window, t, true);
+  const int a = win_a >= 0 ? win_a : block_lower_bound(src.win_t0, src.n_window, t - src.win_maxw, false);
+  const int b = win_a >= 0 ? win_b : block_lower_bound(src.win_t0, src.n_window, t, true);
   if (threadIdx.x == 0) {
     c.t_now[0] = t;
     c.src_window[0] = src.n_always + a;
@@ -155,9 +157,9 @@ __device__ void step_begin_block(const Ctl& c, int I, int only_item, double h, c
   }
 }
 
-__global__ void k_step_begin(Ctl c, int I, int only_item, double h, SourceTable src) {
+__global__ void k_step_begin(Ctl c, int I, int only_item, double h, SourceTable src, int win_a, int win_b) {
   if (*c.stall) return;
-  step_begin_block(c, I, only_item, h, src);
+  step_begin_block(c, I, only_item, h, src, win_a, win_b);
 }
 
 // Sum / max over the 64 lanes of a wavefront (every lane gets the result).
@@ -262,7 +264,8 @@ __global__ void k_decide(Ctl c, DecideArgs da) { decide_block(c, da); }
 // the clock, 0 does neither; the failure flag is always gathered.  Items still iterating mean the
 // close was queued ahead of the step's last decision: set the stall flag and do nothing.  With
 // begin_next the same block then opens the next step (step_begin_block for every item).
-__global__ void k_step_end(Ctl c, int I, int count_step, int begin_next, double h, SourceTable src) {
+__global__ void k_step_end(Ctl c, int I, int count_step, int begin_next, double h, SourceTable src,
+                           int win_a, int win_b) {
   __shared__ long long s_sw[4], s_upd[4];
   __shared__ int s_mx[4], s_fail[4], s_act[4];
   __shared__ double s_res[4];
@@ -317,7 +320,7 @@ __global__ void k_step_end(Ctl c, int I, int count_step, int begin_next, double 
   }
   if (!begin_next) return;
   __syncthreads();  // the new step index is visible to the block
-  step_begin_block(c, I, -1, h, src);
+  step_begin_block(c, I, -1, h, src, win_a, win_b);
 }
 
 // ------------------------------------------------------------------------------------
@@ -1238,15 +1241,15 @@ __global__ void k_ind_update_item(const GridDesc* __restrict__ grids, int grid, 
 // Launch wrappers
 // ------------------------------------------------------------------------------------
 
-hipError_t launch_step_begin(const Ctl& c, int I, int only_item, double h, const SourceTable& src,
-                             hipStream_t s) {
-  hipLaunchKernelGGL(k_step_begin, dim3(1), dim3(256), 0, s, c, I, only_item, h, src);
+hipError_t launch_step_begin(const Ctl& c, int I, int only_item, double h, const SourceTable& src, int win_a,
+                             int win_b, hipStream_t s) {
+  hipLaunchKernelGGL(k_step_begin, dim3(1), dim3(256), 0, s, c, I, only_item, h, src, win_a, win_b);
   return hipGetLastError();
 }
 
 hipError_t launch_step_end(const Ctl& c, int I, int count_step, int begin_next, double h, const SourceTable& src,
-                           hipStream_t s) {
-  hipLaunchKernelGGL(k_step_end, dim3(1), dim3(256), 0, s, c, I, count_step, begin_next, h, src);
+                           int win_a, int win_b, hipStream_t s) {
+  hipLaunchKernelGGL(k_step_end, dim3(1), dim3(256), 0, s, c, I, count_step, begin_next, h, src, win_a, win_b);
   return hipGetLastError();
 }
 

@@ -192,8 +192,10 @@ struct DecideArgs {
 };
 
 // ---- launch wrappers (kernels.hip) ----
-hipError_t launch_step_begin(const Ctl& c, int G, int only_item, double h, const SourceTable& src,
-                             hipStream_t s);
+// win_a >= 0: the source window [win_a, win_b) of the step being opened, found by the host;
+// -1: searched on the device (launches replayed from graphs, or steps the host does not track)
+hipError_t launch_step_begin(const Ctl& c, int G, int only_item, double h, const SourceTable& src, int win_a,
+                             int win_b, hipStream_t s);
 hipError_t launch_rhs(const Tile* tiles, int ntiles, int tile_rows, const GridDesc* grids,
                       const Ctl& c, hipStream_t s);
 // b -= sign * I(t_now + shift) at every source in the window of the step being opened
@@ -217,7 +219,7 @@ hipError_t launch_sweep(bool fp32, bool multi, int ordering, int nl, int tile_ro
                         double omega, hipStream_t s);
 // count_step: 1 statistics and clock, 2 clock only, 0 neither; begin_next opens the next step.
 hipError_t launch_step_end(const Ctl& c, int G, int count_step, int begin_next, double h, const SourceTable& src,
-                           hipStream_t s);
+                           int win_a, int win_b, hipStream_t s);
 // adjoint of the softplus loss (tiles of one item; vk, vprev and grads are plain slices)
 hipError_t launch_loss(const Tile* tiles, int ntiles, int tile_rows, const GridDesc* grids, const Ctl& c,
                        double margin, double* part, double* total, hipStream_t s);

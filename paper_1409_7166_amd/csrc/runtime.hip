@@ -163,6 +163,7 @@ struct pg_ctx {
   bool begun_next = false;                       // the last close also began the next step
   bool prev_valid = false;                       // graph grids' vprev holds v(t-h) (three-level)
   bool fuse_rhs_next = false;                    // the next residual pass also forms the mesh RHS
+  bool capturing = false;                        // launches are being captured into a graph
   std::vector<double> win_t0_host;               // bucket starts of the windowed sources (host copy)
   std::vector<ProfEvent> prof_live;
   std::vector<hipEvent_t> prof_pool;
@@ -912,6 +913,17 @@ bool sources_may_act(const pg_ctx* c, int64_t dev_step) {
   return lo < hi;
 }
 
+// The window of windowed sources for step index dev_step (t = (dev_step + 1) h), as the device
+// search computes it: [first t0 >= t - widest window, first t0 > t).  -1 when dev_step < 0.
+void host_window(const pg_ctx* c, int64_t dev_step, int* a, int* b) {
+  *a = *b = -1;
+  if (dev_step < 0) return;
+  const double t = (double)(dev_step + 1) * c->opt.h;
+  const auto& w = c->win_t0_host;
+  *a = (int)(std::lower_bound(w.begin(), w.end(), t - c->src_table.win_maxw) - w.begin());
+  *b = (int)(std::upper_bound(w.begin(), w.end(), t) - w.begin());
+}
+
 // Begin a step at time (step + 1) h: activate every item (only_item < 0) or one item, form the
 // right-hand side on the active tiles, subtract the sources.  `begun`: the previous close has
 // already opened the clock and the items.  dev_step >= 0 (the device step index the opening
@@ -932,7 +944,9 @@ pg_status begin_step(pg_ctx* c, int only_item, bool begun = false, int64_t dev_s
   const bool three = c->opt.recurrence == PG_REC_THREE_LEVEL && c->n_gchunks_all > 0;
   if (!begun) {
     ProfScope ps(c, 3, 0);
-    e = launch_step_begin(k, G, only_item, c->opt.h, c->src_table, c->stream);
+    int wa = -1, wb = -1;
+    host_window(c, dev_step, &wa, &wb);
+    e = launch_step_begin(k, G, only_item, c->opt.h, c->src_table, wa, wb, c->stream);
     if (e != hipSuccess) return set_err(c, PG_ERR_DEVICE, "step launch: %s", hipGetErrorString(e));
   }
   // A step opened from the host's clock (dev_step >= 0) with no source that can be non-zero
@@ -1142,7 +1156,9 @@ pg_status end_step(pg_ctx* c, int count_step = 1, int begin_next = 0) {
   hipError_t e;
   {
     ProfScope ps(c, 3, 0);
-    e = launch_step_end(k, n_items(c), count_step, begin_next, c->opt.h, c->src_table, c->stream);
+    int wa = -1, wb = -1;
+    if (begin_next && !c->capturing) host_window(c, c->step + 1, &wa, &wb);
+    e = launch_step_end(k, n_items(c), count_step, begin_next, c->opt.h, c->src_table, wa, wb, c->stream);
     if (e != hipSuccess) return set_err(c, PG_ERR_DEVICE, "step-end launch: %s", hipGetErrorString(e));
   }
   if (c->n_ind_total) {
@@ -1161,10 +1177,12 @@ pg_status capture(pg_ctx* c, hipGraphExec_t* out, F body) {
   const int saved_prof = c->profile_every;
   c->stream = c->cap_stream;
   c->profile_every = 0;
+  c->capturing = true;
   hipError_t e = hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal);
   pg_status st = e == hipSuccess ? body() : PG_ERR_DEVICE;
   hipGraph_t g = nullptr;
   hipError_t e2 = hipStreamEndCapture(c->cap_stream, &g);
+  c->capturing = false;
   c->stream = saved;
   c->profile_every = saved_prof;
   if (e != hipSuccess || e2 != hipSuccess)
@@ -1335,7 +1353,7 @@ pg_status loss_backward(pg_ctx* c, double tol_adj, double* dC, double* dgE, doub
     for (int q = 1; q <= len; ++q) {
       PG_TRY(begin_step(c, A.item));
       PG_TRY(solve_active(c, c->opt.tol));
-      hipError_t e2 = launch_step_end(c->ctl, n_items(c), 2, 0, c->opt.h, c->src_table, c->stream);
+      hipError_t e2 = launch_step_end(c->ctl, n_items(c), 2, 0, c->opt.h, c->src_table, -1, -1, c->stream);
       if (e2 == hipSuccess) e2 = launch_ind_update_item(gd, A.grid, A.item, A.scen, c->ctl, ni, c->stream);
       if (e2 != hipSuccess) return set_err(c, PG_ERR_DEVICE, "step-end launch: %s", hipGetErrorString(e2));
       c->step++;
@@ -1353,7 +1371,7 @@ pg_status loss_backward(pg_ctx* c, double tol_adj, double* dC, double* dgE, doub
         e = launch_adj_rhs(T, nt, c->tile_rows, gd, c->ctl, seg + (size_t)q * ns, A.margin, (const double*)A.mu.p,
                            ni, c->stream);
       if (e != hipSuccess) return set_err(c, PG_ERR_DEVICE, "adjoint rhs: %s", hipGetErrorString(e));
-      e = launch_step_begin(c->ctl, n_items(c), A.item, c->opt.h, c->src_table, c->stream);
+      e = launch_step_begin(c->ctl, n_items(c), A.item, c->opt.h, c->src_table, -1, -1, c->stream);
       if (e != hipSuccess) return set_err(c, PG_ERR_DEVICE, "adjoint step: %s", hipGetErrorString(e));
       PG_TRY(solve_active(c, tol_adj));
       e = launch_adj_grad(T, nt, c->tile_rows, gd, c->ctl, seg + (size_t)q * ns, seg + (size_t)(q - 1) * ns,
@@ -1819,7 +1837,7 @@ pg_status item_absmax(pg_ctx* c, int item, int op, int which, double* out) {
 
 // Activate one item (the others exit at once) without forming a right-hand side.
 pg_status activate_only(pg_ctx* c, int item) {
-  hipError_t e = launch_step_begin(c->ctl, n_items(c), item, c->opt.h, c->src_table, c->stream);
+  hipError_t e = launch_step_begin(c->ctl, n_items(c), item, c->opt.h, c->src_table, -1, -1, c->stream);
   return e == hipSuccess ? PG_OK : set_err(c, PG_ERR_DEVICE, "activation: %s", hipGetErrorString(e));
 }
 
