@@ -401,7 +401,13 @@ __global__ void k_sources(SourceTable src, const GridDesc* __restrict__ grids, C
 // ------------------------------------------------------------------------------------
 template <typename T, int NL, int TY>
 __device__ void resid_tile(const Tile* __restrict__ tiles, int ti, const GridDesc* __restrict__ grids,
-                           const Ctl& c, int has_d, int din, int fuse_rhs) {
+                           const Ctl& c, int has_d, int din, int fuse) {
+  // fuse (the first pass of a step whose sources are all zero, has_d = 0): kFuseRhs forms b here;
+  // kFuseProbe stores neither b nor r (only the norm counts); kFuseNoNorm stores b and r and
+  // leaves the norm alone.  These passes form M_ii from the conductances they load and the pad
+  // conductance G0 = (G0 Vdd) / Vdd, instead of reading it.
+  const int fuse_rhs = fuse & kFuseRhs;
+  const bool store = !(fuse & kFuseProbe), norm = !(fuse & kFuseNoNorm);
   constexpr int NP = kTileX / 2, HP = NP + 2, HY = TY + 2;
   constexpr int NT = 64 * TY;
   __shared__ double2 sv[NL][HY][HP];
@@ -442,6 +448,8 @@ __device__ void resid_tile(const Tile* __restrict__ tiles, int ti, const GridDes
   const int lane = threadIdx.x & 63, row = threadIdx.x >> 6;
   const int x = x0 + 2 * lane, y = y0 + row;
   const int hp = lane + 1, hy = row + 1;
+  const bool dfly = fuse_rhs && G.vdd != 0.0;
+  const double inv_vdd = dfly ? 1.0 / G.vdd : 0.0;
   double m = 0.0;
   if (x < X && y < ny) {
     double* __restrict__ vout = G.v[vi ^ 1] + off;
@@ -450,11 +458,12 @@ __device__ void resid_tile(const Tile* __restrict__ tiles, int ti, const GridDes
     for (int l = 0; l < NL; ++l) {
       const int64_t i = l * P + (int64_t)y * X + x;
       const double2 own = sv[l][hy][hp];
-      double2 b2;
+      double2 b2, ch2 = make_double2(0.0, 0.0), bc2 = make_double2(0.0, 0.0);
       if (fuse_rhs) {
-        // the step's right-hand side formed here (the first pass of a step whose sources are all
-        // zero): b = (C/h) v + G0 Vdd - inductor history, exactly as k_rhs forms it
-        const double2 ch2 = ld2(G.ch64, i), bc2 = ld2(G.bconst64, i);
+        // the step's right-hand side formed here: b = (C/h) v + G0 Vdd - inductor history,
+        // exactly as k_rhs forms it
+        ch2 = ld2(G.ch64, i);
+        bc2 = ld2(G.bconst64, i);
         b2.x = ch2.x * own.x + bc2.x;
         b2.y = ch2.y * own.y + bc2.y;
         if (G.n_ind) {
@@ -470,17 +479,24 @@ __device__ void resid_tile(const Tile* __restrict__ tiles, int ti, const GridDes
             if (q) b2.y = bb; else b2.x = bb;
           }
         }
-        st2(G.b + off, i, b2);
+        if (store) st2(G.b + off, i, b2);
       } else {
         b2 = ld2(bvec, i);
       }
-      const double2 D2 = ld2(G.D64, i), ge = ld2(G.gE64, i), gn = ld2(G.gN64, i);
+      const double2 ge = ld2(G.gE64, i), gn = ld2(G.gN64, i);
       const double2 gs = y > 0 ? ld2(G.gN64, i - X) : make_double2(0.0, 0.0);
       const double gw = x > 0 ? G.gE64[i - 1] : 0.0;
       double2 gu = make_double2(0.0, 0.0), gd = make_double2(0.0, 0.0);
       if (NL > 1) {
         if (l < NL - 1) gu = ld2(G.gU64, i);
         if (l > 0) gd = ld2(G.gU64, i - P);
+      }
+      double2 D2;
+      if (dfly) {  // node x: east ge.x, west gw; node x + 1: east ge.y, west ge.x
+        D2.x = mesh_diag(ch2.x, ge.x, gw, gn.x, gs.x, gu.x, gd.x, bc2.x * inv_vdd);
+        D2.y = mesh_diag(ch2.y, ge.y, ge.x, gn.y, gs.y, gu.y, gd.y, bc2.y * inv_vdd);
+      } else {
+        D2 = ld2(G.D64, i);
       }
       const double2 eastp = sv[l][hy][hp + 1], westp = sv[l][hy][hp - 1];
       const double2 nth = sv[l][hy + 1][hp], sth = sv[l][hy - 1][hp];
@@ -496,14 +512,17 @@ __device__ void resid_tile(const Tile* __restrict__ tiles, int ti, const GridDes
       if (x >= nx) r0 = 0.0;
       if (x + 1 >= nx) r1 = 0.0;
       if (has_d) st2(vout, i, own);
-      V2<T> rr;
-      rr.x = (T)r0;
-      rr.y = (T)r1;
-      st2(r, i, rr);
+      if (store) {
+        V2<T> rr;
+        rr.x = (T)r0;
+        rr.y = (T)r1;
+        st2(r, i, rr);
+      }
       if (x < nx) m = nan_max(m, fabs(r0) / D2.x);
       if (x + 1 < nx) m = nan_max(m, fabs(r1) / D2.y);
     }
   }
+  if (!norm) return;  // uniform over the block
   // wavefront max, then across the block, then one atomic per block
   for (int off = 32; off > 0; off >>= 1) m = nan_max(m, __shfl_xor(m, off, 64));
   if (lane == 0) wmax[row] = m;
@@ -518,9 +537,9 @@ __device__ void resid_tile(const Tile* __restrict__ tiles, int ti, const GridDes
 template <typename T, int NL, int TY>
 __global__ __launch_bounds__(64 * TY) void k_resid(const Tile* __restrict__ tiles, int ntiles,
                                                   const GridDesc* __restrict__ grids, Ctl c,
-                                                  int has_d, int din, int fuse_rhs) {
+                                                  int has_d, int din, int fuse) {
   const int ti = xcd_tile(ntiles);
-  if (!*c.stall && ti >= 0) resid_tile<T, NL, TY>(tiles, ti, grids, c, has_d, din, fuse_rhs);
+  if (!*c.stall && ti >= 0) resid_tile<T, NL, TY>(tiles, ti, grids, c, has_d, din, fuse);
 }
 
 // ------------------------------------------------------------------------------------
@@ -1445,13 +1464,13 @@ hipError_t launch_adj_grad(const Tile* tiles, int ntiles, int tile_rows, const G
 
 template <typename T, int NL, int TY>
 static void resid_t(bool multi, const Tile* tiles, int ntiles, const GridDesc* grids, const Ctl& c, int has_d,
-                    int din, int fuse_rhs, hipStream_t s) {
+                    int din, int fuse, hipStream_t s) {
   if (multi)
     hipLaunchKernelGGL((k_resid_multi<T, NL, TY>), dim3(xcd_blocks(ntiles)), dim3(64 * TY), 0, s, tiles,
                        ntiles, grids, c, has_d, din);
   else
     hipLaunchKernelGGL((k_resid<T, NL, TY>), dim3(xcd_blocks(ntiles)), dim3(64 * TY), 0, s, tiles,
-                       ntiles, grids, c, has_d, din, fuse_rhs);
+                       ntiles, grids, c, has_d, din, fuse);
 }
 
 template <typename T, int NL, int TY>
@@ -1493,12 +1512,12 @@ static void sweep2_t(const Tile* tiles, int ntiles, const GridDesc* grids, const
   }
 
 hipError_t launch_resid(bool fp32, bool multi, int nl, int tile_rows, const Tile* tiles, int ntiles,
-                        const GridDesc* grids, const Ctl& c, int has_d, int din, int fuse_rhs, hipStream_t s) {
+                        const GridDesc* grids, const Ctl& c, int has_d, int din, int fuse, hipStream_t s) {
   if (ntiles <= 0) return hipSuccess;
   if (fp32) {
-    PG_DISPATCH_NL_TY(resid_t, float, multi, tiles, ntiles, grids, c, has_d, din, fuse_rhs, s)
+    PG_DISPATCH_NL_TY(resid_t, float, multi, tiles, ntiles, grids, c, has_d, din, fuse, s)
   } else {
-    PG_DISPATCH_NL_TY(resid_t, double, multi, tiles, ntiles, grids, c, has_d, din, fuse_rhs, s)
+    PG_DISPATCH_NL_TY(resid_t, double, multi, tiles, ntiles, grids, c, has_d, din, fuse, s)
   }
   return hipGetLastError();
 }

@@ -36,6 +36,16 @@ __device__ __forceinline__ void raise_max(unsigned long long* p, double x) {
   if (b > __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) atomicMax(p, b);
 }
 
+// Diagonal of M at a mesh node from the terms the residual pass has at hand: C/h, the six
+// neighbour conductances (east, west, north, south, up, down; zero where absent) and the pad
+// conductance, summed in this order without contraction, so the host (which stores M_ii) and the
+// device (which forms it in the first pass of a step) get the same bits.
+__host__ __device__ inline double mesh_diag(double ch, double e, double w, double n, double s, double u, double d,
+                                            double pad) {
+#pragma clang fp contract(off)
+  return ((((((ch + e) + w) + n) + s) + u) + d) + pad;
+}
+
 // Per-grid device descriptor.  A layered mesh (kind 0) stores every per-node array with a row
 // pitch X >= nx (a multiple of kPitchAlign): slot (l*ny + y)*X + x.  Coefficients are zero in
 // the padding columns, at x = nx-1 (gE), y = ny-1 (gN), on the top layer (gU) and wherever no
@@ -202,10 +212,14 @@ hipError_t launch_rhs(const Tile* tiles, int ntiles, int tile_rows, const GridDe
 hipError_t launch_sources(const SourceTable& src, const GridDesc* grids, const Ctl& c, double shift, double sign,
                           hipStream_t s);
 // multi: the tiles are scenario blocks (Tile.pad consecutive scenarios of one grid).
-// fuse_rhs (single-scenario tiles, has_d = 0): also form and store the step's right-hand side,
-// as k_rhs would, for a step whose sources are all zero (no k_rhs or k_sources launch before it)
+// fuse (single-scenario tiles, has_d = 0; the first pass of a step whose sources are all zero, so
+// no k_rhs or k_sources launch precedes it): kFuseRhs forms the step's right-hand side as k_rhs
+// would and stores it; with kFuseProbe it stores neither b nor r (a step expected to converge
+// at once only needs the norm); with kFuseNoNorm it stores both and leaves the norm alone (the
+// pass that follows a probe that found work).
+constexpr int kFuseRhs = 1, kFuseProbe = 2, kFuseNoNorm = 4;
 hipError_t launch_resid(bool fp32, bool multi, int nl, int tile_rows, const Tile* tiles, int ntiles,
-                        const GridDesc* grids, const Ctl& c, int has_d, int din, int fuse_rhs, hipStream_t s);
+                        const GridDesc* grids, const Ctl& c, int has_d, int din, int fuse, hipStream_t s);
 // The decision after a residual pass, with sequence number q = (*flag_seq)++, writes
 // ((q & 0x1fffffff) << 2) | (skipped << 1) | (any item still active) to slot q % nslots of
 // c.any_active (host-visible memory), after the slot's accounting words; `skipped` marks a

@@ -100,10 +100,15 @@ struct pg_ctx {
     const double e = opt.precision == PG_PREC_FP32_REFINE ? 4.0 : 8.0;
     return e * ((2.0 + 3.0 * (L - 1)) * an + (double)L * coef);
   }
-  double resid_bytes(int64_t an, int64_t coef, bool has_d, bool fused_rhs = false) const {
+  double resid_bytes(int64_t an, int64_t coef, bool has_d, int fuse = 0) const {
     const double e = opt.precision == PG_PREC_FP32_REFINE ? 4.0 : 8.0;
-    // a pass that forms the right-hand side reads C/h and G0 Vdd and writes b instead of reading it
-    return (16.0 + e + (has_d ? e + 8.0 : 0.0) + (fused_rhs ? 16.0 : 0.0)) * an + 8.0 * coef;
+    if (fuse & kFuseRhs) {
+      // forms b (reads C/h and G0 Vdd, forms M_ii): v, C/h, G0 Vdd, and b and r unless a probe;
+      // coefficients without M_ii (8 B of each 8 (3 + (nl-1)/nl) B per node)
+      const double st = (fuse & kFuseProbe) ? 0.0 : 8.0 + e;
+      return (24.0 + st) * an + 8.0 * coef * 2.0 / 3.0;
+    }
+    return (16.0 + e + (has_d ? e + 8.0 : 0.0)) * an + 8.0 * coef;
   }
   std::vector<Group> tile_groups;                 // sweep/residual tiles by (layers, block): [off, off+count) of tiles_sweep
   int ntiles_all = 0;
@@ -162,7 +167,8 @@ struct pg_ctx {
   bool maybe_stalled = false;                    // a speculative close may have stalled the device
   bool begun_next = false;                       // the last close also began the next step
   bool prev_valid = false;                       // graph grids' vprev holds v(t-h) (three-level)
-  bool fuse_rhs_next = false;                    // the next residual pass also forms the mesh RHS
+  int fuse_next = 0;                             // kFuse* mode of the next residual pass (mesh RHS)
+  bool opening_probe = false;                    // the last queued opening only took the norm
   bool capturing = false;                        // launches are being captured into a graph
   std::vector<double> win_t0_host;               // bucket starts of the windowed sources (host copy)
   std::vector<ProfEvent> prof_live;
@@ -394,17 +400,20 @@ pg_status build_mesh_grid(pg_ctx* c, int gi) {
     D[a] += g;
     bc[a] += g * G.vdd;
   }
-  // diagonal of M and its inverse; padding slots keep D = 0 and invD = 0
+  // diagonal of M and its inverse; padding slots keep D = 0 and invD = 0.  With a non-zero
+  // supply voltage the pad conductance enters as (G0 Vdd) (1/Vdd), the form the first residual
+  // pass of a step recovers it in (mesh_diag); D already holds the pads otherwise.
   std::vector<double> inv(ns, 0.0);
+  const double inv_vdd = G.vdd != 0.0 ? 1.0 / G.vdd : 0.0;
   for (int l = 0; l < nl; ++l)
     for (int y = 0; y < ny; ++y)
       for (int x = 0; x < nx; ++x) {
         const int64_t i = (int64_t)l * PS + (int64_t)y * X + x;
-        double s = ch[i] + gE[i] + gN[i] + gU[i];
-        if (x > 0) s += gE[i - 1];
-        if (y > 0) s += gN[i - X];
-        if (l > 0) s += gU[i - PS];
-        D[i] += s;
+        const double w = x > 0 ? gE[i - 1] : 0.0, s = y > 0 ? gN[i - X] : 0.0, d = l > 0 ? gU[i - PS] : 0.0;
+        if (G.vdd != 0.0)
+          D[i] = mesh_diag(ch[i], gE[i], w, gN[i], s, gU[i], d, bc[i] * inv_vdd);
+        else
+          D[i] = mesh_diag(ch[i], gE[i], w, gN[i], s, gU[i], d, D[i]);
         inv[i] = 1.0 / D[i];
       }
   PG_TRY(upload(c, G.gE64, gE)); PG_TRY(upload(c, G.gN64, gN)); PG_TRY(upload(c, G.gU64, gU));
@@ -815,16 +824,16 @@ int next_tag(pg_ctx* c) { return (int)(c->flag_seq_host++ & kTagMask); }
 // pgrid_internal.h), whose tag is returned.
 pg_status launch_resid_all(pg_ctx* c, int has_d, int din, double tol = 0.0, int* tag = nullptr) {
   const Tile* T = (const Tile*)c->tiles_sweep.p;
-  const int fuse = (!has_d && c->fuse_rhs_next) ? 1 : 0;
-  c->fuse_rhs_next = false;
-  ProfScope ps(c, 1, c->begin_nodes, c->resid_bytes(c->begin_nodes, c->begin_coef, has_d != 0, fuse != 0),
+  const int fuse = has_d ? 0 : c->fuse_next;
+  c->fuse_next = 0;
+  ProfScope ps(c, 1, c->begin_nodes, c->resid_bytes(c->begin_nodes, c->begin_coef, has_d != 0, fuse),
                (int)c->tile_groups.size() + (c->n_gchunks_all ? 1 : 0) + (tag ? 1 : 0));
   for (auto& grp : c->tile_groups) {
     hipError_t e = launch_resid(fp32_mode(c), grp.multi, grp.nl, c->tile_rows, T + grp.off, grp.count,
                                 (const GridDesc*)c->grid_desc.p, c->ctl, has_d, din, fuse, c->stream);
     if (e != hipSuccess) return set_err(c, PG_ERR_DEVICE, "residual launch: %s", hipGetErrorString(e));
   }
-  if (c->n_gchunks_all) {
+  if (c->n_gchunks_all && !(fuse & kFuseNoNorm)) {  // the storing pass after a probe is mesh-only
     hipError_t e = launch_graph_resid(fp32_mode(c), (const GraphChunk*)c->g_chunks_all.p, c->n_gchunks_all,
                                       (const GridDesc*)c->grid_desc.p, c->ctl, has_d, c->stream);
     if (e != hipSuccess) return set_err(c, PG_ERR_DEVICE, "residual launch: %s", hipGetErrorString(e));
@@ -955,7 +964,10 @@ pg_status begin_step(pg_ctx* c, int only_item, bool begun = false, int64_t dev_s
   const bool loads = dev_step < 0 || sources_may_act(c, dev_step);
   bool fuse = only_item < 0 && !loads && c->ntiles_all > 0;
   for (auto& grp : c->tile_groups) fuse = fuse && !grp.multi;
-  c->fuse_rhs_next = fuse;
+  // a step predicted to converge at once (the previous one did) only needs the norm: if it has
+  // work after all, cycle_loop stores b and r before the first sweep
+  c->fuse_next = fuse ? (kFuseRhs | (c->pred_chunks == 0 ? kFuseProbe : 0)) : 0;
+  c->opening_probe = (c->fuse_next & kFuseProbe) != 0;
   const Tile* T = (const Tile*)c->tiles_all.p;
   int off = 0, cnt = fuse ? 0 : c->ntiles_all;
   if (only_item >= 0) { off = c->item_tile_off[only_item]; cnt = c->item_tile_cnt[only_item]; }
@@ -1070,11 +1082,20 @@ pg_status cycle_loop(pg_ctx* c, double tol, bool graphs, int first, bool specula
   int spec_tag = -1;
   size_t spec_b = 0, spec_e = 0;
   if (next_first) *next_first = -1;
+  // the step's opening only took the norm (a probe): its b and r are stored before the first
+  // sweep, by a pass that leaves the decided norm alone
+  bool need_store = c->opening_probe;
+  c->opening_probe = false;
   while (true) {
     if (!spec_live) {
       int want = consumed <= c->pred_chunks ? c->pred_chunks : consumed + L;
       want = std::min(want, consumed + kFlagSlots - 2);  // never reuse a slot still awaited
       while (issued < max_chunks && issued < want) {
+        if (need_store) {
+          c->fuse_next = kFuseRhs | kFuseNoNorm;
+          PG_TRY(launch_resid_all(c, 0, 0));
+          need_store = false;
+        }
         c->cur_chunk = ++issued;
         int tag = 0;
         PG_TRY(issue_cycle(c, tol, graphs, &tag));
@@ -1230,6 +1251,7 @@ pg_status queue_opening(pg_ctx* c, int* first, int ahead) {
   c->cur_chunk = 0;
   if (c->opt.graphs) {
     if (!c->graphs_ready) PG_TRY(build_graphs(c));
+    c->opening_probe = false;
     {
       ProfScope ps(c, 3, 0);
       HIP_TRY(c, hipGraphLaunch(c->g_prologue, c->stream));

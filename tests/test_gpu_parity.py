@@ -353,3 +353,32 @@ def test_autotune_restores_state_and_caches(tmp_path):
         again = ctx.autotune(4, cache)
     assert again["omega"] == pytest.approx(chosen["omega"]) and again["check_every"] == chosen["check_every"]
     assert again["sweeps_per_launch"] == chosen["sweeps_per_launch"] and again["tile_rows"] == chosen["tile_rows"]
+
+
+@pytest.mark.parametrize("prec", [pg.PG_PREC_FP64, pg.PG_PREC_FP32_REFINE])
+def test_probe_opening_that_finds_work(prec):
+    """A grid with no sources converges at once, so its next openings only take the norm (the
+    right-hand side is formed inside that pass); a state set from outside then makes such an
+    opening find work, and its b and r are stored before the first sweep.  Every step against
+    the oracle from the same state."""
+    w = small_multilayer(side=48, seed=37, nl=2, pad_every=16, steps=12)
+    mesh = w.meshes[0]
+    rng = np.random.default_rng(11)
+    v_pert = mesh.vdd - rng.uniform(0.0, 0.02, mesh.n)
+    circ, info = mesh_to_circuit(mesh, None)
+    st = BEStepper(circ, w.h)
+    say(f"[gpu] probe opening prec={prec}")
+    with gpu_context(w, precision=prec, tol=1e-11, omega=1.6) as ctx:
+        ctx.set_pulses(0, 0, Pulses(np.zeros(0, np.int32), np.zeros(0), np.zeros(0), np.zeros(0)))
+        ctx.step(3)  # converged at once: the later openings are probes
+        assert np.max(np.abs(ctx.read_voltages() - mesh.vdd)) <= 1e-12
+        ctx.set_state(0, 0, v_pert)
+        v = v_pert.copy()
+        worst = 0.0
+        for k in range(10):
+            v, _ = st.step(v, np.zeros(0), np.zeros(0))
+            ctx.step(1)
+            worst = max(worst, float(np.max(np.abs(ctx.read_voltages() - v))))
+        stats = ctx.stats()
+    say(f"  max err={worst:.3e} V, sweeps={stats['sweeps']}")
+    assert worst <= PARITY_V and stats["sweeps"] > 0
