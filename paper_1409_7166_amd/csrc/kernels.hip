@@ -257,15 +257,14 @@ __device__ void decide_block(const Ctl& c, const DecideArgs& da) {
   }
 }
 
-__global__ void k_decide(Ctl c, DecideArgs da) { decide_block(c, da); }
 
 
 // Close a step: count_step 1 adds the step's statistics and advances the clock, 2 only advances
 // the clock, 0 does neither; the failure flag is always gathered.  Items still iterating mean the
 // close was queued ahead of the step's last decision: set the stall flag and do nothing.  With
 // begin_next the same block then opens the next step (step_begin_block for every item).
-__global__ void k_step_end(Ctl c, int I, int count_step, int begin_next, double h, SourceTable src,
-                           int win_a, int win_b) {
+__device__ void close_block(const Ctl& c, int I, int count_step, int begin_next, double h, const SourceTable& src,
+                            int win_a, int win_b) {
   __shared__ long long s_sw[4], s_upd[4];
   __shared__ int s_mx[4], s_fail[4], s_act[4];
   __shared__ double s_res[4];
@@ -321,6 +320,21 @@ __global__ void k_step_end(Ctl c, int I, int count_step, int begin_next, double 
   if (!begin_next) return;
   __syncthreads();  // the new step index is visible to the block
   step_begin_block(c, I, -1, h, src, win_a, win_b);
+}
+
+__global__ void k_step_end(Ctl c, int I, int count_step, int begin_next, double h, SourceTable src,
+                           int win_a, int win_b) {
+  close_block(c, I, count_step, begin_next, h, src, win_a, win_b);
+}
+
+// A decision, optionally followed in the same block by the step's close (the opening of a step
+// expected to converge at once carries its close, one launch fewer per such step).  Every value
+// the close reads from the control block was written by the same thread in the decision.
+__global__ void k_decide(Ctl c, DecideArgs da, CloseArgs ca) {
+  decide_block(c, da);
+  if (!ca.on) return;
+  __syncthreads();
+  close_block(c, da.I, ca.count_step, ca.begin_next, ca.h, ca.src, ca.win_a, ca.win_b);
 }
 
 // ------------------------------------------------------------------------------------
@@ -1398,8 +1412,8 @@ __global__ void k_resume(Ctl c) {
   if (threadIdx.x == 0) c.stall[0] = 0;
 }
 
-hipError_t launch_decide(const Ctl& c, const DecideArgs& da, hipStream_t s) {
-  hipLaunchKernelGGL(k_decide, dim3(1), dim3(256), 0, s, c, da);
+hipError_t launch_decide(const Ctl& c, const DecideArgs& da, const CloseArgs& ca, hipStream_t s) {
+  hipLaunchKernelGGL(k_decide, dim3(1), dim3(256), 0, s, c, da, ca);
   return hipGetLastError();
 }
 

@@ -224,7 +224,13 @@ hipError_t launch_resid(bool fp32, bool multi, int nl, int tile_rows, const Tile
 // ((q & 0x1fffffff) << 2) | (skipped << 1) | (any item still active) to slot q % nslots of
 // c.any_active (host-visible memory), after the slot's accounting words; `skipped` marks a
 // decision that found the stall flag set and took no action.
-hipError_t launch_decide(const Ctl& c, const DecideArgs& da, hipStream_t s);
+// A step's close carried by a decision (on = 1): as launch_step_end's arguments.
+struct CloseArgs {
+  int on, count_step, begin_next, win_a, win_b;
+  double h;
+  SourceTable src;
+};
+hipError_t launch_decide(const Ctl& c, const DecideArgs& da, const CloseArgs& ca, hipStream_t s);
 // Two red-black sweeps in one launch (tiles may be scenario blocks); reads d[din], writes d[din ^ 1].
 hipError_t launch_sweep2(bool fp32, int nl, int tile_rows, const Tile* tiles, int ntiles, const GridDesc* grids,
                          const Ctl& c, int din, int zero_in, double omega, hipStream_t s);

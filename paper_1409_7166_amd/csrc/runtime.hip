@@ -169,6 +169,7 @@ struct pg_ctx {
   bool prev_valid = false;                       // graph grids' vprev holds v(t-h) (three-level)
   int fuse_next = 0;                             // kFuse* mode of the next residual pass (mesh RHS)
   bool opening_probe = false;                    // the last queued opening only took the norm
+  bool opening_closes = false;                   // ... and its decision carries the step's close
   bool capturing = false;                        // launches are being captured into a graph
   std::vector<double> win_t0_host;               // bucket starts of the windowed sources (host copy)
   std::vector<ProfEvent> prof_live;
@@ -822,7 +823,8 @@ int next_tag(pg_ctx* c) { return (int)(c->flag_seq_host++ & kTagMask); }
 
 // One residual pass over every tile group; with `tag`, followed by its decision (see
 // pgrid_internal.h), whose tag is returned.
-pg_status launch_resid_all(pg_ctx* c, int has_d, int din, double tol = 0.0, int* tag = nullptr) {
+pg_status launch_resid_all(pg_ctx* c, int has_d, int din, double tol = 0.0, int* tag = nullptr,
+                           const CloseArgs* close = nullptr) {
   const Tile* T = (const Tile*)c->tiles_sweep.p;
   const int fuse = has_d ? 0 : c->fuse_next;
   c->fuse_next = 0;
@@ -841,7 +843,8 @@ pg_status launch_resid_all(pg_ctx* c, int has_d, int din, double tol = 0.0, int*
   if (!tag) return PG_OK;
   const DecideArgs da{1, n_items(c), (int)c->grids.size(), has_d, c->opt.check_every, c->opt.max_sweeps,
                       kFlagSlots, tol, (const GridDesc*)c->grid_desc.p};
-  hipError_t e = launch_decide(c->ctl, da, c->stream);
+  CloseArgs none{};
+  hipError_t e = launch_decide(c->ctl, da, close ? *close : none, c->stream);
   if (e != hipSuccess) return set_err(c, PG_ERR_DEVICE, "decision launch: %s", hipGetErrorString(e));
   *tag = next_tag(c);
   return PG_OK;
@@ -1055,7 +1058,7 @@ pg_status issue_cycle(pg_ctx* c, double tol, bool graphs, int* tag) {
 // The host queues as many cycles as the previous step needed before waiting; past that
 // prediction it keeps `lookahead` cycles queued beyond the one whose decision it waits for.
 // Cycles queued after convergence find every item inactive and exit at once.
-pg_status queue_opening(pg_ctx* c, int* first, int ahead);
+pg_status queue_opening(pg_ctx* c, int* first, int ahead, bool close_after = false);
 pg_status queue_close(pg_ctx* c, bool open_next);
 
 pg_status resume(pg_ctx* c) {
@@ -1066,7 +1069,7 @@ pg_status resume(pg_ctx* c) {
 }
 
 pg_status cycle_loop(pg_ctx* c, double tol, bool graphs, int first, bool speculate = false,
-                     int* next_first = nullptr) {
+                     int* next_first = nullptr, bool speculate_after = false) {
   const int nchk = c->opt.check_every;
   const int L = c->opt.lookahead;
   std::deque<int> pending{first};
@@ -1086,6 +1089,8 @@ pg_status cycle_loop(pg_ctx* c, double tol, bool graphs, int first, bool specula
   // sweep, by a pass that leaves the decided norm alone
   bool need_store = c->opening_probe;
   c->opening_probe = false;
+  const bool closed_ahead = c->opening_closes;  // the opening's decision carries this step's close
+  c->opening_closes = false;
   while (true) {
     if (!spec_live) {
       int want = consumed <= c->pred_chunks ? c->pred_chunks : consumed + L;
@@ -1107,8 +1112,8 @@ pg_status cycle_loop(pg_ctx* c, double tol, bool graphs, int first, bool specula
       const int saved_chunk = c->cur_chunk;
       spec_b = c->prof_live.size();
       c->maybe_stalled = true;
-      PG_TRY(queue_close(c, true));
-      PG_TRY(queue_opening(c, &spec_tag, 1));
+      if (!closed_ahead) PG_TRY(queue_close(c, true));
+      PG_TRY(queue_opening(c, &spec_tag, 1, speculate_after && c->pred_chunks == 0 && !graphs));
       spec_e = c->prof_live.size();
       c->cur_chunk = saved_chunk;
       spec_live = true;
@@ -1247,8 +1252,9 @@ pg_status build_graphs(pg_ctx* c) {
 
 // Queue the opening of a step: clock and activation, right-hand side, sources, first residual
 // and its decision (tag in *first).
-pg_status queue_opening(pg_ctx* c, int* first, int ahead) {
+pg_status queue_opening(pg_ctx* c, int* first, int ahead, bool close_after) {
   c->cur_chunk = 0;
+  c->opening_closes = false;
   if (c->opt.graphs) {
     if (!c->graphs_ready) PG_TRY(build_graphs(c));
     c->opening_probe = false;
@@ -1262,7 +1268,23 @@ pg_status queue_opening(pg_ctx* c, int* first, int ahead) {
   const bool begun = c->begun_next;  // the previous close already opened the clock and the items
   c->begun_next = false;
   PG_TRY(begin_step(c, -1, begun, c->step + ahead));
-  return launch_resid_all(c, 0, 0, c->opt.tol, first);
+  if (!close_after) return launch_resid_all(c, 0, 0, c->opt.tol, first);
+  // a step expected to converge at once (the previous one did) and followed by another: its
+  // opening's decision also closes it and opens the next step; if it finds work, the close
+  // stalls the device and cycle_loop goes on as after any stalled close
+  CloseArgs ca{1, 1, 1, -1, -1, c->opt.h, c->src_table};
+  host_window(c, c->step + ahead + 1, &ca.win_a, &ca.win_b);
+  c->maybe_stalled = true;
+  PG_TRY(launch_resid_all(c, 0, 0, c->opt.tol, first, &ca));
+  if (c->n_ind_total) {
+    ProfScope ps(c, 3, 0);
+    hipError_t e = launch_inductors((const GridDesc*)c->grid_desc.p, (const int32_t*)c->ind_grid.p,
+                                    (const int32_t*)c->ind_local.p, c->n_ind_total, c->ctl, c->stream);
+    if (e != hipSuccess) return set_err(c, PG_ERR_DEVICE, "inductor launch: %s", hipGetErrorString(e));
+  }
+  c->opening_closes = true;
+  c->begun_next = true;
+  return PG_OK;
 }
 
 // Queue the close of a step: statistics and clock, inductor branch currents; with open_next
@@ -1279,17 +1301,17 @@ pg_status queue_close(pg_ctx* c, bool open_next) {
 
 // One BE step of every item.  With `speculate`, the next step's opening is queued ahead (see
 // cycle_loop) and picked up by the next call.
-pg_status one_step(pg_ctx* c, bool speculate = false) {
+pg_status one_step(pg_ctx* c, bool speculate = false, bool speculate_after = false) {
   int first = 0;
   if (c->opening_queued) {
     first = c->opening_tag;
     c->opening_queued = false;
   } else {
     if (c->maybe_stalled) PG_TRY(resume(c));  // an earlier call stopped on an error mid-speculation
-    PG_TRY(queue_opening(c, &first, 0));
+    PG_TRY(queue_opening(c, &first, 0, speculate && c->pred_chunks == 0 && !c->opt.graphs));
   }
   int next = -1;
-  PG_TRY(cycle_loop(c, c->opt.tol, c->opt.graphs != 0, first, speculate, &next));
+  PG_TRY(cycle_loop(c, c->opt.tol, c->opt.graphs != 0, first, speculate, &next, speculate_after));
   if (next >= 0) {
     c->opening_queued = true;
     c->opening_tag = next;
@@ -1963,7 +1985,7 @@ pg_status pg_run_transient(pg_ctx* c, int32_t nsteps, int32_t record_every, int3
   const auto t0 = std::chrono::steady_clock::now();
   int rec = 0;
   for (int k = 0; k < nsteps; ++k) {
-    PG_TRY(one_step(c, k + 1 < nsteps));
+    PG_TRY(one_step(c, k + 1 < nsteps, k + 2 < nsteps));
     if (out && ((k + 1) % record_every) == 0) {
       PG_TRY(pg_read_voltages(c, grid, scen, out + (size_t)rec * c->grids[grid].n, c->grids[grid].n));
       ++rec;
@@ -2406,7 +2428,7 @@ extern "C" pg_status pg_autotune(pg_ctx* c, int32_t nsteps, const char* cache_pa
     HIP_TRY(c, hipStreamSynchronize(c->stream));
     const auto t0 = std::chrono::steady_clock::now();
     pg_status st = PG_OK;
-    for (int k = 0; k < nsteps && st == PG_OK; ++k) st = one_step(c, k + 1 < nsteps);
+    for (int k = 0; k < nsteps && st == PG_OK; ++k) st = one_step(c, k + 1 < nsteps, k + 2 < nsteps);
     HIP_TRY(c, hipStreamSynchronize(c->stream));
     int32_t failed = 0;
     HIP_TRY(c, hipMemcpy(&failed, c->ctl.stat_failed, sizeof failed, hipMemcpyDeviceToHost));
