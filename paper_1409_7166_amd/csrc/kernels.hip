@@ -139,14 +139,14 @@ __device__ int block_lower_bound(const double* __restrict__ a, int n, double key
 // non-zero at t.  win_a >= 0: the window's bounds [win_a, win_b) in the windowed sources, found
 // by the host for the step it knows will be opened; else searched here.
 __device__ void step_begin_block(const Ctl& c, int I, int only_item, double h, const SourceTable& src,
-                                 int win_a, int win_b) {
+                                 int win_a, int win_b, long long step = -1) {
   for (int g = threadIdx.x; g < I; g += blockDim.x) {
     c.active[g] = (only_item < 0 || g == only_item) ? 1 : 0;
     c.step_sweeps[g] = 0;
     c.failed[g] = 0;
     c.norm_bits[g] = 0ull;
   }
-  const double t = (double)(c.step[0] + 1) * h;
+  const double t = (double)((step >= 0 ? step : c.step[0]) + 1) * h;
   // windowed sources whose first breakpoint lies in [t - widest window, t]
   const int a = win_a >= 0 ? win_a : block_lower_bound(src.win_t0, src.n_window, t - src.win_maxw, false);
   const int b = win_a >= 0 ? win_b : block_lower_bound(src.win_t0, src.n_window, t, true);
@@ -194,66 +194,79 @@ __device__ void decide_block(const Ctl& c, const DecideArgs& da) {
     }
     return;
   }
-  if (threadIdx.x == 0) { any = 0; worked = 0; act_nodes = 0ull; act_coef = 0ull; }
-  __syncthreads();
-  for (int g = threadIdx.x; g < I; g += blockDim.x) {
-    if (c.active[g]) {
-      atomicOr(&worked, 1);
-      if (has_d) {
-        c.vidx[g] ^= 1;
-        c.step_sweeps[g] += nchk;
-      }
-      // the other workgroups' atomicMax results, read at device scope (not from a stale L1 line)
-      const double nm = __longlong_as_double(
-          (long long)__hip_atomic_load(&c.norm_bits[g], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
-      c.last_norm[g] = nm;
-      const bool conv = nm <= tol;                 // false for NaN
-      const bool spent = c.step_sweeps[g] >= max_sweeps;
-      const int act = (!conv && !spent) ? 1 : 0;
-      c.active[g] = act;
-      if (!conv && spent) c.failed[g] = 1;
-      if (act) atomicOr(&any, 1);
-    }
-    c.norm_bits[g] = 0ull;
-  }
-  __syncthreads();
-  // the work the next sweeps will do: active scenarios, and the coefficients of the grids with
-  // an active scenario (marked in a bitmap of grids)
+  // every load the decision needs is issued up front, so the block waits for memory about once:
+  // the item's state, its mesh nodes and grid, each grid's coefficient words, the flag sequence
   constexpr int kMaxGridWords = 1024;
   __shared__ unsigned int gbits[kMaxGridWords];
+  __shared__ int seq_s;
   const bool bitmap = G <= 32 * kMaxGridWords;
   const int nwords = bitmap ? (G + 31) / 32 : 0;
+  long long coef_mine = 0;  // coefficient words of grid threadIdx.x (the common case G <= blockDim)
+  if (bitmap && (int)threadIdx.x < G) coef_mine = grids[threadIdx.x].coef_words;
+  if (threadIdx.x == 0) {
+    any = 0; worked = 0; act_nodes = 0ull; act_coef = 0ull;
+    seq_s = c.flag_seq[0];
+  }
   for (int w = threadIdx.x; w < nwords; w += blockDim.x) gbits[w] = 0u;
   __syncthreads();
   long long mine = 0;
   for (int g = threadIdx.x; g < I; g += blockDim.x) {
-    if (!c.active[g]) continue;
-    mine += c.nodes[g];
+    const int was = c.active[g];
+    const long long nodes = c.nodes[g];
     const int gi = c.item_grid[g];
-    if (bitmap) atomicOr(&gbits[gi >> 5], 1u << (gi & 31));
+    const int swept = c.step_sweeps[g];
+    // the other workgroups' atomicMax results, read at device scope (not from a stale L1 line)
+    const double nm = __longlong_as_double(
+        (long long)__hip_atomic_load(&c.norm_bits[g], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+    if (was) {
+      atomicOr(&worked, 1);
+      const int sw = has_d ? swept + nchk : swept;
+      if (has_d) {
+        c.vidx[g] ^= 1;
+        c.step_sweeps[g] = sw;
+      }
+      c.last_norm[g] = nm;
+      const bool conv = nm <= tol;                 // false for NaN
+      const bool spent = sw >= max_sweeps;
+      const int act = (!conv && !spent) ? 1 : 0;
+      c.active[g] = act;
+      if (!conv && spent) c.failed[g] = 1;
+      if (act) {
+        atomicOr(&any, 1);
+        // the work the next sweeps will do: active scenarios, and the coefficients of the grids
+        // with an active scenario (marked in a bitmap of grids)
+        mine += nodes;
+        if (bitmap) atomicOr(&gbits[gi >> 5], 1u << (gi & 31));
+      }
+    }
+    c.norm_bits[g] = 0ull;
   }
   mine = wave_sum(mine);
   if ((threadIdx.x & 63) == 0 && mine) atomicAdd(&act_nodes, (unsigned long long)mine);
   __syncthreads();
   for (int gi = threadIdx.x; gi < G; gi += blockDim.x) {
-    const GridDesc& D = grids[gi];
     bool any_in_grid = false;
+    long long words;
     if (bitmap) {
       any_in_grid = (gbits[gi >> 5] >> (gi & 31)) & 1u;
+      words = gi == (int)threadIdx.x ? coef_mine : grids[gi].coef_words;
     } else {
+      const GridDesc& D = grids[gi];
       for (int sc = 0; sc < D.S && !any_in_grid; ++sc) any_in_grid = c.active[D.item0 + sc] != 0;
+      words = D.coef_words;
     }
-    if (any_in_grid) atomicAdd(&act_coef, (unsigned long long)D.coef_words);
+    if (any_in_grid) atomicAdd(&act_coef, (unsigned long long)words);
   }
   __syncthreads();
   if (threadIdx.x == 0) {
-    const int seq = c.flag_seq[0];
+    const int seq = seq_s;
+    const long long checks = worked ? c.stat_checks[0] : 0;
     c.flag_seq[0] = seq + 1;
     c.acct[2 * (seq % nslots)] = (long long)act_nodes;
     c.acct[2 * (seq % nslots) + 1] = (long long)act_coef;
     __threadfence_system();
     c.any_active[seq % nslots] = (int32_t)(((uint32_t)seq & 0x1fffffffu) << 2 | (uint32_t)any);
-    if (worked) c.stat_checks[0] += 1;
+    if (worked) c.stat_checks[0] = checks + 1;
   }
 }
 
@@ -305,21 +318,27 @@ __device__ void close_block(const Ctl& c, int I, int count_step, int begin_next,
     if (threadIdx.x == 0) c.stall[0] = 1;
     return;
   }
+  __shared__ long long new_step;
   if (threadIdx.x == 0) {
-    c.stat_failed[0] |= fail;
+    // every statistic is read before any is written, so the loads go out together
+    const int f0 = c.stat_failed[0], mx0 = c.stat_max_sweeps[0];
+    const long long sw0 = c.stat_sweeps[0], up0 = c.stat_updates[0], st0 = c.step[0];
+    const double mr0 = c.stat_max_res[0];
+    c.stat_failed[0] = f0 | fail;
     if (count_step == 1) {
-      c.stat_sweeps[0] += sw;
-      c.stat_updates[0] += upd;
+      c.stat_sweeps[0] = sw0 + sw;
+      c.stat_updates[0] = up0 + upd;
       c.stat_last_sweeps[0] = mx;
-      if (mx > c.stat_max_sweeps[0]) c.stat_max_sweeps[0] = mx;
+      c.stat_max_sweeps[0] = mx > mx0 ? mx : mx0;
       c.stat_last_res[0] = res;
-      c.stat_max_res[0] = nan_max(c.stat_max_res[0], res);
+      c.stat_max_res[0] = nan_max(mr0, res);
     }
-    if (count_step) c.step[0] += 1;
+    new_step = count_step ? st0 + 1 : st0;
+    if (count_step) c.step[0] = new_step;
   }
   if (!begin_next) return;
-  __syncthreads();  // the new step index is visible to the block
-  step_begin_block(c, I, -1, h, src, win_a, win_b);
+  __syncthreads();  // the new step index is known to the block
+  step_begin_block(c, I, -1, h, src, win_a, win_b, new_step);
 }
 
 __global__ void k_step_end(Ctl c, int I, int count_step, int begin_next, double h, SourceTable src,
