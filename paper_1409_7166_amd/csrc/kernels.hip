@@ -381,7 +381,9 @@ __global__ __launch_bounds__(kThreads) void k_rhs(const Tile* __restrict__ tiles
     const int x = tl.x0 + xx, y = tl.y0 + yy;
     if (x >= X || y >= ny) continue;
     const int64_t i = l * P + (int64_t)y * X + x;
-    double bb = G.ch64[i] * v[i] + G.bconst64[i];
+    // layers with no capacitance (or no constant injection) contribute exact zeros
+    const double bcv = ((G.bc_layers >> l) & 1u) ? G.bconst64[i] : 0.0;
+    double bb = ((G.ch_layers >> l) & 1u) ? G.ch64[i] * v[i] + bcv : bcv;
     if (G.n_ind) {
       for (int j = G.inc_off[i]; j < G.inc_off[i + 1]; ++j) {
         const int e = G.inc_ind[j];
@@ -495,8 +497,8 @@ __device__ void resid_tile(const Tile* __restrict__ tiles, int ti, const GridDes
       if (fuse_rhs) {
         // the step's right-hand side formed here: b = (C/h) v + G0 Vdd - inductor history,
         // exactly as k_rhs forms it
-        ch2 = ld2(G.ch64, i);
-        bc2 = ld2(G.bconst64, i);
+        if ((G.ch_layers >> l) & 1u) ch2 = ld2(G.ch64, i);
+        if ((G.bc_layers >> l) & 1u) bc2 = ld2(G.bconst64, i);
         b2.x = ch2.x * own.x + bc2.x;
         b2.y = ch2.y * own.y + bc2.y;
         if (G.n_ind) {

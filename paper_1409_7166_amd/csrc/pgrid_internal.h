@@ -111,6 +111,9 @@ struct GridDesc {
   const double* bl64;
   // coefficient words one sweep reads (for the activity accounting of the decision)
   int64_t coef_words;
+  // layered mesh: bit l set if layer l has a non-zero C/h (ch_layers) or a non-zero constant
+  // injection (bc_layers); layers without are neither read nor written as anything but zero
+  uint32_t ch_layers, bc_layers;
 };
 
 // 256 consecutive slots of one scenario of a general-graph grid, all of one colour in the sweep

@@ -56,6 +56,7 @@ struct GridHost {
   std::vector<int32_t> ind_a, ind_b, ind_branch;
   std::vector<double> ind_sign;
   int64_t coef_words = 0;                        // coefficient words of one sweep (accounting)
+  uint32_t ch_layers = 0, bc_layers = 0;         // layers with non-zero C/h, constant injection
   // device buffers
   DBuf gE64, gN64, gU64, D64, ch64, bconst64, gEs, gNs, gUs, invDs;
   DBuf v0, v1, b, r, d0, d1;
@@ -417,6 +418,12 @@ pg_status build_mesh_grid(pg_ctx* c, int gi) {
           D[i] = mesh_diag(ch[i], gE[i], w, gN[i], s, gU[i], d, D[i]);
         inv[i] = 1.0 / D[i];
       }
+  G.ch_layers = G.bc_layers = 0;
+  for (int l = 0; l < nl; ++l)
+    for (int64_t i = (int64_t)l * PS; i < (int64_t)(l + 1) * PS; ++i) {
+      if (ch[i] != 0.0) G.ch_layers |= 1u << l;
+      if (bc[i] != 0.0) G.bc_layers |= 1u << l;
+    }
   PG_TRY(upload(c, G.gE64, gE)); PG_TRY(upload(c, G.gN64, gN)); PG_TRY(upload(c, G.gU64, gU));
   PG_TRY(upload(c, G.D64, D)); PG_TRY(upload(c, G.ch64, ch)); PG_TRY(upload(c, G.bconst64, bc));
   const bool f32 = fp32_mode(c);
@@ -558,6 +565,8 @@ GridDesc make_desc(pg_ctx* c, GridHost& H) {
     H.coef_words = 3 * H.n + (int64_t)H.nx * H.ny * (H.nl - 1);
   }
   D.coef_words = H.coef_words;
+  D.ch_layers = H.ch_layers;
+  D.bc_layers = H.bc_layers;
   return D;
 }
 
