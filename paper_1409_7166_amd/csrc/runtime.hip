@@ -104,16 +104,17 @@ struct pg_ctx {
   double resid_bytes(int64_t an, int64_t coef, bool has_d, int fuse = 0) const {
     const double e = opt.precision == PG_PREC_FP32_REFINE ? 4.0 : 8.0;
     if (fuse & kFuseRhs) {
-      // forms b (reads C/h and G0 Vdd, forms M_ii): v, C/h, G0 Vdd, and b and r unless a probe;
-      // coefficients without M_ii (8 B of each 8 (3 + (nl-1)/nl) B per node)
+      // forms b and M_ii: v, C/h and G0 Vdd on the layers that have them (fuse_read bytes per
+      // node on average), b and r unless a probe; coefficients without M_ii (one word per node)
       const double st = (fuse & kFuseProbe) ? 0.0 : 8.0 + e;
-      return (24.0 + st) * an + 8.0 * coef * 2.0 / 3.0;
+      return (fuse_read + st) * an + 8.0 * (double)std::max<int64_t>(0, coef - an);
     }
     return (16.0 + e + (has_d ? e + 8.0 : 0.0)) * an + 8.0 * coef;
   }
   std::vector<Group> tile_groups;                 // sweep/residual tiles by (layers, block): [off, off+count) of tiles_sweep
   int ntiles_all = 0;
   int tile_rows = 16;
+  double fuse_read = 24.0;                       // bytes per node a right-hand-side-forming pass reads
   // general-graph chunks: all slots (right-hand side, residual) and, per colour index, the
   // chunks of that colour over every graph grid ([off, off+count) of g_chunks_sweep)
   DBuf g_chunks_all, g_chunks_sweep;
@@ -659,10 +660,18 @@ pg_status prepare(pg_ctx* c) {
   c->all_nodes = 0;
   c->all_coef = 0;
   for (auto& grp : c->tile_groups) c->all_nodes += grp.nodes;
+  double fr = 0.0, fn = 0.0;
   for (auto& H : c->grids) {
     c->all_coef += H.coef_words;
-    if (H.kind) c->all_nodes += H.n * H.S;
+    if (H.kind) {
+      c->all_nodes += H.n * H.S;
+    } else {
+      const double w = (double)H.n * H.S;
+      fr += w * (8.0 + 8.0 * (__builtin_popcount(H.ch_layers) + __builtin_popcount(H.bc_layers)) / H.nl);
+      fn += w;
+    }
   }
+  c->fuse_read = fn > 0 ? fr / fn : 24.0;
   // general-graph chunks: every slot of every scenario (right-hand side, residual), and the
   // sweep chunks colour by colour
   std::vector<GraphChunk> gall, gsweep;
