@@ -219,8 +219,10 @@ hipError_t launch_sources(const SourceTable& src, const GridDesc* grids, const C
 // no k_rhs or k_sources launch precedes it): kFuseRhs forms the step's right-hand side as k_rhs
 // would and stores it; with kFuseProbe it stores neither b nor r (a step expected to converge
 // at once only needs the norm); with kFuseNoNorm it stores both and leaves the norm alone (the
-// pass that follows a probe that found work).
-constexpr int kFuseRhs = 1, kFuseProbe = 2, kFuseNoNorm = 4;
+// pass that follows a probe that found work).  kFuseCancelled with kFuseProbe (every mesh grid
+// has a non-zero supply) takes the probe kernel, whose norm bounds the FP64 one from above;
+// kFuseInd tells it that some grid carries inductors.
+constexpr int kFuseRhs = 1, kFuseProbe = 2, kFuseNoNorm = 4, kFuseCancelled = 8, kFuseInd = 16;
 hipError_t launch_resid(bool fp32, bool multi, int nl, int tile_rows, const Tile* tiles, int ntiles,
                         const GridDesc* grids, const Ctl& c, int has_d, int din, int fuse, hipStream_t s);
 // The decision after a residual pass, with sequence number q = (*flag_seq)++, writes

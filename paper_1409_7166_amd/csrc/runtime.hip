@@ -103,6 +103,11 @@ struct pg_ctx {
   }
   double resid_bytes(int64_t an, int64_t coef, bool has_d, int fuse = 0) const {
     const double e = opt.precision == PG_PREC_FP32_REFINE ? 4.0 : 8.0;
+    if ((fuse & kFuseProbe) && (fuse & kFuseCancelled)) {
+      // the cancelled-form probe: v and G0 Vdd on the layers that have it (probe_read bytes per
+      // node on average), and the sweeps' coefficient words (1/M_ii included) in their precision
+      return probe_read * an + e * (double)coef;
+    }
     if (fuse & kFuseRhs) {
       // forms b and M_ii: v, C/h and G0 Vdd on the layers that have them (fuse_read bytes per
       // node on average), b and r unless a probe; coefficients without M_ii (one word per node)
@@ -115,6 +120,8 @@ struct pg_ctx {
   int ntiles_all = 0;
   int tile_rows = 16;
   double fuse_read = 24.0;                       // bytes per node a right-hand-side-forming pass reads
+  double probe_read = 16.0;                      // bytes per node a cancelled-form probe reads besides coefficients
+  bool probe_cancelled = true;                   // every mesh grid has a non-zero supply (cancelled-form probes)
   // general-graph chunks: all slots (right-hand side, residual) and, per colour index, the
   // chunks of that colour over every graph grid ([off, off+count) of g_chunks_sweep)
   DBuf g_chunks_all, g_chunks_sweep;
@@ -660,7 +667,8 @@ pg_status prepare(pg_ctx* c) {
   c->all_nodes = 0;
   c->all_coef = 0;
   for (auto& grp : c->tile_groups) c->all_nodes += grp.nodes;
-  double fr = 0.0, fn = 0.0;
+  double fr = 0.0, fp = 0.0, fn = 0.0;
+  c->probe_cancelled = true;
   for (auto& H : c->grids) {
     c->all_coef += H.coef_words;
     if (H.kind) {
@@ -668,10 +676,13 @@ pg_status prepare(pg_ctx* c) {
     } else {
       const double w = (double)H.n * H.S;
       fr += w * (8.0 + 8.0 * (__builtin_popcount(H.ch_layers) + __builtin_popcount(H.bc_layers)) / H.nl);
+      fp += w * (8.0 + 8.0 * __builtin_popcount(H.bc_layers) / H.nl);
       fn += w;
+      if (H.vdd == 0.0) c->probe_cancelled = false;
     }
   }
   c->fuse_read = fn > 0 ? fr / fn : 24.0;
+  c->probe_read = fn > 0 ? fp / fn : 16.0;
   // general-graph chunks: every slot of every scenario (right-hand side, residual), and the
   // sweep chunks colour by colour
   std::vector<GraphChunk> gall, gsweep;
@@ -844,7 +855,8 @@ int next_tag(pg_ctx* c) { return (int)(c->flag_seq_host++ & kTagMask); }
 pg_status launch_resid_all(pg_ctx* c, int has_d, int din, double tol = 0.0, int* tag = nullptr,
                            const CloseArgs* close = nullptr) {
   const Tile* T = (const Tile*)c->tiles_sweep.p;
-  const int fuse = has_d ? 0 : c->fuse_next;
+  int fuse = has_d ? 0 : c->fuse_next;
+  if ((fuse & kFuseProbe) && c->probe_cancelled) fuse |= kFuseCancelled | (c->n_ind_total ? kFuseInd : 0);
   c->fuse_next = 0;
   ProfScope ps(c, 1, c->begin_nodes, c->resid_bytes(c->begin_nodes, c->begin_coef, has_d != 0, fuse),
                (int)c->tile_groups.size() + (c->n_gchunks_all ? 1 : 0) + (tag ? 1 : 0));

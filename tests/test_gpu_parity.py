@@ -382,3 +382,44 @@ def test_probe_opening_that_finds_work(prec):
         stats = ctx.stats()
     say(f"  max err={worst:.3e} V, sweeps={stats['sweeps']}")
     assert worst <= PARITY_V and stats["sweeps"] > 0
+
+
+@pytest.mark.parametrize("prec", [pg.PG_PREC_FP64, pg.PG_PREC_FP32_REFINE])
+def test_probe_norm_bounds_the_fp64_residual(prec):
+    """An opening predicted to converge at once takes the FP32 probe, whose norm must bound the
+    FP64 Jacobi-scaled residual from above and exceed it by at most its rounding term,
+    2^-19 max_i S_i / M_ii with S_i = sum_j |M_ij| (|e_i| + |e_j|) (e = v - Vdd): a state whose
+    residual sits below the tolerance is accepted unchanged with that norm, and one above it is
+    stepped."""
+    from oracle import BESystem, scaled_residual
+    w = small_multilayer(side=40, seed=43, nl=3, pad_every=8, steps=4)
+    mesh = w.meshes[0]
+    circ, info = mesh_to_circuit(mesh, None)
+    sysm = BESystem(circ, w.h)
+    rng = np.random.default_rng(17)
+    delta = rng.uniform(0.0, 1.0, mesh.n)
+    none = np.zeros(0)
+    unit = scaled_residual(sysm, mesh.vdd - delta, none, mesh.vdd - delta, none)  # linear in delta
+    tol = 1e-6
+    A = abs(sysm.M.tocsr())
+    rowsum = np.asarray(A.sum(axis=1)).ravel()
+    for target, quiet in ((0.3 * tol, True), (3.0 * tol, False)):
+        vq = mesh.vdd - delta * (target / unit)
+        true = scaled_residual(sysm, vq, none, vq, none)
+        e = np.abs(vq - mesh.vdd)
+        # sum_j |M_ij| |e_j| + (sum_j |M_ij|) |e_i| covers S_i (M_ii >= G0_i + sum_j g_ij)
+        slack = 2.0 ** -19 * float(np.max((A @ e + rowsum * e) / sysm.M.diagonal()))
+        say(f"[gpu] probe bound prec={prec} target={target:.1e} true={true:.3e} slack={slack:.1e}")
+        with gpu_context(w, precision=prec, tol=tol, omega=1.6) as ctx:
+            ctx.set_pulses(0, 0, Pulses(np.zeros(0, np.int32), np.zeros(0), np.zeros(0), np.zeros(0)))
+            ctx.step(2)  # converged at once from v = Vdd: the next opening is a probe
+            ctx.set_state(0, 0, vq)
+            ctx.step(1)
+            st = ctx.stats()
+            v1 = ctx.read_voltages()
+        if quiet:
+            say(f"  accepted: probe norm={st['last_residual']:.6e}")
+            assert st["last_step_sweeps"] == 0 and np.array_equal(v1, vq)
+            assert true <= st["last_residual"] <= true * (1 + 1e-9) + slack
+        else:
+            assert st["last_step_sweeps"] > 0 and st["last_residual"] <= tol
