@@ -31,18 +31,9 @@ template <> struct Vec2<float> { using type = float2; };
 template <> struct Vec2<double> { using type = double2; };
 template <typename T> using V2 = typename Vec2<T>::type;
 
-// Device buffers reach the kernels as generic pointers (through the grid descriptors), and a
-// load through a generic pointer is a flat load, which also counts against the scalar/LDS wait
-// counter: every wait for a descriptor field or an LDS value would then drain the vector loads
-// in flight as well.  These helpers address the global segment directly (every buffer they
-// touch is device or host-mapped global memory), so the two counters stay apart.
-#define PG_GLOBAL __attribute__((address_space(1)))
-template <typename T>
-__device__ __forceinline__ T ld1(const T* __restrict__ p, int64_t i) {
-  return ((const PG_GLOBAL T*)p)[i];
-}
-// pairs move as native two-element vectors (the HIP vector classes copy through generic
-// references, which would turn the access back into a flat one)
+// Pairs move through the global segment (ld1 in pgrid_internal.h says why) as native
+// two-element vectors: the HIP vector classes copy through generic references, which would turn
+// the access back into a flat one.
 template <typename T> using NV2 = T __attribute__((ext_vector_type(2)));
 template <typename T>
 __device__ __forceinline__ V2<T> ld2(const T* __restrict__ p, int64_t i) {
@@ -107,6 +98,82 @@ __device__ __forceinline__ void load_pair(const GridDesc& G, const T* __restrict
   const V2<T> rr = ld2(r, l * (int64_t)G.X * G.ny + (int64_t)y * G.X + x);
   mine.r = pick(rr, e);
   other.r = pick(rr, 1 - e);
+}
+
+// A pair's coefficients and right-hand side as they come from memory (both nodes, as native
+// vectors), so a kernel can issue the loads of one layer while it computes another, and pick a
+// node's values only where it uses them.
+template <typename T>
+struct PairRaw {
+  NV2<T> ge, gn, gs, gu, gd, iv, rr;
+  T gw;
+};
+
+template <typename T>
+__device__ __forceinline__ NV2<T> ld2n(const T* __restrict__ p, int64_t i) {
+  return *((const PG_GLOBAL NV2<T>*)(p + i));
+}
+
+template <typename T, int NL>
+__device__ __forceinline__ void load_pair_raw(const GridDesc& G, const T* __restrict__ gE, const T* __restrict__ gN,
+                                              const T* __restrict__ gU, const T* __restrict__ invD,
+                                              const T* __restrict__ r, int l, int y, int x, PairRaw<T>& p) {
+  const int64_t P = (int64_t)G.X * G.ny;
+  const int64_t i = l * P + (int64_t)y * G.X + x;
+  const NV2<T> z = {T(0), T(0)};
+  p.ge = ld2n(gE, i);
+  p.gn = ld2n(gN, i);
+  p.iv = ld2n(invD, i);
+  p.rr = ld2n(r, i);
+  p.gs = y > 0 ? ld2n(gN, i - G.X) : z;
+  p.gw = x > 0 ? ld1(gE, i - 1) : T(0);
+  p.gu = z;
+  p.gd = z;
+  if (NL > 1) {
+    if (l < NL - 1) p.gu = ld2n(gU, i);
+    if (l > 0) p.gd = ld2n(gU, i - P);
+  }
+}
+
+// Element e of a raw pair (element 1's west edge is element 0's east edge).
+template <typename T>
+__device__ __forceinline__ NodeCoef<T> node_of(const PairRaw<T>& p, int e) {
+  const NV2<T> ge = p.ge, gn = p.gn, gs = p.gs, gu = p.gu, gd = p.gd, iv = p.iv, rr = p.rr;
+  NodeCoef<T> k;
+  k.e = e ? ge.y : ge.x;
+  k.w = e ? ge.x : p.gw;
+  k.n = e ? gn.y : gn.x;
+  k.s = e ? gs.y : gs.x;
+  k.u = e ? gu.y : gu.x;
+  k.d = e ? gd.y : gd.x;
+  k.inv = e ? iv.y : iv.x;
+  k.r = e ? rr.y : rr.x;
+  return k;
+}
+
+// One node's coefficients and right-hand side, word by word (node xn of row y, layer l): the
+// words load_pair_raw reads for that node.
+template <typename T, int NL>
+__device__ __forceinline__ NodeCoef<T> load_node(const GridDesc& G, const T* __restrict__ gE,
+                                                 const T* __restrict__ gN, const T* __restrict__ gU,
+                                                 const T* __restrict__ invD, const T* __restrict__ r, int l, int y,
+                                                 int xn) {
+  const int64_t P = (int64_t)G.X * G.ny;
+  const int64_t i = l * P + (int64_t)y * G.X + xn;
+  NodeCoef<T> k;
+  k.e = ld1(gE, i);
+  k.w = xn > 0 ? ld1(gE, i - 1) : T(0);
+  k.n = ld1(gN, i);
+  k.s = y > 0 ? ld1(gN, i - G.X) : T(0);
+  k.u = T(0);
+  k.d = T(0);
+  if (NL > 1) {
+    if (l < NL - 1) k.u = ld1(gU, i);
+    if (l > 0) k.d = ld1(gU, i - P);
+  }
+  k.inv = ld1(invD, i);
+  k.r = ld1(r, i);
+  return k;
 }
 
 // SOR update of element e of the staged pair (l, hy, hp) from its staged neighbours.
@@ -677,23 +744,44 @@ __device__ void probe_tile(const Tile* __restrict__ tiles, int ti, const GridDes
   const double inv_vdd = 1.0 / vdd;
   double m = 0.0;
   if (x < X && y < ny) {
+    // one layer's words; the next layer's loads are issued before this layer is evaluated
+    struct Words {
+      NV2<T> ge, gn, gs, gu, gd, iv;
+      T gw;
+      NV2<double> bc;
+    };
+    auto load = [&](int l, Words& w) {
+      const int64_t i = l * P + (int64_t)y * X + x;
+      const NV2<T> z = {T(0), T(0)};
+      w.ge = ld2n(sE, i);
+      w.gn = ld2n(sN, i);
+      w.iv = ld2n(sI, i);
+      w.gs = y > 0 ? ld2n(sN, i - X) : z;
+      w.gw = x > 0 ? ld1(sE, i - 1) : T(0);
+      w.gu = z;
+      w.gd = z;
+      if (NL > 1) {
+        if (l < NL - 1) w.gu = ld2n(sU, i);
+        if (l > 0) w.gd = ld2n(sU, i - P);
+      }
+      w.bc = NV2<double>{0.0, 0.0};
+      if ((G.bc_layers >> l) & 1u) w.bc = ld2n(G.bconst64, i);
+    };
+    // (with inductors the history loop needs the registers: each layer loads as it starts)
+    Words cur, nxt;
+    load(0, cur);
 #pragma unroll
     for (int l = 0; l < NL; ++l) {
+      if (IND) {
+        if (l > 0) load(l, cur);
+      } else if (l + 1 < NL) {
+        load(l + 1, nxt);
+      }
       const int64_t i = l * P + (int64_t)y * X + x;
-      const V2<T> ge = ld2(sE, i), gn = ld2(sN, i), iv = ld2(sI, i);
-      const V2<T> gs = y > 0 ? ld2(sN, i - X) : zero2<T>();
-      const T gw = x > 0 ? ld1(sE, i - 1) : T(0);
-      V2<T> gu = zero2<T>(), gd = zero2<T>();
-      if (NL > 1) {
-        if (l < NL - 1) gu = ld2(sU, i);
-        if (l > 0) gd = ld2(sU, i - P);
-      }
+      const NV2<T> ge = cur.ge, gn = cur.gn, gs = cur.gs, gu = cur.gu, gd = cur.gd, iv = cur.iv;
+      const T gw = cur.gw;
+      const float2 pad = make_float2((float)(cur.bc.x * inv_vdd), (float)(cur.bc.y * inv_vdd));
       double2 hist = make_double2(0.0, 0.0);
-      float2 pad = make_float2(0.0f, 0.0f);
-      if ((G.bc_layers >> l) & 1u) {
-        const double2 bc = ld2(G.bconst64, i);
-        pad = make_float2((float)(bc.x * inv_vdd), (float)(bc.y * inv_vdd));
-      }
       if (IND && G.n_ind) {  // history_i: alpha_k i_k summed over branches k leaving node i, minus entering
         const double* __restrict__ il = G.ind_i + (int64_t)tl.scen * G.n_ind;
         for (int q = 0; q < 2; ++q) {
@@ -732,6 +820,7 @@ __device__ void probe_tile(const Tile* __restrict__ tiles, int ti, const GridDes
       const double q1 = fabs((double)r1 - hist.y) + (double)(kBound * s1);
       if (x < nx) m = nan_max(m, q0 * ((double)iv.x * kWiden));
       if (x + 1 < nx) m = nan_max(m, q1 * ((double)iv.y * kWiden));
+      if (!IND && l + 1 < NL) cur = nxt;
     }
   }
   for (int o = 32; o > 0; o >>= 1) m = nan_max(m, __shfl_xor(m, o, 64));
@@ -808,20 +897,25 @@ __global__ __launch_bounds__(64 * TY) void k_sweep_rb(const Tile* __restrict__ t
   const int hp = lane + 1, hy = row + 2;
   const bool mine = x < X && y < ny;
 
-  // red half-sweep on the owned pairs; keep the black partner's coefficients
+  // red half-sweep on the owned pairs; keep the black partner's coefficients.  Each layer's
+  // update runs while the next layer's loads are in flight.
   NodeCoef<T> keep[NL];
   if (mine) {
+    PairRaw<T> cur, nxt;
+    load_pair_raw<T, NL>(G, gE, gN, gU, invD, r, 0, y, x, cur);
 #pragma unroll
     for (int l = 0; l < NL; ++l) {
+      if (l + 1 < NL) load_pair_raw<T, NL>(G, gE, gN, gU, invD, r, l + 1, y, x, nxt);
       const int er = (y + l) & 1;  // x is even: the pair's red node is x + er
-      NodeCoef<T> kr;
-      load_pair<T, NL>(G, gE, gN, gU, invD, r, l, y, x, er, kr, keep[l]);
-      const T nv = relax<T, NL, HY, HP>(sd, l, hy, hp, er, kr, omega);
+      keep[l] = node_of(cur, 1 - er);
+      const T nv = relax<T, NL, HY, HP>(sd, l, hy, hp, er, node_of(cur, er), omega);
       put(sd[l][hy][hp], er, nv);
+      if (l + 1 < NL) cur = nxt;
     }
   }
   // red half-sweep on the one-node ring: rows y0-1 and y0+TY (tile columns), and the
-  // columns x0-1 and x0+TX (tile rows).  Only the ring node of each edge pair is updated.
+  // columns x0-1 and x0+TX (tile rows).  Only the ring node of each edge pair is updated, so
+  // only its words are loaded.
   constexpr int NRING = 2 * NP + 2 * TY;
   for (int k = threadIdx.x; k < NL * NRING; k += NT) {
     const int l = k / NRING;
@@ -841,8 +935,7 @@ __global__ __launch_bounds__(64 * TY) void k_sweep_rb(const Tile* __restrict__ t
     if (gx < 0 || gx >= X || gy < 0 || gy >= ny) continue;
     const int er = (gy + l) & 1;
     if (want >= 0 && er != want) continue;
-    NodeCoef<T> kr, kb;
-    load_pair<T, NL>(G, gE, gN, gU, invD, r, l, gy, gx, er, kr, kb);
+    const NodeCoef<T> kr = load_node<T, NL>(G, gE, gN, gU, invD, r, l, gy, gx + er);
     const T nv = relax<T, NL, HY, HP>(sd, l, rhy, rhp, er, kr, omega);
     put(sd[l][rhy][rhp], er, nv);
   }

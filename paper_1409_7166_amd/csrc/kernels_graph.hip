@@ -156,31 +156,34 @@ __global__ __launch_bounds__(kChunk) void k_graph_sweep(const GraphChunk* __rest
   T* __restrict__ d = static_cast<T*>(G.d[0]) + off;
   const T* __restrict__ r = static_cast<const T*>(G.r) + off;
   const T* __restrict__ wv = static_cast<const T*>(G.sl_ws);
-  const int base = G.sl_off[i >> 6] + (i & 63), w = (G.sl_off[(i >> 6) + 1] - G.sl_off[i >> 6]) >> 6;
+  // chunks start on 64-slot slices and cover whole ones, so the slice is uniform over the wave
+  const int sl = __builtin_amdgcn_readfirstlane(i >> 6);
+  const int o0 = ld1(G.sl_off, sl), o1 = ld1(G.sl_off, sl + 1);
+  const int base = o0 + (i & 63), w = (o1 - o0) >> 6;
   // zero_in: only neighbours already updated in this sweep (slot < lim) carry a value
   const int lim = zero_in ? ch.lim : 0x7fffffff;
-  T acc = r[i];
+  T acc = ld1(r, i);
+  const T inv = ld1(static_cast<const T*>(G.invDs), i);
+  const T old = zero_in ? T(0) : ld1(d, i);
   int k = 0;
   for (; k + 4 <= w; k += 4) {  // four table entries, then their four gathers, in flight together
     int j[4];
     T g[4], dj[4];
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-      j[q] = G.sl_col[base + ((k + q) << 6)];
-      g[q] = wv[base + ((k + q) << 6)];
+      j[q] = ld1(G.sl_col, base + ((k + q) << 6));
+      g[q] = ld1(wv, base + ((k + q) << 6));
     }
 #pragma unroll
-    for (int q = 0; q < 4; ++q) dj[q] = j[q] < lim ? d[j[q]] : T(0);
+    for (int q = 0; q < 4; ++q) dj[q] = j[q] < lim ? ld1(d, j[q]) : T(0);
 #pragma unroll
     for (int q = 0; q < 4; ++q) acc += g[q] * dj[q];
   }
   for (; k < w; ++k) {
-    const int j = G.sl_col[base + (k << 6)];
-    if (j < lim) acc += wv[base + (k << 6)] * d[j];
+    const int j = ld1(G.sl_col, base + (k << 6));
+    if (j < lim) acc += ld1(wv, base + (k << 6)) * ld1(d, j);
   }
-  const T inv = static_cast<const T*>(G.invDs)[i];
-  const T old = zero_in ? T(0) : d[i];
-  d[i] = old + omega * (inv * acc - old);
+  st1(d, i, old + omega * (inv * acc - old));
 }
 
 // FP64 residual r = b - M v' with v' = v + d[0] (has_d) written to the other voltage buffer, r in
@@ -202,30 +205,32 @@ __global__ __launch_bounds__(kChunk) void k_graph_resid(const GraphChunk* __rest
   double m = 0.0;
   if ((int)threadIdx.x < ch.count) {
     const int i = ch.slot0 + (int)threadIdx.x;
-    const double D = G.D64[i];
-    const double own = has_d ? v[i] + (double)d[i] : v[i];
-    double acc = G.b[off + i] - D * own;
-    const int base = G.sl_off[i >> 6] + (i & 63), w = (G.sl_off[(i >> 6) + 1] - G.sl_off[i >> 6]) >> 6;
+    const double D = ld1(G.D64, i);
+    const double own = has_d ? ld1(v, i) + (double)ld1(d, i) : ld1(v, i);
+    double acc = ld1(G.b, off + i) - D * own;
+    const int sl = __builtin_amdgcn_readfirstlane(i >> 6);  // uniform over the wave (see k_graph_sweep)
+    const int o0 = ld1(G.sl_off, sl), o1 = ld1(G.sl_off, sl + 1);
+    const int base = o0 + (i & 63), w = (o1 - o0) >> 6;
     int k = 0;
     for (; k + 4 <= w; k += 4) {  // four table entries, then their gathers, in flight together
       int j[4];
       double g[4], x[4];
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
-        j[q] = G.sl_col[base + ((k + q) << 6)];
-        g[q] = G.sl_w64[base + ((k + q) << 6)];
+        j[q] = ld1(G.sl_col, base + ((k + q) << 6));
+        g[q] = ld1(G.sl_w64, base + ((k + q) << 6));
       }
 #pragma unroll
-      for (int q = 0; q < 4; ++q) x[q] = has_d ? v[j[q]] + (double)d[j[q]] : v[j[q]];
+      for (int q = 0; q < 4; ++q) x[q] = has_d ? ld1(v, j[q]) + (double)ld1(d, j[q]) : ld1(v, j[q]);
 #pragma unroll
       for (int q = 0; q < 4; ++q) acc += g[q] * x[q];
     }
     for (; k < w; ++k) {
-      const int j = G.sl_col[base + (k << 6)];
-      acc += G.sl_w64[base + (k << 6)] * (has_d ? v[j] + (double)d[j] : v[j]);
+      const int j = ld1(G.sl_col, base + (k << 6));
+      acc += ld1(G.sl_w64, base + (k << 6)) * (has_d ? ld1(v, j) + (double)ld1(d, j) : ld1(v, j));
     }
-    if (has_d) G.v[vi ^ 1][off + i] = own;
-    static_cast<T*>(G.r)[off + i] = (T)acc;
+    if (has_d) st1(G.v[vi ^ 1], off + i, own);
+    st1(static_cast<T*>(G.r), off + i, (T)acc);
     if (D > 0.0) m = fabs(acc) / D;  // padding slots (D = 0) carry r = 0
   }
   for (int o = 32; o > 0; o >>= 1) m = nan_max(m, __shfl_xor(m, o, 64));

@@ -24,6 +24,21 @@ __device__ __forceinline__ int xcd_tile(int ntiles) {
 inline unsigned xcd_blocks(int ntiles) { return 8u * (unsigned)((ntiles + 7) / 8); }
 
 // max that keeps a NaN (a diverged residual must never read as converged)
+// Device buffers reach the kernels as generic pointers (through the grid descriptors), and a
+// load through a generic pointer is a flat load, which also counts against the scalar/LDS wait
+// counter: every wait for a descriptor field or an LDS value would then drain the vector loads
+// in flight as well.  These helpers address the global segment directly (every buffer they
+// touch is device or host-mapped global memory), so the two counters stay apart.
+#define PG_GLOBAL __attribute__((address_space(1)))
+template <typename T>
+__device__ __forceinline__ T ld1(const T* __restrict__ p, int64_t i) {
+  return ((const PG_GLOBAL T*)p)[i];
+}
+template <typename T>
+__device__ __forceinline__ void st1(T* __restrict__ p, int64_t i, T v) {
+  ((PG_GLOBAL T*)p)[i] = v;
+}
+
 __device__ __forceinline__ double nan_max(double m, double x) {
   return (x > m || x != x) ? x : m;
 }

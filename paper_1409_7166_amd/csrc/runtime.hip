@@ -2449,6 +2449,8 @@ extern "C" pg_status pg_autotune(pg_ctx* c, int32_t nsteps, const char* cache_pa
     if (chosen) *chosen = best;
     return PG_OK;
   }
+  // report what runs: 0 sweeps per launch means the default, one
+  if (best.sweeps_per_launch == 0) best.sweeps_per_launch = 1;
   Snapshot sn;
   PG_TRY(take_snapshot(c, sn));
   auto trial = [&](const pg_options& o, double* secs) -> pg_status {
@@ -2495,6 +2497,7 @@ extern "C" pg_status pg_autotune(pg_ctx* c, int32_t nsteps, const char* cache_pa
     if (t < best_t) { best_t = t; best = o; }
   }
   for (int f = 1; f <= 2 && best.ordering == PG_ORDER_RED_BLACK; ++f) {
+    if (f == best.sweeps_per_launch) continue;
     pg_options o = best;
     o.sweeps_per_launch = f;
     double t;
