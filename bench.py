@@ -47,7 +47,7 @@ def parse():
     ap.add_argument("--graphs", type=int, default=-1, help="replay each step from captured HIP graphs (1) or "
                                                            "launch kernels one by one (0); -1: the workload's "
                                                            "tuned choice")
-    ap.add_argument("--profile-every", type=int, default=8,
+    ap.add_argument("--profile-every", type=int, default=32,
                     help="time every n-th sweep block, residual pass and other launch with HIP events "
                          "during the timed region (0: off)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
