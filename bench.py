@@ -231,7 +231,7 @@ def copy_probe():
 
 # (workload, precision, tolerance, steps) of the side-by-side report
 SIDE_BY_SIDE = [
-    ("config1", "fp32+ref", 1e-6, 1000), ("config1", "fp64", 1e-6, 1000), ("config1", "fp32+ref", 1e-9, 300),
+    ("config1", "fp32+ref", 1e-6, 1000), ("config1", "fp64", 1e-6, 1000), ("config1", "fp32+ref", 1e-10, 300),
     ("config3a", "fp32+ref", 1e-6, 500), ("config3b", "fp32+ref", 1e-6, 500),
     ("config2", "fp64", 1e-6, 2000), ("config2", "fp32+ref", 1e-6, 2000),
     ("config4", "fp64", 1e-6, 200), ("config0", "fp64", 1e-6, 100),
