@@ -1025,50 +1025,133 @@ __global__ __launch_bounds__(64 * TY) void k_sweep_rb_multi(const Tile* __restri
     ring_i[t] = l * P + (int64_t)gy * X + gx + er;
   }
 
-  for (int sc = 0; sc < tl.pad; ++sc) {
-    if (!c.active[tl.item + sc]) continue;  // uniform across the block
-    const int64_t off = (int64_t)(tl.scen + sc) * G.nstore;
-    const T* __restrict__ dold = static_cast<const T*>(G.d[din]) + off;
-    T* __restrict__ dnew = static_cast<T*>(G.d[din ^ 1]) + off;
-    const T* __restrict__ r = static_cast<const T*>(G.r) + off;
-    __syncthreads();  // the previous scenario's readers are done with sd
-    for (int k = threadIdx.x; k < NL * HY * HP; k += NT) {
-      const int l = k / (HY * HP);
-      const int rem = k - l * (HY * HP);
-      const int shy = rem / HP, shp = rem - shy * HP;
-      const int sx = x0 - 2 + 2 * shp, sy = y0 - 2 + shy;
-      V2<T> val = zero2<T>();
-      if (!zero_in && sx >= 0 && sx < X && sy >= 0 && sy < ny) val = ld2(dold, l * P + (int64_t)sy * X + sx);
-      sd[l][shy][shp] = val;
-    }
-    __syncthreads();
-    if (mine) {
+  // The scenario loop.  Single-layer FP32 blocks first collect the block's still-iterating
+  // scenarios (at most 16) and keep one scenario of loads in flight ahead: while scenario s is
+  // swept, the next active one's old correction and right-hand side are already being read.
+  // Elsewhere the second set of registers would cost occupancy or spills, so each scenario loads
+  // as it starts.
+  constexpr bool kAhead = NL == 1 && sizeof(T) == 4;
+  if constexpr (kAhead) {
+    unsigned amask = 0u;
+    for (int sc = 0; sc < tl.pad; ++sc) amask |= (c.active[tl.item + sc] ? 1u : 0u) << sc;
+    constexpr int NS = NL * HY * HP, SPT = (NS + NT - 1) / NT;
+    struct Loads {
+      V2<T> stage[SPT];
+      V2<T> rr[NL];
+      T rring[RT];
+    };
+    auto issue = [&](int sc, Loads& L) {
+      const int64_t off = (int64_t)(tl.scen + sc) * G.nstore;
+      const T* __restrict__ dold = static_cast<const T*>(G.d[din]) + off;
+      const T* __restrict__ r = static_cast<const T*>(G.r) + off;
 #pragma unroll
-      for (int l = 0; l < NL; ++l) {
-        const int er = (y + l) & 1;
-        const V2<T> rr = ld2(r, l * P + (int64_t)y * X + x);
-        kr[l].r = pick(rr, er);
-        kb[l].r = pick(rr, 1 - er);
-        const T nv = relax<T, NL, HY, HP>(sd, l, hy, hp, er, kr[l], omega);
-        put(sd[l][hy][hp], er, nv);
+      for (int q = 0; q < SPT; ++q) {
+        const int k = threadIdx.x + q * NT;
+        const int l = k / (HY * HP);
+        const int rem = k - l * (HY * HP);
+        const int shy = rem / HP, shp = rem - shy * HP;
+        const int sx = x0 - 2 + 2 * shp, sy = y0 - 2 + shy;
+        L.stage[q] = zero2<T>();
+        if (!zero_in && k < NS && sx >= 0 && sx < X && sy >= 0 && sy < ny) L.stage[q] = ld2(dold, l * P + (int64_t)sy * X + sx);
       }
-    }
 #pragma unroll
-    for (int t = 0; t < RT; ++t) {
-      if (ring_e[t] < 0) continue;
-      kring[t].r = r[ring_i[t]];
-      const T nv = relax<T, NL, HY, HP>(sd, ring_l[t], ring_hy[t], ring_hp[t], ring_e[t], kring[t], omega);
-      put(sd[ring_l[t]][ring_hy[t]][ring_hp[t]], ring_e[t], nv);
-    }
-    __syncthreads();
-    if (mine) {
+      for (int l = 0; l < NL; ++l) L.rr[l] = mine ? ld2(r, l * P + (int64_t)y * X + x) : zero2<T>();
 #pragma unroll
-      for (int l = 0; l < NL; ++l) {
-        const int eb = 1 - ((y + l) & 1);
-        V2<T> out = sd[l][hy][hp];
-        const T nv = relax<T, NL, HY, HP>(sd, l, hy, hp, eb, kb[l], omega);
-        put(out, eb, nv);
-        st2(dnew, l * P + (int64_t)y * X + x, out);
+      for (int t = 0; t < RT; ++t) L.rring[t] = ring_e[t] >= 0 ? ld1(r, ring_i[t]) : T(0);
+    };
+    Loads cur, nxt;
+    int sc = amask ? __builtin_ctz(amask) : -1;
+    if (sc >= 0) issue(sc, cur);
+    while (sc >= 0) {
+      const unsigned rest = amask & ~((2u << sc) - 1u);  // active scenarios after sc
+      const int sn = rest ? __builtin_ctz(rest) : -1;
+      if (sn >= 0) issue(sn, nxt);
+      const int64_t off = (int64_t)(tl.scen + sc) * G.nstore;
+      T* __restrict__ dnew = static_cast<T*>(G.d[din ^ 1]) + off;
+      __syncthreads();  // the previous scenario's readers are done with sd
+#pragma unroll
+      for (int q = 0; q < SPT; ++q) {
+        const int k = threadIdx.x + q * NT;
+        if (k < NS) (&sd[0][0][0])[k] = cur.stage[q];
+      }
+      __syncthreads();
+      if (mine) {
+#pragma unroll
+        for (int l = 0; l < NL; ++l) {
+          const int er = (y + l) & 1;
+          kr[l].r = pick(cur.rr[l], er);
+          kb[l].r = pick(cur.rr[l], 1 - er);
+          const T nv = relax<T, NL, HY, HP>(sd, l, hy, hp, er, kr[l], omega);
+          put(sd[l][hy][hp], er, nv);
+        }
+      }
+#pragma unroll
+      for (int t = 0; t < RT; ++t) {
+        if (ring_e[t] < 0) continue;
+        kring[t].r = cur.rring[t];
+        const T nv = relax<T, NL, HY, HP>(sd, ring_l[t], ring_hy[t], ring_hp[t], ring_e[t], kring[t], omega);
+        put(sd[ring_l[t]][ring_hy[t]][ring_hp[t]], ring_e[t], nv);
+      }
+      __syncthreads();
+      if (mine) {
+#pragma unroll
+        for (int l = 0; l < NL; ++l) {
+          const int eb = 1 - ((y + l) & 1);
+          V2<T> out = sd[l][hy][hp];
+          const T nv = relax<T, NL, HY, HP>(sd, l, hy, hp, eb, kb[l], omega);
+          put(out, eb, nv);
+          st2(dnew, l * P + (int64_t)y * X + x, out);
+        }
+      }
+      sc = sn;
+      if (sn >= 0) cur = nxt;
+    }
+  } else {
+    for (int sc = 0; sc < tl.pad; ++sc) {
+      if (!c.active[tl.item + sc]) continue;  // uniform across the block
+      const int64_t off = (int64_t)(tl.scen + sc) * G.nstore;
+      const T* __restrict__ dold = static_cast<const T*>(G.d[din]) + off;
+      T* __restrict__ dnew = static_cast<T*>(G.d[din ^ 1]) + off;
+      const T* __restrict__ r = static_cast<const T*>(G.r) + off;
+      __syncthreads();  // the previous scenario's readers are done with sd
+      for (int k = threadIdx.x; k < NL * HY * HP; k += NT) {
+        const int l = k / (HY * HP);
+        const int rem = k - l * (HY * HP);
+        const int shy = rem / HP, shp = rem - shy * HP;
+        const int sx = x0 - 2 + 2 * shp, sy = y0 - 2 + shy;
+        V2<T> val = zero2<T>();
+        if (!zero_in && sx >= 0 && sx < X && sy >= 0 && sy < ny) val = ld2(dold, l * P + (int64_t)sy * X + sx);
+        sd[l][shy][shp] = val;
+      }
+      __syncthreads();
+      if (mine) {
+#pragma unroll
+        for (int l = 0; l < NL; ++l) {
+          const int er = (y + l) & 1;
+          const V2<T> rr = ld2(r, l * P + (int64_t)y * X + x);
+          kr[l].r = pick(rr, er);
+          kb[l].r = pick(rr, 1 - er);
+          const T nv = relax<T, NL, HY, HP>(sd, l, hy, hp, er, kr[l], omega);
+          put(sd[l][hy][hp], er, nv);
+        }
+      }
+#pragma unroll
+      for (int t = 0; t < RT; ++t) {
+        if (ring_e[t] < 0) continue;
+        kring[t].r = r[ring_i[t]];
+        const T nv = relax<T, NL, HY, HP>(sd, ring_l[t], ring_hy[t], ring_hp[t], ring_e[t], kring[t], omega);
+        put(sd[ring_l[t]][ring_hy[t]][ring_hp[t]], ring_e[t], nv);
+      }
+      __syncthreads();
+      if (mine) {
+#pragma unroll
+        for (int l = 0; l < NL; ++l) {
+          const int eb = 1 - ((y + l) & 1);
+          V2<T> out = sd[l][hy][hp];
+          const T nv = relax<T, NL, HY, HP>(sd, l, hy, hp, eb, kb[l], omega);
+          put(out, eb, nv);
+          st2(dnew, l * P + (int64_t)y * X + x, out);
+        }
       }
     }
   }
