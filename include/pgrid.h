@@ -120,11 +120,15 @@ typedef struct pg_stats {
   int64_t steps;              /* backward-Euler steps completed */
   int64_t sweeps;             /* sweeps summed over grids */
   int64_t node_updates;       /* sum over sweeps of active nodes x scenarios */
-  int64_t checks;             /* FP64 residual passes */
+  int64_t checks;             /* residual passes (each followed by a decision) */
   int32_t last_step_sweeps;   /* max over grids, last step */
   int32_t max_step_sweeps;    /* max over steps and grids */
-  double last_residual;       /* max over grids of the final scaled residual of the last step, V */
-  double max_final_residual;  /* max over steps of the final scaled residual, V */
+  /* The final scaled residual max_i |(b - M v)_i| / M_ii of a step, V.  For a step that
+   * converged at its opening (no sweep) on a mesh with a non-zero supply it is the opening
+   * probe's value, an upper bound of the FP64 norm that exceeds it by at most its rounding
+   * term (single-precision arithmetic on v - Vdd). */
+  double last_residual;       /* max over grids, last step */
+  double max_final_residual;  /* max over steps */
   double seconds;             /* wall time inside pg_step / pg_run_transient */
 } pg_stats;
 
