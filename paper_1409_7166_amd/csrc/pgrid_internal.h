@@ -23,7 +23,6 @@ __device__ __forceinline__ int xcd_tile(int ntiles) {
 }
 inline unsigned xcd_blocks(int ntiles) { return 8u * (unsigned)((ntiles + 7) / 8); }
 
-// max that keeps a NaN (a diverged residual must never read as converged)
 // Device buffers reach the kernels as generic pointers (through the grid descriptors), and a
 // load through a generic pointer is a flat load, which also counts against the scalar/LDS wait
 // counter: every wait for a descriptor field or an LDS value would then drain the vector loads
@@ -39,6 +38,7 @@ __device__ __forceinline__ void st1(T* __restrict__ p, int64_t i, T v) {
   ((PG_GLOBAL T*)p)[i] = v;
 }
 
+// max that keeps a NaN (a diverged residual must never read as converged)
 __device__ __forceinline__ double nan_max(double m, double x) {
   return (x > m || x != x) ? x : m;
 }
