@@ -190,7 +190,8 @@ __global__ __launch_bounds__(kChunk) void k_graph_sweep(const GraphChunk* __rest
 // the sweep precision, and the Jacobi-scaled norm max |r_i| / M_ii of the chunk's item.
 template <typename T>
 __global__ __launch_bounds__(kChunk) void k_graph_resid(const GraphChunk* __restrict__ chunks, int n,
-                                                       const GridDesc* __restrict__ grids, Ctl c, int has_d) {
+                                                       const GridDesc* __restrict__ grids, Ctl c, int has_d,
+                                                       int norm) {
   __shared__ double wmax[kChunk / 64];
   if (*c.stall) return;
   const int ci = xcd_tile(n);
@@ -232,6 +233,90 @@ __global__ __launch_bounds__(kChunk) void k_graph_resid(const GraphChunk* __rest
     if (has_d) st1(G.v[vi ^ 1], off + i, own);
     st1(static_cast<T*>(G.r), off + i, (T)acc);
     if (D > 0.0) m = fabs(acc) / D;  // padding slots (D = 0) carry r = 0
+  }
+  if (!norm) return;  // uniform over the grid
+  for (int o = 32; o > 0; o >>= 1) m = nan_max(m, __shfl_xor(m, o, 64));
+  if ((threadIdx.x & 63) == 0) wmax[threadIdx.x >> 6] = m;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double bm = wmax[0];
+    for (int k = 1; k < kChunk / 64; ++k) bm = nan_max(bm, wmax[k]);
+    raise_max(&c.norm_bits[ch.item], bm);
+  }
+}
+
+// The opening probe of a general netlist: a step predicted to converge at once, with the sources
+// all zero and v' = v.  The C/h terms of b and of M v' cancel exactly (the coupling capacitors'
+// with their off-diagonal entries), and with e = v - vref
+//   r_i = q_i - history_i - gsup_i e_i + sum_j wG_ij (e_j - e_i),
+// wG the conductance part of M's off-diagonal (resistors and inductor companions), gsup_i the
+// conductance from node i to supplies and ground, q_i = (G0 v_s + (h/L) v_s)_i - gsup_i vref.
+// The conductance terms are evaluated in FP32; every rounding in them (of e, wG and gsup, of the
+// differences, products and the sum of k + 1 terms) is a relative error of at most u = 2^-24 on
+// a term of S_i = gsup_i |e_i| + sum_j wG_ij (|e_i| + |e_j|), so (k + 8) 2^-23 S_i, k the row's
+// table width, bounds their total error; the scale 1/M_ii is widened by its rounding.  The
+// result bounds the FP64 norm from above.
+template <typename T>
+__global__ __launch_bounds__(kChunk) void k_graph_probe(const GraphChunk* __restrict__ chunks, int n,
+                                                       const GridDesc* __restrict__ grids, Ctl c) {
+  constexpr double kWiden = sizeof(T) == 4 ? 1.0 + 0x1p-22 : 1.0 + 0x1p-51;
+  __shared__ double wmax[kChunk / 64];
+  if (*c.stall) return;
+  const int ci = xcd_tile(n);
+  if (ci < 0) return;
+  const GraphChunk ch = chunks[ci];
+  if (!c.active[ch.item]) return;  // uniform over the block
+  const GridDesc& G = grids[ch.grid];
+  const int64_t off = (int64_t)ch.scen * G.nstore;
+  const double* __restrict__ v = G.v[c.vidx[ch.item]] + off;
+  const double vref = G.vdd;
+  double m = 0.0;
+  if ((int)threadIdx.x < ch.count) {
+    const int i = ch.slot0 + (int)threadIdx.x;
+    const T inv = ld1(static_cast<const T*>(G.invDs), i);
+    const double q0 = ld1(G.gq64, i);
+    const float gs = ld1(G.gsup32, i);
+    const float ei = (float)(ld1(v, i) - vref), ai = fabsf(ei);
+    // chunks start on 64-slot slices and cover whole ones, so the slice is uniform over the wave
+    const int sl = __builtin_amdgcn_readfirstlane(i >> 6);
+    const int o0 = ld1(G.sl_off, sl), o1 = ld1(G.sl_off, sl + 1);
+    const int base = o0 + (i & 63), w = (o1 - o0) >> 6;
+    float r = -gs * ei, s = gs * ai;
+    int k = 0;
+    for (; k + 4 <= w; k += 4) {  // four table entries, then their gathers, in flight together
+      int j[4];
+      float g[4], ej[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        j[q] = ld1(G.sl_col, base + ((k + q) << 6));
+        g[q] = ld1(G.gw32, base + ((k + q) << 6));
+      }
+#pragma unroll
+      for (int q = 0; q < 4; ++q) ej[q] = (float)(ld1(v, j[q]) - vref);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        r += g[q] * (ej[q] - ei);
+        s += g[q] * (ai + fabsf(ej[q]));
+      }
+    }
+    for (; k < w; ++k) {
+      const float g = ld1(G.gw32, base + (k << 6));
+      const float ej = (float)(ld1(v, ld1(G.sl_col, base + (k << 6))) - vref);
+      r += g * (ej - ei);
+      s += g * (ai + fabsf(ej));
+    }
+    double hist = 0.0;  // b's history: -alpha_k i_k for each branch k leaving node i (+ entering)
+    if (G.n_ind) {
+      const double* __restrict__ il = G.ind_i + (int64_t)ch.scen * G.n_ind;
+      for (int t = G.inc_off[i]; t < G.inc_off[i + 1]; ++t) {
+        const int e = G.inc_ind[t];
+        const int kk = (e > 0 ? e : -e) - 1;
+        const double term = G.ind_alpha[kk] * il[kk];
+        hist += (e > 0) ? -term : term;
+      }
+    }
+    const double bound = fabs(q0 + hist + (double)r) + (double)((float)(w + 8) * 0x1p-23f * s);
+    m = bound * ((double)inv * kWiden);  // padding slots: inv = 0
   }
   for (int o = 32; o > 0; o >>= 1) m = nan_max(m, __shfl_xor(m, o, 64));
   if ((threadIdx.x & 63) == 0) wmax[threadIdx.x >> 6] = m;
@@ -288,13 +373,23 @@ hipError_t launch_graph_sweep(bool fp32, const GraphChunk* ch, int n, const Grid
   return hipGetLastError();
 }
 
-hipError_t launch_graph_resid(bool fp32, const GraphChunk* ch, int n, const GridDesc* grids, const Ctl& c,
-                              int has_d, hipStream_t s) {
+hipError_t launch_graph_probe(bool fp32, const GraphChunk* ch, int n, const GridDesc* grids, const Ctl& c,
+                              hipStream_t s) {
   if (n <= 0) return hipSuccess;
   if (fp32)
-    hipLaunchKernelGGL(k_graph_resid<float>, dim3(xcd_blocks(n)), dim3(kChunk), 0, s, ch, n, grids, c, has_d);
+    hipLaunchKernelGGL(k_graph_probe<float>, dim3(xcd_blocks(n)), dim3(kChunk), 0, s, ch, n, grids, c);
   else
-    hipLaunchKernelGGL(k_graph_resid<double>, dim3(xcd_blocks(n)), dim3(kChunk), 0, s, ch, n, grids, c, has_d);
+    hipLaunchKernelGGL(k_graph_probe<double>, dim3(xcd_blocks(n)), dim3(kChunk), 0, s, ch, n, grids, c);
+  return hipGetLastError();
+}
+
+hipError_t launch_graph_resid(bool fp32, const GraphChunk* ch, int n, const GridDesc* grids, const Ctl& c,
+                              int has_d, hipStream_t s, int norm) {
+  if (n <= 0) return hipSuccess;
+  if (fp32)
+    hipLaunchKernelGGL(k_graph_resid<float>, dim3(xcd_blocks(n)), dim3(kChunk), 0, s, ch, n, grids, c, has_d, norm);
+  else
+    hipLaunchKernelGGL(k_graph_resid<double>, dim3(xcd_blocks(n)), dim3(kChunk), 0, s, ch, n, grids, c, has_d, norm);
   return hipGetLastError();
 }
 

@@ -124,6 +124,12 @@ struct GridDesc {
   const double* sl_g64;
   const double* bres64;
   const double* bl64;
+  // general graph, the opening probe (k_graph_probe): per slot the constant q_i (FP64) and the
+  // conductance gsup_i from the node to supplies and ground (FP32), per table entry the
+  // conductance part of w (resistors and inductor companions, no capacitors; FP32)
+  const double* gq64;
+  const float* gsup32;
+  const float* gw32;
   // coefficient words one sweep reads (for the activity accounting of the decision)
   int64_t coef_words;
   // layered mesh: bit l set if layer l has a non-zero C/h (ch_layers) or a non-zero constant
@@ -302,8 +308,14 @@ hipError_t launch_graph_kcl(const GraphChunk* ch, int n, const GridDesc* grids, 
 hipError_t launch_graph_absmax_b(const GraphChunk* ch, int n, const GridDesc* grids, const Ctl& c, hipStream_t s);
 hipError_t launch_graph_sweep(bool fp32, const GraphChunk* ch, int n, const GridDesc* grids, const Ctl& c,
                               int zero_in, double omega, hipStream_t s);
+// norm = 0: the residual and v are stored but the norm is left alone (the pass that stores b and r
+// after an opening probe found work, whose decision has already taken the norm)
 hipError_t launch_graph_resid(bool fp32, const GraphChunk* ch, int n, const GridDesc* grids, const Ctl& c,
-                              int has_d, hipStream_t s);
+                              int has_d, hipStream_t s, int norm = 1);
+// the opening probe of a step predicted to converge at once (sources all zero, two-level step):
+// an upper bound of the FP64 scaled residual norm into c.norm_bits[item]; stores nothing
+hipError_t launch_graph_probe(bool fp32, const GraphChunk* ch, int n, const GridDesc* grids, const Ctl& c,
+                              hipStream_t s);
 hipError_t launch_gather(const double* src, const int32_t* slot, double* dst, int64_t n, hipStream_t s);
 hipError_t launch_swap_vidx(const Ctl& c, int item, int32_t* saved, hipStream_t s);
 hipError_t launch_inductors(const GridDesc* grids, const int32_t* ind_grid,

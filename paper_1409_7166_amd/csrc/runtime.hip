@@ -63,6 +63,7 @@ struct GridHost {
   DBuf ind_a_d, ind_b_d, ind_geq_d, ind_alpha_d, ind_i_d, inc_off_d, inc_ind_d, ind_vfar_d;
   DBuf slot_d, sl_off_d, sl_col_d, sl_w64_d, sl_ws_d, cap_off_d, cap_col_d, cap_val_d;
   DBuf vprev0, vprev1, g3diag_d, sl_g64_d, bres_d, bl_d;  // three-level recurrence
+  DBuf gq64_d, gsup32_d, gw32_d;                          // opening probe (general graph)
   int sweep_fp32 = -1;                           // precision the sweep buffers were built for
 };
 
@@ -162,6 +163,7 @@ struct pg_ctx {
   bool graphs_ready = false;
   int64_t all_nodes = 0;                         // mesh nodes x scenarios over all grids
   int64_t all_coef = 0;                          // coefficient words over all grids
+  int64_t graph_nodes = 0, graph_coef = 0, graph_entries = 0;  // the general graphs' share (slots x scenarios)
   int64_t begin_nodes = 0, begin_coef = 0;       // work of the step's first residual (items begun)
   long long* host_acct = nullptr;                // pinned [slots][2]: active work after each decision
   long long* dev_acct = nullptr;
@@ -177,7 +179,10 @@ struct pg_ctx {
   bool begun_next = false;                       // the last close also began the next step
   bool prev_valid = false;                       // graph grids' vprev holds v(t-h) (three-level)
   int fuse_next = 0;                             // kFuse* mode of the next residual pass (mesh RHS)
+  bool gprobe_next = false;                      // the next residual pass probes the general graphs
+  bool gstore_next = false;                      // the next residual pass forms and stores their b, r
   bool opening_probe = false;                    // the last queued opening only took the norm
+  bool opening_gprobe = false;                   // ... on the general graphs
   bool opening_closes = false;                   // ... and its decision carries the step's close
   bool capturing = false;                        // launches are being captured into a graph
   std::vector<double> win_t0_host;               // bucket starts of the windowed sources (host copy)
@@ -491,6 +496,33 @@ pg_status build_graph_grid(pg_ctx* c, int gi) {
   const size_t ne = F.col.size();
   std::vector<double> w(ne), cap;
   for (size_t e = 0; e < ne; ++e) w[e] = F.g[e] + h * F.inv_l[e] + (dc ? 0.0 : F.cc[e] / h);
+  // the opening probe's quantities: with e = v - vref, at v' = v and zero sources the residual is
+  // q_i - history_i - gsup_i e_i + sum_j wG_ij (e_j - e_i), wG = the conductance part of w,
+  // gsup_i = D_i - C_i/h - sum_j wG_ij (the conductance to supplies and ground), and
+  // q_i = (G0 v_s + (h/L) v_s)_i - gsup_i vref
+  {
+    std::vector<double> gsum(ns, 0.0);
+    std::vector<float> wg32(ne);
+    const int64_t nsl = (int64_t)F.soff.size() - 1;
+    for (int64_t sl = 0; sl < nsl; ++sl) {
+      const int64_t b0 = F.soff[sl], width = (F.soff[sl + 1] - b0) / kSlice;
+      for (int64_t k = 0; k < width; ++k)
+        for (int j = 0; j < kSlice; ++j) {
+          const int64_t e = b0 + k * kSlice + j;
+          const double wg = F.g[e] + h * F.inv_l[e];
+          gsum[sl * kSlice + j] += wg;
+          wg32[e] = (float)wg;
+        }
+    }
+    std::vector<double> q(ns, 0.0);
+    std::vector<float> gsup(ns, 0.0f);
+    for (int64_t s = 0; s < ns; ++s) {
+      const double gs = (D[s] - ch[s]) - gsum[s];
+      gsup[s] = (float)gs;
+      q[s] = bc[s] - gs * G.vdd;
+    }
+    PG_TRY(upload(c, G.gq64_d, q)); PG_TRY(upload(c, G.gsup32_d, gsup)); PG_TRY(upload(c, G.gw32_d, wg32));
+  }
   if (F.has_coupling) {  // same size at DC (zeros: capacitors open), so the buffer stays put
     cap.assign(F.cval.size(), 0.0);
     if (!dc)
@@ -567,6 +599,7 @@ GridDesc make_desc(pg_ctx* c, GridHost& H) {
     D.vprev[0] = (double*)H.vprev0.p; D.vprev[1] = (double*)H.vprev1.p;
     D.g3diag = (const double*)H.g3diag_d.p; D.sl_g64 = (const double*)H.sl_g64_d.p;
     D.bres64 = (const double*)H.bres_d.p; D.bl64 = (const double*)H.bl_d.p;
+    D.gq64 = (const double*)H.gq64_d.p; D.gsup32 = (const float*)H.gsup32_d.p; D.gw32 = (const float*)H.gw32_d.p;
     // invD, w (the column indices count as half a word in FP64 residuals)
     H.coef_words = H.nstore + (3 * H.form.nnz) / 2;
   } else {
@@ -666,6 +699,7 @@ pg_status prepare(pg_ctx* c) {
   c->ntiles_all = (int)tiles.size();
   c->all_nodes = 0;
   c->all_coef = 0;
+  c->graph_nodes = c->graph_coef = c->graph_entries = 0;
   for (auto& grp : c->tile_groups) c->all_nodes += grp.nodes;
   double fr = 0.0, fp = 0.0, fn = 0.0;
   c->probe_cancelled = true;
@@ -673,6 +707,9 @@ pg_status prepare(pg_ctx* c) {
     c->all_coef += H.coef_words;
     if (H.kind) {
       c->all_nodes += H.n * H.S;
+      c->graph_nodes += H.n * H.S;
+      c->graph_coef += H.coef_words;
+      c->graph_entries += (H.form.soff.empty() ? 0 : (int64_t)H.form.soff.back()) * H.S;  // padded table
     } else {
       const double w = (double)H.n * H.S;
       fr += w * (8.0 + 8.0 * (__builtin_popcount(H.ch_layers) + __builtin_popcount(H.bc_layers)) / H.nl);
@@ -853,21 +890,42 @@ int next_tag(pg_ctx* c) { return (int)(c->flag_seq_host++ & kTagMask); }
 // One residual pass over every tile group; with `tag`, followed by its decision (see
 // pgrid_internal.h), whose tag is returned.
 pg_status launch_resid_all(pg_ctx* c, int has_d, int din, double tol = 0.0, int* tag = nullptr,
-                           const CloseArgs* close = nullptr) {
+                           const CloseArgs* close = nullptr, bool meshes = true) {
   const Tile* T = (const Tile*)c->tiles_sweep.p;
   int fuse = has_d ? 0 : c->fuse_next;
   if ((fuse & kFuseProbe) && c->probe_cancelled) fuse |= kFuseCancelled | (c->n_ind_total ? kFuseInd : 0);
   c->fuse_next = 0;
-  ProfScope ps(c, 1, c->begin_nodes, c->resid_bytes(c->begin_nodes, c->begin_coef, has_d != 0, fuse),
-               (int)c->tile_groups.size() + (c->n_gchunks_all ? 1 : 0) + (tag ? 1 : 0));
+  const bool gprobe = !has_d && c->gprobe_next, gstore = !has_d && c->gstore_next;
+  c->gprobe_next = c->gstore_next = false;
+  double bytes = c->resid_bytes(c->begin_nodes, c->begin_coef, has_d != 0, fuse);
+  if (gprobe || gstore) {  // whole steps only: the meshes' share, then the graphs' by their pass
+    const double e = c->opt.precision == PG_PREC_FP32_REFINE ? 4.0 : 8.0;
+    const double gn = (double)c->graph_nodes;
+    bytes = meshes ? c->resid_bytes(c->all_nodes - c->graph_nodes, c->all_coef - c->graph_coef, false, fuse) : 0.0;
+    if (gprobe)  // v, 1/M_ii, q, gsup per slot; column and FP32 conductance per table entry
+      bytes += (20.0 + e) * gn + 8.0 * (double)c->graph_entries;
+    else  // b formed (C/h, constant, v, b), then r and v stored
+      bytes += 32.0 * gn + (16.0 + e) * gn + 8.0 * (double)c->graph_coef;
+  }
+  ProfScope ps(c, 1, c->begin_nodes, bytes, (int)c->tile_groups.size() + (c->n_gchunks_all ? 1 : 0) + (tag ? 1 : 0));
   for (auto& grp : c->tile_groups) {
+    if (!meshes) break;
     hipError_t e = launch_resid(fp32_mode(c), grp.multi, grp.nl, c->tile_rows, T + grp.off, grp.count,
                                 (const GridDesc*)c->grid_desc.p, c->ctl, has_d, din, fuse, c->stream);
     if (e != hipSuccess) return set_err(c, PG_ERR_DEVICE, "residual launch: %s", hipGetErrorString(e));
   }
-  if (c->n_gchunks_all && !(fuse & kFuseNoNorm)) {  // the storing pass after a probe is mesh-only
-    hipError_t e = launch_graph_resid(fp32_mode(c), (const GraphChunk*)c->g_chunks_all.p, c->n_gchunks_all,
-                                      (const GridDesc*)c->grid_desc.p, c->ctl, has_d, c->stream);
+  if (c->n_gchunks_all) {
+    const GraphChunk* GC = (const GraphChunk*)c->g_chunks_all.p;
+    const GridDesc* GD = (const GridDesc*)c->grid_desc.p;
+    hipError_t e = hipSuccess;
+    if (gprobe) {  // the opening probe
+      e = launch_graph_probe(fp32_mode(c), GC, c->n_gchunks_all, GD, c->ctl, c->stream);
+    } else if (gstore) {  // after a probe that found work: b, then r and v without the norm
+      e = launch_graph_rhs(GC, c->n_gchunks_all, GD, c->ctl, 0, c->stream);
+      if (e == hipSuccess) e = launch_graph_resid(fp32_mode(c), GC, c->n_gchunks_all, GD, c->ctl, 0, c->stream, 0);
+    } else if (!(fuse & kFuseNoNorm)) {  // a mesh-only storing pass leaves the graphs alone
+      e = launch_graph_resid(fp32_mode(c), GC, c->n_gchunks_all, GD, c->ctl, has_d, c->stream);
+    }
     if (e != hipSuccess) return set_err(c, PG_ERR_DEVICE, "residual launch: %s", hipGetErrorString(e));
   }
   if (!tag) return PG_OK;
@@ -1001,11 +1059,16 @@ pg_status begin_step(pg_ctx* c, int only_item, bool begun = false, int64_t dev_s
   // work after all, cycle_loop stores b and r before the first sweep
   c->fuse_next = fuse ? (kFuseRhs | (c->pred_chunks == 0 ? kFuseProbe : 0)) : 0;
   c->opening_probe = (c->fuse_next & kFuseProbe) != 0;
+  // general graphs likewise: a step predicted to converge at once (two-level) opens with
+  // k_graph_probe instead of the right-hand side and residual passes
+  const bool gprobe = only_item < 0 && !loads && c->n_gchunks_all > 0 && !three && c->pred_chunks == 0;
+  c->gprobe_next = gprobe;
+  c->opening_gprobe = gprobe;
   const Tile* T = (const Tile*)c->tiles_all.p;
   int off = 0, cnt = fuse ? 0 : c->ntiles_all;
   if (only_item >= 0) { off = c->item_tile_off[only_item]; cnt = c->item_tile_cnt[only_item]; }
   const GraphChunk* GC = (const GraphChunk*)c->g_chunks_all.p;
-  int goff = 0, gcnt = c->n_gchunks_all;
+  int goff = 0, gcnt = gprobe ? 0 : c->n_gchunks_all;
   if (only_item >= 0) { goff = c->item_gchunk_off[only_item]; gcnt = c->item_gchunk_cnt[only_item]; }
   if (cnt > 0 || gcnt > 0) {
     ProfScope ps(c, 2, 0, 0.0, (cnt > 0 ? 1 : 0) + (gcnt > 0 ? 1 : 0));
@@ -1118,7 +1181,8 @@ pg_status cycle_loop(pg_ctx* c, double tol, bool graphs, int first, bool specula
   // the step's opening only took the norm (a probe): its b and r are stored before the first
   // sweep, by a pass that leaves the decided norm alone
   bool need_store = c->opening_probe;
-  c->opening_probe = false;
+  bool need_gstore = c->opening_gprobe;
+  c->opening_probe = c->opening_gprobe = false;
   const bool closed_ahead = c->opening_closes;  // the opening's decision carries this step's close
   c->opening_closes = false;
   while (true) {
@@ -1126,10 +1190,12 @@ pg_status cycle_loop(pg_ctx* c, double tol, bool graphs, int first, bool specula
       int want = consumed <= c->pred_chunks ? c->pred_chunks : consumed + L;
       want = std::min(want, consumed + kFlagSlots - 2);  // never reuse a slot still awaited
       while (issued < max_chunks && issued < want) {
-        if (need_store) {
+        if (need_store || need_gstore) {
           c->fuse_next = kFuseRhs | kFuseNoNorm;
-          PG_TRY(launch_resid_all(c, 0, 0));
-          need_store = false;
+          c->gstore_next = need_gstore;
+          // meshes whose opening was not a probe have stored their b and r already
+          PG_TRY(launch_resid_all(c, 0, 0, 0.0, nullptr, nullptr, need_store));
+          need_store = need_gstore = false;
         }
         c->cur_chunk = ++issued;
         int tag = 0;
@@ -1603,7 +1669,8 @@ void pg_destroy(pg_ctx* c) {
                     &H.v0, &H.v1, &H.b, &H.r, &H.d0, &H.d1, &H.ind_a_d, &H.ind_b_d, &H.ind_geq_d,
                     &H.ind_alpha_d, &H.ind_i_d, &H.inc_off_d, &H.inc_ind_d, &H.ind_vfar_d,
                     &H.slot_d, &H.sl_off_d, &H.sl_col_d, &H.sl_w64_d, &H.sl_ws_d, &H.cap_off_d, &H.cap_col_d,
-                    &H.cap_val_d, &H.vprev0, &H.vprev1, &H.g3diag_d, &H.sl_g64_d, &H.bres_d, &H.bl_d};
+                    &H.cap_val_d, &H.vprev0, &H.vprev1, &H.g3diag_d, &H.sl_g64_d, &H.bres_d, &H.bl_d,
+                    &H.gq64_d, &H.gsup32_d, &H.gw32_d};
     for (DBuf* b : bufs) dfree(*b);
   }
   DBuf* bufs[] = {&c->grid_desc, &c->tiles_all, &c->tiles_sweep, &c->src_grid, &c->src_index, &c->src_off, &c->src_t, &c->src_i,

@@ -221,3 +221,52 @@ def test_three_level_recurrence_needs_general_netlists():
         with pytest.raises(pg.PgError) as e:
             ctx.step(1)
         assert e.value.status == -8
+
+
+@pytest.mark.parametrize("rlc", [False, True])
+@pytest.mark.parametrize("prec", [pg.PG_PREC_FP64, pg.PG_PREC_FP32_REFINE])
+def test_graph_probe_bounds_the_fp64_residual(prec, rlc):
+    """An opening predicted to converge at once takes the netlist probe (coupling capacitors,
+    two supplies and leaks to ground in the cancelled form; with series R-L vias and pure-L pads,
+    the inductor history): its norm bounds the FP64 scaled residual from above, within its
+    rounding term, so a state just inside the tolerance is kept unchanged and one outside it is
+    stepped to the oracle's solution."""
+    from oracle import BESystem, scaled_residual
+    net, _ = irregular_grid(side=24, nl=3 if rlc else 2, seed=29, rlc=rlc)
+    circ = _circuit(net)
+    sysm = BESystem(circ, H)
+    none = np.zeros(0)
+    vdc, ildc = dc_solve(circ, none)  # the source-free equilibrium: a zero residual
+    assert scaled_residual(sysm, vdc, ildc, vdc, none) < 1e-12
+    rng = np.random.default_rng(31)
+    delta = rng.uniform(0.0, 1.0, net.n)
+    unit = scaled_residual(sysm, vdc - delta, ildc, vdc - delta, none)  # linear in delta
+    tol = 1e-6
+    A = abs(sysm.M.tocsr())
+    rowsum = np.asarray(A.sum(axis=1)).ravel()
+    width = int(np.max(np.diff(A.indptr)))  # bounds every table width
+    quiet = Pulses(np.zeros(0, np.int32), np.zeros(0), np.zeros(0), np.zeros(0))
+    for target, accepted in ((0.3 * tol, True), (3.0 * tol, False)):
+        vq = vdc - delta * (target / unit)
+        true = scaled_residual(sysm, vq, ildc, vq, none)
+        e = np.abs(vq - net.source_v[0])
+        # sum_j |M_ij| |e_j| + (sum_j |M_ij|) |e_i| covers the rounding scale S_i of every row
+        slack = (width + 8) * 2.0 ** -23 * float(np.max((A @ e + rowsum * e) / sysm.M.diagonal()))
+        say(f"[gpu] graph probe prec={prec} rlc={rlc} target={target:.1e} true={true:.3e} slack={slack:.1e}")
+        with _ctx(precision=prec, tol=tol, omega=1.6) as ctx:
+            g = _upload(ctx, net, [quiet])
+            ctx.set_state(g, 0, vdc, ildc if ildc.size else None)
+            ctx.step(2)  # converged at once: the next opening is a probe
+            ctx.set_state(g, 0, vq, ildc if ildc.size else None)
+            ctx.step(1)
+            st = ctx.stats()
+            v1 = ctx.read_voltages(g)
+        if accepted:
+            say(f"  accepted: probe norm={st['last_residual']:.6e}")
+            assert st["last_step_sweeps"] == 0 and np.array_equal(v1, vq)
+            assert true * (1 - 1e-9) <= st["last_residual"] <= true * (1 + 1e-9) + slack
+        else:
+            ref, _ = BEStepper(circ, H).step(vq, ildc, none)
+            say(f"  stepped: sweeps={st['last_step_sweeps']} err={np.max(np.abs(v1 - ref)):.2e} V")
+            assert st["last_step_sweeps"] > 0 and st["last_residual"] <= tol
+            assert np.max(np.abs(v1 - ref)) <= 1e3 * tol

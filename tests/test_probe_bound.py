@@ -67,3 +67,70 @@ def test_rounding_term_is_needed():
         exact = _exact(e, g, 10.0, 0.0)
         below += Fraction(q - float(np.float32(np.float32(2.0 ** -19) * np.float32(s)))) < exact
     assert below > 0
+
+
+def _graph_probe(e64, g64, gsup64, q64, hist64, fma):
+    """The netlist probe's arithmetic for one slot: e64[0] its deviation from the reference
+    supply, e64[1:] its table entries' (padding entries carry g = 0 and the slot's own e), FP32
+    conductance-part values g64, the conductance to supplies and ground gsup64, and the FP64
+    constant q64 and history hist64.  With `fma` each product-accumulate rounds once."""
+    f = np.float32
+    ei = f(e64[0])
+    ai = f(abs(ei))
+    ej = [f(x) for x in e64[1:]]
+    g = [f(x) for x in g64]
+    gs = f(gsup64)
+
+    def acc(a, x, y):  # a + x * y in FP32
+        if fma:
+            return f(float(Fraction(float(a)) + Fraction(float(x)) * Fraction(float(y))))
+        return f(a + f(x * y))
+
+    r = f(-gs * ei)
+    s = f(gs * ai)
+    for k in range(len(g)):
+        r = acc(r, g[k], f(ej[k] - ei))
+        s = acc(s, g[k], f(ai + f(abs(ej[k]))))
+    w = len(g)
+    term = float(f(f(w + 8) * f(2.0 ** -23) * s))
+    return abs(q64 + hist64 + float(r)) + term, float(s)
+
+
+def _graph_exact(e64, g64, gsup64, q64, hist64):
+    E = [Fraction(x) for x in e64]
+    r = Fraction(q64) + Fraction(hist64) - Fraction(gsup64) * E[0]
+    for k in range(len(g64)):
+        r += Fraction(g64[k]) * (E[k + 1] - E[0])
+    return abs(r)
+
+
+@pytest.mark.parametrize("fma", [False, True])
+def test_netlist_probe_norm_bounds_the_exact_residual(fma):
+    """The general-netlist probe: rows of 1 to 16 table entries (padding entries, zero
+    conductances, near-cancelling neighbours, a supply term and a history), evaluated with and
+    without fused multiply-adds: (w + 8) 2^-23 S_i bounds the FP32 error.  The FP64 sum of the
+    constant, the history and the FP32 value rounds once more at 2^-53, as the FP64 residual
+    pass does, and the check allows that."""
+    rng = np.random.default_rng(11 + fma)
+    worst, below = 0.0, 0
+    for _ in range(4000):
+        w = int(rng.integers(1, 17))
+        scale = 10.0 ** rng.uniform(-9, -0.5)
+        e = -scale * rng.uniform(0.0, 1.0, w + 1) + rng.choice([0.0, 0.05])  # second supply above
+        if rng.uniform() < 0.3:
+            e[1:] = e[0] + scale * rng.normal(0.0, 1e-3, w)
+        g = rng.uniform(0.1, 10.0, w) * (rng.uniform(size=w) > 0.2)
+        pad = rng.uniform(size=w) < 0.2  # padding: g = 0 and the slot's own value
+        g[pad], e[1:][pad] = 0.0, e[0]
+        gsup = rng.choice([0.0, 1e-3, 10.0])
+        q = rng.normal(0.0, 0.1) * gsup
+        hist = rng.normal(0.0, 1e-3) if rng.uniform() < 0.2 else 0.0
+        bound, s = _graph_probe(e, g, gsup, q, hist, fma)
+        exact = _graph_exact(e, g, gsup, q, hist)
+        fp64 = 2.0 ** -52 * (abs(q) + abs(hist) + float(exact))
+        assert Fraction(bound) + Fraction(fp64) >= exact, (e, g, gsup, q, hist)
+        term = (w + 8) * 2.0 ** -23 * s
+        below += Fraction(bound - term) + Fraction(fp64) < exact  # without the term
+        worst = max(worst, (float(exact) - (bound - (w + 8) * 2.0 ** -23 * s)) / ((w + 8) * 2.0 ** -23 * s + 1e-300))
+    # the FP32 error uses at most the whole term, and without it the value can fall short
+    assert worst <= 1.0 and below > 0
