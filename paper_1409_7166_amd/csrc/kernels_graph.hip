@@ -251,11 +251,13 @@ __global__ __launch_bounds__(kChunk) void k_graph_resid(const GraphChunk* __rest
 //   r_i = q_i - history_i - gsup_i e_i + sum_j wG_ij (e_j - e_i),
 // wG the conductance part of M's off-diagonal (resistors and inductor companions), gsup_i the
 // conductance from node i to supplies and ground, q_i = (G0 v_s + (h/L) v_s)_i - gsup_i vref.
-// The conductance terms are evaluated in FP32; every rounding in them (of e, wG and gsup, of the
-// differences, products and the sum of k + 1 terms) is a relative error of at most u = 2^-24 on
-// a term of S_i = gsup_i |e_i| + sum_j wG_ij (|e_i| + |e_j|), so (k + 8) 2^-23 S_i, k the row's
-// table width, bounds their total error; the scale 1/M_ii is widened by its rounding.  The
-// result bounds the FP64 norm from above.
+// The conductance terms are evaluated in FP32 on e_i and on the neighbour differences
+// v_j - v_i (formed in FP64, exact for voltages within a factor of two of each other, then
+// rounded); every rounding in them (of e_i, of the differences, of wG and gsup, of the products
+// and of the sum of k + 1 terms) is a relative error of at most u = 2^-24 on a term of
+// S_i = gsup_i |e_i| + sum_j wG_ij |v_j - v_i|, so (k + 8) 2^-23 S_i, k the row's table width,
+// bounds their total error; the scale 1/M_ii is widened by its rounding.  The result bounds the
+// FP64 norm from above.
 template <typename T>
 __global__ __launch_bounds__(kChunk) void k_graph_probe(const GraphChunk* __restrict__ chunks, int n,
                                                        const GridDesc* __restrict__ grids, Ctl c) {
@@ -276,34 +278,35 @@ __global__ __launch_bounds__(kChunk) void k_graph_probe(const GraphChunk* __rest
     const T inv = ld1(static_cast<const T*>(G.invDs), i);
     const double q0 = ld1(G.gq64, i);
     const float gs = ld1(G.gsup32, i);
-    const float ei = (float)(ld1(v, i) - vref), ai = fabsf(ei);
+    const double vi = ld1(v, i);
+    const float ei = (float)(vi - vref);
     // chunks start on 64-slot slices and cover whole ones, so the slice is uniform over the wave
     const int sl = __builtin_amdgcn_readfirstlane(i >> 6);
     const int o0 = ld1(G.sl_off, sl), o1 = ld1(G.sl_off, sl + 1);
     const int base = o0 + (i & 63), w = (o1 - o0) >> 6;
-    float r = -gs * ei, s = gs * ai;
+    float r = -gs * ei, s = gs * fabsf(ei);
     int k = 0;
     for (; k + 4 <= w; k += 4) {  // four table entries, then their gathers, in flight together
       int j[4];
-      float g[4], ej[4];
+      float g[4], dj[4];
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         j[q] = ld1(G.sl_col, base + ((k + q) << 6));
         g[q] = ld1(G.gw32, base + ((k + q) << 6));
       }
 #pragma unroll
-      for (int q = 0; q < 4; ++q) ej[q] = (float)(ld1(v, j[q]) - vref);
+      for (int q = 0; q < 4; ++q) dj[q] = (float)(ld1(v, j[q]) - vi);
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
-        r += g[q] * (ej[q] - ei);
-        s += g[q] * (ai + fabsf(ej[q]));
+        r += g[q] * dj[q];
+        s += g[q] * fabsf(dj[q]);
       }
     }
     for (; k < w; ++k) {
       const float g = ld1(G.gw32, base + (k << 6));
-      const float ej = (float)(ld1(v, ld1(G.sl_col, base + (k << 6))) - vref);
-      r += g * (ej - ei);
-      s += g * (ai + fabsf(ej));
+      const float dj = (float)(ld1(v, ld1(G.sl_col, base + (k << 6))) - vi);
+      r += g * dj;
+      s += g * fabsf(dj);
     }
     double hist = 0.0;  // b's history: -alpha_k i_k for each branch k leaving node i (+ entering)
     if (G.n_ind) {

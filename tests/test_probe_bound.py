@@ -69,15 +69,16 @@ def test_rounding_term_is_needed():
     assert below > 0
 
 
-def _graph_probe(e64, g64, gsup64, q64, hist64, fma):
-    """The netlist probe's arithmetic for one slot: e64[0] its deviation from the reference
-    supply, e64[1:] its table entries' (padding entries carry g = 0 and the slot's own e), FP32
-    conductance-part values g64, the conductance to supplies and ground gsup64, and the FP64
-    constant q64 and history hist64.  With `fma` each product-accumulate rounds once."""
+def _graph_probe(v64, vref, g64, gsup64, q64, hist64, fma):
+    """The netlist probe's arithmetic for one slot: v64[0] its voltage, v64[1:] its table
+    entries' (padding entries carry g = 0 and the slot's own voltage), vref the reference supply,
+    FP32 conductance-part values g64, the conductance to supplies and ground gsup64, and the FP64
+    constant q64 and history hist64.  e_i = v_i - vref and the neighbour differences
+    v_j - v_i are formed in FP64 and rounded to FP32.  With `fma` each product-accumulate rounds
+    once."""
     f = np.float32
-    ei = f(e64[0])
-    ai = f(abs(ei))
-    ej = [f(x) for x in e64[1:]]
+    ei = f(v64[0] - vref)
+    dj = [f(x - v64[0]) for x in v64[1:]]
     g = [f(x) for x in g64]
     gs = f(gsup64)
 
@@ -87,50 +88,52 @@ def _graph_probe(e64, g64, gsup64, q64, hist64, fma):
         return f(a + f(x * y))
 
     r = f(-gs * ei)
-    s = f(gs * ai)
+    s = f(gs * f(abs(ei)))
     for k in range(len(g)):
-        r = acc(r, g[k], f(ej[k] - ei))
-        s = acc(s, g[k], f(ai + f(abs(ej[k]))))
+        r = acc(r, g[k], dj[k])
+        s = acc(s, g[k], f(abs(dj[k])))
     w = len(g)
     term = float(f(f(w + 8) * f(2.0 ** -23) * s))
     return abs(q64 + hist64 + float(r)) + term, float(s)
 
 
-def _graph_exact(e64, g64, gsup64, q64, hist64):
-    E = [Fraction(x) for x in e64]
-    r = Fraction(q64) + Fraction(hist64) - Fraction(gsup64) * E[0]
+def _graph_exact(v64, vref, g64, gsup64, q64, hist64):
+    V = [Fraction(x) for x in v64]
+    r = Fraction(q64) + Fraction(hist64) - Fraction(gsup64) * (V[0] - Fraction(vref))
     for k in range(len(g64)):
-        r += Fraction(g64[k]) * (E[k + 1] - E[0])
+        r += Fraction(g64[k]) * (V[k + 1] - V[0])
     return abs(r)
 
 
 @pytest.mark.parametrize("fma", [False, True])
 def test_netlist_probe_norm_bounds_the_exact_residual(fma):
     """The general-netlist probe: rows of 1 to 16 table entries (padding entries, zero
-    conductances, near-cancelling neighbours, a supply term and a history), evaluated with and
-    without fused multiply-adds: (w + 8) 2^-23 S_i bounds the FP32 error.  The FP64 sum of the
-    constant, the history and the FP32 value rounds once more at 2^-53, as the FP64 residual
-    pass does, and the check allows that."""
+    conductances, near-equal neighbours, a supply term and a history, voltages around a 1.0 V
+    reference and a 1.05 V second supply), evaluated with and without fused multiply-adds:
+    (w + 8) 2^-23 S_i bounds the FP32 error.  The FP64 sum of the constant, the history and the
+    FP32 value rounds once more at 2^-53, as the FP64 residual pass does, and the check allows
+    that."""
     rng = np.random.default_rng(11 + fma)
     worst, below = 0.0, 0
+    vref = 1.0
     for _ in range(4000):
         w = int(rng.integers(1, 17))
         scale = 10.0 ** rng.uniform(-9, -0.5)
-        e = -scale * rng.uniform(0.0, 1.0, w + 1) + rng.choice([0.0, 0.05])  # second supply above
+        v = vref + rng.choice([0.0, 0.05]) - scale * rng.uniform(0.0, 1.0, w + 1)
         if rng.uniform() < 0.3:
-            e[1:] = e[0] + scale * rng.normal(0.0, 1e-3, w)
+            v[1:] = v[0] + scale * rng.normal(0.0, 1e-3, w)
         g = rng.uniform(0.1, 10.0, w) * (rng.uniform(size=w) > 0.2)
         pad = rng.uniform(size=w) < 0.2  # padding: g = 0 and the slot's own value
-        g[pad], e[1:][pad] = 0.0, e[0]
+        g[pad], v[1:][pad] = 0.0, v[0]
         gsup = rng.choice([0.0, 1e-3, 10.0])
         q = rng.normal(0.0, 0.1) * gsup
         hist = rng.normal(0.0, 1e-3) if rng.uniform() < 0.2 else 0.0
-        bound, s = _graph_probe(e, g, gsup, q, hist, fma)
-        exact = _graph_exact(e, g, gsup, q, hist)
+        bound, s = _graph_probe(v, vref, g, gsup, q, hist, fma)
+        exact = _graph_exact(v, vref, g, gsup, q, hist)
         fp64 = 2.0 ** -52 * (abs(q) + abs(hist) + float(exact))
-        assert Fraction(bound) + Fraction(fp64) >= exact, (e, g, gsup, q, hist)
+        assert Fraction(bound) + Fraction(fp64) >= exact, (v, g, gsup, q, hist)
         term = (w + 8) * 2.0 ** -23 * s
         below += Fraction(bound - term) + Fraction(fp64) < exact  # without the term
-        worst = max(worst, (float(exact) - (bound - (w + 8) * 2.0 ** -23 * s)) / ((w + 8) * 2.0 ** -23 * s + 1e-300))
+        worst = max(worst, (float(exact) - (bound - term)) / (term + 1e-300))
     # the FP32 error uses at most the whole term, and without it the value can fall short
     assert worst <= 1.0 and below > 0
