@@ -9,7 +9,7 @@ import pytest
 
 import paper_1409_7166_amd as pg
 from bench import TUNED
-from helpers import PARITY_V, gpu_context, oracle_run, say
+from helpers import PARITY_V, gpu_context, oracle_run, say, torch_stream
 from oracle import BESystem, BEStepper, mesh_to_circuit, scaled_residual
 from oracle.sources import currents_at
 from oracle.transient import initial_state
@@ -116,3 +116,44 @@ def test_config3b_full_batch_sampled_grids():
         err = np.max(np.abs(got[g] - Vref[-1]))
         say(f"  grid {g} ({w.meshes[g].nx}^2): err {err:.3e} V")
         assert err <= PARITY_V
+
+
+@pytest.mark.timeout(900)
+def test_graph1_full_size_residual_of_sampled_steps():
+    """The irregular 3-layer 1024x1024 netlist (3,145,728 nodes) from its DC operating point, in
+    the launch configuration bench.py times at its 1e-6 V tolerance: the oracle-assembled FP64
+    scaled residual of sampled steps meets the tolerance, both for steps that took sweeps and
+    for quiet steps accepted by the netlist probe alone."""
+    from oracle import Circuit
+    from workloads import graph1
+    steps = 160  # loads on steps 1-69, then quiet
+    w = graph1(steps=steps)
+    net, p = w.nets[0], w.pulses[0][0]
+    tol = 1e-6
+    samples = set(range(10, steps + 1, 10))
+    got, swept = {}, {}
+    say(f"[gpu] graph1 full size, {steps} steps, residual property")
+    ctx = pg.Context(0, torch_stream())
+    with ctx:
+        ctx.set_options(h=w.h, **_opts("graph1", pg.PG_PREC_FP32_REFINE, tol))
+        g = ctx.upload_netlist(net.n, net.p, net.source_v, net.frm, net.to, net.kind, net.value, None, 1)
+        ctx.set_pulses(g, 0, p)
+        ctx.dc_operating_point(0, omega=1.98, tol=1e-9, max_sweeps=2000000)
+        prev = None
+        for k in range(1, steps + 1):
+            if k in samples:
+                prev = ctx.read_voltages(g)
+            ctx.step(1)
+            if k in samples:
+                got[k] = (prev, ctx.read_voltages(g))
+                swept[k] = ctx.stats()["last_step_sweeps"]
+    say(f"  sweeps at the sampled steps: {swept}; assembling the oracle system ...")
+    circ = Circuit(net.n, net.source_v, net.frm.astype(np.int64), net.to.astype(np.int64), net.kind, net.value)
+    sysm = BESystem(circ, w.h)
+    worst = {True: 0.0, False: 0.0}
+    for k, (vp, vk) in sorted(got.items()):
+        res = scaled_residual(sysm, vp, np.zeros(0), vk, currents_at(p, k * w.h))
+        say(f"  step {k}: sweeps {swept[k]}, oracle-assembled scaled residual {res:.3e} V")
+        worst[swept[k] == 0] = max(worst[swept[k] == 0], res)
+    assert max(worst.values()) <= tol * (1 + 1e-6)
+    assert any(s == 0 for s in swept.values()) and any(s > 0 for s in swept.values())
