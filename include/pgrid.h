@@ -124,9 +124,11 @@ typedef struct pg_stats {
   int32_t last_step_sweeps;   /* max over grids, last step */
   int32_t max_step_sweeps;    /* max over steps and grids */
   /* The final scaled residual max_i |(b - M v)_i| / M_ii of a step, V.  For a step that
-   * converged at its opening (no sweep) on a mesh with a non-zero supply it is the opening
-   * probe's value, an upper bound of the FP64 norm that exceeds it by at most its rounding
-   * term (single-precision arithmetic on v - Vdd). */
+   * converged at its opening (no sweep), on a mesh with a non-zero supply or on a general
+   * netlist (two-level recurrence), it is the opening probe's value: an upper bound of the
+   * FP64 norm that exceeds it by at most its rounding term (single-precision arithmetic on
+   * v - Vdd for meshes, on v_i minus the first supply and on neighbour differences for
+   * netlists). */
   double last_residual;       /* max over grids, last step */
   double max_final_residual;  /* max over steps */
   double seconds;             /* wall time inside pg_step / pg_run_transient */
