@@ -68,7 +68,7 @@ TUNED = {
     "config3a": dict(omega=1.7, check_every=8, tile_rows=16, scen_block=16, graphs=0),
     "config3b": dict(omega=1.6, check_every=8, graphs=0),
     "config4": dict(omega=1.6, check_every=6, graphs=0),
-    "graph1": dict(omega=1.6, check_every=8, graphs=0),
+    "graph1": dict(omega=1.6, check_every=6, graphs=0),
     "graph_mesh1": dict(omega=1.6, check_every=8, graphs=0),
 }
 
