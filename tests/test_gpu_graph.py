@@ -316,3 +316,37 @@ def test_graph_probe_bounds_the_fp64_residual(prec, rlc):
             say(f"  stepped: sweeps={st['last_step_sweeps']} residual={res:.2e} V "
                 f"err={np.max(np.abs(v1 - ref)):.2e} V")
             assert st["last_step_sweeps"] > 0 and st["last_residual"] <= tol and res <= tol
+
+
+def test_graph_probe_per_scenario_outcomes():
+    """Two scenarios of one netlist open a step with the probe from states near the source-free
+    equilibrium, one inside the tolerance and one outside: the first keeps its state bit for bit,
+    the second alone is stored and stepped until the oracle's FP64 residual of its result meets
+    the tolerance; then the other way round."""
+    from oracle import BESystem, scaled_residual
+    net, _ = irregular_grid(side=20, nl=2, seed=33)
+    circ = _circuit(net)
+    sysm, none = BESystem(circ, H), np.zeros(0)
+    vdc, _ = dc_solve(circ, none)
+    delta = np.random.default_rng(34).uniform(0.0, 1.0, net.n)
+    unit = scaled_residual(sysm, vdc - delta, none, vdc - delta, none)
+    tol = 1e-6
+    quiet = Pulses(np.zeros(0, np.int32), np.zeros(0), np.zeros(0), np.zeros(0))
+    say("[gpu] graph probe, two scenarios with different outcomes")
+    with _ctx(precision=pg.PG_PREC_FP32_REFINE, tol=tol, omega=1.6) as ctx:
+        g = _upload(ctx, net, [quiet, quiet])
+        for fail in (0, 1):
+            for s in (0, 1):
+                ctx.set_state(g, s, vdc)
+            ctx.step(2)  # converged at once: the next opening probes
+            assert ctx.stats()["last_step_sweeps"] == 0
+            start = [vdc - delta * ((3.0 if s == fail else 0.3) * tol / unit) for s in (0, 1)]
+            for s in (0, 1):
+                ctx.set_state(g, s, start[s])
+            ctx.step(1)
+            assert ctx.stats()["last_step_sweeps"] > 0
+            got = [ctx.read_voltages(g, s) for s in (0, 1)]
+            res = scaled_residual(sysm, start[fail], none, got[fail], none)
+            say(f"  scenario {fail} stepped: residual={res:.2e} V")
+            assert np.array_equal(got[1 - fail], start[1 - fail])
+            assert res <= tol and not np.array_equal(got[fail], start[fail])
