@@ -165,23 +165,21 @@ __global__ __launch_bounds__(kChunk) void k_graph_sweep(const GraphChunk* __rest
   T acc = ld1(r, i);
   const T inv = ld1(static_cast<const T*>(G.invDs), i);
   const T old = zero_in ? T(0) : ld1(d, i);
-  int k = 0;
-  for (; k + 4 <= w; k += 4) {  // four table entries, then their four gathers, in flight together
+  // four table entries, then their four gathers, in flight together; a last group of fewer than
+  // four (w is uniform over the wave) loads only its entries and adds exact zeros for the rest
+  for (int k = 0; k < w; k += 4) {
+    const int nq = w - k;
     int j[4];
     T g[4], dj[4];
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-      j[q] = ld1(G.sl_col, base + ((k + q) << 6));
-      g[q] = ld1(wv, base + ((k + q) << 6));
+      j[q] = q < nq ? ld1(G.sl_col, base + ((k + q) << 6)) : lim;
+      g[q] = q < nq ? ld1(wv, base + ((k + q) << 6)) : T(0);
     }
 #pragma unroll
     for (int q = 0; q < 4; ++q) dj[q] = j[q] < lim ? ld1(d, j[q]) : T(0);
 #pragma unroll
     for (int q = 0; q < 4; ++q) acc += g[q] * dj[q];
-  }
-  for (; k < w; ++k) {
-    const int j = ld1(G.sl_col, base + (k << 6));
-    if (j < lim) acc += ld1(wv, base + (k << 6)) * ld1(d, j);
   }
   st1(d, i, old + omega * (inv * acc - old));
 }
