@@ -709,7 +709,7 @@ pg_status prepare(pg_ctx* c) {
       c->all_nodes += H.n * H.S;
       c->graph_nodes += H.n * H.S;
       c->graph_coef += H.coef_words;
-      c->graph_entries += (H.form.soff.empty() ? 0 : (int64_t)H.form.soff.back()) * H.S;  // padded table
+      c->graph_entries += H.form.nnz * H.S;  // algorithmic: the stored padding is not charged
     } else {
       const double w = (double)H.n * H.S;
       fr += w * (8.0 + 8.0 * (__builtin_popcount(H.ch_layers) + __builtin_popcount(H.bc_layers)) / H.nl);
