@@ -274,9 +274,9 @@ __device__ void decide_block(const Ctl& c, const DecideArgs& da) {
     if (threadIdx.x == 0) {
       const int seq = c.flag_seq[0];
       c.flag_seq[0] = seq + 1;
-      c.acct[2 * (seq % nslots)] = 0;
-      c.acct[2 * (seq % nslots) + 1] = 0;
-      __threadfence_system();
+      const long long tag = (long long)(((unsigned long long)(uint32_t)seq & 0xffffffull) << 40);
+      c.acct[2 * (seq % nslots)] = tag;
+      c.acct[2 * (seq % nslots) + 1] = tag;
       c.any_active[seq % nslots] = (int32_t)(((uint32_t)seq & 0x1fffffffu) << 2 | 2u);
     }
     return;
@@ -349,9 +349,12 @@ __device__ void decide_block(const Ctl& c, const DecideArgs& da) {
     const int seq = seq_s;
     const long long checks = worked ? c.stat_checks[0] : 0;
     c.flag_seq[0] = seq + 1;
-    c.acct[2 * (seq % nslots)] = (long long)act_nodes;
-    c.acct[2 * (seq % nslots) + 1] = (long long)act_coef;
-    __threadfence_system();
+    // each accounting word carries the low 24 bits of the sequence above its 40-bit value, so the
+    // host sees when it has arrived and no fence is needed before the flag
+    const unsigned long long tag = ((unsigned long long)(uint32_t)seq & 0xffffffull) << 40;
+    constexpr unsigned long long kValue = (1ull << 40) - 1;
+    c.acct[2 * (seq % nslots)] = (long long)(tag | (act_nodes & kValue));
+    c.acct[2 * (seq % nslots) + 1] = (long long)(tag | (act_coef & kValue));
     c.any_active[seq % nslots] = (int32_t)(((uint32_t)seq & 0x1fffffffu) << 2 | (uint32_t)any);
     if (worked) c.stat_checks[0] = checks + 1;
   }

@@ -1098,6 +1098,25 @@ pg_status begin_step(pg_ctx* c, int only_item, bool begun = false, int64_t dev_s
 // (tag << 2) | (skipped << 1) | any after writing its accounting words; every so often ask
 // whether the stream still has work, so a flag that can no longer arrive is reported, not
 // awaited.
+// The active work a decision found (scenario nodes, coefficient words).  k_decide stores these
+// two words just before its flag without a fence; each carries the low 24 bits of the decision's
+// sequence above a 40-bit value, so once the flag is seen the host waits until both match.
+pg_status read_acct(pg_ctx* c, int tag, long long* nodes, long long* coef) {
+  const int slot = tag % kFlagSlots;
+  const unsigned long long want = (uint32_t)tag & 0xffffffu, value = (1ull << 40) - 1;
+  for (long spin = 1;; ++spin) {
+    const unsigned long long a = (unsigned long long)__atomic_load_n(c->host_acct + 2 * slot, __ATOMIC_ACQUIRE);
+    const unsigned long long b = (unsigned long long)__atomic_load_n(c->host_acct + 2 * slot + 1, __ATOMIC_ACQUIRE);
+    if ((a >> 40) == want && (b >> 40) == want) {
+      *nodes = (long long)(a & value);
+      *coef = (long long)(b & value);
+      return PG_OK;
+    }
+    if ((spin & 1023) == 0 && hipStreamQuery(c->stream) == hipSuccess && spin > (1L << 20))
+      return set_err(c, PG_ERR_STATE, "decision %d: accounting words out of sequence", tag);
+  }
+}
+
 pg_status wait_decision(pg_ctx* c, int tag, int* any, int* skipped = nullptr) {
   const int slot = tag % kFlagSlots;
   const uint32_t want = (uint32_t)tag;
@@ -1220,9 +1239,9 @@ pg_status cycle_loop(pg_ctx* c, double tol, bool graphs, int first, bool specula
     int any = 0;
     PG_TRY(wait_decision(c, t0, &any));
     ++consumed;
-    const int s0 = t0 % kFlagSlots;
-    work.emplace_back(__atomic_load_n(c->host_acct + 2 * s0, __ATOMIC_ACQUIRE),
-                      __atomic_load_n(c->host_acct + 2 * s0 + 1, __ATOMIC_ACQUIRE));
+    long long a_nodes = 0, a_coef = 0;
+    PG_TRY(read_acct(c, t0, &a_nodes, &a_coef));
+    work.emplace_back(a_nodes, a_coef);
     if (!any) {
       last = consumed - 1;
       break;
