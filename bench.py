@@ -9,9 +9,14 @@ stopping at a Jacobi-scaled residual of 1e-6 V.  One bench step is one backward-
 run first; the state is then reset to t = 0 and exactly K steps are timed, so the timed region is
 steps 1..K of the transient.  Inputs are resident on the GPU before timing starts.
 
-Prints one JSON line with the metric (node-updates/s), the roofline of the sweep kernel (its
-algorithmic bytes over its HIP-event-timed duration), and the FP64 CPU oracle timed on a bounded
-sample of the same workload.
+Prints one JSON line: the metric (node-updates/s) of that headline run, the roofline of its sweep
+kernel (algorithmic bytes over the HIP-event-timed duration) and the FP64 CPU oracle timed on a
+bounded sample of the same workload; then, under "legs", the same measurement for plain FP64 and
+FP32 + FP64 refinement on the 3-layer mesh and for the 256-scenario batch, each at the 1e-6 V
+stopping tolerance and at a parity tolerance, and a 3-layer 2048 x 2048 mesh whose sweep working
+set exceeds the 256 MB Infinity Cache.  Each run also carries its error against the FP64 oracle:
+after the timed region the whole transient is run again (untimed) and the voltages of a seeded
+sample of nodes are compared at every step with the oracle's values stored under tests/golden/.
 """
 import argparse
 import json
@@ -22,7 +27,11 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-HBM_PEAK = 8.0e12  # B/s, MI355X HBM3E
+HBM_PEAK = 8.0e12   # B/s, MI355X HBM3E
+MALL_BYTES = 256 * 2 ** 20  # MI355X Infinity Cache (memory-attached last-level cache)
+
+WORKLOADS = ["config0", "config1", "config2", "config4", "config3a", "config3b", "graph1", "graph_mesh1",
+             "config1_hbm"]
 
 
 def parse():
@@ -30,15 +39,14 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=1000)
     ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--workload", default="config1", choices=["config0", "config1", "config2", "config4",
-                                                             "config3a", "config3b", "graph1", "graph_mesh1"])
+    ap.add_argument("--workload", default="config1", choices=WORKLOADS)
     ap.add_argument("--tol", type=float, default=1e-6)
     ap.add_argument("--precision", default=None, choices=[None, "fp64", "fp32+ref"])
     ap.add_argument("--omega", type=float, default=None)
     ap.add_argument("--check-every", type=int, default=None)
     ap.add_argument("--tile-rows", type=int, default=0)
     ap.add_argument("--sweeps-per-launch", type=int, default=0,
-                    help="red-black sweeps fused per kernel launch, 1 or 2 (0: library default)")
+                    help="red-black sweeps fused per kernel launch, 1 or 2 (0: the workload's tuned choice)")
     ap.add_argument("--scen-block", type=int, default=0,
                     help="scenarios per sweep workgroup on multi-scenario grids (0: library default)")
     ap.add_argument("--lookahead", type=int, default=1)
@@ -51,9 +59,12 @@ def parse():
                     help="time every n-th sweep block, residual pass and other launch with HIP events "
                          "during the timed region (0: off)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-legs", action="store_true",
+                    help="time only the chosen workload (no side legs in the JSON line)")
+    ap.add_argument("--no-verify", action="store_true",
+                    help="skip the untimed runs that compare sampled voltages with the oracle's stored values")
     ap.add_argument("--side-by-side", action="store_true",
-                    help="instead of the one headline line, print one JSON line per workload and precision "
-                         "(plain FP64, FP32 + FP64 refinement, batched; 1e-6 V and a parity tolerance)")
+                    help="instead of the one headline line, print one JSON line per workload and precision")
     ap.add_argument("--copy-probe", action="store_true",
                     help="run only a plain 1 GiB device copy (counter calibration) and exit")
     return ap.parse_args()
@@ -64,6 +75,7 @@ def parse():
 TUNED = {
     "config0": dict(omega=1.6, check_every=8, graphs=1),
     "config1": dict(omega=1.6, check_every=8, tile_rows=16, graphs=0),
+    "config1_hbm": dict(omega=1.6, check_every=8, tile_rows=16, graphs=0),
     "config2": dict(omega=1.8, check_every=16, graphs=0),
     "config3a": dict(omega=1.7, check_every=8, tile_rows=16, scen_block=16, graphs=0),
     "config3b": dict(omega=1.6, check_every=8, graphs=0),
@@ -72,6 +84,24 @@ TUNED = {
     "graph_mesh1": dict(omega=1.6, check_every=8, graphs=0),
 }
 
+# Stopping tolerance at which the transient meets the 1e-6 V per-node, per-step bar against the
+# oracle (measured by the verification run below and by the GPU tests); the 1e-6 V point is the
+# metric's own stopping rule and misses that bar.
+PARITY_TOL = {"config0": 1e-10, "config1": 1e-10, "config3a": 1e-10, "config2": 1e-11, "config4": 1e-10}
+
+# The side legs of the default run: (workload, precision, tolerance).
+LEGS = [
+    ("config1", "fp32+ref", 1e-10),
+    ("config1", "fp64", 1e-6), ("config1", "fp64", 1e-10),
+    ("config3a", "fp32+ref", 1e-6), ("config3a", "fp32+ref", 1e-10),
+    ("config1_hbm", "fp32+ref", 1e-6),
+]
+
+# Oracle values of sampled nodes at every step (written by tests/golden/make_golden.py).
+GOLDEN = {
+    "config1": os.path.join(ROOT, "tests", "golden", "config1_rc_3x1024x1024_samples.npz"),
+    "config3a": os.path.join(ROOT, "tests", "golden", "config3a_batch_256scen_256x256_samples.npz"),
+}
 
 COUNTERS = os.path.join(ROOT, "profiles", "k_sweep_rb_rc3x1024_counters.json")
 
@@ -95,6 +125,12 @@ def counter_traffic(avg_alg_bytes):
 
 def make_workload(name):
     import workloads
+    if name == "config1_hbm":
+        # the 3-layer recipe at 2048 x 2048 (12,582,912 nodes): its FP32 sweep working set
+        # (~336 MB) does not fit in the Infinity Cache, so the sweeps stream from HBM
+        w = workloads.config1(side=2048)
+        w.name = "rc_3x2048x2048"
+        return w
     return getattr(workloads, name)()
 
 
@@ -114,8 +150,56 @@ def sweep_kernel_name(w, sweeps_per_launch):
     return " + ".join(names[m] for m in sorted(multi))
 
 
-def run_gpu(w, steps, warmup, precision, tol, omega, check_every, tile_rows, lookahead, profile_every, graphs,
-            scen_block=0, sweeps_per_launch=0, recurrence=0):
+def verify(ctx, w, name):
+    """Untimed: the whole transient again from t = 0 in the same launch configuration, comparing
+    at every step the voltages of the stored sample of nodes (and the largest drop over all nodes)
+    with the oracle's.  Returns a dict, or None when no stored values exist for the workload."""
+    import numpy as np
+    import torch
+
+    path = GOLDEN.get(name)
+    if path is None or not os.path.exists(path):
+        return None
+    g = np.load(path)
+    nodes = g["nodes"].astype(np.int64)
+    steps = int(g["steps"])
+    vdd = float(g["vdd"])
+    scen = g["scenarios"].tolist() if "scenarios" in g.files else [0]
+    ref = g["drops"].astype(np.float64)              # [steps, nodes] or [scen, steps, nodes]
+    ref_max = g["max_drop"]
+    if ref.ndim == 2:
+        ref, ref_max = ref[None], ref_max[None]
+    mesh = w.meshes[0]
+    buf = torch.empty(mesh.n, dtype=torch.float64, device="cuda:0")
+    idx = torch.from_numpy(nodes).to("cuda:0")
+    worst = np.zeros(len(scen))
+    worst_max = np.zeros(len(scen))
+    ctx.reset()
+    sweeps0 = ctx.stats()["sweeps"]
+    t0 = time.perf_counter()
+    for k in range(steps):
+        ctx.step(1)
+        for j, s in enumerate(scen):
+            ctx.read_voltages_dev(0, s, buf)
+            d = vdd - buf
+            samp = d[idx].cpu().numpy()
+            dmax = float(d.max())
+            worst[j] = max(worst[j], float(np.max(np.abs(samp - ref[j, k]))))
+            worst_max[j] = max(worst_max[j], abs(dmax - float(ref_max[j, k])))
+    torch.cuda.synchronize()
+    st = ctx.stats()
+    return {"max_abs_error_V": float(worst.max()), "max_drop_error_V": float(worst_max.max()),
+            "steps": steps, "scenarios": len(scen), "sampled_nodes": int(nodes.size),
+            "sweeps_per_step": (st["sweeps"] - sweeps0) / steps,
+            "peak_drop_V": float(np.max(ref_max)), "seconds": time.perf_counter() - t0,
+            "against": os.path.relpath(path, ROOT),
+            "what": "max over every step and the sampled nodes (all layers; the bottom-layer nodes farthest "
+                    "from the pads among them) of |v_gpu - v_oracle|; max_drop_error_V compares the largest "
+                    "drop over all nodes at every step"}
+
+
+def run_gpu(w, name, steps, warmup, precision, tol, omega, check_every, tile_rows, lookahead, profile_every,
+            graphs, scen_block=0, sweeps_per_launch=0, recurrence=0, do_verify=True):
     import torch
     import paper_1409_7166_amd as pg
 
@@ -135,6 +219,7 @@ def run_gpu(w, steps, warmup, precision, tol, omega, check_every, tile_rows, loo
             ctx.upload_mesh(grid, len(scen))
         for s, p in enumerate(scen):
             ctx.set_pulses(g, s, p)
+
     def start():
         ctx.reset()
         if getattr(w, "dc_start", False):  # the DC operating point at t = 0, outside the timed region
@@ -155,19 +240,42 @@ def run_gpu(w, steps, warmup, precision, tol, omega, check_every, tile_rows, loo
     st = ctx.stats()
     kt = ctx.kernel_times()
     st["options"] = ctx.options()
+    err = verify(ctx, w, name) if do_verify else None
     ctx.close()
-    return elapsed, st, kt
+    return elapsed, st, kt, err
+
+
+def host_info():
+    """CPU model, logical CPUs and the CPUs this process may run on."""
+    model = None
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except AttributeError:
+        usable = os.cpu_count()
+    return {"cpu_model": model, "nproc": os.cpu_count(), "usable_cpus": usable}
 
 
 def cpu_baseline(workload_name, budget_steps=100):
-    """The FP64 oracle on a bounded sample: the same recipe on a reduced mesh, a few steps."""
+    """The FP64 oracle on a bounded sample: the same recipe on a reduced mesh, a few steps.
+
+    The oracle factors each step matrix once with SuperLU and takes two triangular solves per
+    step; scipy runs both on one thread, and a transient's steps are sequential, so the oracle
+    uses one core whatever the host has (the host's count is reported beside it)."""
     import numpy as np
     import workloads
     from oracle import BEStepper, mesh_to_circuit
     from oracle.sources import currents_at
 
+    note = "SuperLU (scipy) factorises and solves on one thread; the steps of a transient are sequential"
     if workload_name in ("graph1", "graph_mesh1"):
-        from oracle import BEStepper, Circuit
+        from oracle import Circuit
         w = getattr(workloads, workload_name)(side=256)
         net, p = w.nets[0], w.pulses[0][0]
         sample = f"{w.name}: the 1024x1024 recipe at 256x256 ({net.n:,} nodes)"
@@ -185,9 +293,10 @@ def cpu_baseline(workload_name, budget_steps=100):
         t2 = time.perf_counter()
         return {"value": net.n * budget_steps / (t2 - t0), "unit": "node-steps/s", "cores": 1, "kind": "oracle",
                 "sample": f"{sample}, {budget_steps} backward-Euler steps incl. assembly and factorisation "
-                          f"({t1 - t0:.1f} s) and solves ({t2 - t1:.1f} s); SuperLU is single-threaded",
-                "solve_only_node_steps_per_s": net.n * budget_steps / (t2 - t1)}
-    if workload_name == "config1":
+                          f"({t1 - t0:.1f} s) and solves ({t2 - t1:.1f} s)",
+                "solve_only_node_steps_per_s": net.n * budget_steps / (t2 - t1), "threads": note,
+                "host": host_info()}
+    if workload_name in ("config1", "config1_hbm"):
         w = workloads.config1(side=256)
         sample = "3-layer 256x256 mesh with the 1024x1024 recipe (196,608 nodes)"
     elif workload_name == "config4":
@@ -213,8 +322,8 @@ def cpu_baseline(workload_name, budget_steps=100):
     return {
         "value": n * budget_steps / (t2 - t0), "unit": "node-steps/s", "cores": 1, "kind": "oracle",
         "sample": f"{sample}, {budget_steps} backward-Euler steps incl. assembly and factorisation "
-                  f"({t1 - t0:.1f} s) and solves ({t2 - t1:.1f} s); SuperLU is single-threaded",
-        "solve_only_node_steps_per_s": n * budget_steps / (t2 - t1),
+                  f"({t1 - t0:.1f} s) and solves ({t2 - t1:.1f} s)",
+        "solve_only_node_steps_per_s": n * budget_steps / (t2 - t1), "threads": note, "host": host_info(),
     }
 
 
@@ -239,7 +348,7 @@ SIDE_BY_SIDE = [
 ]
 
 
-def measure(name, prec, tol, steps, args):
+def measure(name, prec, tol, steps, args, do_verify=True):
     """One timed run: the JSON record of bench.py for workload `name`."""
     w = make_workload(name)
     prec = prec or w.precision
@@ -251,9 +360,10 @@ def measure(name, prec, tol, steps, args):
         rows = 8  # FP64 layered tiles of 16 rows need more registers than one wave slot allows
     graphs = tuned["graphs"] if args.graphs < 0 else args.graphs
     block = args.scen_block or tuned.get("scen_block", 0)
-    elapsed, st, kt = run_gpu(w, steps, args.warmup, prec, tol, omega, chk, rows,
-                              args.lookahead, args.profile_every, graphs, block,
-                              args.sweeps_per_launch, args.recurrence)
+    spl_opt = args.sweeps_per_launch or tuned.get("sweeps_per_launch", 0)
+    elapsed, st, kt, err = run_gpu(w, name, steps, args.warmup, prec, tol, omega, chk, rows,
+                                   args.lookahead, args.profile_every, graphs, block,
+                                   spl_opt, args.recurrence, do_verify and not args.no_verify)
     nodes = w.nodes
     value = st["node_updates"] / elapsed
     spl = st["options"]["sweeps_per_launch"] or 1
@@ -265,9 +375,12 @@ def measure(name, prec, tol, steps, args):
         traffic = counter_traffic(per_launch) if name == "config1" and prec == "fp32+ref" else None
         roof = {"bound": "hbm", "achieved": achieved / 1e9, "peak": HBM_PEAK / 1e9, "unit": "GB/s",
                 "frac": achieved / HBM_PEAK, "traffic": traffic,
+                # "mall": the sweep's working set fits in the 256 MB Infinity Cache, so part of its
+                # traffic may be served there; "hbm": it does not, and the sweeps stream from HBM
+                "regime": "mall" if per_launch <= MALL_BYTES else "hbm",
                 "kernel": sweep_kernel_name(w, spl), "timed_launches": kt["sweep_launches"],
                 "avg_launch_us": kt["sweep_ms"] * 1e3 / kt["sweep_launches"],
-                "bytes_per_launch": kt["sweep_bytes"] / kt["sweep_launches"]}
+                "bytes_per_launch": per_launch}
     out = {
         "metric": "node-updates/s at 1e-6 V scaled residual",
         "value": value, "unit": "node-updates/s", "n_gpus": 1, "steps": steps, "warmup": args.warmup,
@@ -284,11 +397,24 @@ def measure(name, prec, tol, steps, args):
                    "max_step_sweeps": st["max_step_sweeps"], "max_final_residual_V": st["max_final_residual"],
                    "node_steps_per_s": nodes * steps / elapsed},
         "roofline": roof,
+        "error_vs_oracle": err,
     }
     if kt["resid_launches"]:
         out["residual_kernel"] = {"avg_launch_us": kt["resid_ms"] * 1e3 / kt["resid_launches"],
                                   "achieved_GBps": kt["resid_bytes"] / (kt["resid_ms"] * 1e-3) / 1e9}
     return out
+
+
+def leg_summary(rec):
+    """The fields of one side leg."""
+    roof = rec["roofline"] or {}
+    return {"workload": rec["config"]["workload"], "precision": rec["config"]["precision"],
+            "tol_V": rec["config"]["tol_V"], "node_updates_per_s": rec["value"],
+            "ms_per_step": rec["ms_per_step"], "node_steps_per_s": rec["config"]["node_steps_per_s"],
+            "sweeps_per_step": rec["config"]["sweeps_per_step"], "steps": rec["steps"],
+            "roofline": {k: roof.get(k) for k in ("kernel", "frac", "achieved", "avg_launch_us",
+                                                  "bytes_per_launch", "regime")} if roof else None,
+            "error_vs_oracle": rec["error_vs_oracle"]}
 
 
 def main():
@@ -305,6 +431,17 @@ def main():
             print(json.dumps(measure(name, prec, tol, steps, args)), flush=True)
         return
     out = measure(args.workload, args.precision, args.tol, args.steps, args)
+    print(f"# headline {args.workload}: {out['value']:.3e} node-updates/s, {out['ms_per_step']:.3f} ms/step",
+          file=sys.stderr, flush=True)
+    if args.workload == "config1" and not args.no_legs:
+        legs = []
+        for name, prec, tol in LEGS:
+            rec = measure(name, prec, tol, args.steps, args)
+            legs.append(leg_summary(rec))
+            print(f"# leg {name} {prec} tol={tol:g}: {rec['value']:.3e} node-updates/s, "
+                  f"{rec['ms_per_step']:.3f} ms/step, error {json.dumps(rec['error_vs_oracle'])}",
+                  file=sys.stderr, flush=True)
+        out["legs"] = legs
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args.workload)
     print(json.dumps(out), flush=True)
