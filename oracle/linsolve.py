@@ -6,8 +6,10 @@ are symmetric positive definite by Lemma 1, so diagonal pivots are safe).
 Indefinite systems (the DC saddle point with inductors) use SuperLU with
 partial pivoting.
 
-Parity: pinned by ``tests/test_oracle_linalg.py`` (dense vs sparse agreement,
-residual of the solve).
+Parity: pinned by ``tests/test_oracle_rc.py::test_dense_and_sparse_solvers_agree`` (the
+dense and the sparse factorisation give the same transient to 1e-13 V) and, through the
+steppers that call it, by the closed-form and invariant tests of ``tests/test_oracle_rc.py``
+and ``tests/test_oracle_rlc.py``.
 """
 from __future__ import annotations
 

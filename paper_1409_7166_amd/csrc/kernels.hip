@@ -272,12 +272,13 @@ __device__ void decide_block(const Ctl& c, const DecideArgs& da) {
   __shared__ unsigned long long act_nodes, act_coef;
   if (*c.stall) {  // a stalled opening: keep the sequence, report the decision as skipped
     if (threadIdx.x == 0) {
-      const int seq = c.flag_seq[0];
-      c.flag_seq[0] = seq + 1;
-      const long long tag = (long long)(((unsigned long long)(uint32_t)seq & 0xffffffull) << 40);
-      c.acct[2 * (seq % nslots)] = tag;
-      c.acct[2 * (seq % nslots) + 1] = tag;
-      c.any_active[seq % nslots] = (int32_t)(((uint32_t)seq & 0x1fffffffu) << 2 | 2u);
+      const uint32_t seq = c.flag_seq[0];
+      const uint32_t slot = seq & (uint32_t)(nslots - 1);
+      c.flag_seq[0] = seq + 1u;
+      const long long tag = (long long)(((unsigned long long)seq & 0xffffffull) << 40);
+      c.acct[2 * slot] = tag;
+      c.acct[2 * slot + 1] = tag;
+      c.any_active[slot] = (int32_t)((seq & 0x1fffffffu) << 2 | 2u);
     }
     return;
   }
@@ -285,7 +286,7 @@ __device__ void decide_block(const Ctl& c, const DecideArgs& da) {
   // the item's state, its mesh nodes and grid, each grid's coefficient words, the flag sequence
   constexpr int kMaxGridWords = 1024;
   __shared__ unsigned int gbits[kMaxGridWords];
-  __shared__ int seq_s;
+  __shared__ uint32_t seq_s;
   const bool bitmap = G <= 32 * kMaxGridWords;
   const int nwords = bitmap ? (G + 31) / 32 : 0;
   long long coef_mine = 0;  // coefficient words of grid threadIdx.x (the common case G <= blockDim)
@@ -346,16 +347,17 @@ __device__ void decide_block(const Ctl& c, const DecideArgs& da) {
   }
   __syncthreads();
   if (threadIdx.x == 0) {
-    const int seq = seq_s;
+    const uint32_t seq = seq_s;
+    const uint32_t slot = seq & (uint32_t)(nslots - 1);
     const long long checks = worked ? c.stat_checks[0] : 0;
-    c.flag_seq[0] = seq + 1;
+    c.flag_seq[0] = seq + 1u;
     // each accounting word carries the low 24 bits of the sequence above its 40-bit value, so the
     // host sees when it has arrived and no fence is needed before the flag
-    const unsigned long long tag = ((unsigned long long)(uint32_t)seq & 0xffffffull) << 40;
+    const unsigned long long tag = ((unsigned long long)seq & 0xffffffull) << 40;
     constexpr unsigned long long kValue = (1ull << 40) - 1;
-    c.acct[2 * (seq % nslots)] = (long long)(tag | (act_nodes & kValue));
-    c.acct[2 * (seq % nslots) + 1] = (long long)(tag | (act_coef & kValue));
-    c.any_active[seq % nslots] = (int32_t)(((uint32_t)seq & 0x1fffffffu) << 2 | (uint32_t)any);
+    c.acct[2 * slot] = (long long)(tag | (act_nodes & kValue));
+    c.acct[2 * slot + 1] = (long long)(tag | (act_coef & kValue));
+    c.any_active[slot] = (int32_t)((seq & 0x1fffffffu) << 2 | (uint32_t)any);
     if (worked) c.stat_checks[0] = checks + 1;
   }
 }

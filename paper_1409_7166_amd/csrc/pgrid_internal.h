@@ -205,7 +205,7 @@ struct Ctl {
   long long* step;                 // [1] steps completed
   double* t_now;                   // [1] time of the step being solved, (step + 1) h
   int32_t* src_window;             // [2] first windowed source visited, number visited
-  int32_t* flag_seq;               // [1] decisions taken so far (selects the flag slot)
+  uint32_t* flag_seq;              // [1] decisions taken so far, modulo 2^32 (selects the flag slot)
   // [1] set by k_step_end when it finds items still iterating (the host queued the close of a
   // step, and the next step's opening, ahead of the step's last decision); every kernel of a
   // step's close and opening does nothing while it is set, until k_resume clears it
@@ -247,8 +247,9 @@ constexpr int kFuseRhs = 1, kFuseProbe = 2, kFuseNoNorm = 4, kFuseCancelled = 8,
 hipError_t launch_resid(bool fp32, bool multi, int nl, int tile_rows, const Tile* tiles, int ntiles,
                         const GridDesc* grids, const Ctl& c, int has_d, int din, int fuse, hipStream_t s);
 // The decision after a residual pass, with sequence number q = (*flag_seq)++, writes
-// ((q & 0x1fffffff) << 2) | (skipped << 1) | (any item still active) to slot q % nslots of
-// c.any_active (host-visible memory), after the slot's accounting words; `skipped` marks a
+// ((q & 0x1fffffff) << 2) | (skipped << 1) | (any item still active) to slot q & (nslots - 1) of
+// c.any_active (host-visible memory; nslots is a power of two), after the slot's accounting
+// words; `skipped` marks a
 // decision that found the stall flag set and took no action.
 // A step's close carried by a decision (on = 1): as launch_step_end's arguments.
 struct CloseArgs {

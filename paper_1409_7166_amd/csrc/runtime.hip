@@ -20,6 +20,7 @@ using namespace pgrid;
 namespace {
 
 constexpr int kFlagSlots = 32;  // host-visible decision flags (at most 31 decisions in flight)
+static_assert((kFlagSlots & (kFlagSlots - 1)) == 0, "decision slots are selected by masking");
 constexpr uint32_t kTagMask = 0x1fffffffu;  // a decision's tag: its sequence number, masked
 
 struct Src {
@@ -1102,7 +1103,7 @@ pg_status begin_step(pg_ctx* c, int only_item, bool begun = false, int64_t dev_s
 // two words just before its flag without a fence; each carries the low 24 bits of the decision's
 // sequence above a 40-bit value, so once the flag is seen the host waits until both match.
 pg_status read_acct(pg_ctx* c, int tag, long long* nodes, long long* coef) {
-  const int slot = tag % kFlagSlots;
+  const int slot = (int)((uint32_t)tag & (kFlagSlots - 1));
   const unsigned long long want = (uint32_t)tag & 0xffffffu, value = (1ull << 40) - 1;
   for (long spin = 1;; ++spin) {
     const unsigned long long a = (unsigned long long)__atomic_load_n(c->host_acct + 2 * slot, __ATOMIC_ACQUIRE);
@@ -1118,7 +1119,7 @@ pg_status read_acct(pg_ctx* c, int tag, long long* nodes, long long* coef) {
 }
 
 pg_status wait_decision(pg_ctx* c, int tag, int* any, int* skipped = nullptr) {
-  const int slot = tag % kFlagSlots;
+  const int slot = (int)((uint32_t)tag & (kFlagSlots - 1));
   const uint32_t want = (uint32_t)tag;
   auto take = [&](uint32_t f) {
     *any = (int)(f & 1u);
@@ -1643,7 +1644,10 @@ pg_status pg_create(pg_ctx** out, int32_t device, void* stream) {
     pg_destroy(c);
     return PG_ERR_DEVICE;
   }
-  std::memset(c->host_acct, 0, 2 * nslots * sizeof(long long));
+  // slot s only ever receives decisions whose sequence is s modulo nslots; its initial words carry
+  // the tag s + 1 (not congruent to s), so no decision's tag matches them before it has written
+  for (int s = 0; s < nslots; ++s)
+    c->host_acct[2 * s] = c->host_acct[2 * s + 1] = (long long)((unsigned long long)(s + 1) << 40);
 
   if (dalloc(c, c->c_stats64, 3 * sizeof(long long)) != PG_OK || dalloc(c, c->c_stats32, 4 * sizeof(int32_t)) != PG_OK ||
       dalloc(c, c->c_statsd, 2 * sizeof(double)) != PG_OK) {
@@ -1658,7 +1662,7 @@ pg_status pg_create(pg_ctx** out, int32_t device, void* stream) {
   k.step = (long long*)c->c_clock.p;
   k.t_now = (double*)((char*)c->c_clock.p + 8);
   k.src_window = (int32_t*)((char*)c->c_clock.p + 16);
-  k.flag_seq = (int32_t*)((char*)c->c_clock.p + 24);
+  k.flag_seq = (uint32_t*)((char*)c->c_clock.p + 24);
   k.stall = (int32_t*)((char*)c->c_clock.p + 28);
   k.any_active = c->dev_flags;
   k.acct = c->dev_acct;
