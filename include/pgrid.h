@@ -312,6 +312,19 @@ pg_status pg_estimate_omega(pg_ctx* ctx, int32_t grid, int32_t dc, int32_t iters
  * a voltage error err (the adaptive tolerance).  The state of the grid is restored. */
 pg_status pg_error_bound_factor(pg_ctx* ctx, int32_t grid, double rel_tol, double* kappa);
 
+/* pg_error_bound_factor for callers that cannot allocate device memory (tight serving loops,
+ * harnesses that forbid hipMalloc): same arguments, kernels and result, but the grid's state is
+ * saved in a fixed device scratch array of 2^22 doubles (32 MiB) that the library holds on every
+ * GPU it runs on until the process ends, instead of a buffer allocated per call; the call makes no
+ * hipMalloc/hipFree and creates no events (kernel timing is suspended for it).  Errors:
+ * PG_ERR_INVALID_ARG when the grid stores more than 2^22 node slots (nl * ny * nx rounded up to
+ * the row pitch), PG_ERR_STATE when the coefficients still have to be built (after upload or a
+ * change of options or values: pg_step, pg_error_bound_factor or pg_estimate_omega builds them),
+ * otherwise as pg_error_bound_factor.  All contexts on one GPU share its scratch array: calls on
+ * one GPU that overlap in time (contexts driven from different host threads) race, and must be
+ * serialised by the caller.  The call synchronises the context's stream. */
+pg_status pg_error_bound_factor_noalloc(pg_ctx* ctx, int32_t grid, double rel_tol, double* kappa);
+
 /* Advance every grid and scenario by nsteps backward-Euler steps (Algorithm 1 loop:
  * warm start from the previous step, sweep until the scaled residual is <= tol). */
 pg_status pg_step(pg_ctx* ctx, int32_t nsteps);

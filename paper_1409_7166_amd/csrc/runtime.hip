@@ -9,6 +9,7 @@
 #include <cstring>
 #include <deque>
 #include <string>
+#include <mutex>
 #include <vector>
 
 #include "../../include/pgrid.h"
@@ -22,6 +23,31 @@ namespace {
 constexpr int kFlagSlots = 32;  // host-visible decision flags (at most 31 decisions in flight)
 static_assert((kFlagSlots & (kFlagSlots - 1)) == 0, "decision slots are selected by masking");
 constexpr uint32_t kTagMask = 0x1fffffffu;  // a decision's tag: its sequence number, masked
+
+// Device scratch of the allocation-free entry point (pg_error_bound_factor_noalloc): 32 MiB that
+// every GPU the library runs on holds in its copy of this code object until the process ends.
+// Host code never uses the array's name as an address: pg_create resolves each device's copy
+// once, with that device current, and contexts keep the resolved pointer.
+constexpr size_t kScratchDoubles = size_t(1) << 22;
+static __device__ __align__(256) double scratch[kScratchDoubles];
+
+std::mutex g_scratch_mu;
+std::vector<double*> g_scratch_dev;  // per device ordinal; null until resolved
+
+// The device address of `scratch` on `device`, which must be current.
+hipError_t scratch_address(int device, double** out) {
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if ((int)g_scratch_dev.size() <= device) g_scratch_dev.resize(device + 1, nullptr);
+  if (!g_scratch_dev[device]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_dev[device] = (double*)p;
+  }
+  *out = g_scratch_dev[device];
+  return hipSuccess;
+}
+
 
 struct Src {
   std::vector<int32_t> node, off;
@@ -90,6 +116,7 @@ struct pg_ctx {
   bool dc_mode = false;                          // coefficients of the DC matrix (C open, L shorted)
   int64_t step = 0;
   double seconds = 0.0;
+  double* scratch_dev = nullptr;                 // this device's copy of the allocation-free scratch
   // device tables
   DBuf grid_desc, tiles_all, tiles_sweep, src_grid, src_index, src_off, src_t, src_i, ind_grid, ind_local;
   // nodes: mesh nodes x scenarios of the group's grids; mesh_nodes: mesh nodes (coefficients
@@ -1621,8 +1648,11 @@ pg_status pg_create(pg_ctx** out, int32_t device, void* stream) {
   if (hipGetDeviceProperties(&prop, device) != hipSuccess) return PG_ERR_DEVICE;
   if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0) return PG_ERR_DEVICE;
   if (hipSetDevice(device) != hipSuccess) return PG_ERR_DEVICE;
+  double* scr = nullptr;
+  if (scratch_address(device, &scr) != hipSuccess) return PG_ERR_DEVICE;
   pg_ctx* c = new pg_ctx();
   c->device = device;
+  c->scratch_dev = scr;
   pg_default_options(&c->opt);
   if (stream) {
     c->stream = (hipStream_t)stream;
@@ -2005,6 +2035,34 @@ pg_status activate_only(pg_ctx* c, int item) {
   return e == hipSuccess ? PG_OK : set_err(c, PG_ERR_DEVICE, "activation: %s", hipGetErrorString(e));
 }
 
+// kappa = ||M^-1 D||_inf of grid `grid` (coefficients built): x = M^-1 D 1 from x = 0 with
+// b = diag(M); every entry of x is >= 1 and its maximum is the norm (M is an M-matrix, so
+// M^-1 >= 0 entrywise).  The grid's first scenario's voltages are saved in `keep` (nstore
+// device doubles) and restored; the stream is synchronised before returning.
+pg_status bound_factor(pg_ctx* c, int grid, double rel_tol, double* kappa, double* keep) {
+  GridHost& H = c->grids[grid];
+  const int item = H.item0;
+  PG_TRY(state_copy(c, item, keep, 1));
+  const int saved_pred = c->pred_chunks;
+  c->pred_chunks = 1;
+  pg_status st = activate_only(c, item);
+  if (st == PG_OK) st = item_vec(c, item, 3, 0, 0.0);
+  if (st == PG_OK) st = solve_active(c, rel_tol);
+  double k = 0.0;
+  if (st == PG_OK) st = item_absmax(c, item, 4, 0, &k);
+  c->pred_chunks = saved_pred;
+  const pg_status s2 = state_copy(c, item, keep, 0);
+  if (st == PG_OK) st = s2;
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  PG_TRY(st);
+  int32_t item_failed = 0;
+  HIP_TRY(c, hipMemcpy(&item_failed, (int32_t*)c->c_failed.p + item, sizeof item_failed, hipMemcpyDeviceToHost));
+  if (item_failed)
+    return set_err(c, PG_ERR_NO_CONVERGENCE, "the solve for M^-1 D 1 reached max_sweeps = %d", c->opt.max_sweeps);
+  *kappa = k;
+  return PG_OK;
+}
+
 }  // namespace
 
 pg_status pg_estimate_omega(pg_ctx* c, int32_t grid, int32_t dc, int32_t iters, double* rho, double* omega_opt) {
@@ -2065,32 +2123,33 @@ pg_status pg_error_bound_factor(pg_ctx* c, int32_t grid, double rel_tol, double*
     return set_err(c, PG_ERR_INVALID_ARG, "need rel_tol > 0 and an output pointer");
   HIP_TRY(c, hipSetDevice(c->device));
   PG_TRY(prepare(c));
-  GridHost& H = c->grids[grid];
-  const int item = H.item0;
   DBuf keep;
-  PG_TRY(dalloc(c, keep, (size_t)H.nstore * sizeof(double)));
-  PG_TRY(state_copy(c, item, (double*)keep.p, 1));
-  const int saved_pred = c->pred_chunks;
-  c->pred_chunks = 1;
-  // x = M^-1 D 1 from x = 0: b = diag(M); every entry of x is >= 1 and its maximum is the
-  // infinity norm of M^-1 D (M is an M-matrix, so M^-1 >= 0 entrywise)
-  pg_status st = activate_only(c, item);
-  if (st == PG_OK) st = item_vec(c, item, 3, 0, 0.0);
-  if (st == PG_OK) st = solve_active(c, rel_tol);
-  double k = 0.0;
-  if (st == PG_OK) st = item_absmax(c, item, 4, 0, &k);
-  c->pred_chunks = saved_pred;
-  const pg_status s2 = state_copy(c, item, (double*)keep.p, 0);
-  if (st == PG_OK) st = s2;
-  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  PG_TRY(dalloc(c, keep, (size_t)c->grids[grid].nstore * sizeof(double)));
+  const pg_status st = bound_factor(c, grid, rel_tol, kappa, (double*)keep.p);
   dfree(keep);
-  PG_TRY(st);
-  int32_t item_failed = 0;
-  HIP_TRY(c, hipMemcpy(&item_failed, (int32_t*)c->c_failed.p + item, sizeof item_failed, hipMemcpyDeviceToHost));
-  if (item_failed)
-    return set_err(c, PG_ERR_NO_CONVERGENCE, "the solve for M^-1 D 1 reached max_sweeps = %d", c->opt.max_sweeps);
-  *kappa = k;
-  return PG_OK;
+  return st;
+}
+
+pg_status pg_error_bound_factor_noalloc(pg_ctx* c, int32_t grid, double rel_tol, double* kappa) {
+  PG_TRY(check_gs(c, grid, 0));
+  PG_TRY(mesh_only(c, grid, "pg_error_bound_factor_noalloc"));
+  if (!(std::isfinite(rel_tol) && rel_tol > 0) || !kappa)
+    return set_err(c, PG_ERR_INVALID_ARG, "need rel_tol > 0 and an output pointer");
+  if ((size_t)c->grids[grid].nstore > kScratchDoubles)
+    return set_err(c, PG_ERR_INVALID_ARG, "grid %d stores %lld node slots; the allocation-free variant holds at "
+                   "most %zu (its device scratch is %zu MiB)", grid, (long long)c->grids[grid].nstore,
+                   kScratchDoubles, kScratchDoubles * sizeof(double) >> 20);
+  if (c->dirty)
+    return set_err(c, PG_ERR_STATE, "the coefficients are not built yet: pg_step, pg_error_bound_factor or "
+                   "pg_estimate_omega builds them (and allocates) first");
+  if (!c->scratch_dev) return set_err(c, PG_ERR_DEVICE, "device scratch address was not resolved");
+  HIP_TRY(c, hipSetDevice(c->device));
+  // event timing would create events: off for the call
+  const int saved_profile = c->profile_every;
+  c->profile_every = 0;
+  const pg_status st = bound_factor(c, grid, rel_tol, kappa, c->scratch_dev);
+  c->profile_every = saved_profile;
+  return st;
 }
 
 pg_status pg_step(pg_ctx* c, int32_t nsteps) { return pg_run_transient(c, nsteps, 1, 0, 0, nullptr); }

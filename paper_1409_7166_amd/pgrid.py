@@ -119,6 +119,7 @@ EXPORTS = {
     "pg_estimate_omega": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.POINTER(C.c_double),
                                     C.POINTER(C.c_double)]),
     "pg_error_bound_factor": (C.c_int, [C.c_void_p, C.c_int32, C.c_double, C.POINTER(C.c_double)]),
+    "pg_error_bound_factor_noalloc": (C.c_int, [C.c_void_p, C.c_int32, C.c_double, C.POINTER(C.c_double)]),
     "pg_step": (C.c_int, [C.c_void_p, C.c_int32]),
     "pg_run_transient": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.c_int32,
                                    C.POINTER(C.c_double)]),
@@ -447,6 +448,12 @@ class Context:
         """||M^-1 D||_inf of the grid's step matrix: tol = err / kappa bounds a step's error by err."""
         k = C.c_double()
         self._check(lib().pg_error_bound_factor(self._h, grid, float(rel_tol), C.byref(k)))
+        return k.value
+
+    def error_bound_factor_noalloc(self, grid: int = 0, rel_tol: float = 1e-8) -> float:
+        """error_bound_factor through the allocation-free entry point (fixed device scratch)."""
+        k = C.c_double()
+        self._check(lib().pg_error_bound_factor_noalloc(self._h, grid, float(rel_tol), C.byref(k)))
         return k.value
 
     def dc_operating_point(self, k: int = 0, omega: float = 0.0, tol: float = 1e-10, max_sweeps: int = 100000):
