@@ -380,6 +380,18 @@ pg_status pg_read_inductor_currents(pg_ctx* ctx, int32_t grid, int32_t scen, dou
 pg_status pg_update_mesh_values(pg_ctx* ctx, int32_t grid, const double* gE, const double* gN,
                                 const double* C);
 
+/* pg_update_mesh_values with the new values in device memory (for instance the data of torch
+ * tensors that an optimiser updates): gE, gN, C are device pointers laid out as in pg_mesh, read
+ * on the context's stream (any may be NULL: unchanged) and copied before the call returns; the
+ * caller keeps ownership.  The values are checked on the device (finite and >= 0, as in
+ * pg_validate_mesh; the anchoring of Lemma 1 is not checked again) and, once the coefficients of
+ * the grid are built, its FP64 and sweep-precision coefficient arrays (M's diagonal with the
+ * unchanged vias and pads included) are rebuilt by kernels, with the bits the host build gives;
+ * nothing crosses PCIe except a status word.  If a rebuild is pending anyway, or the set of layers
+ * with non-zero C changes, the values are copied to the host and the next step rebuilds there.
+ * Errors: PG_ERR_INVALID_ARG naming the first offending entry (nothing is changed). */
+pg_status pg_update_mesh_values_dev(pg_ctx* ctx, int32_t grid, const double* gE, const double* gN, const double* C);
+
 /* Voltage-drop loss of a backward-Euler transient and its gradient by the reverse-time adjoint
  * (mesh grids, RC or with series R-L vias and pads; PG_ERR_UNSUPPORTED for general netlists).
  * From the current state at step k0, pg_loss_forward advances the whole context by nsteps

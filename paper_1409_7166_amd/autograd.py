@@ -4,8 +4,9 @@
 scalar J = sum_k sum_i softplus(Vdd - v_k,i - margin)^2 of a backward-Euler transient run by the
 HIP library from t = 0, with the node capacitances C [nl,ny,nx] and segment conductances
 gE [nl,ny,nx-1], gN [nl,ny-1,nx] taken from the tensors; backward() returns dJ/dC, dJ/dgE,
-dJ/dgN computed on the GPU by the adjoint (`pg_loss_backward_dev`).  Tensors may live on the
-CPU or on the context's GPU; they are float64.
+dJ/dgN computed on the GPU by the adjoint (`pg_loss_backward_dev`).  The tensors are float64,
+on the context's GPU (the coefficients are then rebuilt on the device from their memory,
+`pg_update_mesh_values_dev`) or on the CPU (`pg_update_mesh_values`).
 """
 from __future__ import annotations
 
@@ -15,8 +16,12 @@ import torch
 class SoftplusDropLoss(torch.autograd.Function):
     @staticmethod
     def forward(fctx, C, gE, gN, ctx, grid=0, nsteps=200, ckpt_every=20, margin=0.05, tol_adj=1e-9):
-        ctx.update_mesh_values(grid, gE.detach().cpu().double().numpy(), gN.detach().cpu().double().numpy(),
-                               C.detach().cpu().double().numpy())
+        if C.is_cuda and gE.is_cuda and gN.is_cuda:
+            ctx.update_mesh_values_dev(grid, gE.detach().double().contiguous(), gN.detach().double().contiguous(),
+                                       C.detach().double().contiguous())
+        else:
+            ctx.update_mesh_values(grid, gE.detach().cpu().double().numpy(), gN.detach().cpu().double().numpy(),
+                                   C.detach().cpu().double().numpy())
         ctx.reset()
         J = ctx.loss_forward(grid, 0, nsteps, ckpt_every, margin)
         fctx.pg = ctx

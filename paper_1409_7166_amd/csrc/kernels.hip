@@ -20,6 +20,9 @@
 // exactly the red values a global red-black sweep produces.  One launch therefore performs a
 // whole sweep (ping-pong buffers, no grid-wide barrier), and the black node's coefficients,
 // loaded with its red partner's, stay in registers between the two halves.
+#include <algorithm>
+#include <cfloat>
+
 #include "pgrid_internal.h"
 
 namespace pgrid {
@@ -1949,6 +1952,113 @@ hipError_t launch_sweep2(bool fp32, int nl, int tile_rows, const Tile* tiles, in
   } else {
     PG_DISPATCH_NL_TY(sweep2_t, double, tiles, ntiles, grids, c, din, zero_in, omega, s)
   }
+  return hipGetLastError();
+}
+
+// ---- device rebuild of mesh coefficients (pg_update_mesh_values_dev) -----------------------
+
+__global__ __launch_bounds__(kThreads) void k_mesh_check(const double* __restrict__ gE, const double* __restrict__ gN,
+                                                         const double* __restrict__ C, int nx, int ny, int nl, double h,
+                                                         unsigned long long* bad, unsigned int* ch_mask) {
+  const int64_t nE = (int64_t)nl * ny * (nx - 1), nN = (int64_t)nl * (ny - 1) * nx, nC = (int64_t)nl * ny * nx;
+  const int64_t P = (int64_t)nx * ny;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  unsigned long long mine = ~0ull;
+  unsigned int mask = 0u;
+  for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < nC; k += stride) {
+    if (gE && k < nE) {
+      const double g = ld1(gE, k);
+      if (!(g >= 0.0 && g <= DBL_MAX)) mine = min(mine, (unsigned long long)k);
+    }
+    if (gN && k < nN) {
+      const double g = ld1(gN, k);
+      if (!(g >= 0.0 && g <= DBL_MAX)) mine = min(mine, (1ull << 40) | (unsigned long long)k);
+    }
+    if (C) {
+      const double c = ld1(C, k);
+      if (!(c >= 0.0 && c <= DBL_MAX)) mine = min(mine, (2ull << 40) | (unsigned long long)k);
+      else if (c / h != 0.0) mask |= 1u << (int)(k / P);
+    }
+  }
+  for (int o = 32; o > 0; o >>= 1) {
+    mine = min(mine, (unsigned long long)__shfl_xor((long long)mine, o, 64));
+    mask |= (unsigned int)__shfl_xor((int)mask, o, 64);
+  }
+  if ((threadIdx.x & 63) == 0) {
+    if (mine != ~0ull) atomicMin(bad, mine);
+    if (mask) atomicOr(ch_mask, mask);
+  }
+}
+
+template <typename S>
+__global__ __launch_bounds__(kThreads) void k_mesh_coef(MeshCoefArgs a) {
+  const int nx = a.nx, ny = a.ny, X = a.X;
+  const int64_t PS = (int64_t)X * ny, ns = PS * a.nl;
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= ns) return;
+  const int l = (int)(i / PS);
+  const int64_t rem = i - (int64_t)l * PS;
+  const int y = (int)(rem / X), x = (int)(rem - (int64_t)y * X);
+  double e = 0.0, n = 0.0, ch = 0.0, D = 0.0, inv = 0.0;
+  if (x < nx) {
+    const int64_t rowE = ((int64_t)l * ny + y) * (nx - 1);
+    const double w = x > 0 ? ld1(a.gE_raw, rowE + x - 1) : 0.0;
+    if (x + 1 < nx) e = ld1(a.gE_raw, rowE + x);
+    const double s = y > 0 ? ld1(a.gN_raw, ((int64_t)l * (ny - 1) + y - 1) * nx + x) : 0.0;
+    if (y + 1 < ny) n = ld1(a.gN_raw, ((int64_t)l * (ny - 1) + y) * nx + x);
+    ch = ld1(a.C_raw, ((int64_t)l * ny + y) * nx + x) / a.h;
+    const double u = ld1(a.gU64, i), d = l > 0 ? ld1(a.gU64, i - PS) : 0.0;
+    D = mesh_diag(ch, e, w, n, s, u, d, 0.0);
+    inv = 1.0 / D;
+  }
+  st1(a.gE64, i, e);
+  st1(a.gN64, i, n);
+  st1(a.ch64, i, ch);
+  st1(a.D64, i, D);
+  st1((S*)a.invDs, i, (S)inv);
+  if (a.fp32) {
+    st1((float*)a.gEs, i, (float)e);
+    st1((float*)a.gNs, i, (float)n);
+  }
+}
+
+template <typename S>
+__global__ __launch_bounds__(kThreads) void k_mesh_pads(int n, const int32_t* __restrict__ slot,
+                                                        const double* __restrict__ val, double* D64, void* invDs) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  const int64_t a = ld1(slot, k);
+  const double D = ld1((const double*)D64, a) + ld1(val, k);
+  st1(D64, a, D);
+  st1((S*)invDs, a, (S)(1.0 / D));
+}
+
+hipError_t launch_mesh_check(const double* gE, const double* gN, const double* C, int nx, int ny, int nl, double h,
+                             unsigned long long* bad, unsigned int* ch_mask, hipStream_t s) {
+  const int64_t n = (int64_t)nl * ny * nx;
+  const unsigned blocks = (unsigned)std::min<int64_t>((n + kThreads - 1) / kThreads, 4096);
+  hipLaunchKernelGGL(k_mesh_check, dim3(blocks), dim3(kThreads), 0, s, gE, gN, C, nx, ny, nl, h, bad, ch_mask);
+  return hipGetLastError();
+}
+
+hipError_t launch_mesh_coef(const MeshCoefArgs& a, hipStream_t s) {
+  const int64_t ns = (int64_t)a.X * a.ny * a.nl;
+  const unsigned blocks = (unsigned)((ns + kThreads - 1) / kThreads);
+  if (a.fp32)
+    hipLaunchKernelGGL(k_mesh_coef<float>, dim3(blocks), dim3(kThreads), 0, s, a);
+  else
+    hipLaunchKernelGGL(k_mesh_coef<double>, dim3(blocks), dim3(kThreads), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_mesh_pads(int n, const int32_t* pad_slot, const double* pad_val, double* D64, void* invDs, int fp32,
+                            hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  const unsigned blocks = (unsigned)((n + kThreads - 1) / kThreads);
+  if (fp32)
+    hipLaunchKernelGGL(k_mesh_pads<float>, dim3(blocks), dim3(kThreads), 0, s, n, pad_slot, pad_val, D64, invDs);
+  else
+    hipLaunchKernelGGL(k_mesh_pads<double>, dim3(blocks), dim3(kThreads), 0, s, n, pad_slot, pad_val, D64, invDs);
   return hipGetLastError();
 }
 

@@ -294,6 +294,37 @@ hipError_t launch_state_copy(const Tile* tiles, int ntiles, int tile_rows, const
 // One item's vector utilities (op codes at k_item_vec); tiles are the item's tiles.
 hipError_t launch_item_vec(bool fp32, const Tile* tiles, int ntiles, int tile_rows, const GridDesc* grids,
                            const Ctl& c, int op, int which, double s, hipStream_t st);
+// Device rebuild of a layered mesh's coefficients from new unpadded values (row-major
+// gE [nl][ny][nx-1], gN [nl][ny-1][nx], C [nl][ny][nx], device memory):
+//  launch_mesh_check: every given array (null: skipped) must be finite and >= 0; the smallest
+//    offending position (array 0, 1 or 2 above bit 40) lowers *bad (start it at ~0), and the
+//    layers where C_raw / h is non-zero are OR-ed into *ch_mask (start it at 0).
+//  launch_mesh_coef: from the three arrays and the grid's via conductances gU64, writes gE64,
+//    gN64, ch64 = C/h, D64 = the diagonal without the pad term and 1/D64 (in invDs), and the
+//    sweep-precision copies (gEs, gNs when fp32); padding columns are zero.
+//  launch_mesh_pads: adds the pad term pad_val[k] to D64 at slot pad_slot[k] (distinct slots)
+//    and rewrites its inverse, so D64 gets the bits of mesh_diag with that pad term.
+struct MeshCoefArgs {
+  const double* gE_raw;
+  const double* gN_raw;
+  const double* C_raw;
+  double* gE64;
+  double* gN64;
+  double* ch64;
+  double* D64;
+  const double* gU64;
+  void* gEs;
+  void* gNs;
+  void* invDs;
+  int fp32;
+  int nx, ny, nl, X;
+  double h;
+};
+hipError_t launch_mesh_check(const double* gE, const double* gN, const double* C, int nx, int ny, int nl, double h,
+                             unsigned long long* bad, unsigned int* ch_mask, hipStream_t s);
+hipError_t launch_mesh_coef(const MeshCoefArgs& a, hipStream_t s);
+hipError_t launch_mesh_pads(int n, const int32_t* pad_slot, const double* pad_val, double* D64, void* invDs, int fp32,
+                            hipStream_t s);
 // Clear the stall flag (after the host has re-queued a stalled step's remaining work).
 hipError_t launch_resume(const Ctl& c, hipStream_t s);
 // general graphs: right-hand side, one colour of a sweep (in place on d[0]), FP64 residual

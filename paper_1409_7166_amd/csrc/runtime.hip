@@ -48,7 +48,6 @@ hipError_t scratch_address(int device, double** out) {
   return hipSuccess;
 }
 
-
 struct Src {
   std::vector<int32_t> node, off;
   std::vector<double> t, i;
@@ -92,6 +91,14 @@ struct GridHost {
   DBuf vprev0, vprev1, g3diag_d, sl_g64_d, bres_d, bl_d;  // three-level recurrence
   DBuf gq64_d, gsup32_d, gw32_d;                          // opening probe (general graph)
   int sweep_fp32 = -1;                           // precision the sweep buffers were built for
+  // Library copies of the unpadded gE, gN, C on the device (pg_update_mesh_values_dev): while
+  // raw_valid they equal the grid's current values; while host_stale they, not the host
+  // vectors gE, gN, C, hold them (the host vectors are refreshed before any host rebuild).
+  DBuf gE_raw, gN_raw, C_raw, chk_d;
+  bool raw_valid = false, host_stale = false;
+  // every storage slot with a pad, and the pad term mesh_diag adds to its diagonal
+  DBuf padt_slot_d, padt_val_d;
+  int32_t n_padt = 0;
 };
 
 struct ProfEvent {
@@ -352,6 +359,18 @@ int n_items(const pg_ctx* c) {
 // Builds the padded FP64 coefficient arrays and the companion model of every inductive
 // branch for step h (series R-L: g_eq = h/(L + hR), alpha = L/(L + hR); eq. 10 with the
 // inductor current kept as state), then the sweep-precision copies.
+// Bring the host vectors gE, gN, C of a mesh up to the values a device update left in the
+// library's device copies.
+pg_status ensure_host_values(pg_ctx* c, GridHost& G) {
+  if (!G.host_stale) return PG_OK;
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  HIP_TRY(c, hipMemcpy(G.gE.data(), G.gE_raw.p, G.gE.size() * sizeof(double), hipMemcpyDeviceToHost));
+  HIP_TRY(c, hipMemcpy(G.gN.data(), G.gN_raw.p, G.gN.size() * sizeof(double), hipMemcpyDeviceToHost));
+  HIP_TRY(c, hipMemcpy(G.C.data(), G.C_raw.p, G.C.size() * sizeof(double), hipMemcpyDeviceToHost));
+  G.host_stale = false;
+  return PG_OK;
+}
+
 // Residual and correction buffers in the sweep precision (zero, so padding slots read as zero).
 pg_status alloc_sweep_bufs(pg_ctx* c, GridHost& G, bool f32) {
   const size_t es = f32 ? sizeof(float) : sizeof(double);
@@ -398,6 +417,7 @@ pg_status upload_inductors(pg_ctx* c, GridHost& G, const std::vector<double>& ge
 
 pg_status build_mesh_grid(pg_ctx* c, int gi) {
   GridHost& G = c->grids[gi];
+  PG_TRY(ensure_host_values(c, G));
   const double h = c->opt.h;
   // DC matrix (the limit h -> infinity): no C/h, and a series R-L branch is its resistor
   // (g_eq -> 1/R, alpha -> 0), so the branch update gives the DC current g (v_a - v_b)
@@ -448,17 +468,20 @@ pg_status build_mesh_grid(pg_ctx* c, int gi) {
   // pass of a step recovers it in (mesh_diag); D already holds the pads otherwise.
   std::vector<double> inv(ns, 0.0);
   const double inv_vdd = G.vdd != 0.0 ? 1.0 / G.vdd : 0.0;
+  std::vector<int32_t> padt_slot;  // slots with a pad term, for a device rebuild of D
+  std::vector<double> padt_val;
   for (int l = 0; l < nl; ++l)
     for (int y = 0; y < ny; ++y)
       for (int x = 0; x < nx; ++x) {
         const int64_t i = (int64_t)l * PS + (int64_t)y * X + x;
         const double w = x > 0 ? gE[i - 1] : 0.0, s = y > 0 ? gN[i - X] : 0.0, d = l > 0 ? gU[i - PS] : 0.0;
-        if (G.vdd != 0.0)
-          D[i] = mesh_diag(ch[i], gE[i], w, gN[i], s, gU[i], d, bc[i] * inv_vdd);
-        else
-          D[i] = mesh_diag(ch[i], gE[i], w, gN[i], s, gU[i], d, D[i]);
+        const double pad = G.vdd != 0.0 ? bc[i] * inv_vdd : D[i];
+        if (pad != 0.0) { padt_slot.push_back((int32_t)i); padt_val.push_back(pad); }
+        D[i] = mesh_diag(ch[i], gE[i], w, gN[i], s, gU[i], d, pad);
         inv[i] = 1.0 / D[i];
       }
+  PG_TRY(upload(c, G.padt_slot_d, padt_slot)); PG_TRY(upload(c, G.padt_val_d, padt_val));
+  G.n_padt = (int32_t)padt_slot.size();
   G.ch_layers = G.bc_layers = 0;
   for (int l = 0; l < nl; ++l)
     for (int64_t i = (int64_t)l * PS; i < (int64_t)(l + 1) * PS; ++i) {
@@ -1723,7 +1746,8 @@ void pg_destroy(pg_ctx* c) {
                     &H.ind_alpha_d, &H.ind_i_d, &H.inc_off_d, &H.inc_ind_d, &H.ind_vfar_d,
                     &H.slot_d, &H.sl_off_d, &H.sl_col_d, &H.sl_w64_d, &H.sl_ws_d, &H.cap_off_d, &H.cap_col_d,
                     &H.cap_val_d, &H.vprev0, &H.vprev1, &H.g3diag_d, &H.sl_g64_d, &H.bres_d, &H.bl_d,
-                    &H.gq64_d, &H.gsup32_d, &H.gw32_d};
+                    &H.gq64_d, &H.gsup32_d, &H.gw32_d, &H.gE_raw, &H.gN_raw, &H.C_raw, &H.chk_d,
+                    &H.padt_slot_d, &H.padt_val_d};
     for (DBuf* b : bufs) dfree(*b);
   }
   DBuf* bufs[] = {&c->grid_desc, &c->tiles_all, &c->tiles_sweep, &c->src_grid, &c->src_index, &c->src_off, &c->src_t, &c->src_i,
@@ -1967,9 +1991,11 @@ pg_status pg_dc_operating_point(pg_ctx* c, int64_t k, double omega, double tol, 
     return set_err(c, PG_ERR_INVALID_ARG, "need k >= 0, tol > 0, max_sweeps >= 1 and 0 <= omega < 2");
   HIP_TRY(c, hipSetDevice(c->device));
   PG_TRY(prepare(c));
-  for (int g = 0; g < (int)c->grids.size(); ++g)
+  for (int g = 0; g < (int)c->grids.size(); ++g) {
+    PG_TRY(ensure_host_values(c, c->grids[g]));
     if (!dc_anchored(c->grids[g]))
       return set_err(c, PG_ERR_NOT_SPD, "grid %d: a connected part reaches no pad, so the DC matrix is singular", g);
+  }
   const pg_options saved = c->opt;
   const int64_t saved_step = c->step;
   const int saved_pred = c->pred_chunks;
@@ -2072,6 +2098,7 @@ pg_status pg_estimate_omega(pg_ctx* c, int32_t grid, int32_t dc, int32_t iters, 
     return set_err(c, PG_ERR_INVALID_ARG, "need iters >= 32, dc in {0, 1} and output pointers");
   HIP_TRY(c, hipSetDevice(c->device));
   PG_TRY(prepare(c));
+  if (dc) PG_TRY(ensure_host_values(c, c->grids[grid]));
   if (dc && !dc_anchored(c->grids[grid]))
     return set_err(c, PG_ERR_NOT_SPD, "grid %d: a connected part reaches no pad, so the DC matrix is singular", grid);
   const int item = c->grids[grid].item0;
@@ -2453,11 +2480,72 @@ pg_status pg_update_mesh_values(pg_ctx* c, int32_t grid, const double* gE, const
     if (!(std::isfinite(gN[k]) && gN[k] >= 0)) return set_err(c, PG_ERR_INVALID_ARG, "gN[%zu] invalid", k);
   for (size_t k = 0; C && k < nC; ++k)
     if (!(std::isfinite(C[k]) && C[k] >= 0)) return set_err(c, PG_ERR_INVALID_ARG, "C[%zu] invalid", k);
+  PG_TRY(ensure_host_values(c, H));  // arrays left out keep the values of an earlier device update
   if (gE) H.gE.assign(gE, gE + nE);
   if (gN) H.gN.assign(gN, gN + nN);
   if (C) H.C.assign(C, C + nC);
+  H.raw_valid = false;
   c->dirty = true;
   c->adj.recorded = false;
+  return PG_OK;
+}
+
+pg_status pg_update_mesh_values_dev(pg_ctx* c, int32_t grid, const double* gE, const double* gN, const double* C) {
+  PG_TRY(check_gs(c, grid, 0));
+  PG_TRY(mesh_only(c, grid, "pg_update_mesh_values_dev"));
+  HIP_TRY(c, hipSetDevice(c->device));
+  GridHost& H = c->grids[grid];
+  const size_t nE = H.gE.size(), nN = H.gN.size(), nC = H.C.size();
+  if (!H.raw_valid) {  // the device copies start from the current values
+    PG_TRY(ensure_host_values(c, H));
+    PG_TRY(upload(c, H.gE_raw, H.gE)); PG_TRY(upload(c, H.gN_raw, H.gN)); PG_TRY(upload(c, H.C_raw, H.C));
+    H.raw_valid = true;
+  }
+  // check the new values where the caller left them, before anything is replaced
+  PG_TRY(dalloc(c, H.chk_d, 16));
+  struct { unsigned long long bad; unsigned int mask, pad; } chk{~0ull, 0u, 0u};
+  HIP_TRY(c, hipMemcpyAsync(H.chk_d.p, &chk, sizeof chk, hipMemcpyHostToDevice, c->stream));
+  unsigned long long* bad_d = (unsigned long long*)H.chk_d.p;
+  unsigned int* mask_d = (unsigned int*)(bad_d + 1);
+  hipError_t e = launch_mesh_check(gE, gN, C, H.nx, H.ny, H.nl, c->opt.h, bad_d, mask_d, c->stream);
+  if (e == hipSuccess && !C)  // the layers with capacitance, from the values that stay
+    e = launch_mesh_check(nullptr, nullptr, (const double*)H.C_raw.p, H.nx, H.ny, H.nl, c->opt.h, bad_d, mask_d,
+                          c->stream);
+  if (e != hipSuccess) return set_err(c, PG_ERR_DEVICE, "value check: %s", hipGetErrorString(e));
+  HIP_TRY(c, hipMemcpyAsync(&chk, H.chk_d.p, sizeof chk, hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  if (chk.bad != ~0ull) {
+    static const char* names[3] = {"gE", "gN", "C"};
+    return set_err(c, PG_ERR_INVALID_ARG, "%s[%llu] is not finite and >= 0", names[std::min<unsigned>(2u, (unsigned)(chk.bad >> 40))],
+                   chk.bad & ((1ull << 40) - 1));
+  }
+  if (gE) HIP_TRY(c, hipMemcpyAsync(H.gE_raw.p, gE, nE * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+  if (gN) HIP_TRY(c, hipMemcpyAsync(H.gN_raw.p, gN, nN * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+  if (C) HIP_TRY(c, hipMemcpyAsync(H.C_raw.p, C, nC * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));  // the caller may free or overwrite its arrays on return
+  H.host_stale = true;
+  c->adj.recorded = false;
+  if (c->dirty || chk.mask != H.ch_layers) {
+    // a rebuild is pending anyway, or the layers that carry C/h (which the kernels are told) change:
+    // rebuild on the host from the new values at the next step
+    PG_TRY(ensure_host_values(c, H));
+    c->dirty = true;
+    return PG_OK;
+  }
+  const bool f32 = fp32_mode(c);
+  MeshCoefArgs a{};
+  a.gE_raw = (const double*)H.gE_raw.p; a.gN_raw = (const double*)H.gN_raw.p; a.C_raw = (const double*)H.C_raw.p;
+  a.gE64 = (double*)H.gE64.p; a.gN64 = (double*)H.gN64.p; a.ch64 = (double*)H.ch64.p; a.D64 = (double*)H.D64.p;
+  a.gU64 = (const double*)H.gU64.p;
+  a.gEs = H.gEs.p; a.gNs = H.gNs.p; a.invDs = H.invDs.p;
+  a.fp32 = f32 ? 1 : 0;
+  a.nx = H.nx; a.ny = H.ny; a.nl = H.nl; a.X = H.X;
+  a.h = c->opt.h;
+  e = launch_mesh_coef(a, c->stream);
+  if (e == hipSuccess)
+    e = launch_mesh_pads(H.n_padt, (const int32_t*)H.padt_slot_d.p, (const double*)H.padt_val_d.p, (double*)H.D64.p,
+                         H.invDs.p, a.fp32, c->stream);
+  if (e != hipSuccess) return set_err(c, PG_ERR_DEVICE, "coefficient rebuild: %s", hipGetErrorString(e));
   return PG_OK;
 }
 

@@ -74,6 +74,7 @@ class KernelTimes(C.Structure):
 
 
 _lib = None
+_VOIDP = C.c_void_p  # (methods whose capacitance argument is named C shadow the module)
 
 EXPORTS = {
     "pg_abi_version": (C.c_int32, []),
@@ -136,6 +137,7 @@ EXPORTS = {
     "pg_read_inductor_currents": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.POINTER(C.c_double), C.c_int64]),
     "pg_update_mesh_values": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_double),
                                         C.POINTER(C.c_double)]),
+    "pg_update_mesh_values_dev": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p]),
     "pg_loss_forward": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_double,
                                   C.POINTER(C.c_double)]),
     "pg_loss_backward": (C.c_int, [C.c_void_p, C.c_double, C.POINTER(C.c_double), C.POINTER(C.c_double),
@@ -513,6 +515,24 @@ class Context:
     def update_mesh_values(self, grid: int, gE=None, gN=None, C=None):
         gE, gN, C = _f64(gE), _f64(gN), _f64(C)
         self._check(lib().pg_update_mesh_values(self._h, grid, _dp(gE), _dp(gN), _dp(C)))
+
+    def update_mesh_values_dev(self, grid: int, gE=None, gN=None, C=None):
+        """pg_update_mesh_values_dev: float64 CUDA tensors of the shapes of pg_mesh's gE, gN, C
+        (None: unchanged), read on the context's stream."""
+        info = self.grid_info(grid)
+        nx, ny, nl = info["nx"], info["ny"], info["nl"]
+        want = {"gE": nl * ny * (nx - 1), "gN": nl * (ny - 1) * nx, "C": nl * ny * nx}
+        ptrs = []
+        for name, t in (("gE", gE), ("gN", gN), ("C", C)):
+            if t is None:
+                ptrs.append(None)
+                continue
+            if not (t.is_cuda and t.dtype.is_floating_point and t.element_size() == 8 and t.is_contiguous()):
+                raise ValueError(f"{name} must be a contiguous float64 CUDA tensor")
+            if t.numel() != want[name]:
+                raise ValueError(f"{name} has {t.numel()} entries, the grid needs {want[name]}")
+            ptrs.append(_VOIDP(t.data_ptr()))
+        self._check(lib().pg_update_mesh_values_dev(self._h, grid, *ptrs))
 
     def loss_forward(self, grid: int, scen: int, nsteps: int, ckpt_every: int, margin: float) -> float:
         J = C.c_double()
