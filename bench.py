@@ -90,12 +90,38 @@ TUNED = {
 PARITY_TOL = {"config0": 1e-10, "config1": 1e-10, "config3a": 1e-10, "config3b": 1e-10, "config2": 1e-11,
               "config4": 1e-10}
 
+# Settings at the parity tolerance, where a step needs a hundred sweeps or more: there a larger
+# omega, nearer Young's optimum for the step matrix, and fewer FP64 checks per sweep pay off
+# (chosen by the shortest time per step over the first 200 steps of each transient, its pulses
+# and the start of the relaxation that follows them).
+TUNED_PARITY = {
+    "config0": dict(omega=1.65, check_every=16),
+    "config1": dict(omega=1.87, check_every=32),
+    "config1_hbm": dict(omega=1.87, check_every=32),
+    "config2": dict(omega=1.94, check_every=64),
+    "config3a": dict(omega=1.65, check_every=8),
+    "config3b": dict(omega=1.6, check_every=16),
+    "config4": dict(omega=1.5, check_every=12),
+}
+
+
+def settings(name, tol):
+    """Solver options (omega, check_every, tile_rows, graphs, scen_block, sweeps_per_launch) that
+    bench.py runs workload `name` with at stopping tolerance `tol`."""
+    s = dict(tile_rows=0, scen_block=0, sweeps_per_launch=0)
+    s.update(TUNED[name])
+    ptol = PARITY_TOL.get(name, PARITY_TOL.get(name.replace("_hbm", "")))
+    if ptol is not None and tol <= ptol:
+        s.update(TUNED_PARITY.get(name, {}))
+    return s
+
+
 # The side legs of the default run: (workload, precision, tolerance).
 LEGS = [
     ("config1", "fp32+ref", 1e-10),
     ("config1", "fp64", 1e-6), ("config1", "fp64", 1e-10),
     ("config3a", "fp32+ref", 1e-6), ("config3a", "fp32+ref", 1e-10),
-    ("config1_hbm", "fp32+ref", 1e-6),
+    ("config1_hbm", "fp32+ref", 1e-6), ("config1_hbm", "fp32+ref", 1e-10),
 ]
 
 # Oracle values of sampled nodes at every step (written by tests/golden/make_golden.py).
@@ -353,7 +379,7 @@ def measure(name, prec, tol, steps, args, do_verify=True):
     """One timed run: the JSON record of bench.py for workload `name`."""
     w = make_workload(name)
     prec = prec or w.precision
-    tuned = TUNED[name]
+    tuned = settings(name, tol)
     omega = args.omega or tuned["omega"]
     chk = args.check_every or tuned["check_every"]
     rows = args.tile_rows or tuned.get("tile_rows", 0)

@@ -13,7 +13,7 @@ import numpy as np
 import pytest
 
 import paper_1409_7166_amd as pg
-from bench import TUNED
+from bench import settings
 from helpers import PARITY_V, gpu_context, say
 from oracle import BEStepper, mesh_to_circuit
 from oracle.sources import currents_at
@@ -24,9 +24,10 @@ pytestmark = pytest.mark.gpu
 
 
 def _opts(name, prec, tol):
-    t = TUNED[name]
+    t = settings(name, tol)
     return dict(precision=prec, tol=tol, omega=t["omega"], check_every=t["check_every"], graphs=t["graphs"],
-                max_sweeps=200000, tile_rows=t.get("tile_rows", 0))
+                max_sweeps=200000, tile_rows=t["tile_rows"], scen_block=t["scen_block"],
+                sweeps_per_launch=t["sweeps_per_launch"])
 
 
 def _max_error(w, name, prec, tol, steps):

@@ -8,7 +8,7 @@ import numpy as np
 import pytest
 
 import paper_1409_7166_amd as pg
-from bench import TUNED
+from bench import settings
 from helpers import PARITY_V, gpu_context, oracle_run, say, torch_stream
 from oracle import BESystem, BEStepper, mesh_to_circuit, scaled_residual
 from oracle.sources import currents_at
@@ -19,9 +19,10 @@ pytestmark = pytest.mark.gpu
 
 
 def _opts(name, prec, tol):
-    t = TUNED[name]
+    t = settings(name, tol)
     return dict(precision=prec, tol=tol, omega=t["omega"], check_every=t["check_every"], graphs=t["graphs"],
-                max_sweeps=200000, tile_rows=t.get("tile_rows", 0), scen_block=t.get("scen_block", 0))
+                max_sweeps=200000, tile_rows=t["tile_rows"], scen_block=t["scen_block"],
+                sweeps_per_launch=t["sweeps_per_launch"])
 
 
 @pytest.mark.timeout(600)
@@ -49,7 +50,9 @@ def test_config1_full_size_residual_of_every_sampled_step():
         res = scaled_residual(sysm, vp, np.zeros(0), vk, currents_at(p, k * w.h))
         say(f"  step {k}: oracle-assembled scaled residual {res:.3e} V, max drop {1 - vk.min():.3e} V")
         worst = max(worst, res)
-    assert worst <= 1.01 * tol
+    # the oracle re-evaluates the FP64 residual the GPU stopped on; the two evaluations differ by
+    # a few units in the last place of the largest terms (~10 A against M_ii ~ 10 S), ~1e-15 V
+    assert worst <= tol + 1e-13
     assert 1.0 - got[40][1].min() > 1e-3
 
 

@@ -19,7 +19,7 @@ import pytest
 import torch
 
 import paper_1409_7166_amd as pg
-from bench import GOLDEN, PARITY_TOL, TUNED
+from bench import GOLDEN, PARITY_TOL, settings
 from helpers import PARITY_V, gpu_context, say
 from oracle_stream import BatchStream, OracleStream, balanced_chunks
 from workloads import config1, config2, config3a, config3b
@@ -30,10 +30,11 @@ WORKERS = 16  # CPU share of one GPU on the test boxes
 
 
 def _opts(name, prec):
-    t = TUNED[name]
-    return dict(precision=prec, tol=PARITY_TOL[name], omega=t["omega"], check_every=t["check_every"],
-                graphs=t["graphs"], max_sweeps=200000, tile_rows=t.get("tile_rows", 0),
-                scen_block=t.get("scen_block", 0))
+    tol = PARITY_TOL[name]
+    t = settings(name, tol)
+    return dict(precision=prec, tol=tol, omega=t["omega"], check_every=t["check_every"], graphs=t["graphs"],
+                max_sweeps=200000, tile_rows=t["tile_rows"], scen_block=t["scen_block"],
+                sweeps_per_launch=t["sweeps_per_launch"])
 
 
 def _read_all(ctx, w, bufs):
