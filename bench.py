@@ -55,6 +55,9 @@ def parse():
     ap.add_argument("--graphs", type=int, default=-1, help="replay each step from captured HIP graphs (1) or "
                                                            "launch kernels one by one (0); -1: the workload's "
                                                            "tuned choice")
+    ap.add_argument("--resident", type=int, default=-1,
+                    help="1: one launch per call with one workgroup per item carrying whole steps (meshes of at "
+                         "most 4096 nodes); 0: one launch per sweep; -1: the workload's tuned choice")
     ap.add_argument("--profile-every", type=int, default=32,
                     help="time every n-th sweep block, residual pass and other launch with HIP events "
                          "during the timed region (0: off)")
@@ -73,7 +76,7 @@ def parse():
 # Per-workload solver settings, chosen for the shortest time per step at the 1e-6 V residual
 # (not for the most node-updates: a larger omega needs more sweeps and inflates node-updates/s).
 TUNED = {
-    "config0": dict(omega=1.6, check_every=8, graphs=1),
+    "config0": dict(omega=1.6, check_every=8, graphs=1, resident=1),
     "config1": dict(omega=1.6, check_every=8, tile_rows=16, graphs=0),
     "config1_hbm": dict(omega=1.6, check_every=8, tile_rows=16, graphs=0),
     "config2": dict(omega=1.8, check_every=16, graphs=0),
@@ -106,9 +109,9 @@ TUNED_PARITY = {
 
 
 def settings(name, tol):
-    """Solver options (omega, check_every, tile_rows, graphs, scen_block, sweeps_per_launch) that
-    bench.py runs workload `name` with at stopping tolerance `tol`."""
-    s = dict(tile_rows=0, scen_block=0, sweeps_per_launch=0)
+    """Solver options (omega, check_every, tile_rows, graphs, scen_block, sweeps_per_launch,
+    resident) that bench.py runs workload `name` with at stopping tolerance `tol`."""
+    s = dict(tile_rows=0, scen_block=0, sweeps_per_launch=0, resident=0)
     s.update(TUNED[name])
     ptol = PARITY_TOL.get(name, PARITY_TOL.get(name.replace("_hbm", "")))
     if ptol is not None and tol <= ptol:
@@ -226,7 +229,7 @@ def verify(ctx, w, name):
 
 
 def run_gpu(w, name, steps, warmup, precision, tol, omega, check_every, tile_rows, lookahead, profile_every,
-            graphs, scen_block=0, sweeps_per_launch=0, recurrence=0, do_verify=True):
+            graphs, scen_block=0, sweeps_per_launch=0, recurrence=0, do_verify=True, resident=0):
     import torch
     import paper_1409_7166_amd as pg
 
@@ -236,7 +239,7 @@ def run_gpu(w, name, steps, warmup, precision, tol, omega, check_every, tile_row
     ctx.set_options(h=w.h, tol=tol, omega=omega, check_every=check_every, max_sweeps=100000,
                     precision=pg.PG_PREC_FP32_REFINE if precision == "fp32+ref" else pg.PG_PREC_FP64,
                     tile_rows=tile_rows, lookahead=lookahead, graphs=graphs, scen_block=scen_block,
-                    sweeps_per_launch=sweeps_per_launch, recurrence=recurrence)
+                    sweeps_per_launch=sweeps_per_launch, recurrence=recurrence, resident=resident)
     grids = w.nets if is_netlist(w) else w.meshes
     for g, (grid, scen) in enumerate(zip(grids, w.pulses)):
         if is_netlist(w):
@@ -388,9 +391,10 @@ def measure(name, prec, tol, steps, args, do_verify=True):
     graphs = tuned["graphs"] if args.graphs < 0 else args.graphs
     block = args.scen_block or tuned.get("scen_block", 0)
     spl_opt = args.sweeps_per_launch or tuned.get("sweeps_per_launch", 0)
+    resident = tuned["resident"] if args.resident < 0 else args.resident
     elapsed, st, kt, err = run_gpu(w, name, steps, args.warmup, prec, tol, omega, chk, rows,
                                    args.lookahead, args.profile_every, graphs, block,
-                                   spl_opt, args.recurrence, do_verify and not args.no_verify)
+                                   spl_opt, args.recurrence, do_verify and not args.no_verify, resident)
     nodes = w.nodes
     value = st["node_updates"] / elapsed
     spl = st["options"]["sweeps_per_launch"] or 1
@@ -420,6 +424,7 @@ def measure(name, prec, tol, steps, args, do_verify=True):
                    "scen_block": (st["options"]["scen_block"] or 8) if any(len(p) > 1 for p in w.pulses)
                    else None,
                    "recurrence": "three-level" if args.recurrence else "two-level",
+                   "resident": bool(st["options"]["resident"]),
                    "sweeps_per_step": st["sweeps"] / max(1, st["steps"]),
                    "max_step_sweeps": st["max_step_sweeps"], "max_final_residual_V": st["max_final_residual"],
                    "node_steps_per_s": nodes * steps / elapsed},

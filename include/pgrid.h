@@ -95,7 +95,17 @@ typedef struct pg_options {
                            sweeps stage a wider halo and recompute its rings, and move the bytes
                            of one sweep.  Results are identical.  Jacobi ordering always uses 1 */
   int32_t recurrence;   /* PG_REC_TWO_LEVEL (default) or PG_REC_THREE_LEVEL (general netlists only) */
-  int32_t reserved[2];  /* must be zero */
+  int32_t resident;     /* 1: pg_step / pg_run_transient advance every item in one launch per call
+                           (per recorded interval), one workgroup per item carrying whole steps
+                           (right-hand side, sources, sweeps, the stopping test of Algorithm 1 and
+                           the branch currents) with the voltages in LDS, in FP64 whatever the
+                           precision option; every grid must be a layered mesh of at most 4096
+                           nodes and 2048 series R-L branches, with red-black ordering and the
+                           two-level recurrence (PG_ERR_UNSUPPORTED otherwise, at the next step).
+                           A step that reaches max_sweeps keeps its last iterate and the remaining
+                           steps still run; the call then returns PG_ERR_NO_CONVERGENCE.
+                           0 (default): one launch per sweep, decisions on the device. */
+  int32_t reserved[1];  /* must be zero */
 } pg_options;
 
 /* A layered RC/RLC mesh (the representative node of Fig. 2 repeated on a grid).
@@ -146,7 +156,9 @@ typedef struct pg_stats {
  * residual 8 * (v + b) + e * r [+ e * d + 8 * v_out]; per mesh node of a grid with an active
  * scenario (coefficients are shared by the scenarios of a grid): sweep e * (gE + gN + invD)
  * + e * (nl-1)/nl (vias exist below the top layer only), residual 8 * (D + gE + gN)
- * + 8 * (nl-1)/nl. */
+ * + 8 * (nl-1)/nl; per storage slot of a general netlist with an active scenario, sweep e * invD
+ * and residual 8 * D, and per off-diagonal entry of M (no padding), sweep e * w + 4 (its column
+ * index) and residual 8 * w + 4. */
 typedef struct pg_kernel_times {
   int64_t sweep_launches;  double sweep_ms;      int64_t sweep_node_updates;  double sweep_bytes;
   int64_t resid_launches;  double resid_ms;      int64_t resid_nodes;         double resid_bytes;

@@ -272,15 +272,16 @@ __device__ void decide_block(const Ctl& c, const DecideArgs& da) {
   const GridDesc* __restrict__ grids = da.grids;
   __shared__ int any;
   __shared__ int worked;
-  __shared__ unsigned long long act_nodes, act_coef;
+  __shared__ unsigned long long act_nodes, act_coef, act_rcoef;
   if (*c.stall) {  // a stalled opening: keep the sequence, report the decision as skipped
     if (threadIdx.x == 0) {
       const uint32_t seq = c.flag_seq[0];
       const uint32_t slot = seq & (uint32_t)(nslots - 1);
       c.flag_seq[0] = seq + 1u;
       const long long tag = (long long)(((unsigned long long)seq & 0xffffffull) << 40);
-      c.acct[2 * slot] = tag;
-      c.acct[2 * slot + 1] = tag;
+      c.acct[3 * slot] = tag;
+      c.acct[3 * slot + 1] = tag;
+      c.acct[3 * slot + 2] = tag;
       c.any_active[slot] = (int32_t)((seq & 0x1fffffffu) << 2 | 2u);
     }
     return;
@@ -292,10 +293,13 @@ __device__ void decide_block(const Ctl& c, const DecideArgs& da) {
   __shared__ uint32_t seq_s;
   const bool bitmap = G <= 32 * kMaxGridWords;
   const int nwords = bitmap ? (G + 31) / 32 : 0;
-  long long coef_mine = 0;  // coefficient words of grid threadIdx.x (the common case G <= blockDim)
-  if (bitmap && (int)threadIdx.x < G) coef_mine = grids[threadIdx.x].coef_words;
+  long long coef_mine = 0, rcoef_mine = 0;  // coefficient words of grid threadIdx.x (the common case G <= blockDim)
+  if (bitmap && (int)threadIdx.x < G) {
+    coef_mine = grids[threadIdx.x].coef_words;
+    rcoef_mine = grids[threadIdx.x].resid_words;
+  }
   if (threadIdx.x == 0) {
-    any = 0; worked = 0; act_nodes = 0ull; act_coef = 0ull;
+    any = 0; worked = 0; act_nodes = 0ull; act_coef = 0ull; act_rcoef = 0ull;
     seq_s = c.flag_seq[0];
   }
   for (int w = threadIdx.x; w < nwords; w += blockDim.x) gbits[w] = 0u;
@@ -337,16 +341,21 @@ __device__ void decide_block(const Ctl& c, const DecideArgs& da) {
   __syncthreads();
   for (int gi = threadIdx.x; gi < G; gi += blockDim.x) {
     bool any_in_grid = false;
-    long long words;
+    long long words, rwords;
     if (bitmap) {
       any_in_grid = (gbits[gi >> 5] >> (gi & 31)) & 1u;
       words = gi == (int)threadIdx.x ? coef_mine : grids[gi].coef_words;
+      rwords = gi == (int)threadIdx.x ? rcoef_mine : grids[gi].resid_words;
     } else {
       const GridDesc& D = grids[gi];
       for (int sc = 0; sc < D.S && !any_in_grid; ++sc) any_in_grid = c.active[D.item0 + sc] != 0;
       words = D.coef_words;
+      rwords = D.resid_words;
     }
-    if (any_in_grid) atomicAdd(&act_coef, (unsigned long long)words);
+    if (any_in_grid) {
+      atomicAdd(&act_coef, (unsigned long long)words);
+      atomicAdd(&act_rcoef, (unsigned long long)rwords);
+    }
   }
   __syncthreads();
   if (threadIdx.x == 0) {
@@ -358,8 +367,9 @@ __device__ void decide_block(const Ctl& c, const DecideArgs& da) {
     // host sees when it has arrived and no fence is needed before the flag
     const unsigned long long tag = ((unsigned long long)seq & 0xffffffull) << 40;
     constexpr unsigned long long kValue = (1ull << 40) - 1;
-    c.acct[2 * slot] = (long long)(tag | (act_nodes & kValue));
-    c.acct[2 * slot + 1] = (long long)(tag | (act_coef & kValue));
+    c.acct[3 * slot] = (long long)(tag | (act_nodes & kValue));
+    c.acct[3 * slot + 1] = (long long)(tag | (act_coef & kValue));
+    c.acct[3 * slot + 2] = (long long)(tag | (act_rcoef & kValue));
     c.any_active[slot] = (int32_t)((seq & 0x1fffffffu) << 2 | (uint32_t)any);
     if (worked) c.stat_checks[0] = checks + 1;
   }

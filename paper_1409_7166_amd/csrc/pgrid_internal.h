@@ -130,8 +130,9 @@ struct GridDesc {
   const double* gq64;
   const float* gsup32;
   const float* gw32;
-  // coefficient words one sweep reads (for the activity accounting of the decision)
-  int64_t coef_words;
+  // coefficient words one sweep reads, in the sweep precision, and FP64 words one residual pass
+  // reads (for the activity accounting of the decision)
+  int64_t coef_words, resid_words;
   // layered mesh: bit l set if layer l has a non-zero C/h (ch_layers) or a non-zero constant
   // injection (bc_layers); layers without are neither read nor written as anything but zero
   uint32_t ch_layers, bc_layers;
@@ -325,6 +326,37 @@ hipError_t launch_mesh_check(const double* gE, const double* gN, const double* C
 hipError_t launch_mesh_coef(const MeshCoefArgs& a, hipStream_t s);
 hipError_t launch_mesh_pads(int n, const int32_t* pad_slot, const double* pad_val, double* D64, void* invDs, int fp32,
                             hipStream_t s);
+// Resident path (pg_options.resident): one workgroup per item advances every item of the
+// context (layered meshes of at most kResMaxNodes nodes and kResMaxInd series R-L branches)
+// through nsteps whole backward-Euler steps in one launch, then sets the device clock to
+// k0 + nsteps.  item_src_off / item_src: the source-table entries of each item (CSR).  The
+// statistics are folded into the control block (stat_last_* are reset first).
+constexpr int kResMaxNodes = 4096;
+constexpr int kResMaxInd = 2048;
+struct ResidentArgs {
+  const GridDesc* grids;
+  const int32_t* item_grid;        // [I]
+  const int32_t* vidx;             // [I] current voltage buffer of each item
+  const int32_t* item_src_off;     // [I+1]
+  const int32_t* item_src;
+  const int32_t* src_index;        // the source table's target, offset and breakpoint arrays
+  const int32_t* src_off;
+  const double* src_t;
+  const double* src_i;
+  long long* stat_sweeps;          // the control block's statistics
+  long long* stat_updates;
+  long long* stat_checks;
+  int32_t* stat_max_sweeps;
+  int32_t* stat_last_sweeps;
+  int32_t* stat_failed;
+  double* stat_last_res;
+  double* stat_max_res;
+  long long* step;                 // the device clock
+  long long k0;
+  int n_items, nsteps, check_every, max_sweeps;
+  double h, tol, omega;
+};
+hipError_t launch_resident(const ResidentArgs& a, int max_nodes, bool multi_layer, hipStream_t s);
 // Clear the stall flag (after the host has re-queued a stalled step's remaining work).
 hipError_t launch_resume(const Ctl& c, hipStream_t s);
 // general graphs: right-hand side, one colour of a sweep (in place on d[0]), FP64 residual

@@ -81,7 +81,7 @@ struct GridHost {
   // index into that order; ind_sign[k] turns the stored near -> far current into the branch's
   std::vector<int32_t> ind_a, ind_b, ind_branch;
   std::vector<double> ind_sign;
-  int64_t coef_words = 0;                        // coefficient words of one sweep (accounting)
+  int64_t coef_words = 0, resid_words = 0;       // coefficient words of one sweep / residual (accounting)
   uint32_t ch_layers = 0, bc_layers = 0;         // layers with non-zero C/h, constant injection
   // device buffers
   DBuf gE64, gN64, gU64, D64, ch64, bconst64, gEs, gNs, gUs, invDs;
@@ -137,7 +137,8 @@ struct pg_ctx {
     const double e = opt.precision == PG_PREC_FP32_REFINE ? 4.0 : 8.0;
     return e * ((2.0 + 3.0 * (L - 1)) * an + (double)L * coef);
   }
-  double resid_bytes(int64_t an, int64_t coef, bool has_d, int fuse = 0) const {
+  // `coef` sweep-precision coefficient words (the probe reads those), `rcoef` FP64 words.
+  double resid_bytes(int64_t an, int64_t coef, int64_t rcoef, bool has_d, int fuse = 0) const {
     const double e = opt.precision == PG_PREC_FP32_REFINE ? 4.0 : 8.0;
     if ((fuse & kFuseProbe) && (fuse & kFuseCancelled)) {
       // the cancelled-form probe: v and G0 Vdd on the layers that have it (probe_read bytes per
@@ -148,9 +149,9 @@ struct pg_ctx {
       // forms b and M_ii: v, C/h and G0 Vdd on the layers that have them (fuse_read bytes per
       // node on average), b and r unless a probe; coefficients without M_ii (one word per node)
       const double st = (fuse & kFuseProbe) ? 0.0 : 8.0 + e;
-      return (fuse_read + st) * an + 8.0 * (double)std::max<int64_t>(0, coef - an);
+      return (fuse_read + st) * an + 8.0 * (double)std::max<int64_t>(0, rcoef - an);
     }
-    return (16.0 + e + (has_d ? e + 8.0 : 0.0)) * an + 8.0 * coef;
+    return (16.0 + e + (has_d ? e + 8.0 : 0.0)) * an + 8.0 * rcoef;
   }
   std::vector<Group> tile_groups;                 // sweep/residual tiles by (layers, block): [off, off+count) of tiles_sweep
   int ntiles_all = 0;
@@ -166,6 +167,9 @@ struct pg_ctx {
   std::vector<int> item_gchunk_off, item_gchunk_cnt;
   int n_src = 0, n_ind_total = 0;
   SourceTable src_table{};                       // device source tables (see pgrid_internal.h)
+  DBuf res_src_off, res_src;                     // resident path: each item's source-table entries (CSR)
+  int res_max_nodes = 0;                         // resident path: the largest grid's node count
+  bool res_multi_layer = false;                  // resident path: some grid has more than one layer
   DBuf src_win_t0;
   long long step_host = 0;                       // staging for the device step counter
   DBuf c_clock;                                  // step (int64), t_now (double), window (2 x int32)
@@ -197,10 +201,10 @@ struct pg_ctx {
   hipGraphExec_t g_prologue = nullptr, g_sweeps = nullptr, g_check = nullptr, g_epilogue = nullptr;
   bool graphs_ready = false;
   int64_t all_nodes = 0;                         // mesh nodes x scenarios over all grids
-  int64_t all_coef = 0;                          // coefficient words over all grids
-  int64_t graph_nodes = 0, graph_coef = 0, graph_entries = 0;  // the general graphs' share (slots x scenarios)
-  int64_t begin_nodes = 0, begin_coef = 0;       // work of the step's first residual (items begun)
-  long long* host_acct = nullptr;                // pinned [slots][2]: active work after each decision
+  int64_t all_coef = 0, all_rcoef = 0;           // coefficient words over all grids (sweep, residual)
+  int64_t graph_nodes = 0, graph_coef = 0, graph_rcoef = 0, graph_entries = 0;  // the general graphs' share
+  int64_t begin_nodes = 0, begin_coef = 0, begin_rcoef = 0;  // work of the step's first residual (items begun)
+  long long* host_acct = nullptr;                // pinned [slots][3]: active work after each decision
   long long* dev_acct = nullptr;
   int32_t* dev_flags = nullptr;                  // device address of host_flags
   // profiling
@@ -651,12 +655,16 @@ GridDesc make_desc(pg_ctx* c, GridHost& H) {
     D.g3diag = (const double*)H.g3diag_d.p; D.sl_g64 = (const double*)H.sl_g64_d.p;
     D.bres64 = (const double*)H.bres_d.p; D.bl64 = (const double*)H.bl_d.p;
     D.gq64 = (const double*)H.gq64_d.p; D.gsup32 = (const float*)H.gsup32_d.p; D.gw32 = (const float*)H.gw32_d.p;
-    // invD, w (the column indices count as half a word in FP64 residuals)
-    H.coef_words = H.nstore + (3 * H.form.nnz) / 2;
+    // sweep: 1/M_ii and w in the sweep precision, and a 4-byte column index per table entry;
+    // residual: M_ii and w in FP64 and the column index (half an FP64 word)
+    H.coef_words = H.nstore + (fp32_mode(c) ? 2 * H.form.nnz : (3 * H.form.nnz) / 2);
+    H.resid_words = H.nstore + (3 * H.form.nnz) / 2;
   } else {
     H.coef_words = 3 * H.n + (int64_t)H.nx * H.ny * (H.nl - 1);
+    H.resid_words = H.coef_words;
   }
   D.coef_words = H.coef_words;
+  D.resid_words = H.resid_words;
   D.ch_layers = H.ch_layers;
   D.bc_layers = H.bc_layers;
   return D;
@@ -749,17 +757,19 @@ pg_status prepare(pg_ctx* c) {
   }
   c->ntiles_all = (int)tiles.size();
   c->all_nodes = 0;
-  c->all_coef = 0;
-  c->graph_nodes = c->graph_coef = c->graph_entries = 0;
+  c->all_coef = c->all_rcoef = 0;
+  c->graph_nodes = c->graph_coef = c->graph_rcoef = c->graph_entries = 0;
   for (auto& grp : c->tile_groups) c->all_nodes += grp.nodes;
   double fr = 0.0, fp = 0.0, fn = 0.0;
   c->probe_cancelled = true;
   for (auto& H : c->grids) {
     c->all_coef += H.coef_words;
+    c->all_rcoef += H.resid_words;
     if (H.kind) {
       c->all_nodes += H.n * H.S;
       c->graph_nodes += H.n * H.S;
       c->graph_coef += H.coef_words;
+      c->graph_rcoef += H.resid_words;
       c->graph_entries += H.form.nnz * H.S;  // algorithmic: the stored padding is not charged
     } else {
       const double w = (double)H.n * H.S;
@@ -857,6 +867,30 @@ pg_status prepare(pg_ctx* c) {
                              (const int32_t*)c->src_off.p, (const double*)c->src_t.p, (const double*)c->src_i.p,
                              (int32_t)always.size(), (int32_t)windowed.size(), (const double*)c->src_win_t0.p,
                              win_maxw};
+  if (c->opt.resident) {
+    // resident path: every grid must fit one workgroup; each item's sources, grouped by item
+    c->res_max_nodes = 0;
+    c->res_multi_layer = false;
+    for (int g = 0; g < G; ++g) {
+      const GridHost& H = c->grids[g];
+      if (H.kind || H.n > kResMaxNodes || (int64_t)H.ind_a.size() > kResMaxInd)
+        return set_err(c, PG_ERR_UNSUPPORTED, "resident: grid %d is %s; the resident path takes layered meshes of "
+                       "at most %d nodes and %d series R-L branches", g,
+                       H.kind ? "a general netlist" : "too large", kResMaxNodes, kResMaxInd);
+      c->res_max_nodes = std::max<int>(c->res_max_nodes, (int)H.n);
+      c->res_multi_layer = c->res_multi_layer || H.nl > 1;
+    }
+    if (c->opt.ordering != PG_ORDER_RED_BLACK)
+      return set_err(c, PG_ERR_UNSUPPORTED, "resident: the resident path sweeps in red-black order");
+    const int I = n_items(c);
+    std::vector<int32_t> cnt(I + 1, 0), ids(sg.size());
+    auto item_of = [&](size_t k) { const GridHost& H = c->grids[sg[k]]; return H.item0 + (int)(si[k] / H.nstore); };
+    for (size_t k = 0; k < sg.size(); ++k) cnt[item_of(k) + 1]++;
+    for (int q = 0; q < I; ++q) cnt[q + 1] += cnt[q];
+    std::vector<int32_t> fill(cnt.begin(), cnt.end() - 1);
+    for (size_t k = 0; k < sg.size(); ++k) ids[fill[item_of(k)]++] = (int32_t)k;
+    PG_TRY(upload(c, c->res_src_off, cnt)); PG_TRY(upload(c, c->res_src, ids));
+  }
   // flattened inductor list
   std::vector<int32_t> ig, il;
   for (int g = 0; g < G; ++g)
@@ -948,15 +982,16 @@ pg_status launch_resid_all(pg_ctx* c, int has_d, int din, double tol = 0.0, int*
   c->fuse_next = 0;
   const bool gprobe = !has_d && c->gprobe_next, gstore = !has_d && c->gstore_next;
   c->gprobe_next = c->gstore_next = false;
-  double bytes = c->resid_bytes(c->begin_nodes, c->begin_coef, has_d != 0, fuse);
+  double bytes = c->resid_bytes(c->begin_nodes, c->begin_coef, c->begin_rcoef, has_d != 0, fuse);
   if (gprobe || gstore) {  // whole steps only: the meshes' share, then the graphs' by their pass
     const double e = c->opt.precision == PG_PREC_FP32_REFINE ? 4.0 : 8.0;
     const double gn = (double)c->graph_nodes;
-    bytes = meshes ? c->resid_bytes(c->all_nodes - c->graph_nodes, c->all_coef - c->graph_coef, false, fuse) : 0.0;
+    bytes = meshes ? c->resid_bytes(c->all_nodes - c->graph_nodes, c->all_coef - c->graph_coef,
+                                    c->all_rcoef - c->graph_rcoef, false, fuse) : 0.0;
     if (gprobe)  // v, 1/M_ii, q, gsup per slot; column and FP32 conductance per table entry
       bytes += (20.0 + e) * gn + 8.0 * (double)c->graph_entries;
     else  // b formed (C/h, constant, v, b), then r and v stored
-      bytes += 32.0 * gn + (16.0 + e) * gn + 8.0 * (double)c->graph_coef;
+      bytes += 32.0 * gn + (16.0 + e) * gn + 8.0 * (double)c->graph_rcoef;
   }
   ProfScope ps(c, 1, c->begin_nodes, bytes, (int)c->tile_groups.size() + (c->n_gchunks_all ? 1 : 0) + (tag ? 1 : 0));
   for (auto& grp : c->tile_groups) {
@@ -1083,11 +1118,13 @@ pg_status begin_step(pg_ctx* c, int only_item, bool begun = false, int64_t dev_s
   const int G = n_items(c);
   c->begin_nodes = c->all_nodes;
   c->begin_coef = c->all_coef;
+  c->begin_rcoef = c->all_rcoef;
   if (only_item >= 0) {
     for (auto& H : c->grids)
       if (only_item >= H.item0 && only_item < H.item0 + H.S) {
         c->begin_nodes = H.n;
         c->begin_coef = H.coef_words;
+        c->begin_rcoef = H.resid_words;
       }
   }
   Ctl k = c->ctl;
@@ -1149,18 +1186,25 @@ pg_status begin_step(pg_ctx* c, int only_item, bool begun = false, int64_t dev_s
 // (tag << 2) | (skipped << 1) | any after writing its accounting words; every so often ask
 // whether the stream still has work, so a flag that can no longer arrive is reported, not
 // awaited.
-// The active work a decision found (scenario nodes, coefficient words).  k_decide stores these
-// two words just before its flag without a fence; each carries the low 24 bits of the decision's
-// sequence above a 40-bit value, so once the flag is seen the host waits until both match.
-pg_status read_acct(pg_ctx* c, int tag, long long* nodes, long long* coef) {
+// The active work a decision found (scenario nodes, sweep and residual coefficient words).
+// k_decide stores these three words just before its flag without a fence; each carries the low
+// 24 bits of the decision's sequence above a 40-bit value, so once the flag is seen the host
+// waits until all three match.
+struct Acct { long long nodes, coef, rcoef; };
+pg_status read_acct(pg_ctx* c, int tag, Acct* out) {
   const int slot = (int)((uint32_t)tag & (kFlagSlots - 1));
   const unsigned long long want = (uint32_t)tag & 0xffffffu, value = (1ull << 40) - 1;
   for (long spin = 1;; ++spin) {
-    const unsigned long long a = (unsigned long long)__atomic_load_n(c->host_acct + 2 * slot, __ATOMIC_ACQUIRE);
-    const unsigned long long b = (unsigned long long)__atomic_load_n(c->host_acct + 2 * slot + 1, __ATOMIC_ACQUIRE);
-    if ((a >> 40) == want && (b >> 40) == want) {
-      *nodes = (long long)(a & value);
-      *coef = (long long)(b & value);
+    unsigned long long w[3];
+    bool ok = true;
+    for (int k = 0; k < 3; ++k) {
+      w[k] = (unsigned long long)__atomic_load_n(c->host_acct + 3 * slot + k, __ATOMIC_ACQUIRE);
+      ok = ok && (w[k] >> 40) == want;
+    }
+    if (ok) {
+      out->nodes = (long long)(w[0] & value);
+      out->coef = (long long)(w[1] & value);
+      out->rcoef = (long long)(w[2] & value);
       return PG_OK;
     }
     if ((spin & 1023) == 0 && hipStreamQuery(c->stream) == hipSuccess && spin > (1L << 20))
@@ -1239,7 +1283,7 @@ pg_status cycle_loop(pg_ctx* c, double tol, bool graphs, int first, bool specula
   const size_t prof_base = c->prof_live.size();
   const int max_chunks = (c->opt.max_sweeps + nchk - 1) / nchk;
   int issued = 0, consumed = 0, last = -1;
-  std::vector<std::pair<int64_t, int64_t>> work;  // active work after decision j (0: the initial check)
+  std::vector<Acct> work;  // active work after decision j (0: the initial check)
   // Speculation: after the predicted cycles, queue this step's close and the next step's opening
   // before waiting.  If a decision queued before them converges, the step is done and the next
   // opening is already on its way; if none does, the close stalls the device, the opening does
@@ -1290,9 +1334,9 @@ pg_status cycle_loop(pg_ctx* c, double tol, bool graphs, int first, bool specula
     int any = 0;
     PG_TRY(wait_decision(c, t0, &any));
     ++consumed;
-    long long a_nodes = 0, a_coef = 0;
-    PG_TRY(read_acct(c, t0, &a_nodes, &a_coef));
-    work.emplace_back(a_nodes, a_coef);
+    Acct a{};
+    PG_TRY(read_acct(c, t0, &a));
+    work.push_back(a);
     if (!any) {
       last = consumed - 1;
       break;
@@ -1322,13 +1366,13 @@ pg_status cycle_loop(pg_ctx* c, double tol, bool graphs, int first, bool specula
     ProfEvent& ev = c->prof_live[q];
     if (ev.chunk > last) { ev.kind = -1; continue; }
     if (ev.chunk < 1 || (ev.kind != 0 && ev.kind != 1)) continue;
-    const auto& wk = work[ev.chunk - 1];
+    const Acct& wk = work[ev.chunk - 1];
     if (ev.kind == 0) {
-      ev.units = wk.first * nchk;
-      ev.bytes = c->cycle_bytes(wk.first, wk.second, cycle_launches(c, nchk));
+      ev.units = wk.nodes * nchk;
+      ev.bytes = c->cycle_bytes(wk.nodes, wk.coef, cycle_launches(c, nchk));
     } else {
-      ev.units = wk.first;
-      ev.bytes = c->resid_bytes(wk.first, wk.second, true);
+      ev.units = wk.nodes;
+      ev.bytes = c->resid_bytes(wk.nodes, wk.coef, wk.rcoef, true);
     }
   }
   return PG_OK;
@@ -1467,6 +1511,41 @@ pg_status queue_close(pg_ctx* c, bool open_next) {
 
 // One BE step of every item.  With `speculate`, the next step's opening is queued ahead (see
 // cycle_loop) and picked up by the next call.
+// nsteps whole steps of every item in one launch (the resident path).
+pg_status resident_steps(pg_ctx* c, int nsteps) {
+  ResidentArgs a{};
+  const Ctl& k = c->ctl;
+  a.grids = (const GridDesc*)c->grid_desc.p;
+  a.item_grid = (const int32_t*)c->c_item_grid.p;
+  a.vidx = k.vidx;
+  a.item_src_off = (const int32_t*)c->res_src_off.p;
+  a.item_src = (const int32_t*)c->res_src.p;
+  a.src_index = c->src_table.index;
+  a.src_off = c->src_table.off;
+  a.src_t = c->src_table.t;
+  a.src_i = c->src_table.i;
+  a.stat_sweeps = k.stat_sweeps; a.stat_updates = k.stat_updates; a.stat_checks = k.stat_checks;
+  a.stat_max_sweeps = k.stat_max_sweeps; a.stat_last_sweeps = k.stat_last_sweeps; a.stat_failed = k.stat_failed;
+  a.stat_last_res = k.stat_last_res; a.stat_max_res = k.stat_max_res;
+  a.step = k.step;
+  a.k0 = c->step;
+  a.n_items = n_items(c);
+  a.nsteps = nsteps;
+  a.check_every = c->opt.check_every;
+  a.max_sweeps = c->opt.max_sweeps;
+  a.h = c->opt.h;
+  a.tol = c->opt.tol;
+  a.omega = c->opt.omega;
+  hipError_t e;
+  {
+    ProfScope ps(c, 3, 0);
+    e = launch_resident(a, c->res_max_nodes, c->res_multi_layer, c->stream);
+  }
+  if (e != hipSuccess) return set_err(c, PG_ERR_DEVICE, "resident launch: %s", hipGetErrorString(e));
+  c->step += nsteps;
+  return PG_OK;
+}
+
 pg_status one_step(pg_ctx* c, bool speculate = false, bool speculate_after = false) {
   int first = 0;
   if (c->opening_queued) {
@@ -1691,7 +1770,7 @@ pg_status pg_create(pg_ctx** out, int32_t device, void* stream) {
     return PG_ERR_DEVICE;
   }
   std::memset(c->host_flags, 0xff, nslots * sizeof(int32_t));  // no tag matches before a decision runs
-  if (hipHostMalloc((void**)&c->host_acct, 2 * nslots * sizeof(long long), hipHostMallocMapped | hipHostMallocCoherent) !=
+  if (hipHostMalloc((void**)&c->host_acct, 3 * nslots * sizeof(long long), hipHostMallocMapped | hipHostMallocCoherent) !=
           hipSuccess ||
       hipHostGetDevicePointer((void**)&c->dev_acct, c->host_acct, 0) != hipSuccess) {
     pg_destroy(c);
@@ -1700,7 +1779,7 @@ pg_status pg_create(pg_ctx** out, int32_t device, void* stream) {
   // slot s only ever receives decisions whose sequence is s modulo nslots; its initial words carry
   // the tag s + 1 (not congruent to s), so no decision's tag matches them before it has written
   for (int s = 0; s < nslots; ++s)
-    c->host_acct[2 * s] = c->host_acct[2 * s + 1] = (long long)((unsigned long long)(s + 1) << 40);
+    for (int k = 0; k < 3; ++k) c->host_acct[3 * s + k] = (long long)((unsigned long long)(s + 1) << 40);
 
   if (dalloc(c, c->c_stats64, 3 * sizeof(long long)) != PG_OK || dalloc(c, c->c_stats32, 4 * sizeof(int32_t)) != PG_OK ||
       dalloc(c, c->c_statsd, 2 * sizeof(double)) != PG_OK) {
@@ -1754,7 +1833,7 @@ void pg_destroy(pg_ctx* c) {
                   &c->g_chunks_all, &c->g_chunks_sweep,
                   &c->ind_grid, &c->ind_local, &c->c_norm, &c->c_last, &c->c_active, &c->c_vidx, &c->c_sweeps,
                   &c->c_failed, &c->c_any, &c->c_stats64, &c->c_stats32, &c->c_statsd, &c->c_nodes, &c->c_item_grid,
-                  &c->c_clock, &c->src_win_t0};
+                  &c->c_clock, &c->src_win_t0, &c->res_src_off, &c->res_src};
   for (DBuf* b : bufs) dfree(*b);
   DBuf* abufs[] = {&c->adj.ckpts, &c->adj.vend, &c->adj.seg, &c->adj.lam0, &c->adj.lam1, &c->adj.arhs,
                    &c->adj.dC, &c->adj.dgE, &c->adj.dgN, &c->adj.part, &c->adj.J, &c->adj.saved_vidx,
@@ -1781,7 +1860,7 @@ pg_status pg_set_options(pg_ctx* c, const pg_options* o) {
   // h and precision change the coefficients, tile_rows and scen_block the tiles, the recurrence
   // the buffers of general netlists: rebuild; anything else only invalidates the captured graphs
   if (o->h != c->opt.h || o->precision != c->opt.precision || o->tile_rows != c->opt.tile_rows ||
-      o->scen_block != c->opt.scen_block || o->recurrence != c->opt.recurrence)
+      o->scen_block != c->opt.scen_block || o->recurrence != c->opt.recurrence || o->resident != c->opt.resident)
     c->dirty = true;
   drop_graphs(c);
   c->opt = *o;
@@ -2190,11 +2269,23 @@ pg_status pg_run_transient(pg_ctx* c, int32_t nsteps, int32_t record_every, int3
   if (out) PG_TRY(check_gs(c, grid, scen));
   const auto t0 = std::chrono::steady_clock::now();
   int rec = 0;
-  for (int k = 0; k < nsteps; ++k) {
-    PG_TRY(one_step(c, k + 1 < nsteps, k + 2 < nsteps));
-    if (out && ((k + 1) % record_every) == 0) {
-      PG_TRY(pg_read_voltages(c, grid, scen, out + (size_t)rec * c->grids[grid].n, c->grids[grid].n));
-      ++rec;
+  if (c->opt.resident) {  // one launch per call, or per recorded interval
+    const int chunk = out ? record_every : std::max(1, nsteps);
+    for (int k = 0; k < nsteps; k += chunk) {
+      const int m = std::min(chunk, nsteps - k);
+      PG_TRY(resident_steps(c, m));
+      if (out && m == record_every) {
+        PG_TRY(pg_read_voltages(c, grid, scen, out + (size_t)rec * c->grids[grid].n, c->grids[grid].n));
+        ++rec;
+      }
+    }
+  } else {
+    for (int k = 0; k < nsteps; ++k) {
+      PG_TRY(one_step(c, k + 1 < nsteps, k + 2 < nsteps));
+      if (out && ((k + 1) % record_every) == 0) {
+        PG_TRY(pg_read_voltages(c, grid, scen, out + (size_t)rec * c->grids[grid].n, c->grids[grid].n));
+        ++rec;
+      }
     }
   }
   HIP_TRY(c, hipStreamSynchronize(c->stream));

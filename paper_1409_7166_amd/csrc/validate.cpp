@@ -102,8 +102,9 @@ pg_status pg_validate_options(const pg_options* o, char* msg, size_t len) {
     return fail(PG_ERR_INVALID_ARG, msg, len, "unknown recurrence %d", o->recurrence);
   if (o->recurrence == PG_REC_THREE_LEVEL && o->graphs)
     return fail(PG_ERR_UNSUPPORTED, msg, len, "the three-level recurrence runs with plain launches (graphs = 0)");
-  for (int i = 0; i < 2; ++i)
-    if (o->reserved[i] != 0) return fail(PG_ERR_INVALID_ARG, msg, len, "reserved option fields must be zero");
+  if (o->resident != 0 && o->resident != 1)
+    return fail(PG_ERR_INVALID_ARG, msg, len, "resident must be 0 or 1 (got %d)", o->resident);
+  if (o->reserved[0] != 0) return fail(PG_ERR_INVALID_ARG, msg, len, "reserved option fields must be zero");
   return PG_OK;
 }
 

@@ -39,8 +39,8 @@ class Options(C.Structure):
                 ("max_sweeps", C.c_int32), ("check_every", C.c_int32), ("precision", C.c_int32),
                 ("ordering", C.c_int32), ("tile_rows", C.c_int32), ("lookahead", C.c_int32),
                 ("graphs", C.c_int32), ("scen_block", C.c_int32),
-                ("sweeps_per_launch", C.c_int32), ("recurrence", C.c_int32),
-                ("reserved", C.c_int32 * 2)]
+                ("sweeps_per_launch", C.c_int32), ("recurrence", C.c_int32), ("resident", C.c_int32),
+                ("reserved", C.c_int32 * 1)]
 
 
 class MeshStruct(C.Structure):
