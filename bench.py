@@ -133,21 +133,27 @@ GOLDEN = {
     "config3a": os.path.join(ROOT, "tests", "golden", "config3a_batch_256scen_256x256_samples.npz"),
 }
 
-COUNTERS = os.path.join(ROOT, "profiles", "k_sweep_rb_rc3x1024_counters.json")
+# rocprofv3 FETCH_SIZE / WRITE_SIZE summaries of the FP32 sweep kernel, per workload
+COUNTERS = {
+    "config1": os.path.join(ROOT, "profiles", "k_sweep_rb_rc3x1024_counters.json"),
+    "config1_hbm": os.path.join(ROOT, "profiles", "k_sweep_rb_rc3x2048_counters.json"),
+    "config3a": os.path.join(ROOT, "profiles", "k_sweep_rb_multi_batch256x256_counters.json"),
+}
 
 
-def counter_traffic(avg_alg_bytes):
+def counter_traffic(name, kernel, avg_alg_bytes):
     """HBM traffic per sweep launch from the committed rocprofv3 FETCH_SIZE/WRITE_SIZE summary
-    (scaled by a plain copy's counts), mixed like the timed launches; None if the kernels changed."""
+    (scaled by a plain copy's counts), mixed like the timed launches (full sweeps and the first
+    sweep of each cycle, which reads no old correction); None if the kernels changed since."""
     import hashlib
     try:
-        summ = json.load(open(COUNTERS))
-    except OSError:
+        summ = json.load(open(COUNTERS[name]))
+    except (KeyError, OSError):
         return None
     src = open(os.path.join(ROOT, "paper_1409_7166_amd", "csrc", "kernels.hip"), "rb").read()
-    if hashlib.sha256(src).hexdigest()[:16] != summ["kernels_hip_sha256_16"]:
+    if hashlib.sha256(src).hexdigest()[:16] != summ["kernels_hip_sha256_16"] or kernel not in summ:
         return None
-    full, cold = summ["k_sweep_rb"]["full_launch"], summ["k_sweep_rb"]["cold_start_launch"]
+    full, cold = summ[kernel]["full_launch"], summ[kernel]["cold_start_launch"]
     a_full, a_cold = full["algorithmic_bytes"], cold["algorithmic_bytes"]
     f_cold = min(1.0, max(0.0, (a_full - avg_alg_bytes) / (a_full - a_cold)))
     return f_cold * cold["traffic_bytes"] + (1.0 - f_cold) * full["traffic_bytes"]
@@ -403,7 +409,7 @@ def measure(name, prec, tol, steps, args, do_verify=True):
         sweep_s = kt["sweep_ms"] * 1e-3
         achieved = kt["sweep_bytes"] / sweep_s
         per_launch = kt["sweep_bytes"] / kt["sweep_launches"]
-        traffic = counter_traffic(per_launch) if name == "config1" and prec == "fp32+ref" else None
+        traffic = counter_traffic(name, sweep_kernel_name(w, spl), per_launch) if prec == "fp32+ref" else None
         roof = {"bound": "hbm", "achieved": achieved / 1e9, "peak": HBM_PEAK / 1e9, "unit": "GB/s",
                 "frac": achieved / HBM_PEAK, "traffic": traffic,
                 # "mall": the sweep's working set fits in the 256 MB Infinity Cache, so part of its
