@@ -129,8 +129,12 @@ LEGS = [
 
 # Oracle values of sampled nodes at every step (written by tests/golden/make_golden.py).
 GOLDEN = {
+    "config0": os.path.join(ROOT, "tests", "golden", "config0_rc_32x32_all_nodes.npz"),
     "config1": os.path.join(ROOT, "tests", "golden", "config1_rc_3x1024x1024_samples.npz"),
+    "config2": os.path.join(ROOT, "tests", "golden", "config2_rlc_2x512x512_samples.npz"),
     "config3a": os.path.join(ROOT, "tests", "golden", "config3a_batch_256scen_256x256_samples.npz"),
+    "config3b": os.path.join(ROOT, "tests", "golden", "config3b_batch_64grids_samples.npz"),
+    "config4": os.path.join(ROOT, "tests", "golden", "config4_rc_1024x1024_samples.npz"),
 }
 
 # rocprofv3 FETCH_SIZE / WRITE_SIZE summaries of the FP32 sweep kernel, per workload
@@ -189,7 +193,8 @@ def sweep_kernel_name(w, sweeps_per_launch):
 def verify(ctx, w, name):
     """Untimed: the whole transient again from t = 0 in the same launch configuration, comparing
     at every step the voltages of the stored sample of nodes (and the largest drop over all nodes)
-    with the oracle's.  Returns a dict, or None when no stored values exist for the workload."""
+    with the oracle's, for every stored (grid, scenario) item.  Returns a dict, or None when no
+    stored values exist for the workload."""
     import numpy as np
     import torch
 
@@ -197,41 +202,51 @@ def verify(ctx, w, name):
     if path is None or not os.path.exists(path):
         return None
     g = np.load(path)
-    nodes = g["nodes"].astype(np.int64)
     steps = int(g["steps"])
     vdd = float(g["vdd"])
-    scen = g["scenarios"].tolist() if "scenarios" in g.files else [0]
-    ref = g["drops"].astype(np.float64)              # [steps, nodes] or [scen, steps, nodes]
+    ref = g["drops"].astype(np.float64)              # [steps, K] or [items, steps, K]
     ref_max = g["max_drop"]
     if ref.ndim == 2:
         ref, ref_max = ref[None], ref_max[None]
-    mesh = w.meshes[0]
-    buf = torch.empty(mesh.n, dtype=torch.float64, device="cuda:0")
-    idx = torch.from_numpy(nodes).to("cuda:0")
-    worst = np.zeros(len(scen))
-    worst_max = np.zeros(len(scen))
+    J = ref.shape[0]
+    scen = g["scenarios"].tolist() if "scenarios" in g.files else [0] * J
+    grids = g["grids"].tolist() if "grids" in g.files else [0] * J
+    nodes = g["nodes"].astype(np.int64)
+    nodes = np.broadcast_to(nodes, (J, nodes.shape[-1])) if nodes.ndim == 1 else nodes
+    bufs = {gi: torch.empty(w.meshes[gi].n, dtype=torch.float64, device="cuda:0") for gi in set(grids)}
+    idx = [torch.from_numpy(np.ascontiguousarray(nodes[j])).to("cuda:0") for j in range(J)]
+    worst = np.zeros(J)
+    worst_max = np.zeros(J)
+    il_ref = g["il_every10"] if "il_every10" in g.files else None   # branch currents at steps 10, 20, ..
+    worst_il = 0.0
     ctx.reset()
     sweeps0 = ctx.stats()["sweeps"]
     t0 = time.perf_counter()
     for k in range(steps):
         ctx.step(1)
-        for j, s in enumerate(scen):
-            ctx.read_voltages_dev(0, s, buf)
+        for j in range(J):
+            buf = bufs[grids[j]]
+            ctx.read_voltages_dev(grids[j], scen[j], buf)
             d = vdd - buf
-            samp = d[idx].cpu().numpy()
+            samp = d[idx[j]].cpu().numpy()
             dmax = float(d.max())
             worst[j] = max(worst[j], float(np.max(np.abs(samp - ref[j, k]))))
             worst_max[j] = max(worst_max[j], abs(dmax - float(ref_max[j, k])))
+        if il_ref is not None and (k + 1) % 10 == 0:
+            il = ctx.read_inductor_currents(grids[0], scen[0])
+            worst_il = max(worst_il, float(np.max(np.abs(il - il_ref[(k + 1) // 10 - 1]))))
     torch.cuda.synchronize()
     st = ctx.stats()
     return {"max_abs_error_V": float(worst.max()), "max_drop_error_V": float(worst_max.max()),
-            "steps": steps, "scenarios": len(scen), "sampled_nodes": int(nodes.size),
+            "steps": steps, "items": J, "sampled_nodes": int(nodes.shape[-1]),
             "sweeps_per_step": (st["sweeps"] - sweeps0) / steps,
             "peak_drop_V": float(np.max(ref_max)), "seconds": time.perf_counter() - t0,
             "against": os.path.relpath(path, ROOT),
-            "what": "max over every step and the sampled nodes (all layers; the bottom-layer nodes farthest "
-                    "from the pads among them) of |v_gpu - v_oracle|; max_drop_error_V compares the largest "
-                    "drop over all nodes at every step"}
+            **({"max_branch_current_error_A": worst_il,
+                "max_branch_current_A": float(np.max(np.abs(il_ref)))} if il_ref is not None else {}),
+            "what": "max over every step, the stored (grid, scenario) items and their sampled nodes of "
+                    "|v_gpu - v_oracle|; max_drop_error_V compares the largest drop over all nodes at every step"
+                    + ("; branch currents of every via and pad at every 10th step" if il_ref is not None else "")}
 
 
 def run_gpu(w, name, steps, warmup, precision, tol, omega, check_every, tile_rows, lookahead, profile_every,
@@ -374,12 +389,18 @@ def copy_probe():
     print(json.dumps({"copy_probe_bytes_each_way": n * 4, "launches": 3}))
 
 
-# (workload, precision, tolerance, steps) of the side-by-side report
+# (workload, precision, tolerance, steps) of the side-by-side report: every workload at the
+# metric's 1e-6 V and at its parity tolerance
 SIDE_BY_SIDE = [
-    ("config1", "fp32+ref", 1e-6, 1000), ("config1", "fp64", 1e-6, 1000), ("config1", "fp32+ref", 1e-10, 300),
-    ("config3a", "fp32+ref", 1e-6, 500), ("config3b", "fp32+ref", 1e-6, 500),
-    ("config2", "fp64", 1e-6, 2000), ("config2", "fp32+ref", 1e-6, 2000),
-    ("config4", "fp64", 1e-6, 200), ("config0", "fp64", 1e-6, 100),
+    ("config1", "fp32+ref", 1e-6, 1000), ("config1", "fp32+ref", 1e-10, 1000),
+    ("config1", "fp64", 1e-6, 1000), ("config1", "fp64", 1e-10, 1000),
+    ("config1_hbm", "fp32+ref", 1e-6, 200), ("config1_hbm", "fp32+ref", 1e-10, 200),
+    ("config3a", "fp32+ref", 1e-6, 500), ("config3a", "fp32+ref", 1e-10, 500),
+    ("config3b", "fp32+ref", 1e-6, 500), ("config3b", "fp32+ref", 1e-10, 500),
+    ("config2", "fp64", 1e-6, 2000), ("config2", "fp64", 1e-11, 2000),
+    ("config2", "fp32+ref", 1e-6, 2000), ("config2", "fp32+ref", 1e-11, 2000),
+    ("config4", "fp64", 1e-6, 200), ("config4", "fp64", 1e-10, 200),
+    ("config0", "fp64", 1e-6, 100), ("config0", "fp64", 1e-10, 100),
     ("graph1", "fp32+ref", 1e-6, 1000), ("graph_mesh1", "fp32+ref", 1e-6, 1000),
 ]
 

@@ -1,6 +1,7 @@
 """Write the sampled oracle trajectories under ``tests/golden/`` (FP64 CPU oracle only).
 
-Usage:  python tests/golden/make_golden.py <name> [...]     names: config1, config3a, config2
+Usage:  python tests/golden/make_golden.py <name> [...]
+        names: config0, config1, config2, config3a, config3b, config4
 
 Each file holds, for every backward-Euler step k = 1..K of one seeded workload, the oracle's
 voltages at a fixed, seeded set of sampled nodes (stored as the drop below the supply,
@@ -27,7 +28,7 @@ if ROOT not in sys.path:
 from oracle import BEStepper, mesh_to_circuit  # noqa: E402
 from oracle.sources import currents_at  # noqa: E402
 from oracle.transient import initial_state  # noqa: E402
-from workloads import config1, config2, config3a  # noqa: E402
+from workloads import config0, config1, config2, config3a, config3b, config4  # noqa: E402
 
 SAMPLE_SEED = 71660
 
@@ -114,7 +115,43 @@ def make_config2():
                         workload=np.array(w.name), **out)
 
 
-MAKERS = {"config1": make_config1, "config3a": make_config3a, "config2": make_config2}
+def make_config0():
+    w = config0()
+    mesh, p = w.meshes[0], w.pulses[0][0]
+    out = trajectory(mesh, p, w.h, w.steps, np.arange(mesh.n, dtype=np.int64), log_every=50, tag=w.name)
+    np.savez_compressed(os.path.join(HERE, "config0_rc_32x32_all_nodes.npz"), workload=np.array(w.name), **out)
+
+
+def make_config4():
+    w = config4()
+    mesh, p = w.meshes[0], w.pulses[0][0]
+    out = trajectory(mesh, p, w.h, w.steps, sample_nodes(mesh), log_every=50, tag=w.name)
+    np.savez_compressed(os.path.join(HERE, "config4_rc_1024x1024_samples.npz"), workload=np.array(w.name), **out)
+
+
+def make_config3b():
+    """One grid of each side length of the 64-grid batch (the first of each), every step."""
+    w = config3b()
+    sides = [m.nx for m in w.meshes]
+    grids = [sides.index(s) for s in sorted(set(sides))]
+    res = {}
+    nodes_all = []
+    for g in grids:
+        mesh = w.meshes[g]
+        far = sample_nodes(mesh, n_random=0)
+        nodes = sample_nodes(mesh, n_random=320 - far.size)
+        nodes_all.append(nodes)
+        o = trajectory(mesh, w.pulses[g][0], w.h, w.steps, nodes, log_every=100, tag=f"{w.name}[{g}]")
+        for key in ("drops", "max_drop", "argmax", "sum_drop"):
+            res.setdefault(key, []).append(o[key])
+    np.savez_compressed(os.path.join(HERE, "config3b_batch_64grids_samples.npz"), workload=np.array(w.name),
+                        grids=np.array(grids, np.int64), scenarios=np.zeros(len(grids), np.int64),
+                        nodes=np.array(nodes_all), h=np.float64(w.h), vdd=np.float64(w.meshes[0].vdd),
+                        steps=np.int64(w.steps), **{k: np.array(v) for k, v in res.items()})
+
+
+MAKERS = {"config0": make_config0, "config1": make_config1, "config2": make_config2, "config3a": make_config3a,
+          "config3b": make_config3b, "config4": make_config4}
 
 if __name__ == "__main__":
     names = sys.argv[1:] or list(MAKERS)
