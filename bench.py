@@ -218,6 +218,7 @@ def verify(ctx, w, name):
     worst = np.zeros(J)
     worst_max = np.zeros(J)
     il_ref = g["il_every10"] if "il_every10" in g.files else None   # branch currents at steps 10, 20, ..
+    il_br = g["il_branches"] if "il_branches" in g.files else None
     worst_il = 0.0
     ctx.reset()
     sweeps0 = ctx.stats()["sweeps"]
@@ -234,6 +235,7 @@ def verify(ctx, w, name):
             worst_max[j] = max(worst_max[j], abs(dmax - float(ref_max[j, k])))
         if il_ref is not None and (k + 1) % 10 == 0:
             il = ctx.read_inductor_currents(grids[0], scen[0])
+            il = il[il_br] if il_br is not None else il
             worst_il = max(worst_il, float(np.max(np.abs(il - il_ref[(k + 1) // 10 - 1]))))
     torch.cuda.synchronize()
     st = ctx.stats()

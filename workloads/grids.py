@@ -278,3 +278,31 @@ CONFIGS = {
     "config0": config0, "config1": config1, "config2": config2,
     "config3a": config3a, "config3b": config3b, "config4": config4,
 }
+
+
+def random_mesh(seed, nx, ny, nl, scenarios=1, inductive=False, h=10 * PS, steps=12) -> Workload:
+    """A random layered mesh for property tests: segments U[0.5,2] S, capacitance U[0.1,5] pF
+    on about 70% of the nodes, vias on about 30% of the lower nodes (U[1,6] S; with
+    ``inductive`` about half of them, and of the pads, in series with U[1,10] pH), pads
+    U[5,10] S on about 10% of the top layer plus node 0 of every layer, and per scenario
+    triangular loads on about half of the nodes (peak U[0,5] mA, start U[0,100] ps, width
+    U[20,100] ps)."""
+    r = np.random.default_rng(np.random.SeedSequence(seed))
+    P = nx * ny
+    gE = r.uniform(0.5, 2.0, (nl, ny, nx - 1))
+    gN = r.uniform(0.5, 2.0, (nl, ny - 1, nx))
+    C = r.uniform(0.1 * PF, 5.0 * PF, (nl, ny, nx)) * (r.random((nl, ny, nx)) < 0.7)
+    vias = np.flatnonzero(r.random(P * (nl - 1)) < 0.3).astype(np.int32)
+    via_g = r.uniform(1.0, 6.0, vias.size)
+    via_L = r.uniform(1 * PS, 10 * PS, vias.size) * (r.random(vias.size) < 0.5) if inductive else np.zeros(vias.size)
+    top = (nl - 1) * P + np.flatnonzero(r.random(P) < 0.1)
+    pads = np.unique(np.concatenate([top, np.arange(nl) * P])).astype(np.int32)
+    pad_g = r.uniform(5.0, 10.0, pads.size)
+    pad_L = r.uniform(1 * PS, 10 * PS, pads.size) * (r.random(pads.size) < 0.5) if inductive else np.zeros(pads.size)
+    mesh = Mesh(nx, ny, nl, gE, gN, C, vias, via_g, via_L, pads, pad_g, pad_L)
+    scen = []
+    for _ in range(scenarios):
+        nodes = np.flatnonzero(r.random(nl * P) < 0.5).astype(np.int32)
+        scen.append(Pulses(nodes, r.uniform(0.0, 5 * MA, nodes.size), r.uniform(0.0, 100 * PS, nodes.size),
+                           r.uniform(20 * PS, 100 * PS, nodes.size)))
+    return Workload(f"random_{nl}x{ny}x{nx}_s{seed}", [mesh], [scen], h, steps)
