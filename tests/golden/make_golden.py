@@ -1,7 +1,7 @@
 """Write the sampled oracle trajectories under ``tests/golden/`` (FP64 CPU oracle only).
 
 Usage:  python tests/golden/make_golden.py <name> [...]
-        names: config0, config1, config2, config3a, config3b, config4
+        names: config0, config1, config2, config3a, config3b, config4, config4_adjoint
 
 Each file holds, for every backward-Euler step k = 1..K of one seeded workload, the oracle's
 voltages at a fixed, seeded set of sampled nodes (stored as the drop below the supply,
@@ -28,7 +28,7 @@ if ROOT not in sys.path:
 from oracle import BEStepper, mesh_to_circuit  # noqa: E402
 from oracle.sources import currents_at  # noqa: E402
 from oracle.transient import initial_state  # noqa: E402
-from workloads import config0, config1, config2, config3a, config3b, config4  # noqa: E402
+from workloads import config0, config1, config2, config3a, config3b, config4, random_direction  # noqa: E402
 
 SAMPLE_SEED = 71660
 
@@ -155,7 +155,42 @@ def make_config3b():
                         steps=np.int64(w.steps), **{k: np.array(v) for k, v in res.items()})
 
 
-MAKERS = {"config0": make_config0, "config1": make_config1, "config2": make_config2, "config3a": make_config3a,
+def make_config4_adjoint(margin=0.05, rel_delta=1e-4, n_sample=4096):
+    """The adjoint workload over its 200 steps: J, the oracle adjoint's gradient at seeded sampled
+    entries of dJ/dC, dJ/dgE, dJ/dgN (and each gradient's largest magnitude), the directional
+    derivative along ``workloads.random_direction`` from the oracle adjoint, and the same
+    derivative by a central difference of the oracle's forward transient."""
+    from dataclasses import replace
+    from oracle import adjoint_gradients
+    from oracle.adjoint import forward_states, softplus_loss
+    w = config4()
+    mesh, p = w.meshes[0], w.pulses[0][0]
+    t0 = time.time()
+    J, gC, gE, gN = adjoint_gradients(mesh, p, w.h, w.steps, margin)
+    print(f"adjoint: J = {J:.12e} in {time.time() - t0:.1f} s", flush=True)
+    dC, dE, dN = random_direction(mesh)
+    dot = float(np.sum(gC * dC) + np.sum(gE * dE) + np.sum(gN * dN))
+
+    def J_at(s):
+        m = replace(mesh, C=mesh.C + s * dC, gE=mesh.gE + s * dE, gN=mesh.gN + s * dN)
+        _, V = forward_states(m, p, w.h, w.steps)
+        return softplus_loss(V[1:, : mesh.n], mesh.vdd, margin)
+
+    fd = (J_at(rel_delta) - J_at(-rel_delta)) / (2 * rel_delta)
+    print(f"directional: adjoint {dot:.12e}, central difference {fd:.12e} in {time.time() - t0:.1f} s", flush=True)
+    rng = np.random.default_rng(np.random.SeedSequence(SAMPLE_SEED + 4))
+    out = {}
+    for name, g in (("C", gC), ("gE", gE), ("gN", gN)):
+        idx = np.sort(rng.choice(g.size, size=n_sample, replace=False)).astype(np.int64)
+        out[f"idx_{name}"] = idx
+        out[f"grad_{name}"] = g.ravel()[idx]
+        out[f"maxabs_{name}"] = np.float64(np.max(np.abs(g)))
+    np.savez_compressed(os.path.join(HERE, "config4_adjoint_samples.npz"), workload=np.array(w.name),
+                        J=np.float64(J), margin=np.float64(margin), steps=np.int64(w.steps),
+                        dir_dot=np.float64(dot), dir_fd=np.float64(fd), rel_delta=np.float64(rel_delta), **out)
+
+
+MAKERS = {"config0": make_config0, "config4_adjoint": make_config4_adjoint, "config1": make_config1, "config2": make_config2, "config3a": make_config3a,
           "config3b": make_config3b, "config4": make_config4}
 
 if __name__ == "__main__":

@@ -8,6 +8,8 @@
 * The 256-scenario batch: every node of every scenario at every one of its 500 steps.
 * The 64 uneven grids: every node of every grid at every 5th of their 500 steps.
 * The RLC mesh: every node and every branch current at every 5th of its first 500 steps.
+* The adjoint workload over all 200 steps: the loss, sampled gradient entries against the oracle
+  adjoint and a directional derivative against a central difference of the oracle's transient.
 
 All runs use the launch configuration ``bench.py`` times (its tuned omega, sweeps per check, tile
 rows and scenario blocks) at the parity tolerance ``bench.PARITY_TOL``.  The bar is the 1e-6 V
@@ -189,3 +191,39 @@ def test_config2_rlc_every_5th_step_of_500():
     say(f"  max |i| {imax:.3e} A")
     assert worst_v <= PARITY_V
     assert worst_i <= 1e-6 * max(1.0, imax)
+
+
+@pytest.mark.timeout(600)
+def test_config4_adjoint_all_200_steps():
+    """The adjoint workload over its whole 200 steps with checkpoints every 20: the loss, seeded
+    sampled entries of every gradient against the oracle adjoint (per entry within 1e-4 of the
+    larger of the entry and 1e-3 of the gradient's largest magnitude), and the directional
+    derivative along a seeded direction against a central difference of the oracle's forward
+    transient on the full grid (within 1e-4 relative)."""
+    from workloads import config4, random_direction
+    path = os.path.join(os.path.dirname(GOLDEN["config1"]), "config4_adjoint_samples.npz")
+    if not os.path.exists(path):
+        pytest.skip("stored oracle adjoint values are missing (tests/golden/make_golden.py config4_adjoint)")
+    g = np.load(path)
+    w = config4()
+    mesh = w.meshes[0]
+    steps, margin = int(g["steps"]), float(g["margin"])
+    say(f"[gpu] adjoint 1024x1024, {steps} steps, checkpoints every 20")
+    with gpu_context(w, precision=pg.PG_PREC_FP32_REFINE, tol=1e-11, omega=1.5, max_sweeps=100000) as ctx:
+        J = ctx.loss_forward(0, 0, steps, 20, margin)
+        dC, dE, dN = ctx.loss_backward(1e-10)
+    worst = 0.0
+    for name, grad in (("C", dC), ("gE", dE), ("gN", dN)):
+        ref = g[f"grad_{name}"]
+        got = grad.ravel()[g[f"idx_{name}"]]
+        floor = 1e-3 * float(g[f"maxabs_{name}"])
+        err = np.abs(got - ref) / np.maximum(np.abs(ref), floor)
+        worst = max(worst, float(err.max()))
+    d = random_direction(mesh)
+    dot = float(np.sum(dC * d[0]) + np.sum(dE * d[1]) + np.sum(dN * d[2]))
+    fd, dot_ref = float(g["dir_fd"]), float(g["dir_dot"])
+    say(f"  J={J:.10e} (oracle {float(g['J']):.10e}); worst sampled gradient error {worst:.2e}; "
+        f"directional {dot:.8e}, oracle adjoint {dot_ref:.8e}, oracle central difference {fd:.8e}")
+    assert abs(J - float(g["J"])) <= 1e-9 * abs(float(g["J"]))
+    assert worst <= 1e-4
+    assert abs(dot - fd) <= 1e-4 * abs(fd)

@@ -306,3 +306,10 @@ def random_mesh(seed, nx, ny, nl, scenarios=1, inductive=False, h=10 * PS, steps
         scen.append(Pulses(nodes, r.uniform(0.0, 5 * MA, nodes.size), r.uniform(0.0, 100 * PS, nodes.size),
                            r.uniform(20 * PS, 100 * PS, nodes.size)))
     return Workload(f"random_{nl}x{ny}x{nx}_s{seed}", [mesh], [scen], h, steps)
+
+
+def random_direction(mesh, seed=2024):
+    """A seeded direction in the (C, gE, gN) parameter space: each entry is its parameter's value
+    with a random sign (for directional finite differences)."""
+    r = np.random.default_rng(np.random.SeedSequence(seed))
+    return tuple(r.choice([-1.0, 1.0], size=a.shape) * a for a in (mesh.C, mesh.gE, mesh.gN))
