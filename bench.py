@@ -13,10 +13,12 @@ Prints one JSON line: the metric (node-updates/s) of that headline run, the roof
 kernel (algorithmic bytes over the HIP-event-timed duration) and the FP64 CPU oracle timed on a
 bounded sample of the same workload; then, under "legs", the same measurement for plain FP64 and
 FP32 + FP64 refinement on the 3-layer mesh and for the 256-scenario batch, each at the 1e-6 V
-stopping tolerance and at a parity tolerance, and a 3-layer 2048 x 2048 mesh whose sweep working
-set exceeds the 256 MB Infinity Cache.  Each run also carries its error against the FP64 oracle:
-after the timed region the whole transient is run again (untimed) and the voltages of a seeded
-sample of nodes are compared at every step with the oracle's values stored under tests/golden/.
+stopping tolerance and at a parity tolerance, a 3-layer 2048 x 2048 mesh whose sweep working
+set exceeds the 256 MB Infinity Cache, and ("adjoint") the forward transient and reverse-time
+adjoint of the voltage-drop loss on the 1024 x 1024 adjoint workload.  Each run also carries
+its error against the FP64 oracle: after the timed region the whole transient is run again
+(untimed) and the voltages of a seeded sample of nodes are compared at every step with the
+oracle's values stored under tests/golden/.
 """
 import argparse
 import json
@@ -214,7 +216,7 @@ def verify(ctx, w, name):
     nodes = g["nodes"].astype(np.int64)
     nodes = np.broadcast_to(nodes, (J, nodes.shape[-1])) if nodes.ndim == 1 else nodes
     bufs = {gi: torch.empty(w.meshes[gi].n, dtype=torch.float64, device="cuda:0") for gi in set(grids)}
-    idx = [torch.from_numpy(np.ascontiguousarray(nodes[j])).to("cuda:0") for j in range(J)]
+    idx = [torch.from_numpy(np.array(nodes[j])).to("cuda:0") for j in range(J)]
     worst = np.zeros(J)
     worst_max = np.zeros(J)
     il_ref = g["il_every10"] if "il_every10" in g.files else None   # branch currents at steps 10, 20, ..
@@ -466,6 +468,65 @@ def measure(name, prec, tol, steps, args, do_verify=True):
     return out
 
 
+def measure_adjoint(args, steps=200, ckpt=20, margin=0.05, tol=1e-10, tol_adj=1e-10):
+    """The adjoint workload (1024x1024 RC mesh): one forward transient of `steps` steps keeping
+    checkpoints every `ckpt` steps and the loss, then the reverse-time adjoint with the gradients
+    with respect to every C_i, gE and gN (3,143,680 entries), written to device memory.  Timed from
+    t = 0 (inputs resident) to the gradients in memory, after one untimed pass; checked against
+    the stored oracle adjoint (sampled entries, and a directional derivative against the oracle's
+    central difference on the full grid)."""
+    import numpy as np
+    import torch
+    import paper_1409_7166_amd as pg
+    import workloads
+
+    w = workloads.config4(steps=steps)
+    mesh = w.meshes[0]
+    t = settings("config4", tol)
+    torch.cuda.set_device(0)
+    ctx = pg.Context(0, torch.cuda.current_stream().cuda_stream)
+    ctx.set_options(h=w.h, tol=tol, omega=t["omega"], check_every=t["check_every"], max_sweeps=100000,
+                    precision=pg.PG_PREC_FP64)
+    ctx.upload_mesh(mesh, 1)
+    ctx.set_pulses(0, 0, w.pulses[0][0])
+    grads = [torch.empty(a.shape, dtype=torch.float64, device="cuda:0") for a in (mesh.C, mesh.gE, mesh.gN)]
+
+    def once():
+        ctx.reset()
+        J = ctx.loss_forward(0, 0, steps, ckpt, margin)
+        ctx.loss_backward_dev(tol_adj, *grads)
+        torch.cuda.synchronize()
+        return J
+
+    once()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    J = once()
+    elapsed = time.perf_counter() - t0
+    err = None
+    path = os.path.join(ROOT, "tests", "golden", "config4_adjoint_samples.npz")
+    if os.path.exists(path) and steps == 200:
+        g = np.load(path)
+        worst = 0.0
+        for name, grad in zip(("C", "gE", "gN"), grads):
+            ref = g[f"grad_{name}"]
+            got = grad.reshape(-1)[torch.from_numpy(g[f"idx_{name}"]).to("cuda:0")].cpu().numpy()
+            worst = max(worst, float(np.max(np.abs(got - ref) / np.maximum(np.abs(ref), 1e-3 * float(g[f"maxabs_{name}"])))))
+        d = workloads.random_direction(mesh)
+        dot = float(sum(np.sum(gr.cpu().numpy() * di) for gr, di in zip(grads, d)))
+        err = {"loss_rel_error": abs(J - float(g["J"])) / abs(float(g["J"])), "worst_sampled_gradient_rel_error": worst,
+               "directional_derivative": dot, "oracle_central_difference": float(g["dir_fd"]),
+               "directional_rel_error": abs(dot - float(g["dir_fd"])) / abs(float(g["dir_fd"])),
+               "against": os.path.relpath(path, ROOT)}
+    ctx.close()
+    n_grad = mesh.C.size + mesh.gE.size + mesh.gN.size
+    return {"workload": "adjoint_rc_1024x1024", "steps": steps, "checkpoint_every": ckpt, "tol_V": tol,
+            "tol_adjoint": tol_adj, "ms_forward_and_adjoint": elapsed * 1e3, "gradients": n_grad,
+            "node_steps_per_s": 2 * mesh.n * steps / elapsed, "error_vs_oracle": err,
+            "what": "forward transient with checkpoints and loss, then the adjoint (each segment recomputed from "
+                    "its checkpoint) with every gradient accumulated in FP64 on the device"}
+
+
 def leg_summary(rec):
     """The fields of one side leg."""
     roof = rec["roofline"] or {}
@@ -490,6 +551,7 @@ def main():
     if args.side_by_side:
         for name, prec, tol, steps in SIDE_BY_SIDE:
             print(json.dumps(measure(name, prec, tol, steps, args)), flush=True)
+        print(json.dumps(measure_adjoint(args)), flush=True)
         return
     out = measure(args.workload, args.precision, args.tol, args.steps, args)
     print(f"# headline {args.workload}: {out['value']:.3e} node-updates/s, {out['ms_per_step']:.3f} ms/step",
@@ -503,6 +565,10 @@ def main():
                   f"{rec['ms_per_step']:.3f} ms/step, error {json.dumps(rec['error_vs_oracle'])}",
                   file=sys.stderr, flush=True)
         out["legs"] = legs
+        adj = measure_adjoint(args)
+        print(f"# adjoint: {adj['ms_forward_and_adjoint']:.1f} ms, error {json.dumps(adj['error_vs_oracle'])}",
+              file=sys.stderr, flush=True)
+        out["adjoint"] = adj
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args.workload)
     print(json.dumps(out), flush=True)
