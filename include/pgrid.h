@@ -341,6 +341,20 @@ pg_status pg_error_bound_factor_noalloc(pg_ctx* ctx, int32_t grid, double rel_to
  * warm start from the previous step, sweep until the scaled residual is <= tol). */
 pg_status pg_step(pg_ctx* ctx, int32_t nsteps);
 
+/* Queue nsteps backward-Euler steps of every grid and scenario on the context's stream and return
+ * at once (the resident path, pg_options.resident = 1): three kernel launches, no host wait, no
+ * allocation and no host-visible memory, so a caller can capture the call in a HIP graph (stream
+ * capture on the context's stream, e.g. torch.cuda.graph) and replay it.  Each launch starts
+ * from the step count on the device and advances it, so every replay continues the transient
+ * (the sources are evaluated at the device's time).  The host's step count is refreshed from
+ * the device, after waiting for the context's stream, by the next pg_step, pg_run_transient,
+ * pg_get_time, pg_get_stats, pg_loss_forward or pg_dc_operating_point (replays on another stream
+ * must be synchronised by the caller first); a step of an enqueued launch that reached
+ * max_sweeps is reported by the next pg_step or pg_run_transient as PG_ERR_NO_CONVERGENCE.
+ * PG_ERR_UNSUPPORTED unless resident = 1; PG_ERR_STATE while the coefficients still have to be
+ * built (after upload or a change of options: one pg_step builds them). */
+pg_status pg_step_enqueue(pg_ctx* ctx, int32_t nsteps);
+
 /* pg_step(nsteps) that also copies the voltages of (grid, scen) to out after every
  * record_every-th step: out holds floor(nsteps / record_every) * n doubles (may be NULL). */
 pg_status pg_run_transient(pg_ctx* ctx, int32_t nsteps, int32_t record_every, int32_t grid,

@@ -122,13 +122,16 @@ __global__ __launch_bounds__(T) void k_resident(ResidentArgs a) {
   };
   for (int k = threadIdx.x; k < n_ind; k += T) sil[k] = ld1((const double*)ilg, (int64_t)k);
   const int src0 = a.item_src_off[item], src1 = a.item_src_off[item + 1];
+  // steps completed before this launch: the device clock, which k_resident_clock advances once
+  // every workgroup of the launch has finished (so a replayed launch continues the transient)
+  const long long k0 = __hip_atomic_load(a.step, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   long long tot_sweeps = 0, tot_checks = 0;
   int max_sw = 0, last_sw = 0, failed = 0;
   double last_res = 0.0, max_res = 0.0;
   __syncthreads();
 
   for (int step = 0; step < a.nsteps; ++step) {
-    const double t = (double)(a.k0 + step + 1) * a.h;
+    const double t = (double)(k0 + step + 1) * a.h;
     // right-hand side: (C/h) v + G0 Vdd - the companion history of the series R-L branches
 #pragma unroll
     for (int j = 0; j < NPT; ++j) {
@@ -224,8 +227,8 @@ __global__ void k_resident_prep(int32_t* last_sweeps, double* last_res) {
   last_res[0] = 0.0;
 }
 
-// After a resident launch of nsteps: the device clock (steps completed).
-__global__ void k_resident_clock(long long* step, long long k1) { step[0] = k1; }
+// After a resident launch of nsteps: advance the device clock (steps completed).
+__global__ void k_resident_clock(long long* step, int nsteps) { step[0] += nsteps; }
 
 }  // namespace
 
@@ -248,7 +251,7 @@ hipError_t launch_resident(const ResidentArgs& a, int max_nodes, bool multi_laye
     launch_resident_nl<false>(a, max_nodes, s);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_resident_clock, dim3(1), dim3(1), 0, s, a.step, a.k0 + a.nsteps);
+  hipLaunchKernelGGL(k_resident_clock, dim3(1), dim3(1), 0, s, a.step, a.nsteps);
   return hipGetLastError();
 }
 

@@ -328,8 +328,9 @@ hipError_t launch_mesh_pads(int n, const int32_t* pad_slot, const double* pad_va
                             hipStream_t s);
 // Resident path (pg_options.resident): one workgroup per item advances every item of the
 // context (layered meshes of at most kResMaxNodes nodes and kResMaxInd series R-L branches)
-// through nsteps whole backward-Euler steps in one launch, then sets the device clock to
-// k0 + nsteps.  item_src_off / item_src: the source-table entries of each item (CSR).  The
+// through nsteps whole backward-Euler steps in one launch, from the device clock's step, then
+// advances the clock by nsteps (kernels only, no host interaction: the launch can be captured in
+// a HIP graph and replayed).  item_src_off / item_src: the source-table entries of each item (CSR).  The
 // statistics are folded into the control block (stat_last_* are reset first).
 constexpr int kResMaxNodes = 4096;
 constexpr int kResMaxInd = 2048;
@@ -351,8 +352,7 @@ struct ResidentArgs {
   int32_t* stat_failed;
   double* stat_last_res;
   double* stat_max_res;
-  long long* step;                 // the device clock
-  long long k0;
+  long long* step;                 // the device clock (steps completed; read at the start)
   int n_items, nsteps, check_every, max_sweeps;
   double h, tol, omega;
 };

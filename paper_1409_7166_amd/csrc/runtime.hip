@@ -124,6 +124,7 @@ struct pg_ctx {
   int64_t step = 0;
   double seconds = 0.0;
   double* scratch_dev = nullptr;                 // this device's copy of the allocation-free scratch
+  bool clock_on_device = false;                  // pg_step_enqueue has run: the device clock is authoritative
   // device tables
   DBuf grid_desc, tiles_all, tiles_sweep, src_grid, src_index, src_off, src_t, src_i, ind_grid, ind_local;
   // nodes: mesh nodes x scenarios of the group's grids; mesh_nodes: mesh nodes (coefficients
@@ -1088,6 +1089,19 @@ pg_status set_step(pg_ctx* c, int64_t k) {
   return PG_OK;
 }
 
+// Once pg_step_enqueue has run, a captured graph may replay it at any time without the host's
+// knowledge, so from then on the step count is taken from the device clock, once the context's
+// stream has drained.
+pg_status sync_clock(pg_ctx* c) {
+  if (!c->clock_on_device) return PG_OK;
+  HIP_TRY(c, hipSetDevice(c->device));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  long long k = 0;
+  HIP_TRY(c, hipMemcpy(&k, c->ctl.step, sizeof k, hipMemcpyDeviceToHost));
+  c->step = k;
+  return PG_OK;
+}
+
 // Whether any source can be non-zero at the time of step index `dev_step` (t = (dev_step + 1) h),
 // judged from the host copy of the window table with one step of slack on either side.
 bool sources_may_act(const pg_ctx* c, int64_t dev_step) {
@@ -1511,8 +1525,8 @@ pg_status queue_close(pg_ctx* c, bool open_next) {
 
 // One BE step of every item.  With `speculate`, the next step's opening is queued ahead (see
 // cycle_loop) and picked up by the next call.
-// nsteps whole steps of every item in one launch (the resident path).
-pg_status resident_steps(pg_ctx* c, int nsteps) {
+// The arguments of a resident launch of nsteps steps.
+ResidentArgs resident_args(pg_ctx* c, int nsteps) {
   ResidentArgs a{};
   const Ctl& k = c->ctl;
   a.grids = (const GridDesc*)c->grid_desc.p;
@@ -1528,7 +1542,6 @@ pg_status resident_steps(pg_ctx* c, int nsteps) {
   a.stat_max_sweeps = k.stat_max_sweeps; a.stat_last_sweeps = k.stat_last_sweeps; a.stat_failed = k.stat_failed;
   a.stat_last_res = k.stat_last_res; a.stat_max_res = k.stat_max_res;
   a.step = k.step;
-  a.k0 = c->step;
   a.n_items = n_items(c);
   a.nsteps = nsteps;
   a.check_every = c->opt.check_every;
@@ -1536,6 +1549,12 @@ pg_status resident_steps(pg_ctx* c, int nsteps) {
   a.h = c->opt.h;
   a.tol = c->opt.tol;
   a.omega = c->opt.omega;
+  return a;
+}
+
+// nsteps whole steps of every item in one launch (the resident path).
+pg_status resident_steps(pg_ctx* c, int nsteps) {
+  const ResidentArgs a = resident_args(c, nsteps);
   hipError_t e;
   {
     ProfScope ps(c, 3, 0);
@@ -2069,6 +2088,7 @@ pg_status pg_dc_operating_point(pg_ctx* c, int64_t k, double omega, double tol, 
   if (k < 0 || !(std::isfinite(tol) && tol > 0) || max_sweeps < 1 || !(omega >= 0 && omega < 2))
     return set_err(c, PG_ERR_INVALID_ARG, "need k >= 0, tol > 0, max_sweeps >= 1 and 0 <= omega < 2");
   HIP_TRY(c, hipSetDevice(c->device));
+  PG_TRY(sync_clock(c));
   PG_TRY(prepare(c));
   for (int g = 0; g < (int)c->grids.size(); ++g) {
     PG_TRY(ensure_host_values(c, c->grids[g]));
@@ -2265,6 +2285,7 @@ pg_status pg_run_transient(pg_ctx* c, int32_t nsteps, int32_t record_every, int3
   if (!c) return PG_ERR_INVALID_ARG;
   if (nsteps < 0 || record_every < 1) return set_err(c, PG_ERR_INVALID_ARG, "nsteps >= 0 and record_every >= 1 required");
   HIP_TRY(c, hipSetDevice(c->device));
+  PG_TRY(sync_clock(c));
   PG_TRY(prepare(c));
   if (out) PG_TRY(check_gs(c, grid, scen));
   const auto t0 = std::chrono::steady_clock::now();
@@ -2301,9 +2322,26 @@ pg_status pg_run_transient(pg_ctx* c, int32_t nsteps, int32_t record_every, int3
   return PG_OK;
 }
 
-pg_status pg_get_time(const pg_ctx* c, int64_t* step) {
-  if (!c || !step) return PG_ERR_INVALID_ARG;
+pg_status pg_get_time(const pg_ctx* cc, int64_t* step) {
+  if (!cc || !step) return PG_ERR_INVALID_ARG;
+  pg_ctx* c = const_cast<pg_ctx*>(cc);
+  PG_TRY(sync_clock(c));
   *step = c->step;
+  return PG_OK;
+}
+
+pg_status pg_step_enqueue(pg_ctx* c, int32_t nsteps) {
+  if (!c) return PG_ERR_INVALID_ARG;
+  if (nsteps < 0) return set_err(c, PG_ERR_INVALID_ARG, "nsteps >= 0 required");
+  if (!c->opt.resident)
+    return set_err(c, PG_ERR_UNSUPPORTED, "pg_step_enqueue runs the resident path (pg_options.resident = 1)");
+  if (c->dirty || c->grids.empty())
+    return set_err(c, PG_ERR_STATE, "the coefficients are not built: one pg_step (or pg_run_transient) first");
+  if (nsteps == 0) return PG_OK;
+  ResidentArgs a = resident_args(c, nsteps);
+  const hipError_t e = launch_resident(a, c->res_max_nodes, c->res_multi_layer, c->stream);
+  if (e != hipSuccess) return set_err(c, PG_ERR_DEVICE, "resident launch: %s", hipGetErrorString(e));
+  c->clock_on_device = true;
   return PG_OK;
 }
 
@@ -2390,6 +2428,7 @@ pg_status pg_get_stats(const pg_ctx* cc, pg_stats* out) {
   if (!cc || !out) return PG_ERR_INVALID_ARG;
   pg_ctx* c = const_cast<pg_ctx*>(cc);
   HIP_TRY(c, hipSetDevice(c->device));
+  PG_TRY(sync_clock(c));
   HIP_TRY(c, hipStreamSynchronize(c->stream));
   long long s64[3];
   int32_t s32[4];
@@ -2441,6 +2480,7 @@ pg_status pg_loss_forward(pg_ctx* c, int32_t grid, int32_t scen, int32_t nsteps,
   if (nsteps < 1 || ckpt_every < 1 || !std::isfinite(margin))
     return set_err(c, PG_ERR_INVALID_ARG, "need nsteps >= 1, ckpt_every >= 1 and a finite margin");
   HIP_TRY(c, hipSetDevice(c->device));
+  PG_TRY(sync_clock(c));
   PG_TRY(prepare(c));
   GridHost& H = c->grids[grid];
   auto& A = c->adj;

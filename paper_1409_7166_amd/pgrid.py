@@ -122,6 +122,7 @@ EXPORTS = {
     "pg_error_bound_factor": (C.c_int, [C.c_void_p, C.c_int32, C.c_double, C.POINTER(C.c_double)]),
     "pg_error_bound_factor_noalloc": (C.c_int, [C.c_void_p, C.c_int32, C.c_double, C.POINTER(C.c_double)]),
     "pg_step": (C.c_int, [C.c_void_p, C.c_int32]),
+    "pg_step_enqueue": (C.c_int, [C.c_void_p, C.c_int32]),
     "pg_run_transient": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.c_int32,
                                    C.POINTER(C.c_double)]),
     "pg_get_time": (C.c_int, [C.c_void_p, C.POINTER(C.c_int64)]),
@@ -465,6 +466,10 @@ class Context:
     # -- stepping --------------------------------------------------------------------------
     def step(self, nsteps: int = 1):
         self._check(lib().pg_step(self._h, int(nsteps)))
+
+    def step_enqueue(self, nsteps: int = 1):
+        """Queue nsteps steps on the context's stream without waiting (resident path; capturable)."""
+        self._check(lib().pg_step_enqueue(self._h, int(nsteps)))
 
     def run_transient(self, nsteps: int, record_every: int = 1, grid: int = 0, scen: int = 0):
         n = self._n_nodes(grid)

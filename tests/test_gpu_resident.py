@@ -125,3 +125,52 @@ def test_ineligible_grids_are_refused():
         with pytest.raises(pg.PgError) as ei:
             ctx.step(1)
         assert ei.value.name == "PG_ERR_UNSUPPORTED"
+
+
+def test_enqueued_steps_captured_in_a_hip_graph_and_replayed():
+    """pg_step_enqueue captured once on the context's stream and replayed four times, with eager
+    work and synchronisations between the replays: after each replay the state equals, bit for
+    bit, that of a context stepped eagerly to the same step; the clock and statistics follow."""
+    import torch
+    a = small_rc(40, 33, seed=58, scenarios=3, steps=60)
+    b = small_rc(24, 20, seed=59, steps=60)
+    w = Workload("graph_small", a.meshes + b.meshes, a.pulses + b.pulses, a.h, 60)
+    items = [(0, 0), (0, 1), (0, 2), (1, 0)]
+    torch.cuda.set_device(0)
+    side = torch.cuda.Stream()
+    ctx = pg.Context(0, side.cuda_stream)
+    ctx.set_options(h=w.h, tol=1e-11, omega=1.6, check_every=8, precision=pg.PG_PREC_FP64, resident=1,
+                    max_sweeps=100000)
+    for g, (mesh, scen) in enumerate(zip(w.meshes, w.pulses)):
+        ctx.upload_mesh(mesh, len(scen))
+        for s, p in enumerate(scen):
+            ctx.set_pulses(g, s, p)
+    with gpu_context(w, **_opts()) as ref:
+        with ctx:
+            ctx.step(2)          # builds the coefficients (allocates) outside the capture
+            ref.step(2)
+            graph = torch.cuda.CUDAGraph()
+            with torch.cuda.graph(graph, stream=side):
+                ctx.step_enqueue(5)
+            torch.cuda.synchronize()
+            done = 2             # capture queues nothing
+            for r in range(4):
+                graph.replay()
+                x = torch.ones(1 << 20, device="cuda:0").sum()   # eager work between the replays
+                torch.cuda.synchronize()
+                done += 5
+                ref.step(5)
+                assert ctx.time_index() == done == ref.time_index()
+                for it in items:
+                    assert np.array_equal(ctx.read_voltages(*it), ref.read_voltages(*it)), (r, it)
+                assert float(x) == float(1 << 20)
+            st, sr = ctx.stats(), ref.stats()
+            say(f"[gpu] graph replay of enqueued resident steps: {done} steps, sweeps {st['sweeps']} vs {sr['sweeps']}")
+            assert st["sweeps"] == sr["sweeps"] and st["node_updates"] == sr["node_updates"]
+            ctx.step(3)          # eager steps continue from the replayed state
+            ref.step(3)
+            for it in items:
+                assert np.array_equal(ctx.read_voltages(*it), ref.read_voltages(*it))
+            with pytest.raises(pg.PgError):
+                ctx.set_options(resident=0)
+                ctx.step_enqueue(1)
