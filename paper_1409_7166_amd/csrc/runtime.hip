@@ -2338,6 +2338,9 @@ pg_status pg_step_enqueue(pg_ctx* c, int32_t nsteps) {
   if (c->dirty || c->grids.empty())
     return set_err(c, PG_ERR_STATE, "the coefficients are not built: one pg_step (or pg_run_transient) first");
   if (nsteps == 0) return PG_OK;
+  int cur = -1;  // launches go to the context's device (setting the device is no stream operation)
+  HIP_TRY(c, hipGetDevice(&cur));
+  if (cur != c->device) HIP_TRY(c, hipSetDevice(c->device));
   ResidentArgs a = resident_args(c, nsteps);
   const hipError_t e = launch_resident(a, c->res_max_nodes, c->res_multi_layer, c->stream);
   if (e != hipSuccess) return set_err(c, PG_ERR_DEVICE, "resident launch: %s", hipGetErrorString(e));
