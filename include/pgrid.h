@@ -157,8 +157,8 @@ typedef struct pg_stats {
  * scenario (coefficients are shared by the scenarios of a grid): sweep e * (gE + gN + invD)
  * + e * (nl-1)/nl (vias exist below the top layer only), residual 8 * (D + gE + gN)
  * + 8 * (nl-1)/nl; per storage slot of a general netlist with an active scenario, sweep e * invD
- * and residual 8 * D, and per off-diagonal entry of M (no padding), sweep e * w + 4 (its column
- * index) and residual 8 * w + 4. */
+ * + 2 (its row length) and residual 8 * D + 2, and per off-diagonal entry of M (the table stores
+ * no padding), sweep e * w + 4 (its column index) and residual 8 * w + 4. */
 typedef struct pg_kernel_times {
   int64_t sweep_launches;  double sweep_ms;      int64_t sweep_node_updates;  double sweep_bytes;
   int64_t resid_launches;  double resid_ms;      int64_t resid_nodes;         double resid_bytes;
@@ -224,9 +224,12 @@ pg_status pg_netlist_to_mesh(int32_t n, int32_t p, const double* source_v, int32
 
 /* The colouring used for a general netlist (host only, no device): color[i] in 0..n_colors-1
  * for trivial node i, with no R, L or C branch joining two nodes of one colour (two colours when
- * the node graph is bipartite, else the greedy colouring in node order), and the storage slot of
- * each node: colours in order, node order inside a colour, each colour padded to a multiple of
- * 64 slots (n_slots in all).  color and slot are caller arrays of n entries or NULL. */
+ * the node graph is bipartite, else DSATUR refined by iterated greedy passes; should DSATUR need
+ * more than 64 colours, the greedy colouring in node order), and the storage slot of
+ * each node: colours in order, inside a colour the Cuthill-McKee order of the node graph
+ * (breadth first from a pseudo-peripheral node of each connected part, the parts in the order
+ * of their smallest node, a node's unvisited neighbours by increasing degree, ties by node),
+ * each colour padded to a multiple of 64 slots (n_slots in all).  color and slot are caller arrays of n entries or NULL. */
 pg_status pg_netlist_coloring(int32_t n, int32_t p, const double* source_v, int32_t m, const int32_t* from,
                               const int32_t* to, const uint8_t* kind, const double* value, int32_t* color,
                               int32_t* slot, int32_t* n_colors, int64_t* n_slots, char* msg, size_t msg_len);

@@ -141,6 +141,63 @@ int colour_nodes(int32_t n, const std::vector<int64_t>& off, const std::vector<i
   return nc;
 }
 
+// Cuthill-McKee order: breadth first from a pseudo-peripheral node of each connected part (the
+// parts in the order of their smallest node), the unvisited neighbours of a node taken by
+// increasing degree (ties: node id).  A node's neighbours then lie in the breadth-first levels
+// next to its own, so on mesh-like graphs they sit about one level width apart in this order
+// whatever the numbering (the layers of a layered grid interleave, vias joining nearby slots).
+std::vector<int32_t> cm_order(int32_t n, const std::vector<int64_t>& off, const std::vector<int32_t>& adj) {
+  std::vector<int32_t> order, q, level(n, 0), stamp(n, -1), nb;
+  std::vector<char> placed(n, 0);
+  order.reserve(n);
+  auto deg = [&](int32_t u) { return off[u + 1] - off[u]; };
+  auto before = [&](int32_t a, int32_t b) { return deg(a) != deg(b) ? deg(a) < deg(b) : a < b; };
+  int32_t pass = 0;
+  for (int32_t s0 = 0; s0 < n; ++s0) {
+    if (placed[s0]) continue;
+    // pseudo-peripheral root: from s0, move to a least-degree node of the deepest level while
+    // the depth grows
+    int32_t root = s0, depth = -1;
+    for (int it = 0; it < 8; ++it) {
+      ++pass;
+      q.assign(1, root);
+      stamp[root] = pass;
+      level[root] = 0;
+      for (size_t h = 0; h < q.size(); ++h) {
+        const int32_t u = q[h];
+        for (int64_t k = off[u]; k < off[u + 1]; ++k)
+          if (stamp[adj[k]] != pass) {
+            stamp[adj[k]] = pass;
+            level[adj[k]] = level[u] + 1;
+            q.push_back(adj[k]);
+          }
+      }
+      const int32_t d = level[q.back()];
+      if (d <= depth) break;
+      depth = d;
+      int32_t best = q.back();
+      for (size_t t = q.size(); t-- > 0 && level[q[t]] == d;)
+        if (before(q[t], best)) best = q[t];
+      root = best;
+    }
+    q.assign(1, root);
+    placed[root] = 1;
+    for (size_t h = 0; h < q.size(); ++h) {
+      const int32_t u = q[h];
+      order.push_back(u);
+      nb.clear();
+      for (int64_t k = off[u]; k < off[u + 1]; ++k)
+        if (!placed[adj[k]]) {
+          placed[adj[k]] = 1;
+          nb.push_back(adj[k]);
+        }
+      std::sort(nb.begin(), nb.end(), before);
+      q.insert(q.end(), nb.begin(), nb.end());
+    }
+  }
+  return order;
+}
+
 }  // namespace
 
 pg_status build_graph_form(int32_t n, int32_t p, const double* source_v, int32_t m, const int32_t* from,
@@ -237,7 +294,9 @@ pg_status build_graph_form(int32_t n, int32_t p, const double* source_v, int32_t
   f.ncolors = colour_nodes(n, off, adj, f.color);
   if (f.ncolors > 255)
     return gfail(PG_ERR_UNSUPPORTED, msg, len, "the node graph needs %d colours (at most 255)", f.ncolors);
-  // slots: colour by colour, node order inside a colour, each colour padded to whole slices
+  // slots: colour by colour, Cuthill-McKee order inside a colour (so the neighbours a wavefront
+  // gathers lie close together in each colour, at about the same relative position as the
+  // wavefront's own slots in theirs), each colour padded to whole slices
   std::vector<int64_t> count(f.ncolors, 0);
   for (int32_t i = 0; i < n; ++i) count[f.color[i]]++;
   f.cstart.assign(f.ncolors + 1, 0);
@@ -249,56 +308,61 @@ pg_status build_graph_form(int32_t n, int32_t p, const double* source_v, int32_t
   std::vector<int32_t> node_at(f.nslots, -1);
   {
     std::vector<int64_t> next(f.cstart.begin(), f.cstart.end() - 1);
-    for (int32_t i = 0; i < n; ++i) {
+    for (const int32_t i : cm_order(n, off, adj)) {
       const int64_t s = next[f.color[i]]++;
       f.slot[i] = (int32_t)s;
       node_at[s] = i;
     }
   }
-  // sliced ELL
+  // compact sliced ELL (see GraphForm): row lengths, slice extents, then entry k of each row
+  // that has one, k = 0, 1, ...
   const int64_t nsl = f.nslots / kSlice;
+  f.rlen.assign(f.nslots, 0);
+  for (int64_t s = 0; s < f.nslots; ++s) {
+    const int32_t i = node_at[s];
+    if (i < 0) continue;
+    const int64_t deg = off[i + 1] - off[i];
+    if (deg > kMaxRowLen)
+      return gfail(PG_ERR_UNSUPPORTED, msg, len, "node %d has %lld neighbours (at most %d)", i, (long long)deg,
+                   kMaxRowLen);
+    f.rlen[s] = (uint16_t)deg;
+  }
   f.soff.assign(nsl + 1, 0);
   int64_t total = 0;
   for (int64_t s = 0; s < nsl; ++s) {
-    int64_t w = 0;
-    for (int j = 0; j < kSlice; ++j) {
-      const int32_t i = node_at[s * kSlice + j];
-      if (i >= 0) w = std::max(w, off[i + 1] - off[i]);
-    }
-    total += w * kSlice;
+    for (int j = 0; j < kSlice; ++j) total += f.rlen[s * kSlice + j];
     if (total > (int64_t)INT32_MAX)
-      return gfail(PG_ERR_UNSUPPORTED, msg, len, "the padded neighbour table exceeds 2^31 entries");
+      return gfail(PG_ERR_UNSUPPORTED, msg, len, "the neighbour table exceeds 2^31 entries");
     f.soff[s + 1] = (int32_t)total;
   }
   f.col.assign(total, 0);
   f.g.assign(total, 0.0);
   f.inv_l.assign(total, 0.0);
   f.cc.assign(total, 0.0);
-  std::vector<std::pair<int32_t, int32_t>> row;  // (neighbour slot, pair)
+  std::vector<std::vector<std::pair<int32_t, int32_t>>> rows(kSlice);  // (neighbour slot, pair)
   for (int64_t s = 0; s < nsl; ++s) {
-    const int64_t base = f.soff[s], w = (f.soff[s + 1] - base) / kSlice;
+    size_t w = 0;
     for (int j = 0; j < kSlice; ++j) {
-      const int64_t own = s * kSlice + j;
-      const int32_t i = node_at[own];
-      row.clear();
+      const int32_t i = node_at[s * kSlice + j];
+      rows[j].clear();
       if (i >= 0)
-        for (int64_t k = off[i]; k < off[i + 1]; ++k) row.emplace_back(f.slot[adj[k]], pid[k]);
-      std::sort(row.begin(), row.end());
-      for (int64_t k = 0; k < w; ++k) {
-        const int64_t e = base + k * kSlice + j;
-        if (k < (int64_t)row.size()) {
-          const PairVal& q = pairs[row[k].second];
-          f.col[e] = row[k].first;
-          f.g[e] = q.g;
-          f.inv_l[e] = q.il;
-          f.cc[e] = q.c;
-        } else {
-          f.col[e] = (int32_t)own;
-        }
-      }
+        for (int64_t k = off[i]; k < off[i + 1]; ++k) rows[j].emplace_back(f.slot[adj[k]], pid[k]);
+      std::sort(rows[j].begin(), rows[j].end());
+      w = std::max(w, rows[j].size());
     }
+    int64_t e = f.soff[s];
+    for (size_t k = 0; k < w; ++k)
+      for (int j = 0; j < kSlice; ++j) {
+        if (k >= rows[j].size()) continue;
+        const PairVal& q = pairs[rows[j][k].second];
+        f.col[e] = rows[j][k].first;
+        f.g[e] = q.g;
+        f.inv_l[e] = q.il;
+        f.cc[e] = q.c;
+        ++e;
+      }
   }
-  // coupling-capacitor table
+  // coupling-capacitor table (padded sliced ELL)
   f.csoff.assign(nsl + 1, 0);
   int64_t ctotal = 0;
   std::vector<std::vector<std::pair<int32_t, double>>> crow(kSlice);

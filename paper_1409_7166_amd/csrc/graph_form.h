@@ -19,19 +19,26 @@ struct GraphForm {
   int32_t ncolors = 0;
   std::vector<int32_t> color;        // [n] colour of each trivial node
   std::vector<int64_t> cstart;       // [ncolors + 1] first slot of each colour (multiples of kSlice)
-  std::vector<int32_t> slot;         // [n] node -> slot; slots inside a colour follow node order
+  std::vector<int32_t> slot;         // [n] node -> slot; slots inside a colour follow the
+                                     // Cuthill-McKee order of the node graph
   int64_t nslots = 0;                // cstart[ncolors]
-  // sliced ELL over slots: the entries of slice s are [soff[s], soff[s+1]), column-major in the
-  // slice (entry k of the slice's row j at soff[s] + k * kSlice + j); rows shorter than the
-  // slice's widest row are padded with col = own slot and zero values
+  // compact sliced ELL over slots: the entries of slice s are [soff[s], soff[s+1]), stored
+  // entry by entry: first entry 0 of every row of the slice that has one, in slot order, then
+  // entry 1 of every row that has more than one, and so on (a row's entries follow its
+  // neighbour slots in increasing order).  No padding is stored: entry k of a row sits at
+  // soff[s] + (the slice's entries before k) + (the number of rows before it in the slice with
+  // more than k entries); rlen holds each slot's row length (0 for padding slots)
   std::vector<int32_t> soff;         // [nslots / kSlice + 1]
+  std::vector<uint16_t> rlen;        // [nslots]
   std::vector<int32_t> col;          // neighbour slot
   std::vector<double> g;             // sum of the resistor conductances joining the pair, S
   std::vector<double> inv_l;         // sum of 1 / L over the inductors joining the pair, 1/H
   std::vector<double> cc;            // sum of the capacitors joining the pair, F
   int64_t nnz = 0;                   // off-diagonal pattern entries (both directions, no padding)
-  // the pairs joined by a capacitor alone, as a second sliced-ELL table of the same layout
-  // (most slices are empty), for the off-diagonal part of (C/h) v in the right-hand side
+  // the pairs joined by a capacitor, as a second sliced-ELL table (most slices are empty), for
+  // the off-diagonal part of (C/h) v in the right-hand side; this one is padded: entry k of the
+  // slice's row j at csoff[s] + k * kSlice + j, rows shorter than the slice's widest padded with
+  // col = own slot and zero values
   std::vector<int32_t> csoff, ccol;
   std::vector<double> cval;          // F
   // per trivial node (node order)
@@ -48,6 +55,20 @@ struct GraphForm {
   // through a resistor (else the DC matrix is singular)
   bool dc_anchored = false;
 };
+
+constexpr int kMaxRowLen = 65535;  // neighbours of one node (rlen is 16-bit)
+
+// Calls fn(entry, slot) for every entry of the compact neighbour table, in storage order.
+template <typename Fn>
+void for_each_entry(const GraphForm& f, Fn fn) {
+  const int64_t nsl = (int64_t)f.soff.size() - 1;
+  for (int64_t s = 0; s < nsl; ++s) {
+    int64_t e = f.soff[s];
+    for (int k = 0; e < f.soff[s + 1]; ++k)
+      for (int j = 0; j < kSlice; ++j)
+        if (k < f.rlen[s * kSlice + j]) fn(e++, s * kSlice + j);
+  }
+}
 
 // Validates (pg_validate_netlist) and builds the form; on failure writes a message.
 __attribute__((visibility("hidden"))) pg_status build_graph_form(int32_t n, int32_t p, const double* source_v, int32_t m, const int32_t* from,

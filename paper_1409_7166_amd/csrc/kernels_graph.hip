@@ -4,15 +4,40 @@
 // The nodes are stored colour by colour (no branch joins two nodes of one colour), so all
 // nodes of a colour update independently: one launch per colour, in colour order, is one
 // Gauss-Seidel/SOR sweep of eqs. 16-17 in that node order (Theorem 1), done in place.
-// Neighbours come from a sliced-ELL table with 64-slot slices: lane j of a wavefront owns
-// slot 64 s + j and reads entry k of its row at sl_off[s] + 64 k + j, so the table streams
-// with unit stride and only the neighbour values are gathered (from L2 for graphs whose node
-// numbering keeps neighbours close).
+// Neighbours come from a compact sliced-ELL table with 64-slot slices: lane j of a wavefront
+// owns slot 64 s + j, and the slice stores entry k of the rows that have one contiguously, so
+// the lanes of a wave read each entry level as one unit-stride run with no padding, and only
+// the neighbour values are gathered (from L2 for graphs whose node numbering keeps neighbours
+// close).
 #include "pgrid_internal.h"
 
 namespace pgrid {
 
 namespace {
+
+constexpr int kGraphGroup = 8;  // table entry levels whose loads a lane issues together
+
+// Walks the compact neighbour table (see GridDesc) for the slot of this lane; all 64 lanes of
+// the wave (one slice) take part.  For entry level k the ballot of the lanes whose rows have
+// more than k entries gives each of them its rank (the set bits below its own) and the count
+// that the next level starts after.
+struct RowWalk {
+  int P;    // first table entry of the current level (uniform over the wave)
+  int len;  // this lane's row length
+  __device__ __forceinline__ RowWalk(const GridDesc& G, int i) {
+    P = ld1(G.sl_off, __builtin_amdgcn_readfirstlane(i >> 6));
+    len = ld1(G.sl_len, i);
+  }
+  // some lane of the wave has entry k (uniform)
+  __device__ __forceinline__ bool any(int k) const { return __ballot(k < len) != 0; }
+  // table position of this lane's entry k (meaningful for k < len); moves past level k
+  __device__ __forceinline__ int next(int k) {
+    const unsigned long long m = __ballot(k < len);
+    const int e = P + (int)__builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));
+    P += __popcll(m);
+    return e;
+  }
+};
 
 // b = (C/h) v + G0 v_s + (h/L) v_s - inductor history, with C/h's off-diagonal coupling terms.
 __global__ __launch_bounds__(kChunk) void k_graph_rhs(const GraphChunk* __restrict__ chunks, int n,
@@ -64,8 +89,11 @@ __global__ __launch_bounds__(kChunk) void k_graph_rhs3(const GraphChunk* __restr
   const double vi = v[i];
   double bb = G.ch64[i] * (2.0 * vi - vp[i]) + G.g3diag[i] * vi + G.bl64[i];
   {
-    const int base = G.sl_off[i >> 6] + (i & 63), w = (G.sl_off[(i >> 6) + 1] - G.sl_off[i >> 6]) >> 6;
-    for (int k = 0; k < w; ++k) bb -= G.sl_g64[base + (k << 6)] * v[G.sl_col[base + (k << 6)]];
+    RowWalk t(G, i);
+    for (int k = 0; t.any(k); ++k) {
+      const int e = t.next(k);
+      if (k < t.len) bb -= G.sl_g64[e] * v[G.sl_col[e]];
+    }
   }
   if (G.cap_off) {
     const int base = G.cap_off[i >> 6] + (i & 63), w = (G.cap_off[(i >> 6) + 1] - G.cap_off[i >> 6]) >> 6;
@@ -94,8 +122,11 @@ __global__ __launch_bounds__(kChunk) void k_graph_kcl(const GraphChunk* __restri
   const double* __restrict__ vp = G.vprev[c.step[0] & 1] + off;
   double res = G.ch64[i] * (v[i] - vp[i]) + G.g3diag[i] * v[i] - G.bres64[i];
   {
-    const int base = G.sl_off[i >> 6] + (i & 63), w = (G.sl_off[(i >> 6) + 1] - G.sl_off[i >> 6]) >> 6;
-    for (int k = 0; k < w; ++k) res -= G.sl_g64[base + (k << 6)] * v[G.sl_col[base + (k << 6)]];
+    RowWalk t(G, i);
+    for (int k = 0; t.any(k); ++k) {
+      const int e = t.next(k);
+      if (k < t.len) res -= G.sl_g64[e] * v[G.sl_col[e]];
+    }
   }
   if (G.cap_off) {
     const int base = G.cap_off[i >> 6] + (i & 63), w = (G.cap_off[(i >> 6) + 1] - G.cap_off[i >> 6]) >> 6;
@@ -156,30 +187,29 @@ __global__ __launch_bounds__(kChunk) void k_graph_sweep(const GraphChunk* __rest
   T* __restrict__ d = static_cast<T*>(G.d[0]) + off;
   const T* __restrict__ r = static_cast<const T*>(G.r) + off;
   const T* __restrict__ wv = static_cast<const T*>(G.sl_ws);
-  // chunks start on 64-slot slices and cover whole ones, so the slice is uniform over the wave
-  const int sl = __builtin_amdgcn_readfirstlane(i >> 6);
-  const int o0 = ld1(G.sl_off, sl), o1 = ld1(G.sl_off, sl + 1);
-  const int base = o0 + (i & 63), w = (o1 - o0) >> 6;
+  // chunks start on 64-slot slices and cover whole ones, so a wave is one slice
+  RowWalk t(G, i);
   // zero_in: only neighbours already updated in this sweep (slot < lim) carry a value
   const int lim = zero_in ? ch.lim : 0x7fffffff;
   T acc = ld1(r, i);
   const T inv = ld1(static_cast<const T*>(G.invDs), i);
   const T old = zero_in ? T(0) : ld1(d, i);
-  // four table entries, then their four gathers, in flight together; a last group of fewer than
-  // four (w is uniform over the wave) loads only its entries and adds exact zeros for the rest
-  for (int k = 0; k < w; k += 4) {
-    const int nq = w - k;
-    int j[4];
-    T g[4], dj[4];
+  // kGraphGroup entry levels, then their gathers, in flight together
+  for (int k = 0; t.any(k); k += kGraphGroup) {
+    int j[kGraphGroup];
+    T g[kGraphGroup], dj[kGraphGroup];
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      j[q] = q < nq ? ld1(G.sl_col, base + ((k + q) << 6)) : lim;
-      g[q] = q < nq ? ld1(wv, base + ((k + q) << 6)) : T(0);
+    for (int q = 0; q < kGraphGroup; ++q) {
+      const int e = t.next(k + q);
+      const bool has = k + q < t.len;
+      j[q] = has ? ld1(G.sl_col, e) : lim;
+      g[q] = has ? ld1(wv, e) : T(0);
     }
 #pragma unroll
-    for (int q = 0; q < 4; ++q) dj[q] = j[q] < lim ? ld1(d, j[q]) : T(0);
+    for (int q = 0; q < kGraphGroup; ++q) dj[q] = j[q] < lim ? ld1(d, j[q]) : T(0);
 #pragma unroll
-    for (int q = 0; q < 4; ++q) acc += g[q] * dj[q];
+    for (int q = 0; q < kGraphGroup; ++q)
+      if (k + q < t.len) acc += g[q] * dj[q];
   }
   st1(d, i, old + omega * (inv * acc - old));
 }
@@ -207,26 +237,23 @@ __global__ __launch_bounds__(kChunk) void k_graph_resid(const GraphChunk* __rest
     const double D = ld1(G.D64, i);
     const double own = has_d ? ld1(v, i) + (double)ld1(d, i) : ld1(v, i);
     double acc = ld1(G.b, off + i) - D * own;
-    const int sl = __builtin_amdgcn_readfirstlane(i >> 6);  // uniform over the wave (see k_graph_sweep)
-    const int o0 = ld1(G.sl_off, sl), o1 = ld1(G.sl_off, sl + 1);
-    const int base = o0 + (i & 63), w = (o1 - o0) >> 6;
-    int k = 0;
-    for (; k + 4 <= w; k += 4) {  // four table entries, then their gathers, in flight together
-      int j[4];
-      double g[4], x[4];
+    RowWalk t(G, i);  // a wave is one slice (see k_graph_sweep)
+    for (int k = 0; t.any(k); k += kGraphGroup) {  // kGraphGroup levels, then their gathers, in flight
+      int j[kGraphGroup];
+      double g[kGraphGroup], x[kGraphGroup];
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        j[q] = ld1(G.sl_col, base + ((k + q) << 6));
-        g[q] = ld1(G.sl_w64, base + ((k + q) << 6));
+      for (int q = 0; q < kGraphGroup; ++q) {
+        const int e = t.next(k + q);
+        const bool has = k + q < t.len;
+        j[q] = has ? ld1(G.sl_col, e) : -1;
+        g[q] = has ? ld1(G.sl_w64, e) : 0.0;
       }
 #pragma unroll
-      for (int q = 0; q < 4; ++q) x[q] = has_d ? ld1(v, j[q]) + (double)ld1(d, j[q]) : ld1(v, j[q]);
+      for (int q = 0; q < kGraphGroup; ++q)
+        x[q] = j[q] < 0 ? 0.0 : has_d ? ld1(v, j[q]) + (double)ld1(d, j[q]) : ld1(v, j[q]);
 #pragma unroll
-      for (int q = 0; q < 4; ++q) acc += g[q] * x[q];
-    }
-    for (; k < w; ++k) {
-      const int j = ld1(G.sl_col, base + (k << 6));
-      acc += ld1(G.sl_w64, base + (k << 6)) * (has_d ? ld1(v, j) + (double)ld1(d, j) : ld1(v, j));
+      for (int q = 0; q < kGraphGroup; ++q)
+        if (k + q < t.len) acc += g[q] * x[q];
     }
     if (has_d) st1(G.v[vi ^ 1], off + i, own);
     st1(static_cast<T*>(G.r), off + i, (T)acc);
@@ -253,7 +280,7 @@ __global__ __launch_bounds__(kChunk) void k_graph_resid(const GraphChunk* __rest
 // v_j - v_i (formed in FP64, exact for voltages within a factor of two of each other, then
 // rounded); every rounding in them (of e_i, of the differences, of wG and gsup, of the products
 // and of the sum of k + 1 terms) is a relative error of at most u = 2^-24 on a term of
-// S_i = gsup_i |e_i| + sum_j wG_ij |v_j - v_i|, so (k + 8) 2^-23 S_i, k the row's table width,
+// S_i = gsup_i |e_i| + sum_j wG_ij |v_j - v_i|, so (k + 8) 2^-23 S_i, k the row's length,
 // bounds their total error; the scale 1/M_ii is widened by its rounding.  The result bounds the
 // FP64 norm from above.
 template <typename T>
@@ -278,33 +305,26 @@ __global__ __launch_bounds__(kChunk) void k_graph_probe(const GraphChunk* __rest
     const float gs = ld1(G.gsup32, i);
     const double vi = ld1(v, i);
     const float ei = (float)(vi - vref);
-    // chunks start on 64-slot slices and cover whole ones, so the slice is uniform over the wave
-    const int sl = __builtin_amdgcn_readfirstlane(i >> 6);
-    const int o0 = ld1(G.sl_off, sl), o1 = ld1(G.sl_off, sl + 1);
-    const int base = o0 + (i & 63), w = (o1 - o0) >> 6;
+    RowWalk t(G, i);  // a wave is one slice (see k_graph_sweep)
     float r = -gs * ei, s = gs * fabsf(ei);
-    int k = 0;
-    for (; k + 4 <= w; k += 4) {  // four table entries, then their gathers, in flight together
-      int j[4];
-      float g[4], dj[4];
+    for (int k = 0; t.any(k); k += kGraphGroup) {  // kGraphGroup levels, then their gathers, in flight
+      int j[kGraphGroup];
+      float g[kGraphGroup], dj[kGraphGroup];
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        j[q] = ld1(G.sl_col, base + ((k + q) << 6));
-        g[q] = ld1(G.gw32, base + ((k + q) << 6));
+      for (int q = 0; q < kGraphGroup; ++q) {
+        const int e = t.next(k + q);
+        const bool has = k + q < t.len;
+        j[q] = has ? ld1(G.sl_col, e) : -1;
+        g[q] = has ? ld1(G.gw32, e) : 0.0f;
       }
 #pragma unroll
-      for (int q = 0; q < 4; ++q) dj[q] = (float)(ld1(v, j[q]) - vi);
+      for (int q = 0; q < kGraphGroup; ++q) dj[q] = j[q] < 0 ? 0.0f : (float)(ld1(v, j[q]) - vi);
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        r += g[q] * dj[q];
-        s += g[q] * fabsf(dj[q]);
-      }
-    }
-    for (; k < w; ++k) {
-      const float g = ld1(G.gw32, base + (k << 6));
-      const float dj = (float)(ld1(v, ld1(G.sl_col, base + (k << 6))) - vi);
-      r += g * dj;
-      s += g * fabsf(dj);
+      for (int q = 0; q < kGraphGroup; ++q)
+        if (k + q < t.len) {
+          r += g[q] * dj[q];
+          s += g[q] * fabsf(dj[q]);
+        }
     }
     double hist = 0.0;  // b's history: -alpha_k i_k for each branch k leaving node i (+ entering)
     if (G.n_ind) {
@@ -316,7 +336,7 @@ __global__ __launch_bounds__(kChunk) void k_graph_probe(const GraphChunk* __rest
         hist += (e > 0) ? -term : term;
       }
     }
-    const double bound = fabs(q0 + hist + (double)r) + (double)((float)(w + 8) * 0x1p-23f * s);
+    const double bound = fabs(q0 + hist + (double)r) + (double)((float)(t.len + 8) * 0x1p-23f * s);
     m = bound * ((double)inv * kWiden);  // padding slots: inv = 0
   }
   for (int o = 32; o > 0; o >>= 1) m = nan_max(m, __shfl_xor(m, o, 64));

@@ -66,9 +66,10 @@ __host__ __device__ inline double mesh_diag(double ch, double e, double w, doubl
 // the padding columns, at x = nx-1 (gE), y = ny-1 (gN), on the top layer (gU) and wherever no
 // via exists; invD is zero in the padding, so padding corrections stay zero.  A general graph
 // (kind 1, nx = nodes, ny = nl = 1) stores its nodes colour by colour, each colour padded to
-// whole 64-slot slices, and M's off-diagonal part as a sliced-ELL neighbour table (entry k of
-// slot i at sl_off[i/64] + 64 k + i%64; w = -M_ij > 0, padding entries point at their own slot
-// with w = 0); its padding slots have D = invD = 0.  A grid carries S current scenarios that
+// whole 64-slot slices, and M's off-diagonal part (w = -M_ij > 0) as a compact sliced-ELL
+// neighbour table: slice s (64 slots, one wavefront) stores from sl_off[s] on entry 0 of each of
+// its rows that has one, in slot order, then entry 1 of each row with more than one, and so on;
+// sl_len holds the row lengths.  Its padding slots have D = invD = 0 and no entries.  A grid carries S current scenarios that
 // share its coefficients; state arrays are scenario-major (scenario s occupies slots
 // [s*nstore, (s+1)*nstore)), so one scenario is an ordinary contiguous field.
 struct GridDesc {
@@ -106,8 +107,11 @@ struct GridDesc {
   const double* ind_vfar;          // far-end voltage of a branch with ind_b = -1 (null: vdd)
   double vdd;
   // general graph: neighbour table (see above), and the table of the pairs joined by
-  // capacitors (same layout, values C_ij / h; cap_off null when there are none)
+  // capacitors, padded (entry k of slot i at cap_off[i/64] + 64 k + i%64, rows shorter than
+  // their slice's widest padded with their own slot and zero), values C_ij / h; cap_off null
+  // when there are none
   const int32_t* sl_off;
+  const uint16_t* sl_len;
   const int32_t* sl_col;
   const double* sl_w64;
   const void* sl_ws;               // w in the sweep precision

@@ -87,7 +87,7 @@ struct GridHost {
   DBuf gE64, gN64, gU64, D64, ch64, bconst64, gEs, gNs, gUs, invDs;
   DBuf v0, v1, b, r, d0, d1;
   DBuf ind_a_d, ind_b_d, ind_geq_d, ind_alpha_d, ind_i_d, inc_off_d, inc_ind_d, ind_vfar_d;
-  DBuf slot_d, sl_off_d, sl_col_d, sl_w64_d, sl_ws_d, cap_off_d, cap_col_d, cap_val_d;
+  DBuf slot_d, sl_off_d, sl_len_d, sl_col_d, sl_w64_d, sl_ws_d, cap_off_d, cap_col_d, cap_val_d;
   DBuf vprev0, vprev1, g3diag_d, sl_g64_d, bres_d, bl_d;  // three-level recurrence
   DBuf gq64_d, gsup32_d, gw32_d;                          // opening probe (general graph)
   int sweep_fp32 = -1;                           // precision the sweep buffers were built for
@@ -559,17 +559,11 @@ pg_status build_graph_grid(pg_ctx* c, int gi) {
   {
     std::vector<double> gsum(ns, 0.0);
     std::vector<float> wg32(ne);
-    const int64_t nsl = (int64_t)F.soff.size() - 1;
-    for (int64_t sl = 0; sl < nsl; ++sl) {
-      const int64_t b0 = F.soff[sl], width = (F.soff[sl + 1] - b0) / kSlice;
-      for (int64_t k = 0; k < width; ++k)
-        for (int j = 0; j < kSlice; ++j) {
-          const int64_t e = b0 + k * kSlice + j;
-          const double wg = F.g[e] + h * F.inv_l[e];
-          gsum[sl * kSlice + j] += wg;
-          wg32[e] = (float)wg;
-        }
-    }
+    for_each_entry(F, [&](int64_t e, int64_t s) {
+      const double wg = F.g[e] + h * F.inv_l[e];
+      gsum[s] += wg;
+      wg32[e] = (float)wg;
+    });
     std::vector<double> q(ns, 0.0);
     std::vector<float> gsup(ns, 0.0f);
     for (int64_t s = 0; s < ns; ++s) {
@@ -586,6 +580,7 @@ pg_status build_graph_grid(pg_ctx* c, int gi) {
   }
   PG_TRY(upload(c, G.D64, D)); PG_TRY(upload(c, G.ch64, ch)); PG_TRY(upload(c, G.bconst64, bc));
   PG_TRY(upload(c, G.sl_off_d, F.soff)); PG_TRY(upload(c, G.sl_col_d, F.col)); PG_TRY(upload(c, G.sl_w64_d, w));
+  PG_TRY(upload(c, G.sl_len_d, F.rlen));
   PG_TRY(upload(c, G.slot_d, F.slot));
   if (!F.has_coupling) {
     dfree(G.cap_off_d); dfree(G.cap_col_d); dfree(G.cap_val_d);
@@ -647,7 +642,8 @@ GridDesc make_desc(pg_ctx* c, GridHost& H) {
   D.ind_vfar = (const double*)H.ind_vfar_d.p;
   D.vdd = H.vdd;
   if (H.kind) {
-    D.sl_off = (const int32_t*)H.sl_off_d.p; D.sl_col = (const int32_t*)H.sl_col_d.p;
+    D.sl_off = (const int32_t*)H.sl_off_d.p; D.sl_len = (const uint16_t*)H.sl_len_d.p;
+    D.sl_col = (const int32_t*)H.sl_col_d.p;
     D.sl_w64 = (const double*)H.sl_w64_d.p;
     D.sl_ws = fp32_mode(c) ? H.sl_ws_d.p : H.sl_w64_d.p;
     D.cap_off = (const int32_t*)H.cap_off_d.p; D.cap_col = (const int32_t*)H.cap_col_d.p;
@@ -656,10 +652,12 @@ GridDesc make_desc(pg_ctx* c, GridHost& H) {
     D.g3diag = (const double*)H.g3diag_d.p; D.sl_g64 = (const double*)H.sl_g64_d.p;
     D.bres64 = (const double*)H.bres_d.p; D.bl64 = (const double*)H.bl_d.p;
     D.gq64 = (const double*)H.gq64_d.p; D.gsup32 = (const float*)H.gsup32_d.p; D.gw32 = (const float*)H.gw32_d.p;
-    // sweep: 1/M_ii and w in the sweep precision, and a 4-byte column index per table entry;
-    // residual: M_ii and w in FP64 and the column index (half an FP64 word)
-    H.coef_words = H.nstore + (fp32_mode(c) ? 2 * H.form.nnz : (3 * H.form.nnz) / 2);
-    H.resid_words = H.nstore + (3 * H.form.nnz) / 2;
+    // sweep: 1/M_ii and w in the sweep precision, a 2-byte row length per slot and a 4-byte
+    // column index per table entry; residual: M_ii and w in FP64, the row length (a quarter of
+    // an FP64 word) and the column index (half a word); nstore is a multiple of 64
+    H.coef_words = fp32_mode(c) ? H.nstore + H.nstore / 2 + 2 * H.form.nnz
+                                : H.nstore + H.nstore / 4 + (3 * H.form.nnz) / 2;
+    H.resid_words = H.nstore + H.nstore / 4 + (3 * H.form.nnz) / 2;
   } else {
     H.coef_words = 3 * H.n + (int64_t)H.nx * H.ny * (H.nl - 1);
     H.resid_words = H.coef_words;
@@ -771,7 +769,7 @@ pg_status prepare(pg_ctx* c) {
       c->graph_nodes += H.n * H.S;
       c->graph_coef += H.coef_words;
       c->graph_rcoef += H.resid_words;
-      c->graph_entries += H.form.nnz * H.S;  // algorithmic: the stored padding is not charged
+      c->graph_entries += H.form.nnz * H.S;  // table entries (the table stores no padding)
     } else {
       const double w = (double)H.n * H.S;
       fr += w * (8.0 + 8.0 * (__builtin_popcount(H.ch_layers) + __builtin_popcount(H.bc_layers)) / H.nl);
@@ -783,7 +781,10 @@ pg_status prepare(pg_ctx* c) {
   c->fuse_read = fn > 0 ? fr / fn : 24.0;
   c->probe_read = fn > 0 ? fp / fn : 16.0;
   // general-graph chunks: every slot of every scenario (right-hand side, residual), and the
-  // sweep chunks colour by colour
+  // sweep chunks colour by colour.  In the first list each scenario's chunks interleave the
+  // colours by position inside their colour: a node's neighbours lie at about the same relative
+  // position of the other colours, so the run of chunks one XCD takes (xcd_tile) finds most of
+  // its neighbour values in chunks of its own, in its own L2.
   std::vector<GraphChunk> gall, gsweep;
   c->gcolor.clear();
   c->item_gchunk_off.assign(n_items(c), 0);
@@ -795,8 +796,18 @@ pg_status prepare(pg_ctx* c) {
     maxc = std::max(maxc, H.form.ncolors);
     for (int sc = 0; sc < H.S; ++sc) {
       c->item_gchunk_off[H.item0 + sc] = (int)gall.size();
-      for (int64_t s0 = 0; s0 < H.nstore; s0 += kChunk)
-        gall.push_back(GraphChunk{g, H.item0 + sc, sc, (int32_t)s0, (int32_t)std::min<int64_t>(kChunk, H.nstore - s0), 0});
+      std::vector<std::pair<double, GraphChunk>> keyed;
+      for (int k = 0; k < H.form.ncolors; ++k) {
+        const int64_t a = H.form.cstart[k], b = H.form.cstart[k + 1];
+        for (int64_t s0 = a; s0 < b; s0 += kChunk)
+          keyed.emplace_back((double)(s0 - a) / (double)(b - a),
+                             GraphChunk{g, H.item0 + sc, sc, (int32_t)s0, (int32_t)std::min<int64_t>(kChunk, b - s0), 0});
+      }
+      std::stable_sort(keyed.begin(), keyed.end(),
+                       [](const std::pair<double, GraphChunk>& x, const std::pair<double, GraphChunk>& y) {
+                         return x.first < y.first;
+                       });
+      for (const auto& kc : keyed) gall.push_back(kc.second);
       c->item_gchunk_cnt[H.item0 + sc] = (int)gall.size() - c->item_gchunk_off[H.item0 + sc];
     }
   }
@@ -989,8 +1000,8 @@ pg_status launch_resid_all(pg_ctx* c, int has_d, int din, double tol = 0.0, int*
     const double gn = (double)c->graph_nodes;
     bytes = meshes ? c->resid_bytes(c->all_nodes - c->graph_nodes, c->all_coef - c->graph_coef,
                                     c->all_rcoef - c->graph_rcoef, false, fuse) : 0.0;
-    if (gprobe)  // v, 1/M_ii, q, gsup per slot; column and FP32 conductance per table entry
-      bytes += (20.0 + e) * gn + 8.0 * (double)c->graph_entries;
+    if (gprobe)  // v, 1/M_ii, q, gsup, row length per slot; column and FP32 conductance per entry
+      bytes += (22.0 + e) * gn + 8.0 * (double)c->graph_entries;
     else  // b formed (C/h, constant, v, b), then r and v stored
       bytes += 32.0 * gn + (16.0 + e) * gn + 8.0 * (double)c->graph_rcoef;
   }
@@ -1842,7 +1853,7 @@ void pg_destroy(pg_ctx* c) {
     DBuf* bufs[] = {&H.gE64, &H.gN64, &H.gU64, &H.D64, &H.ch64, &H.bconst64, &H.gEs, &H.gNs, &H.gUs, &H.invDs,
                     &H.v0, &H.v1, &H.b, &H.r, &H.d0, &H.d1, &H.ind_a_d, &H.ind_b_d, &H.ind_geq_d,
                     &H.ind_alpha_d, &H.ind_i_d, &H.inc_off_d, &H.inc_ind_d, &H.ind_vfar_d,
-                    &H.slot_d, &H.sl_off_d, &H.sl_col_d, &H.sl_w64_d, &H.sl_ws_d, &H.cap_off_d, &H.cap_col_d,
+                    &H.slot_d, &H.sl_off_d, &H.sl_len_d, &H.sl_col_d, &H.sl_w64_d, &H.sl_ws_d, &H.cap_off_d, &H.cap_col_d,
                     &H.cap_val_d, &H.vprev0, &H.vprev1, &H.g3diag_d, &H.sl_g64_d, &H.bres_d, &H.bl_d,
                     &H.gq64_d, &H.gsup32_d, &H.gw32_d, &H.gE_raw, &H.gN_raw, &H.C_raw, &H.chk_d,
                     &H.padt_slot_d, &H.padt_val_d};

@@ -8,6 +8,10 @@
 //   * a mesh's branch list maps back onto exactly the mesh (pg_netlist_to_mesh round trip);
 //   * the colouring joins no two nodes of one colour by an R, L or C branch, and the slots
 //     are a permutation that follows the colours, each colour padded to a multiple of 64;
+//   * walking the compact neighbour table level by level, as a wavefront does (the rows with
+//     more than k entries take entry k in slot order), gives every node exactly its
+//     neighbours, in increasing slot order, with the summed R, 1/L and C of the branches
+//     joining each pair, and each slice's walk ends at the next slice's first entry;
 //   * every corrupted input is refused with PG_ERR_INVALID_ARG;
 //   * every status is one of pg_status, and messages are terminated within their buffers.
 // The sanitizers report any out-of-bounds access, use after free, leak or undefined behaviour.
@@ -293,6 +297,81 @@ void arbitrary_netlists(Rng& r) {
   CHECK(known_status(s), "colouring status %d", s);
 }
 
+// The compact neighbour table of the graph form against the branch list: the walk a wavefront
+// makes over each 64-slot slice (entry level k holds entry k of every row longer than k, in
+// slot order) must give each node's neighbours with their summed values.
+bool table_matches(const Netlist& nl, const std::vector<int32_t>& slot) {
+  pgrid::GraphForm f;
+  char msg[128];
+  pg_status s = pgrid::build_graph_form(nl.n, nl.p, nl.source_v.data(), (int32_t)nl.kind.size(), nl.from.data(),
+                                        nl.to.data(), nl.kind.data(), nl.value.data(), f, msg, sizeof msg);
+  CHECK(s == PG_OK, "graph form of a valid random graph: %d (%s)", s, msg);
+  if (s != PG_OK) return false;
+  struct Val { double g = 0, il = 0, c = 0; };
+  std::vector<std::vector<std::pair<int32_t, Val>>> want(f.nslots);  // by slot: (neighbour slot, values)
+  {
+    std::vector<std::pair<std::pair<int32_t, int32_t>, Val>> pairs;
+    for (size_t e = 0; e < nl.kind.size(); ++e) {
+      const int a = nl.from[e], b = nl.to[e];
+      const char k = (char)nl.kind[e];
+      if (k == 'I' || a < 0 || b < 0 || a >= nl.n || b >= nl.n) continue;
+      Val v;
+      if (k == 'R') v.g = nl.value[e];
+      if (k == 'L') v.il = 1.0 / nl.value[e];
+      if (k == 'C') v.c = nl.value[e];
+      pairs.push_back({{std::min(a, b), std::max(a, b)}, v});
+    }
+    std::sort(pairs.begin(), pairs.end(), [](const auto& x, const auto& y) { return x.first < y.first; });
+    for (size_t q = 0; q < pairs.size();) {
+      Val sum;
+      size_t t = q;
+      for (; t < pairs.size() && pairs[t].first == pairs[q].first; ++t) {
+        sum.g += pairs[t].second.g; sum.il += pairs[t].second.il; sum.c += pairs[t].second.c;
+      }
+      const int a = pairs[q].first.first, b = pairs[q].first.second;
+      want[slot[a]].push_back({slot[b], sum});
+      want[slot[b]].push_back({slot[a], sum});
+      q = t;
+    }
+    for (auto& w : want) std::sort(w.begin(), w.end(), [](const auto& x, const auto& y) { return x.first < y.first; });
+  }
+  const int64_t nsl = f.nslots / pgrid::kSlice;
+  bool ok = (int64_t)f.soff.size() == nsl + 1 && (int64_t)f.rlen.size() == f.nslots && f.soff[0] == 0 &&
+            (int64_t)f.col.size() == f.soff[nsl] && f.soff[nsl] == f.nnz;
+  CHECK(ok, "graph table extents: %zu offsets, %zu lengths, %zu entries, nnz %lld", f.soff.size(), f.rlen.size(),
+        f.col.size(), (long long)f.nnz);
+  if (!ok) return false;
+  auto close = [](double x, double y) { return std::fabs(x - y) <= 1e-12 * std::max(std::fabs(x), std::fabs(y)); };
+  for (int64_t sl = 0; sl < nsl; ++sl) {
+    std::vector<std::vector<int64_t>> got(pgrid::kSlice);
+    int64_t P = f.soff[sl];
+    for (int k = 0;; ++k) {
+      int rank = 0;
+      for (int j = 0; j < pgrid::kSlice; ++j)
+        if (k < f.rlen[sl * pgrid::kSlice + j]) got[j].push_back(P + rank++);
+      if (rank == 0) break;
+      P += rank;
+    }
+    CHECK(P == f.soff[sl + 1], "slice %lld: the walk ends at %lld, the next slice starts at %d", (long long)sl,
+          (long long)P, f.soff[sl + 1]);
+    if (P != f.soff[sl + 1]) return false;
+    for (int j = 0; j < pgrid::kSlice; ++j) {
+      const int64_t own = sl * pgrid::kSlice + j;
+      const auto& w = want[own];
+      bool row_ok = got[j].size() == w.size();
+      for (size_t q = 0; row_ok && q < w.size(); ++q) {
+        const int64_t e = got[j][q];
+        row_ok = f.col[e] == w[q].first && close(f.g[e], w[q].second.g) && close(f.inv_l[e], w[q].second.il) &&
+                 close(f.cc[e], w[q].second.c);
+      }
+      CHECK(row_ok, "slot %lld: its table row (%zu entries) is not its %zu neighbours", (long long)own,
+            got[j].size(), w.size());
+      if (!row_ok) return false;
+    }
+  }
+  return true;
+}
+
 // A random valid general netlist: a random tree of resistors over n trivial nodes, extra R, L and
 // coupling-C branches between random pairs, capacitors and current sources to ground, and
 // resistors to the supplies; the colouring must separate every coupled pair.
@@ -339,6 +418,7 @@ void random_graph(Rng& r) {
     if (!ok) return;
     seen[slot[i]] = 1;
   }
+  if (!table_matches(nl, slot)) return;
   ++graphs_ok;
 }
 

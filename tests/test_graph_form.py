@@ -24,16 +24,69 @@ def test_coloring_is_proper_and_slots_follow_colours(rlc):
     assert np.all(color[a] != color[b])
     assert nc >= 3  # the diagonal straps close odd cycles
     assert np.array_equal(np.sort(np.unique(color)), np.arange(nc))
-    # slots: a bijection into [0, n_slots), colours in order, node order inside a colour,
-    # each colour's block padded to whole 64-slot slices
+    # slots: a bijection into [0, n_slots), colours in order, each colour's block contiguous and
+    # padded to whole 64-slot slices
     assert len(np.unique(slot)) == net.n and slot.min() >= 0 and slot.max() < ns and ns % 64 == 0
     start = 0
     for c in range(nc):
         nodes = np.nonzero(color == c)[0]
-        s = slot[nodes]
-        assert s[0] == start and np.all(np.diff(s) == 1)
+        assert np.array_equal(np.sort(slot[nodes]), start + np.arange(nodes.size))
         start += -(-nodes.size // 64) * 64
     assert start == ns
+
+
+def _cuthill_mckee(n, a, b):
+    """Breadth first from a pseudo-peripheral node of each connected part (parts by smallest node),
+    unvisited neighbours by increasing degree, ties by node."""
+    nbrs = [set() for _ in range(n)]
+    for x, y in zip(a.tolist(), b.tolist()):
+        nbrs[x].add(y)
+        nbrs[y].add(x)
+    deg = [len(s) for s in nbrs]
+    key = lambda u: (deg[u], u)
+    placed, order = [False] * n, []
+    for s0 in range(n):
+        if placed[s0]:
+            continue
+        root, depth = s0, -1
+        for _ in range(8):
+            lev = {root: 0}
+            q = [root]
+            for u in q:
+                for w in sorted(nbrs[u]):
+                    if w not in lev:
+                        lev[w] = lev[u] + 1
+                        q.append(w)
+            d = lev[q[-1]]
+            if d <= depth:
+                break
+            depth = d
+            root = min((u for u in q if lev[u] == d), key=key)
+        placed[root] = True
+        q = [root]
+        for u in q:
+            order.append(u)
+            new = sorted((w for w in nbrs[u] if not placed[w]), key=key)
+            for w in new:
+                placed[w] = True
+            q.extend(new)
+    return order
+
+
+@pytest.mark.parametrize("seed", [5, 11])
+def test_slots_follow_cuthill_mckee_order_inside_each_colour(seed):
+    net, _ = irregular_grid(side=20, nl=3, seed=seed)
+    color, slot, nc, ns = pg.netlist_coloring(net.n, net.p, net.source_v, net.frm, net.to, net.kind, net.value)
+    a, b = _pattern_edges(net)
+    order = _cuthill_mckee(net.n, a, b)
+    assert sorted(order) == list(range(net.n))
+    for c in range(nc):
+        in_c = [u for u in order if color[u] == c]
+        assert np.all(np.diff(slot[in_c]) == 1)
+    # neighbours lie close in this order: the widest gap along a branch is a small fraction of n
+    rank = np.empty(net.n, dtype=np.int64)
+    rank[order] = np.arange(net.n)
+    assert np.max(np.abs(rank[a] - rank[b])) < net.n // 4
 
 
 def test_mesh_branch_list_is_two_coloured_checkerboard():
