@@ -33,7 +33,7 @@ HBM_PEAK = 8.0e12   # B/s, MI355X HBM3E
 MALL_BYTES = 256 * 2 ** 20  # MI355X Infinity Cache (memory-attached last-level cache)
 
 WORKLOADS = ["config0", "config1", "config2", "config4", "config3a", "config3b", "graph1", "graph_mesh1",
-             "config1_hbm"]
+             "config1_hbm", "graph1_shuffled"]
 
 
 def parse():
@@ -81,11 +81,12 @@ TUNED = {
     "config0": dict(omega=1.6, check_every=8, graphs=1, resident=1),
     "config1": dict(omega=1.6, check_every=8, tile_rows=16, graphs=0),
     "config1_hbm": dict(omega=1.6, check_every=8, tile_rows=16, graphs=0),
-    "config2": dict(omega=1.8, check_every=16, graphs=0),
+    "config2": dict(omega=1.8, check_every=16, graphs=0, sweeps_per_launch_fp32=4),
     "config3a": dict(omega=1.7, check_every=8, tile_rows=16, scen_block=16, graphs=0),
     "config3b": dict(omega=1.6, check_every=8, graphs=0),
     "config4": dict(omega=1.6, check_every=6, graphs=0),
     "graph1": dict(omega=1.6, check_every=6, graphs=0),
+    "graph1_shuffled": dict(omega=1.6, check_every=6, graphs=0),
     "graph_mesh1": dict(omega=1.6, check_every=8, graphs=0),
 }
 
@@ -110,15 +111,26 @@ TUNED_PARITY = {
 }
 
 
-def settings(name, tol):
+def settings(name, tol, precision="fp32+ref"):
     """Solver options (omega, check_every, tile_rows, graphs, scen_block, sweeps_per_launch,
-    resident) that bench.py runs workload `name` with at stopping tolerance `tol`."""
+    resident) that bench.py runs workload `name` with at stopping tolerance `tol` and sweep
+    precision `precision` ("fp64", "fp32+ref" or the library's constant); four sweeps per launch
+    (sweeps_per_launch_fp32) apply to FP32 sweeps only."""
+    fp32 = precision in ("fp32+ref", pg_const("PG_PREC_FP32_REFINE"))
     s = dict(tile_rows=0, scen_block=0, sweeps_per_launch=0, resident=0)
     s.update(TUNED[name])
     ptol = PARITY_TOL.get(name, PARITY_TOL.get(name.replace("_hbm", "")))
     if ptol is not None and tol <= ptol:
         s.update(TUNED_PARITY.get(name, {}))
+    spl32 = s.pop("sweeps_per_launch_fp32", None)
+    if fp32 and spl32:
+        s["sweeps_per_launch"] = spl32
     return s
+
+
+def pg_const(name):
+    import paper_1409_7166_amd as pg
+    return getattr(pg, name)
 
 
 # The side legs of the default run: (workload, precision, tolerance).
@@ -144,6 +156,7 @@ COUNTERS = {
     "config1": os.path.join(ROOT, "profiles", "k_sweep_rb_rc3x1024_counters.json"),
     "config1_hbm": os.path.join(ROOT, "profiles", "k_sweep_rb_rc3x2048_counters.json"),
     "config3a": os.path.join(ROOT, "profiles", "k_sweep_rb_multi_batch256x256_counters.json"),
+    "graph1": os.path.join(ROOT, "profiles", "k_graph_sweep_irregular3x1024_counters.json"),
 }
 
 
@@ -156,8 +169,9 @@ def counter_traffic(name, kernel, avg_alg_bytes):
         summ = json.load(open(COUNTERS[name]))
     except (KeyError, OSError):
         return None
-    src = open(os.path.join(ROOT, "paper_1409_7166_amd", "csrc", "kernels.hip"), "rb").read()
-    if hashlib.sha256(src).hexdigest()[:16] != summ["kernels_hip_sha256_16"] or kernel not in summ:
+    src = open(os.path.join(ROOT, summ.get("source", "paper_1409_7166_amd/csrc/kernels.hip")), "rb").read()
+    if hashlib.sha256(src).hexdigest()[:16] != summ.get("source_sha256_16", summ.get("kernels_hip_sha256_16")) \
+            or kernel not in summ:
         return None
     full, cold = summ[kernel]["full_launch"], summ[kernel]["cold_start_launch"]
     a_full, a_cold = full["algorithmic_bytes"], cold["algorithmic_bytes"]
@@ -173,6 +187,8 @@ def make_workload(name):
         w = workloads.config1(side=2048)
         w.name = "rc_3x2048x2048"
         return w
+    if name == "graph1_shuffled":  # the irregular netlist with its node ids in random order
+        return workloads.graph1(shuffle=True)
     return getattr(workloads, name)()
 
 
@@ -329,9 +345,10 @@ def cpu_baseline(workload_name, budget_steps=100):
     from oracle.sources import currents_at
 
     note = "SuperLU (scipy) factorises and solves on one thread; the steps of a transient are sequential"
-    if workload_name in ("graph1", "graph_mesh1"):
+    if workload_name in ("graph1", "graph_mesh1", "graph1_shuffled"):
         from oracle import Circuit
-        w = getattr(workloads, workload_name)(side=256)
+        w = workloads.graph1(side=256, shuffle=True) if workload_name == "graph1_shuffled" else \
+            getattr(workloads, workload_name)(side=256)
         net, p = w.nets[0], w.pulses[0][0]
         sample = f"{w.name}: the 1024x1024 recipe at 256x256 ({net.n:,} nodes)"
         circ = Circuit(net.n, net.source_v, net.frm.astype(np.int64), net.to.astype(np.int64), net.kind, net.value)
@@ -413,7 +430,7 @@ def measure(name, prec, tol, steps, args, do_verify=True):
     """One timed run: the JSON record of bench.py for workload `name`."""
     w = make_workload(name)
     prec = prec or w.precision
-    tuned = settings(name, tol)
+    tuned = settings(name, tol, prec)
     omega = args.omega or tuned["omega"]
     chk = args.check_every or tuned["check_every"]
     rows = args.tile_rows or tuned.get("tile_rows", 0)
@@ -482,7 +499,7 @@ def measure_adjoint(args, steps=200, ckpt=20, margin=0.05, tol=1e-10, tol_adj=1e
 
     w = workloads.config4(steps=steps)
     mesh = w.meshes[0]
-    t = settings("config4", tol)
+    t = settings("config4", tol, "fp64")
     torch.cuda.set_device(0)
     ctx = pg.Context(0, torch.cuda.current_stream().cuda_stream)
     ctx.set_options(h=w.h, tol=tol, omega=t["omega"], check_every=t["check_every"], max_sweeps=100000,

@@ -91,9 +91,14 @@ typedef struct pg_options {
   int32_t graphs;       /* 1: replay each step's launches from captured HIP graphs; 0: launch one by one */
   int32_t scen_block;   /* scenarios per sweep/residual workgroup on grids that carry several
                            scenarios (coefficients are loaded once per block): 1..16 (0 = 8) */
-  int32_t sweeps_per_launch; /* red-black sweeps fused into one kernel launch: 1 or 2 (0 = 1); two
-                           sweeps stage a wider halo and recompute its rings, and move the bytes
-                           of one sweep.  Results are identical.  Jacobi ordering always uses 1 */
+  int32_t sweeps_per_launch; /* red-black sweeps fused into one kernel launch: 1, 2 or 4 (0 = 1).
+                           Two sweeps stage a wider halo and recompute its rings; four (FP32
+                           sweeps only: PG_PREC_FP32_REFINE, else PG_ERR_INVALID_ARG) stage the
+                           tile with an 8-node halo and its coefficients once and run all four
+                           sweeps on chip, on single-scenario meshes of 1-2 layers with 4, 8 or
+                           16 tile rows or 3 layers with 4 (otherwise one sweep per launch).  A
+                           launch moves the bytes of about one sweep.  Results are identical.
+                           Jacobi ordering always uses 1 */
   int32_t recurrence;   /* PG_REC_TWO_LEVEL (default) or PG_REC_THREE_LEVEL (general netlists only) */
   int32_t resident;     /* 1: pg_step / pg_run_transient advance every item in one launch per call
                            (per recorded interval), one workgroup per item carrying whole steps
@@ -151,7 +156,9 @@ typedef struct pg_stats {
  * once) are left out.
  * *_bytes are algorithmic bytes of the timed launches, charged for the (grid, scenario) items
  * that were still iterating (the rest exit at once): every array the kernel needs read once
- * and every array it produces written once, with e = 4 (FP32 sweeps) or 8 (FP64) bytes.  Per
+ * and every array it produces written once, with e = 4 (FP32 sweeps) or 8 (FP64) bytes; sweeps
+ * are charged one by one, so a launch that fuses k sweeps (sweeps_per_launch) is charged the
+ * bytes of k one-sweep launches, although it moves about those of one.  Per
  * active node and scenario: sweep e * (r + d_new [+ d_old unless it starts from zero]),
  * residual 8 * (v + b) + e * r [+ e * d + 8 * v_out]; per mesh node of a grid with an active
  * scenario (coefficients are shared by the scenarios of a grid): sweep e * (gE + gN + invD)

@@ -18,7 +18,7 @@ ROOT = os.path.dirname(HERE)
 OBJ = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libpgrid.so")
 
-HIP_SOURCES = ["kernels.hip", "kernels_graph.hip", "kernels_resident.hip", "runtime.hip"]
+HIP_SOURCES = ["kernels.hip", "kernels_graph.hip", "kernels_resident.hip", "kernels_tb.hip", "runtime.hip"]
 HOST_SOURCES = ["validate.cpp", "netlist.cpp", "graph.cpp"]
 ARCH = "gfx950"
 

@@ -1,0 +1,144 @@
+// gfx950 kernel that runs K red-black SOR sweeps (eqs. 16-17) of a layered mesh per launch, for
+// meshes whose tiles are too few to hide a launch (a few hundred tiles: about one per CU).
+//
+// Overlapped temporal blocking.  A workgroup stages its 128 x TY tile (all layers) with a halo
+// of H = 2K nodes on every side once: the old correction in LDS, the right-hand side and the
+// coefficients of every staged pair in registers.  Half-sweep i (i = 1 .. 2K, red first) updates
+// the nodes of its colour that lie within H - i nodes of the tile (the tile's box grown by
+// H - i in x and in y, clipped to the mesh).  A node's update reads its four in-plane neighbours
+// (one step in x or in y) and the nodes above and below it, all of which lie in the box of the
+// previous half-sweep, so every value read is the one a mesh-wide half-sweep would have
+// produced; after the last (black) half-sweep the tile's own nodes hold exactly the result of K
+// separate sweeps, and only they are written.  Each node update is the same expression, on the
+// same operands, as in the one-sweep kernel, so the results are bit-identical.
+//
+// A launch reads the arrays of one sweep for its tile plus the halo (the halo mostly from L2:
+// it belongs to the neighbouring tiles of the same XCD) and does K sweeps of work.
+#include "mesh_tile.h"
+
+namespace pgrid {
+
+namespace {
+
+constexpr int kTbThreads = 1024;
+
+template <typename T, int NL, int TY, int K>
+__global__ __launch_bounds__(kTbThreads) void k_sweep_tb(const Tile* __restrict__ tiles, int ntiles,
+                                                        const GridDesc* __restrict__ grids, Ctl c, int din,
+                                                        int zero_in, T omega) {
+  constexpr int H = 2 * K;               // staged nodes beyond the tile on every side
+  constexpr int HP = kTileX / 2 + H;     // staged pairs per row
+  constexpr int HY = TY + 2 * H;         // staged rows
+  constexpr int NQ = NL * HY * HP;       // staged pairs
+  constexpr int J = (NQ + kTbThreads - 1) / kTbThreads;
+  constexpr int kOut = 0xff;             // distance of a node outside the mesh (never updated)
+  static_assert(H < kOut, "distances are stored in 8 bits");
+  __shared__ V2<T> sd[NL][HY][HP];
+  const int ti = xcd_tile(ntiles);
+  if (ti < 0) return;
+  const Tile tl = tiles[ti];
+  if (!c.active[tl.item]) return;
+  const GridDesc& G = grids[tl.grid];
+  const int ny = G.ny, X = G.X;
+  const int64_t P = (int64_t)X * ny;
+  const int64_t off = (int64_t)tl.scen * G.nstore;
+  const int x0 = tl.x0, y0 = tl.y0;
+  const T* __restrict__ dold = static_cast<const T*>(G.d[din]) + off;
+  T* __restrict__ dnew = static_cast<T*>(G.d[din ^ 1]) + off;
+  const T* __restrict__ gE = static_cast<const T*>(G.gEs);
+  const T* __restrict__ gN = static_cast<const T*>(G.gNs);
+  const T* __restrict__ gU = static_cast<const T*>(G.gUs);
+  const T* __restrict__ invD = static_cast<const T*>(G.invDs);
+  const T* __restrict__ r = static_cast<const T*>(G.r) + off;
+
+  // Staged pair q = (l HY + hy) HP + hp of this thread: q = threadIdx.x + j * kTbThreads.  For
+  // each, the pair's coefficients and r, its packed position (l, hy, hp), and the distance from
+  // the tile of its red node (bits 0-7) and of its black node (bits 8-15).
+  PairRaw<T> pr[J];
+  int at[J], dist[J];
+  {
+    V2<T> dv[J];
+#pragma unroll
+    for (int j = 0; j < J; ++j) {
+      const int q = threadIdx.x + j * kTbThreads;
+      const int l = q / (HY * HP), rem = q - l * (HY * HP), hy = rem / HP, hp = rem - hy * HP;
+      const int gx = x0 - H + 2 * hp, gy = y0 - H + hy;
+      at[j] = (l << 16) | (hy << 8) | hp;
+      dist[j] = kOut | (kOut << 8);
+      dv[j] = zero2<T>();
+      if (q < NQ && gx >= 0 && gx < X && gy >= 0 && gy < ny) {
+        if (!zero_in) dv[j] = ld2(dold, l * P + (int64_t)gy * X + gx);
+        load_pair_raw<T, NL>(G, gE, gN, gU, invD, r, l, gy, gx, pr[j]);
+        const int er = (gy + l) & 1;  // gx is even: the pair's red node is gx + er
+        const int dy = max(max(y0 - gy, gy - (y0 + TY - 1)), 0);
+        const int xr = gx + er, xb = gx + 1 - er;
+        const int dr = max(max(max(x0 - xr, xr - (x0 + kTileX - 1)), 0), dy);
+        const int db = max(max(max(x0 - xb, xb - (x0 + kTileX - 1)), 0), dy);
+        dist[j] = dr | (db << 8);
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < J; ++j) {
+      const int q = threadIdx.x + j * kTbThreads;
+      if (q < NQ) (&sd[0][0][0])[q] = dv[j];
+    }
+  }
+  __syncthreads();
+
+#pragma unroll
+  for (int i = 1; i <= 2 * K; ++i) {
+    const int colour = (i - 1) & 1;
+#pragma unroll
+    for (int j = 0; j < J; ++j) {
+      const int dc = colour ? (dist[j] >> 8) : (dist[j] & 0xff);
+      if (dc > H - i) continue;  // outside this half-sweep's box, or outside the mesh
+      const int l = at[j] >> 16, hy = (at[j] >> 8) & 0xff, hp = at[j] & 0xff;
+      const int gy = y0 - H + hy;
+      const int ec = ((gy + l) & 1) ^ colour;  // element of the pair with this colour
+      const T nv = relax<T, NL, HY, HP>(sd, l, hy, hp, ec, node_of(pr[j], ec), omega);
+      if (i < 2 * K) {
+        put(sd[l][hy][hp], ec, nv);
+      } else {  // the tile's black nodes: write the pair with its red partner's final value
+        V2<T> out = sd[l][hy][hp];
+        put(out, ec, nv);
+        st2(dnew, l * P + (int64_t)gy * X + (x0 - H + 2 * hp), out);
+      }
+    }
+    if (i < 2 * K) __syncthreads();
+  }
+}
+
+template <int NL, int TY>
+void tb_t(const Tile* tiles, int ntiles, const GridDesc* grids, const Ctl& c, int din, int zero_in, double omega,
+          hipStream_t s) {
+  hipLaunchKernelGGL((k_sweep_tb<float, NL, TY, kTbSweeps>), dim3(xcd_blocks(ntiles)), dim3(kTbThreads), 0, s,
+                     tiles, ntiles, grids, c, din, zero_in, (float)omega);
+}
+
+}  // namespace
+
+// The shapes instantiated below (their staged pairs' registers fit without spilling): one or two
+// layers with 4, 8 or 16 tile rows, three layers with 4.
+bool sweep_tb_supported(bool fp32, bool multi, int ordering, int nl, int tile_rows) {
+  if (!fp32 || multi || ordering != 0) return false;  // FP32 red-black sweeps of single-scenario grids
+  return ((nl == 1 || nl == 2) && (tile_rows == 4 || tile_rows == 8 || tile_rows == 16)) ||
+         (nl == 3 && tile_rows == 4);
+}
+
+hipError_t launch_sweep_tb(int nl, int tile_rows, const Tile* tiles, int ntiles, const GridDesc* grids,
+                           const Ctl& c, int din, int zero_in, double omega, hipStream_t s) {
+  if (ntiles <= 0) return hipSuccess;
+  switch (nl * 100 + tile_rows) {
+    case 104: tb_t<1, 4>(tiles, ntiles, grids, c, din, zero_in, omega, s); break;
+    case 108: tb_t<1, 8>(tiles, ntiles, grids, c, din, zero_in, omega, s); break;
+    case 116: tb_t<1, 16>(tiles, ntiles, grids, c, din, zero_in, omega, s); break;
+    case 204: tb_t<2, 4>(tiles, ntiles, grids, c, din, zero_in, omega, s); break;
+    case 208: tb_t<2, 8>(tiles, ntiles, grids, c, din, zero_in, omega, s); break;
+    case 216: tb_t<2, 16>(tiles, ntiles, grids, c, din, zero_in, omega, s); break;
+    case 304: tb_t<3, 4>(tiles, ntiles, grids, c, din, zero_in, omega, s); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+}  // namespace pgrid

@@ -132,11 +132,12 @@ struct pg_ctx {
   // multi: the group's tiles are scenario blocks (Tile.pad consecutive scenarios of a grid)
   struct Group { int nl, off, count; int64_t nodes, mesh_nodes; bool multi; };
   // Algorithmic bytes (see pgrid.h) for `an` active mesh nodes x scenarios whose grids hold
-  // `coef` coefficient words: a cycle of L sweep launches (the first starts from d = 0 and reads
-  // no old correction; a launch of two fused sweeps moves the bytes of one), and one residual pass.
-  double cycle_bytes(int64_t an, int64_t coef, int L) const {
+  // `coef` coefficient words: a cycle of nchk sweeps, charged sweep by sweep as one-sweep
+  // launches move them (the first starts from d = 0 and reads no old correction; a launch that
+  // fuses several sweeps is charged each of them), and one residual pass.
+  double cycle_bytes(int64_t an, int64_t coef, int nchk) const {
     const double e = opt.precision == PG_PREC_FP32_REFINE ? 4.0 : 8.0;
-    return e * ((2.0 + 3.0 * (L - 1)) * an + (double)L * coef);
+    return e * ((2.0 + 3.0 * (nchk - 1)) * an + (double)nchk * coef);
   }
   // `coef` sweep-precision coefficient words (the probe reads those), `rcoef` FP64 words.
   double resid_bytes(int64_t an, int64_t coef, int64_t rcoef, bool has_d, int fuse = 0) const {
@@ -160,6 +161,7 @@ struct pg_ctx {
   double fuse_read = 24.0;                       // bytes per node a right-hand-side-forming pass reads
   double probe_read = 16.0;                      // bytes per node a cancelled-form probe reads besides coefficients
   bool probe_cancelled = true;                   // every mesh grid has a non-zero supply (cancelled-form probes)
+  bool tb_ok = false;                            // every mesh tile group has the four-sweep kernel
   // general-graph chunks: all slots (right-hand side, residual) and, per colour index, the
   // chunks of that colour over every graph grid ([off, off+count) of g_chunks_sweep)
   DBuf g_chunks_all, g_chunks_sweep;
@@ -755,6 +757,9 @@ pg_status prepare(pg_ctx* c) {
     }
   }
   c->ntiles_all = (int)tiles.size();
+  c->tb_ok = true;
+  for (auto& grp : c->tile_groups)
+    c->tb_ok = c->tb_ok && sweep_tb_supported(fp32_mode(c), grp.multi, c->opt.ordering, grp.nl, TY);
   c->all_nodes = 0;
   c->all_coef = c->all_rcoef = 0;
   c->graph_nodes = c->graph_coef = c->graph_rcoef = c->graph_entries = 0;
@@ -1037,16 +1042,20 @@ pg_status launch_resid_all(pg_ctx* c, int has_d, int din, double tol = 0.0, int*
 }
 
 // Sweeps fused per launch (1 or 2); Jacobi sweeps are always launched one by one.
+// Sweeps per launch of every mesh tile group: 4 only where every group has the four-sweep
+// kernel (else the groups' launch counts, and so the buffer holding a cycle's result, would differ).
 int sweeps_per_launch(const pg_ctx* c) {
   if (c->opt.ordering != PG_ORDER_RED_BLACK) return 1;
-  return c->opt.sweeps_per_launch ? c->opt.sweeps_per_launch : 1;
+  const int spl = c->opt.sweeps_per_launch ? c->opt.sweeps_per_launch : 1;
+  return spl == kTbSweeps && !c->tb_ok ? 1 : spl;
 }
 
-// Kernel launches per tile group in a cycle of nchk sweeps; the cycle's result is in d[launches & 1].
-// (General graphs sweep in place in d[0], one launch per colour.)
+// Kernel launches per tile group in a cycle of nchk sweeps (fused launches, then one-sweep
+// launches for the remainder); the cycle's result is in d[launches & 1].  (General graphs sweep
+// in place in d[0], one launch per colour.)
 int cycle_launches(const pg_ctx* c, int nchk) {
   const int spl = sweeps_per_launch(c);
-  return (nchk + spl - 1) / spl;
+  return nchk / spl + nchk % spl;
 }
 
 // All kernel launches of a cycle of nchk sweeps.
@@ -1065,7 +1074,11 @@ pg_status launch_sweeps(pg_ctx* c, int nchk) {
     for (int s = 0, j = 0; s < nchk; ++j) {
       const int zero_in = s == 0 ? 1 : 0;
       hipError_t e;
-      if (spl == 2 && nchk - s >= 2) {
+      if (spl == kTbSweeps && nchk - s >= kTbSweeps) {
+        e = launch_sweep_tb(grp.nl, c->tile_rows, T + grp.off, grp.count, (const GridDesc*)c->grid_desc.p, c->ctl,
+                            j & 1, zero_in, c->opt.omega, c->stream);
+        s += kTbSweeps;
+      } else if (spl == 2 && nchk - s >= 2) {
         e = launch_sweep2(fp32_mode(c), grp.nl, c->tile_rows, T + grp.off, grp.count,
                           (const GridDesc*)c->grid_desc.p, c->ctl, j & 1, zero_in, c->opt.omega, c->stream);
         s += 2;
@@ -1394,7 +1407,7 @@ pg_status cycle_loop(pg_ctx* c, double tol, bool graphs, int first, bool specula
     const Acct& wk = work[ev.chunk - 1];
     if (ev.kind == 0) {
       ev.units = wk.nodes * nchk;
-      ev.bytes = c->cycle_bytes(wk.nodes, wk.coef, cycle_launches(c, nchk));
+      ev.bytes = c->cycle_bytes(wk.nodes, wk.coef, nchk);
     } else {
       ev.units = wk.nodes;
       ev.bytes = c->resid_bytes(wk.nodes, wk.coef, wk.rcoef, true);
@@ -2878,8 +2891,9 @@ extern "C" pg_status pg_autotune(pg_ctx* c, int32_t nsteps, const char* cache_pa
     PG_TRY(trial(o, &t));
     if (t < best_t) { best_t = t; best = o; }
   }
-  for (int f = 1; f <= 2 && best.ordering == PG_ORDER_RED_BLACK; ++f) {
-    if (f == best.sweeps_per_launch) continue;
+  for (int f : {1, 2, kTbSweeps}) {
+    if (f == best.sweeps_per_launch || best.ordering != PG_ORDER_RED_BLACK) continue;
+    if (f == kTbSweeps && best.precision != PG_PREC_FP32_REFINE) continue;
     pg_options o = best;
     o.sweeps_per_launch = f;
     double t;

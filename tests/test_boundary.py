@@ -103,10 +103,15 @@ def test_options_validation():
     assert (o.h, o.tol, o.omega, o.check_every) == (10e-12, 1e-6, 1.0, 8)
     for k, v in (("omega", 2.0), ("omega", 0.0), ("h", 0.0), ("h", float("nan")), ("tol", -1.0),
                  ("max_sweeps", 0), ("check_every", 0), ("precision", 5), ("ordering", 3),
-                 ("tile_rows", 12), ("lookahead", 9), ("recurrence", 2)):
+                 ("tile_rows", 12), ("lookahead", 9), ("recurrence", 2), ("sweeps_per_launch", 3),
+                 ("sweeps_per_launch", 5)):
         bad = pg.default_options(**{k: v})
         st, msg = pg.validate_options(bad)
         assert st == -1, (k, v)
+    # four sweeps per launch run FP32 sweeps only
+    st, msg = pg.validate_options(pg.default_options(sweeps_per_launch=4))
+    assert st == -1 and "FP32" in msg
+    assert pg.validate_options(pg.default_options(sweeps_per_launch=4, precision=pg.PG_PREC_FP32_REFINE))[0] == 0
     # the three-level recurrence runs with plain launches only
     st, msg = pg.validate_options(pg.default_options(recurrence=pg.PG_REC_THREE_LEVEL, graphs=1))
     assert st == -8 and "plain launches" in msg

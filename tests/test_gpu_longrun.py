@@ -33,7 +33,7 @@ WORKERS = 16  # CPU share of one GPU on the test boxes
 
 def _opts(name, prec):
     tol = PARITY_TOL[name]
-    t = settings(name, tol)
+    t = settings(name, tol, prec)
     return dict(precision=prec, tol=tol, omega=t["omega"], check_every=t["check_every"], graphs=t["graphs"],
                 max_sweeps=200000, tile_rows=t["tile_rows"], scen_block=t["scen_block"],
                 sweeps_per_launch=t["sweeps_per_launch"])

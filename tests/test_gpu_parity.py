@@ -230,6 +230,47 @@ def test_two_sweeps_per_launch_equal_two_launches(case):
     assert err <= PARITY_V
 
 
+@pytest.mark.parametrize("case", ["rlc_two_layer_rows8", "one_layer_rows16", "three_layer_rows4", "ragged_rows4",
+                                  "unsupported_falls_back"])
+def test_four_sweeps_per_launch_equal_four_launches(case):
+    """Four red-black sweeps per launch (temporal blocking: the tile with an 8-node halo staged
+    once, four sweeps on chip) give the voltages of four separate sweeps bit for bit: several
+    tiles in x and y so the halos overlap neighbouring tiles, ragged edges, cycle lengths that
+    leave one-sweep launches at the end of a cycle, the RLC grid's branch currents, and a
+    context whose tile groups have no four-sweep kernel (it sweeps once per launch)."""
+    lg4 = (1.0, 2.0, 4.0, 8.0)
+    if case == "rlc_two_layer_rows8":
+        w, rows, chk = small_rlc(side=300, seed=71, steps=30), 8, 16
+        w.pulses[0][0] = compressed(w.pulses[0][0], start=0.02, width=0.3)
+    elif case == "one_layer_rows16":
+        w, rows, chk = small_multilayer(side=260, seed=72, nl=1, layer_g=lg4[:1], pad_every=16, steps=20), 16, 10
+        w.pulses[0][0] = compressed(w.pulses[0][0], start=0.25, width=1.0)
+    elif case == "three_layer_rows4":
+        w, rows, chk = small_multilayer(side=140, seed=73, nl=3, pad_every=32, steps=20), 4, 9
+        w.pulses[0][0] = compressed(w.pulses[0][0], start=0.08, width=1.0)
+    elif case == "ragged_rows4":
+        w, rows, chk = small_multilayer(side=77, seed=74, nl=2, layer_g=lg4[:2], pad_every=16, steps=20), 4, 7
+        w.pulses[0][0] = compressed(w.pulses[0][0], start=0.25, width=1.0)
+    else:  # three layers with 8 tile rows: no four-sweep kernel for that shape
+        w, rows, chk = small_multilayer(side=100, seed=75, nl=3, pad_every=32, steps=20), 8, 8
+        w.pulses[0][0] = compressed(w.pulses[0][0], start=0.08, width=1.0)
+    steps = w.steps if w.steps <= 30 else 30
+    res = {}
+    for spl in (1, 4):
+        say(f"[gpu] four sweeps per launch case={case} sweeps_per_launch={spl}")
+        with gpu_context(w, precision=pg.PG_PREC_FP32_REFINE, tol=1e-11, omega=1.6, tile_rows=rows,
+                         check_every=chk, sweeps_per_launch=spl, max_sweeps=50000) as ctx:
+            ctx.step(steps)
+            res[spl] = (ctx.read_voltages(0, 0), ctx.read_inductor_currents(0, 0), ctx.stats())
+    assert np.array_equal(res[1][0], res[4][0]), np.max(np.abs(res[1][0] - res[4][0]))
+    assert np.array_equal(res[1][1], res[4][1])
+    assert res[1][2]["sweeps"] == res[4][2]["sweeps"]
+    Vref, _ = oracle_run(w.meshes[0], w.pulses[0][0], w.h, steps)
+    err = np.max(np.abs(res[4][0] - Vref[-1]))
+    say(f"  sweeps={res[4][2]['sweeps']} err={err:.3e}")
+    assert err <= PARITY_V
+
+
 def test_netlist_upload_equals_mesh_upload():
     """An RLC grid uploaded as the oracle's branch list (pg_upload_netlist) steps bit for bit like
     the same grid uploaded as a mesh, and both match the oracle."""

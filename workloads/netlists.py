@@ -261,16 +261,17 @@ class NetWorkload:
         return sum(n.n * len(p) for n, p in zip(self.nets, self.pulses))
 
 
-def graph1(side=1024, steps=1000) -> NetWorkload:
+def graph1(side=1024, steps=1000, shuffle=False) -> NetWorkload:
     """A 3-layer irregular RC grid at the scale of the 3-layer 1024 x 1024 mesh: 3,145,728 nodes,
     10 % of segments dropped, 5 % diagonal straps, 5 % coupling capacitors, 1 % leaks, 5 S vias
     every 4 nodes, 10 S pads every 64 nodes on the top layer alternating between 1.0 V and
-    1.05 V, 30 % of the bottom layer pulsing; natural (geometric) node numbering.  With two supply
-    voltages v = 1.0 V is not a steady state, so the transient starts from the DC operating point
-    at t = 0 (no load is on at t = 0)."""
+    1.05 V, 30 % of the bottom layer pulsing; natural (geometric) node numbering, or with
+    shuffle=True node ids in random order (as a netlist extracted from a layout may number
+    them).  With two supply voltages v = 1.0 V is not a steady state, so the transient starts
+    from the DC operating point at t = 0 (no load is on at t = 0)."""
     net, scen = irregular_grid(side=side, nl=3, seed=41, via_every=4, pad_every=64, fraction=0.3,
-                               shuffle=False, start_max=500 * PS)
-    return NetWorkload(f"graph_irregular_3x{side}", [net], [scen], 10 * PS, steps,
+                               shuffle=shuffle, start_max=500 * PS)
+    return NetWorkload(f"graph_irregular_3x{side}" + ("_shuffled" if shuffle else ""), [net], [scen], 10 * PS, steps,
                        note="irregular 3-layer RC netlist, colour-ordered sweeps", dc_start=True)
 
 
