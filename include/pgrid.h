@@ -95,8 +95,8 @@ typedef struct pg_options {
                            Two sweeps stage a wider halo and recompute its rings; four (FP32
                            sweeps only: PG_PREC_FP32_REFINE, else PG_ERR_INVALID_ARG) stage the
                            tile with an 8-node halo and its coefficients once and run all four
-                           sweeps on chip, on single-scenario meshes of 1-2 layers with 4, 8 or
-                           16 tile rows or 3 layers with 4 (otherwise one sweep per launch).  A
+                           sweeps on chip, on single-scenario meshes of 1 layer with 4, 8 or 16
+                           tile rows or 2 layers with 4 or 8 (otherwise one sweep per launch).  A
                            launch moves the bytes of about one sweep.  Results are identical.
                            Jacobi ordering always uses 1 */
   int32_t recurrence;   /* PG_REC_TWO_LEVEL (default) or PG_REC_THREE_LEVEL (general netlists only) */

@@ -85,23 +85,52 @@ __global__ __launch_bounds__(kTbThreads) void k_sweep_tb(const Tile* __restrict_
   }
   __syncthreads();
 
+  // Each pair update first issues all its LDS reads, then computes and writes; a pair outside
+  // the half-sweep's box reads its own word in place of every neighbour and writes nothing, so
+  // the reads carry no branch and the compiler can run them ahead of the previous pair's update.
+  // Within a half-sweep the words written (this colour) are read only by the thread that owns
+  // them.  The update is relax()'s expression, term for term.
+  const T* __restrict__ fs = reinterpret_cast<const T*>(&sd[0][0][0]);  // element k of pair q at 2q + k
+  T* __restrict__ fw = reinterpret_cast<T*>(&sd[0][0][0]);
 #pragma unroll
   for (int i = 1; i <= 2 * K; ++i) {
     const int colour = (i - 1) & 1;
 #pragma unroll
     for (int j = 0; j < J; ++j) {
       const int dc = colour ? (dist[j] >> 8) : (dist[j] & 0xff);
-      if (dc > H - i) continue;  // outside this half-sweep's box, or outside the mesh
+      const bool ok = dc <= H - i;  // inside this half-sweep's box (never for nodes outside the mesh)
       const int l = at[j] >> 16, hy = (at[j] >> 8) & 0xff, hp = at[j] & 0xff;
-      const int gy = y0 - H + hy;
-      const int ec = ((gy + l) & 1) ^ colour;  // element of the pair with this colour
-      const T nv = relax<T, NL, HY, HP>(sd, l, hy, hp, ec, node_of(pr[j], ec), omega);
+      const int q = (l * HY + hy) * HP + hp;
+      const int e = ((y0 - H + hy + l) & 1) ^ colour;  // element of the pair with this colour
+      const int me = 2 * q + e;
+      const V2<T> own = sd[l][hy][hp];
+      // the one in-plane x neighbour in another pair: the east pair's element 0 for e = 1, the
+      // west pair's element 1 for e = 0
+      const T side = fs[ok ? (e ? 2 * q + 2 : 2 * q - 1) : me];
+      const T nn = fs[ok ? me + 2 * HP : me];
+      const T ss = fs[ok ? me - 2 * HP : me];
+      T uu = T(0), dd = T(0);
+      if (NL > 1) {
+        uu = fs[ok && l < NL - 1 ? me + 2 * HY * HP : me];
+        dd = fs[ok && l > 0 ? me - 2 * HY * HP : me];
+      }
+      if (!ok) continue;
+      const NodeCoef<T> k = node_of(pr[j], e);
+      const T old = pick(own, e);
+      const T east = e ? side : own.y;
+      const T west = e ? own.x : side;
+      T acc = k.r + k.e * east + k.w * west + k.n * nn + k.s * ss;
+      if (NL > 1) {
+        if (l < NL - 1) acc += k.u * uu;
+        if (l > 0) acc += k.d * dd;
+      }
+      const T nv = old + omega * (k.inv * acc - old);
       if (i < 2 * K) {
-        put(sd[l][hy][hp], ec, nv);
+        fw[me] = nv;
       } else {  // the tile's black nodes: write the pair with its red partner's final value
-        V2<T> out = sd[l][hy][hp];
-        put(out, ec, nv);
-        st2(dnew, l * P + (int64_t)gy * X + (x0 - H + 2 * hp), out);
+        V2<T> out = own;
+        put(out, e, nv);
+        st2(dnew, l * P + (int64_t)(y0 - H + hy) * X + (x0 - H + 2 * hp), out);
       }
     }
     if (i < 2 * K) __syncthreads();
@@ -117,12 +146,12 @@ void tb_t(const Tile* tiles, int ntiles, const GridDesc* grids, const Ctl& c, in
 
 }  // namespace
 
-// The shapes instantiated below (their staged pairs' registers fit without spilling): one or two
-// layers with 4, 8 or 16 tile rows, three layers with 4.
+// The shapes instantiated below (their staged pairs' registers fit without spilling): one layer
+// with 4, 8 or 16 tile rows, two layers with 4 or 8.
 bool sweep_tb_supported(bool fp32, bool multi, int ordering, int nl, int tile_rows) {
   if (!fp32 || multi || ordering != 0) return false;  // FP32 red-black sweeps of single-scenario grids
-  return ((nl == 1 || nl == 2) && (tile_rows == 4 || tile_rows == 8 || tile_rows == 16)) ||
-         (nl == 3 && tile_rows == 4);
+  return (nl == 1 && (tile_rows == 4 || tile_rows == 8 || tile_rows == 16)) ||
+         (nl == 2 && (tile_rows == 4 || tile_rows == 8));
 }
 
 hipError_t launch_sweep_tb(int nl, int tile_rows, const Tile* tiles, int ntiles, const GridDesc* grids,
@@ -134,8 +163,6 @@ hipError_t launch_sweep_tb(int nl, int tile_rows, const Tile* tiles, int ntiles,
     case 116: tb_t<1, 16>(tiles, ntiles, grids, c, din, zero_in, omega, s); break;
     case 204: tb_t<2, 4>(tiles, ntiles, grids, c, din, zero_in, omega, s); break;
     case 208: tb_t<2, 8>(tiles, ntiles, grids, c, din, zero_in, omega, s); break;
-    case 216: tb_t<2, 16>(tiles, ntiles, grids, c, din, zero_in, omega, s); break;
-    case 304: tb_t<3, 4>(tiles, ntiles, grids, c, din, zero_in, omega, s); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

@@ -230,7 +230,7 @@ def test_two_sweeps_per_launch_equal_two_launches(case):
     assert err <= PARITY_V
 
 
-@pytest.mark.parametrize("case", ["rlc_two_layer_rows8", "one_layer_rows16", "three_layer_rows4", "ragged_rows4",
+@pytest.mark.parametrize("case", ["rlc_two_layer_rows8", "one_layer_rows16", "two_layer_rows4", "ragged_rows4",
                                   "unsupported_falls_back"])
 def test_four_sweeps_per_launch_equal_four_launches(case):
     """Four red-black sweeps per launch (temporal blocking: the tile with an 8-node halo staged
@@ -245,14 +245,14 @@ def test_four_sweeps_per_launch_equal_four_launches(case):
     elif case == "one_layer_rows16":
         w, rows, chk = small_multilayer(side=260, seed=72, nl=1, layer_g=lg4[:1], pad_every=16, steps=20), 16, 10
         w.pulses[0][0] = compressed(w.pulses[0][0], start=0.25, width=1.0)
-    elif case == "three_layer_rows4":
-        w, rows, chk = small_multilayer(side=140, seed=73, nl=3, pad_every=32, steps=20), 4, 9
+    elif case == "two_layer_rows4":
+        w, rows, chk = small_multilayer(side=140, seed=73, nl=2, layer_g=lg4[:2], pad_every=32, steps=20), 4, 9
         w.pulses[0][0] = compressed(w.pulses[0][0], start=0.08, width=1.0)
     elif case == "ragged_rows4":
         w, rows, chk = small_multilayer(side=77, seed=74, nl=2, layer_g=lg4[:2], pad_every=16, steps=20), 4, 7
         w.pulses[0][0] = compressed(w.pulses[0][0], start=0.25, width=1.0)
-    else:  # three layers with 8 tile rows: no four-sweep kernel for that shape
-        w, rows, chk = small_multilayer(side=100, seed=75, nl=3, pad_every=32, steps=20), 8, 8
+    else:  # three layers: no four-sweep kernel for that shape
+        w, rows, chk = small_multilayer(side=100, seed=75, nl=3, pad_every=32, steps=20), 4, 8
         w.pulses[0][0] = compressed(w.pulses[0][0], start=0.08, width=1.0)
     steps = w.steps if w.steps <= 30 else 30
     res = {}
