@@ -157,6 +157,7 @@ COUNTERS = {
     "config1_hbm": os.path.join(ROOT, "profiles", "k_sweep_rb_rc3x2048_counters.json"),
     "config3a": os.path.join(ROOT, "profiles", "k_sweep_rb_multi_batch256x256_counters.json"),
     "graph1": os.path.join(ROOT, "profiles", "k_graph_sweep_irregular3x1024_counters.json"),
+    "config2": os.path.join(ROOT, "profiles", "k_sweep_tb_rlc2x512_counters.json"),
 }
 
 
@@ -169,9 +170,8 @@ def counter_traffic(name, kernel, avg_alg_bytes):
         summ = json.load(open(COUNTERS[name]))
     except (KeyError, OSError):
         return None
-    src = open(os.path.join(ROOT, summ.get("source", "paper_1409_7166_amd/csrc/kernels.hip")), "rb").read()
-    if hashlib.sha256(src).hexdigest()[:16] != summ.get("source_sha256_16", summ.get("kernels_hip_sha256_16")) \
-            or kernel not in summ:
+    src = b"".join(open(os.path.join(ROOT, f), "rb").read() for f in summ["sources"])
+    if hashlib.sha256(src).hexdigest()[:16] != summ["sources_sha256_16"] or kernel not in summ:
         return None
     full, cold = summ[kernel]["full_launch"], summ[kernel]["cold_start_launch"]
     a_full, a_cold = full["algorithmic_bytes"], cold["algorithmic_bytes"]
@@ -197,10 +197,12 @@ def is_netlist(w):
 
 
 def sweep_kernel_name(w, sweeps_per_launch):
-    """The red-black sweep kernel(s) the workload runs: two fused sweeps per launch, or one per
-    launch with scenario blocks for multi-scenario grids; the colour kernel for netlists."""
+    """The red-black sweep kernel(s) the workload runs: four or two fused sweeps per launch, or
+    one per launch with scenario blocks for multi-scenario grids; the colour kernel for netlists."""
     if is_netlist(w):
         return "k_graph_sweep"
+    if sweeps_per_launch == 4:
+        return "k_sweep_tb"
     if sweeps_per_launch == 2:
         return "k_sweep_rb2"
     multi = {len(p) > 1 for p in w.pulses}
