@@ -79,11 +79,11 @@ def parse():
 # (not for the most node-updates: a larger omega needs more sweeps and inflates node-updates/s).
 TUNED = {
     "config0": dict(omega=1.6, check_every=8, graphs=1, resident=1),
-    "config1": dict(omega=1.6, check_every=8, tile_rows=16, graphs=0),
+    "config1": dict(omega=1.6, check_every=8, tile_rows=16, graphs=0, sweeps_per_launch_fp32=2),
     "config1_hbm": dict(omega=1.6, check_every=8, tile_rows=16, graphs=0),
     "config2": dict(omega=1.8, check_every=16, graphs=0, sweeps_per_launch_fp32=4),
     "config3a": dict(omega=1.7, check_every=8, tile_rows=16, scen_block=16, graphs=0),
-    "config3b": dict(omega=1.6, check_every=8, graphs=0),
+    "config3b": dict(omega=1.6, check_every=8, graphs=0, sweeps_per_launch_fp32=4),
     "config4": dict(omega=1.6, check_every=6, graphs=0),
     "graph1": dict(omega=1.6, check_every=6, graphs=0),
     "graph1_shuffled": dict(omega=1.6, check_every=6, graphs=0),
@@ -153,7 +153,7 @@ GOLDEN = {
 
 # rocprofv3 FETCH_SIZE / WRITE_SIZE summaries of the FP32 sweep kernel, per workload
 COUNTERS = {
-    "config1": os.path.join(ROOT, "profiles", "k_sweep_rb_rc3x1024_counters.json"),
+    "config1": os.path.join(ROOT, "profiles", "k_sweep_tb_rc3x1024_counters.json"),
     "config1_hbm": os.path.join(ROOT, "profiles", "k_sweep_rb_rc3x2048_counters.json"),
     "config3a": os.path.join(ROOT, "profiles", "k_sweep_rb_multi_batch256x256_counters.json"),
     "graph1": os.path.join(ROOT, "profiles", "k_graph_sweep_irregular3x1024_counters.json"),
@@ -196,12 +196,15 @@ def is_netlist(w):
     return hasattr(w, "nets")
 
 
-def sweep_kernel_name(w, sweeps_per_launch):
-    """The red-black sweep kernel(s) the workload runs: four or two fused sweeps per launch, or
-    one per launch with scenario blocks for multi-scenario grids; the colour kernel for netlists."""
+def sweep_kernel_name(w, sweep_launch):
+    """The red-black sweep kernel(s) the workload runs, from (sweeps per launch, staged once) as
+    the library reports them: fused sweeps staged once per launch, two fused sweeps recomputing
+    halo rings, or one per launch with scenario blocks for multi-scenario grids; the colour
+    kernel for netlists."""
+    sweeps_per_launch, staged = sweep_launch
     if is_netlist(w):
         return "k_graph_sweep"
-    if sweeps_per_launch == 4:
+    if staged:
         return "k_sweep_tb"
     if sweeps_per_launch == 2:
         return "k_sweep_rb2"
@@ -313,6 +316,7 @@ def run_gpu(w, name, steps, warmup, precision, tol, omega, check_every, tile_row
     st = ctx.stats()
     kt = ctx.kernel_times()
     st["options"] = ctx.options()
+    st["sweep_launch"] = ctx.sweep_launch_info() if not is_netlist(w) else (1, False)
     err = verify(ctx, w, name) if do_verify else None
     ctx.close()
     return elapsed, st, kt, err
@@ -447,19 +451,20 @@ def measure(name, prec, tol, steps, args, do_verify=True):
                                    spl_opt, args.recurrence, do_verify and not args.no_verify, resident)
     nodes = w.nodes
     value = st["node_updates"] / elapsed
-    spl = st["options"]["sweeps_per_launch"] or 1
+    spl = st["sweep_launch"][0]
     roof = None
     if kt["sweep_launches"]:
         sweep_s = kt["sweep_ms"] * 1e-3
         achieved = kt["sweep_bytes"] / sweep_s
         per_launch = kt["sweep_bytes"] / kt["sweep_launches"]
-        traffic = counter_traffic(name, sweep_kernel_name(w, spl), per_launch) if prec == "fp32+ref" else None
+        traffic = counter_traffic(name, sweep_kernel_name(w, st["sweep_launch"]), per_launch) \
+            if prec == "fp32+ref" else None
         roof = {"bound": "hbm", "achieved": achieved / 1e9, "peak": HBM_PEAK / 1e9, "unit": "GB/s",
                 "frac": achieved / HBM_PEAK, "traffic": traffic,
                 # "mall": the sweep's working set fits in the 256 MB Infinity Cache, so part of its
                 # traffic may be served there; "hbm": it does not, and the sweeps stream from HBM
                 "regime": "mall" if per_launch <= MALL_BYTES else "hbm",
-                "kernel": sweep_kernel_name(w, spl), "timed_launches": kt["sweep_launches"],
+                "kernel": sweep_kernel_name(w, st["sweep_launch"]), "timed_launches": kt["sweep_launches"],
                 "avg_launch_us": kt["sweep_ms"] * 1e3 / kt["sweep_launches"],
                 "bytes_per_launch": per_launch}
     out = {

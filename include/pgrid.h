@@ -388,6 +388,13 @@ pg_status pg_grid_info(const pg_ctx* ctx, int32_t grid, int32_t* nx, int32_t* ny
  * without timing.  *chosen (may be NULL) receives the options set. */
 pg_status pg_autotune(pg_ctx* ctx, int32_t nsteps, const char* cache_path, pg_options* chosen);
 
+/* How the mesh sweeps run under the current options (the context's device data are built first if
+ * the grids or options changed, as pg_step does): *sweeps_per_launch receives the sweeps each
+ * mesh sweep launch performs (1, 2 or 4: four only where every tile group has the four-sweep
+ * kernel, else one), *staged 1 if every fused launch stages its tiles once and sweeps on chip,
+ * 0 if some recompute halo rings from memory or the sweeps run one per launch. */
+pg_status pg_sweep_launch_info(pg_ctx* ctx, int32_t* sweeps_per_launch, int32_t* staged);
+
 /* Size of a general-netlist grid: trivial nodes, colours, storage slots, off-diagonal entries
  * of M (both directions) and L branches.  PG_ERR_INVALID_ARG for a mesh grid. */
 pg_status pg_graph_info(const pg_ctx* ctx, int32_t grid, int32_t* n_nodes, int32_t* n_colors, int64_t* n_slots,

@@ -137,34 +137,42 @@ __global__ __launch_bounds__(kTbThreads) void k_sweep_tb(const Tile* __restrict_
   }
 }
 
-template <int NL, int TY>
+template <int K, int NL, int TY>
 void tb_t(const Tile* tiles, int ntiles, const GridDesc* grids, const Ctl& c, int din, int zero_in, double omega,
           hipStream_t s) {
-  hipLaunchKernelGGL((k_sweep_tb<float, NL, TY, kTbSweeps>), dim3(xcd_blocks(ntiles)), dim3(kTbThreads), 0, s,
-                     tiles, ntiles, grids, c, din, zero_in, (float)omega);
+  hipLaunchKernelGGL((k_sweep_tb<float, NL, TY, K>), dim3(xcd_blocks(ntiles)), dim3(kTbThreads), 0, s, tiles,
+                     ntiles, grids, c, din, zero_in, (float)omega);
 }
+
+// The shapes instantiated below, those whose staged pairs' registers fit without spilling:
+// k = 4 with one layer and 4, 8 or 16 tile rows or two layers and 4 or 8; k = 2 with one to three
+// layers and 4, 8 or 16 tile rows or four layers and 4 or 8.
+constexpr int kTbShapes[] = {4104, 4108, 4116, 4204, 4208,
+                             2104, 2108, 2116, 2204, 2208, 2216, 2304, 2308, 2316, 2404, 2408};
 
 }  // namespace
 
-// The shapes instantiated below (their staged pairs' registers fit without spilling): one layer
-// with 4, 8 or 16 tile rows, two layers with 4 or 8.
-bool sweep_tb_supported(bool fp32, bool multi, int ordering, int nl, int tile_rows) {
+bool sweep_tb_supported(bool fp32, bool multi, int ordering, int nl, int tile_rows, int k) {
   if (!fp32 || multi || ordering != 0) return false;  // FP32 red-black sweeps of single-scenario grids
-  return (nl == 1 && (tile_rows == 4 || tile_rows == 8 || tile_rows == 16)) ||
-         (nl == 2 && (tile_rows == 4 || tile_rows == 8));
+  for (int sh : kTbShapes)
+    if (sh == k * 1000 + nl * 100 + tile_rows) return true;
+  return false;
 }
 
-hipError_t launch_sweep_tb(int nl, int tile_rows, const Tile* tiles, int ntiles, const GridDesc* grids,
+hipError_t launch_sweep_tb(int k, int nl, int tile_rows, const Tile* tiles, int ntiles, const GridDesc* grids,
                            const Ctl& c, int din, int zero_in, double omega, hipStream_t s) {
   if (ntiles <= 0) return hipSuccess;
-  switch (nl * 100 + tile_rows) {
-    case 104: tb_t<1, 4>(tiles, ntiles, grids, c, din, zero_in, omega, s); break;
-    case 108: tb_t<1, 8>(tiles, ntiles, grids, c, din, zero_in, omega, s); break;
-    case 116: tb_t<1, 16>(tiles, ntiles, grids, c, din, zero_in, omega, s); break;
-    case 204: tb_t<2, 4>(tiles, ntiles, grids, c, din, zero_in, omega, s); break;
-    case 208: tb_t<2, 8>(tiles, ntiles, grids, c, din, zero_in, omega, s); break;
+#define PG_TB(K, NL, TY)                                                    \
+  case K * 1000 + NL * 100 + TY:                                            \
+    tb_t<K, NL, TY>(tiles, ntiles, grids, c, din, zero_in, omega, s);       \
+    break;
+  switch (k * 1000 + nl * 100 + tile_rows) {
+    PG_TB(4, 1, 4) PG_TB(4, 1, 8) PG_TB(4, 1, 16) PG_TB(4, 2, 4) PG_TB(4, 2, 8)
+    PG_TB(2, 1, 4) PG_TB(2, 1, 8) PG_TB(2, 1, 16) PG_TB(2, 2, 4) PG_TB(2, 2, 8) PG_TB(2, 2, 16)
+    PG_TB(2, 3, 4) PG_TB(2, 3, 8) PG_TB(2, 3, 16) PG_TB(2, 4, 4) PG_TB(2, 4, 8)
     default: return hipErrorInvalidValue;
   }
+#undef PG_TB
   return hipGetLastError();
 }
 

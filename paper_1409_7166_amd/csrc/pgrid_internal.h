@@ -269,11 +269,12 @@ hipError_t launch_sweep2(bool fp32, int nl, int tile_rows, const Tile* tiles, in
 hipError_t launch_sweep(bool fp32, bool multi, int ordering, int nl, int tile_rows, const Tile* tiles,
                         int ntiles, const GridDesc* grids, const Ctl& c, int din, int zero_in,
                         double omega, hipStream_t s);
-// kTbSweeps red-black sweeps in one launch by temporal blocking (kernels_tb.hip), for the tile
-// groups sweep_tb_supported accepts (ordering: 0 red-black); reads d[din], writes d[din ^ 1].
+// k = 2 or kTbSweeps red-black sweeps in one launch by temporal blocking (kernels_tb.hip), for
+// the tile groups sweep_tb_supported accepts (ordering: 0 red-black); reads d[din], writes
+// d[din ^ 1].
 constexpr int kTbSweeps = 4;
-bool sweep_tb_supported(bool fp32, bool multi, int ordering, int nl, int tile_rows);
-hipError_t launch_sweep_tb(int nl, int tile_rows, const Tile* tiles, int ntiles, const GridDesc* grids,
+bool sweep_tb_supported(bool fp32, bool multi, int ordering, int nl, int tile_rows, int k);
+hipError_t launch_sweep_tb(int k, int nl, int tile_rows, const Tile* tiles, int ntiles, const GridDesc* grids,
                            const Ctl& c, int din, int zero_in, double omega, hipStream_t s);
 // count_step: 1 statistics and clock, 2 clock only, 0 neither; begin_next opens the next step.
 hipError_t launch_step_end(const Ctl& c, int G, int count_step, int begin_next, double h, const SourceTable& src,

@@ -759,7 +759,7 @@ pg_status prepare(pg_ctx* c) {
   c->ntiles_all = (int)tiles.size();
   c->tb_ok = true;
   for (auto& grp : c->tile_groups)
-    c->tb_ok = c->tb_ok && sweep_tb_supported(fp32_mode(c), grp.multi, c->opt.ordering, grp.nl, TY);
+    c->tb_ok = c->tb_ok && sweep_tb_supported(fp32_mode(c), grp.multi, c->opt.ordering, grp.nl, TY, kTbSweeps);
   c->all_nodes = 0;
   c->all_coef = c->all_rcoef = 0;
   c->graph_nodes = c->graph_coef = c->graph_rcoef = c->graph_entries = 0;
@@ -1075,12 +1075,16 @@ pg_status launch_sweeps(pg_ctx* c, int nchk) {
       const int zero_in = s == 0 ? 1 : 0;
       hipError_t e;
       if (spl == kTbSweeps && nchk - s >= kTbSweeps) {
-        e = launch_sweep_tb(grp.nl, c->tile_rows, T + grp.off, grp.count, (const GridDesc*)c->grid_desc.p, c->ctl,
-                            j & 1, zero_in, c->opt.omega, c->stream);
+        e = launch_sweep_tb(kTbSweeps, grp.nl, c->tile_rows, T + grp.off, grp.count,
+                            (const GridDesc*)c->grid_desc.p, c->ctl, j & 1, zero_in, c->opt.omega, c->stream);
         s += kTbSweeps;
-      } else if (spl == 2 && nchk - s >= 2) {
-        e = launch_sweep2(fp32_mode(c), grp.nl, c->tile_rows, T + grp.off, grp.count,
-                          (const GridDesc*)c->grid_desc.p, c->ctl, j & 1, zero_in, c->opt.omega, c->stream);
+      } else if (spl == 2 && nchk - s >= 2) {  // staged once where the group has the kernel, else rings
+        if (sweep_tb_supported(fp32_mode(c), grp.multi, c->opt.ordering, grp.nl, c->tile_rows, 2))
+          e = launch_sweep_tb(2, grp.nl, c->tile_rows, T + grp.off, grp.count, (const GridDesc*)c->grid_desc.p,
+                              c->ctl, j & 1, zero_in, c->opt.omega, c->stream);
+        else
+          e = launch_sweep2(fp32_mode(c), grp.nl, c->tile_rows, T + grp.off, grp.count,
+                            (const GridDesc*)c->grid_desc.p, c->ctl, j & 1, zero_in, c->opt.omega, c->stream);
         s += 2;
       } else {
         e = launch_sweep(fp32_mode(c), grp.multi, c->opt.ordering, grp.nl, c->tile_rows, T + grp.off, grp.count,
@@ -1953,6 +1957,20 @@ pg_status pg_upload_mesh(pg_ctx* c, const pg_mesh* m, int32_t n_scen, int32_t* g
   PG_TRY(alloc_ctl(c));
   c->dirty = true;
   if (grid_id) *grid_id = (int32_t)c->grids.size() - 1;
+  return PG_OK;
+}
+
+pg_status pg_sweep_launch_info(pg_ctx* c, int32_t* sweeps_per_launch_out, int32_t* staged) {
+  if (!c) return PG_ERR_INVALID_ARG;
+  if (!sweeps_per_launch_out || !staged) return set_err(c, PG_ERR_INVALID_ARG, "output pointers are NULL");
+  HIP_TRY(c, hipSetDevice(c->device));
+  PG_TRY(prepare(c));
+  const int spl = sweeps_per_launch(c);
+  bool all = spl > 1 && !c->tile_groups.empty();
+  for (auto& grp : c->tile_groups)
+    all = all && sweep_tb_supported(fp32_mode(c), grp.multi, c->opt.ordering, grp.nl, c->tile_rows, spl);
+  *sweeps_per_launch_out = spl;
+  *staged = all ? 1 : 0;
   return PG_OK;
 }
 

@@ -133,6 +133,7 @@ EXPORTS = {
     "pg_graph_info": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_int32),
                                 C.POINTER(C.c_int64), C.POINTER(C.c_int64), C.POINTER(C.c_int32)]),
     "pg_autotune": (C.c_int, [C.c_void_p, C.c_int32, C.c_char_p, C.POINTER(Options)]),
+    "pg_sweep_launch_info": (C.c_int, [C.c_void_p, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
     "pg_read_voltages": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.POINTER(C.c_double), C.c_int64]),
     "pg_read_voltages_dev": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_void_p, C.c_int64]),
     "pg_read_inductor_currents": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.POINTER(C.c_double), C.c_int64]),
@@ -412,6 +413,12 @@ class Context:
         self._check(lib().pg_graph_info(self._h, grid, C.byref(n), C.byref(nc), C.byref(ns), C.byref(nnz),
                                         C.byref(ni)))
         return GraphShape(n.value, nc.value, ns.value, nnz.value, ni.value)
+
+    def sweep_launch_info(self) -> tuple:
+        """(sweeps per mesh sweep launch, whether every fused launch stages its tiles once)."""
+        spl, staged = C.c_int32(), C.c_int32()
+        self._check(lib().pg_sweep_launch_info(self._h, C.byref(spl), C.byref(staged)))
+        return spl.value, bool(staged.value)
 
     def _n_nodes(self, grid: int) -> int:
         m = self.meshes[grid]

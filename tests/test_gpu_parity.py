@@ -191,11 +191,14 @@ def test_scenario_blocks_on_layered_meshes(prec, ordering, rows, block, nl):
         assert err <= PARITY_V
 
 
-@pytest.mark.parametrize("case", ["rc32_fp64", "three_layer_fp32", "blocks_fp32", "four_layer_fp64"])
+@pytest.mark.parametrize("case", ["rc32_fp64", "three_layer_fp32", "blocks_fp32", "four_layer_fp64",
+                                  "rlc_fp32_rows8"])
 def test_two_sweeps_per_launch_equal_two_launches(case):
-    """Fusing two red-black sweeps into one launch (four-node halo, recomputed rings) gives the
-    voltages of two separate sweeps bit for bit, including an odd cycle length (one single-sweep
-    launch at the end of each cycle), ragged tiles and scenario blocks."""
+    """Fusing two red-black sweeps into one launch gives the voltages of two separate sweeps bit
+    for bit, including an odd cycle length (one single-sweep launch at the end of each cycle),
+    ragged tiles and scenario blocks: FP32 sweeps of single-scenario meshes stage the tile with a
+    four-node halo once (three_layer_fp32, rlc_fp32_rows8), the others recompute the halo's rings
+    (FP64, scenario blocks)."""
     lg4 = (1.0, 2.0, 4.0, 8.0)
     if case == "rc32_fp64":
         w, prec, rows, chk, block = config0(), pg.PG_PREC_FP64, 8, 7, 0
@@ -209,10 +212,14 @@ def test_two_sweeps_per_launch_equal_two_launches(case):
                                                    pad_every=16).pulses[0][0], start=0.25, width=1.0)
                        for s in range(5)]
         prec, rows, chk, block = pg.PG_PREC_FP32_REFINE, 4, 5, 3
-    else:
+    elif case == "four_layer_fp64":
         w = small_multilayer(side=77, seed=82, nl=4, layer_g=lg4, pad_every=16, steps=20)
         w.pulses[0][0] = compressed(w.pulses[0][0], start=0.25, width=1.0)
         prec, rows, chk, block = pg.PG_PREC_FP64, 4, 9, 0
+    else:
+        w = small_rlc(side=150, seed=83, steps=20)
+        w.pulses[0][0] = compressed(w.pulses[0][0], start=0.02, width=0.3)
+        prec, rows, chk, block = pg.PG_PREC_FP32_REFINE, 8, 7, 0
     steps = 20
     res = {}
     for spl in (1, 2):
@@ -221,6 +228,8 @@ def test_two_sweeps_per_launch_equal_two_launches(case):
                          scen_block=block, sweeps_per_launch=spl) as ctx:
             ctx.step(steps)
             res[spl] = ([ctx.read_voltages(0, s) for s in range(len(w.pulses[0]))], ctx.stats())
+            staged = case in ("three_layer_fp32", "rlc_fp32_rows8")
+            assert ctx.sweep_launch_info() == ((2, staged) if spl == 2 else (1, False))
     for a, b in zip(res[1][0], res[2][0]):
         assert np.array_equal(a, b), np.max(np.abs(a - b))
     assert res[1][1]["sweeps"] == res[2][1]["sweeps"]
@@ -262,6 +271,8 @@ def test_four_sweeps_per_launch_equal_four_launches(case):
                          check_every=chk, sweeps_per_launch=spl, max_sweeps=50000) as ctx:
             ctx.step(steps)
             res[spl] = (ctx.read_voltages(0, 0), ctx.read_inductor_currents(0, 0), ctx.stats())
+            fused = (4, True) if case != "unsupported_falls_back" else (1, False)
+            assert ctx.sweep_launch_info() == (fused if spl == 4 else (1, False))
     assert np.array_equal(res[1][0], res[4][0]), np.max(np.abs(res[1][0] - res[4][0]))
     assert np.array_equal(res[1][1], res[4][1])
     assert res[1][2]["sweeps"] == res[4][2]["sweeps"]
@@ -382,7 +393,7 @@ def test_autotune_restores_state_and_caches(tmp_path):
         assert ctx.time_index() == 5
         assert np.array_equal(ctx.read_voltages(), v5)
         assert 0 < chosen["omega"] < 2 and chosen["check_every"] >= 1 and chosen["tile_rows"] in (4, 8, 16)
-        assert chosen["sweeps_per_launch"] in (1, 2)
+        assert chosen["sweeps_per_launch"] in (1, 2, 4)
         ctx.step(15)
         V = ctx.read_voltages()
     import json
