@@ -463,7 +463,7 @@ def measure(name, prec, tol, steps, args, do_verify=True):
                 "frac": achieved / HBM_PEAK, "traffic": traffic,
                 # "mall": the sweep's working set fits in the 256 MB Infinity Cache, so part of its
                 # traffic may be served there; "hbm": it does not, and the sweeps stream from HBM
-                "regime": "mall" if per_launch <= MALL_BYTES else "hbm",
+                "regime": "mall" if per_launch / spl <= MALL_BYTES else "hbm",  # one sweep's arrays
                 "kernel": sweep_kernel_name(w, st["sweep_launch"]), "timed_launches": kt["sweep_launches"],
                 "avg_launch_us": kt["sweep_ms"] * 1e3 / kt["sweep_launches"],
                 "bytes_per_launch": per_launch}
