@@ -82,7 +82,7 @@ TUNED = {
     "config1": dict(omega=1.6, check_every=8, tile_rows=16, graphs=0, sweeps_per_launch_fp32=2),
     "config1_hbm": dict(omega=1.6, check_every=8, tile_rows=16, graphs=0),
     "config2": dict(omega=1.8, check_every=16, graphs=0, sweeps_per_launch_fp32=4),
-    "config3a": dict(omega=1.7, check_every=8, tile_rows=16, scen_block=16, graphs=0),
+    "config3a": dict(omega=1.7, check_every=8, tile_rows=16, scen_block=16, graphs=0, sweeps_per_launch_fp32=4),
     "config3b": dict(omega=1.6, check_every=8, graphs=0, sweeps_per_launch_fp32=4),
     "config4": dict(omega=1.6, check_every=6, graphs=0),
     "graph1": dict(omega=1.6, check_every=6, graphs=0),
@@ -155,7 +155,7 @@ GOLDEN = {
 COUNTERS = {
     "config1": os.path.join(ROOT, "profiles", "k_sweep_tb_rc3x1024_counters.json"),
     "config1_hbm": os.path.join(ROOT, "profiles", "k_sweep_rb_rc3x2048_counters.json"),
-    "config3a": os.path.join(ROOT, "profiles", "k_sweep_rb_multi_batch256x256_counters.json"),
+    "config3a": os.path.join(ROOT, "profiles", "k_sweep_tb_batch256x256_counters.json"),
     "graph1": os.path.join(ROOT, "profiles", "k_graph_sweep_irregular3x1024_counters.json"),
     "config2": os.path.join(ROOT, "profiles", "k_sweep_tb_rlc2x512_counters.json"),
 }

@@ -196,9 +196,9 @@ def test_scenario_blocks_on_layered_meshes(prec, ordering, rows, block, nl):
 def test_two_sweeps_per_launch_equal_two_launches(case):
     """Fusing two red-black sweeps into one launch gives the voltages of two separate sweeps bit
     for bit, including an odd cycle length (one single-sweep launch at the end of each cycle),
-    ragged tiles and scenario blocks: FP32 sweeps of single-scenario meshes stage the tile with a
-    four-node halo once (three_layer_fp32, rlc_fp32_rows8), the others recompute the halo's rings
-    (FP64, scenario blocks)."""
+    ragged tiles and scenario blocks: FP32 sweeps stage the tile with a four-node halo once
+    (three_layer_fp32, rlc_fp32_rows8, and blocks_fp32 scenario by scenario), FP64 sweeps recompute
+    the halo's rings."""
     lg4 = (1.0, 2.0, 4.0, 8.0)
     if case == "rc32_fp64":
         w, prec, rows, chk, block = config0(), pg.PG_PREC_FP64, 8, 7, 0
@@ -228,7 +228,7 @@ def test_two_sweeps_per_launch_equal_two_launches(case):
                          scen_block=block, sweeps_per_launch=spl) as ctx:
             ctx.step(steps)
             res[spl] = ([ctx.read_voltages(0, s) for s in range(len(w.pulses[0]))], ctx.stats())
-            staged = case in ("three_layer_fp32", "rlc_fp32_rows8")
+            staged = case in ("three_layer_fp32", "rlc_fp32_rows8", "blocks_fp32")
             assert ctx.sweep_launch_info() == ((2, staged) if spl == 2 else (1, False))
     for a, b in zip(res[1][0], res[2][0]):
         assert np.array_equal(a, b), np.max(np.abs(a - b))
@@ -240,7 +240,7 @@ def test_two_sweeps_per_launch_equal_two_launches(case):
 
 
 @pytest.mark.parametrize("case", ["rlc_two_layer_rows8", "one_layer_rows16", "two_layer_rows4", "ragged_rows4",
-                                  "unsupported_falls_back"])
+                                  "blocks_rows16", "unsupported_falls_back"])
 def test_four_sweeps_per_launch_equal_four_launches(case):
     """Four red-black sweeps per launch (temporal blocking: the tile with an 8-node halo staged
     once, four sweeps on chip) give the voltages of four separate sweeps bit for bit: several
@@ -260,24 +260,32 @@ def test_four_sweeps_per_launch_equal_four_launches(case):
     elif case == "ragged_rows4":
         w, rows, chk = small_multilayer(side=77, seed=74, nl=2, layer_g=lg4[:2], pad_every=16, steps=20), 4, 7
         w.pulses[0][0] = compressed(w.pulses[0][0], start=0.25, width=1.0)
+    elif case == "blocks_rows16":  # five scenarios on one mesh, swept in blocks of three
+        w, rows, chk = small_multilayer(side=150, seed=76, nl=1, layer_g=lg4[:1], pad_every=16, steps=20), 16, 10
+        w.pulses[0] = [compressed(small_multilayer(side=150, seed=96 + s, nl=1, layer_g=lg4[:1],
+                                                   pad_every=16).pulses[0][0], start=0.25, width=1.0)
+                       for s in range(5)]
     else:  # three layers: no four-sweep kernel for that shape
         w, rows, chk = small_multilayer(side=100, seed=75, nl=3, pad_every=32, steps=20), 4, 8
         w.pulses[0][0] = compressed(w.pulses[0][0], start=0.08, width=1.0)
     steps = w.steps if w.steps <= 30 else 30
     res = {}
+    ns = len(w.pulses[0])
     for spl in (1, 4):
         say(f"[gpu] four sweeps per launch case={case} sweeps_per_launch={spl}")
         with gpu_context(w, precision=pg.PG_PREC_FP32_REFINE, tol=1e-11, omega=1.6, tile_rows=rows,
-                         check_every=chk, sweeps_per_launch=spl, max_sweeps=50000) as ctx:
+                         check_every=chk, sweeps_per_launch=spl, scen_block=3, max_sweeps=50000) as ctx:
             ctx.step(steps)
-            res[spl] = (ctx.read_voltages(0, 0), ctx.read_inductor_currents(0, 0), ctx.stats())
+            res[spl] = ([ctx.read_voltages(0, s) for s in range(ns)],
+                        [ctx.read_inductor_currents(0, s) for s in range(ns)], ctx.stats())
             fused = (4, True) if case != "unsupported_falls_back" else (1, False)
             assert ctx.sweep_launch_info() == (fused if spl == 4 else (1, False))
-    assert np.array_equal(res[1][0], res[4][0]), np.max(np.abs(res[1][0] - res[4][0]))
-    assert np.array_equal(res[1][1], res[4][1])
+    for s in range(ns):
+        assert np.array_equal(res[1][0][s], res[4][0][s]), np.max(np.abs(res[1][0][s] - res[4][0][s]))
+        assert np.array_equal(res[1][1][s], res[4][1][s])
     assert res[1][2]["sweeps"] == res[4][2]["sweeps"]
     Vref, _ = oracle_run(w.meshes[0], w.pulses[0][0], w.h, steps)
-    err = np.max(np.abs(res[4][0] - Vref[-1]))
+    err = np.max(np.abs(res[4][0][0] - Vref[-1]))
     say(f"  sweeps={res[4][2]['sweeps']} err={err:.3e}")
     assert err <= PARITY_V
 
