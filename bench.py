@@ -81,10 +81,10 @@ TUNED = {
     "config0": dict(omega=1.6, check_every=8, graphs=1, resident=1),
     "config1": dict(omega=1.6, check_every=8, tile_rows=16, graphs=0, sweeps_per_launch_fp32=2),
     "config1_hbm": dict(omega=1.6, check_every=8, tile_rows=16, graphs=0),
-    "config2": dict(omega=1.8, check_every=16, graphs=0, sweeps_per_launch_fp32=4),
+    "config2": dict(omega=1.8, check_every=16, graphs=0, sweeps_per_launch=2, sweeps_per_launch_fp32=4),
     "config3a": dict(omega=1.7, check_every=8, tile_rows=16, scen_block=16, graphs=0, sweeps_per_launch_fp32=4),
     "config3b": dict(omega=1.6, check_every=8, graphs=0, sweeps_per_launch_fp32=4),
-    "config4": dict(omega=1.6, check_every=6, graphs=0),
+    "config4": dict(omega=1.6, check_every=6, tile_rows=16, graphs=0, sweeps_per_launch=4),
     "graph1": dict(omega=1.6, check_every=6, graphs=0),
     "graph1_shuffled": dict(omega=1.6, check_every=6, graphs=0),
     "graph_mesh1": dict(omega=1.6, check_every=8, graphs=0),
@@ -510,7 +510,7 @@ def measure_adjoint(args, steps=200, ckpt=20, margin=0.05, tol=1e-10, tol_adj=1e
     torch.cuda.set_device(0)
     ctx = pg.Context(0, torch.cuda.current_stream().cuda_stream)
     ctx.set_options(h=w.h, tol=tol, omega=t["omega"], check_every=t["check_every"], max_sweeps=100000,
-                    precision=pg.PG_PREC_FP64)
+                    precision=pg.PG_PREC_FP64, tile_rows=t["tile_rows"], sweeps_per_launch=t["sweeps_per_launch"])
     ctx.upload_mesh(mesh, 1)
     ctx.set_pulses(0, 0, w.pulses[0][0])
     grads = [torch.empty(a.shape, dtype=torch.float64, device="cuda:0") for a in (mesh.C, mesh.gE, mesh.gN)]

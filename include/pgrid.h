@@ -92,15 +92,16 @@ typedef struct pg_options {
   int32_t scen_block;   /* scenarios per sweep/residual workgroup on grids that carry several
                            scenarios (coefficients are loaded once per block): 1..16 (0 = 8) */
   int32_t sweeps_per_launch; /* red-black sweeps fused into one kernel launch: 1, 2 or 4 (0 = 1).
-                           Fused FP32 sweeps stage the tile with a halo of 2 per sweep and its
+                           Fused sweeps stage the tile with a halo of 2 nodes per sweep and its
                            coefficients once and run the sweeps on chip (the scenarios of a
-                           scenario block in turn); four (FP32 sweeps only: PG_PREC_FP32_REFINE,
-                           else PG_ERR_INVALID_ARG) on meshes of 1 layer with 4, 8 or 16 tile rows
-                           or 2 layers with 4 (8 too for single-scenario grids), otherwise one
-                           sweep per launch; two on meshes of 1-4 layers (shapes:
-                           pg_sweep_launch_info), else, and for FP64 sweeps, by recomputing the
-                           halo's rings from memory.  A staged launch moves the bytes of about
-                           one sweep.  Results are identical.  Jacobi ordering always uses 1 */
+                           scenario block in turn), where the tile shape has the kernel: four
+                           needs every tile group to have it (FP32: 1 layer with 4, 8 or 16 tile
+                           rows, 2 layers with 4, or 8 without scenario blocks; FP64: 1 layer
+                           without scenario blocks), else one sweep per launch; two (FP32: 1-4
+                           layers, FP64: 1 layer or 2 with 4 rows) falls back per tile group to
+                           recomputing the halo's rings from memory.  pg_sweep_launch_info tells
+                           which runs.  A staged launch moves the bytes of about one sweep.
+                           Results are identical.  Jacobi ordering always uses 1 */
   int32_t recurrence;   /* PG_REC_TWO_LEVEL (default) or PG_REC_THREE_LEVEL (general netlists only) */
   int32_t resident;     /* 1: pg_step / pg_run_transient advance every item in one launch per call
                            (per recorded interval), one workgroup per item carrying whole steps

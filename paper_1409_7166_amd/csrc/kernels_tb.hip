@@ -176,58 +176,74 @@ __global__ __launch_bounds__(kTbThreads) void k_sweep_tb(const Tile* __restrict_
   }
 }
 
-template <int K, int NL, int TY, bool MULTI>
+template <typename T, int K, int NL, int TY, bool MULTI>
 void tb_t(const Tile* tiles, int ntiles, const GridDesc* grids, const Ctl& c, int din, int zero_in, double omega,
           hipStream_t s) {
-  hipLaunchKernelGGL((k_sweep_tb<float, NL, TY, K, MULTI>), dim3(xcd_blocks(ntiles)), dim3(kTbThreads), 0, s,
-                     tiles, ntiles, grids, c, din, zero_in, (float)omega);
+  hipLaunchKernelGGL((k_sweep_tb<T, NL, TY, K, MULTI>), dim3(xcd_blocks(ntiles)), dim3(kTbThreads), 0, s, tiles,
+                     ntiles, grids, c, din, zero_in, (T)omega);
 }
 
 // The shapes instantiated below, those whose staged pairs' registers fit without spilling, as
-// k * 1000 + layers * 100 + tile rows: single-scenario tiles (kTbShapes) and scenario blocks
-// (kTbMultiShapes, whose scenario loop keeps more registers live).
-constexpr int kTbShapes[] = {4104, 4108, 4116, 4204, 4208,
-                             2104, 2108, 2116, 2204, 2208, 2216, 2304, 2308, 2316, 2404, 2408};
-constexpr int kTbMultiShapes[] = {4104, 4108, 4116, 4204, 2104, 2108, 2116, 2204, 2208, 2304};
+// k * 1000 + layers * 100 + tile rows: FP32 single-scenario tiles and scenario blocks (whose
+// scenario loop keeps more registers live), FP64 (twice the registers per staged pair) likewise.
+constexpr int kTbShapes32[] = {4104, 4108, 4116, 4204, 4208,
+                               2104, 2108, 2116, 2204, 2208, 2216, 2304, 2308, 2316, 2404, 2408};
+constexpr int kTbMulti32[] = {4104, 4108, 4116, 4204, 2104, 2108, 2116, 2204, 2208, 2304};
+constexpr int kTbShapes64[] = {4104, 4108, 4116, 2104, 2108, 2116, 2204};
+constexpr int kTbMulti64[] = {2104, 2108, 2116};
+
+template <size_t N>
+bool in_list(const int (&a)[N], int key) {
+  for (int v : a)
+    if (v == key) return true;
+  return false;
+}
 
 }  // namespace
 
 bool sweep_tb_supported(bool fp32, bool multi, int ordering, int nl, int tile_rows, int k) {
-  if (!fp32 || ordering != 0) return false;  // FP32 red-black sweeps
+  if (ordering != 0) return false;  // red-black sweeps
   const int key = k * 1000 + nl * 100 + tile_rows;
-  if (multi) {
-    for (int sh : kTbMultiShapes)
-      if (sh == key) return true;
-    return false;
-  }
-  for (int sh : kTbShapes)
-    if (sh == key) return true;
-  return false;
+  if (fp32) return multi ? in_list(kTbMulti32, key) : in_list(kTbShapes32, key);
+  return multi ? in_list(kTbMulti64, key) : in_list(kTbShapes64, key);
 }
 
-hipError_t launch_sweep_tb(int k, bool multi, int nl, int tile_rows, const Tile* tiles, int ntiles,
+hipError_t launch_sweep_tb(bool fp32, int k, bool multi, int nl, int tile_rows, const Tile* tiles, int ntiles,
                            const GridDesc* grids, const Ctl& c, int din, int zero_in, double omega, hipStream_t s) {
   if (ntiles <= 0) return hipSuccess;
-  if (!sweep_tb_supported(true, multi, 0, nl, tile_rows, k)) return hipErrorInvalidValue;
-#define PG_TB(K, NL, TY)                                                                  \
-  case K * 1000 + NL * 100 + TY:                                                          \
-    tb_t<K, NL, TY, false>(tiles, ntiles, grids, c, din, zero_in, omega, s);              \
+  if (!sweep_tb_supported(fp32, multi, 0, nl, tile_rows, k)) return hipErrorInvalidValue;
+  const int key = k * 1000 + nl * 100 + tile_rows;
+#define PG_TB(T, K, NL, TY)                                                   \
+  case K * 1000 + NL * 100 + TY:                                              \
+    tb_t<T, K, NL, TY, false>(tiles, ntiles, grids, c, din, zero_in, omega, s); \
     break;
-#define PG_TB_BOTH(K, NL, TY)                                                             \
-  case K * 1000 + NL * 100 + TY:                                                          \
-    if (multi)                                                                            \
-      tb_t<K, NL, TY, true>(tiles, ntiles, grids, c, din, zero_in, omega, s);             \
-    else                                                                                  \
-      tb_t<K, NL, TY, false>(tiles, ntiles, grids, c, din, zero_in, omega, s);            \
+#define PG_TB_BOTH(T, K, NL, TY)                                              \
+  case K * 1000 + NL * 100 + TY:                                              \
+    if (multi)                                                                \
+      tb_t<T, K, NL, TY, true>(tiles, ntiles, grids, c, din, zero_in, omega, s); \
+    else                                                                      \
+      tb_t<T, K, NL, TY, false>(tiles, ntiles, grids, c, din, zero_in, omega, s); \
     break;
-  switch (k * 1000 + nl * 100 + tile_rows) {
-    PG_TB_BOTH(4, 1, 4) PG_TB_BOTH(4, 1, 8) PG_TB_BOTH(4, 1, 16) PG_TB_BOTH(4, 2, 4) PG_TB(4, 2, 8)
-    PG_TB_BOTH(2, 1, 4) PG_TB_BOTH(2, 1, 8) PG_TB_BOTH(2, 1, 16) PG_TB_BOTH(2, 2, 4) PG_TB_BOTH(2, 2, 8)
-    PG_TB(2, 2, 16) PG_TB_BOTH(2, 3, 4) PG_TB(2, 3, 8) PG_TB(2, 3, 16) PG_TB(2, 4, 4) PG_TB(2, 4, 8)
-    default: return hipErrorInvalidValue;
+  if (fp32) {
+    switch (key) {
+      PG_TB_BOTH(float, 4, 1, 4) PG_TB_BOTH(float, 4, 1, 8) PG_TB_BOTH(float, 4, 1, 16)
+      PG_TB_BOTH(float, 4, 2, 4) PG_TB(float, 4, 2, 8)
+      PG_TB_BOTH(float, 2, 1, 4) PG_TB_BOTH(float, 2, 1, 8) PG_TB_BOTH(float, 2, 1, 16)
+      PG_TB_BOTH(float, 2, 2, 4) PG_TB_BOTH(float, 2, 2, 8) PG_TB(float, 2, 2, 16)
+      PG_TB_BOTH(float, 2, 3, 4) PG_TB(float, 2, 3, 8) PG_TB(float, 2, 3, 16)
+      PG_TB(float, 2, 4, 4) PG_TB(float, 2, 4, 8)
+      default: return hipErrorInvalidValue;
+    }
+  } else {
+    switch (key) {
+      PG_TB(double, 4, 1, 4) PG_TB(double, 4, 1, 8) PG_TB(double, 4, 1, 16)
+      PG_TB_BOTH(double, 2, 1, 4) PG_TB_BOTH(double, 2, 1, 8) PG_TB_BOTH(double, 2, 1, 16)
+      PG_TB(double, 2, 2, 4)
+      default: return hipErrorInvalidValue;
+    }
   }
-#undef PG_TB_BOTH
 #undef PG_TB
+#undef PG_TB_BOTH
   return hipGetLastError();
 }
 

@@ -274,7 +274,7 @@ hipError_t launch_sweep(bool fp32, bool multi, int ordering, int nl, int tile_ro
 // d[din ^ 1].
 constexpr int kTbSweeps = 4;
 bool sweep_tb_supported(bool fp32, bool multi, int ordering, int nl, int tile_rows, int k);
-hipError_t launch_sweep_tb(int k, bool multi, int nl, int tile_rows, const Tile* tiles, int ntiles,
+hipError_t launch_sweep_tb(bool fp32, int k, bool multi, int nl, int tile_rows, const Tile* tiles, int ntiles,
                            const GridDesc* grids, const Ctl& c, int din, int zero_in, double omega, hipStream_t s);
 // count_step: 1 statistics and clock, 2 clock only, 0 neither; begin_next opens the next step.
 hipError_t launch_step_end(const Ctl& c, int G, int count_step, int begin_next, double h, const SourceTable& src,

@@ -1075,12 +1075,13 @@ pg_status launch_sweeps(pg_ctx* c, int nchk) {
       const int zero_in = s == 0 ? 1 : 0;
       hipError_t e;
       if (spl == kTbSweeps && nchk - s >= kTbSweeps) {
-        e = launch_sweep_tb(kTbSweeps, grp.multi, grp.nl, c->tile_rows, T + grp.off, grp.count,
+        e = launch_sweep_tb(fp32_mode(c), kTbSweeps, grp.multi, grp.nl, c->tile_rows, T + grp.off, grp.count,
                             (const GridDesc*)c->grid_desc.p, c->ctl, j & 1, zero_in, c->opt.omega, c->stream);
         s += kTbSweeps;
       } else if (spl == 2 && nchk - s >= 2) {  // staged once where the group has the kernel, else rings
         if (sweep_tb_supported(fp32_mode(c), grp.multi, c->opt.ordering, grp.nl, c->tile_rows, 2))
-          e = launch_sweep_tb(2, grp.multi, grp.nl, c->tile_rows, T + grp.off, grp.count, (const GridDesc*)c->grid_desc.p,
+          e = launch_sweep_tb(fp32_mode(c), 2, grp.multi, grp.nl, c->tile_rows, T + grp.off, grp.count,
+                              (const GridDesc*)c->grid_desc.p,
                               c->ctl, j & 1, zero_in, c->opt.omega, c->stream);
         else
           e = launch_sweep2(fp32_mode(c), grp.nl, c->tile_rows, T + grp.off, grp.count,
@@ -2911,7 +2912,6 @@ extern "C" pg_status pg_autotune(pg_ctx* c, int32_t nsteps, const char* cache_pa
   }
   for (int f : {1, 2, kTbSweeps}) {
     if (f == best.sweeps_per_launch || best.ordering != PG_ORDER_RED_BLACK) continue;
-    if (f == kTbSweeps && best.precision != PG_PREC_FP32_REFINE) continue;
     pg_options o = best;
     o.sweeps_per_launch = f;
     double t;

@@ -98,8 +98,6 @@ pg_status pg_validate_options(const pg_options* o, char* msg, size_t len) {
     return fail(PG_ERR_INVALID_ARG, msg, len, "scen_block must be 0 (default) or 1..16");
   if (o->sweeps_per_launch < 0 || o->sweeps_per_launch > 4 || o->sweeps_per_launch == 3)
     return fail(PG_ERR_INVALID_ARG, msg, len, "sweeps_per_launch must be 0 (default), 1, 2 or 4");
-  if (o->sweeps_per_launch == 4 && o->precision != PG_PREC_FP32_REFINE)
-    return fail(PG_ERR_INVALID_ARG, msg, len, "sweeps_per_launch 4 runs FP32 sweeps (PG_PREC_FP32_REFINE) only");
   if (o->recurrence != PG_REC_TWO_LEVEL && o->recurrence != PG_REC_THREE_LEVEL)
     return fail(PG_ERR_INVALID_ARG, msg, len, "unknown recurrence %d", o->recurrence);
   if (o->recurrence == PG_REC_THREE_LEVEL && o->graphs)

@@ -108,9 +108,8 @@ def test_options_validation():
         bad = pg.default_options(**{k: v})
         st, msg = pg.validate_options(bad)
         assert st == -1, (k, v)
-    # four sweeps per launch run FP32 sweeps only
-    st, msg = pg.validate_options(pg.default_options(sweeps_per_launch=4))
-    assert st == -1 and "FP32" in msg
+    # four sweeps per launch in either precision (tile groups without the kernel sweep once per launch)
+    assert pg.validate_options(pg.default_options(sweeps_per_launch=4))[0] == 0
     assert pg.validate_options(pg.default_options(sweeps_per_launch=4, precision=pg.PG_PREC_FP32_REFINE))[0] == 0
     # the three-level recurrence runs with plain launches only
     st, msg = pg.validate_options(pg.default_options(recurrence=pg.PG_REC_THREE_LEVEL, graphs=1))

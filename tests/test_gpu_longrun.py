@@ -194,12 +194,14 @@ def test_config2_rlc_every_5th_step_of_500():
 
 
 @pytest.mark.timeout(600)
-def test_config4_adjoint_all_200_steps():
+@pytest.mark.parametrize("launch", ["fp32_one_sweep", "bench_fp64_four_sweeps"])
+def test_config4_adjoint_all_200_steps(launch):
     """The adjoint workload over its whole 200 steps with checkpoints every 20: the loss, seeded
     sampled entries of every gradient against the oracle adjoint (per entry within 1e-4 of the
     larger of the entry and 1e-3 of the gradient's largest magnitude), and the directional
     derivative along a seeded direction against a central difference of the oracle's forward
-    transient on the full grid (within 1e-4 relative)."""
+    transient on the full grid (within 1e-4 relative); with FP32 sweeps one per launch, and with
+    the settings bench.py times (FP64 sweeps four per launch on 16-row tiles)."""
     from workloads import config4, random_direction
     path = os.path.join(os.path.dirname(GOLDEN["config1"]), "config4_adjoint_samples.npz")
     if not os.path.exists(path):
@@ -208,10 +210,18 @@ def test_config4_adjoint_all_200_steps():
     w = config4()
     mesh = w.meshes[0]
     steps, margin = int(g["steps"]), float(g["margin"])
-    say(f"[gpu] adjoint 1024x1024, {steps} steps, checkpoints every 20")
-    with gpu_context(w, precision=pg.PG_PREC_FP32_REFINE, tol=1e-11, omega=1.5, max_sweeps=100000) as ctx:
+    say(f"[gpu] adjoint 1024x1024, {steps} steps, checkpoints every 20, {launch}")
+    if launch == "fp32_one_sweep":
+        opts = dict(precision=pg.PG_PREC_FP32_REFINE, tol=1e-11, omega=1.5, max_sweeps=100000)
+    else:
+        t = settings("config4", 1e-10, pg.PG_PREC_FP64)
+        opts = dict(precision=pg.PG_PREC_FP64, tol=1e-10, omega=t["omega"], check_every=t["check_every"],
+                    tile_rows=t["tile_rows"], sweeps_per_launch=t["sweeps_per_launch"], max_sweeps=100000)
+    with gpu_context(w, **opts) as ctx:
         J = ctx.loss_forward(0, 0, steps, 20, margin)
         dC, dE, dN = ctx.loss_backward(1e-10)
+        if launch != "fp32_one_sweep":
+            assert ctx.sweep_launch_info() == (4, True)
     worst = 0.0
     for name, grad in (("C", dC), ("gE", dE), ("gN", dN)):
         ref = g[f"grad_{name}"]

@@ -196,9 +196,9 @@ def test_scenario_blocks_on_layered_meshes(prec, ordering, rows, block, nl):
 def test_two_sweeps_per_launch_equal_two_launches(case):
     """Fusing two red-black sweeps into one launch gives the voltages of two separate sweeps bit
     for bit, including an odd cycle length (one single-sweep launch at the end of each cycle),
-    ragged tiles and scenario blocks: FP32 sweeps stage the tile with a four-node halo once
-    (three_layer_fp32, rlc_fp32_rows8, and blocks_fp32 scenario by scenario), FP64 sweeps recompute
-    the halo's rings."""
+    ragged tiles and scenario blocks: where the tile shape has the kernel the tile is staged with
+    a four-node halo once (three_layer_fp32, rlc_fp32_rows8, blocks_fp32 scenario by scenario, and
+    the one-layer FP64 rc32_fp64), else the halo's rings are recomputed (four_layer_fp64)."""
     lg4 = (1.0, 2.0, 4.0, 8.0)
     if case == "rc32_fp64":
         w, prec, rows, chk, block = config0(), pg.PG_PREC_FP64, 8, 7, 0
@@ -228,7 +228,7 @@ def test_two_sweeps_per_launch_equal_two_launches(case):
                          scen_block=block, sweeps_per_launch=spl) as ctx:
             ctx.step(steps)
             res[spl] = ([ctx.read_voltages(0, s) for s in range(len(w.pulses[0]))], ctx.stats())
-            staged = case in ("three_layer_fp32", "rlc_fp32_rows8", "blocks_fp32")
+            staged = case in ("three_layer_fp32", "rlc_fp32_rows8", "blocks_fp32", "rc32_fp64")
             assert ctx.sweep_launch_info() == ((2, staged) if spl == 2 else (1, False))
     for a, b in zip(res[1][0], res[2][0]):
         assert np.array_equal(a, b), np.max(np.abs(a - b))
@@ -240,13 +240,14 @@ def test_two_sweeps_per_launch_equal_two_launches(case):
 
 
 @pytest.mark.parametrize("case", ["rlc_two_layer_rows8", "one_layer_rows16", "two_layer_rows4", "ragged_rows4",
-                                  "blocks_rows16", "unsupported_falls_back"])
+                                  "blocks_rows16", "one_layer_fp64_rows8", "unsupported_falls_back"])
 def test_four_sweeps_per_launch_equal_four_launches(case):
     """Four red-black sweeps per launch (temporal blocking: the tile with an 8-node halo staged
     once, four sweeps on chip) give the voltages of four separate sweeps bit for bit: several
     tiles in x and y so the halos overlap neighbouring tiles, ragged edges, cycle lengths that
-    leave one-sweep launches at the end of a cycle, the RLC grid's branch currents, and a
-    context whose tile groups have no four-sweep kernel (it sweeps once per launch)."""
+    leave one-sweep launches at the end of a cycle, the RLC grid's branch currents, scenario
+    blocks, FP64 sweeps, and a context whose tile groups have no four-sweep kernel (it sweeps
+    once per launch)."""
     lg4 = (1.0, 2.0, 4.0, 8.0)
     if case == "rlc_two_layer_rows8":
         w, rows, chk = small_rlc(side=300, seed=71, steps=30), 8, 16
@@ -265,6 +266,9 @@ def test_four_sweeps_per_launch_equal_four_launches(case):
         w.pulses[0] = [compressed(small_multilayer(side=150, seed=96 + s, nl=1, layer_g=lg4[:1],
                                                    pad_every=16).pulses[0][0], start=0.25, width=1.0)
                        for s in range(5)]
+    elif case == "one_layer_fp64_rows8":
+        w, rows, chk = small_multilayer(side=200, seed=77, nl=1, layer_g=lg4[:1], pad_every=16, steps=20), 8, 12
+        w.pulses[0][0] = compressed(w.pulses[0][0], start=0.25, width=1.0)
     else:  # three layers: no four-sweep kernel for that shape
         w, rows, chk = small_multilayer(side=100, seed=75, nl=3, pad_every=32, steps=20), 4, 8
         w.pulses[0][0] = compressed(w.pulses[0][0], start=0.08, width=1.0)
@@ -273,7 +277,8 @@ def test_four_sweeps_per_launch_equal_four_launches(case):
     ns = len(w.pulses[0])
     for spl in (1, 4):
         say(f"[gpu] four sweeps per launch case={case} sweeps_per_launch={spl}")
-        with gpu_context(w, precision=pg.PG_PREC_FP32_REFINE, tol=1e-11, omega=1.6, tile_rows=rows,
+        prec = pg.PG_PREC_FP64 if "fp64" in case else pg.PG_PREC_FP32_REFINE
+        with gpu_context(w, precision=prec, tol=1e-11, omega=1.6, tile_rows=rows,
                          check_every=chk, sweeps_per_launch=spl, scen_block=3, max_sweeps=50000) as ctx:
             ctx.step(steps)
             res[spl] = ([ctx.read_voltages(0, s) for s in range(ns)],
