@@ -192,13 +192,14 @@ def test_scenario_blocks_on_layered_meshes(prec, ordering, rows, block, nl):
 
 
 @pytest.mark.parametrize("case", ["rc32_fp64", "three_layer_fp32", "blocks_fp32", "four_layer_fp64",
-                                  "rlc_fp32_rows8"])
+                                  "rlc_fp32_rows8", "four_layer_fp32", "blocks_fp64"])
 def test_two_sweeps_per_launch_equal_two_launches(case):
     """Fusing two red-black sweeps into one launch gives the voltages of two separate sweeps bit
     for bit, including an odd cycle length (one single-sweep launch at the end of each cycle),
     ragged tiles and scenario blocks: where the tile shape has the kernel the tile is staged with
-    a four-node halo once (three_layer_fp32, rlc_fp32_rows8, blocks_fp32 scenario by scenario, and
-    the one-layer FP64 rc32_fp64), else the halo's rings are recomputed (four_layer_fp64)."""
+    a four-node halo once (three_layer_fp32, rlc_fp32_rows8, four_layer_fp32, blocks_fp32 and
+    blocks_fp64 scenario by scenario, and the one-layer FP64 rc32_fp64), else the halo's rings are
+    recomputed (four_layer_fp64)."""
     lg4 = (1.0, 2.0, 4.0, 8.0)
     if case == "rc32_fp64":
         w, prec, rows, chk, block = config0(), pg.PG_PREC_FP64, 8, 7, 0
@@ -216,6 +217,16 @@ def test_two_sweeps_per_launch_equal_two_launches(case):
         w = small_multilayer(side=77, seed=82, nl=4, layer_g=lg4, pad_every=16, steps=20)
         w.pulses[0][0] = compressed(w.pulses[0][0], start=0.25, width=1.0)
         prec, rows, chk, block = pg.PG_PREC_FP64, 4, 9, 0
+    elif case == "four_layer_fp32":
+        w = small_multilayer(side=77, seed=84, nl=4, layer_g=lg4, pad_every=16, steps=20)
+        w.pulses[0][0] = compressed(w.pulses[0][0], start=0.25, width=1.0)
+        prec, rows, chk, block = pg.PG_PREC_FP32_REFINE, 4, 9, 0
+    elif case == "blocks_fp64":
+        w = small_multilayer(side=140, seed=85, nl=1, layer_g=lg4[:1], pad_every=16, steps=20)
+        w.pulses[0] = [compressed(small_multilayer(side=140, seed=95 + s, nl=1, layer_g=lg4[:1],
+                                                   pad_every=16).pulses[0][0], start=0.25, width=1.0)
+                       for s in range(5)]
+        prec, rows, chk, block = pg.PG_PREC_FP64, 8, 5, 2
     else:
         w = small_rlc(side=150, seed=83, steps=20)
         w.pulses[0][0] = compressed(w.pulses[0][0], start=0.02, width=0.3)
@@ -228,7 +239,8 @@ def test_two_sweeps_per_launch_equal_two_launches(case):
                          scen_block=block, sweeps_per_launch=spl) as ctx:
             ctx.step(steps)
             res[spl] = ([ctx.read_voltages(0, s) for s in range(len(w.pulses[0]))], ctx.stats())
-            staged = case in ("three_layer_fp32", "rlc_fp32_rows8", "blocks_fp32", "rc32_fp64")
+            staged = case in ("three_layer_fp32", "rlc_fp32_rows8", "blocks_fp32", "rc32_fp64", "four_layer_fp32",
+                              "blocks_fp64")
             assert ctx.sweep_launch_info() == ((2, staged) if spl == 2 else (1, False))
     for a, b in zip(res[1][0], res[2][0]):
         assert np.array_equal(a, b), np.max(np.abs(a - b))
