@@ -1,8 +1,8 @@
 """Randomised parity (hypothesis, fixed derandomised draws): random layered meshes of 1-4 layers
 and ragged sizes, RC or with series R-L vias and pads, one to three scenarios, through the HIP
-path with randomly chosen precision, tile rows and launch path (one launch per sweep, or the
-resident path where the mesh fits one workgroup), against the oracle at every node of every
-step.  Bar: 1e-6 V per node per step, branch currents within 1e-6 of their largest magnitude."""
+path with randomly chosen precision, tile rows and launch path (one, two or four sweeps per
+launch, or the resident path where the mesh fits one workgroup), against the oracle at every node
+of every step.  Bar: 1e-6 V per node per step, branch currents within 1e-6 of their largest magnitude."""
 import numpy as np
 import pytest
 from hypothesis import HealthCheck, given, settings
@@ -18,18 +18,18 @@ from workloads import random_mesh
 pytestmark = pytest.mark.gpu
 
 
-@settings(max_examples=30, deadline=None, derandomize=True, suppress_health_check=[HealthCheck.too_slow])
+@settings(max_examples=60, deadline=None, derandomize=True, suppress_health_check=[HealthCheck.too_slow])
 @given(nx=st.integers(2, 45), ny=st.integers(2, 37), nl=st.integers(1, 4), seed=st.integers(0, 10**6),
        scen=st.integers(1, 3), inductive=st.booleans(), fp32=st.booleans(), tile_rows=st.sampled_from([4, 8, 16]),
-       resident=st.booleans())
-def test_random_meshes_every_node_every_step(nx, ny, nl, seed, scen, inductive, fp32, tile_rows, resident):
+       resident=st.booleans(), spl=st.sampled_from([1, 2, 4]))
+def test_random_meshes_every_node_every_step(nx, ny, nl, seed, scen, inductive, fp32, tile_rows, resident, spl):
     steps = 10
     w = random_mesh(seed, nx, ny, nl, scenarios=scen, inductive=inductive, h=1e-12 if inductive else 1e-11,
                     steps=steps)
     mesh = w.meshes[0]
     resident = resident and mesh.n <= 4096
     say(f"[gpu] random {nl}x{ny}x{nx} seed={seed} scen={scen} L={inductive} fp32={fp32} rows={tile_rows} "
-        f"resident={resident}")
+        f"resident={resident} sweeps_per_launch={spl}")
     refs = []
     ind = None
     for p in w.pulses[0]:
@@ -47,7 +47,7 @@ def test_random_meshes_every_node_every_step(nx, ny, nl, seed, scen, inductive, 
     prec = pg.PG_PREC_FP32_REFINE if fp32 else pg.PG_PREC_FP64
     worst_v = worst_i = 0.0
     with gpu_context(w, precision=prec, tol=1e-11, omega=1.5, check_every=8, tile_rows=tile_rows,
-                     resident=int(resident), max_sweeps=100000) as ctx:
+                     resident=int(resident), sweeps_per_launch=spl, max_sweeps=100000) as ctx:
         for k in range(steps):
             ctx.step(1)
             for s in range(scen):
