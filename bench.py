@@ -60,6 +60,9 @@ def parse():
     ap.add_argument("--resident", type=int, default=-1,
                     help="1: one launch per call with one workgroup per item carrying whole steps (meshes of at "
                          "most 4096 nodes); 0: one launch per sweep; -1: the workload's tuned choice")
+    ap.add_argument("--predictor", type=int, default=-1,
+                    help="1: start each mesh step's sweeps from the linear extrapolation of the last two "
+                         "steps; 0: from the last step (Algorithm 1); -1: the workload's tuned choice")
     ap.add_argument("--profile-every", type=int, default=32,
                     help="time every n-th sweep block, residual pass and other launch with HIP events "
                          "during the timed region (0: off)")
@@ -113,11 +116,11 @@ TUNED_PARITY = {
 
 def settings(name, tol, precision="fp32+ref"):
     """Solver options (omega, check_every, tile_rows, graphs, scen_block, sweeps_per_launch,
-    resident) that bench.py runs workload `name` with at stopping tolerance `tol` and sweep
+    resident, predictor) that bench.py runs workload `name` with at stopping tolerance `tol` and sweep
     precision `precision` ("fp64", "fp32+ref" or the library's constant); four sweeps per launch
     (sweeps_per_launch_fp32) apply to FP32 sweeps only."""
     fp32 = precision in ("fp32+ref", pg_const("PG_PREC_FP32_REFINE"))
-    s = dict(tile_rows=0, scen_block=0, sweeps_per_launch=0, resident=0)
+    s = dict(tile_rows=0, scen_block=0, sweeps_per_launch=0, resident=0, predictor=0)
     s.update(TUNED[name])
     ptol = PARITY_TOL.get(name, PARITY_TOL.get(name.replace("_hbm", "")))
     if ptol is not None and tol <= ptol:
@@ -275,7 +278,7 @@ def verify(ctx, w, name):
 
 
 def run_gpu(w, name, steps, warmup, precision, tol, omega, check_every, tile_rows, lookahead, profile_every,
-            graphs, scen_block=0, sweeps_per_launch=0, recurrence=0, do_verify=True, resident=0):
+            graphs, scen_block=0, sweeps_per_launch=0, recurrence=0, do_verify=True, resident=0, predictor=0):
     import torch
     import paper_1409_7166_amd as pg
 
@@ -285,7 +288,8 @@ def run_gpu(w, name, steps, warmup, precision, tol, omega, check_every, tile_row
     ctx.set_options(h=w.h, tol=tol, omega=omega, check_every=check_every, max_sweeps=100000,
                     precision=pg.PG_PREC_FP32_REFINE if precision == "fp32+ref" else pg.PG_PREC_FP64,
                     tile_rows=tile_rows, lookahead=lookahead, graphs=graphs, scen_block=scen_block,
-                    sweeps_per_launch=sweeps_per_launch, recurrence=recurrence, resident=resident)
+                    sweeps_per_launch=sweeps_per_launch, recurrence=recurrence, resident=resident,
+                    predictor=predictor)
     grids = w.nets if is_netlist(w) else w.meshes
     for g, (grid, scen) in enumerate(zip(grids, w.pulses)):
         if is_netlist(w):
@@ -446,9 +450,11 @@ def measure(name, prec, tol, steps, args, do_verify=True):
     block = args.scen_block or tuned.get("scen_block", 0)
     spl_opt = args.sweeps_per_launch or tuned.get("sweeps_per_launch", 0)
     resident = tuned["resident"] if args.resident < 0 else args.resident
+    predictor = tuned["predictor"] if args.predictor < 0 else args.predictor
     elapsed, st, kt, err = run_gpu(w, name, steps, args.warmup, prec, tol, omega, chk, rows,
                                    args.lookahead, args.profile_every, graphs, block,
-                                   spl_opt, args.recurrence, do_verify and not args.no_verify, resident)
+                                   spl_opt, args.recurrence, do_verify and not args.no_verify, resident,
+                                   predictor)
     nodes = w.nodes
     value = st["node_updates"] / elapsed
     spl = st["sweep_launch"][0]
@@ -480,6 +486,7 @@ def measure(name, prec, tol, steps, args, do_verify=True):
                    else None,
                    "recurrence": "three-level" if args.recurrence else "two-level",
                    "resident": bool(st["options"]["resident"]),
+                   "predictor": bool(st["options"]["predictor"]),
                    "sweeps_per_step": st["sweeps"] / max(1, st["steps"]),
                    "max_step_sweeps": st["max_step_sweeps"], "max_final_residual_V": st["max_final_residual"],
                    "node_steps_per_s": nodes * steps / elapsed},

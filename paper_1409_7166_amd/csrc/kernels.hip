@@ -287,10 +287,12 @@ __global__ void k_decide(Ctl c, DecideArgs da, CloseArgs ca) {
 
 // ------------------------------------------------------------------------------------
 // Right-hand side of the step (eq. 2 / eq. 10): b = (C/h) v + G0 Vdd - inductor history.
-// Sources are subtracted afterwards by k_sources.
+// Sources are subtracted afterwards by k_sources.  predict = 1: also keep v(t) in vhist;
+// predict = 2: also replace v by the step's first iterate 2 v(t) - v(t-h) (v(t-h) read from
+// vhist) and keep v(t) in vhist.
 // ------------------------------------------------------------------------------------
 __global__ __launch_bounds__(kThreads) void k_rhs(const Tile* __restrict__ tiles, int ntiles,
-                                                 const GridDesc* __restrict__ grids, Ctl c, int TY) {
+                                                 const GridDesc* __restrict__ grids, Ctl c, int TY, int predict) {
   if (*c.stall) return;  // a stalled step opening
   const int ti = xcd_tile(ntiles);
   if (ti < 0) return;
@@ -299,8 +301,9 @@ __global__ __launch_bounds__(kThreads) void k_rhs(const Tile* __restrict__ tiles
   const int X = G.X, ny = G.ny;
   const int64_t P = (int64_t)X * ny;
   const int64_t off = (int64_t)tl.scen * G.nstore;
-  const double* __restrict__ v = G.v[c.vidx[tl.item]] + off;
+  double* __restrict__ v = G.v[c.vidx[tl.item]] + off;
   double* __restrict__ b = G.b + off;
+  double* __restrict__ vh = predict ? G.vhist + off : nullptr;
   const double* __restrict__ il = G.ind_i + (int64_t)tl.scen * G.n_ind;
   const int per_layer = kTileX * TY;
   for (int k = threadIdx.x; k < per_layer * G.nl; k += kThreads) {
@@ -322,6 +325,11 @@ __global__ __launch_bounds__(kThreads) void k_rhs(const Tile* __restrict__ tiles
       }
     }
     b[i] = bb;
+    if (predict) {
+      const double vt = v[i];
+      if (predict == 2) v[i] = 2.0 * vt - vh[i];
+      vh[i] = vt;
+    }
   }
 }
 
@@ -1511,10 +1519,10 @@ hipError_t launch_step_end(const Ctl& c, int I, int count_step, int begin_next, 
 }
 
 hipError_t launch_rhs(const Tile* tiles, int ntiles, int tile_rows, const GridDesc* grids,
-                      const Ctl& c, hipStream_t s) {
+                      const Ctl& c, hipStream_t s, int predict) {
   if (ntiles <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_rhs, dim3(xcd_blocks(ntiles)), dim3(kThreads), 0, s, tiles, ntiles,
-                     grids, c, tile_rows);
+                     grids, c, tile_rows, predict);
   return hipGetLastError();
 }
 

@@ -86,6 +86,7 @@ struct GridHost {
   // device buffers
   DBuf gE64, gN64, gU64, D64, ch64, bconst64, gEs, gNs, gUs, invDs;
   DBuf v0, v1, b, r, d0, d1;
+  DBuf vh;                                       // v(t-h) per scenario (meshes, predictor on)
   DBuf ind_a_d, ind_b_d, ind_geq_d, ind_alpha_d, ind_i_d, inc_off_d, inc_ind_d, ind_vfar_d;
   DBuf slot_d, sl_off_d, sl_len_d, sl_col_d, sl_w64_d, sl_ws_d, cap_off_d, cap_col_d, cap_val_d;
   DBuf vprev0, vprev1, g3diag_d, sl_g64_d, bres_d, bl_d;  // three-level recurrence
@@ -219,7 +220,7 @@ struct pg_ctx {
   int opening_tag = 0;                           // ... and the tag of its first decision
   bool maybe_stalled = false;                    // a speculative close may have stalled the device
   bool begun_next = false;                       // the last close also began the next step
-  bool prev_valid = false;                       // graph grids' vprev holds v(t-h) (three-level)
+  bool prev_valid = false;                       // v(t-h) is kept: graph grids' vprev (three-level), meshes' vh (predictor)
   int fuse_next = 0;                             // kFuse* mode of the next residual pass (mesh RHS)
   bool gprobe_next = false;                      // the next residual pass probes the general graphs
   bool gstore_next = false;                      // the next residual pass forms and stores their b, r
@@ -620,6 +621,12 @@ pg_status sync_desc(pg_ctx* c, int gi);
 
 pg_status build_grid(pg_ctx* c, int gi) {
   PG_TRY(c->grids[gi].kind ? build_graph_grid(c, gi) : build_mesh_grid(c, gi));
+  GridHost& H = c->grids[gi];
+  if (!H.kind && c->opt.predictor) {  // filled by the first opening (prev_valid is false then)
+    if (!H.vh.p) PG_TRY(dalloc(c, H.vh, (size_t)H.nstore * H.S * sizeof(double)));
+  } else {
+    dfree(H.vh);
+  }
   return sync_desc(c, gi);
 }
 
@@ -635,6 +642,7 @@ GridDesc make_desc(pg_ctx* c, GridHost& H) {
   else { D.gEs = H.gE64.p; D.gNs = H.gN64.p; D.gUs = H.gU64.p; }
   D.invDs = H.invDs.p;
   D.v[0] = (double*)H.v0.p; D.v[1] = (double*)H.v1.p; D.b = (double*)H.b.p;
+  D.vhist = (double*)H.vh.p;
   D.r = H.r.p; D.d[0] = H.d0.p; D.d[1] = H.d1.p;
   D.n_ind = (int32_t)H.ind_a.size();
   D.ind_a = (const int32_t*)H.ind_a_d.p; D.ind_b = (const int32_t*)H.ind_b_d.p;
@@ -1184,7 +1192,10 @@ pg_status begin_step(pg_ctx* c, int only_item, bool begun = false, int64_t dev_s
   // needs no separate right-hand-side pass on single-scenario meshes: the step's first residual
   // pass forms b itself (launch_resid_all picks up fuse_rhs_next).
   const bool loads = dev_step < 0 || sources_may_act(c, dev_step);
-  bool fuse = only_item < 0 && !loads && c->ntiles_all > 0;
+  // the predictor moves v to the step's first iterate after the right-hand side has read v(t),
+  // so the right-hand side keeps its own pass
+  const int predict = c->opt.predictor && only_item < 0 ? (c->prev_valid ? 2 : 1) : 0;
+  bool fuse = only_item < 0 && !loads && c->ntiles_all > 0 && !predict;
   for (auto& grp : c->tile_groups) fuse = fuse && !grp.multi;
   // a step predicted to converge at once (the previous one did) only needs the norm: if it has
   // work after all, cycle_loop stores b and r before the first sweep
@@ -1203,7 +1214,7 @@ pg_status begin_step(pg_ctx* c, int only_item, bool begun = false, int64_t dev_s
   if (only_item >= 0) { goff = c->item_gchunk_off[only_item]; gcnt = c->item_gchunk_cnt[only_item]; }
   if (cnt > 0 || gcnt > 0) {
     ProfScope ps(c, 2, 0, 0.0, (cnt > 0 ? 1 : 0) + (gcnt > 0 ? 1 : 0));
-    e = launch_rhs(T + off, cnt, c->tile_rows, (const GridDesc*)c->grid_desc.p, k, c->stream);
+    e = launch_rhs(T + off, cnt, c->tile_rows, (const GridDesc*)c->grid_desc.p, k, c->stream, predict);
     if (e == hipSuccess) {
       if (three && c->prev_valid)
         e = launch_graph_rhs3(GC + goff, gcnt, (const GridDesc*)c->grid_desc.p, k, c->stream);
@@ -1220,7 +1231,7 @@ pg_status begin_step(pg_ctx* c, int only_item, bool begun = false, int64_t dev_s
       e = launch_sources(c->src_table, (const GridDesc*)c->grid_desc.p, k, -c->opt.h, -1.0, c->stream);
     if (e != hipSuccess) return set_err(c, PG_ERR_DEVICE, "source launch: %s", hipGetErrorString(e));
   }
-  if (three) c->prev_valid = true;
+  if (three || predict) c->prev_valid = true;
   return PG_OK;
 }
 
@@ -1869,7 +1880,7 @@ void pg_destroy(pg_ctx* c) {
   if (c->stream) (void)hipStreamSynchronize(c->stream);
   for (auto& H : c->grids) {
     DBuf* bufs[] = {&H.gE64, &H.gN64, &H.gU64, &H.D64, &H.ch64, &H.bconst64, &H.gEs, &H.gNs, &H.gUs, &H.invDs,
-                    &H.v0, &H.v1, &H.b, &H.r, &H.d0, &H.d1, &H.ind_a_d, &H.ind_b_d, &H.ind_geq_d,
+                    &H.v0, &H.v1, &H.b, &H.r, &H.d0, &H.d1, &H.vh, &H.ind_a_d, &H.ind_b_d, &H.ind_geq_d,
                     &H.ind_alpha_d, &H.ind_i_d, &H.inc_off_d, &H.inc_ind_d, &H.ind_vfar_d,
                     &H.slot_d, &H.sl_off_d, &H.sl_len_d, &H.sl_col_d, &H.sl_w64_d, &H.sl_ws_d, &H.cap_off_d, &H.cap_col_d,
                     &H.cap_val_d, &H.vprev0, &H.vprev1, &H.g3diag_d, &H.sl_g64_d, &H.bres_d, &H.bl_d,
@@ -1908,7 +1919,8 @@ pg_status pg_set_options(pg_ctx* c, const pg_options* o) {
   // h and precision change the coefficients, tile_rows and scen_block the tiles, the recurrence
   // the buffers of general netlists: rebuild; anything else only invalidates the captured graphs
   if (o->h != c->opt.h || o->precision != c->opt.precision || o->tile_rows != c->opt.tile_rows ||
-      o->scen_block != c->opt.scen_block || o->recurrence != c->opt.recurrence || o->resident != c->opt.resident)
+      o->scen_block != c->opt.scen_block || o->recurrence != c->opt.recurrence || o->resident != c->opt.resident ||
+      o->predictor != c->opt.predictor)
     c->dirty = true;
   drop_graphs(c);
   c->opt = *o;

@@ -104,7 +104,10 @@ pg_status pg_validate_options(const pg_options* o, char* msg, size_t len) {
     return fail(PG_ERR_UNSUPPORTED, msg, len, "the three-level recurrence runs with plain launches (graphs = 0)");
   if (o->resident != 0 && o->resident != 1)
     return fail(PG_ERR_INVALID_ARG, msg, len, "resident must be 0 or 1 (got %d)", o->resident);
-  if (o->reserved[0] != 0) return fail(PG_ERR_INVALID_ARG, msg, len, "reserved option fields must be zero");
+  if (o->predictor != 0 && o->predictor != 1)
+    return fail(PG_ERR_INVALID_ARG, msg, len, "predictor must be 0 or 1 (got %d)", o->predictor);
+  if (o->predictor && o->graphs)
+    return fail(PG_ERR_UNSUPPORTED, msg, len, "the predictor runs with plain launches (graphs = 0)");
   return PG_OK;
 }
 

@@ -40,7 +40,7 @@ class Options(C.Structure):
                 ("ordering", C.c_int32), ("tile_rows", C.c_int32), ("lookahead", C.c_int32),
                 ("graphs", C.c_int32), ("scen_block", C.c_int32),
                 ("sweeps_per_launch", C.c_int32), ("recurrence", C.c_int32), ("resident", C.c_int32),
-                ("reserved", C.c_int32 * 1)]
+                ("predictor", C.c_int32)]
 
 
 class MeshStruct(C.Structure):
@@ -380,7 +380,7 @@ class Context:
     def options(self) -> dict:
         o = Options()
         self._check(lib().pg_get_options(self._h, C.byref(o)))
-        return {f: getattr(o, f) for f, _ in Options._fields_ if f != "reserved"}
+        return {f: getattr(o, f) for f, _ in Options._fields_}
 
     def upload_mesh(self, mesh, n_scen: int = 1) -> int:
         hold = mesh_struct(mesh)
@@ -498,7 +498,7 @@ class Context:
         o = Options()
         self._check(lib().pg_autotune(self._h, int(nsteps), cache_path.encode() if cache_path else None,
                                       C.byref(o)))
-        return {f: getattr(o, f) for f, _ in Options._fields_ if f != "reserved"}
+        return {f: getattr(o, f) for f, _ in Options._fields_}
 
     def time_index(self) -> int:
         k = C.c_int64()

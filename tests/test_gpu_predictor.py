@@ -1,0 +1,77 @@
+"""The extrapolated first iterate (pg_options.predictor = 1): each step's sweeps start from
+2 V(s-1) - V(s-2) instead of Algorithm 1's V(s-1).  The stopping test is unchanged, so the
+voltages must match the oracle at every node of every step as closely as without it (the 1e-6 V
+bar), on RC and RLC meshes (branch currents too), on scenarios, with fused sweeps and after the
+state or the clock is set mid-run (the first step after either starts from V(s-1)); on a
+pulse-driven mesh it must need fewer sweeps."""
+import numpy as np
+import pytest
+
+import paper_1409_7166_amd as pg
+from helpers import PARITY_V, compressed, gpu_context, oracle_run, say
+from workloads import small_multilayer, small_rc, small_rlc
+
+pytestmark = pytest.mark.gpu
+
+
+def _run(w, steps, predictor, **opts):
+    out = []
+    with gpu_context(w, predictor=predictor, **opts) as ctx:
+        for _ in range(steps):
+            ctx.step(1)
+            out.append(np.stack([ctx.read_voltages(0, s) for s in range(len(w.pulses[0]))]))
+        cur = np.stack([ctx.read_inductor_currents(0, s) for s in range(len(w.pulses[0]))])
+        return np.array(out), cur, ctx.stats()
+
+
+@pytest.mark.parametrize("case", ["three_layer_fp32_fused", "rlc_fp64", "scenarios_fp32"])
+def test_predictor_matches_the_oracle_every_step(case):
+    if case == "three_layer_fp32_fused":
+        w = small_multilayer(side=100, seed=91, nl=3, pad_every=32, steps=60)
+        w.pulses[0][0] = compressed(w.pulses[0][0], start=0.2, width=1.0)
+        opts = dict(precision=pg.PG_PREC_FP32_REFINE, tol=1e-10, omega=1.7, check_every=16, tile_rows=16,
+                    sweeps_per_launch=2)
+    elif case == "rlc_fp64":
+        w = small_rlc(side=60, seed=92, steps=40)
+        w.pulses[0][0] = compressed(w.pulses[0][0], start=0.02, width=0.3)
+        opts = dict(precision=pg.PG_PREC_FP64, tol=1e-11, omega=1.7, check_every=16)
+    else:
+        w = small_rc(70, 44, seed=93, scenarios=3, steps=40)
+        w.pulses[0] = [compressed(p, start=0.3, width=1.0) for p in w.pulses[0]]
+        opts = dict(precision=pg.PG_PREC_FP32_REFINE, tol=1e-10, omega=1.6, check_every=8, scen_block=2)
+    steps = w.steps
+    say(f"[gpu] predictor case={case}")
+    res = {p: _run(w, steps, p, max_sweeps=100000, **opts) for p in (0, 1)}
+    for s, pulses in enumerate(w.pulses[0]):
+        Vref, Iref = oracle_run(w.meshes[0], pulses, w.h, steps)
+        for p in (0, 1):
+            err = float(np.max(np.abs(res[p][0][:, s, :] - Vref)))
+            say(f"  scenario {s} predictor={p}: max err over {steps} steps {err:.2e} V, "
+                f"sweeps {res[p][2]['sweeps']}")
+            assert err <= PARITY_V
+    if case == "rlc_fp64":  # branch currents after the last step, the same either way within the tolerance
+        assert np.max(np.abs(res[1][1] - res[0][1])) <= 1e-6 * max(1.0, float(np.max(np.abs(res[0][1]))))
+    if case == "three_layer_fp32_fused":
+        assert res[1][2]["sweeps"] < res[0][2]["sweeps"]
+
+
+def test_predictor_restarts_after_the_state_or_clock_is_set():
+    """Setting the state or the clock discards the kept V(s-2): the next step starts from V(s-1),
+    and the transient still matches the oracle at every step."""
+    w = small_multilayer(side=64, seed=94, nl=2, layer_g=(1.0, 4.0), pad_every=16, steps=40)
+    w.pulses[0][0] = compressed(w.pulses[0][0], start=0.2, width=1.0)
+    Vref, _ = oracle_run(w.meshes[0], w.pulses[0][0], w.h, 40)
+    opts = dict(precision=pg.PG_PREC_FP32_REFINE, tol=1e-10, omega=1.6, check_every=8, predictor=1,
+                max_sweeps=100000)
+    say("[gpu] predictor with the state and the clock set mid-run")
+    worst = 0.0
+    with gpu_context(w, **opts) as ctx:
+        for k in range(1, 41):
+            if k == 15:  # the state as it is: the history restarts
+                ctx.set_state(0, 0, ctx.read_voltages(0, 0))
+            if k == 25:  # the clock set to where it is
+                ctx.set_time_index(ctx.time_index())
+            ctx.step(1)
+            worst = max(worst, float(np.max(np.abs(ctx.read_voltages(0, 0) - Vref[k - 1]))))
+    say(f"  max err {worst:.2e} V")
+    assert worst <= PARITY_V
