@@ -105,12 +105,12 @@ PARITY_TOL = {"config0": 1e-10, "config1": 1e-10, "config3a": 1e-10, "config3b":
 # and the start of the relaxation that follows them).
 TUNED_PARITY = {
     "config0": dict(omega=1.65, check_every=16),
-    "config1": dict(omega=1.87, check_every=32),
-    "config1_hbm": dict(omega=1.87, check_every=32),
-    "config2": dict(omega=1.94, check_every=64),
+    "config1": dict(omega=1.86, check_every=12, predictor=1),
+    "config1_hbm": dict(omega=1.86, check_every=12, predictor=1),
+    "config2": dict(omega=1.9, check_every=32, predictor=1),
     "config3a": dict(omega=1.65, check_every=8),
     "config3b": dict(omega=1.6, check_every=16),
-    "config4": dict(omega=1.5, check_every=12),
+    "config4": dict(omega=1.5, check_every=12, predictor=1),
 }
 
 

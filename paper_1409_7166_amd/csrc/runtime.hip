@@ -2356,8 +2356,13 @@ pg_status pg_run_transient(pg_ctx* c, int32_t nsteps, int32_t record_every, int3
       }
     }
   } else {
+    // With the predictor the next step's opening overwrites v with its first iterate, so a step
+    // whose voltages are recorded does not queue that opening ahead of the record's copy.
+    auto ahead = [&](int k) {
+      return k + 1 < nsteps && !(out && c->opt.predictor && (k + 1) % record_every == 0);
+    };
     for (int k = 0; k < nsteps; ++k) {
-      PG_TRY(one_step(c, k + 1 < nsteps, k + 2 < nsteps));
+      PG_TRY(one_step(c, ahead(k), ahead(k + 1)));
       if (out && ((k + 1) % record_every) == 0) {
         PG_TRY(pg_read_voltages(c, grid, scen, out + (size_t)rec * c->grids[grid].n, c->grids[grid].n));
         ++rec;

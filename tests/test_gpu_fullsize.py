@@ -22,7 +22,7 @@ def _opts(name, prec, tol):
     t = settings(name, tol, prec)
     return dict(precision=prec, tol=tol, omega=t["omega"], check_every=t["check_every"], graphs=t["graphs"],
                 max_sweeps=200000, tile_rows=t["tile_rows"], scen_block=t["scen_block"],
-                sweeps_per_launch=t["sweeps_per_launch"])
+                sweeps_per_launch=t["sweeps_per_launch"], predictor=t["predictor"])
 
 
 @pytest.mark.timeout(600)

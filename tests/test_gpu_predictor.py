@@ -75,3 +75,22 @@ def test_predictor_restarts_after_the_state_or_clock_is_set():
             worst = max(worst, float(np.max(np.abs(ctx.read_voltages(0, 0) - Vref[k - 1]))))
     say(f"  max err {worst:.2e} V")
     assert worst <= PARITY_V
+
+
+@pytest.mark.parametrize("record_every", [1, 3])
+def test_predictor_recorded_transient_matches_the_oracle(record_every):
+    """pg_run_transient queues a step's successor ahead of its wait; with the predictor that
+    opening rewrites v, so every recorded voltage must still be the converged V(s), not the next
+    step's first iterate."""
+    w = small_multilayer(side=64, seed=95, nl=2, layer_g=(1.0, 4.0), pad_every=16, steps=30)
+    w.pulses[0][0] = compressed(w.pulses[0][0], start=0.2, width=1.0)
+    Vref, _ = oracle_run(w.meshes[0], w.pulses[0][0], w.h, 30)
+    say(f"[gpu] predictor recorded transient every {record_every}")
+    with gpu_context(w, precision=pg.PG_PREC_FP32_REFINE, tol=1e-10, omega=1.6, check_every=8, predictor=1,
+                     max_sweeps=100000) as ctx:
+        V = ctx.run_transient(30, record_every=record_every)
+        last = ctx.read_voltages(0, 0)
+    err = float(np.max(np.abs(V - Vref[record_every - 1::record_every])))
+    say(f"  max err over the records {err:.2e} V")
+    assert err <= PARITY_V
+    assert np.max(np.abs(last - Vref[-1])) <= PARITY_V
