@@ -291,44 +291,54 @@ __global__ void k_decide(Ctl c, DecideArgs da, CloseArgs ca) {
 // predict = 2: also replace v by the step's first iterate 2 v(t) - v(t-h) (v(t-h) read from
 // vhist) and keep v(t) in vhist.
 // ------------------------------------------------------------------------------------
-__global__ __launch_bounds__(kThreads) void k_rhs(const Tile* __restrict__ tiles, int ntiles,
-                                                 const GridDesc* __restrict__ grids, Ctl c, int TY, int predict) {
+__global__ __launch_bounds__(1024) void k_rhs(const Tile* __restrict__ tiles, int ntiles,
+                                             const GridDesc* __restrict__ grids, Ctl c, int predict) {
   if (*c.stall) return;  // a stalled step opening
   const int ti = xcd_tile(ntiles);
   if (ti < 0) return;
   const Tile tl = tiles[ti];
   const GridDesc& G = grids[tl.grid];
   const int X = G.X, ny = G.ny;
+  // 64 x TY threads: thread (row w, lane j) owns the node pair (x0 + 2j, x0 + 2j + 1) of row
+  // y0 + w in every layer, as in the sweeps (the pitch X is even, so a pair never straddles rows)
+  const int x = tl.x0 + 2 * (int)(threadIdx.x & 63), y = tl.y0 + (int)(threadIdx.x >> 6);
+  if (x >= X || y >= ny) return;
   const int64_t P = (int64_t)X * ny;
   const int64_t off = (int64_t)tl.scen * G.nstore;
   double* __restrict__ v = G.v[c.vidx[tl.item]] + off;
   double* __restrict__ b = G.b + off;
   double* __restrict__ vh = predict ? G.vhist + off : nullptr;
   const double* __restrict__ il = G.ind_i + (int64_t)tl.scen * G.n_ind;
-  const int per_layer = kTileX * TY;
-  for (int k = threadIdx.x; k < per_layer * G.nl; k += kThreads) {
-    const int l = k / per_layer;
-    const int rem = k - l * per_layer;
-    const int yy = rem / kTileX, xx = rem - yy * kTileX;
-    const int x = tl.x0 + xx, y = tl.y0 + yy;
-    if (x >= X || y >= ny) continue;
+  for (int l = 0; l < G.nl; ++l) {
     const int64_t i = l * P + (int64_t)y * X + x;
+    const double2 vt = ld2(v, i);
     // layers with no capacitance (or no constant injection) contribute exact zeros
-    const double bcv = ((G.bc_layers >> l) & 1u) ? G.bconst64[i] : 0.0;
-    double bb = ((G.ch_layers >> l) & 1u) ? G.ch64[i] * v[i] + bcv : bcv;
+    const double2 bcv = ((G.bc_layers >> l) & 1u) ? ld2(G.bconst64, i) : make_double2(0.0, 0.0);
+    double2 bb = bcv;
+    if ((G.ch_layers >> l) & 1u) {
+      const double2 ch = ld2(G.ch64, i);
+      bb.x = ch.x * vt.x + bcv.x;
+      bb.y = ch.y * vt.y + bcv.y;
+    }
     if (G.n_ind) {
-      for (int j = G.inc_off[i]; j < G.inc_off[i + 1]; ++j) {
-        const int e = G.inc_ind[j];
-        const int kk = (e > 0 ? e : -e) - 1;
-        const double term = G.ind_alpha[kk] * il[kk];
-        bb += (e > 0) ? -term : term;
+      for (int q = 0; q < 2; ++q) {
+        double h = q ? bb.y : bb.x;
+        for (int j = G.inc_off[i + q]; j < G.inc_off[i + q + 1]; ++j) {
+          const int e = G.inc_ind[j];
+          const int kk = (e > 0 ? e : -e) - 1;
+          const double term = G.ind_alpha[kk] * il[kk];
+          h += (e > 0) ? -term : term;
+        }
+        if (q) bb.y = h; else bb.x = h;
       }
     }
-    b[i] = bb;
+    st2(b, i, bb);
     if (predict) {
-      const double vt = v[i];
-      if (predict == 2) v[i] = 2.0 * vt - vh[i];
-      vh[i] = vt;
+      if (predict == 2) {
+        const double2 vp = ld2(vh, i);
+        st2(v, i, make_double2(2.0 * vt.x - vp.x, 2.0 * vt.y - vp.y));
+      }
+      st2(vh, i, vt);
     }
   }
 }
@@ -1521,8 +1531,8 @@ hipError_t launch_step_end(const Ctl& c, int I, int count_step, int begin_next, 
 hipError_t launch_rhs(const Tile* tiles, int ntiles, int tile_rows, const GridDesc* grids,
                       const Ctl& c, hipStream_t s, int predict) {
   if (ntiles <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_rhs, dim3(xcd_blocks(ntiles)), dim3(kThreads), 0, s, tiles, ntiles,
-                     grids, c, tile_rows, predict);
+  hipLaunchKernelGGL(k_rhs, dim3(xcd_blocks(ntiles)), dim3(64 * tile_rows), 0, s, tiles, ntiles, grids, c,
+                     predict);
   return hipGetLastError();
 }
 
