@@ -289,7 +289,8 @@ __global__ void k_decide(Ctl c, DecideArgs da, CloseArgs ca) {
 // Right-hand side of the step (eq. 2 / eq. 10): b = (C/h) v + G0 Vdd - inductor history.
 // Sources are subtracted afterwards by k_sources.  predict = 1: also keep v(t) in vhist;
 // predict = 2: also replace v by the step's first iterate 2 v(t) - v(t-h) (v(t-h) read from
-// vhist) and keep v(t) in vhist.
+// vhist) and keep v(t) in vhist.  A tile may be a block of Tile.pad consecutive scenarios of one
+// grid: the shared C/h and G0 Vdd of a node pair are loaded once for all of them.
 // ------------------------------------------------------------------------------------
 __global__ __launch_bounds__(1024) void k_rhs(const Tile* __restrict__ tiles, int ntiles,
                                              const GridDesc* __restrict__ grids, Ctl c, int predict) {
@@ -304,41 +305,43 @@ __global__ __launch_bounds__(1024) void k_rhs(const Tile* __restrict__ tiles, in
   const int x = tl.x0 + 2 * (int)(threadIdx.x & 63), y = tl.y0 + (int)(threadIdx.x >> 6);
   if (x >= X || y >= ny) return;
   const int64_t P = (int64_t)X * ny;
-  const int64_t off = (int64_t)tl.scen * G.nstore;
-  double* __restrict__ v = G.v[c.vidx[tl.item]] + off;
-  double* __restrict__ b = G.b + off;
-  double* __restrict__ vh = predict ? G.vhist + off : nullptr;
-  const double* __restrict__ il = G.ind_i + (int64_t)tl.scen * G.n_ind;
   for (int l = 0; l < G.nl; ++l) {
     const int64_t i = l * P + (int64_t)y * X + x;
-    const double2 vt = ld2(v, i);
     // layers with no capacitance (or no constant injection) contribute exact zeros
+    const bool has_ch = (G.ch_layers >> l) & 1u;
     const double2 bcv = ((G.bc_layers >> l) & 1u) ? ld2(G.bconst64, i) : make_double2(0.0, 0.0);
-    double2 bb = bcv;
-    if ((G.ch_layers >> l) & 1u) {
-      const double2 ch = ld2(G.ch64, i);
-      bb.x = ch.x * vt.x + bcv.x;
-      bb.y = ch.y * vt.y + bcv.y;
-    }
-    if (G.n_ind) {
-      for (int q = 0; q < 2; ++q) {
-        double h = q ? bb.y : bb.x;
-        for (int j = G.inc_off[i + q]; j < G.inc_off[i + q + 1]; ++j) {
-          const int e = G.inc_ind[j];
-          const int kk = (e > 0 ? e : -e) - 1;
-          const double term = G.ind_alpha[kk] * il[kk];
-          h += (e > 0) ? -term : term;
+    const double2 ch = has_ch ? ld2(G.ch64, i) : make_double2(0.0, 0.0);
+    for (int s = 0; s < tl.pad; ++s) {
+      const int64_t off = (int64_t)(tl.scen + s) * G.nstore;
+      double* __restrict__ v = G.v[c.vidx[tl.item + s]] + off;
+      const double2 vt = ld2(v, i);
+      double2 bb = bcv;
+      if (has_ch) {
+        bb.x = ch.x * vt.x + bcv.x;
+        bb.y = ch.y * vt.y + bcv.y;
+      }
+      if (G.n_ind) {
+        const double* __restrict__ il = G.ind_i + (int64_t)(tl.scen + s) * G.n_ind;
+        for (int q = 0; q < 2; ++q) {
+          double h = q ? bb.y : bb.x;
+          for (int j = G.inc_off[i + q]; j < G.inc_off[i + q + 1]; ++j) {
+            const int e = G.inc_ind[j];
+            const int kk = (e > 0 ? e : -e) - 1;
+            const double term = G.ind_alpha[kk] * il[kk];
+            h += (e > 0) ? -term : term;
+          }
+          if (q) bb.y = h; else bb.x = h;
         }
-        if (q) bb.y = h; else bb.x = h;
       }
-    }
-    st2(b, i, bb);
-    if (predict) {
-      if (predict == 2) {
-        const double2 vp = ld2(vh, i);
-        st2(v, i, make_double2(2.0 * vt.x - vp.x, 2.0 * vt.y - vp.y));
+      st2(G.b + off, i, bb);
+      if (predict) {
+        double* __restrict__ vh = G.vhist + off;
+        if (predict == 2) {
+          const double2 vp = ld2(vh, i);
+          st2(v, i, make_double2(2.0 * vt.x - vp.x, 2.0 * vt.y - vp.y));
+        }
+        st2(vh, i, vt);
       }
-      st2(vh, i, vt);
     }
   }
 }

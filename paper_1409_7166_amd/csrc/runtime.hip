@@ -1206,9 +1206,17 @@ pg_status begin_step(pg_ctx* c, int only_item, bool begun = false, int64_t dev_s
   const bool gprobe = only_item < 0 && !loads && c->n_gchunks_all > 0 && !three && c->pred_chunks == 0;
   c->gprobe_next = gprobe;
   c->opening_gprobe = gprobe;
-  const Tile* T = (const Tile*)c->tiles_all.p;
-  int off = 0, cnt = fuse ? 0 : c->ntiles_all;
-  if (only_item >= 0) { off = c->item_tile_off[only_item]; cnt = c->item_tile_cnt[only_item]; }
+  // every item: the sweeps' tiles, whose scenario blocks load the shared C/h and G0 Vdd once;
+  // one item: its own single-scenario tiles
+  const Tile* T = (const Tile*)c->tiles_sweep.p;
+  int off = 0, cnt = 0;
+  if (!fuse)
+    for (auto& grp : c->tile_groups) cnt = std::max(cnt, grp.off + grp.count);
+  if (only_item >= 0) {
+    T = (const Tile*)c->tiles_all.p;
+    off = c->item_tile_off[only_item];
+    cnt = c->item_tile_cnt[only_item];
+  }
   const GraphChunk* GC = (const GraphChunk*)c->g_chunks_all.p;
   int goff = 0, gcnt = gprobe ? 0 : c->n_gchunks_all;
   if (only_item >= 0) { goff = c->item_gchunk_off[only_item]; gcnt = c->item_gchunk_cnt[only_item]; }
