@@ -8,7 +8,7 @@ import numpy as np
 import pytest
 
 import paper_1409_7166_amd as pg
-from helpers import PARITY_V, compressed, gpu_context, oracle_run, say
+from helpers import PARITY_V, compressed, gpu_context, oracle_run, say, torch_stream
 from workloads import small_multilayer, small_rc, small_rlc
 
 pytestmark = pytest.mark.gpu
@@ -94,3 +94,30 @@ def test_predictor_recorded_transient_matches_the_oracle(record_every):
     say(f"  max err over the records {err:.2e} V")
     assert err <= PARITY_V
     assert np.max(np.abs(last - Vref[-1])) <= PARITY_V
+
+
+def test_predictor_is_ignored_by_the_resident_path_and_by_netlists():
+    """The header states that the resident path and general netlists ignore the option: their
+    voltages are bitwise those without it."""
+    from workloads import irregular_grid
+    w = small_rc(32, 32, seed=96, steps=30)
+    w.pulses[0][0] = compressed(w.pulses[0][0], start=0.2, width=1.0)
+    out = {}
+    for pred in (0, 1):
+        with gpu_context(w, resident=1, predictor=pred, tol=1e-10, omega=1.6) as ctx:
+            ctx.step(30)
+            out[pred] = ctx.read_voltages(0, 0)
+    say("[gpu] predictor ignored: resident path")
+    assert np.array_equal(out[0], out[1])
+    net, scen = irregular_grid(side=24, nl=2, seed=97, scenarios=1)
+    for pred in (0, 1):
+        ctx = pg.Context(0, torch_stream())
+        ctx.set_options(h=1e-11, tol=1e-10, omega=1.5, check_every=8, precision=pg.PG_PREC_FP32_REFINE,
+                        predictor=pred)
+        with ctx:
+            g = ctx.upload_netlist(net.n, net.p, net.source_v, net.frm, net.to, net.kind, net.value, None, 1)
+            ctx.set_pulses(g, 0, scen[0])
+            ctx.step(30)
+            out[pred] = ctx.read_voltages(g, 0)
+    say("[gpu] predictor ignored: general netlist")
+    assert np.array_equal(out[0], out[1])
