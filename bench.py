@@ -517,7 +517,8 @@ def measure_adjoint(args, steps=200, ckpt=20, margin=0.05, tol=1e-10, tol_adj=1e
     torch.cuda.set_device(0)
     ctx = pg.Context(0, torch.cuda.current_stream().cuda_stream)
     ctx.set_options(h=w.h, tol=tol, omega=t["omega"], check_every=t["check_every"], max_sweeps=100000,
-                    precision=pg.PG_PREC_FP64, tile_rows=t["tile_rows"], sweeps_per_launch=t["sweeps_per_launch"])
+                    precision=pg.PG_PREC_FP64, tile_rows=t["tile_rows"], sweeps_per_launch=t["sweeps_per_launch"],
+                    predictor=t["predictor"])
     ctx.upload_mesh(mesh, 1)
     ctx.set_pulses(0, 0, w.pulses[0][0])
     grads = [torch.empty(a.shape, dtype=torch.float64, device="cuda:0") for a in (mesh.C, mesh.gE, mesh.gN)]

@@ -120,9 +120,13 @@ typedef struct pg_options {
                            and the converged solution unchanged and, on smooth stretches of a
                            transient, needs fewer sweeps.  It keeps one more FP64 voltage array
                            per scenario and forms every step's right-hand side in its own pass
-                           (no opening probe).  Ignored by the resident path, by general
-                           netlists and by the single-item solves of the adjoint's backward
-                           pass.  0 or 1; 1 needs graphs = 0 (else PG_ERR_UNSUPPORTED). */
+                           (no opening probe).  Ignored by the resident path and by general
+                           netlists.  In the adjoint's backward pass (pg_loss_backward*) the
+                           recomputed steps of a segment start, from its second step on, from
+                           the extrapolation of the two states before, and each adjoint solve
+                           from 2 lambda(k+1) - lambda(k+2) (two more state arrays of the item,
+                           allocated by pg_loss_forward when the option is on).  0 or 1; 1 needs
+                           graphs = 0 (else PG_ERR_UNSUPPORTED). */
 } pg_options;
 
 /* A layered RC/RLC mesh (the representative node of Fig. 2 repeated on a grid).

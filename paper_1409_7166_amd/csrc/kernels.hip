@@ -1573,7 +1573,7 @@ __global__ __launch_bounds__(kThreads) void k_state_copy(const Tile* __restrict_
     const int x = tl.x0 + xx, y = tl.y0 + yy;
     if (x >= X || y >= ny) continue;
     const int64_t i = l * P + (int64_t)y * X + x;
-    if (to_buf) buf[i] = v[i]; else v[i] = buf[i];
+    if (to_buf == 1) buf[i] = v[i]; else if (to_buf == 0) v[i] = buf[i]; else v[i] = 2.0 * v[i] - buf[i];
   }
 }
 

@@ -187,6 +187,7 @@ struct pg_ctx {
     int64_t k0 = 0;
     GridDesc view{};                             // the grid's descriptor with lambda as its state
     DBuf ckpts, vend, seg, lam0, lam1, arhs, dC, dgE, dgN, part, J, saved_vidx;
+    DBuf lamp, lamq;  // the adjoint states of the last two solves (predictor on)
     // vias then pads: storage slot, index among the inductive branches (-1: resistive), g, L,
     // and the gradients with respect to g and L
     DBuf br_slot, br_ind, br_g, br_L, dbr_g, dbr_L;
@@ -1635,6 +1636,7 @@ pg_status one_step(pg_ctx* c, bool speculate = false, bool speculate_after = fal
 }
 
 // ---- adjoint helpers ----------------------------------------------------------------
+// to_buf 1: buf <- v; 0: v <- buf; 2: v <- 2 v - buf (the extrapolated first iterate)
 pg_status state_copy(pg_ctx* c, int item, double* buf, int to_buf) {
   const Tile* T = (const Tile*)c->tiles_all.p + c->item_tile_off[item];
   hipError_t e = launch_state_copy(T, c->item_tile_cnt[item], c->tile_rows, (const GridDesc*)c->grid_desc.p,
@@ -1695,6 +1697,10 @@ pg_status loss_backward(pg_ctx* c, double tol_adj, double* dC, double* dgE, doub
   const Tile* T = (const Tile*)c->tiles_all.p + c->item_tile_off[A.item];
   const int nt = c->item_tile_cnt[A.item];
   const GridDesc* gd = (const GridDesc*)c->grid_desc.p;
+  // with the predictor: the adjoint states of the last two solves (lam_keep[lam_cur] the older)
+  double* lam_keep[2] = {(double*)A.lamp.p, (double*)A.lamq.p};
+  int lam_cur = 0;
+  bool lam_prev = false;
   for (int j = A.nseg - 1; j >= 0; --j) {
     const int kb = j * A.ckpt, ke = std::min(A.K, kb + A.ckpt), len = ke - kb;
     // recompute the forward states of the segment from its checkpoint (only this item steps)
@@ -1708,6 +1714,8 @@ pg_status loss_backward(pg_ctx* c, double tol_adj, double* dC, double* dgE, doub
     PG_TRY(set_step(c, A.k0 + kb));
     for (int q = 1; q <= len; ++q) {
       PG_TRY(begin_step(c, A.item));
+      // with the predictor, from the segment's second step on: start from 2 v(q-1) - v(q-2)
+      if (c->opt.predictor && q >= 2) PG_TRY(state_copy(c, A.item, seg + (size_t)(q - 2) * ns, 2));
       PG_TRY(solve_active(c, c->opt.tol));
       hipError_t e2 = launch_step_end(c->ctl, n_items(c), 2, 0, c->opt.h, c->src_table, -1, -1, c->stream);
       if (e2 == hipSuccess) e2 = launch_ind_update_item(gd, A.grid, A.item, A.scen, c->ctl, ni, c->stream);
@@ -1729,6 +1737,12 @@ pg_status loss_backward(pg_ctx* c, double tol_adj, double* dC, double* dgE, doub
       if (e != hipSuccess) return set_err(c, PG_ERR_DEVICE, "adjoint rhs: %s", hipGetErrorString(e));
       e = launch_step_begin(c->ctl, n_items(c), A.item, c->opt.h, c->src_table, -1, -1, c->stream);
       if (e != hipSuccess) return set_err(c, PG_ERR_DEVICE, "adjoint step: %s", hipGetErrorString(e));
+      if (c->opt.predictor && A.lamp.p) {  // keep lambda_{q+1}; start from 2 lambda_{q+1} - lambda_{q+2}
+        PG_TRY(state_copy(c, A.item, lam_keep[1 - lam_cur], 1));
+        if (lam_prev) PG_TRY(state_copy(c, A.item, lam_keep[lam_cur], 2));
+        lam_cur = 1 - lam_cur;
+        lam_prev = true;
+      }
       PG_TRY(solve_active(c, tol_adj));
       e = launch_adj_grad(T, nt, c->tile_rows, gd, c->ctl, seg + (size_t)q * ns, seg + (size_t)(q - 1) * ns,
                           1.0 / c->opt.h, (double*)A.dC.p, (double*)A.dgE.p, (double*)A.dgN.p, c->stream);
@@ -2562,6 +2576,10 @@ pg_status pg_loss_forward(pg_ctx* c, int32_t grid, int32_t scen, int32_t nsteps,
   PG_TRY(dalloc(c, A.ckpts, (size_t)A.nseg * ns * sizeof(double)));
   PG_TRY(dalloc(c, A.vend, ns * sizeof(double)));
   PG_TRY(dalloc(c, A.seg, (size_t)(A.ckpt + 1) * ns * sizeof(double)));
+  if (c->opt.predictor) {
+    PG_TRY(dalloc(c, A.lamp, ns * sizeof(double)));
+    PG_TRY(dalloc(c, A.lamq, ns * sizeof(double)));
+  }
   PG_TRY(dalloc(c, A.lam0, nfull * sizeof(double)));
   PG_TRY(dalloc(c, A.lam1, nfull * sizeof(double)));
   PG_TRY(dalloc(c, A.arhs, nfull * sizeof(double)));

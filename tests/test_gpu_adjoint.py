@@ -27,12 +27,15 @@ def _case(side_x=40, side_y=36, steps=30):
     return w, w.meshes[0], p
 
 
-@pytest.mark.parametrize("prec", [pg.PG_PREC_FP64, pg.PG_PREC_FP32_REFINE])
-def test_adjoint_matches_oracle_adjoint(prec):
+@pytest.mark.parametrize("prec,predictor", [(pg.PG_PREC_FP64, 0), (pg.PG_PREC_FP32_REFINE, 0),
+                                            (pg.PG_PREC_FP64, 1)])
+def test_adjoint_matches_oracle_adjoint(prec, predictor):
+    """With the predictor the forward steps, the recomputed ones and the adjoint solves start
+    from extrapolated iterates; the stopping tests are the same, and so is the bar."""
     w, mesh, p = _case()
     K, ck, margin = 30, 7, 0.05
-    say(f"[gpu] adjoint 40x40 prec={prec}")
-    with gpu_context(w, precision=prec, tol=1e-12, omega=1.5, max_sweeps=50000) as ctx:
+    say(f"[gpu] adjoint 40x40 prec={prec} predictor={predictor}")
+    with gpu_context(w, precision=prec, tol=1e-12, omega=1.5, max_sweeps=50000, predictor=predictor) as ctx:
         J = ctx.loss_forward(0, 0, K, ck, margin)
         dC, dE, dN = ctx.loss_backward(1e-10)
         assert ctx.time_index() == K

@@ -201,7 +201,8 @@ def test_config4_adjoint_all_200_steps(launch):
     larger of the entry and 1e-3 of the gradient's largest magnitude), and the directional
     derivative along a seeded direction against a central difference of the oracle's forward
     transient on the full grid (within 1e-4 relative); with FP32 sweeps one per launch, and with
-    the settings bench.py times (FP64 sweeps four per launch on 16-row tiles)."""
+    the settings bench.py times (FP64 sweeps four per launch on 16-row tiles, each solve started
+    from the extrapolated iterate)."""
     from workloads import config4, random_direction
     path = os.path.join(os.path.dirname(GOLDEN["config1"]), "config4_adjoint_samples.npz")
     if not os.path.exists(path):
@@ -216,7 +217,8 @@ def test_config4_adjoint_all_200_steps(launch):
     else:
         t = settings("config4", 1e-10, pg.PG_PREC_FP64)
         opts = dict(precision=pg.PG_PREC_FP64, tol=1e-10, omega=t["omega"], check_every=t["check_every"],
-                    tile_rows=t["tile_rows"], sweeps_per_launch=t["sweeps_per_launch"], max_sweeps=100000)
+                    tile_rows=t["tile_rows"], sweeps_per_launch=t["sweeps_per_launch"], max_sweeps=100000,
+                    predictor=t["predictor"])
     with gpu_context(w, **opts) as ctx:
         J = ctx.loss_forward(0, 0, steps, 20, margin)
         dC, dE, dN = ctx.loss_backward(1e-10)
