@@ -61,8 +61,9 @@ def parse():
                     help="1: one launch per call with one workgroup per item carrying whole steps (meshes of at "
                          "most 4096 nodes); 0: one launch per sweep; -1: the workload's tuned choice")
     ap.add_argument("--predictor", type=int, default=-1,
-                    help="1: start each mesh step's sweeps from the linear extrapolation of the last two "
-                         "steps; 0: from the last step (Algorithm 1); -1: the workload's tuned choice")
+                    help="2: start each mesh step's sweeps from the quadratic extrapolation of the last "
+                         "three steps; 1: the linear one of the last two; 0: from the last step (Algorithm 1); "
+                         "-1: the workload's tuned choice")
     ap.add_argument("--profile-every", type=int, default=32,
                     help="time every n-th sweep block, residual pass and other launch with HIP events "
                          "during the timed region (0: off)")
@@ -105,12 +106,12 @@ PARITY_TOL = {"config0": 1e-10, "config1": 1e-10, "config3a": 1e-10, "config3b":
 # and the start of the relaxation that follows them).
 TUNED_PARITY = {
     "config0": dict(omega=1.65, check_every=16),
-    "config1": dict(omega=1.86, check_every=12, predictor=1),
-    "config1_hbm": dict(omega=1.86, check_every=12, predictor=1),
-    "config2": dict(omega=1.9, check_every=32, predictor=1),
+    "config1": dict(omega=1.86, check_every=12, predictor=2),
+    "config1_hbm": dict(omega=1.86, check_every=12, predictor=2),
+    "config2": dict(omega=1.9, check_every=32, predictor=2),
     "config3a": dict(omega=1.65, check_every=8),
     "config3b": dict(omega=1.6, check_every=16),
-    "config4": dict(omega=1.5, check_every=12, predictor=1),
+    "config4": dict(omega=1.5, check_every=12, predictor=2),
 }
 
 
@@ -486,7 +487,7 @@ def measure(name, prec, tol, steps, args, do_verify=True):
                    else None,
                    "recurrence": "three-level" if args.recurrence else "two-level",
                    "resident": bool(st["options"]["resident"]),
-                   "predictor": bool(st["options"]["predictor"]),
+                   "predictor": int(st["options"]["predictor"]),
                    "sweeps_per_step": st["sweeps"] / max(1, st["steps"]),
                    "max_step_sweeps": st["max_step_sweeps"], "max_final_residual_V": st["max_final_residual"],
                    "node_steps_per_s": nodes * steps / elapsed},

@@ -118,15 +118,17 @@ typedef struct pg_options {
                            linear extrapolation 2 V(s-1) - V(s-2) (from V(s-1) on the first step
                            after the state or the clock was set), which leaves the stopping test
                            and the converged solution unchanged and, on smooth stretches of a
-                           transient, needs fewer sweeps.  It keeps one more FP64 voltage array
-                           per scenario and forms every step's right-hand side in its own pass
-                           (no opening probe).  Ignored by the resident path and by general
+                           transient, needs fewer sweeps; 2: from the quadratic extrapolation
+                           3 V(s-1) - 3 V(s-2) + V(s-3) (the linear one on the second step after
+                           a restart, V(s-1) on the first).  It keeps one (two for 2) more FP64
+                           voltage arrays per scenario and forms every step's right-hand side in
+                           its own pass (no opening probe).  Ignored by the resident path and by general
                            netlists.  In the adjoint's backward pass (pg_loss_backward*) the
                            recomputed steps of a segment start, from its second step on, from
                            the extrapolation of the two states before, and each adjoint solve
                            from 2 lambda(k+1) - lambda(k+2) (two more state arrays of the item,
-                           allocated by pg_loss_forward when the option is on).  0 or 1; 1 needs
-                           graphs = 0 (else PG_ERR_UNSUPPORTED). */
+                           allocated by pg_loss_forward when the option is on).  0, 1 or 2;
+                           1 and 2 need graphs = 0 (else PG_ERR_UNSUPPORTED). */
 } pg_options;
 
 /* A layered RC/RLC mesh (the representative node of Fig. 2 repeated on a grid).

@@ -289,7 +289,9 @@ __global__ void k_decide(Ctl c, DecideArgs da, CloseArgs ca) {
 // Right-hand side of the step (eq. 2 / eq. 10): b = (C/h) v + G0 Vdd - inductor history.
 // Sources are subtracted afterwards by k_sources.  predict = 1: also keep v(t) in vhist;
 // predict = 2: also replace v by the step's first iterate 2 v(t) - v(t-h) (v(t-h) read from
-// vhist) and keep v(t) in vhist.  A tile may be a block of Tile.pad consecutive scenarios of one
+// vhist) and keep v(t) in vhist; predict = 3: start from 3 v(t) - 3 v(t-h) + v(t-2h) (v(t-2h)
+// read from vhist2).  With vhist2 present, the old vhist moves there.  A tile may be a block of
+// Tile.pad consecutive scenarios of one
 // grid: the shared C/h and G0 Vdd of a node pair are loaded once for all of them.
 // ------------------------------------------------------------------------------------
 __global__ __launch_bounds__(1024) void k_rhs(const Tile* __restrict__ tiles, int ntiles,
@@ -336,9 +338,16 @@ __global__ __launch_bounds__(1024) void k_rhs(const Tile* __restrict__ tiles, in
       st2(G.b + off, i, bb);
       if (predict) {
         double* __restrict__ vh = G.vhist + off;
-        if (predict == 2) {
-          const double2 vp = ld2(vh, i);
-          st2(v, i, make_double2(2.0 * vt.x - vp.x, 2.0 * vt.y - vp.y));
+        double* __restrict__ vh2 = G.vhist2 ? G.vhist2 + off : nullptr;
+        if (predict >= 2) {
+          const double2 p1 = ld2(vh, i);
+          if (predict == 3) {
+            const double2 p2 = ld2(vh2, i);
+            st2(v, i, make_double2(3.0 * (vt.x - p1.x) + p2.x, 3.0 * (vt.y - p1.y) + p2.y));
+          } else {
+            st2(v, i, make_double2(2.0 * vt.x - p1.x, 2.0 * vt.y - p1.y));
+          }
+          if (vh2) st2(vh2, i, p1);
         }
         st2(vh, i, vt);
       }

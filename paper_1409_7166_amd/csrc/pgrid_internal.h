@@ -106,8 +106,10 @@ struct GridDesc {
   const int32_t* inc_ind;          // signed: k+1 if the slot is ind_a[k], -(k+1) if ind_b[k]
   const double* ind_vfar;          // far-end voltage of a branch with ind_b = -1 (null: vdd)
   double vdd;
-  // layered mesh under pg_options.predictor: v(t-h) per scenario (same layout as v), else null
+  // layered mesh under pg_options.predictor: v(t-h) per scenario (same layout as v), else null;
+  // v(t-2h) likewise under the quadratic predictor
   double* vhist;
+  double* vhist2;
   // general graph: neighbour table (see above), and the table of the pairs joined by
   // capacitors, padded (entry k of slot i at cap_off[i/64] + 64 k + i%64, rows shorter than
   // their slice's widest padded with their own slot and zero), values C_ij / h; cap_off null
@@ -237,7 +239,8 @@ struct DecideArgs {
 // -1: searched on the device (launches replayed from graphs, or steps the host does not track)
 hipError_t launch_step_begin(const Ctl& c, int G, int only_item, double h, const SourceTable& src, int win_a,
                              int win_b, hipStream_t s);
-// predict: 0 none, 1 keep v in vhist, 2 also start the step from 2 v - vhist (k_rhs)
+// predict: 0 none, 1 keep v in vhist, 2 also start the step from 2 v - vhist, 3 from
+// 3 v - 3 vhist + vhist2 (k_rhs; vhist2, where present, takes the old vhist)
 hipError_t launch_rhs(const Tile* tiles, int ntiles, int tile_rows, const GridDesc* grids,
                       const Ctl& c, hipStream_t s, int predict = 0);
 // b -= sign * I(t_now + shift) at every source in the window of the step being opened

@@ -86,7 +86,7 @@ struct GridHost {
   // device buffers
   DBuf gE64, gN64, gU64, D64, ch64, bconst64, gEs, gNs, gUs, invDs;
   DBuf v0, v1, b, r, d0, d1;
-  DBuf vh;                                       // v(t-h) per scenario (meshes, predictor on)
+  DBuf vh, vh2;                                  // v(t-h), v(t-2h) per scenario (meshes, predictor on)
   DBuf ind_a_d, ind_b_d, ind_geq_d, ind_alpha_d, ind_i_d, inc_off_d, inc_ind_d, ind_vfar_d;
   DBuf slot_d, sl_off_d, sl_len_d, sl_col_d, sl_w64_d, sl_ws_d, cap_off_d, cap_col_d, cap_val_d;
   DBuf vprev0, vprev1, g3diag_d, sl_g64_d, bres_d, bl_d;  // three-level recurrence
@@ -221,7 +221,8 @@ struct pg_ctx {
   int opening_tag = 0;                           // ... and the tag of its first decision
   bool maybe_stalled = false;                    // a speculative close may have stalled the device
   bool begun_next = false;                       // the last close also began the next step
-  bool prev_valid = false;                       // v(t-h) is kept: graph grids' vprev (three-level), meshes' vh (predictor)
+  bool prev_valid = false;                       // v(t-h) is kept: graph grids' vprev (three-level)
+  int pred_hist = 0;                             // earlier states the predictor holds (meshes' vh, vh2)
   int fuse_next = 0;                             // kFuse* mode of the next residual pass (mesh RHS)
   bool gprobe_next = false;                      // the next residual pass probes the general graphs
   bool gstore_next = false;                      // the next residual pass forms and stores their b, r
@@ -623,10 +624,16 @@ pg_status sync_desc(pg_ctx* c, int gi);
 pg_status build_grid(pg_ctx* c, int gi) {
   PG_TRY(c->grids[gi].kind ? build_graph_grid(c, gi) : build_mesh_grid(c, gi));
   GridHost& H = c->grids[gi];
-  if (!H.kind && c->opt.predictor) {  // filled by the first opening (prev_valid is false then)
+  // the predictor's history, filled by the openings that follow (pred_hist is 0 then)
+  if (!H.kind && c->opt.predictor) {
     if (!H.vh.p) PG_TRY(dalloc(c, H.vh, (size_t)H.nstore * H.S * sizeof(double)));
   } else {
     dfree(H.vh);
+  }
+  if (!H.kind && c->opt.predictor == 2) {
+    if (!H.vh2.p) PG_TRY(dalloc(c, H.vh2, (size_t)H.nstore * H.S * sizeof(double)));
+  } else {
+    dfree(H.vh2);
   }
   return sync_desc(c, gi);
 }
@@ -644,6 +651,7 @@ GridDesc make_desc(pg_ctx* c, GridHost& H) {
   D.invDs = H.invDs.p;
   D.v[0] = (double*)H.v0.p; D.v[1] = (double*)H.v1.p; D.b = (double*)H.b.p;
   D.vhist = (double*)H.vh.p;
+  D.vhist2 = (double*)H.vh2.p;
   D.r = H.r.p; D.d[0] = H.d0.p; D.d[1] = H.d1.p;
   D.n_ind = (int32_t)H.ind_a.size();
   D.ind_a = (const int32_t*)H.ind_a_d.p; D.ind_b = (const int32_t*)H.ind_b_d.p;
@@ -704,6 +712,7 @@ pg_status prepare(pg_ctx* c) {
   }
   if (!c->dirty) return PG_OK;
   c->prev_valid = false;
+  c->pred_hist = 0;
   drop_graphs(c);
   const int G = (int)c->grids.size();
   c->tile_rows = c->opt.tile_rows ? c->opt.tile_rows : 8;
@@ -1119,6 +1128,7 @@ pg_status launch_sweeps(pg_ctx* c, int nchk) {
 pg_status set_step(pg_ctx* c, int64_t k) {
   c->step = k;
   c->prev_valid = false;     // the three-level recurrence restarts with a two-level step
+  c->pred_hist = 0;          // and the predictor from v(t)
   c->begun_next = false;     // a clock change voids any step opened ahead
   c->opening_queued = false;
   c->step_host = (long long)k;
@@ -1193,9 +1203,10 @@ pg_status begin_step(pg_ctx* c, int only_item, bool begun = false, int64_t dev_s
   // needs no separate right-hand-side pass on single-scenario meshes: the step's first residual
   // pass forms b itself (launch_resid_all picks up fuse_rhs_next).
   const bool loads = dev_step < 0 || sources_may_act(c, dev_step);
-  // the predictor moves v to the step's first iterate after the right-hand side has read v(t),
+  // the predictor moves v to the step's first iterate after the right-hand side has read v(t):
+  // 1 keeps v(t) only, 2 starts from 2 v(t) - v(t-h), 3 from 3 v(t) - 3 v(t-h) + v(t-2h)
   // so the right-hand side keeps its own pass
-  const int predict = c->opt.predictor && only_item < 0 ? (c->prev_valid ? 2 : 1) : 0;
+  const int predict = c->opt.predictor && only_item < 0 ? 1 + std::min(c->pred_hist, c->opt.predictor) : 0;
   bool fuse = only_item < 0 && !loads && c->ntiles_all > 0 && !predict;
   for (auto& grp : c->tile_groups) fuse = fuse && !grp.multi;
   // a step predicted to converge at once (the previous one did) only needs the norm: if it has
@@ -1240,7 +1251,8 @@ pg_status begin_step(pg_ctx* c, int only_item, bool begun = false, int64_t dev_s
       e = launch_sources(c->src_table, (const GridDesc*)c->grid_desc.p, k, -c->opt.h, -1.0, c->stream);
     if (e != hipSuccess) return set_err(c, PG_ERR_DEVICE, "source launch: %s", hipGetErrorString(e));
   }
-  if (three || predict) c->prev_valid = true;
+  if (three) c->prev_valid = true;
+  if (predict) c->pred_hist = std::min(c->pred_hist + 1, c->opt.predictor);
   return PG_OK;
 }
 
@@ -1776,6 +1788,7 @@ pg_status loss_backward(pg_ctx* c, double tol_adj, double* dC, double* dgE, doub
 
 pg_status fill_v(pg_ctx* c, GridHost& H, const double* v, int scen, int32_t vidx) {
   c->prev_valid = false;
+  c->pred_hist = 0;
   // write the voltages of one scenario into its slice of the current buffer
   std::vector<double> buf((size_t)H.nstore, H.vdd);
   for (int64_t i = 0; i < H.n; ++i) buf[(size_t)H.storage(i)] = v ? v[i] : H.vdd;
@@ -1902,7 +1915,7 @@ void pg_destroy(pg_ctx* c) {
   if (c->stream) (void)hipStreamSynchronize(c->stream);
   for (auto& H : c->grids) {
     DBuf* bufs[] = {&H.gE64, &H.gN64, &H.gU64, &H.D64, &H.ch64, &H.bconst64, &H.gEs, &H.gNs, &H.gUs, &H.invDs,
-                    &H.v0, &H.v1, &H.b, &H.r, &H.d0, &H.d1, &H.vh, &H.ind_a_d, &H.ind_b_d, &H.ind_geq_d,
+                    &H.v0, &H.v1, &H.b, &H.r, &H.d0, &H.d1, &H.vh, &H.vh2, &H.ind_a_d, &H.ind_b_d, &H.ind_geq_d,
                     &H.ind_alpha_d, &H.ind_i_d, &H.inc_off_d, &H.inc_ind_d, &H.ind_vfar_d,
                     &H.slot_d, &H.sl_off_d, &H.sl_len_d, &H.sl_col_d, &H.sl_w64_d, &H.sl_ws_d, &H.cap_off_d, &H.cap_col_d,
                     &H.cap_val_d, &H.vprev0, &H.vprev1, &H.g3diag_d, &H.sl_g64_d, &H.bres_d, &H.bl_d,

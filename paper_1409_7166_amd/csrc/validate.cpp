@@ -104,8 +104,8 @@ pg_status pg_validate_options(const pg_options* o, char* msg, size_t len) {
     return fail(PG_ERR_UNSUPPORTED, msg, len, "the three-level recurrence runs with plain launches (graphs = 0)");
   if (o->resident != 0 && o->resident != 1)
     return fail(PG_ERR_INVALID_ARG, msg, len, "resident must be 0 or 1 (got %d)", o->resident);
-  if (o->predictor != 0 && o->predictor != 1)
-    return fail(PG_ERR_INVALID_ARG, msg, len, "predictor must be 0 or 1 (got %d)", o->predictor);
+  if (o->predictor < 0 || o->predictor > 2)
+    return fail(PG_ERR_INVALID_ARG, msg, len, "predictor must be 0, 1 or 2 (got %d)", o->predictor);
   if (o->predictor && o->graphs)
     return fail(PG_ERR_UNSUPPORTED, msg, len, "the predictor runs with plain launches (graphs = 0)");
   return PG_OK;

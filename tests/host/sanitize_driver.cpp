@@ -435,7 +435,7 @@ void options(Rng& r) {
       case 2: b.omega = 2.0 + r.unit(); break;
       case 3: b.max_sweeps = 0; break;
       case 4: b.tile_rows = 5; break;
-      case 5: b.predictor = 2; break;
+      case 5: b.predictor = 3; break;
     }
     const pg_status s = pg_validate_options(&b, msg, (size_t)r.below(33));
     CHECK(s == PG_ERR_INVALID_ARG, "option corruption %d gave %d", t, s);

@@ -104,7 +104,7 @@ def test_options_validation():
     for k, v in (("omega", 2.0), ("omega", 0.0), ("h", 0.0), ("h", float("nan")), ("tol", -1.0),
                  ("max_sweeps", 0), ("check_every", 0), ("precision", 5), ("ordering", 3),
                  ("tile_rows", 12), ("lookahead", 9), ("recurrence", 2), ("sweeps_per_launch", 3),
-                 ("sweeps_per_launch", 5), ("predictor", 2)):
+                 ("sweeps_per_launch", 5), ("predictor", 3)):
         bad = pg.default_options(**{k: v})
         st, msg = pg.validate_options(bad)
         assert st == -1, (k, v)
@@ -115,6 +115,8 @@ def test_options_validation():
     st, msg = pg.validate_options(pg.default_options(predictor=1, graphs=1))
     assert st == -8 and "plain launches" in msg
     assert pg.validate_options(pg.default_options(predictor=1))[0] == 0
+    assert pg.validate_options(pg.default_options(predictor=2))[0] == 0
+    assert pg.validate_options(pg.default_options(predictor=2, graphs=1))[0] == -8
     # the three-level recurrence runs with plain launches only
     st, msg = pg.validate_options(pg.default_options(recurrence=pg.PG_REC_THREE_LEVEL, graphs=1))
     assert st == -8 and "plain launches" in msg

@@ -1,5 +1,6 @@
-"""The extrapolated first iterate (pg_options.predictor = 1): each step's sweeps start from
-2 V(s-1) - V(s-2) instead of Algorithm 1's V(s-1).  The stopping test is unchanged, so the
+"""The extrapolated first iterate: each step's sweeps start from 2 V(s-1) - V(s-2)
+(pg_options.predictor = 1) or 3 V(s-1) - 3 V(s-2) + V(s-3) (= 2) instead of Algorithm 1's
+V(s-1).  The stopping test is unchanged, so the
 voltages must match the oracle at every node of every step as closely as without it (the 1e-6 V
 bar), on RC and RLC meshes (branch currents too), on scenarios, with fused sweeps and after the
 state or the clock is set mid-run (the first step after either starts from V(s-1)); on a
@@ -24,8 +25,9 @@ def _run(w, steps, predictor, **opts):
         return np.array(out), cur, ctx.stats()
 
 
+@pytest.mark.parametrize("order", [1, 2])
 @pytest.mark.parametrize("case", ["three_layer_fp32_fused", "rlc_fp64", "scenarios_fp32"])
-def test_predictor_matches_the_oracle_every_step(case):
+def test_predictor_matches_the_oracle_every_step(case, order):
     if case == "three_layer_fp32_fused":
         w = small_multilayer(side=100, seed=91, nl=3, pad_every=32, steps=60)
         w.pulses[0][0] = compressed(w.pulses[0][0], start=0.2, width=1.0)
@@ -40,11 +42,12 @@ def test_predictor_matches_the_oracle_every_step(case):
         w.pulses[0] = [compressed(p, start=0.3, width=1.0) for p in w.pulses[0]]
         opts = dict(precision=pg.PG_PREC_FP32_REFINE, tol=1e-10, omega=1.6, check_every=8, scen_block=2)
     steps = w.steps
-    say(f"[gpu] predictor case={case}")
-    res = {p: _run(w, steps, p, max_sweeps=100000, **opts) for p in (0, 1)}
+    say(f"[gpu] predictor case={case} order={order}")
+    res = {p: _run(w, steps, p, max_sweeps=100000, **opts) for p in (0, order)}
+    res[1] = res[order]
     for s, pulses in enumerate(w.pulses[0]):
         Vref, Iref = oracle_run(w.meshes[0], pulses, w.h, steps)
-        for p in (0, 1):
+        for p in (0, order):
             err = float(np.max(np.abs(res[p][0][:, s, :] - Vref)))
             say(f"  scenario {s} predictor={p}: max err over {steps} steps {err:.2e} V, "
                 f"sweeps {res[p][2]['sweeps']}")
@@ -55,15 +58,16 @@ def test_predictor_matches_the_oracle_every_step(case):
         assert res[1][2]["sweeps"] < res[0][2]["sweeps"]
 
 
-def test_predictor_restarts_after_the_state_or_clock_is_set():
+@pytest.mark.parametrize("order", [1, 2])
+def test_predictor_restarts_after_the_state_or_clock_is_set(order):
     """Setting the state or the clock discards the kept V(s-2): the next step starts from V(s-1),
     and the transient still matches the oracle at every step."""
     w = small_multilayer(side=64, seed=94, nl=2, layer_g=(1.0, 4.0), pad_every=16, steps=40)
     w.pulses[0][0] = compressed(w.pulses[0][0], start=0.2, width=1.0)
     Vref, _ = oracle_run(w.meshes[0], w.pulses[0][0], w.h, 40)
-    opts = dict(precision=pg.PG_PREC_FP32_REFINE, tol=1e-10, omega=1.6, check_every=8, predictor=1,
+    opts = dict(precision=pg.PG_PREC_FP32_REFINE, tol=1e-10, omega=1.6, check_every=8, predictor=order,
                 max_sweeps=100000)
-    say("[gpu] predictor with the state and the clock set mid-run")
+    say(f"[gpu] predictor (order {order}) with the state and the clock set mid-run")
     worst = 0.0
     with gpu_context(w, **opts) as ctx:
         for k in range(1, 41):
@@ -77,8 +81,9 @@ def test_predictor_restarts_after_the_state_or_clock_is_set():
     assert worst <= PARITY_V
 
 
+@pytest.mark.parametrize("order", [1, 2])
 @pytest.mark.parametrize("record_every", [1, 3])
-def test_predictor_recorded_transient_matches_the_oracle(record_every):
+def test_predictor_recorded_transient_matches_the_oracle(record_every, order):
     """pg_run_transient queues a step's successor ahead of its wait; with the predictor that
     opening rewrites v, so every recorded voltage must still be the converged V(s), not the next
     step's first iterate."""
@@ -86,7 +91,7 @@ def test_predictor_recorded_transient_matches_the_oracle(record_every):
     w.pulses[0][0] = compressed(w.pulses[0][0], start=0.2, width=1.0)
     Vref, _ = oracle_run(w.meshes[0], w.pulses[0][0], w.h, 30)
     say(f"[gpu] predictor recorded transient every {record_every}")
-    with gpu_context(w, precision=pg.PG_PREC_FP32_REFINE, tol=1e-10, omega=1.6, check_every=8, predictor=1,
+    with gpu_context(w, precision=pg.PG_PREC_FP32_REFINE, tol=1e-10, omega=1.6, check_every=8, predictor=order,
                      max_sweeps=100000) as ctx:
         V = ctx.run_transient(30, record_every=record_every)
         last = ctx.read_voltages(0, 0)
@@ -103,14 +108,14 @@ def test_predictor_is_ignored_by_the_resident_path_and_by_netlists():
     w = small_rc(32, 32, seed=96, steps=30)
     w.pulses[0][0] = compressed(w.pulses[0][0], start=0.2, width=1.0)
     out = {}
-    for pred in (0, 1):
+    for pred in (0, 2):
         with gpu_context(w, resident=1, predictor=pred, tol=1e-10, omega=1.6) as ctx:
             ctx.step(30)
             out[pred] = ctx.read_voltages(0, 0)
     say("[gpu] predictor ignored: resident path")
-    assert np.array_equal(out[0], out[1])
+    assert np.array_equal(out[0], out[2])
     net, scen = irregular_grid(side=24, nl=2, seed=97, scenarios=1)
-    for pred in (0, 1):
+    for pred in (0, 2):
         ctx = pg.Context(0, torch_stream())
         ctx.set_options(h=1e-11, tol=1e-10, omega=1.5, check_every=8, precision=pg.PG_PREC_FP32_REFINE,
                         predictor=pred)
@@ -120,4 +125,4 @@ def test_predictor_is_ignored_by_the_resident_path_and_by_netlists():
             ctx.step(30)
             out[pred] = ctx.read_voltages(g, 0)
     say("[gpu] predictor ignored: general netlist")
-    assert np.array_equal(out[0], out[1])
+    assert np.array_equal(out[0], out[2])
